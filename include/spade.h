@@ -1,0 +1,175 @@
+/*
+ * spade.h -- C ABI of the canvas point-in-polygon engine for AMD MI355X (gfx950).
+ *
+ * The three queries follow the paper's statement of them (Sec. 5.2):
+ *   - spatial selection with a polygonal constraint: the points of a dataset
+ *     that intersect one polygon (for points, intersection = containment,
+ *     Sec. 7 "Containment Queries");
+ *   - the polygon-point join, evaluated as a collection of selections, one
+ *     per polygon of the polygon dataset ("Spatial Joins", case (1));
+ *   - the polygon-point aggregation: per-polygon point counts without
+ *     materialising the join ("Spatial Aggregations", second plan).
+ * Polygons are rasterised into a discrete canvas (Sec. 4.1/4.2: a pixel grid
+ * of polygon ids with boundary pixels pointing into a boundary index,
+ * Sec. 4.3); points in non-boundary pixels take the pixel's label, points in
+ * boundary pixels get an exact crossing-number test.  Results are exact.
+ *
+ * Containment rule (the paper fixes none): a point p is inside polygon P iff
+ * an odd number of P's edges (a,b) have (a.y > p.y) != (b.y > p.y) and meet
+ * the horizontal line through p strictly to the right of p, the side test
+ * being the exact sign of the orientation determinant.  Equivalently p is
+ * classified as p + (eps, eps^2): boundary points belong to the polygon on
+ * their +x side (above, for horizontal edges), so a tessellation counts every
+ * point of its union exactly once.  Rings are implicitly closed; a polygon's
+ * rings combine by even-odd parity (holes, multi-polygons); horizontal and
+ * zero-length edges never count.
+ *
+ * Conventions for every call:
+ *   - Array pointers are HIP DEVICE pointers on the context's device, unless
+ *     stated otherwise; scalar out-parameters (n_out, sizes) are host pointers.
+ *   - The caller owns every input and output buffer; the library never frees
+ *     or retains them past the call.  The context owns its scratch memory.
+ *   - Work is ordered on the context's stream.  The plain query calls return
+ *     after their results are complete (one stream synchronisation).
+ *   - Return value: SPADE_OK (0) or a negative SPADE_E_* code; the message
+ *     of the last failure on a context is available from spade_last_error.
+ *   - Coordinates are IEEE float64.  Exactness holds for finite coordinates
+ *     whose pairwise products neither overflow nor underflow (|c| <= 2^500).
+ *     Non-finite polygon vertices are rejected (SPADE_E_INVALID); points with
+ *     a NaN or infinite coordinate lie in no polygon.
+ *   - Point ids are 0-based indices into the point arrays (uint32: n < 2^32);
+ *     polygon ids are 0-based positions in the polygon set (< 2^31 - 1).
+ *   - One context per host thread; contexts are independent.
+ */
+#ifndef SPADE_H
+#define SPADE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    SPADE_OK = 0,
+    SPADE_E_INVALID = -1,      /* bad argument or malformed polygon set      */
+    SPADE_E_CAPACITY = -2,     /* output buffer too small; *n_out = needed   */
+    SPADE_E_NOMEM = -3,        /* device allocation failed                   */
+    SPADE_E_HIP = -4,          /* HIP runtime error (message has the text)   */
+    SPADE_E_UNSUPPORTED = -5,  /* valid request outside this build's limits  */
+    SPADE_E_TOO_LARGE = -6     /* n >= 2^32 points or n_polys >= 2^31 - 1    */
+};
+
+/* Points: structure of arrays, n entries each (device pointers). */
+typedef struct {
+    int64_t n;
+    const double *x;
+    const double *y;
+} spade_points;
+
+/* Polygon set in CSR form (device pointers).
+ *   poly_ring_off [n_polys + 1]: rings of polygon k are
+ *                  poly_ring_off[k] .. poly_ring_off[k+1]-1; NULL means ring k
+ *                  is polygon k (n_rings == n_polys).
+ *   ring_vtx_off  [n_rings + 1]: vertices of ring r are ring_vtx_off[r] ..
+ *                  ring_vtx_off[r+1]-1, non-decreasing, ring_vtx_off[0] == 0.
+ *   vx, vy        [ring_vtx_off[n_rings]]: vertex coordinates; a ring is
+ *                  closed implicitly (do not repeat the first vertex; a
+ *                  repeated one is a zero-length edge and is ignored).
+ * n_rings is passed explicitly so that the offsets can be validated. */
+typedef struct {
+    int64_t n_polys;
+    int64_t n_rings;
+    const int64_t *poly_ring_off;
+    const int64_t *ring_vtx_off;
+    const double *vx;
+    const double *vy;
+} spade_polys;
+
+typedef struct spade_ctx spade_ctx;
+typedef struct spade_canvas spade_canvas;
+
+/* Create a context on HIP device `device`, ordering its work on `stream`
+ * (a hipStream_t; NULL = the device's null stream).  *out receives the
+ * context.  Returns SPADE_E_HIP if the device cannot be selected. */
+int spade_ctx_create(int device, void *stream, spade_ctx **out);
+
+/* Destroy a context and free its scratch memory (NULL is a no-op). */
+void spade_ctx_destroy(spade_ctx *ctx);
+
+/* Change the stream later calls are ordered on (NULL = null stream). */
+int spade_ctx_set_stream(spade_ctx *ctx, void *stream);
+
+/* Message for the last failing call on ctx ("" if none).  Valid until the
+ * next call on ctx. */
+const char *spade_last_error(const spade_ctx *ctx);
+
+/* Canvas resolution used by later calls on ctx: width x height pixels over
+ * the polygons' bounding box (the paper's canvas resolution, Sec. 4.2).
+ * 0 x 0 selects it automatically.  Results never depend on it: it only
+ * changes how many points need the exact boundary test.  Limits:
+ * 1 <= width <= 8192, 1 <= height <= 65535. */
+int spade_ctx_set_canvas_size(spade_ctx *ctx, int32_t width, int32_t height);
+
+/* Selection (Sec. 5.2, "Spatial Selection"): ids of the points inside the
+ * single polygon of `poly` (n_polys must be 1), in ascending order.
+ * out_ids [cap] device buffer.  *n_out (host) receives the number of
+ * matching points.  If it exceeds cap, the first cap ids are written and
+ * SPADE_E_CAPACITY is returned (the paper's two-step Map, Sec. 5.1). */
+int spade_select(spade_ctx *ctx, const spade_points *pts, const spade_polys *poly,
+                 uint32_t *out_ids, int64_t cap, int64_t *n_out);
+
+/* Aggregation (Sec. 5.2, "Spatial Aggregations", plan over point data):
+ * out_counts [n_polys] device buffer, overwritten with the number of points
+ * inside each polygon.  Overlapping polygons each count the point. */
+int spade_join_count(spade_ctx *ctx, const spade_points *pts, const spade_polys *polys,
+                     uint64_t *out_counts);
+
+/* Polygon-point join (Sec. 5.2, "Spatial Joins", polygon x point): every
+ * pair (point id, polygon id) with the point inside the polygon, ascending by
+ * point id then polygon id, as two device arrays of capacity cap.  *n_out
+ * (host) receives the number of pairs; SPADE_E_CAPACITY as for select. */
+int spade_join_pairs(spade_ctx *ctx, const spade_points *pts, const spade_polys *polys,
+                     uint32_t *out_pt, uint32_t *out_poly, int64_t cap, int64_t *n_out);
+
+/* ---- Resident canvases (the constraint canvas kept on the device and
+ * probed many times; canvases are built on the fly from vector data,
+ * Sec. 4.2).  A canvas owns device memory until spade_canvas_destroy. */
+
+/* Rasterise `polys` into a new canvas on ctx's device (the polygon arrays
+ * may be freed after the call returns). */
+int spade_canvas_build(spade_ctx *ctx, const spade_polys *polys, spade_canvas **out);
+
+/* Free a canvas (NULL is a no-op).  Must not be in use by queued work. */
+void spade_canvas_destroy(spade_canvas *cv);
+
+/* Canvas facts: width, height, polygon count, boundary-pixel count and
+ * device bytes held (any pointer may be NULL). */
+int spade_canvas_info(const spade_canvas *cv, int32_t *width, int32_t *height,
+                      int64_t *n_polys, int64_t *n_boundary_pixels, int64_t *device_bytes);
+
+/* The three queries against a prebuilt canvas; same contracts as above.
+ * spade_canvas_join_count_async only enqueues (no synchronisation); its
+ * counts are complete when ctx's stream reaches that point. */
+int spade_canvas_select(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts,
+                        uint32_t *out_ids, int64_t cap, int64_t *n_out);
+int spade_canvas_join_count(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts,
+                            uint64_t *out_counts);
+int spade_canvas_join_count_async(spade_ctx *ctx, const spade_canvas *cv,
+                                  const spade_points *pts, uint64_t *out_counts);
+int spade_canvas_join_pairs(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts,
+                            uint32_t *out_pt, uint32_t *out_poly, int64_t cap, int64_t *n_out);
+
+/* Device-side exact predicate, exposed for testing the arithmetic in
+ * isolation: for n triples (a, b, c) stored as 6 device arrays, writes
+ * sign((b-a) x (c-a)) in {-1, 0, 1} to out[n] (device int32). */
+int spade_orient_batch(spade_ctx *ctx, int64_t n, const double *ax, const double *ay,
+                       const double *bx, const double *by, const double *cx,
+                       const double *cy, int32_t *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPADE_H */

@@ -1,0 +1,335 @@
+// C ABI of the canvas engine: contexts, scratch memory, argument checks and
+// the query entry points declared in include/spade.h.
+#include "common.h"
+#include "exact.h"
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+
+namespace spade {
+
+int set_error(spade_ctx *ctx, int code, const std::string &msg)
+{
+    if (ctx) ctx->err = msg;
+    return code;
+}
+
+int hip_fail(spade_ctx *ctx, hipError_t e, const char *what)
+{
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    return set_error(ctx, e == hipErrorOutOfMemory ? SPADE_E_NOMEM : SPADE_E_HIP, m);
+}
+
+void free_buf(DevBuf &b)
+{
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+}
+
+// Grow a device buffer to at least `bytes` (contents are not preserved).
+int ensure(spade_ctx *ctx, DevBuf &b, size_t bytes)
+{
+    if (bytes == 0) bytes = 1;
+    if (b.cap >= bytes) return SPADE_OK;
+    free_buf(b);
+    size_t want = bytes + bytes / 4 + 256;
+    hipError_t e = hipMalloc(&b.p, want);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        b.p = nullptr;
+        e = hipMalloc(&b.p, bytes);
+        want = bytes;
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        b.p = nullptr;
+        set_error(ctx, SPADE_E_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+        return SPADE_E_NOMEM;
+    }
+    b.cap = want;
+    return SPADE_OK;
+}
+
+void *ensure_pinned(spade_ctx *ctx, size_t bytes)
+{
+    if (ctx->pinned_cap >= bytes) return ctx->pinned;
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    ctx->pinned = nullptr;
+    ctx->pinned_cap = 0;
+    size_t want = std::max<size_t>(bytes, 4096);
+    if (hipHostMalloc(&ctx->pinned, want, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        ctx->pinned = nullptr;
+        return nullptr;
+    }
+    ctx->pinned_cap = want;
+    return ctx->pinned;
+}
+
+static int check_ctx(spade_ctx *ctx)
+{
+    if (!ctx) return SPADE_E_INVALID;
+    ctx->err.clear();
+    if (hipSetDevice(ctx->device) != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(ctx, SPADE_E_HIP, "hipSetDevice failed");
+    }
+    return SPADE_OK;
+}
+
+static int check_points(spade_ctx *ctx, const spade_points *pts)
+{
+    if (!pts) return set_error(ctx, SPADE_E_INVALID, "points is NULL");
+    if (pts->n < 0) return set_error(ctx, SPADE_E_INVALID, "negative point count");
+    if (pts->n >= (int64_t)0xffffffffLL) return set_error(ctx, SPADE_E_TOO_LARGE, "point ids are uint32: n must be < 2^32 - 1");
+    if (pts->n > 0 && (!pts->x || !pts->y)) return set_error(ctx, SPADE_E_INVALID, "point coordinate array is NULL");
+    return SPADE_OK;
+}
+
+static int check_polys(spade_ctx *ctx, const spade_polys *p)
+{
+    if (!p) return set_error(ctx, SPADE_E_INVALID, "polygon set is NULL");
+    if (p->n_polys < 0 || p->n_rings < 0) return set_error(ctx, SPADE_E_INVALID, "negative polygon or ring count");
+    if (p->n_polys >= 0x7fffffffLL) return set_error(ctx, SPADE_E_TOO_LARGE, "polygon ids must be < 2^31 - 1");
+    if (!p->poly_ring_off && p->n_rings != p->n_polys)
+        return set_error(ctx, SPADE_E_INVALID, "poly_ring_off is NULL but n_rings != n_polys");
+    if (p->poly_ring_off == nullptr && p->n_polys > 0 && !p->ring_vtx_off)
+        return set_error(ctx, SPADE_E_INVALID, "ring_vtx_off is NULL");
+    if (p->n_rings > 0 && (!p->ring_vtx_off || !p->vx || !p->vy))
+        return set_error(ctx, SPADE_E_INVALID, "ring_vtx_off / vx / vy is NULL");
+    if (p->n_polys > 0 && p->poly_ring_off == nullptr && p->n_rings == 0)
+        return set_error(ctx, SPADE_E_INVALID, "polygons without rings");
+    return SPADE_OK;
+}
+
+}  // namespace spade
+
+using namespace spade;
+
+extern "C" {
+
+int spade_ctx_create(int device, void *stream, spade_ctx **out)
+{
+    if (!out) return SPADE_E_INVALID;
+    *out = nullptr;
+    if (hipSetDevice(device) != hipSuccess) {
+        (void)hipGetLastError();
+        return SPADE_E_HIP;
+    }
+    spade_ctx *c = new (std::nothrow) spade_ctx();
+    if (!c) return SPADE_E_NOMEM;
+    c->device = device;
+    c->stream = (hipStream_t)stream;
+    *out = c;
+    return SPADE_OK;
+}
+
+void spade_ctx_destroy(spade_ctx *ctx)
+{
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (auto &b : ctx->scratch) free_buf(b);
+    if (ctx->plain) {
+        free_buf(ctx->plain->cells);
+        free_buf(ctx->plain->cands);
+        free_buf(ctx->plain->elist);
+        free_buf(ctx->plain->edges);
+        delete ctx->plain;
+    }
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    delete ctx;
+}
+
+int spade_ctx_set_stream(spade_ctx *ctx, void *stream)
+{
+    if (!ctx) return SPADE_E_INVALID;
+    ctx->stream = (hipStream_t)stream;
+    return SPADE_OK;
+}
+
+const char *spade_last_error(const spade_ctx *ctx)
+{
+    return ctx ? ctx->err.c_str() : "null context";
+}
+
+int spade_ctx_set_canvas_size(spade_ctx *ctx, int32_t width, int32_t height)
+{
+    if (!ctx) return SPADE_E_INVALID;
+    if (width == 0 && height == 0) { ctx->canvas_w = ctx->canvas_h = 0; return SPADE_OK; }
+    if (width < 1 || width > 8192 || height < 1 || height > 65535)
+        return set_error(ctx, SPADE_E_INVALID, "canvas size must be 0x0 or within 1..8192 x 1..65535");
+    ctx->canvas_w = width;
+    ctx->canvas_h = height;
+    return SPADE_OK;
+}
+
+int spade_canvas_build(spade_ctx *ctx, const spade_polys *polys, spade_canvas **out)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!out) return set_error(ctx, SPADE_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if ((rc = check_polys(ctx, polys))) return rc;
+    spade_canvas *cv = new (std::nothrow) spade_canvas();
+    if (!cv) return set_error(ctx, SPADE_E_NOMEM, "host allocation failed");
+    cv->device = ctx->device;
+    rc = build_canvas(ctx, polys, cv);
+    if (rc) {
+        spade_canvas_destroy(cv);
+        return rc;
+    }
+    *out = cv;
+    return SPADE_OK;
+}
+
+void spade_canvas_destroy(spade_canvas *cv)
+{
+    if (!cv) return;
+    (void)hipSetDevice(cv->device);
+    free_buf(cv->cells);
+    free_buf(cv->cands);
+    free_buf(cv->elist);
+    free_buf(cv->edges);
+    delete cv;
+}
+
+int spade_canvas_info(const spade_canvas *cv, int32_t *width, int32_t *height, int64_t *n_polys,
+                      int64_t *n_boundary_pixels, int64_t *device_bytes)
+{
+    if (!cv) return SPADE_E_INVALID;
+    if (width) *width = cv->view.W;
+    if (height) *height = cv->view.H;
+    if (n_polys) *n_polys = cv->view.M;
+    if (n_boundary_pixels) *n_boundary_pixels = cv->n_boundary;
+    if (device_bytes) *device_bytes = (int64_t)cv->bytes();
+    return SPADE_OK;
+}
+
+int spade_canvas_join_count_async(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts,
+                                  uint64_t *out_counts)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!cv) return set_error(ctx, SPADE_E_INVALID, "canvas is NULL");
+    if ((rc = check_points(ctx, pts))) return rc;
+    if (cv->view.M > 0 && !out_counts) return set_error(ctx, SPADE_E_INVALID, "out_counts is NULL");
+    return probe_count(ctx, cv, pts, out_counts);
+}
+
+int spade_canvas_join_count(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts,
+                            uint64_t *out_counts)
+{
+    int rc = spade_canvas_join_count_async(ctx, cv, pts, out_counts);
+    if (rc) return rc;
+    SPADE_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return SPADE_OK;
+}
+
+static int emit_common(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts,
+                       uint32_t *out_pt, uint32_t *out_poly, int64_t cap, int64_t *n_out)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!cv) return set_error(ctx, SPADE_E_INVALID, "canvas is NULL");
+    if ((rc = check_points(ctx, pts))) return rc;
+    if (!n_out) return set_error(ctx, SPADE_E_INVALID, "n_out is NULL");
+    if (cap < 0) return set_error(ctx, SPADE_E_INVALID, "negative capacity");
+    if (cap > 0 && !out_pt) return set_error(ctx, SPADE_E_INVALID, "output array is NULL");
+    return probe_emit(ctx, cv, pts, out_pt, out_poly, cap, n_out);
+}
+
+int spade_canvas_select(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts,
+                        uint32_t *out_ids, int64_t cap, int64_t *n_out)
+{
+    if (cv && cv->view.M != 1) return set_error(ctx, SPADE_E_INVALID, "selection needs exactly one polygon");
+    return emit_common(ctx, cv, pts, out_ids, nullptr, cap, n_out);
+}
+
+int spade_canvas_join_pairs(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts,
+                            uint32_t *out_pt, uint32_t *out_poly, int64_t cap, int64_t *n_out)
+{
+    if (cap > 0 && !out_poly) return set_error(ctx, SPADE_E_INVALID, "out_poly is NULL");
+    return emit_common(ctx, cv, pts, out_pt, out_poly, cap, n_out);
+}
+
+// Plain calls: rasterise into the context's own canvas, then probe.
+static int plain_build(spade_ctx *ctx, const spade_polys *polys, spade_canvas **cvo)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if ((rc = check_polys(ctx, polys))) return rc;
+    if (!ctx->plain) {
+        ctx->plain = new (std::nothrow) spade_canvas();
+        if (!ctx->plain) return set_error(ctx, SPADE_E_NOMEM, "host allocation failed");
+        ctx->plain->device = ctx->device;
+    }
+    rc = build_canvas(ctx, polys, ctx->plain);
+    if (rc) return rc;
+    *cvo = ctx->plain;
+    return SPADE_OK;
+}
+
+int spade_select(spade_ctx *ctx, const spade_points *pts, const spade_polys *poly, uint32_t *out_ids,
+                 int64_t cap, int64_t *n_out)
+{
+    if (!ctx) return SPADE_E_INVALID;
+    if (n_out) *n_out = 0;
+    if (poly && poly->n_polys != 1) return set_error(ctx, SPADE_E_INVALID, "selection needs exactly one polygon");
+    int rc = check_points(ctx, pts);
+    if (rc) return rc;
+    spade_canvas *cv = nullptr;
+    if ((rc = plain_build(ctx, poly, &cv))) return rc;
+    return spade_canvas_select(ctx, cv, pts, out_ids, cap, n_out);
+}
+
+int spade_join_count(spade_ctx *ctx, const spade_points *pts, const spade_polys *polys, uint64_t *out_counts)
+{
+    if (!ctx) return SPADE_E_INVALID;
+    int rc = check_points(ctx, pts);
+    if (rc) return rc;
+    spade_canvas *cv = nullptr;
+    if ((rc = plain_build(ctx, polys, &cv))) return rc;
+    return spade_canvas_join_count(ctx, cv, pts, out_counts);
+}
+
+int spade_join_pairs(spade_ctx *ctx, const spade_points *pts, const spade_polys *polys, uint32_t *out_pt,
+                     uint32_t *out_poly, int64_t cap, int64_t *n_out)
+{
+    if (!ctx) return SPADE_E_INVALID;
+    if (n_out) *n_out = 0;
+    int rc = check_points(ctx, pts);
+    if (rc) return rc;
+    spade_canvas *cv = nullptr;
+    if ((rc = plain_build(ctx, polys, &cv))) return rc;
+    return spade_canvas_join_pairs(ctx, cv, pts, out_pt, out_poly, cap, n_out);
+}
+
+// ---- exact predicate, exposed for isolated testing
+
+__global__ void k_orient(int64_t n, const double *ax, const double *ay, const double *bx, const double *by,
+                         const double *cx, const double *cy, int32_t *out)
+{
+    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += nth)
+        out[i] = orient_sign(ax[i], ay[i], bx[i], by[i], cx[i], cy[i]);
+}
+
+int spade_orient_batch(spade_ctx *ctx, int64_t n, const double *ax, const double *ay, const double *bx,
+                       const double *by, const double *cx, const double *cy, int32_t *out)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (n < 0) return set_error(ctx, SPADE_E_INVALID, "negative count");
+    if (n == 0) return SPADE_OK;
+    if (!ax || !ay || !bx || !by || !cx || !cy || !out) return set_error(ctx, SPADE_E_INVALID, "NULL array");
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192));
+    hipLaunchKernelGGL(k_orient, dim3(grid), dim3(256), 0, ctx->stream, n, ax, ay, bx, by, cx, cy, out);
+    SPADE_HIP(ctx, hipGetLastError());
+    SPADE_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return SPADE_OK;
+}
+
+}  // extern "C"

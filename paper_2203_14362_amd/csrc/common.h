@@ -1,0 +1,115 @@
+// Internal declarations of the canvas engine (device structs, context,
+// scratch management).  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+#include <vector>
+
+#include "../../include/spade.h"
+
+namespace spade {
+
+// Canvas word (one uint32 per pixel):
+//   0                  : the pixel lies in no polygon
+//   1 .. 2^31-1        : every point of the pixel lies in polygon (word - 1)
+//                        and in no other
+//   BFLAG | r          : boundary pixel; its candidate records start at index
+//                        r of the record array and run up to a record flagged
+//                        LAST.
+// This is the paper's discrete canvas (Sec. 4.1: an object id plus a pointer
+// v_b into the boundary index) restricted to polygons.
+constexpr uint32_t BFLAG = 0x80000000u;
+
+// Candidate record of a boundary pixel for one polygon (the boundary index
+// entry, Sec. 4.3).  A point p of the pixel is inside polygon `poly` iff
+//     S  XOR  (XOR over partial-right edges e of straddle(e, p.y))
+//        XOR  (XOR over local edges e of cross(e, p))
+// where local edges touch the (margin-dilated) pixel, partial-right edges lie
+// entirely to its right but end inside the pixel row, and S is the parity of
+// the edges entirely to the right that span the whole row.
+struct Cand {
+    uint32_t poly;
+    uint32_t meta;   // bit 0: S, bit 1: last record of the pixel, bits 2..31: n_local
+    uint32_t eoff;   // first edge id in the edge-index list
+    uint32_t npart;  // partial-right edges following the n_local local ones
+};
+constexpr uint32_t CAND_S = 1u;
+constexpr uint32_t CAND_LAST = 2u;
+
+// Edge in world coordinates with lo.y <= hi.y.
+struct Edge {
+    double xlo, ylo, xhi, yhi;
+};
+
+// Everything a probe kernel needs, passed by value.
+struct CanvasView {
+    double X0, Y0, sx, sy;        // pixel u = (x - X0) * sx, v = (y - Y0) * sy
+    double bx0, by0, bx1, by1;    // half-open bounding box of all polygons
+    int32_t W, H;
+    int64_t M;                    // number of polygons
+    const uint32_t *cells;        // W * H words, row-major
+    const Cand *cands;
+    const uint32_t *elist;
+    const Edge *edges;
+};
+
+// Growable device buffer owned by a context or canvas.
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+};
+
+}  // namespace spade
+
+struct spade_canvas {
+    int device = 0;
+    spade::CanvasView view{};
+    int64_t n_boundary = 0;
+    int64_t n_cands = 0;
+    int64_t n_elist = 0;
+    int64_t n_edges = 0;
+    spade::DevBuf cells, cands, elist, edges;
+    size_t bytes() const { return cells.cap + cands.cap + elist.cap + edges.cap; }
+};
+
+struct spade_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    int32_t canvas_w = 0, canvas_h = 0;     // 0 = automatic
+    spade::DevBuf scratch[16];              // reusable scratch slots
+    void *pinned = nullptr;                 // small pinned host staging area
+    spade_canvas *plain = nullptr;          // canvas reused by the plain query calls
+    size_t pinned_cap = 0;
+};
+
+namespace spade {
+
+// Scratch slot ids inside a context.
+enum Slot {
+    S_BLOCKRED = 0, S_RINGPOLY, S_NROWS, S_ROWOFF, S_KEYS, S_KEYS2, S_VALS, S_VALS2,
+    S_ENTC, S_ENTF, S_CUBTMP, S_ROWCNT, S_NEXTP, S_PROBE, S_LOOKBACK, S_MISC
+};
+
+int set_error(spade_ctx *ctx, int code, const std::string &msg);
+int hip_fail(spade_ctx *ctx, hipError_t e, const char *what);
+int ensure(spade_ctx *ctx, DevBuf &b, size_t bytes);
+void *ensure_pinned(spade_ctx *ctx, size_t bytes);
+void free_buf(DevBuf &b);
+
+int build_canvas(spade_ctx *ctx, const spade_polys *polys, spade_canvas *cv);
+
+int probe_count(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts,
+                uint64_t *out_counts);
+int probe_emit(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts,
+               uint32_t *out_pt, uint32_t *out_poly, int64_t cap, int64_t *n_out);
+
+}  // namespace spade
+
+#define SPADE_HIP(ctx, call)                                               \
+    do {                                                                   \
+        hipError_t e_ = (call);                                            \
+        if (e_ != hipSuccess) return spade::hip_fail((ctx), e_, #call);    \
+    } while (0)

@@ -1,0 +1,294 @@
+"""Python binding of libspade.so: argument marshalling only.
+
+Every step of a query (rasterisation, probing, exact tests, counting,
+ordered compaction) runs in the library's HIP kernels.  torch supplies device
+memory and the current stream.  The binding refuses to run without the
+compiled library: there is no fallback implementation.
+
+Polygon sets are dicts in CSR layout (see ``workloads.gen``) with host numpy
+arrays or device tensors: ``n_polys``, ``poly_ring_off`` (or None),
+``ring_vtx_off``, ``vx``, ``vy``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libspade.so")
+
+SPADE_OK = 0
+SPADE_E_INVALID = -1
+SPADE_E_CAPACITY = -2
+SPADE_E_NOMEM = -3
+SPADE_E_HIP = -4
+SPADE_E_UNSUPPORTED = -5
+SPADE_E_TOO_LARGE = -6
+
+EXPORTS = [
+    "spade_ctx_create", "spade_ctx_destroy", "spade_ctx_set_stream", "spade_last_error",
+    "spade_ctx_set_canvas_size", "spade_select", "spade_join_count", "spade_join_pairs",
+    "spade_canvas_build", "spade_canvas_destroy", "spade_canvas_info", "spade_canvas_select",
+    "spade_canvas_join_count", "spade_canvas_join_count_async", "spade_canvas_join_pairs",
+    "spade_orient_batch",
+]
+
+
+class SpadeError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("spade error %d: %s" % (code, msg))
+        self.code = code
+
+
+class _Points(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("x", ctypes.c_void_p), ("y", ctypes.c_void_p)]
+
+
+class _Polys(ctypes.Structure):
+    _fields_ = [("n_polys", ctypes.c_int64), ("n_rings", ctypes.c_int64),
+                ("poly_ring_off", ctypes.c_void_p), ("ring_vtx_off", ctypes.c_void_p),
+                ("vx", ctypes.c_void_p), ("vy", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load_library():
+    """Load libspade.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libspade.so is missing: build it with paper_2203_14362_amd.build.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    P = ctypes.POINTER
+    lib.spade_ctx_create.argtypes = [ctypes.c_int, vp, P(vp)]
+    lib.spade_ctx_destroy.argtypes = [vp]
+    lib.spade_ctx_destroy.restype = None
+    lib.spade_ctx_set_stream.argtypes = [vp, vp]
+    lib.spade_last_error.argtypes = [vp]
+    lib.spade_last_error.restype = ctypes.c_char_p
+    lib.spade_ctx_set_canvas_size.argtypes = [vp, i32, i32]
+    lib.spade_select.argtypes = [vp, P(_Points), P(_Polys), vp, i64, P(i64)]
+    lib.spade_join_count.argtypes = [vp, P(_Points), P(_Polys), vp]
+    lib.spade_join_pairs.argtypes = [vp, P(_Points), P(_Polys), vp, vp, i64, P(i64)]
+    lib.spade_canvas_build.argtypes = [vp, P(_Polys), P(vp)]
+    lib.spade_canvas_destroy.argtypes = [vp]
+    lib.spade_canvas_destroy.restype = None
+    lib.spade_canvas_info.argtypes = [vp, P(i32), P(i32), P(i64), P(i64), P(i64)]
+    lib.spade_canvas_select.argtypes = [vp, vp, P(_Points), vp, i64, P(i64)]
+    lib.spade_canvas_join_count.argtypes = [vp, vp, P(_Points), vp]
+    lib.spade_canvas_join_count_async.argtypes = [vp, vp, P(_Points), vp]
+    lib.spade_canvas_join_pairs.argtypes = [vp, vp, P(_Points), vp, vp, i64, P(i64)]
+    lib.spade_orient_batch.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp]
+    for name in EXPORTS:
+        f = getattr(lib, name)
+        if f.restype is ctypes.c_int:
+            f.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _dev_f64(a, device):
+    if isinstance(a, torch.Tensor):
+        t = a.to(device=device, dtype=torch.float64)
+    else:
+        t = torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(device)
+    return t.contiguous()
+
+
+def _dev_i64(a, device):
+    if isinstance(a, torch.Tensor):
+        t = a.to(device=device, dtype=torch.int64)
+    else:
+        t = torch.from_numpy(np.ascontiguousarray(a, dtype=np.int64)).to(device)
+    return t.contiguous()
+
+
+class DevicePolys:
+    """A polygon set resident on the device, in the C ABI's CSR layout."""
+
+    def __init__(self, polys, device):
+        self.n_polys = int(polys["n_polys"])
+        pro = polys.get("poly_ring_off")
+        self.ring_vtx_off = _dev_i64(polys["ring_vtx_off"], device)
+        self.n_rings = int(self.ring_vtx_off.numel()) - 1
+        self.poly_ring_off = None if pro is None else _dev_i64(pro, device)
+        self.vx = _dev_f64(polys["vx"], device)
+        self.vy = _dev_f64(polys["vy"], device)
+
+    def cstruct(self):
+        return _Polys(self.n_polys, self.n_rings,
+                      0 if self.poly_ring_off is None else self.poly_ring_off.data_ptr(),
+                      self.ring_vtx_off.data_ptr() if self.ring_vtx_off.numel() else 0,
+                      self.vx.data_ptr() if self.vx.numel() else 0,
+                      self.vy.data_ptr() if self.vy.numel() else 0)
+
+
+def _points(x, y):
+    if x.dtype != torch.float64 or y.dtype != torch.float64:
+        raise TypeError("points must be float64 tensors")
+    if x.shape != y.shape or x.dim() != 1:
+        raise ValueError("x and y must be 1-D tensors of equal length")
+    if not (x.is_contiguous() and y.is_contiguous()):
+        raise ValueError("point arrays must be contiguous")
+    n = x.numel()
+    return _Points(n, x.data_ptr() if n else 0, y.data_ptr() if n else 0)
+
+
+class Canvas:
+    """A rasterised polygon set resident on the device."""
+
+    def __init__(self, ctx: "Context", handle):
+        self.ctx = ctx
+        self.handle = handle
+
+    def info(self):
+        w, h = ctypes.c_int32(), ctypes.c_int32()
+        m, nb, by = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        self.ctx.lib.spade_canvas_info(self.handle, ctypes.byref(w), ctypes.byref(h), ctypes.byref(m),
+                                       ctypes.byref(nb), ctypes.byref(by))
+        return {"width": w.value, "height": h.value, "n_polys": m.value,
+                "boundary_pixels": nb.value, "device_bytes": by.value}
+
+    def close(self):
+        if self.handle:
+            self.ctx.lib.spade_canvas_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Context:
+    """One spade_ctx bound to a device; calls run on torch's current stream."""
+
+    def __init__(self, device=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("a HIP device is required")
+        self.lib = load_library()
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else
+                                   torch.device(device).index or 0)
+        h = ctypes.c_void_p()
+        rc = self.lib.spade_ctx_create(self.device.index, None, ctypes.byref(h))
+        if rc != SPADE_OK:
+            raise SpadeError(rc, "spade_ctx_create failed")
+        self.handle = h
+
+    # -- helpers
+    def _check(self, rc):
+        if rc != SPADE_OK:
+            raise SpadeError(rc, self.lib.spade_last_error(self.handle).decode())
+
+    def _sync_stream(self):
+        s = torch.cuda.current_stream(self.device)
+        self.lib.spade_ctx_set_stream(self.handle, ctypes.c_void_p(s.cuda_stream))
+
+    def set_canvas_size(self, width: int = 0, height: int = 0):
+        self._check(self.lib.spade_ctx_set_canvas_size(self.handle, int(width), int(height)))
+
+    def polys(self, polys):
+        return polys if isinstance(polys, DevicePolys) else DevicePolys(polys, self.device)
+
+    # -- canvases
+    def canvas(self, polys) -> Canvas:
+        self._sync_stream()
+        dp = self.polys(polys)
+        h = ctypes.c_void_p()
+        self._check(self.lib.spade_canvas_build(self.handle, ctypes.byref(dp.cstruct()), ctypes.byref(h)))
+        return Canvas(self, h)
+
+    # -- queries
+    def join_count(self, x, y, polys_or_canvas, out=None, sync=True):
+        """Per-polygon counts as an int64 tensor (values are the uint64 counts)."""
+        self._sync_stream()
+        P = _points(x, y)
+        if isinstance(polys_or_canvas, Canvas):
+            M = polys_or_canvas.info()["n_polys"]
+        else:
+            dp = self.polys(polys_or_canvas)
+            M = dp.n_polys
+        if out is None:
+            out = torch.empty(M, dtype=torch.int64, device=self.device)
+        optr = out.data_ptr() if M else 0
+        if isinstance(polys_or_canvas, Canvas):
+            fn = self.lib.spade_canvas_join_count if sync else self.lib.spade_canvas_join_count_async
+            self._check(fn(self.handle, polys_or_canvas.handle, ctypes.byref(P), ctypes.c_void_p(optr)))
+        else:
+            self._check(self.lib.spade_join_count(self.handle, ctypes.byref(P),
+                                                  ctypes.byref(dp.cstruct()), ctypes.c_void_p(optr)))
+        return out
+
+    def _emit(self, x, y, target, pairs, cap):
+        P = _points(x, y)
+        n = P.n
+        if cap is None:
+            cap = max(n, 1)
+        while True:
+            pt = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device)
+            pg = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device) if pairs else None
+            nout = ctypes.c_int64()
+            self._sync_stream()
+            if isinstance(target, Canvas):
+                if pairs:
+                    rc = self.lib.spade_canvas_join_pairs(self.handle, target.handle, ctypes.byref(P),
+                                                          ctypes.c_void_p(pt.data_ptr()),
+                                                          ctypes.c_void_p(pg.data_ptr()), cap,
+                                                          ctypes.byref(nout))
+                else:
+                    rc = self.lib.spade_canvas_select(self.handle, target.handle, ctypes.byref(P),
+                                                      ctypes.c_void_p(pt.data_ptr()), cap, ctypes.byref(nout))
+            else:
+                dp = self.polys(target)
+                if pairs:
+                    rc = self.lib.spade_join_pairs(self.handle, ctypes.byref(P), ctypes.byref(dp.cstruct()),
+                                                   ctypes.c_void_p(pt.data_ptr()), ctypes.c_void_p(pg.data_ptr()),
+                                                   cap, ctypes.byref(nout))
+                else:
+                    rc = self.lib.spade_select(self.handle, ctypes.byref(P), ctypes.byref(dp.cstruct()),
+                                               ctypes.c_void_p(pt.data_ptr()), cap, ctypes.byref(nout))
+            if rc == SPADE_E_CAPACITY:
+                cap = int(nout.value)
+                continue
+            self._check(rc)
+            m = int(nout.value)
+            return (pt[:m], pg[:m]) if pairs else pt[:m]
+
+    def select(self, x, y, poly_or_canvas, cap=None):
+        """Ascending ids (int32 tensor) of the points inside the one polygon."""
+        return self._emit(x, y, poly_or_canvas, False, cap)
+
+    def join_pairs(self, x, y, polys_or_canvas, cap=None):
+        """(point ids, polygon ids) int32 tensors, ascending by (point, polygon)."""
+        return self._emit(x, y, polys_or_canvas, True, cap)
+
+    def orient(self, a, b, c):
+        """Device exact orientation signs for (n,2) float64 tensors a, b, c."""
+        self._sync_stream()
+        a = a.to(self.device, torch.float64).contiguous()
+        b = b.to(self.device, torch.float64).contiguous()
+        c = c.to(self.device, torch.float64).contiguous()
+        cols = [t[:, i].contiguous() for t in (a, b, c) for i in (0, 1)]
+        n = a.shape[0]
+        out = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
+        self._check(self.lib.spade_orient_batch(self.handle, n, *[ctypes.c_void_p(t.data_ptr()) for t in cols],
+                                                ctypes.c_void_p(out.data_ptr())))
+        return out[:n]
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.spade_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
