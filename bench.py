@@ -1,0 +1,180 @@
+#!/usr/bin/env python3
+"""Benchmark of the canvas point-in-polygon join-count on one MI355X.
+
+Workload (the headline configuration): 100,000,000 FP64 points drawn from a
+taxi-like mixture of 32 anisotropic Gaussians over a 60 x 60 km extent
+(seed 2) against 260 Voronoi-tessellation polygons whose shared edges are
+jittered to 50..500 vertices (seed 2); output: exact per-polygon counts.
+
+A step is one whole join-count with every input already resident in HBM:
+rasterising the polygons into the canvas and boundary index, then probing
+every point (spade_join_count).  ``value`` is points per second of whole
+steps.  The probe kernel's duration is taken with HIP events on the stream
+it runs on (the library's phase timers) over the timed steps; its roofline
+entry prices 16 algorithmic bytes per point (two float64 coordinates)
+against the 8 TB/s HBM peak.  ``cpu_baseline`` times the CPU oracle on a
+bounded prefix of the same points with every host core.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "points/sec for PIP join-count (bit-exact) + % HBM peak; p50/p99 served query latency"
+PEAK_HBM_GBS = 8000.0
+BYTES_PER_POINT = 16.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("probe.hip", "exact.h", "common.h"):
+        with open(os.path.join(ROOT, "paper_2203_14362_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(n_points):
+    """HBM bytes per probe launch from committed rocprofv3 counter runs, if
+    they were taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "k_count_join_c100m_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("kernel_source_hash") != kernel_source_hash() or int(d.get("n_points", -1)) != n_points:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--points", type=int, default=100_000_000)
+    ap.add_argument("--polygons", type=int, default=260)
+    ap.add_argument("--canvas", type=int, nargs=2, default=(0, 0), metavar=("W", "H"))
+    ap.add_argument("--cpu-sample", type=int, default=40_000_000,
+                    help="points of the prefix timed with the CPU oracle (0 = skip)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        log("bench.py measures one GPU: this build runs on a single MI355X and has no "
+            "multi-GPU path (--gpus %d requested)." % args.gpus)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from workloads import gen
+    from paper_2203_14362_amd import Context
+
+    N = args.points
+    t = time.time()
+    x, y = gen.mixture_points(N, seed=2, L=gen.EXTENT_M)
+    polys, info = gen.voronoi_jitter(args.polygons, 50, 500, seed=2, L=gen.EXTENT_M, return_info=True)
+    log("inputs: %d points, %d polygons (%d vertices) generated in %.1fs"
+        % (N, polys["n_polys"], int(info["vertex_counts"].sum()), time.time() - t))
+
+    ctx = Context(0)
+    ctx.set_canvas_size(*args.canvas)
+    dx = torch.from_numpy(x).cuda()
+    dy = torch.from_numpy(y).cuda()
+    dpolys = ctx.polys(polys)
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+
+    for _ in range(args.warmup):
+        counts = ctx.join_count(dx, dy, dpolys)
+    torch.cuda.synchronize()
+    total = int(counts.sum().item())
+    if total != N:
+        raise SystemExit("counts sum to %d, expected %d (tessellation covers every point)" % (total, N))
+    log("warmup done")
+
+    raster_ms, probe_ms = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        counts = ctx.join_count(dx, dy, dpolys)
+        r, p = ctx.last_timing()
+        raster_ms.append(r)
+        probe_ms.append(p)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1000.0 / args.steps
+    gpu_counts = counts.cpu().numpy().astype(np.uint64)
+    log("timed %d steps: %.3f ms/step (raster %.3f ms, probe %.3f ms)"
+        % (args.steps, ms_per_step, float(np.mean(raster_ms)), float(np.mean(probe_ms))))
+
+    cv = ctx.canvas(dpolys)
+    cinfo = cv.info()
+    cv.close()
+
+    probe_s = float(np.mean(probe_ms)) / 1000.0
+    achieved = BYTES_PER_POINT * N / probe_s / 1e9
+    traffic = load_traffic(N)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+                "kernel": "k_count", "bytes_per_point": BYTES_PER_POINT,
+                "points_per_launch": N, "avg_launch_ms": round(probe_s * 1000.0, 4)}
+
+    cpu = None
+    S = min(args.cpu_sample, N)
+    if S > 0:
+        import oracle
+        t = time.time()
+        want = oracle.join_count(x[:S], y[:S], polys)
+        dt = time.time() - t
+        sub = ctx.join_count(dx[:S].contiguous(), dy[:S].contiguous(), dpolys).cpu().numpy().astype(np.uint64)
+        parity = bool(np.array_equal(sub, want))
+        cpu = {"value": round(S / dt, 1), "unit": "points/s", "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": "first %d of the %d points, all %d polygons, join-count" % (S, N, polys["n_polys"]),
+               "seconds": round(dt, 2), "gpu_matches_oracle_on_sample": parity}
+        log("cpu oracle: %d points in %.2fs on %d threads; GPU parity on sample: %s"
+            % (S, dt, oracle.num_threads(), parity))
+        if not parity:
+            raise SystemExit("GPU counts differ from the oracle on the sample")
+
+    out = {
+        "metric": METRIC,
+        "value": round(N / (ms_per_step / 1000.0), 1),
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "join-count: 100M taxi-like clustered FP64 points (32-Gaussian mixture, "
+                               "60x60 km) x 260 Voronoi-jitter polygons (50-500 vertices)",
+                   "points": N, "polygons": polys["n_polys"],
+                   "vertices": int(info["vertex_counts"].sum()),
+                   "canvas": [cinfo["width"], cinfo["height"]],
+                   "boundary_pixels": cinfo["boundary_pixels"],
+                   "raster_ms": round(float(np.mean(raster_ms)), 4),
+                   "probe_ms": round(float(np.mean(probe_ms)), 4),
+                   "probe_points_per_s": round(N / probe_s, 1),
+                   "counts_sum": int(gpu_counts.sum())},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

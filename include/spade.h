@@ -112,6 +112,14 @@ const char *spade_last_error(const spade_ctx *ctx);
  * 1 <= width <= 8192, 1 <= height <= 65535. */
 int spade_ctx_set_canvas_size(spade_ctx *ctx, int32_t width, int32_t height);
 
+/* Phase timing (tracing aid).  on != 0 makes later query calls record HIP
+ * events on ctx's stream around the rasterisation and around the probe
+ * kernel; spade_ctx_last_timing waits for the last probe and returns both
+ * durations in milliseconds (raster_ms is 0 when the last query used a
+ * prebuilt canvas).  Either out-pointer may be NULL. */
+int spade_ctx_set_timing(spade_ctx *ctx, int on);
+int spade_ctx_last_timing(spade_ctx *ctx, float *raster_ms, float *probe_ms);
+
 /* Selection (Sec. 5.2, "Spatial Selection"): ids of the points inside the
  * single polygon of `poly` (n_polys must be 1), in ascending order.
  * out_ids [cap] device buffer.  *n_out (host) receives the number of

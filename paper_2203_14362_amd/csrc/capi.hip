@@ -135,11 +135,15 @@ void spade_ctx_destroy(spade_ctx *ctx)
     if (ctx->plain) {
         free_buf(ctx->plain->cells);
         free_buf(ctx->plain->cands);
-        free_buf(ctx->plain->elist);
+        free_buf(ctx->plain->ledges);
+        free_buf(ctx->plain->pspan);
         free_buf(ctx->plain->edges);
+        free_buf(ctx->plain->coarse);
         delete ctx->plain;
     }
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    for (auto &e : ctx->ev)
+        if (e) (void)hipEventDestroy(e);
     delete ctx;
 }
 
@@ -163,6 +167,31 @@ int spade_ctx_set_canvas_size(spade_ctx *ctx, int32_t width, int32_t height)
         return set_error(ctx, SPADE_E_INVALID, "canvas size must be 0x0 or within 1..8192 x 1..65535");
     ctx->canvas_w = width;
     ctx->canvas_h = height;
+    return SPADE_OK;
+}
+
+int spade_ctx_set_timing(spade_ctx *ctx, int on)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (on && !ctx->ev[0])
+        for (auto &e : ctx->ev) SPADE_HIP(ctx, hipEventCreate(&e));
+    ctx->timing = on != 0;
+    ctx->timed_raster = false;
+    return SPADE_OK;
+}
+
+int spade_ctx_last_timing(spade_ctx *ctx, float *raster_ms, float *probe_ms)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!ctx->timing) return set_error(ctx, SPADE_E_INVALID, "timing is not enabled");
+    SPADE_HIP(ctx, hipEventSynchronize(ctx->ev[3]));
+    float r = 0.f, p = 0.f;
+    if (ctx->timed_raster) SPADE_HIP(ctx, hipEventElapsedTime(&r, ctx->ev[0], ctx->ev[1]));
+    SPADE_HIP(ctx, hipEventElapsedTime(&p, ctx->ev[2], ctx->ev[3]));
+    if (raster_ms) *raster_ms = r;
+    if (probe_ms) *probe_ms = p;
     return SPADE_OK;
 }
 
@@ -191,8 +220,10 @@ void spade_canvas_destroy(spade_canvas *cv)
     (void)hipSetDevice(cv->device);
     free_buf(cv->cells);
     free_buf(cv->cands);
-    free_buf(cv->elist);
+    free_buf(cv->ledges);
+    free_buf(cv->pspan);
     free_buf(cv->edges);
+    free_buf(cv->coarse);
     delete cv;
 }
 
@@ -216,6 +247,7 @@ int spade_canvas_join_count_async(spade_ctx *ctx, const spade_canvas *cv, const 
     if (!cv) return set_error(ctx, SPADE_E_INVALID, "canvas is NULL");
     if ((rc = check_points(ctx, pts))) return rc;
     if (cv->view.M > 0 && !out_counts) return set_error(ctx, SPADE_E_INVALID, "out_counts is NULL");
+    if (cv != ctx->plain) ctx->timed_raster = false;
     return probe_count(ctx, cv, pts, out_counts);
 }
 
@@ -238,6 +270,7 @@ static int emit_common(spade_ctx *ctx, const spade_canvas *cv, const spade_point
     if (!n_out) return set_error(ctx, SPADE_E_INVALID, "n_out is NULL");
     if (cap < 0) return set_error(ctx, SPADE_E_INVALID, "negative capacity");
     if (cap > 0 && !out_pt) return set_error(ctx, SPADE_E_INVALID, "output array is NULL");
+    if (cv != ctx->plain) ctx->timed_raster = false;
     return probe_emit(ctx, cv, pts, out_pt, out_poly, cap, n_out);
 }
 
@@ -266,8 +299,11 @@ static int plain_build(spade_ctx *ctx, const spade_polys *polys, spade_canvas **
         if (!ctx->plain) return set_error(ctx, SPADE_E_NOMEM, "host allocation failed");
         ctx->plain->device = ctx->device;
     }
+    if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[0], ctx->stream));
     rc = build_canvas(ctx, polys, ctx->plain);
     if (rc) return rc;
+    if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[1], ctx->stream));
+    ctx->timed_raster = ctx->timing;
     *cvo = ctx->plain;
     return SPADE_OK;
 }

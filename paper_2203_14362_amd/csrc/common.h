@@ -28,14 +28,19 @@ constexpr uint32_t BFLAG = 0x80000000u;
 //        XOR  (XOR over local edges e of cross(e, p))
 // where local edges touch the (margin-dilated) pixel, partial-right edges lie
 // entirely to its right but end inside the pixel row, and S is the parity of
-// the edges entirely to the right that span the whole row.
+// the edges entirely to the right that span the whole row.  Local edges are
+// stored with their coordinates (contiguous from eoff); partial-right edges
+// only need their y-range (contiguous from poff).
 struct Cand {
     uint32_t poly;
-    uint32_t meta;   // bit 0: S, bit 1: last record of the pixel, bits 2..31: n_local
-    uint32_t eoff;   // first edge id in the edge-index list
-    uint32_t npart;  // partial-right edges following the n_local local ones
+    uint32_t meta;   // bit 0: S, bit 1: last record of the pixel,
+                     // bits 2..16: n_local, bits 17..31: n_partial
+    uint32_t eoff;   // first local edge in the local-edge array
+    uint32_t poff;   // first partial-right y-range in the span array
 };
 constexpr uint32_t CAND_S = 1u;
+// Coarse canvas word of a block whose pixels do not all share one label.
+constexpr uint16_t COARSE_MIXED = 0x8000u;
 constexpr uint32_t CAND_LAST = 2u;
 
 // Edge in world coordinates with lo.y <= hi.y.
@@ -48,11 +53,14 @@ struct CanvasView {
     double X0, Y0, sx, sy;        // pixel u = (x - X0) * sx, v = (y - Y0) * sy
     double bx0, by0, bx1, by1;    // half-open bounding box of all polygons
     int32_t W, H;
+    int32_t Wt;                   // 16 x 16 pixel tiles per canvas row
+    int32_t Wc, Hc, blog;         // coarse grid: one word per 2^blog x 2^blog pixels
     int64_t M;                    // number of polygons
-    const uint32_t *cells;        // W * H words, row-major
+    const uint32_t *cells;        // canvas words, tile-major (16 x 16 tiles)
+    const uint16_t *coarse;       // Wc * Hc coarse words, row-major
     const Cand *cands;
-    const uint32_t *elist;
-    const Edge *edges;
+    const Edge *ledges;           // local edges of the records
+    const double2 *pspan;         // (ylo, yhi) of partial-right edges
 };
 
 // Growable device buffer owned by a context or canvas.
@@ -70,8 +78,8 @@ struct spade_canvas {
     int64_t n_cands = 0;
     int64_t n_elist = 0;
     int64_t n_edges = 0;
-    spade::DevBuf cells, cands, elist, edges;
-    size_t bytes() const { return cells.cap + cands.cap + elist.cap + edges.cap; }
+    spade::DevBuf cells, cands, ledges, pspan, edges, coarse;
+    size_t bytes() const { return cells.cap + cands.cap + ledges.cap + pspan.cap + coarse.cap; }
 };
 
 struct spade_ctx {
@@ -82,6 +90,9 @@ struct spade_ctx {
     spade::DevBuf scratch[16];              // reusable scratch slots
     void *pinned = nullptr;                 // small pinned host staging area
     spade_canvas *plain = nullptr;          // canvas reused by the plain query calls
+    bool timing = false;                    // record phase events (raster, probe)
+    bool timed_raster = false;              // last query rasterised under timing
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     size_t pinned_cap = 0;
 };
 
@@ -100,6 +111,10 @@ void *ensure_pinned(spade_ctx *ctx, size_t bytes);
 void free_buf(DevBuf &b);
 
 int build_canvas(spade_ctx *ctx, const spade_polys *polys, spade_canvas *cv);
+
+// LDS bytes the count probe leaves for the coarse canvas, given the polygon
+// count (its histogram shares the LDS).
+size_t coarse_lds_budget(int64_t M);
 
 int probe_count(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts,
                 uint64_t *out_counts);

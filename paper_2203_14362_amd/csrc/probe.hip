@@ -2,14 +2,20 @@
 // (aggregation) and mask + Map (selection / join) applied to a stream of
 // points (Sec. 5.1, 5.2), as compute kernels.
 //
-// Every point is read once from HBM (FP64 structure of arrays, coalesced),
-// rejected if it lies outside the half-open bounding box of the polygons,
-// mapped to its pixel and classified by the canvas word: a label is final,
-// a boundary pixel runs the exact test of each candidate polygon.
+// Every point is read once from HBM (FP64 structure of arrays, coalesced,
+// non-temporal), rejected if it lies outside the half-open bounding box of
+// the polygons and mapped to its pixel.  The pixel is classified in two
+// levels: a coarse canvas held in LDS by every workgroup answers directly
+// for blocks whose pixels share one label; points in mixed blocks read their
+// canvas word from the tile-major canvas in global memory (L2 / MALL).  A
+// label is final; a boundary pixel needs the exact test of each candidate
+// polygon.  Boundary points are compacted per wavefront (ballot + prefix
+// count) into an LDS queue and tested in full wavefronts, so the rare,
+// latency-bound exact tests do not stall the stream.
 //
 //   k_count  per-polygon counts: workgroup-private histograms in LDS
-//            (additive blend), flushed with one 64-bit atomic per polygon and
-//            workgroup; polygon sets too large for LDS use global atomics.
+//            (additive blend), flushed into a context accumulator; the last
+//            workgroup copies the counts out and clears the accumulator.
 //   k_emit   ordered output (point ids, or (point, polygon) pairs ascending):
 //            the paper's Map into a null-padded list plus a scan, fused into
 //            one pass with a decoupled look-back prefix over chunks of points
@@ -21,12 +27,31 @@
 
 namespace spade {
 
-constexpr int PROBE_THREADS = 256;
-constexpr int HIST_MAX = 16384;           // polygons counted in LDS
-constexpr int EMIT_ITEMS = 16;            // points per thread per chunk
-constexpr int EMIT_CHUNK = PROBE_THREADS * EMIT_ITEMS;
+constexpr int CNT_THREADS = 1024;         // count probe workgroup
+constexpr int CNT_UNROLL = 4;             // points per thread per iteration
+constexpr int QCAP = 64;                  // boundary queue entries per wavefront
+constexpr int HIST_MAX = 8192;            // polygons counted in LDS
+constexpr int EMIT_THREADS = 512;
+constexpr int EMIT_ITEMS = 8;             // points per thread per chunk
+constexpr int EMIT_CHUNK = EMIT_THREADS * EMIT_ITEMS;
+constexpr size_t LDS_TOTAL = 160 * 1024;
+constexpr size_t LDS_RESERVE = 2048;      // static LDS of the kernels
+constexpr size_t QUEUE_BYTES = (size_t)(CNT_THREADS / 64) * QCAP * 20;
 
-__device__ __forceinline__ uint32_t canvas_word(const CanvasView &cv, double x, double y)
+size_t coarse_lds_budget(int64_t M)
+{
+    size_t hist = (M <= HIST_MAX) ? sizeof(uint32_t) * (size_t)M : 0;
+    size_t used = LDS_RESERVE + QUEUE_BYTES + hist;
+    return used < LDS_TOTAL ? LDS_TOTAL - used : 0;
+}
+
+__device__ __forceinline__ size_t tile_index(int Wt, int c, int r)
+{
+    return ((size_t)(r >> 4) * Wt + (c >> 4)) * 256 + ((r & 15) << 4) + (c & 15);
+}
+
+// Canvas word of (x, y): 0, label + 1, or BFLAG | first candidate record.
+__device__ __forceinline__ uint32_t lookup(const CanvasView &cv, const uint16_t *coarse, double x, double y)
 {
     // exact half-open bbox test; NaN fails every comparison
     if (!(cv.bx0 <= x && x < cv.bx1 && cv.by0 <= y && y < cv.by1)) return 0u;
@@ -34,75 +59,150 @@ __device__ __forceinline__ uint32_t canvas_word(const CanvasView &cv, double x, 
     const double v = __dmul_rn(__dsub_rn(y, cv.Y0), cv.sy);
     const int c = min((int)u, cv.W - 1);
     const int r = min((int)v, cv.H - 1);
-    return cv.cells[(size_t)r * cv.W + c];
+    const uint16_t cw = coarse[(r >> cv.blog) * cv.Wc + (c >> cv.blog)];
+    if (cw != COARSE_MIXED) return cw;
+    return cv.cells[tile_index(cv.Wt, c, r)];
 }
 
 __device__ __forceinline__ bool cand_inside(const CanvasView &cv, const Cand &cd, double x, double y)
 {
     bool in = (cd.meta & CAND_S) != 0;
-    const uint32_t nloc = cd.meta >> 2;
-    const uint32_t *el = cv.elist + cd.eoff;
+    const uint32_t nloc = (cd.meta >> 2) & 0x7fffu;
+    const uint32_t npart = cd.meta >> 17;
+    const Edge *le = cv.ledges + cd.eoff;
     for (uint32_t t = 0; t < nloc; ++t) {
-        const Edge e = cv.edges[el[t]];
+        const Edge e = le[t];
         in ^= crosses(e.xlo, e.ylo, e.xhi, e.yhi, x, y);
     }
-    for (uint32_t t = 0; t < cd.npart; ++t) {
-        const Edge e = cv.edges[el[nloc + t]];
-        in ^= straddles(e.ylo, e.yhi, y);
+    const double2 *ps = cv.pspan + cd.poff;
+    for (uint32_t t = 0; t < npart; ++t) {
+        const double2 s = ps[t];
+        in ^= straddles(s.x, s.y, y);
     }
     return in;
 }
 
+// Cooperative copy of the coarse canvas into LDS.
+__device__ __forceinline__ void load_coarse(const CanvasView &cv, uint16_t *dst, int nthreads)
+{
+    const int n = cv.Wc * cv.Hc;
+    const int n2 = n >> 1;
+    const uint32_t *src2 = (const uint32_t *)cv.coarse;
+    uint32_t *dst2 = (uint32_t *)dst;
+    for (int i = threadIdx.x; i < n2; i += nthreads) dst2[i] = src2[i];
+    if ((n & 1) && threadIdx.x == 0) dst[n - 1] = cv.coarse[n - 1];
+}
+
+__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63; }
+
 // ------------------------------------------------------------ join-count
 
-template <bool LDS>
-__global__ __launch_bounds__(PROBE_THREADS) void k_count(CanvasView cv, int64_t n, const double *X,
-                                                         const double *Y,
-                                                         unsigned long long *counts)
+// Counts accumulate in a context-owned accumulator `acc` that is all zero
+// between calls: the last workgroup to finish (found with a counter, after a
+// device-scope fence) copies acc into the caller's output and clears acc and
+// the counter again, so a query is a single kernel launch with no memset.
+template <bool LDSHIST>
+__global__ __launch_bounds__(CNT_THREADS) void k_count(CanvasView cv, int64_t n, const double *X,
+                                                       const double *Y, unsigned long long *acc,
+                                                       unsigned int *done, unsigned long long *out)
 {
-    extern __shared__ uint32_t hist[];
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ bool s_last;
     const int M = (int)cv.M;
-    if (LDS) {
-        for (int k = threadIdx.x; k < M; k += PROBE_THREADS) hist[k] = 0;
-        __syncthreads();
-    }
+    const size_t coarse_bytes = ((size_t)cv.Wc * cv.Hc * 2 + 15) & ~(size_t)15;
+    uint16_t *coarse = (uint16_t *)smem;
+    uint32_t *hist = (uint32_t *)(smem + coarse_bytes);
+    const size_t hist_bytes = LDSHIST ? (((size_t)M * 4 + 15) & ~(size_t)15) : 0;
+    unsigned char *qbase = smem + coarse_bytes + hist_bytes;
+    const int wv = threadIdx.x >> 6;
+    double *qx = (double *)(qbase) + wv * QCAP;
+    double *qy = (double *)(qbase) + (CNT_THREADS / 64) * QCAP + wv * QCAP;
+    uint32_t *qr = (uint32_t *)((double *)(qbase) + 2 * (CNT_THREADS / 64) * QCAP) + wv * QCAP;
+
+    load_coarse(cv, coarse, CNT_THREADS);
+    if (LDSHIST)
+        for (int k = threadIdx.x; k < M; k += CNT_THREADS) hist[k] = 0;
+    __syncthreads();
+
     auto add = [&](uint32_t k) {
-        if (LDS) atomicAdd(&hist[k], 1u);
-        else atomicAdd(&counts[k], 1ull);
+        if (LDSHIST) atomicAdd(&hist[k], 1u);
+        else atomicAdd(&acc[k], 1ull);
     };
-    const int64_t stride = (int64_t)gridDim.x * PROBE_THREADS * 2;
-    for (int64_t base = (int64_t)blockIdx.x * PROBE_THREADS * 2 + threadIdx.x; base < n; base += stride) {
-        double xs[2], ys[2];
-        bool ok[2];
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const int64_t i = base + (int64_t)u * PROBE_THREADS;
-            ok[u] = i < n;
-            xs[u] = ok[u] ? __builtin_nontemporal_load(X + i) : 0.0;
-            ys[u] = ok[u] ? __builtin_nontemporal_load(Y + i) : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            if (!ok[u]) continue;
-            const uint32_t w = canvas_word(cv, xs[u], ys[u]);
-            if (w == 0u) continue;
-            if (!(w & BFLAG)) { add(w - 1u); continue; }
-            uint32_t rec = w & ~BFLAG;
+    const uint32_t lane = lane_id();
+    uint32_t qn = 0;   // wave-uniform queue length
+    auto drain = [&]() {
+        __builtin_amdgcn_wave_barrier();
+        if (lane < qn) {
+            const double x = qx[lane], y = qy[lane];
+            uint32_t rec = qr[lane];
             while (true) {
                 const Cand cd = cv.cands[rec];
-                if (cand_inside(cv, cd, xs[u], ys[u])) add(cd.poly);
+                if (cand_inside(cv, cd, x, y)) add(cd.poly);
                 if (cd.meta & CAND_LAST) break;
                 ++rec;
             }
         }
-    }
-    if (LDS) {
-        __syncthreads();
-        for (int k = threadIdx.x; k < M; k += PROBE_THREADS) {
-            const uint32_t c = hist[k];
-            if (c) atomicAdd(&counts[k], (unsigned long long)c);
+        __builtin_amdgcn_wave_barrier();
+        qn = 0;
+    };
+
+    // software pipeline: the next iteration's points are in flight while the
+    // current ones are classified
+    const int64_t step = (int64_t)gridDim.x * CNT_THREADS * CNT_UNROLL;
+    double xn[CNT_UNROLL], yn[CNT_UNROLL];
+    auto fetch = [&](int64_t b) {
+#pragma unroll
+        for (int u = 0; u < CNT_UNROLL; ++u) {
+            const int64_t i = b + (int64_t)u * CNT_THREADS + threadIdx.x;
+            xn[u] = i < n ? __builtin_nontemporal_load(X + i) : NAN;
+            yn[u] = i < n ? __builtin_nontemporal_load(Y + i) : NAN;
+        }
+    };
+    int64_t base = (int64_t)blockIdx.x * CNT_THREADS * CNT_UNROLL;
+    if (base < n) fetch(base);
+    for (; base < n; base += step) {
+        double xs[CNT_UNROLL], ys[CNT_UNROLL];
+#pragma unroll
+        for (int u = 0; u < CNT_UNROLL; ++u) { xs[u] = xn[u]; ys[u] = yn[u]; }
+        if (base + step < n) fetch(base + step);
+#pragma unroll
+        for (int u = 0; u < CNT_UNROLL; ++u) {
+            const uint32_t w = lookup(cv, coarse, xs[u], ys[u]);
+            const bool bnd = (w & BFLAG) != 0;
+            if (w != 0u && !bnd) add(w - 1u);
+            const unsigned long long mask = __ballot(bnd);
+            const uint32_t nnew = (uint32_t)__popcll(mask);
+            if (nnew == 0) continue;
+            if (qn + nnew > QCAP) drain();
+            if (bnd) {
+                const uint32_t slot = qn + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+                qx[slot] = xs[u];
+                qy[slot] = ys[u];
+                qr[slot] = w & ~BFLAG;
+            }
+            qn += nnew;
         }
     }
+    if (qn) drain();
+
+    if (LDSHIST) {
+        __syncthreads();
+        for (int k = threadIdx.x; k < M; k += CNT_THREADS) {
+            const uint32_t c = hist[k];
+            if (c) atomicAdd(&acc[k], (unsigned long long)c);
+        }
+    }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = (atomicAdd(done, 1u) == gridDim.x - 1);
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    for (int k = threadIdx.x; k < M; k += CNT_THREADS) {
+        out[k] = __hip_atomic_load(&acc[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        acc[k] = 0ull;
+    }
+    if (threadIdx.x == 0) *done = 0u;
 }
 
 __global__ void k_zero_u64(int64_t n, unsigned long long *p)
@@ -123,31 +223,57 @@ static int num_cus(spade_ctx *ctx)
     return cached;
 }
 
+// The accumulator lives in a context scratch slot that is zeroed whenever it
+// is (re)allocated; k_count leaves it zeroed.
+static int count_acc(spade_ctx *ctx, int64_t M, unsigned long long **acc, unsigned int **done)
+{
+    DevBuf &b = ctx->scratch[S_PROBE];
+    const size_t need = sizeof(unsigned long long) * (size_t)(M + 1);
+    if (b.cap < need) {
+        if (ensure(ctx, b, need)) return SPADE_E_NOMEM;
+        SPADE_HIP(ctx, hipMemsetAsync(b.p, 0, b.cap, ctx->stream));
+    }
+    *acc = (unsigned long long *)b.p;
+    *done = (unsigned int *)((unsigned long long *)b.p + M);
+    return SPADE_OK;
+}
+
+static size_t coarse_bytes_of(const CanvasView &v)
+{
+    return ((size_t)v.Wc * v.Hc * 2 + 15) & ~(size_t)15;
+}
+
 int probe_count(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts, uint64_t *out_counts)
 {
     hipStream_t st = ctx->stream;
     const CanvasView &v = cv->view;
     const int64_t M = v.M;
-    if (M > 0) {
-        hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)std::min<int64_t>((M + 255) / 256, 1024)), dim3(256),
-                           0, st, M, (unsigned long long *)out_counts);
-        SPADE_HIP(ctx, hipGetLastError());
-    }
-    if (pts->n == 0 || M == 0) return SPADE_OK;
+    if (M == 0) return SPADE_OK;
+    unsigned long long *acc = nullptr;
+    unsigned int *done = nullptr;
+    int rc = count_acc(ctx, M, &acc, &done);
+    if (rc) return rc;
     const int cus = num_cus(ctx);
-    const int64_t need = (pts->n + 2 * PROBE_THREADS - 1) / (2 * PROBE_THREADS);
-    if (M <= HIST_MAX) {
-        const size_t lds = sizeof(uint32_t) * (size_t)M;
-        const int per_cu = M <= 2048 ? 8 : (M <= 8192 ? 2 : 1);
-        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)cus * per_cu));
-        hipLaunchKernelGGL(k_count<true>, dim3(grid), dim3(PROBE_THREADS), lds, st, v, pts->n, pts->x,
-                           pts->y, (unsigned long long *)out_counts);
+    const bool ldshist = M <= HIST_MAX;
+    const size_t lds = coarse_bytes_of(v) + (ldshist ? (((size_t)M * 4 + 15) & ~(size_t)15) : 0) + QUEUE_BYTES;
+    if (lds + LDS_RESERVE > LDS_TOTAL) return set_error(ctx, SPADE_E_HIP, "internal: probe LDS budget exceeded");
+    const int per_cu = std::max<int>(1, (int)(LDS_TOTAL / (lds + LDS_RESERVE)));
+    const int64_t need = std::max<int64_t>(1, (pts->n + CNT_THREADS * CNT_UNROLL - 1) / (CNT_THREADS * CNT_UNROLL));
+    const int grid = (int)std::min<int64_t>(need, (int64_t)cus * std::min(per_cu, 2));
+    if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[2], st));
+    if (ldshist) {
+        SPADE_HIP(ctx, hipFuncSetAttribute((const void *)k_count<true>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        hipLaunchKernelGGL(k_count<true>, dim3(grid), dim3(CNT_THREADS), lds, st, v, pts->n, pts->x,
+                           pts->y, acc, done, (unsigned long long *)out_counts);
     } else {
-        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)cus * 8));
-        hipLaunchKernelGGL(k_count<false>, dim3(grid), dim3(PROBE_THREADS), 0, st, v, pts->n, pts->x,
-                           pts->y, (unsigned long long *)out_counts);
+        SPADE_HIP(ctx, hipFuncSetAttribute((const void *)k_count<false>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        hipLaunchKernelGGL(k_count<false>, dim3(grid), dim3(CNT_THREADS), lds, st, v, pts->n, pts->x,
+                           pts->y, acc, done, (unsigned long long *)out_counts);
     }
     SPADE_HIP(ctx, hipGetLastError());
+    if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[3], st));
     return SPADE_OK;
 }
 
@@ -157,7 +283,7 @@ constexpr unsigned long long LB_AGG = 1ull << 62;
 constexpr unsigned long long LB_PRE = 2ull << 62;
 constexpr unsigned long long LB_VAL = (1ull << 62) - 1;
 
-// Block-wide exclusive scan of one value per thread (256 threads, 4 waves).
+// Block-wide exclusive scan of one value per thread (EMIT_THREADS threads).
 __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *wsum, uint32_t &total)
 {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -172,7 +298,7 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *wsum, 
     uint32_t pre = 0;
     total = 0;
 #pragma unroll
-    for (int q = 0; q < PROBE_THREADS / 64; ++q) {
+    for (int q = 0; q < EMIT_THREADS / 64; ++q) {
         uint32_t s = wsum[q];
         if (q < wv) pre += s;
         total += s;
@@ -181,16 +307,20 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *wsum, 
     return pre + inc - v;
 }
 
-__global__ __launch_bounds__(PROBE_THREADS) void k_emit(CanvasView cv, int64_t n, const double *X,
-                                                        const double *Y, uint32_t *out_pt,
-                                                        uint32_t *out_poly, int64_t cap,
-                                                        unsigned long long *status,
-                                                        unsigned int *chunk_ctr, int64_t nchunks,
-                                                        unsigned long long *total_out)
+__global__ __launch_bounds__(EMIT_THREADS) void k_emit(CanvasView cv, int64_t n, const double *X,
+                                                       const double *Y, uint32_t *out_pt,
+                                                       uint32_t *out_poly, int64_t cap,
+                                                       unsigned long long *status,
+                                                       unsigned int *chunk_ctr, int64_t nchunks,
+                                                       unsigned long long *total_out)
 {
+    extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t s_chunk;
-    __shared__ uint32_t wsum[PROBE_THREADS / 64];
+    __shared__ uint32_t wsum[EMIT_THREADS / 64];
     __shared__ unsigned long long s_prefix;
+    uint16_t *coarse = (uint16_t *)smem;
+    load_coarse(cv, coarse, EMIT_THREADS);
+    __syncthreads();
     while (true) {
         if (threadIdx.x == 0) s_chunk = atomicAdd(chunk_ctr, 1u);
         __syncthreads();
@@ -203,12 +333,12 @@ __global__ __launch_bounds__(PROBE_THREADS) void k_emit(CanvasView cv, int64_t n
         uint32_t cnt[EMIT_ITEMS];
 #pragma unroll
         for (int it = 0; it < EMIT_ITEMS; ++it) {
-            const int64_t i = base + (int64_t)it * PROBE_THREADS + threadIdx.x;
+            const int64_t i = base + (int64_t)it * EMIT_THREADS + threadIdx.x;
             cnt[it] = 0;
             lab[it] = 0;
             if (i >= n) continue;
             const double x = __builtin_nontemporal_load(X + i), y = __builtin_nontemporal_load(Y + i);
-            const uint32_t w = canvas_word(cv, x, y);
+            const uint32_t w = lookup(cv, coarse, x, y);
             if (w == 0u) continue;
             if (!(w & BFLAG)) { cnt[it] = 1; lab[it] = w - 1u; continue; }
             uint32_t rec = w & ~BFLAG, first = 0, m = 0;
@@ -261,7 +391,7 @@ __global__ __launch_bounds__(PROBE_THREADS) void k_emit(CanvasView cv, int64_t n
 #pragma unroll
         for (int it = 0; it < EMIT_ITEMS; ++it) {
             if (cnt[it] == 0) continue;
-            const int64_t i = base + (int64_t)it * PROBE_THREADS + threadIdx.x;
+            const int64_t i = base + (int64_t)it * EMIT_THREADS + threadIdx.x;
             unsigned long long pos = prefix + excl[it];
             if (cnt[it] == 1) {
                 if ((int64_t)pos < cap) {
@@ -290,12 +420,6 @@ __global__ __launch_bounds__(PROBE_THREADS) void k_emit(CanvasView cv, int64_t n
     }
 }
 
-__global__ void k_zero_u32(int64_t n, unsigned int *p)
-{
-    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += nth) p[i] = 0u;
-}
-
 int probe_emit(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts, uint32_t *out_pt,
                uint32_t *out_poly, int64_t cap, int64_t *n_out)
 {
@@ -312,11 +436,16 @@ int probe_emit(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts, 
     hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)std::min<int64_t>((nchunks + 2 + 255) / 256, 4096)),
                        dim3(256), 0, st, nchunks + 2, status);
     SPADE_HIP(ctx, hipGetLastError());
+    const size_t lds = coarse_bytes_of(cv->view);
+    const int per_cu = std::max<int>(1, (int)(LDS_TOTAL / (lds + LDS_RESERVE)));
     const int cus = num_cus(ctx);
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(nchunks, (int64_t)cus * 4));
-    hipLaunchKernelGGL(k_emit, dim3(grid), dim3(PROBE_THREADS), 0, st, cv->view, n, pts->x, pts->y,
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(nchunks, (int64_t)cus * std::min(per_cu, 4)));
+    SPADE_HIP(ctx, hipFuncSetAttribute((const void *)k_emit, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[2], st));
+    hipLaunchKernelGGL(k_emit, dim3(grid), dim3(EMIT_THREADS), lds, st, cv->view, n, pts->x, pts->y,
                        out_pt, out_poly, cap, status, ctr, nchunks, total);
     SPADE_HIP(ctx, hipGetLastError());
+    if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[3], st));
     unsigned long long *h = (unsigned long long *)ensure_pinned(ctx, 64);
     if (!h) return set_error(ctx, SPADE_E_NOMEM, "pinned staging allocation failed");
     SPADE_HIP(ctx, hipMemcpyAsync(h, total, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));

@@ -178,13 +178,15 @@ __global__ __launch_bounds__(256) void k_entries(int64_t V, const Edge *edges, c
 // After the sort, vals holds the edge id and a second array the permutation;
 // gather the per-entry payload into sorted order.
 __global__ void k_gather_entries(int64_t T, const uint32_t *perm, const uint32_t *ent_c,
-                                 const uint8_t *ent_f, uint32_t *s_c, uint8_t *s_f)
+                                 const uint8_t *ent_f, const uint64_t *skeys, int cbits, uint64_t pmask,
+                                 uint32_t *s_c, uint8_t *s_f, uint32_t *s_poly)
 {
     const int64_t nth = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < T; i += nth) {
         uint32_t p = perm[i];
         s_c[i] = ent_c[p];
         s_f[i] = ent_f[p];
+        s_poly[i] = (uint32_t)((skeys[i] >> cbits) & pmask);
     }
 }
 
@@ -212,297 +214,507 @@ __global__ void k_row_off(int64_t T, const uint64_t *skeys, int shift, int32_t H
 
 // ------------------------------------------------------------ per-row scanline
 
-// In-place block-wide inclusive scan of a[0..n) (n <= MAXW) with 256 threads.
+// Column arrays of a row live in LDS with one pad word per 32 so that the
+// contiguous per-thread chunks of the scans do not collide in LDS banks.
+__device__ __forceinline__ int cix(int c) { return c + (c >> 5); }
+__host__ __device__ inline int col_words(int W) { return W + 1 + (W + 1) / 32 + 1; }
+
+// Block-wide in-place inclusive scan of a[cix(0..n)) with ROW_THREADS
+// threads: contiguous per-thread chunks, wave-level shuffle scan of the
+// chunk totals, one LDS word per wave.  `op` must be associative and
+// commutative.
 template <typename T, typename Op>
-__device__ void block_scan(T *a, int n, T *tmp, Op op, T ident)
+__device__ void block_scan(T *a, int n, T *wtot, Op op, T ident)
 {
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int per = (n + ROW_THREADS - 1) / ROW_THREADS;
-    const int b = threadIdx.x * per;
-    const int e = min(n, b + per);
+    const int b = min(n, tid * per), e = min(n, b + per);
     T acc = ident;
-    for (int i = b; i < e; ++i) { acc = op(acc, a[i]); a[i] = acc; }
-    tmp[threadIdx.x] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        T run = ident;
-        for (int t = 0; t < ROW_THREADS; ++t) { T v = tmp[t]; tmp[t] = run; run = op(run, v); }
+    for (int i = b; i < e; ++i) { acc = op(acc, a[cix(i)]); a[cix(i)] = acc; }
+    T inc = acc;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        T t = __shfl_up(inc, d, 64);
+        if (lane >= d) inc = op(inc, t);
     }
+    if (lane == 63) wtot[wv] = inc;
     __syncthreads();
-    const T pre = tmp[threadIdx.x];
-    for (int i = b; i < e; ++i) a[i] = op(pre, a[i]);
+    T pre = ident;
+    for (int q = 0; q < wv; ++q) pre = op(pre, wtot[q]);
+    T prev = __shfl_up(inc, 1, 64);
+    if (lane > 0) pre = op(pre, prev);
+    for (int i = b; i < e; ++i) a[cix(i)] = op(pre, a[cix(i)]);
     __syncthreads();
 }
 
 struct RowArgs {
     Map m;
-    int cbits;
-    uint64_t pmask;
+    int Wt;                  // canvas tiles per row (tile = 16 x 16 pixels)
+    int cap;                 // entries of one row staged in LDS
     const uint32_t *row_off;
-    const uint64_t *skeys;
+    const uint32_t *spoly;   // polygon per sorted entry
     const uint32_t *sedge;   // edge id per sorted entry
     const uint32_t *sc;      // c0 | c1 << 16
     const uint8_t *sf;
-    uint32_t *nextp;         // next partial entry at or after i within its run
     const Edge *edges;
+    uint32_t *gaux;          // 5 words per entry for rows too long to stage
     // count pass
-    uint64_t *row_nrec, *row_nel, *row_nbp;
+    uint64_t *row_nrec, *row_nloc, *row_npart, *row_nbp;
     // emit pass
-    const uint64_t *rec_base, *el_base;
+    const uint64_t *rec_base, *loc_base, *part_base;
     uint32_t *cells;
     Cand *cands;
-    uint32_t *elist;
+    Edge *ledges;
+    double2 *pspan;
     unsigned *errflags;
 };
 
-// Emits (or counts) the records of one run (entries [i, je) of polygon k in
-// row r).  `cls` holds the pixel classes of the row.
+// Entries of one row, relative to its first entry, with their per-row
+// auxiliary arrays (LDS when the row is staged, global memory otherwise).
+struct RowData {
+    const uint32_t *poly;
+    const uint32_t *c;
+    const uint8_t *f;
+    const uint32_t *edge;
+    uint32_t *pm;     // running max over the run up to q of (c1 + 1): low 16 bits all
+                      // entries, high 16 bits non-horizontal entries (0: none)
+    uint32_t *pre;    // inclusive row prefix: partial count (bits 0..30, sum) and
+                      // spanning parity (bit 31, xor)
+    uint32_t *rhead;  // run list: first entry, end, inclusive prefix of column spans
+    uint32_t *rend;
+    uint32_t *rspan;
+    int n;
+};
+
+// Row-level LDS state shared by the run workers.
+struct RowShared {
+    int32_t *sa;        // footprint counts -> per-column record counts / bases
+    int32_t *sb;        // claim counts -> per-column fill counters
+    uint32_t *sx;       // claimant xor -> pixel class
+    uint32_t *locfill;  // row-local fill counter of the local-edge array
+    uint32_t *nruns;
+};
+
+__device__ __forceinline__ size_t tile_index(int Wt, int c, int r)
+{
+    return ((size_t)(r >> 4) * Wt + (c >> 4)) * 256 + ((r & 15) << 4) + (c & 15);
+}
+
+__device__ __forceinline__ bool is_partial(uint8_t f) { return !(f & F_SPAN) && !(f & F_HORIZ); }
+__device__ __forceinline__ bool is_spanning(uint8_t f) { return (f & F_SPAN) && !(f & F_HORIZ); }
+
+__device__ __forceinline__ uint32_t pre_own(uint8_t f)
+{
+    return (is_partial(f) ? 1u : 0u) | (is_spanning(f) ? 0x80000000u : 0u);
+}
+
+// Combines two prefix words: 31-bit sum of partial counts, xor of parities.
+__device__ __forceinline__ uint32_t pre_op(uint32_t a, uint32_t b)
+{
+    return ((a + b) & 0x7fffffffu) | ((a ^ b) & 0x80000000u);
+}
+
+// Exclusive row prefix at q (q may be n).
+__device__ __forceinline__ uint32_t pre_excl(const RowData &D, int q)
+{
+    return q == 0 ? 0u : D.pre[q - 1];
+}
+
+// Records of one run at one column.  A point p of the pixel is inside the
+// run's polygon iff  S ^ XOR(partial-right straddles) ^ XOR(local crosses),
+// with S the parity of the run's spanning entries starting right of col,
+// partial-right entries those partial entries starting right of col, and
+// local entries the non-horizontal entries whose footprint contains col.
 template <bool EMIT>
-__device__ void run_records(const RowArgs &A, int r, int i, int je, uint32_t k,
-                            const uint32_t *cls, int32_t *colcnt, int32_t *colfill,
-                            uint32_t *elfill, uint64_t &nel)
+__device__ __forceinline__ void column_record(const RowArgs &A, const RowData &D, const RowShared &L,
+                                              int i, int je, int col, uint64_t rec_base_r,
+                                              uint64_t loc_base_r, uint64_t part_base_r,
+                                              uint64_t &nloc_tot)
+{
+    // sp: first entry of the run whose footprint starts right of col
+    int lo = i, hi = je;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if ((int)(D.c[mid] & 0xffff) <= col) lo = mid + 1; else hi = mid;
+    }
+    const int sp = lo;
+    if (sp == i || (int)(D.pm[sp - 1] & 0xffff) <= col) return;   // col outside the run's footprints
+    const uint32_t pe = pre_excl(D, je), ps = pre_excl(D, sp);
+    const uint32_t S = ((pe ^ ps) >> 31) & 1u;
+    const uint32_t npart = (pe & 0x7fffffffu) - (ps & 0x7fffffffu);
+    uint32_t nloc = 0;
+    for (int q = sp - 1; q >= i && (int)(D.pm[q] >> 16) > col; --q)
+        if ((int)(D.c[q] >> 16) >= col && !(D.f[q] & F_HORIZ)) ++nloc;
+    if (nloc > 0x7fffu || npart > 0x7fffu) atomicOr(A.errflags, 16u);
+    if (!EMIT) {
+        atomicAdd(&L.sa[cix(col)], 1);
+        nloc_tot += nloc;
+        return;
+    }
+    const uint64_t slot = rec_base_r + (uint64_t)L.sa[cix(col)] + (uint64_t)atomicAdd(&L.sb[cix(col)], 1);
+    uint64_t eoff = 0;
+    if (nloc) {
+        eoff = loc_base_r + atomicAdd(L.locfill, nloc);
+        uint64_t o = eoff;
+        for (int q = sp - 1; q >= i && (int)(D.pm[q] >> 16) > col; --q)
+            if ((int)(D.c[q] >> 16) >= col && !(D.f[q] & F_HORIZ)) A.ledges[o++] = A.edges[D.edge[q]];
+    }
+    Cand cd;
+    cd.poly = D.poly[i];
+    cd.meta = S | ((nloc & 0x7fffu) << 2) | ((npart & 0x7fffu) << 17);
+    cd.eoff = (uint32_t)eoff;
+    cd.poff = (uint32_t)(part_base_r + (ps & 0x7fffffffu));
+    A.cands[slot] = cd;
+}
+
+// Claimant records of a run in rows where interiors overlap: every boundary
+// column inside the run's interior spans gets (S = 1, no edges).
+template <bool EMIT>
+__device__ void claimant_walk(const RowArgs &A, const RowData &D, const RowShared &L, int i, int je,
+                              uint64_t rec_base_r)
 {
     const int W = A.m.W;
-    // spanning parity over the run and widest footprint
-    uint32_t stot = 0, wtot = 0;
-    int maxlen = 0;
-    for (int q = i; q < je; ++q) {
-        uint8_t f = A.sf[q];
-        if ((f & F_SPAN) && !(f & F_HORIZ)) stot ^= 1u;
-        if (f & F_W) wtot ^= 1u;
-        uint32_t c = A.sc[q];
-        maxlen = max(maxlen, (int)(c >> 16) - (int)(c & 0xffff));
-    }
-    auto emit = [&](int col, uint32_t S, int sp, int lp, bool with_edges) {
-        // count locals and partials
-        uint32_t nloc = 0, npart = 0;
-        if (with_edges) {
-            for (int q = lp; q < sp; ++q) {
-                uint32_t c = A.sc[q];
-                if ((int)(c >> 16) >= col && !(A.sf[q] & F_HORIZ)) ++nloc;
-            }
-            for (int q = (sp < je) ? (int)A.nextp[sp] : je; q < je; q = (q + 1 < je) ? (int)A.nextp[q + 1] : je)
-                ++npart;
-        }
-        if (!EMIT) {
-            atomicAdd(&colcnt[col], 1);
-            nel += nloc + npart;
-            return;
-        }
-        const uint64_t slot = A.rec_base[r] + (uint64_t)colcnt[col] + (uint64_t)atomicAdd(&colfill[col], 1);
-        uint64_t eoff = 0;
-        if (nloc + npart) {
-            eoff = A.el_base[r] + atomicAdd(elfill, nloc + npart);
-            uint64_t o = eoff;
-            for (int q = lp; q < sp; ++q) {
-                uint32_t c = A.sc[q];
-                if ((int)(c >> 16) >= col && !(A.sf[q] & F_HORIZ)) A.elist[o++] = A.sedge[q];
-            }
-            for (int q = (sp < je) ? (int)A.nextp[sp] : je; q < je; q = (q + 1 < je) ? (int)A.nextp[q + 1] : je)
-                A.elist[o++] = A.sedge[q];
-        }
+    uint32_t par = 0;
+    for (int q = i; q < je; ++q) par ^= (D.f[q] & F_W) ? 1u : 0u;
+    auto emit = [&](int col) {
+        if (!EMIT) { atomicAdd(&L.sa[cix(col)], 1); return; }
+        const uint64_t slot = rec_base_r + (uint64_t)L.sa[cix(col)] + (uint64_t)atomicAdd(&L.sb[cix(col)], 1);
         Cand cd;
-        cd.poly = k;
-        cd.meta = (S & 1u) | (nloc << 2);
-        cd.eoff = (uint32_t)eoff;
-        cd.npart = npart;
+        cd.poly = D.poly[i];
+        cd.meta = CAND_S;
+        cd.eoff = 0;
+        cd.poff = 0;
         A.cands[slot] = cd;
     };
-
-    // (a) every column of the union of the run's footprints
-    {
-        int col = (int)(A.sc[i] & 0xffff);
-        int reach = -1, sp = i, lp = i;
-        uint32_t sleft = 0;
-        while (true) {
-            while (sp < je && (int)(A.sc[sp] & 0xffff) <= col) {
-                reach = max(reach, (int)(A.sc[sp] >> 16));
-                uint8_t f = A.sf[sp];
-                if ((f & F_SPAN) && !(f & F_HORIZ)) sleft ^= 1u;
-                ++sp;
-            }
-            if (col > reach) {
-                if (sp >= je) break;
-                col = (int)(A.sc[sp] & 0xffff);
-                continue;
-            }
-            while (lp < sp && (int)(A.sc[lp] & 0xffff) < col - maxlen) ++lp;
-            emit(col, stot ^ sleft, sp, lp, true);
-            if (++col >= W) break;
-        }
+    int mx = -1;
+    const int c0first = (int)(D.c[i] & 0xffff);
+    if (par)
+        for (int col = 0; col < c0first; ++col)
+            if (L.sx[cix(col)] & BFLAG) emit(col);
+    for (int q = i; q < je; ++q) {
+        const uint32_t c = D.c[q];
+        mx = max(mx, (int)(c >> 16));
+        if (D.f[q] & F_W) par ^= 1u;
+        const int nc0 = (q + 1 < je) ? (int)(D.c[q + 1] & 0xffff) : W;
+        const int lo = max((int)(c & 0xffff), mx + 1), hi = nc0 - 1;
+        if (par)
+            for (int col = lo; col <= hi; ++col)
+                if (L.sx[cix(col)] & BFLAG) emit(col);
     }
-    // (b) interior columns of the run that are boundary pixels because of
-    //     other polygons: the polygon covers the whole pixel (S = 1, no edges)
-    {
+}
+
+// Calls fn(i, je) for every run (maximal block of entries of one polygon)
+// whose first entry this thread owns.
+template <typename Fn>
+__device__ __forceinline__ void for_each_run(const RowData &D, Fn fn)
+{
+    for (int i = threadIdx.x; i < D.n; i += ROW_THREADS) {
+        const uint32_t k = D.poly[i];
+        if (i != 0 && D.poly[i - 1] == k) continue;
+        int je = i + 1;
+        while (je < D.n && D.poly[je] == k) ++je;
+        fn(i, je);
+    }
+}
+
+// Block-wide in-place inclusive scan of a[0..n) under an associative,
+// commutative operator.
+template <typename Op>
+__device__ void block_plain_scan(uint32_t *a, int n, uint32_t *wtot, Op op)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int per = (n + ROW_THREADS - 1) / ROW_THREADS;
+    const int b = min(n, tid * per), e = min(n, b + per);
+    uint32_t acc = 0;
+    for (int q = b; q < e; ++q) { acc = op(acc, a[q]); a[q] = acc; }
+    uint32_t inc = acc;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t t = __shfl_up(inc, d, 64);
+        if (lane >= d) inc = op(inc, t);
+    }
+    if (lane == 63) wtot[wv] = inc;
+    __syncthreads();
+    uint32_t pre = 0;
+    for (int q = 0; q < wv; ++q) pre = op(pre, wtot[q]);
+    uint32_t prev = __shfl_up(inc, 1, 64);
+    if (lane > 0) pre = op(pre, prev);
+    for (int q = b; q < e; ++q) a[q] = op(pre, a[q]);
+    __syncthreads();
+}
+
+// Runs every (run, column) item of the row through column_record.
+template <bool EMIT>
+__device__ void all_column_records(const RowArgs &A, const RowData &D, const RowShared &L,
+                                   uint64_t rec_base_r, uint64_t loc_base_r, uint64_t part_base_r,
+                                   uint64_t &nloc_tot)
+{
+    const int nr = (int)*L.nruns;
+    if (nr == 0) return;
+    const uint32_t total = D.rspan[nr - 1];
+    for (uint32_t t = threadIdx.x; t < total; t += ROW_THREADS) {
+        int lo = 0, hi = nr - 1;            // first run with rspan > t
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (D.rspan[mid] > t) hi = mid; else lo = mid + 1;
+        }
+        const int i = (int)D.rhead[lo], je = (int)D.rend[lo];
+        const uint32_t before = lo ? D.rspan[lo - 1] : 0u;
+        const int col = (int)(D.c[i] & 0xffff) + (int)(t - before);
+        column_record<EMIT>(A, D, L, i, je, col, rec_base_r, loc_base_r, part_base_r, nloc_tot);
+    }
+}
+
+// Dynamic LDS: three padded column arrays, then `cap` staged entries with
+// their auxiliary words, then the run list (at most cap / 2 runs).
+__host__ __device__ inline size_t row_lds_bytes(int W, int cap)
+{
+    return (size_t)3 * col_words(W) * 4 + (size_t)cap * 21 + (size_t)(cap / 2 + 1) * 12 + 32;
+}
+
+template <bool EMIT>
+__device__ void process_row(const RowArgs &A, const RowData &D, const RowShared &L, int r,
+                            int32_t *wtoti, uint32_t *wtotu, uint32_t *s_nbp, uint32_t *s_multi,
+                            unsigned long long *s_nloc, unsigned long long *s_nrec)
+{
+    const int W = A.m.W;
+    const int tid = threadIdx.x;
+
+    // phase 1: per run, footprints (boundary counts), interior claims, the
+    //          running footprint maxima and the run list; per entry, the
+    //          partial / spanning indicators to be scanned
+    for (int q = tid; q < D.n; q += ROW_THREADS) D.pre[q] = pre_own(D.f[q]);
+    for_each_run(D, [&](int i, int je) {
+        const uint32_t lab = D.poly[i] + 1;
+        uint32_t wtot = 0;
+        for (int q = i; q < je; ++q) wtot ^= (D.f[q] & F_W) ? 1u : 0u;
         uint32_t par = wtot;
         int mx = -1;
-        int c0first = (int)(A.sc[i] & 0xffff);
-        if (par)
-            for (int col = 0; col < c0first; ++col)
-                if (cls[col] == BFLAG) emit(col, 1u, 0, 0, false);
-        for (int q = i; q < je; ++q) {
-            uint32_t c = A.sc[q];
-            mx = max(mx, (int)(c >> 16));
-            if (A.sf[q] & F_W) par ^= 1u;
-            int nc0 = (q + 1 < je) ? (int)(A.sc[q + 1] & 0xffff) : W;
-            int lo = max((int)(c & 0xffff), mx + 1), hi = nc0 - 1;
-            if (par)
-                for (int col = lo; col <= hi; ++col)
-                    if (cls[col] == BFLAG) emit(col, 1u, 0, 0, false);
+        uint32_t mall = 0, mnh = 0;
+        const int c0first = (int)(D.c[i] & 0xffff);
+        if (par && c0first > 0) {
+            atomicAdd(&L.sb[cix(0)], 1); atomicSub(&L.sb[cix(c0first)], 1);
+            atomicXor(&L.sx[cix(0)], lab); atomicXor(&L.sx[cix(c0first)], lab);
         }
+        for (int q = i; q < je; ++q) {
+            const uint32_t c = D.c[q];
+            const int c0 = (int)(c & 0xffff), c1 = (int)(c >> 16);
+            const uint8_t f = D.f[q];
+            atomicAdd(&L.sa[cix(c0)], 1);
+            atomicSub(&L.sa[cix(c1 + 1)], 1);
+            mx = max(mx, c1);
+            mall = max(mall, (uint32_t)c1 + 1u);
+            if (!(f & F_HORIZ)) mnh = max(mnh, (uint32_t)c1 + 1u);
+            D.pm[q] = mall | (mnh << 16);
+            if (f & F_W) par ^= 1u;
+            const int nc0 = (q + 1 < je) ? (int)(D.c[q + 1] & 0xffff) : W;
+            const int lo = max(c0, mx + 1), hi = nc0 - 1;
+            if (par && lo <= hi) {
+                atomicAdd(&L.sb[cix(lo)], 1); atomicSub(&L.sb[cix(hi + 1)], 1);
+                atomicXor(&L.sx[cix(lo)], lab); atomicXor(&L.sx[cix(hi + 1)], lab);
+            }
+        }
+        const uint32_t j = atomicAdd(L.nruns, 1u);
+        D.rhead[j] = (uint32_t)i;
+        D.rend[j] = (uint32_t)je;
+        D.rspan[j] = (uint32_t)((int)mall - c0first);   // columns c0first .. max c1
+    });
+    __syncthreads();
+
+    // phase 2: prefix scans -> per-pixel boundary count, claim count,
+    //          claimant; per-entry partial/spanning prefixes; run spans
+    block_scan(L.sa, W, wtoti, [](int32_t a, int32_t b) { return a + b; }, 0);
+    block_scan(L.sb, W, wtoti, [](int32_t a, int32_t b) { return a + b; }, 0);
+    block_scan(L.sx, W, wtotu, [](uint32_t a, uint32_t b) { return a ^ b; }, 0u);
+    block_plain_scan(D.pre, D.n, wtotu, [](uint32_t a, uint32_t b) { return pre_op(a, b); });
+    block_plain_scan(D.rspan, (int)*L.nruns, wtotu, [](uint32_t a, uint32_t b) { return a + b; });
+
+    // phase 3: classify pixels.  sx := 0 (no polygon), label + 1, or for a
+    // boundary pixel BFLAG | (label + 1 of its single interior claimant, or 0);
+    // sa := per-column record counters, starting with the claimant record.
+    uint32_t nb = 0, multi = 0;
+    for (int c = tid; c < W; c += ROW_THREADS) {
+        const int32_t bc = L.sa[cix(c)], cc = L.sb[cix(c)];
+        const uint32_t xc = L.sx[cix(c)];
+        const bool bnd = bc > 0 || cc >= 2;
+        L.sx[cix(c)] = bnd ? (BFLAG | (cc == 1 ? xc : 0u)) : (cc == 1 ? xc : 0u);
+        L.sa[cix(c)] = (bnd && cc == 1) ? 1 : 0;
+        L.sb[cix(c)] = 0;
+        nb += bnd ? 1u : 0u;
+        multi |= (cc >= 2) ? 1u : 0u;
+    }
+    atomicAdd(s_nbp, nb);
+    if (multi) atomicOr(s_multi, 1u);
+    __syncthreads();
+    const bool rmulti = *s_multi != 0;
+    if (rmulti) {
+        // overlapping interiors: every claimant record comes from the run walk
+        for (int c = tid; c < W; c += ROW_THREADS) L.sa[cix(c)] = 0;
+        __syncthreads();
+    }
+
+    // phase 4: count records per column (and local-edge totals)
+    uint64_t nloc = 0;
+    all_column_records<false>(A, D, L, 0, 0, 0, nloc);
+    if (rmulti) for_each_run(D, [&](int i, int je) { claimant_walk<false>(A, D, L, i, je, 0); });
+    atomicAdd(s_nloc, (unsigned long long)nloc);
+    __syncthreads();
+
+    if (!EMIT) {
+        uint32_t nrec = 0;
+        for (int c = tid; c < W; c += ROW_THREADS) nrec += (uint32_t)L.sa[cix(c)];
+        atomicAdd(s_nrec, (unsigned long long)nrec);
+        __syncthreads();
+        if (tid == 0) {
+            A.row_nrec[r] = *s_nrec;
+            A.row_nloc[r] = *s_nloc;
+            A.row_npart[r] = D.n ? (D.pre[D.n - 1] & 0x7fffffffu) : 0u;
+            A.row_nbp[r] = *s_nbp;
+        }
+        return;
+    }
+
+    // exclusive column bases for the records of this row
+    block_scan(L.sa, W, wtoti, [](int32_t a, int32_t b) { return a + b; }, 0);
+    {
+        int32_t mine[MAXW / ROW_THREADS];
+        int cnt = 0;
+        for (int c = tid; c < W; c += ROW_THREADS) mine[cnt++] = (c == 0) ? 0 : L.sa[cix(c - 1)];
+        __syncthreads();
+        cnt = 0;
+        for (int c = tid; c < W; c += ROW_THREADS) { L.sa[cix(c)] = mine[cnt++]; L.sb[cix(c)] = 0; }
+        __syncthreads();
+    }
+
+    // phase 5: records, local edges, partial spans (in row entry order)
+    const uint64_t rec_base_r = A.rec_base[r], loc_base_r = A.loc_base[r], part_base_r = A.part_base[r];
+    {
+        uint64_t dummy = 0;
+        all_column_records<true>(A, D, L, rec_base_r, loc_base_r, part_base_r, dummy);
+        if (rmulti) for_each_run(D, [&](int i, int je) { claimant_walk<true>(A, D, L, i, je, rec_base_r); });
+        else
+            for (int c = tid; c < W; c += ROW_THREADS) {
+                const uint32_t w = L.sx[cix(c)];
+                if ((w & BFLAG) && (w & ~BFLAG)) {
+                    const uint64_t slot = rec_base_r + (uint64_t)L.sa[cix(c)] + (uint64_t)atomicAdd(&L.sb[cix(c)], 1);
+                    Cand cd;
+                    cd.poly = (w & ~BFLAG) - 1u;
+                    cd.meta = CAND_S;
+                    cd.eoff = 0;
+                    cd.poff = 0;
+                    A.cands[slot] = cd;
+                }
+            }
+        for (int q = tid; q < D.n; q += ROW_THREADS)
+            if (is_partial(D.f[q])) {
+                const Edge e = A.edges[D.edge[q]];
+                A.pspan[part_base_r + (pre_excl(D, q) & 0x7fffffffu)] = make_double2(e.ylo, e.yhi);
+            }
+    }
+    __syncthreads();
+
+    // phase 6: order each pixel's records by polygon, flag the last one,
+    //          write the canvas row (tile-major)
+    for (int c = tid; c < W; c += ROW_THREADS) {
+        uint32_t word = L.sx[cix(c)];
+        if (word & BFLAG) {
+            const uint64_t base = rec_base_r + (uint64_t)L.sa[cix(c)];
+            const int n = L.sb[cix(c)];
+            if (n <= 0) { atomicOr(A.errflags, 8u); word = 0; }
+            else {
+                Cand *cs = A.cands + base;
+                for (int a = 1; a < n; ++a) {
+                    Cand key = cs[a];
+                    int b = a - 1;
+                    while (b >= 0 && cs[b].poly > key.poly) { cs[b + 1] = cs[b]; --b; }
+                    cs[b + 1] = key;
+                }
+                cs[n - 1].meta |= CAND_LAST;
+                word = BFLAG | (uint32_t)base;
+            }
+        }
+        A.cells[tile_index(A.Wt, c, r)] = word;
     }
 }
 
 template <bool EMIT>
 __global__ __launch_bounds__(ROW_THREADS) void k_rows(RowArgs A)
 {
-    __shared__ int32_t sa[MAXW + 1];
-    __shared__ int32_t sb[MAXW + 1];
-    __shared__ uint32_t sx[MAXW + 1];
-    __shared__ int32_t tmpi[ROW_THREADS];
-    __shared__ uint32_t tmpu[ROW_THREADS];
-    __shared__ uint32_t s_elfill, s_nbp;
-    __shared__ unsigned long long s_nel;
-    const int W = A.m.W, H = A.m.H;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int32_t wtoti[ROW_THREADS / 64];
+    __shared__ uint32_t wtotu[ROW_THREADS / 64];
+    __shared__ uint32_t s_locfill, s_nruns, s_nbp, s_multi;
+    __shared__ unsigned long long s_nloc, s_nrec;
+    const int W = A.m.W, H = A.m.H, cap = A.cap;
+    const int cw = col_words(W);
+    RowShared L;
+    L.sa = (int32_t *)smem;
+    L.sb = L.sa + cw;
+    L.sx = (uint32_t *)(L.sb + cw);
+    L.locfill = &s_locfill;
+    L.nruns = &s_nruns;
+    uint32_t *lpoly = L.sx + cw;
+    uint32_t *lc = lpoly + cap;
+    uint32_t *ledge = lc + cap;
+    uint32_t *lpm = ledge + cap;
+    uint32_t *lpre = lpm + cap;
+    uint32_t *lrh = lpre + cap;
+    uint32_t *lre = lrh + (cap / 2 + 1);
+    uint32_t *lrs = lre + (cap / 2 + 1);
+    uint8_t *lf = (uint8_t *)(lrs + (cap / 2 + 1));
     const int tid = threadIdx.x;
 
     for (int r = blockIdx.x; r < H; r += gridDim.x) {
         const int s = (int)A.row_off[r], e = (int)A.row_off[r + 1];
-        for (int c = tid; c <= W; c += ROW_THREADS) { sa[c] = 0; sb[c] = 0; sx[c] = 0; }
-        if (tid == 0) { s_elfill = 0; s_nbp = 0; s_nel = 0; }
-        __syncthreads();
-
-        // phase 1: footprints (boundary counts) and interior claims per run
-        for (int i = s + tid; i < e; i += ROW_THREADS) {
-            const uint32_t k = (uint32_t)((A.skeys[i] >> A.cbits) & A.pmask);
-            if (i != s && (uint32_t)((A.skeys[i - 1] >> A.cbits) & A.pmask) == k) continue;
-            int je = i + 1;
-            while (je < e && (uint32_t)((A.skeys[je] >> A.cbits) & A.pmask) == k) ++je;
-            uint32_t wtot = 0;
-            for (int q = i; q < je; ++q) wtot ^= (A.sf[q] & F_W) ? 1u : 0u;
-            if (!EMIT) {
-                int nxt = je;
-                for (int q = je - 1; q >= i; --q) {
-                    uint8_t f = A.sf[q];
-                    if (!(f & F_SPAN) && !(f & F_HORIZ)) nxt = q;
-                    A.nextp[q] = (uint32_t)nxt;
-                }
-            }
-            uint32_t par = wtot;
-            int mx = -1;
-            const uint32_t lab = k + 1;
-            int c0first = (int)(A.sc[i] & 0xffff);
-            if (par && c0first > 0) {
-                atomicAdd(&sb[0], 1); atomicSub(&sb[c0first], 1);
-                atomicXor(&sx[0], lab); atomicXor(&sx[c0first], lab);
-            }
-            for (int q = i; q < je; ++q) {
-                const uint32_t c = A.sc[q];
-                const int c0 = (int)(c & 0xffff), c1 = (int)(c >> 16);
-                atomicAdd(&sa[c0], 1);
-                atomicSub(&sa[c1 + 1], 1);
-                mx = max(mx, c1);
-                if (A.sf[q] & F_W) par ^= 1u;
-                const int nc0 = (q + 1 < je) ? (int)(A.sc[q + 1] & 0xffff) : W;
-                const int lo = max(c0, mx + 1), hi = nc0 - 1;
-                if (par && lo <= hi) {
-                    atomicAdd(&sb[lo], 1); atomicSub(&sb[hi + 1], 1);
-                    atomicXor(&sx[lo], lab); atomicXor(&sx[hi + 1], lab);
-                }
+        const int n = e - s;
+        if (n <= cap) {
+            for (int q = tid; q < n; q += ROW_THREADS) {
+                lpoly[q] = A.spoly[s + q];
+                lc[q] = A.sc[s + q];
+                ledge[q] = A.sedge[s + q];
+                lf[q] = A.sf[s + q];
             }
         }
+        for (int c = tid; c < cw; c += ROW_THREADS) { L.sa[c] = 0; L.sb[c] = 0; L.sx[c] = 0; }
+        if (tid == 0) { s_locfill = 0; s_nruns = 0; s_nbp = 0; s_multi = 0; s_nloc = 0; s_nrec = 0; }
         __syncthreads();
-
-        // phase 2: prefix scans -> per-pixel boundary count, claim count, claimant
-        block_scan(sa, W, tmpi, [](int32_t a, int32_t b) { return a + b; }, 0);
-        block_scan(sb, W, tmpi, [](int32_t a, int32_t b) { return a + b; }, 0);
-        block_scan(sx, W, tmpu, [](uint32_t a, uint32_t b) { return a ^ b; }, 0u);
-
-        // phase 3: classify pixels; sx := class, sa := per-column record count
-        uint32_t nb = 0;
-        for (int c = tid; c < W; c += ROW_THREADS) {
-            const bool bnd = sa[c] > 0 || sb[c] >= 2;
-            sx[c] = bnd ? BFLAG : (sb[c] == 1 ? sx[c] : 0u);
-            nb += bnd ? 1u : 0u;
-        }
-        atomicAdd(&s_nbp, nb);
-        __syncthreads();
-        for (int c = tid; c < W; c += ROW_THREADS) { sa[c] = 0; sb[c] = 0; }
-        __syncthreads();
-
-        // phase 4: count records per column (both passes need the counts)
-        uint64_t nel = 0;
-        for (int i = s + tid; i < e; i += ROW_THREADS) {
-            const uint32_t k = (uint32_t)((A.skeys[i] >> A.cbits) & A.pmask);
-            if (i != s && (uint32_t)((A.skeys[i - 1] >> A.cbits) & A.pmask) == k) continue;
-            int je = i + 1;
-            while (je < e && (uint32_t)((A.skeys[je] >> A.cbits) & A.pmask) == k) ++je;
-            run_records<false>(A, r, i, je, k, sx, sa, sb, &s_elfill, nel);
-        }
-        atomicAdd(&s_nel, (unsigned long long)nel);
-        __syncthreads();
-
-        if (!EMIT) {
-            uint32_t nrec = 0;
-            for (int c = tid; c < W; c += ROW_THREADS) nrec += (uint32_t)sa[c];
-            tmpu[tid] = nrec;
-            __syncthreads();
-            if (tid == 0) {
-                uint64_t t = 0;
-                for (int q = 0; q < ROW_THREADS; ++q) t += tmpu[q];
-                A.row_nrec[r] = t;
-                A.row_nel[r] = s_nel;
-                A.row_nbp[r] = s_nbp;
-            }
-            __syncthreads();
-            continue;
-        }
-
-        // exclusive column bases for the records of this row
-        block_scan(sa, W, tmpi, [](int32_t a, int32_t b) { return a + b; }, 0);
-        {
-            int32_t mine[MAXW / ROW_THREADS];
-            int cnt = 0;
-            for (int c = tid; c < W; c += ROW_THREADS) mine[cnt++] = (c == 0) ? 0 : sa[c - 1];
-            __syncthreads();
-            cnt = 0;
-            for (int c = tid; c < W; c += ROW_THREADS) { sa[c] = mine[cnt++]; sb[c] = 0; }
-            __syncthreads();
-        }
-
-        // phase 5: emit records and edge ids
-        for (int i = s + tid; i < e; i += ROW_THREADS) {
-            const uint32_t k = (uint32_t)((A.skeys[i] >> A.cbits) & A.pmask);
-            if (i != s && (uint32_t)((A.skeys[i - 1] >> A.cbits) & A.pmask) == k) continue;
-            int je = i + 1;
-            while (je < e && (uint32_t)((A.skeys[je] >> A.cbits) & A.pmask) == k) ++je;
-            uint64_t dummy = 0;
-            run_records<true>(A, r, i, je, k, sx, sa, sb, &s_elfill, dummy);
+        if (n <= cap) {
+            const RowData D{lpoly, lc, lf, ledge, lpm, lpre, lrh, lre, lrs, n};
+            process_row<EMIT>(A, D, L, r, wtoti, wtotu, &s_nbp, &s_multi, &s_nloc, &s_nrec);
+        } else {
+            uint32_t *g = A.gaux + (size_t)5 * s;
+            const RowData D{A.spoly + s, A.sc + s, A.sf + s, A.sedge + s, g, g + n, g + 2 * n, g + 3 * n,
+                            g + 4 * n, n};
+            process_row<EMIT>(A, D, L, r, wtoti, wtotu, &s_nbp, &s_multi, &s_nloc, &s_nrec);
         }
         __syncthreads();
+    }
+}
 
-        // phase 6: order each pixel's records by polygon, flag the last one,
-        //          write the canvas row
-        for (int c = tid; c < W; c += ROW_THREADS) {
-            uint32_t word = sx[c];
-            if (word == BFLAG) {
-                const uint64_t base = A.rec_base[r] + (uint64_t)sa[c];
-                const int n = sb[c];
-                if (n <= 0) { atomicOr(A.errflags, 8u); word = 0; }
-                else {
-                    Cand *cs = A.cands + base;
-                    for (int a = 1; a < n; ++a) {
-                        Cand key = cs[a];
-                        int b = a - 1;
-                        while (b >= 0 && cs[b].poly > key.poly) { cs[b + 1] = cs[b]; --b; }
-                        cs[b + 1] = key;
-                    }
-                    cs[n - 1].meta |= CAND_LAST;
-                    word = BFLAG | (uint32_t)base;
-                }
-            }
-            A.cells[(size_t)r * W + c] = word;
+// Coarse canvas: one 16-bit word per B x B block of pixels (B = 2^blog >= 16),
+// holding the block's common label + 1 (0: in no polygon) when every pixel
+// of the block carries that same non-boundary value, else COARSE_MIXED.  One
+// wavefront per block.
+__global__ __launch_bounds__(256) void k_coarse(int W, int H, int Wt, int blog, int Wc, int Hc,
+                                                const uint32_t *cells, uint16_t *coarse)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int B = 1 << blog;
+    for (int64_t cell = wave; cell < (int64_t)Wc * Hc; cell += nw) {
+        const int cy = (int)(cell / Wc), cx = (int)(cell % Wc);
+        const int c0 = cx << blog, r0 = cy << blog;
+        const int cw = min(B, W - c0), ch = min(B, H - r0);
+        const uint32_t first = cells[tile_index(Wt, c0, r0)];
+        bool same = true;
+        for (int p = lane; p < cw * ch; p += 64) {
+            const int c = c0 + p % cw, r = r0 + p / cw;
+            same &= cells[tile_index(Wt, c, r)] == first;
         }
-        __syncthreads();
+        const bool all = __all(same);
+        if (lane == 0)
+            coarse[cell] = (all && !(first & BFLAG) && first < COARSE_MIXED) ? (uint16_t)first : COARSE_MIXED;
     }
 }
 
@@ -603,16 +815,32 @@ int build_canvas(spade_ctx *ctx, const spade_polys *polys, spade_canvas *cv)
     view.X0 = m.X0; view.Y0 = m.Y0; view.sx = m.sx; view.sy = m.sy;
     view.W = W; view.H = H;
 
-    if (ensure(ctx, cv->cells, sizeof(uint32_t) * (size_t)W * H)) return SPADE_E_NOMEM;
+    const int Wt = (W + 15) / 16, Ht = (H + 15) / 16;
+    view.Wt = Wt;
+    const size_t ncells = (size_t)Wt * Ht * 256;
+    if (ensure(ctx, cv->cells, sizeof(uint32_t) * ncells)) return SPADE_E_NOMEM;
     view.cells = (const uint32_t *)cv->cells.p;
+    // coarse grid: blocks of 2^blog pixels, as fine as the probe's LDS allows
+    int blog = 4;
+    const size_t cbudget = coarse_lds_budget(M);
+    while (blog < 15 && (size_t)((W + (1 << blog) - 1) >> blog) * ((H + (1 << blog) - 1) >> blog) * 2 > cbudget)
+        ++blog;
+    view.blog = blog;
+    view.Wc = (W + (1 << blog) - 1) >> blog;
+    view.Hc = (H + (1 << blog) - 1) >> blog;
+    if (ensure(ctx, cv->coarse, sizeof(uint16_t) * ((size_t)view.Wc * view.Hc + 2))) return SPADE_E_NOMEM;
+    view.coarse = (const uint16_t *)cv->coarse.p;
     if (ensure(ctx, cv->edges, sizeof(Edge) * (size_t)std::max<int64_t>(V, 1))) return SPADE_E_NOMEM;
-    view.edges = (const Edge *)cv->edges.p;
     cv->n_edges = V;
     if (empty) {
-        SPADE_HIP(ctx, hipMemsetAsync(cv->cells.p, 0, sizeof(uint32_t) * (size_t)W * H, st));
-        if (ensure(ctx, cv->cands, sizeof(Cand)) || ensure(ctx, cv->elist, sizeof(uint32_t))) return SPADE_E_NOMEM;
+        SPADE_HIP(ctx, hipMemsetAsync(cv->cells.p, 0, sizeof(uint32_t) * ncells, st));
+        SPADE_HIP(ctx, hipMemsetAsync(cv->coarse.p, 0, sizeof(uint16_t) * ((size_t)view.Wc * view.Hc + 2), st));
+        if (ensure(ctx, cv->cands, sizeof(Cand)) || ensure(ctx, cv->ledges, sizeof(Edge)) ||
+            ensure(ctx, cv->pspan, sizeof(double2)))
+            return SPADE_E_NOMEM;
         view.cands = (const Cand *)cv->cands.p;
-        view.elist = (const uint32_t *)cv->elist.p;
+        view.ledges = (const Edge *)cv->ledges.p;
+        view.pspan = (const double2 *)cv->pspan.p;
         cv->n_boundary = cv->n_cands = cv->n_elist = 0;
         return SPADE_OK;
     }
@@ -654,15 +882,16 @@ int build_canvas(spade_ctx *ctx, const spade_polys *polys, spade_canvas *cv)
     DevBuf &dk = ctx->scratch[S_KEYS], &dk2 = ctx->scratch[S_KEYS2];
     DevBuf &dv = ctx->scratch[S_VALS], &dv2 = ctx->scratch[S_VALS2];
     DevBuf &dc = ctx->scratch[S_ENTC], &df = ctx->scratch[S_ENTF];
-    DevBuf &dnext = ctx->scratch[S_NEXTP], &drow = ctx->scratch[S_ROWOFF], &drc = ctx->scratch[S_ROWCNT];
+    DevBuf &drow = ctx->scratch[S_ROWOFF], &drc = ctx->scratch[S_ROWCNT];
     const size_t Ts = (size_t)std::max<uint64_t>(T, 1);
     // dc: ent_c[T] | sorted c[T] | perm[T] | perm2[T]; df: ent_f[T] | sorted f[T]
     if (ensure(ctx, dk, 8 * Ts) || ensure(ctx, dk2, 8 * Ts) || ensure(ctx, dv, 4 * Ts) ||
-        ensure(ctx, dv2, 4 * Ts) || ensure(ctx, dc, 16 * Ts) || ensure(ctx, df, 2 * Ts + 16) ||
-        ensure(ctx, dnext, 4 * Ts) || ensure(ctx, drow, 4 * ((size_t)H + 1)) ||
-        ensure(ctx, drc, 8 * 6 * ((size_t)H + 1)))
+        ensure(ctx, dv2, 4 * Ts) || ensure(ctx, dc, 20 * Ts) || ensure(ctx, df, 2 * Ts + 16) ||
+        ensure(ctx, drow, 4 * ((size_t)H + 1)) ||
+        ensure(ctx, drc, 8 * 8 * ((size_t)H + 1)))
         return SPADE_E_NOMEM;
     uint32_t *ent_c = (uint32_t *)dc.p, *s_c = ent_c + Ts, *perm = s_c + Ts, *perm2 = perm + Ts;
+    uint32_t *s_poly = perm2 + Ts;
     uint8_t *ent_f = (uint8_t *)df.p, *s_f = ent_f + Ts;
     hipLaunchKernelGGL(k_entries, dim3(grid_for(V)), dim3(256), 0, st, V, (const Edge *)cv->edges.p,
                        epoly, erow0, nrows, eoff, m, cbits, pbits, (uint64_t *)dk.p, (uint32_t *)dv.p,
@@ -686,7 +915,8 @@ int build_canvas(spade_ctx *ctx, const spade_polys *polys, spade_canvas *cv)
     }
     // sorted edge ids: vals[perm2[i]]
     hipLaunchKernelGGL(k_gather_entries, dim3(grid_for((int64_t)T)), dim3(256), 0, st, (int64_t)T,
-                       perm2, ent_c, ent_f, s_c, s_f);
+                       perm2, ent_c, ent_f, (const uint64_t *)dk2.p, cbits,
+                       (pbits >= 64) ? ~0ULL : ((1ULL << pbits) - 1), s_c, s_f, s_poly);
     SPADE_HIP(ctx, hipGetLastError());
     uint32_t *s_edge = (uint32_t *)dv2.p;
     hipLaunchKernelGGL(k_gather_u32, dim3(grid_for((int64_t)T)), dim3(256), 0, st, (int64_t)T,
@@ -698,64 +928,90 @@ int build_canvas(spade_ctx *ctx, const spade_polys *polys, spade_canvas *cv)
     SPADE_HIP(ctx, hipGetLastError());
 
     uint64_t *row_nrec = (uint64_t *)drc.p;
-    uint64_t *row_nel = row_nrec + (H + 1);
-    uint64_t *row_nbp = row_nel + (H + 1);
+    uint64_t *row_nloc = row_nrec + (H + 1);
+    uint64_t *row_npart = row_nloc + (H + 1);
+    uint64_t *row_nbp = row_npart + (H + 1);
     uint64_t *rec_base = row_nbp + (H + 1);
-    uint64_t *el_base = rec_base + (H + 1);
-    SPADE_HIP(ctx, hipMemsetAsync(drc.p, 0, 8 * 6 * ((size_t)H + 1), st));
+    uint64_t *loc_base = rec_base + (H + 1);
+    uint64_t *part_base = loc_base + (H + 1);
+    uint64_t *bp_scan = part_base + (H + 1);
+    SPADE_HIP(ctx, hipMemsetAsync(drc.p, 0, 8 * 8 * ((size_t)H + 1), st));
 
     RowArgs ra{};
     ra.m = m;
-    ra.cbits = cbits;
-    ra.pmask = (pbits >= 64) ? ~0ULL : ((1ULL << pbits) - 1);
+    ra.Wt = Wt;
     ra.row_off = (const uint32_t *)drow.p;
-    ra.skeys = (const uint64_t *)dk2.p;
+    ra.spoly = s_poly;
     ra.sedge = s_edge;
     ra.sc = s_c;
     ra.sf = s_f;
-    ra.nextp = (uint32_t *)dnext.p;
     ra.edges = (const Edge *)cv->edges.p;
-    ra.row_nrec = row_nrec; ra.row_nel = row_nel; ra.row_nbp = row_nbp;
-    ra.rec_base = rec_base; ra.el_base = el_base;
+    ra.row_nrec = row_nrec; ra.row_nloc = row_nloc; ra.row_npart = row_npart; ra.row_nbp = row_nbp;
+    ra.rec_base = rec_base; ra.loc_base = loc_base; ra.part_base = part_base;
     ra.errflags = d_err;
-    const int rgrid = std::min(H, 4096);
-    hipLaunchKernelGGL(k_rows<false>, dim3(rgrid), dim3(ROW_THREADS), 0, st, ra);
+    // stage up to `cap` entries of a row in LDS; aim for two workgroups per CU
+    const size_t col_bytes = row_lds_bytes(W, 0);
+    const size_t target = (col_bytes <= 60 * 1024) ? 78 * 1024 : 150 * 1024;
+    ra.cap = (int)std::max<size_t>(256, (target - std::min(target - 256 * 27, col_bytes)) / 27);
+    if (T > (uint64_t)ra.cap) {
+        // some row may exceed the LDS stage: global auxiliary words for it
+        if (ensure(ctx, ctx->scratch[S_NEXTP], sizeof(uint32_t) * 5 * Ts)) return SPADE_E_NOMEM;
+        ra.gaux = (uint32_t *)ctx->scratch[S_NEXTP].p;
+    }
+    const size_t rlds = row_lds_bytes(W, ra.cap);
+    SPADE_HIP(ctx, hipFuncSetAttribute((const void *)k_rows<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)rlds));
+    SPADE_HIP(ctx, hipFuncSetAttribute((const void *)k_rows<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)rlds));
+    const int rgrid = std::min(H, 8192);
+    hipLaunchKernelGGL(k_rows<false>, dim3(rgrid), dim3(ROW_THREADS), rlds, st, ra);
     SPADE_HIP(ctx, hipGetLastError());
 
-    // per-row bases (inclusive scan shifted: scan H+1 entries with a zero tail)
+    // per-row bases (exclusive scans over H+1 entries with a zero tail)
     tb = 0;
     SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(nullptr, tb, row_nrec, rec_base, H + 1, st));
     if (ensure(ctx, cub, tb)) return SPADE_E_NOMEM;
     SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(cub.p, tb, row_nrec, rec_base, H + 1, st));
-    SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(cub.p, tb, row_nel, el_base, H + 1, st));
-    // total boundary pixels: scan into the (unused) tail of row_nbp's neighbour
-    uint64_t *bp_scan = el_base + (H + 1);
+    SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(cub.p, tb, row_nloc, loc_base, H + 1, st));
+    SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(cub.p, tb, row_npart, part_base, H + 1, st));
     SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(cub.p, tb, row_nbp, bp_scan, H + 1, st));
     uint64_t *hs = (uint64_t *)ensure_pinned(ctx, 64);
     SPADE_HIP(ctx, hipMemcpyAsync(hs + 0, rec_base + H, 8, hipMemcpyDeviceToHost, st));
-    SPADE_HIP(ctx, hipMemcpyAsync(hs + 1, el_base + H, 8, hipMemcpyDeviceToHost, st));
-    SPADE_HIP(ctx, hipMemcpyAsync(hs + 2, bp_scan + H, 8, hipMemcpyDeviceToHost, st));
+    SPADE_HIP(ctx, hipMemcpyAsync(hs + 1, loc_base + H, 8, hipMemcpyDeviceToHost, st));
+    SPADE_HIP(ctx, hipMemcpyAsync(hs + 2, part_base + H, 8, hipMemcpyDeviceToHost, st));
+    SPADE_HIP(ctx, hipMemcpyAsync(hs + 3, bp_scan + H, 8, hipMemcpyDeviceToHost, st));
     SPADE_HIP(ctx, hipStreamSynchronize(st));
-    const uint64_t nrec = hs[0], nel = hs[1], nbp = hs[2];
+    const uint64_t nrec = hs[0], nloc = hs[1], npart = hs[2], nbp = hs[3];
     if (nrec >= (uint64_t)BFLAG) return set_error(ctx, SPADE_E_UNSUPPORTED, "boundary index exceeds 2^31 records; lower the canvas resolution");
-    if (nel >= 0xffffffffULL) return set_error(ctx, SPADE_E_UNSUPPORTED, "boundary edge list exceeds 2^32 entries");
+    if (nloc >= 0xffffffffULL || npart >= 0xffffffffULL)
+        return set_error(ctx, SPADE_E_UNSUPPORTED, "boundary edge lists exceed 2^32 entries");
     if (ensure(ctx, cv->cands, sizeof(Cand) * (size_t)std::max<uint64_t>(nrec, 1)) ||
-        ensure(ctx, cv->elist, sizeof(uint32_t) * (size_t)std::max<uint64_t>(nel, 1)))
+        ensure(ctx, cv->ledges, sizeof(Edge) * (size_t)std::max<uint64_t>(nloc, 1)) ||
+        ensure(ctx, cv->pspan, sizeof(double2) * (size_t)std::max<uint64_t>(npart, 1)))
         return SPADE_E_NOMEM;
     ra.cells = (uint32_t *)cv->cells.p;
     ra.cands = (Cand *)cv->cands.p;
-    ra.elist = (uint32_t *)cv->elist.p;
-    hipLaunchKernelGGL(k_rows<true>, dim3(rgrid), dim3(ROW_THREADS), 0, st, ra);
+    ra.ledges = (Edge *)cv->ledges.p;
+    ra.pspan = (double2 *)cv->pspan.p;
+    hipLaunchKernelGGL(k_rows<true>, dim3(rgrid), dim3(ROW_THREADS), rlds, st, ra);
     SPADE_HIP(ctx, hipGetLastError());
+    {
+        const int64_t ncoarse = (int64_t)view.Wc * view.Hc;
+        const int cgrid = (int)std::max<int64_t>(1, std::min<int64_t>((ncoarse + 3) / 4, 65536));
+        hipLaunchKernelGGL(k_coarse, dim3(cgrid), dim3(256), 0, st, W, H, Wt, blog, view.Wc, view.Hc,
+                           (const uint32_t *)cv->cells.p, (uint16_t *)cv->coarse.p);
+        SPADE_HIP(ctx, hipGetLastError());
+    }
     unsigned *herr2 = (unsigned *)ensure_pinned(ctx, 64);
     SPADE_HIP(ctx, hipMemcpyAsync(herr2, d_err, sizeof(unsigned), hipMemcpyDeviceToHost, st));
     SPADE_HIP(ctx, hipStreamSynchronize(st));
     if (herr2[0] & 8u) return set_error(ctx, SPADE_E_HIP, "internal: boundary pixel without candidates");
+    if (herr2[0] & 16u)
+        return set_error(ctx, SPADE_E_UNSUPPORTED, "a boundary pixel has more than 32767 edges of one polygon; raise the canvas resolution");
     view.cands = (const Cand *)cv->cands.p;
-    view.elist = (const uint32_t *)cv->elist.p;
+    view.ledges = (const Edge *)cv->ledges.p;
+    view.pspan = (const double2 *)cv->pspan.p;
     cv->n_boundary = (int64_t)nbp;
     cv->n_cands = (int64_t)nrec;
-    cv->n_elist = (int64_t)nel;
+    cv->n_elist = (int64_t)(nloc + npart);
     return SPADE_OK;
 }
 

@@ -33,7 +33,7 @@ EXPORTS = [
     "spade_ctx_set_canvas_size", "spade_select", "spade_join_count", "spade_join_pairs",
     "spade_canvas_build", "spade_canvas_destroy", "spade_canvas_info", "spade_canvas_select",
     "spade_canvas_join_count", "spade_canvas_join_count_async", "spade_canvas_join_pairs",
-    "spade_orient_batch",
+    "spade_orient_batch", "spade_ctx_set_timing", "spade_ctx_last_timing",
 ]
 
 
@@ -85,6 +85,8 @@ def load_library():
     lib.spade_canvas_join_count_async.argtypes = [vp, vp, P(_Points), vp]
     lib.spade_canvas_join_pairs.argtypes = [vp, vp, P(_Points), vp, vp, i64, P(i64)]
     lib.spade_orient_batch.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp]
+    lib.spade_ctx_set_timing.argtypes = [vp, ctypes.c_int]
+    lib.spade_ctx_last_timing.argtypes = [vp, P(ctypes.c_float), P(ctypes.c_float)]
     for name in EXPORTS:
         f = getattr(lib, name)
         if f.restype is ctypes.c_int:
@@ -193,6 +195,15 @@ class Context:
 
     def set_canvas_size(self, width: int = 0, height: int = 0):
         self._check(self.lib.spade_ctx_set_canvas_size(self.handle, int(width), int(height)))
+
+    def set_timing(self, on: bool = True):
+        self._check(self.lib.spade_ctx_set_timing(self.handle, 1 if on else 0))
+
+    def last_timing(self):
+        """(raster_ms, probe_ms) of the last query (HIP events on its stream)."""
+        r, p = ctypes.c_float(), ctypes.c_float()
+        self._check(self.lib.spade_ctx_last_timing(self.handle, ctypes.byref(r), ctypes.byref(p)))
+        return float(r.value), float(p.value)
 
     def polys(self, polys):
         return polys if isinstance(polys, DevicePolys) else DevicePolys(polys, self.device)

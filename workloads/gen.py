@@ -96,11 +96,16 @@ def _mixture_chunk(params, n, rng):
     return outx, outy
 
 
-def mixture_points(n: int, seed: int = 2, L: float = EXTENT_M, out=None):
+def mixture_points(n: int, seed: int = 2, L: float = EXTENT_M, out=None, workers: int = 0):
     """n taxi-like clustered points in [0,L)^2, generated chunk by chunk.
 
     ``out`` may be a pair of preallocated float64 arrays (e.g. memory maps).
+    Chunks are independent streams, so ``workers`` threads give the same
+    result as one (0 = up to 16 threads).
     """
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+
     params = mixture_params(seed, L)
     if out is None:
         x = np.empty(n)
@@ -108,13 +113,22 @@ def mixture_points(n: int, seed: int = 2, L: float = EXTENT_M, out=None):
     else:
         x, y = out
     nchunks = (n + CHUNK - 1) // CHUNK
-    for ci in range(nchunks):
+
+    def work(ci):
         lo = ci * CHUNK
         m = min(CHUNK, n - lo)
-        rng = rng_for(seed, 2, ci)
-        cx, cy = _mixture_chunk(params, m, rng)
+        cx, cy = _mixture_chunk(params, m, rng_for(seed, 2, ci))
         x[lo:lo + m] = cx
         y[lo:lo + m] = cy
+
+    if workers <= 0:
+        workers = min(16, os.cpu_count() or 1)
+    if workers == 1 or nchunks <= 1:
+        for ci in range(nchunks):
+            work(ci)
+    else:
+        with ThreadPoolExecutor(min(workers, nchunks)) as ex:
+            list(ex.map(work, range(nchunks)))
     return x, y
 
 
