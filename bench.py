@@ -68,6 +68,9 @@ def main():
     ap.add_argument("--canvas", type=int, nargs=2, default=(0, 0), metavar=("W", "H"))
     ap.add_argument("--cpu-sample", type=int, default=40_000_000,
                     help="points of the prefix timed with the CPU oracle (0 = skip)")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="before the timed steps, copy a buffer of this many MiB on the device "
+                         "(a reference kernel of known traffic for hardware counter runs)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -95,6 +98,14 @@ def main():
     torch.cuda.synchronize()
     ctx.set_timing(True)
 
+    if args.calibrate_copy_mib > 0:
+        src = torch.ones(args.calibrate_copy_mib * (1 << 20) // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: %d MiB read, %d MiB written" % (args.calibrate_copy_mib, args.calibrate_copy_mib))
+        del src, dst
     for _ in range(args.warmup):
         counts = ctx.join_count(dx, dy, dpolys)
     torch.cuda.synchronize()

@@ -109,7 +109,7 @@ const char *spade_last_error(const spade_ctx *ctx);
  * the polygons' bounding box (the paper's canvas resolution, Sec. 4.2).
  * 0 x 0 selects it automatically.  Results never depend on it: it only
  * changes how many points need the exact boundary test.  Limits:
- * 1 <= width <= 8192, 1 <= height <= 65535. */
+ * 1 <= width <= 8192, 1 <= height <= 16384. */
 int spade_ctx_set_canvas_size(spade_ctx *ctx, int32_t width, int32_t height);
 
 /* Phase timing (tracing aid).  on != 0 makes later query calls record HIP
@@ -153,13 +153,15 @@ int spade_canvas_build(spade_ctx *ctx, const spade_polys *polys, spade_canvas **
 void spade_canvas_destroy(spade_canvas *cv);
 
 /* Canvas facts: width, height, polygon count, boundary-pixel count and
- * device bytes held (any pointer may be NULL). */
+ * device bytes held (any pointer may be NULL).  For a batch canvas set:
+ * the first canvas's width and height, totals for the rest. */
 int spade_canvas_info(const spade_canvas *cv, int32_t *width, int32_t *height,
                       int64_t *n_polys, int64_t *n_boundary_pixels, int64_t *device_bytes);
 
 /* The three queries against a prebuilt canvas; same contracts as above.
  * spade_canvas_join_count_async only enqueues (no synchronisation); its
- * counts are complete when ctx's stream reaches that point. */
+ * counts are complete when ctx's stream reaches that point.  A batch canvas
+ * set (spade_batch_build) is refused here (SPADE_E_INVALID). */
 int spade_canvas_select(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts,
                         uint32_t *out_ids, int64_t cap, int64_t *n_out);
 int spade_canvas_join_count(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts,
@@ -168,6 +170,55 @@ int spade_canvas_join_count_async(spade_ctx *ctx, const spade_canvas *cv,
                                   const spade_points *pts, uint64_t *out_counts);
 int spade_canvas_join_pairs(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts,
                             uint32_t *out_pt, uint32_t *out_poly, int64_t cap, int64_t *n_out);
+
+/* ---- Resident point tables and query batches.  Many queries share one
+ * pass over a resident, spatially clustered point table (the data stays in
+ * HBM; each table chunk is read once for all queries whose bounding box
+ * meets it), and the query polygons of a batch are rasterised as one canvas
+ * set in the same kernel launches. */
+typedef struct spade_table spade_table;
+
+/* Copy the points into a new device-resident table clustered by a grid over
+ * their bounding box (the input arrays may be freed after the call).  Point
+ * ids in results stay the 0-based positions in the input arrays; points with
+ * a non-finite coordinate are kept and lie in no polygon.  At most 2^31 - 1
+ * points (SPADE_E_TOO_LARGE beyond). */
+int spade_table_create(spade_ctx *ctx, const spade_points *pts, spade_table **out);
+
+/* Free a table (NULL is a no-op).  Must not be in use by queued work. */
+void spade_table_destroy(spade_table *t);
+
+/* Table facts: points, grid side, chunks, device bytes (NULL-able). */
+int spade_table_info(const spade_table *t, int64_t *n, int32_t *grid, int64_t *chunks,
+                     int64_t *device_bytes);
+
+/* Rasterise a batch of queries into one canvas set: query q consists of
+ * polygons qbound[q] .. qbound[q+1]-1 of `polys` (qbound: host array of
+ * nq + 1 non-decreasing offsets, qbound[0] == 0, qbound[nq] == n_polys).
+ * Each query gets its own canvas sized for its polygons. */
+int spade_batch_build(spade_ctx *ctx, const spade_polys *polys, int32_t nq, const int64_t *qbound,
+                      spade_canvas **out);
+
+/* Selection for every query of a batch (each query must hold exactly one
+ * polygon), over a table: the ids of the table points inside, ascending
+ * within each query, queries one after another in out_ids [cap] (device).
+ * out_off [nq + 1] (host) receives each query's start; out_off[nq] is the
+ * total.  If the total exceeds cap, nothing is written to out_ids and
+ * SPADE_E_CAPACITY is returned with out_off filled.  Evaluated with the
+ * paper's two-step Map (Sec. 5.1): a count pass, then a write pass. */
+int spade_batch_select(spade_ctx *ctx, const spade_canvas *set, const spade_table *t,
+                       uint32_t *out_ids, int64_t cap, int64_t *out_off);
+
+/* Join-count for every query of a batch over a table: out_counts [n_polys
+ * of the batch] (device) receives, for each polygon of the batch polygon
+ * set, the number of table points inside it. */
+int spade_batch_join_count(spade_ctx *ctx, const spade_canvas *set, const spade_table *t,
+                           uint64_t *out_counts);
+
+/* Canvas sizing for later builds when no fixed size is set: about `ppv`
+ * pixels per polygon vertex, between 64 x 64 and 4096 x 4096 pixels per
+ * canvas (default 256).  The autotuner sets this. */
+int spade_ctx_set_pixels_per_vertex(spade_ctx *ctx, double ppv);
 
 /* Device-side exact predicate, exposed for testing the arithmetic in
  * isolation: for n triples (a, b, c) stored as 6 device arrays, writes

@@ -1,0 +1,717 @@
+// Resident point tables and query batches.
+//
+// A table keeps the points in HBM sorted by the cell of a G x G grid over
+// their bounding box (row-major cells) and cut into chunks of CHUNK points
+// with their exact bounding boxes.  A batch is a canvas set (one canvas per
+// query).  Work is organised by (chunk, query) pairs whose boxes overlap:
+// one workgroup holds a chunk's points in registers and tests them against
+// every query that can contain one of them, so a chunk is read from HBM once
+// per pass for the whole batch.  Selection output uses the paper's two-step
+// Map (Sec. 5.1): a count pass sizes every (chunk, query) pair, a scan places
+// the pairs query by query, a write pass stores the ids, and a segmented
+// radix sort orders each query's ids.
+#include "common.h"
+#include "exact.h"
+#include "lookup.h"
+
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+namespace spade {
+
+constexpr int CHUNK = 4096;               // table points per chunk
+constexpr int BT_THREADS = 256;           // batch probe workgroup
+constexpr int BT_PER = CHUNK / BT_THREADS;
+constexpr int GRID_MAX = 1024;            // table grid side
+
+}  // namespace spade
+
+struct spade_table {
+    int device = 0;
+    int64_t n = 0;        // points
+    int64_t nfin = 0;     // points with finite coordinates (clustered prefix)
+    int G = 1;
+    double X0 = 0, Y0 = 0, sx = 0, sy = 0;
+    int64_t nchunk = 0;
+    spade::DevBuf x, y, ids, cell_off, chunk_bb;
+    size_t bytes() const { return x.cap + y.cap + ids.cap + cell_off.cap + chunk_bb.cap; }
+};
+
+namespace spade {
+
+__device__ __forceinline__ unsigned long long okey(double v)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    return (b & 0x8000000000000000ull) ? ~b : (b | 0x8000000000000000ull);
+}
+
+static double from_okey(unsigned long long k)
+{
+    const unsigned long long b = (k & 0x8000000000000000ull) ? (k & 0x7fffffffffffffffull) : ~k;
+    double d;
+    std::memcpy(&d, &b, sizeof d);
+    return d;
+}
+
+static int grid_of(int64_t n, int64_t cap = 65536)
+{
+    return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, cap));
+}
+
+static int bits_of(uint64_t v)
+{
+    int b = 0;
+    while (b < 64 && (v >> b) != 0) ++b;
+    return b;
+}
+
+// Bounding box of the finite points: keys of (min x, -max x, min y, -max y).
+__global__ __launch_bounds__(256) void k_pt_bbox(int64_t n, const double *X, const double *Y,
+                                                 unsigned long long *bb)
+{
+    __shared__ unsigned long long s[4][256];
+    unsigned long long k0 = ~0ull, k1 = ~0ull, k2 = ~0ull, k3 = ~0ull;
+    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += nth) {
+        const double x = X[i], y = Y[i];
+        if (!isfinite(x) || !isfinite(y)) continue;
+        k0 = min(k0, okey(x)); k1 = min(k1, okey(-x));
+        k2 = min(k2, okey(y)); k3 = min(k3, okey(-y));
+    }
+    s[0][threadIdx.x] = k0; s[1][threadIdx.x] = k1; s[2][threadIdx.x] = k2; s[3][threadIdx.x] = k3;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int q = 0; q < 4; ++q) s[q][threadIdx.x] = min(s[q][threadIdx.x], s[q][threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) atomicMin(&bb[threadIdx.x], s[threadIdx.x][0]);
+}
+
+// Grid cell key of every point (non-finite points: G * G, sorted last).
+__global__ void k_pt_key(int64_t n, const double *X, const double *Y, double X0, double Y0, double sx,
+                         double sy, int G, uint32_t *keys, uint32_t *idx)
+{
+    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += nth) {
+        const double x = X[i], y = Y[i];
+        uint32_t k = (uint32_t)G * (uint32_t)G;
+        if (isfinite(x) && isfinite(y)) {
+            const int cx = (int)fmin((double)(G - 1), fmax(0.0, floor((x - X0) * sx)));
+            const int cy = (int)fmin((double)(G - 1), fmax(0.0, floor((y - Y0) * sy)));
+            k = (uint32_t)cy * (uint32_t)G + (uint32_t)cx;
+        }
+        keys[i] = k;
+        idx[i] = (uint32_t)i;
+    }
+}
+
+__global__ void k_pt_gather(int64_t n, const uint32_t *perm, const double *X, const double *Y, double *x2,
+                            double *y2)
+{
+    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += nth) {
+        const uint32_t p = perm[i];
+        x2[i] = X[p];
+        y2[i] = Y[p];
+    }
+}
+
+// cell_off[c] = first sorted point of cell c (c = 0 .. G*G + 1).
+__global__ void k_cell_off(int64_t n, const uint32_t *skeys, int64_t ncell, uint32_t *cell_off)
+{
+    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += nth) {
+        const int64_t ki = (i < n) ? (int64_t)skeys[i] : ncell;
+        const int64_t kp = (i == 0) ? -1 : (int64_t)skeys[i - 1];
+        for (int64_t c = kp + 1; c <= ki; ++c) cell_off[c] = (uint32_t)i;
+    }
+}
+
+// Exact bounding box of every chunk of the finite prefix (one wave per chunk).
+__global__ __launch_bounds__(256) void k_chunk_bb(int64_t nfin, int64_t nchunk, const double *X,
+                                                  const double *Y, double4 *bb)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t c = wave; c < nchunk; c += nw) {
+        const int64_t b = c * CHUNK, e = std::min<int64_t>(nfin, b + CHUNK);
+        double x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY;
+        for (int64_t i = b + lane; i < e; i += 64) {
+            x0 = fmin(x0, X[i]); x1 = fmax(x1, X[i]);
+            y0 = fmin(y0, Y[i]); y1 = fmax(y1, Y[i]);
+        }
+        for (int d = 32; d > 0; d >>= 1) {
+            x0 = fmin(x0, __shfl_xor(x0, d, 64)); x1 = fmax(x1, __shfl_xor(x1, d, 64));
+            y0 = fmin(y0, __shfl_xor(y0, d, 64)); y1 = fmax(y1, __shfl_xor(y1, d, 64));
+        }
+        if (lane == 0) bb[c] = make_double4(x0, y0, x1, y1);
+    }
+}
+
+// ------------------------------------------------------------ pairs
+
+// Chunk c can hold a point of canvas q: its closed point box meets the
+// canvas's half-open polygon box.
+__device__ __forceinline__ bool overlaps(const double4 &b, const CanvasDesc &d)
+{
+    return !d.empty && b.z >= d.bx0 && b.x < d.bx1 && b.w >= d.by0 && b.y < d.by1;
+}
+
+// Pass 1 counts overlapping chunks per canvas, pass 2 lists them (query-major).
+template <bool FILL>
+__global__ __launch_bounds__(256) void k_pairs(int nq, int64_t nchunk, const double4 *bb, const CanvasDesc *cds,
+                                               unsigned long long *qcount, const unsigned long long *qbase,
+                                               unsigned long long *qfill, uint32_t *pq, uint32_t *pc)
+{
+    for (int q = blockIdx.y; q < nq; q += gridDim.y) {
+        const CanvasDesc d = cds[q];
+        uint32_t mine = 0;
+        for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nchunk;
+             c += (int64_t)gridDim.x * blockDim.x) {
+            if (!overlaps(bb[c], d)) continue;
+            if (!FILL) { ++mine; continue; }
+            const unsigned long long p = qbase[q] + atomicAdd(&qfill[q], 1ull);
+            pq[p] = (uint32_t)q;
+            pc[p] = (uint32_t)c;
+        }
+        if (!FILL && mine) atomicAdd(&qcount[q], (unsigned long long)mine);
+    }
+}
+
+// Chunk-major lists of pair ids (counting sort by chunk).
+__global__ void k_pair_chunk_count(int64_t np, const uint32_t *pc, unsigned int *ccount)
+{
+    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < np; p += nth) atomicAdd(&ccount[pc[p]], 1u);
+}
+
+__global__ void k_pair_chunk_fill(int64_t np, const uint32_t *pc, const unsigned int *cbase, unsigned int *cfill,
+                                  uint32_t *plist)
+{
+    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < np; p += nth) {
+        const uint32_t c = pc[p];
+        plist[cbase[c] + atomicAdd(&cfill[c], 1u)] = (uint32_t)p;
+    }
+}
+
+// Canvas q of a set as a probe view (descriptor in device memory).
+__device__ __forceinline__ CanvasView set_view(const CanvasDesc &d, const uint32_t *cells, const uint16_t *coarse,
+                                               const uint4 *desc, const uint32_t *bpix, const Cand *cands,
+                                               const Edge *ledges, const double2 *pspan)
+{
+    CanvasView v;
+    v.X0 = d.X0; v.Y0 = d.Y0; v.sx = d.sx; v.sy = d.sy;
+    v.bx0 = d.bx0; v.by0 = d.by0; v.bx1 = d.bx1; v.by1 = d.by1;
+    v.W = d.W; v.H = d.H; v.Wt = d.Wt; v.Wc = d.Wc; v.Hc = d.Hc; v.blog = d.blog;
+    v.M = d.M;
+    v.cells = cells + d.cell_off;
+    v.coarse = coarse + d.coarse_off;
+    v.desc = desc + d.desc_off;
+    v.bpix = bpix;
+    v.cands = cands;
+    v.ledges = ledges;
+    v.pspan = pspan;
+    return v;
+}
+
+struct SetArgs {
+    const CanvasDesc *cds;
+    const uint32_t *cells;
+    const uint16_t *coarse;
+    const uint4 *desc;
+    const uint32_t *bpix;
+    const Cand *cands;
+    const Edge *ledges;
+    const double2 *pspan;
+};
+
+// ------------------------------------------------------------ batch select
+
+// Pass 1 (EMIT = false): matches per pair into pcount.  Pass 2 (EMIT): ids
+// of the matching points from pbase[pair] on, in an order the per-query
+// sort that follows makes ascending.
+template <bool EMIT>
+__global__ __launch_bounds__(BT_THREADS) void k_batch_select(SetArgs S, int64_t nfin, int64_t nchunk,
+                                                             const double *X, const double *Y,
+                                                             const uint32_t *ids, const unsigned int *cbase,
+                                                             const uint32_t *plist, const uint32_t *pq,
+                                                             uint32_t *pcount, const unsigned long long *pbase,
+                                                             uint32_t *out)
+{
+    __shared__ uint32_t wsum[BT_THREADS / 64];
+    for (int64_t c = blockIdx.x; c < nchunk; c += gridDim.x) {
+        const int64_t b = c * CHUNK;
+        double xs[BT_PER], ys[BT_PER];
+#pragma unroll
+        for (int u = 0; u < BT_PER; ++u) {
+            const int64_t i = b + (int64_t)u * BT_THREADS + threadIdx.x;   // coalesced
+            xs[u] = i < nfin ? X[i] : NAN;
+            ys[u] = i < nfin ? Y[i] : NAN;
+        }
+        for (uint32_t t = cbase[c]; t < cbase[c + 1]; ++t) {
+            const uint32_t p = plist[t];
+            const CanvasDesc d = S.cds[pq[p]];
+            const CanvasView v = set_view(d, S.cells, S.coarse, S.desc, S.bpix, S.cands, S.ledges, S.pspan);
+            uint32_t hit = 0;
+#pragma unroll
+            for (int u = 0; u < BT_PER; ++u) {
+                const uint32_t w = lookup(v, v.coarse, xs[u], ys[u]);
+                bool in = false;
+                if (w & BFLAG) {
+                    uint32_t rec = w & ~BFLAG;
+                    while (true) {
+                        const Cand cd = v.cands[rec];
+                        if (cand_inside(v, cd, xs[u], ys[u])) in = true;
+                        if (cd.meta & CAND_LAST) break;
+                        ++rec;
+                    }
+                } else {
+                    in = w != 0u;
+                }
+                hit |= (in ? 1u : 0u) << u;
+            }
+            // block-wide exclusive scan of the per-thread match counts
+            const uint32_t cnt = (uint32_t)__popc(hit);
+            const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+            uint32_t inc = cnt;
+#pragma unroll
+            for (int dd = 1; dd < 64; dd <<= 1) {
+                const uint32_t tt = __shfl_up(inc, dd, 64);
+                if (lane >= dd) inc += tt;
+            }
+            if (lane == 63) wsum[wv] = inc;
+            __syncthreads();
+            uint32_t pre = 0, tot = 0;
+#pragma unroll
+            for (int q = 0; q < BT_THREADS / 64; ++q) {
+                if (q < wv) pre += wsum[q];
+                tot += wsum[q];
+            }
+            __syncthreads();
+            if (!EMIT) {
+                if (threadIdx.x == 0) pcount[p] = tot;
+            } else if (hit) {
+                unsigned long long pos = pbase[p] + pre + inc - cnt;
+#pragma unroll
+                for (int u = 0; u < BT_PER; ++u)
+                    if (hit & (1u << u)) out[pos++] = ids[b + (int64_t)u * BT_THREADS + threadIdx.x];
+            }
+        }
+    }
+}
+
+// Query starts from pair bases: qoff[q] = pbase[first pair of q], qoff[nq] = total.
+__global__ void k_query_off(int nq, const unsigned long long *qbase, const unsigned long long *pbase, int64_t np,
+                            unsigned long long total, unsigned long long *qoff)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q > nq) return;
+    if (q == nq) { qoff[nq] = total; return; }
+    const unsigned long long p = qbase[q];
+    qoff[q] = (p < (unsigned long long)np) ? pbase[p] : total;
+}
+
+// ------------------------------------------------------------ batch join-count
+
+constexpr int HSLOTS = 512;   // LDS hash slots per workgroup
+
+template <bool dummy>
+__global__ __launch_bounds__(BT_THREADS) void k_batch_count(SetArgs S, int64_t nfin, int64_t nchunk,
+                                                            const double *X, const double *Y,
+                                                            const unsigned int *cbase, const uint32_t *plist,
+                                                            const uint32_t *pq, unsigned long long *counts)
+{
+    __shared__ unsigned long long hkey[HSLOTS];   // polygon id + 1 (0: empty)
+    __shared__ uint32_t hval[HSLOTS];
+    for (int64_t c = blockIdx.x; c < nchunk; c += gridDim.x) {
+        const int64_t b = c * CHUNK;
+        double xs[BT_PER], ys[BT_PER];
+#pragma unroll
+        for (int u = 0; u < BT_PER; ++u) {
+            const int64_t i = b + (int64_t)u * BT_THREADS + threadIdx.x;
+            xs[u] = i < nfin ? X[i] : NAN;
+            ys[u] = i < nfin ? Y[i] : NAN;
+        }
+        for (int s = threadIdx.x; s < HSLOTS; s += BT_THREADS) { hkey[s] = 0ull; hval[s] = 0u; }
+        __syncthreads();
+        for (uint32_t t = cbase[c]; t < cbase[c + 1]; ++t) {
+            const uint32_t p = plist[t];
+            const CanvasDesc d = S.cds[pq[p]];
+            const CanvasView v = set_view(d, S.cells, S.coarse, S.desc, S.bpix, S.cands, S.ledges, S.pspan);
+            auto add = [&](uint32_t label) {
+                const unsigned long long key = (unsigned long long)(d.poly_base + label) + 1ull;
+                uint32_t h = (uint32_t)(key * 0x9E3779B97F4A7C15ull >> 55) & (HSLOTS - 1);
+                for (int probe = 0; probe < 8; ++probe, h = (h + 1) & (HSLOTS - 1)) {
+                    unsigned long long cur = hkey[h];
+                    if (cur == 0ull) {
+                        cur = atomicCAS(&hkey[h], 0ull, key);
+                        if (cur == 0ull) cur = key;
+                    }
+                    if (cur == key) { atomicAdd(&hval[h], 1u); return; }
+                }
+                atomicAdd(&counts[key - 1ull], 1ull);
+            };
+#pragma unroll
+            for (int u = 0; u < BT_PER; ++u) {
+                const uint32_t w = lookup(v, v.coarse, xs[u], ys[u]);
+                if (w == 0u) continue;
+                if (!(w & BFLAG)) { add(w - 1u); continue; }
+                uint32_t rec = w & ~BFLAG;
+                while (true) {
+                    const Cand cd = v.cands[rec];
+                    if (cand_inside(v, cd, xs[u], ys[u])) add(cd.poly);
+                    if (cd.meta & CAND_LAST) break;
+                    ++rec;
+                }
+            }
+        }
+        __syncthreads();
+        for (int s = threadIdx.x; s < HSLOTS; s += BT_THREADS)
+            if (hkey[s]) atomicAdd(&counts[hkey[s] - 1ull], (unsigned long long)hval[s]);
+        __syncthreads();
+    }
+}
+
+__global__ void k_zero64(int64_t n, unsigned long long *p)
+{
+    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += nth) p[i] = 0ull;
+}
+
+__global__ void k_zero32(int64_t n, unsigned int *p)
+{
+    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += nth) p[i] = 0u;
+}
+
+static int num_cus_of(int device)
+{
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || v <= 0) v = 256;
+    return v;
+}
+
+// Batch scratch: pairs in query-major order, their chunk-major lists.
+struct Pairs {
+    int64_t np = 0;
+    uint32_t *pq = nullptr, *pc = nullptr, *plist = nullptr;
+    unsigned int *cbase = nullptr;
+    unsigned long long *qbase = nullptr;
+};
+
+static int make_pairs(spade_ctx *ctx, const spade_canvas *set, const spade_table *t, Pairs &P)
+{
+    hipStream_t st = ctx->stream;
+    const int nq = set->nc;
+    const int64_t nchunk = t->nchunk;
+    DevBuf &bq = ctx->scratch[S_KEYS];
+    if (ensure(ctx, bq, sizeof(unsigned long long) * (3 * (size_t)nq + 3) + sizeof(unsigned int) * 2 * ((size_t)nchunk + 2)))
+        return SPADE_E_NOMEM;
+    unsigned long long *qcount = (unsigned long long *)bq.p;
+    unsigned long long *qbase = qcount + (nq + 1);
+    unsigned long long *qfill = qbase + (nq + 1);
+    unsigned int *ccount = (unsigned int *)(qfill + (nq + 1));
+    unsigned int *cbase = ccount + (nchunk + 1);
+    hipLaunchKernelGGL(k_zero64, dim3(grid_of(3 * nq + 3, 1024)), dim3(256), 0, st, (int64_t)(3 * nq + 3), qcount);
+    hipLaunchKernelGGL(k_zero32, dim3(grid_of(2 * nchunk + 2, 4096)), dim3(256), 0, st, (int64_t)(2 * nchunk + 2), ccount);
+    SPADE_HIP(ctx, hipGetLastError());
+    const CanvasDesc *cds = (const CanvasDesc *)set->dcds.p;
+    const double4 *bb = (const double4 *)t->chunk_bb.p;
+    dim3 g((unsigned)std::max<int64_t>(1, std::min<int64_t>((nchunk + 255) / 256, 64)), (unsigned)std::min(nq, 32768));
+    if (nchunk > 0) {
+        hipLaunchKernelGGL(k_pairs<false>, g, dim3(256), 0, st, nq, nchunk, bb, cds, qcount, nullptr, nullptr, nullptr, nullptr);
+        SPADE_HIP(ctx, hipGetLastError());
+    }
+    DevBuf &cub = ctx->scratch[S_CUBTMP];
+    size_t tb = 0;
+    SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(nullptr, tb, qcount, qbase, nq + 1, st));
+    if (ensure(ctx, cub, tb)) return SPADE_E_NOMEM;
+    SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(cub.p, tb, qcount, qbase, nq + 1, st));
+    unsigned long long *h = (unsigned long long *)ensure_pinned(ctx, 64);
+    SPADE_HIP(ctx, hipMemcpyAsync(h, qbase + nq, 8, hipMemcpyDeviceToHost, st));
+    SPADE_HIP(ctx, hipStreamSynchronize(st));
+    const int64_t np = (int64_t)h[0];
+    if (np >= 0xffffffffLL) return set_error(ctx, SPADE_E_UNSUPPORTED, "too many (chunk, query) pairs in one batch");
+    DevBuf &bp = ctx->scratch[S_VALS];
+    if (ensure(ctx, bp, sizeof(uint32_t) * 3 * (size_t)std::max<int64_t>(np, 1))) return SPADE_E_NOMEM;
+    P.np = np;
+    P.pq = (uint32_t *)bp.p;
+    P.pc = P.pq + std::max<int64_t>(np, 1);
+    P.plist = P.pc + std::max<int64_t>(np, 1);
+    P.cbase = cbase;
+    P.qbase = qbase;
+    if (np > 0) {
+        hipLaunchKernelGGL(k_pairs<true>, g, dim3(256), 0, st, nq, nchunk, bb, cds, nullptr, qbase, qfill, P.pq, P.pc);
+        hipLaunchKernelGGL(k_pair_chunk_count, dim3(grid_of(np)), dim3(256), 0, st, np, P.pc, ccount);
+        SPADE_HIP(ctx, hipGetLastError());
+    }
+    tb = 0;
+    SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(nullptr, tb, ccount, cbase, (int)(nchunk + 1), st));
+    if (ensure(ctx, cub, tb)) return SPADE_E_NOMEM;
+    SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(cub.p, tb, ccount, cbase, (int)(nchunk + 1), st));
+    if (np > 0) {
+        hipLaunchKernelGGL(k_zero32, dim3(grid_of(nchunk + 1, 4096)), dim3(256), 0, st, nchunk + 1, ccount);
+        hipLaunchKernelGGL(k_pair_chunk_fill, dim3(grid_of(np)), dim3(256), 0, st, np, P.pc, cbase, ccount, P.plist);
+        SPADE_HIP(ctx, hipGetLastError());
+    }
+    return SPADE_OK;
+}
+
+static SetArgs set_args(const spade_canvas *set)
+{
+    SetArgs S;
+    S.cds = (const CanvasDesc *)set->dcds.p;
+    S.cells = (const uint32_t *)set->cells.p;
+    S.coarse = (const uint16_t *)set->coarse.p;
+    S.desc = (const uint4 *)set->desc.p;
+    S.bpix = (const uint32_t *)set->bpix.p;
+    S.cands = (const Cand *)set->cands.p;
+    S.ledges = (const Edge *)set->ledges.p;
+    S.pspan = (const double2 *)set->pspan.p;
+    return S;
+}
+
+}  // namespace spade
+
+using namespace spade;
+
+extern "C" {
+
+int spade_ctx_set_pixels_per_vertex(spade_ctx *ctx, double ppv)
+{
+    if (!ctx) return SPADE_E_INVALID;
+    if (!(ppv >= 1.0 && ppv <= 1e7)) return set_error(ctx, SPADE_E_INVALID, "pixels per vertex must be in [1, 1e7]");
+    ctx->ppv = ppv;
+    return SPADE_OK;
+}
+
+int spade_table_create(spade_ctx *ctx, const spade_points *pts, spade_table **out)
+{
+    if (!ctx || !out) return SPADE_E_INVALID;
+    *out = nullptr;
+    ctx->err.clear();
+    if (hipSetDevice(ctx->device) != hipSuccess) return set_error(ctx, SPADE_E_HIP, "hipSetDevice failed");
+    if (!pts || pts->n < 0 || (pts->n > 0 && (!pts->x || !pts->y)))
+        return set_error(ctx, SPADE_E_INVALID, "invalid point arrays");
+    if (pts->n > (int64_t)INT32_MAX) return set_error(ctx, SPADE_E_TOO_LARGE, "a table holds at most 2^31 - 1 points");
+    hipStream_t st = ctx->stream;
+    spade_table *t = new (std::nothrow) spade_table();
+    if (!t) return set_error(ctx, SPADE_E_NOMEM, "host allocation failed");
+    t->device = ctx->device;
+    const int64_t n = pts->n;
+    t->n = n;
+    auto fail = [&](int rc) { spade_table_destroy(t); return rc; };
+    const size_t ns = (size_t)std::max<int64_t>(n, 1);
+    if (ensure(ctx, t->x, 8 * ns) || ensure(ctx, t->y, 8 * ns) || ensure(ctx, t->ids, 4 * ns)) return fail(SPADE_E_NOMEM);
+    // bounding box and grid
+    DevBuf &bb = ctx->scratch[S_BLOCKRED];
+    if (ensure(ctx, bb, 64)) return fail(SPADE_E_NOMEM);
+    SPADE_HIP(ctx, hipMemsetAsync(bb.p, 0xff, 32, st));
+    if (n > 0) hipLaunchKernelGGL(k_pt_bbox, dim3(grid_of(n, 1024)), dim3(256), 0, st, n, pts->x, pts->y, (unsigned long long *)bb.p);
+    unsigned long long *h = (unsigned long long *)ensure_pinned(ctx, 64);
+    SPADE_HIP(ctx, hipMemcpyAsync(h, bb.p, 32, hipMemcpyDeviceToHost, st));
+    SPADE_HIP(ctx, hipStreamSynchronize(st));
+    double x0 = from_okey(h[0]), x1 = -from_okey(h[1]), y0 = from_okey(h[2]), y1 = -from_okey(h[3]);
+    if (!(x0 <= x1)) { x0 = 0; x1 = 1; y0 = 0; y1 = 1; }
+    const int G = (int)std::max<int64_t>(1, std::min<int64_t>(GRID_MAX, (int64_t)std::sqrt((double)n / 64.0)));
+    t->G = G;
+    t->X0 = x0; t->Y0 = y0;
+    t->sx = (x1 > x0) ? G / (x1 - x0) : 0.0;
+    t->sy = (y1 > y0) ? G / (y1 - y0) : 0.0;
+    const int64_t ncell = (int64_t)G * G;
+    // sort by cell
+    DevBuf &dk = ctx->scratch[S_KEYS], &dk2 = ctx->scratch[S_KEYS2], &dv = ctx->scratch[S_VALS];
+    if (ensure(ctx, dk, 4 * ns) || ensure(ctx, dk2, 4 * ns) || ensure(ctx, dv, 4 * ns) ||
+        ensure(ctx, t->cell_off, 4 * ((size_t)ncell + 2)))
+        return fail(SPADE_E_NOMEM);
+    if (n > 0) {
+        hipLaunchKernelGGL(k_pt_key, dim3(grid_of(n)), dim3(256), 0, st, n, pts->x, pts->y, t->X0, t->Y0, t->sx, t->sy,
+                           G, (uint32_t *)dk.p, (uint32_t *)dv.p);
+        SPADE_HIP(ctx, hipGetLastError());
+        DevBuf &cub = ctx->scratch[S_CUBTMP];
+        size_t tb = 0;
+        const int kb = std::max(1, bits_of((uint64_t)ncell));
+        SPADE_HIP(ctx, hipcub::DeviceRadixSort::SortPairs(nullptr, tb, (const uint32_t *)dk.p, (uint32_t *)dk2.p,
+                                                          (const uint32_t *)dv.p, (uint32_t *)t->ids.p, (int)n, 0, kb, st));
+        if (ensure(ctx, cub, tb)) return fail(SPADE_E_NOMEM);
+        SPADE_HIP(ctx, hipcub::DeviceRadixSort::SortPairs(cub.p, tb, (const uint32_t *)dk.p, (uint32_t *)dk2.p,
+                                                          (const uint32_t *)dv.p, (uint32_t *)t->ids.p, (int)n, 0, kb, st));
+        hipLaunchKernelGGL(k_pt_gather, dim3(grid_of(n)), dim3(256), 0, st, n, (const uint32_t *)t->ids.p, pts->x, pts->y,
+                           (double *)t->x.p, (double *)t->y.p);
+        hipLaunchKernelGGL(k_cell_off, dim3(grid_of(n + 1)), dim3(256), 0, st, n, (const uint32_t *)dk2.p, ncell,
+                           (uint32_t *)t->cell_off.p);
+        SPADE_HIP(ctx, hipGetLastError());
+        uint32_t *hf = (uint32_t *)ensure_pinned(ctx, 64);
+        SPADE_HIP(ctx, hipMemcpyAsync(hf, (uint32_t *)t->cell_off.p + ncell, 4, hipMemcpyDeviceToHost, st));
+        SPADE_HIP(ctx, hipStreamSynchronize(st));
+        t->nfin = hf[0];
+    }
+    t->nchunk = (t->nfin + CHUNK - 1) / CHUNK;
+    if (ensure(ctx, t->chunk_bb, sizeof(double4) * (size_t)std::max<int64_t>(t->nchunk, 1))) return fail(SPADE_E_NOMEM);
+    if (t->nchunk > 0) {
+        hipLaunchKernelGGL(k_chunk_bb, dim3(grid_of(t->nchunk * 64, 8192)), dim3(256), 0, st, t->nfin, t->nchunk,
+                           (const double *)t->x.p, (const double *)t->y.p, (double4 *)t->chunk_bb.p);
+        SPADE_HIP(ctx, hipGetLastError());
+    }
+    SPADE_HIP(ctx, hipStreamSynchronize(st));
+    *out = t;
+    return SPADE_OK;
+}
+
+void spade_table_destroy(spade_table *t)
+{
+    if (!t) return;
+    (void)hipSetDevice(t->device);
+    free_buf(t->x);
+    free_buf(t->y);
+    free_buf(t->ids);
+    free_buf(t->cell_off);
+    free_buf(t->chunk_bb);
+    delete t;
+}
+
+int spade_table_info(const spade_table *t, int64_t *n, int32_t *grid, int64_t *chunks, int64_t *device_bytes)
+{
+    if (!t) return SPADE_E_INVALID;
+    if (n) *n = t->n;
+    if (grid) *grid = t->G;
+    if (chunks) *chunks = t->nchunk;
+    if (device_bytes) *device_bytes = (int64_t)t->bytes();
+    return SPADE_OK;
+}
+
+int spade_batch_build(spade_ctx *ctx, const spade_polys *polys, int32_t nq, const int64_t *qbound,
+                      spade_canvas **out)
+{
+    if (!ctx || !out) return SPADE_E_INVALID;
+    *out = nullptr;
+    ctx->err.clear();
+    if (hipSetDevice(ctx->device) != hipSuccess) return set_error(ctx, SPADE_E_HIP, "hipSetDevice failed");
+    if (!polys || nq < 1 || !qbound) return set_error(ctx, SPADE_E_INVALID, "a batch needs polygons and nq >= 1 queries");
+    if (polys->n_polys < 0 || polys->n_rings < 0 || (!polys->poly_ring_off && polys->n_rings != polys->n_polys))
+        return set_error(ctx, SPADE_E_INVALID, "malformed polygon set");
+    if (polys->n_rings > 0 && (!polys->ring_vtx_off || !polys->vx || !polys->vy))
+        return set_error(ctx, SPADE_E_INVALID, "ring_vtx_off / vx / vy is NULL");
+    if (qbound[0] != 0 || qbound[nq] != polys->n_polys) return set_error(ctx, SPADE_E_INVALID, "qbound must run from 0 to n_polys");
+    for (int q = 0; q < nq; ++q)
+        if (qbound[q + 1] < qbound[q]) return set_error(ctx, SPADE_E_INVALID, "qbound must be non-decreasing");
+    spade_canvas *cv = new (std::nothrow) spade_canvas();
+    if (!cv) return set_error(ctx, SPADE_E_NOMEM, "host allocation failed");
+    cv->device = ctx->device;
+    const int rc = build_set(ctx, polys, nq, qbound, cv);
+    if (rc) {
+        spade_canvas_destroy(cv);
+        return rc;
+    }
+    *out = cv;
+    return SPADE_OK;
+}
+
+int spade_batch_select(spade_ctx *ctx, const spade_canvas *set, const spade_table *t, uint32_t *out_ids, int64_t cap,
+                       int64_t *out_off)
+{
+    if (!ctx || !set || !t || !out_off) return ctx ? set_error(ctx, SPADE_E_INVALID, "NULL argument") : SPADE_E_INVALID;
+    ctx->err.clear();
+    if (hipSetDevice(ctx->device) != hipSuccess) return set_error(ctx, SPADE_E_HIP, "hipSetDevice failed");
+    const int nq = set->nc;
+    for (int q = 0; q < nq; ++q)
+        if (set->descs[q].M != 1) return set_error(ctx, SPADE_E_INVALID, "batch selection needs exactly one polygon per query");
+    if (cap < 0 || (cap > 0 && !out_ids)) return set_error(ctx, SPADE_E_INVALID, "bad output buffer");
+    hipStream_t st = ctx->stream;
+    ctx->timed_raster = false;
+    Pairs P;
+    int rc = make_pairs(ctx, set, t, P);
+    if (rc) return rc;
+    const int64_t np = P.np;
+    DevBuf &bc = ctx->scratch[S_VALS2];
+    DevBuf &bo = ctx->scratch[S_ENTC];
+    if (ensure(ctx, bc, sizeof(uint32_t) * (size_t)(np + 1) + sizeof(unsigned long long) * (size_t)(np + 1) +
+                            sizeof(unsigned long long) * (size_t)(nq + 2) + 64))
+        return SPADE_E_NOMEM;
+    uint32_t *pcount = (uint32_t *)bc.p;
+    unsigned long long *pbase = (unsigned long long *)(((uintptr_t)(pcount + np + 1) + 7) & ~(uintptr_t)7);
+    unsigned long long *qoff = pbase + (np + 1);
+    const SetArgs S = set_args(set);
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(t->nchunk, (int64_t)num_cus_of(ctx->device) * 8));
+    hipLaunchKernelGGL(k_zero32, dim3(1), dim3(64), 0, st, (int64_t)1, (unsigned int *)(pcount + np));
+    if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[2], st));
+    if (np > 0) {
+        hipLaunchKernelGGL(k_batch_select<false>, dim3(grid), dim3(BT_THREADS), 0, st, S, t->nfin, t->nchunk,
+                           (const double *)t->x.p, (const double *)t->y.p, (const uint32_t *)t->ids.p, P.cbase,
+                           P.plist, P.pq, pcount, nullptr, nullptr);
+        SPADE_HIP(ctx, hipGetLastError());
+    }
+    DevBuf &cub = ctx->scratch[S_CUBTMP];
+    size_t tb = 0;
+    SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(nullptr, tb, pcount, pbase, (int)(np + 1), st));
+    if (ensure(ctx, cub, tb)) return SPADE_E_NOMEM;
+    SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(cub.p, tb, pcount, pbase, (int)(np + 1), st));
+    unsigned long long *h = (unsigned long long *)ensure_pinned(ctx, sizeof(unsigned long long) * (size_t)(nq + 2) + 64);
+    SPADE_HIP(ctx, hipMemcpyAsync(h, pbase + np, 8, hipMemcpyDeviceToHost, st));
+    SPADE_HIP(ctx, hipStreamSynchronize(st));
+    const unsigned long long total = h[0];
+    hipLaunchKernelGGL(k_query_off, dim3((nq + 1 + 255) / 256), dim3(256), 0, st, nq, P.qbase, pbase, np, total, qoff);
+    SPADE_HIP(ctx, hipGetLastError());
+    SPADE_HIP(ctx, hipMemcpyAsync(h, qoff, sizeof(unsigned long long) * (size_t)(nq + 1), hipMemcpyDeviceToHost, st));
+    SPADE_HIP(ctx, hipStreamSynchronize(st));
+    for (int q = 0; q <= nq; ++q) out_off[q] = (int64_t)h[q];
+    if ((int64_t)total > cap) return set_error(ctx, SPADE_E_CAPACITY, "output capacity too small");
+    if (total == 0) {
+        if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[3], st));
+        return SPADE_OK;
+    }
+    if (ensure(ctx, bo, sizeof(uint32_t) * (size_t)total)) return SPADE_E_NOMEM;
+    hipLaunchKernelGGL(k_batch_select<true>, dim3(grid), dim3(BT_THREADS), 0, st, S, t->nfin, t->nchunk,
+                       (const double *)t->x.p, (const double *)t->y.p, (const uint32_t *)t->ids.p, P.cbase, P.plist,
+                       P.pq, nullptr, (const unsigned long long *)pbase, (uint32_t *)bo.p);
+    SPADE_HIP(ctx, hipGetLastError());
+    tb = 0;
+    SPADE_HIP(ctx, hipcub::DeviceSegmentedRadixSort::SortKeys(nullptr, tb, (const uint32_t *)bo.p, out_ids, (int)total,
+                                                              nq, qoff, qoff + 1, 0, 32, st));
+    if (ensure(ctx, cub, tb)) return SPADE_E_NOMEM;
+    SPADE_HIP(ctx, hipcub::DeviceSegmentedRadixSort::SortKeys(cub.p, tb, (const uint32_t *)bo.p, out_ids, (int)total,
+                                                              nq, qoff, qoff + 1, 0, 32, st));
+    if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[3], st));
+    SPADE_HIP(ctx, hipStreamSynchronize(st));
+    return SPADE_OK;
+}
+
+int spade_batch_join_count(spade_ctx *ctx, const spade_canvas *set, const spade_table *t, uint64_t *out_counts)
+{
+    if (!ctx || !set || !t) return ctx ? set_error(ctx, SPADE_E_INVALID, "NULL argument") : SPADE_E_INVALID;
+    ctx->err.clear();
+    if (hipSetDevice(ctx->device) != hipSuccess) return set_error(ctx, SPADE_E_HIP, "hipSetDevice failed");
+    int64_t M = 0;
+    for (const auto &d : set->descs) M += d.M;
+    if (M > 0 && !out_counts) return set_error(ctx, SPADE_E_INVALID, "out_counts is NULL");
+    hipStream_t st = ctx->stream;
+    ctx->timed_raster = false;
+    Pairs P;
+    int rc = make_pairs(ctx, set, t, P);
+    if (rc) return rc;
+    if (M > 0) {
+        hipLaunchKernelGGL(k_zero64, dim3(grid_of(M, 4096)), dim3(256), 0, st, M, (unsigned long long *)out_counts);
+        SPADE_HIP(ctx, hipGetLastError());
+    }
+    const SetArgs S = set_args(set);
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(t->nchunk, (int64_t)num_cus_of(ctx->device) * 8));
+    if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[2], st));
+    if (P.np > 0) {
+        hipLaunchKernelGGL(k_batch_count<true>, dim3(grid), dim3(BT_THREADS), 0, st, S, t->nfin, t->nchunk,
+                           (const double *)t->x.p, (const double *)t->y.p, P.cbase, P.plist, P.pq,
+                           (unsigned long long *)out_counts);
+        SPADE_HIP(ctx, hipGetLastError());
+    }
+    if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[3], st));
+    SPADE_HIP(ctx, hipStreamSynchronize(st));
+    return SPADE_OK;
+}
+
+}  // extern "C"

@@ -139,6 +139,9 @@ void spade_ctx_destroy(spade_ctx *ctx)
         free_buf(ctx->plain->pspan);
         free_buf(ctx->plain->edges);
         free_buf(ctx->plain->coarse);
+        free_buf(ctx->plain->dcds);
+        free_buf(ctx->plain->desc);
+        free_buf(ctx->plain->bpix);
         delete ctx->plain;
     }
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
@@ -163,8 +166,8 @@ int spade_ctx_set_canvas_size(spade_ctx *ctx, int32_t width, int32_t height)
 {
     if (!ctx) return SPADE_E_INVALID;
     if (width == 0 && height == 0) { ctx->canvas_w = ctx->canvas_h = 0; return SPADE_OK; }
-    if (width < 1 || width > 8192 || height < 1 || height > 65535)
-        return set_error(ctx, SPADE_E_INVALID, "canvas size must be 0x0 or within 1..8192 x 1..65535");
+    if (width < 1 || width > 8192 || height < 1 || height > 16384)
+        return set_error(ctx, SPADE_E_INVALID, "canvas size must be 0x0 or within 1..8192 x 1..16384");
     ctx->canvas_w = width;
     ctx->canvas_h = height;
     return SPADE_OK;
@@ -224,6 +227,9 @@ void spade_canvas_destroy(spade_canvas *cv)
     free_buf(cv->pspan);
     free_buf(cv->edges);
     free_buf(cv->coarse);
+    free_buf(cv->dcds);
+    free_buf(cv->desc);
+    free_buf(cv->bpix);
     delete cv;
 }
 
@@ -231,9 +237,11 @@ int spade_canvas_info(const spade_canvas *cv, int32_t *width, int32_t *height, i
                       int64_t *n_boundary_pixels, int64_t *device_bytes)
 {
     if (!cv) return SPADE_E_INVALID;
+    int64_t m = 0;
+    for (const auto &d : cv->descs) m += d.M;
     if (width) *width = cv->view.W;
     if (height) *height = cv->view.H;
-    if (n_polys) *n_polys = cv->view.M;
+    if (n_polys) *n_polys = m;
     if (n_boundary_pixels) *n_boundary_pixels = cv->n_boundary;
     if (device_bytes) *device_bytes = (int64_t)cv->bytes();
     return SPADE_OK;
@@ -245,6 +253,7 @@ int spade_canvas_join_count_async(spade_ctx *ctx, const spade_canvas *cv, const 
     int rc = check_ctx(ctx);
     if (rc) return rc;
     if (!cv) return set_error(ctx, SPADE_E_INVALID, "canvas is NULL");
+    if (cv->nc != 1) return set_error(ctx, SPADE_E_INVALID, "a batch canvas set is queried with the batch calls");
     if ((rc = check_points(ctx, pts))) return rc;
     if (cv->view.M > 0 && !out_counts) return set_error(ctx, SPADE_E_INVALID, "out_counts is NULL");
     if (cv != ctx->plain) ctx->timed_raster = false;
@@ -266,6 +275,7 @@ static int emit_common(spade_ctx *ctx, const spade_canvas *cv, const spade_point
     int rc = check_ctx(ctx);
     if (rc) return rc;
     if (!cv) return set_error(ctx, SPADE_E_INVALID, "canvas is NULL");
+    if (cv->nc != 1) return set_error(ctx, SPADE_E_INVALID, "a batch canvas set is queried with the batch calls");
     if ((rc = check_points(ctx, pts))) return rc;
     if (!n_out) return set_error(ctx, SPADE_E_INVALID, "n_out is NULL");
     if (cap < 0) return set_error(ctx, SPADE_E_INVALID, "negative capacity");
@@ -277,7 +287,7 @@ static int emit_common(spade_ctx *ctx, const spade_canvas *cv, const spade_point
 int spade_canvas_select(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts,
                         uint32_t *out_ids, int64_t cap, int64_t *n_out)
 {
-    if (cv && cv->view.M != 1) return set_error(ctx, SPADE_E_INVALID, "selection needs exactly one polygon");
+    if (cv && cv->nc == 1 && cv->view.M != 1) return set_error(ctx, SPADE_E_INVALID, "selection needs exactly one polygon");
     return emit_common(ctx, cv, pts, out_ids, nullptr, cap, n_out);
 }
 

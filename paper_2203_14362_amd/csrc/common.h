@@ -39,13 +39,45 @@ struct Cand {
     uint32_t poff;   // first partial-right y-range in the span array
 };
 constexpr uint32_t CAND_S = 1u;
-// Coarse canvas word of a block whose pixels do not all share one label.
-constexpr uint16_t COARSE_MIXED = 0x8000u;
 constexpr uint32_t CAND_LAST = 2u;
+// Coarse canvas word (one per 2^blog x 2^blog block of pixels):
+//   label + 1 (0: in no polygon) when every pixel of the block carries that
+//   same non-boundary canvas word;
+//   COARSE_MIXED | m for a mixed block with compact records m;
+//   COARSE_FULL when the block must be read from the full canvas.
+// A mixed block has one 16-byte record per 32 pixels (in pixel order, pixel
+// p of a block at (p mod 2^blog, p div 2^blog)): a 2-bit code per pixel
+// (0, 1: palette word 0 or 1, 2: in no polygon, 3: boundary pixel), the
+// boundary-pixel array index of the group's first boundary pixel, and two
+// 16-bit palette canvas words.  The boundary-pixel array holds each boundary
+// pixel's first candidate record.  Blocks with more than two non-zero
+// non-boundary words, or words above 0xffff, are COARSE_FULL.
+constexpr uint16_t COARSE_MIXED = 0x8000u;
+constexpr uint16_t COARSE_FULL = 0xffffu;
+
+// Bytes of the compact records of one mixed block of 2^blog pixels a side.
+__host__ __device__ inline uint32_t desc_bytes(int blog) { return (1u << (2 * blog)) / 2u; }
 
 // Edge in world coordinates with lo.y <= hi.y.
 struct Edge {
     double xlo, ylo, xhi, yhi;
+};
+
+// One canvas of a canvas set: its world->pixel map, bounding box, size and
+// where its words live in the set's shared arrays.  A set rasterises many
+// polygon groups (one per canvas) in the same kernel launches; canvas q owns
+// polygons [poly_base, poly_base + M) and labels them 0..M-1.
+struct CanvasDesc {
+    double X0, Y0, sx, sy, hy;    // pixel u = (x - X0) * sx, v = (y - Y0) * sy; hy = 1 / sy
+    double bx0, by0, bx1, by1;    // half-open bounding box of the canvas's polygons
+    int32_t W, H, Wt, Wc, Hc, blog;
+    int32_t empty;                // no polygon area: every point is outside
+    int32_t pad;
+    int64_t poly_base, M;
+    int64_t row_base;             // first global row of the set
+    int64_t cell_off;             // first canvas word (tile-major, 16 x 16 tiles)
+    int64_t coarse_off;           // first coarse word
+    int64_t desc_off;             // first mixed-block record (in 16-byte units)
 };
 
 // Everything a probe kernel needs, passed by value.
@@ -58,6 +90,8 @@ struct CanvasView {
     int64_t M;                    // number of polygons
     const uint32_t *cells;        // canvas words, tile-major (16 x 16 tiles)
     const uint16_t *coarse;       // Wc * Hc coarse words, row-major
+    const uint4 *desc;            // mixed-block records, 2^(2 blog) / 32 per block
+    const uint32_t *bpix;         // first candidate record of each boundary pixel
     const Cand *cands;
     const Edge *ledges;           // local edges of the records
     const double2 *pspan;         // (ylo, yhi) of partial-right edges
@@ -73,13 +107,19 @@ struct DevBuf {
 
 struct spade_canvas {
     int device = 0;
-    spade::CanvasView view{};
+    int nc = 1;                               // canvases in the set
+    std::vector<spade::CanvasDesc> descs;     // host copy of the canvas descriptors
+    spade::DevBuf dcds;                       // device copy
+    spade::CanvasView view{};                 // probe view of canvas 0
     int64_t n_boundary = 0;
     int64_t n_cands = 0;
     int64_t n_elist = 0;
     int64_t n_edges = 0;
-    spade::DevBuf cells, cands, ledges, pspan, edges, coarse;
-    size_t bytes() const { return cells.cap + cands.cap + ledges.cap + pspan.cap + coarse.cap; }
+    spade::DevBuf cells, cands, ledges, pspan, edges, coarse, desc, bpix;
+    size_t bytes() const
+    {
+        return cells.cap + cands.cap + ledges.cap + pspan.cap + coarse.cap + desc.cap + bpix.cap;
+    }
 };
 
 struct spade_ctx {
@@ -87,6 +127,7 @@ struct spade_ctx {
     hipStream_t stream = nullptr;
     std::string err;
     int32_t canvas_w = 0, canvas_h = 0;     // 0 = automatic
+    double ppv = 256.0;                     // automatic sizing: pixels per vertex
     spade::DevBuf scratch[16];              // reusable scratch slots
     void *pinned = nullptr;                 // small pinned host staging area
     spade_canvas *plain = nullptr;          // canvas reused by the plain query calls
@@ -111,6 +152,9 @@ void *ensure_pinned(spade_ctx *ctx, size_t bytes);
 void free_buf(DevBuf &b);
 
 int build_canvas(spade_ctx *ctx, const spade_polys *polys, spade_canvas *cv);
+// Rasterises polygons [pbound[q], pbound[q+1]) into canvas q, q < nc.
+int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *pbound, spade_canvas *cv);
+CanvasView view_of(const spade_canvas *cv, int q);
 
 // LDS bytes the count probe leaves for the coarse canvas, given the polygon
 // count (its histogram shares the LDS).

@@ -1,0 +1,122 @@
+// Device-side canvas lookup shared by the probe kernels (single canvas and
+// canvas sets): pixel mapping, the coarse / mixed-block / full canvas
+// levels, and the exact test of one boundary-index record.
+#pragma once
+
+#include "common.h"
+#include "exact.h"
+
+namespace spade {
+
+__device__ __forceinline__ size_t tile_index(int Wt, int c, int r)
+{
+    return ((size_t)(r >> 4) * Wt + (c >> 4)) * 256 + ((r & 15) << 4) + (c & 15);
+}
+
+// Global-memory views: loads through these are known not to touch LDS, so
+// the compiler may issue them ahead of the LDS histogram updates.
+typedef const uint32_t __attribute__((address_space(1))) *gu32p;
+typedef const uint16_t __attribute__((address_space(1))) *gu16p;
+typedef const uint64_t __attribute__((address_space(1))) *gu64p;
+
+// Canvas lookup state of one point: the word once known, or where to read it.
+struct Look {
+    uint32_t word;   // final canvas word when kind == 0
+    uint32_t kind;   // 0: final, 1: mixed-block descriptor, 2: full canvas
+    uint32_t m;      // descriptor index (kind 1)
+    uint32_t pix;    // pixel within its coarse block (kind 1)
+    uint32_t fidx;   // full-canvas index (kinds 1 and 2)
+};
+
+// Level 1: bbox test, pixel mapping, coarse word from LDS.
+__device__ __forceinline__ Look look_coarse(const CanvasView &cv, const uint16_t *coarse, double x, double y)
+{
+    Look L{0u, 0u, 0u, 0u, 0u};
+    // exact half-open bbox test; NaN fails every comparison
+    if (!(cv.bx0 <= x && x < cv.bx1 && cv.by0 <= y && y < cv.by1)) return L;
+    const double u = __dmul_rn(__dsub_rn(x, cv.X0), cv.sx);
+    const double v = __dmul_rn(__dsub_rn(y, cv.Y0), cv.sy);
+    const int c = min((int)u, cv.W - 1);
+    const int r = min((int)v, cv.H - 1);
+    const uint16_t cw = coarse[(r >> cv.blog) * cv.Wc + (c >> cv.blog)];
+    if (!(cw & COARSE_MIXED)) { L.word = cw; return L; }
+    L.fidx = (uint32_t)tile_index(cv.Wt, c, r);
+    if (cw == COARSE_FULL) { L.kind = 2; return L; }
+    L.kind = 1;
+    L.m = cw & 0x7fffu;
+    const int B = 1 << cv.blog;
+    L.pix = (uint32_t)(((r & (B - 1)) << cv.blog) | (c & (B - 1)));
+    return L;
+}
+
+// The compact record of the 32-pixel group holding a mixed-block pixel.
+__device__ __forceinline__ uint4 read_group(const CanvasView &cv, const Look &L)
+{
+    const uint32_t G = 1u << (2 * cv.blog - 5);
+    const gu32p q = (gu32p)(cv.desc + (size_t)L.m * G + (L.pix >> 5));
+    return make_uint4(q[0], q[1], q[2], q[3]);
+}
+
+// Level 2: resolve a group record.  Returns true with the final word, or
+// false with `bidx`, the boundary-pixel array index of the pixel.
+__device__ __forceinline__ bool resolve_group(const uint4 &R, Look &L, uint32_t &bidx)
+{
+    const uint64_t codes = (uint64_t)R.x | ((uint64_t)R.y << 32);
+    const uint32_t sh = 2u * (L.pix & 31u);
+    const uint32_t code = (uint32_t)(codes >> sh) & 3u;
+    if (code < 3u) {
+        L.word = code == 0u ? (R.w & 0xffffu) : (code == 1u ? (R.w >> 16) : 0u);
+        L.kind = 0;
+        return true;
+    }
+    const uint64_t both = codes & (codes >> 1) & 0x5555555555555555ull;
+    const uint64_t below = sh ? (both & ((1ull << sh) - 1ull)) : 0ull;
+    bidx = R.z + (uint32_t)__popcll(below);
+    return false;
+}
+
+// Canvas word of (x, y): 0, label + 1, or BFLAG | first candidate record.
+__device__ __forceinline__ uint32_t lookup(const CanvasView &cv, const uint16_t *coarse, double x, double y)
+{
+    Look L = look_coarse(cv, coarse, x, y);
+    if (L.kind == 0) return L.word;
+    if (L.kind == 1) {
+        uint32_t bidx = 0;
+        if (resolve_group(read_group(cv, L), L, bidx)) return L.word;
+        return BFLAG | ((gu32p)cv.bpix)[bidx];
+    }
+    return ((gu32p)cv.cells)[L.fidx];
+}
+
+__device__ __forceinline__ bool cand_inside(const CanvasView &cv, const Cand &cd, double x, double y)
+{
+    bool in = (cd.meta & CAND_S) != 0;
+    const uint32_t nloc = (cd.meta >> 2) & 0x7fffu;
+    const uint32_t npart = cd.meta >> 17;
+    const Edge *le = cv.ledges + cd.eoff;
+    for (uint32_t t = 0; t < nloc; ++t) {
+        const Edge e = le[t];
+        in ^= crosses(e.xlo, e.ylo, e.xhi, e.yhi, x, y);
+    }
+    const double2 *ps = cv.pspan + cd.poff;
+    for (uint32_t t = 0; t < npart; ++t) {
+        const double2 s = ps[t];
+        in ^= straddles(s.x, s.y, y);
+    }
+    return in;
+}
+
+// Cooperative copy of the coarse canvas into LDS.
+__device__ __forceinline__ void load_coarse(const CanvasView &cv, uint16_t *dst, int nthreads)
+{
+    const int n = cv.Wc * cv.Hc;
+    const int n2 = n >> 1;
+    const uint32_t *src2 = (const uint32_t *)cv.coarse;
+    uint32_t *dst2 = (uint32_t *)dst;
+    for (int i = threadIdx.x; i < n2; i += nthreads) dst2[i] = src2[i];
+    if ((n & 1) && threadIdx.x == 0) dst[n - 1] = cv.coarse[n - 1];
+}
+
+__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63; }
+
+}  // namespace spade

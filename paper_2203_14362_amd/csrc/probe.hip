@@ -22,6 +22,7 @@
 //            claimed in order.
 #include "common.h"
 #include "exact.h"
+#include "lookup.h"
 
 #include <algorithm>
 
@@ -44,56 +45,6 @@ size_t coarse_lds_budget(int64_t M)
     size_t used = LDS_RESERVE + QUEUE_BYTES + hist;
     return used < LDS_TOTAL ? LDS_TOTAL - used : 0;
 }
-
-__device__ __forceinline__ size_t tile_index(int Wt, int c, int r)
-{
-    return ((size_t)(r >> 4) * Wt + (c >> 4)) * 256 + ((r & 15) << 4) + (c & 15);
-}
-
-// Canvas word of (x, y): 0, label + 1, or BFLAG | first candidate record.
-__device__ __forceinline__ uint32_t lookup(const CanvasView &cv, const uint16_t *coarse, double x, double y)
-{
-    // exact half-open bbox test; NaN fails every comparison
-    if (!(cv.bx0 <= x && x < cv.bx1 && cv.by0 <= y && y < cv.by1)) return 0u;
-    const double u = __dmul_rn(__dsub_rn(x, cv.X0), cv.sx);
-    const double v = __dmul_rn(__dsub_rn(y, cv.Y0), cv.sy);
-    const int c = min((int)u, cv.W - 1);
-    const int r = min((int)v, cv.H - 1);
-    const uint16_t cw = coarse[(r >> cv.blog) * cv.Wc + (c >> cv.blog)];
-    if (cw != COARSE_MIXED) return cw;
-    return cv.cells[tile_index(cv.Wt, c, r)];
-}
-
-__device__ __forceinline__ bool cand_inside(const CanvasView &cv, const Cand &cd, double x, double y)
-{
-    bool in = (cd.meta & CAND_S) != 0;
-    const uint32_t nloc = (cd.meta >> 2) & 0x7fffu;
-    const uint32_t npart = cd.meta >> 17;
-    const Edge *le = cv.ledges + cd.eoff;
-    for (uint32_t t = 0; t < nloc; ++t) {
-        const Edge e = le[t];
-        in ^= crosses(e.xlo, e.ylo, e.xhi, e.yhi, x, y);
-    }
-    const double2 *ps = cv.pspan + cd.poff;
-    for (uint32_t t = 0; t < npart; ++t) {
-        const double2 s = ps[t];
-        in ^= straddles(s.x, s.y, y);
-    }
-    return in;
-}
-
-// Cooperative copy of the coarse canvas into LDS.
-__device__ __forceinline__ void load_coarse(const CanvasView &cv, uint16_t *dst, int nthreads)
-{
-    const int n = cv.Wc * cv.Hc;
-    const int n2 = n >> 1;
-    const uint32_t *src2 = (const uint32_t *)cv.coarse;
-    uint32_t *dst2 = (uint32_t *)dst;
-    for (int i = threadIdx.x; i < n2; i += nthreads) dst2[i] = src2[i];
-    if ((n & 1) && threadIdx.x == 0) dst[n - 1] = cv.coarse[n - 1];
-}
-
-__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63; }
 
 // ------------------------------------------------------------ join-count
 
@@ -165,9 +116,30 @@ __global__ __launch_bounds__(CNT_THREADS) void k_count(CanvasView cv, int64_t n,
 #pragma unroll
         for (int u = 0; u < CNT_UNROLL; ++u) { xs[u] = xn[u]; ys[u] = yn[u]; }
         if (base + step < n) fetch(base + step);
+        // the canvas reads of this iteration are issued level by level, all
+        // points of a level before any result is used
+        Look lk[CNT_UNROLL];
+        uint4 dr[CNT_UNROLL];
+        uint32_t ws[CNT_UNROLL], bidx[CNT_UNROLL];
+#pragma unroll
+        for (int u = 0; u < CNT_UNROLL; ++u) lk[u] = look_coarse(cv, coarse, xs[u], ys[u]);
+#pragma unroll
+        for (int u = 0; u < CNT_UNROLL; ++u)
+            if (lk[u].kind == 1) dr[u] = read_group(cv, lk[u]);
 #pragma unroll
         for (int u = 0; u < CNT_UNROLL; ++u) {
-            const uint32_t w = lookup(cv, coarse, xs[u], ys[u]);
+            bidx[u] = 0;
+            if (lk[u].kind == 1) resolve_group(dr[u], lk[u], bidx[u]);
+            ws[u] = lk[u].word;
+        }
+#pragma unroll
+        for (int u = 0; u < CNT_UNROLL; ++u) {
+            if (lk[u].kind == 1) ws[u] = BFLAG | ((gu32p)cv.bpix)[bidx[u]];
+            else if (lk[u].kind == 2) ws[u] = ((gu32p)cv.cells)[lk[u].fidx];
+        }
+#pragma unroll
+        for (int u = 0; u < CNT_UNROLL; ++u) {
+            const uint32_t w = ws[u];
             const bool bnd = (w & BFLAG) != 0;
             if (w != 0u && !bnd) add(w - 1u);
             const unsigned long long mask = __ballot(bnd);

@@ -47,10 +47,34 @@ constexpr uint8_t F_SPAN = 1;    // edge spans the whole dilated row band
 constexpr uint8_t F_W = 2;       // edge straddles the row-centre line
 constexpr uint8_t F_HORIZ = 4;   // horizontal edge (never crosses)
 
-struct Map {
-    double X0, Y0, sx, sy, hy;
-    int32_t W, H;
-};
+// Canvas of polygon k: canvases own contiguous polygon ranges.
+__device__ __forceinline__ int canvas_of_poly(const CanvasDesc *cds, int nc, int64_t k)
+{
+    int lo = 0, hi = nc - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (cds[mid].poly_base <= k) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Canvas holding global row r (rows of all canvases are concatenated).
+__device__ __forceinline__ int canvas_of_row(const CanvasDesc *cds, int nc, int64_t r)
+{
+    int lo = 0, hi = nc - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (cds[mid].row_base <= r) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Order-preserving map of a double to an unsigned integer (for atomic min/max).
+__device__ __forceinline__ unsigned long long dkey(double v)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    return (b & 0x8000000000000000ull) ? ~b : (b | 0x8000000000000000ull);
+}
 
 // ------------------------------------------------------------ validation
 
@@ -59,6 +83,7 @@ __global__ __launch_bounds__(256) void k_validate(int64_t M, int64_t R, const in
                                                   const double *vy, int32_t *ring_poly,
                                                   double *blockred, unsigned *errflags)
 {
+    // (per-canvas boxes are computed by k_canvas_bbox once ring_poly is known)
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nth = (int64_t)gridDim.x * blockDim.x;
     for (int64_t k = tid; k < M; k += nth) {
@@ -93,12 +118,77 @@ __global__ __launch_bounds__(256) void k_validate(int64_t M, int64_t R, const in
         for (int q = 0; q < 4; ++q) blockred[blockIdx.x * 4 + q] = s[q][0];
 }
 
+// Per-canvas bounding boxes: bb[4 q + 0..3] = keys of min x, -max x, min y,
+// -max y over the vertices of canvas q's polygons (ordered-key atomics).
+// Each thread reduces a run of BB_SPAN consecutive vertices, flushing when
+// the canvas changes; a wave whose runs all end in one canvas merges them
+// before its atomics, so one canvas of many vertices costs few atomics.
+constexpr int BB_SPAN = 32;
+
+__device__ __forceinline__ void bb_flush(unsigned long long *bb, int q, const unsigned long long k[4])
+{
+    atomicMin(&bb[4 * q + 0], k[0]);
+    atomicMin(&bb[4 * q + 1], k[1]);
+    atomicMin(&bb[4 * q + 2], k[2]);
+    atomicMin(&bb[4 * q + 3], k[3]);
+}
+
+__global__ __launch_bounds__(256) void k_canvas_bbox(int64_t R, const int64_t *rvo, int64_t V,
+                                                     const double *vx, const double *vy,
+                                                     const int32_t *ring_poly, const CanvasDesc *cds,
+                                                     int nc, unsigned long long *bb)
+{
+    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    const int64_t nspan = (V + BB_SPAN - 1) / BB_SPAN;
+    // every lane runs the same number of iterations (the wave merge below)
+    const int64_t iters = (nspan + nth - 1) / nth;
+    for (int64_t it = 0; it < iters; ++it) {
+        const int64_t sp = it * nth + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        int q = -1;
+        unsigned long long k[4] = {~0ull, ~0ull, ~0ull, ~0ull};
+        if (sp < nspan) {
+            const int64_t j0 = sp * BB_SPAN, j1 = min(V, j0 + BB_SPAN);
+            int64_t lo = 0, hi = R;
+            while (hi - lo > 1) {
+                const int64_t mid = (lo + hi) >> 1;
+                if (rvo[mid] <= j0) lo = mid; else hi = mid;
+            }
+            int64_t r = lo;
+            q = canvas_of_poly(cds, nc, ring_poly[r]);
+            for (int64_t j = j0; j < j1; ++j) {
+                if (j >= rvo[r + 1]) {
+                    while (j >= rvo[r + 1]) ++r;
+                    const int qn = canvas_of_poly(cds, nc, ring_poly[r]);
+                    if (qn != q) {
+                        bb_flush(bb, q, k);
+                        k[0] = k[1] = k[2] = k[3] = ~0ull;
+                        q = qn;
+                    }
+                }
+                const double x = vx[j], y = vy[j];
+                k[0] = min(k[0], dkey(x)); k[1] = min(k[1], dkey(-x));
+                k[2] = min(k[2], dkey(y)); k[3] = min(k[3], dkey(-y));
+            }
+        }
+        const int q0 = __shfl(q, 0, 64);
+        if (__all(q == q0 || q == -1) && q0 != -1) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                for (int d = 32; d > 0; d >>= 1) k[t] = min(k[t], (unsigned long long)__shfl_xor(k[t], d, 64));
+            if ((threadIdx.x & 63) == 0) bb_flush(bb, q0, k);
+        } else if (q != -1) {
+            bb_flush(bb, q, k);
+        }
+    }
+}
+
 // ------------------------------------------------------------ edges
 
 __global__ __launch_bounds__(256) void k_edges(int64_t R, const int64_t *rvo, int64_t V,
                                                const double *vx, const double *vy,
-                                               const int32_t *ring_poly, Map m, Edge *edges,
-                                               uint32_t *epoly, int32_t *erow0, uint64_t *nrows)
+                                               const int32_t *ring_poly, const CanvasDesc *cds, int nc,
+                                               Edge *edges, uint32_t *epoly, int32_t *erow0,
+                                               uint64_t *nrows)
 {
     const int64_t nth = (int64_t)gridDim.x * blockDim.x;
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < V; j += nth) {
@@ -112,11 +202,12 @@ __global__ __launch_bounds__(256) void k_edges(int64_t R, const int64_t *rvo, in
         const int64_t nx = (j + 1 < rvo[r + 1]) ? j + 1 : rvo[r];
         double ax = vx[j], ay = vy[j], bx = vx[nx], by = vy[nx];
         epoly[j] = (uint32_t)ring_poly[r];
+        const CanvasDesc &m = cds[canvas_of_poly(cds, nc, ring_poly[r])];
         Edge e;
         if (ay <= by) { e.xlo = ax; e.ylo = ay; e.xhi = bx; e.yhi = by; }
         else          { e.xlo = bx; e.ylo = by; e.xhi = ax; e.yhi = ay; }
         edges[j] = e;
-        if (ax == bx && ay == by) { nrows[j] = 0; erow0[j] = 0; continue; }   // zero length
+        if ((ax == bx && ay == by) || m.empty) { nrows[j] = 0; erow0[j] = 0; continue; }   // zero length
         double vlo = __dmul_rn(__dsub_rn(e.ylo, m.Y0), m.sy);
         double vhi = __dmul_rn(__dsub_rn(e.yhi, m.Y0), m.sy);
         double f0 = floor(vlo - MARGIN), f1 = floor(vhi + MARGIN);
@@ -131,9 +222,10 @@ __global__ __launch_bounds__(256) void k_edges(int64_t R, const int64_t *rvo, in
 
 __global__ __launch_bounds__(256) void k_entries(int64_t V, const Edge *edges, const uint32_t *epoly,
                                                  const int32_t *erow0, const uint64_t *nrows,
-                                                 const uint64_t *off, Map m, int cbits, int pbits,
+                                                 const uint64_t *off, const CanvasDesc *cds, int nc,
+                                                 int cbits, int pbits,
                                                  uint64_t *keys, uint32_t *vals, uint32_t *ent_c,
-                                                 uint8_t *ent_f)
+                                                 uint8_t *ent_f, unsigned long long *sumw)
 {
     const int64_t nth = (int64_t)gridDim.x * blockDim.x;
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < V; j += nth) {
@@ -141,12 +233,14 @@ __global__ __launch_bounds__(256) void k_entries(int64_t V, const Edge *edges, c
         if (nr == 0) continue;
         const Edge e = edges[j];
         const bool horiz = (e.ylo == e.yhi);
+        const CanvasDesc &m = cds[canvas_of_poly(cds, nc, epoly[j])];
         const double ulo = __dmul_rn(__dsub_rn(e.xlo, m.X0), m.sx);
         const double uhi = __dmul_rn(__dsub_rn(e.xhi, m.X0), m.sx);
         const double vlo = __dmul_rn(__dsub_rn(e.ylo, m.Y0), m.sy);
         const double vhi = __dmul_rn(__dsub_rn(e.yhi, m.Y0), m.sy);
-        const uint64_t poly = epoly[j];
+        const uint64_t poly = (uint64_t)((int64_t)epoly[j] - m.poly_base);
         const uint64_t base = off[j];
+        unsigned long long wsum = 0;
         for (uint64_t t = 0; t < nr; ++t) {
             const int32_t r = erow0[j] + (int32_t)t;
             const double b0 = (double)r - MARGIN, b1 = (double)r + 1.0 + MARGIN;
@@ -167,11 +261,13 @@ __global__ __launch_bounds__(256) void k_entries(int64_t V, const Edge *edges, c
             const double yc = m.Y0 + ((double)r + 0.5) * m.hy;
             const bool w = !horiz && straddles(e.ylo, e.yhi, yc);
             const uint64_t idx = base + t;
-            keys[idx] = ((uint64_t)r << (pbits + cbits)) | (poly << cbits) | (uint64_t)c0;
+            keys[idx] = ((uint64_t)(m.row_base + r) << (pbits + cbits)) | (poly << cbits) | (uint64_t)c0;
             vals[idx] = (uint32_t)j;
             ent_c[idx] = (uint32_t)c0 | ((uint32_t)c1 << 16);
             ent_f[idx] = (span ? F_SPAN : 0) | (w ? F_W : 0) | (horiz ? F_HORIZ : 0);
+            wsum += (unsigned long long)(c1 - c0 + 1);
         }
+        atomicAdd(sumw, wsum);
     }
 }
 
@@ -202,7 +298,7 @@ __global__ void k_iota(int64_t T, uint32_t *v)
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < T; i += nth) v[i] = (uint32_t)i;
 }
 
-__global__ void k_row_off(int64_t T, const uint64_t *skeys, int shift, int32_t H, uint32_t *row_off)
+__global__ void k_row_off(int64_t T, const uint64_t *skeys, int shift, int64_t H, uint32_t *row_off)
 {
     const int64_t nth = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= T; i += nth) {
@@ -248,8 +344,10 @@ __device__ void block_scan(T *a, int n, T *wtot, Op op, T ident)
 }
 
 struct RowArgs {
-    Map m;
-    int Wt;                  // canvas tiles per row (tile = 16 x 16 pixels)
+    const CanvasDesc *cds;   // canvases of the set
+    int nc;
+    int maxW;                // widest canvas (LDS column arrays)
+    int64_t Htot;            // rows of all canvases
     int cap;                 // entries of one row staged in LDS
     const uint32_t *row_off;
     const uint32_t *spoly;   // polygon per sorted entry
@@ -257,7 +355,13 @@ struct RowArgs {
     const uint32_t *sc;      // c0 | c1 << 16
     const uint8_t *sf;
     const Edge *edges;
-    uint32_t *gaux;          // 5 words per entry for rows too long to stage
+    uint32_t *gaux;          // 6 words per entry for rows too long to stage
+    int min_n;               // this launch handles rows with min_n <= entries (<= max_n)
+    int max_n;
+    // single-pass allocation: per-row output ranges reserved with atomics
+    int alloc;
+    unsigned long long *gctr;    // [0] records, [1] local edges, [2] partial spans, [3] boundary pixels
+    unsigned long long cap_rec, cap_loc, cap_part;
     // count pass
     uint64_t *row_nrec, *row_nloc, *row_npart, *row_nbp;
     // emit pass
@@ -280,9 +384,10 @@ struct RowData {
                       // entries, high 16 bits non-horizontal entries (0: none)
     uint32_t *pre;    // inclusive row prefix: partial count (bits 0..30, sum) and
                       // spanning parity (bit 31, xor)
-    uint32_t *rhead;  // run list: first entry, end, inclusive prefix of column spans
-    uint32_t *rend;
-    uint32_t *rspan;
+    uint32_t *ihead;  // footprint-union intervals of the runs: run start, run end,
+    uint32_t *iend;   // first column, inclusive prefix of interval lengths
+    uint32_t *icol;
+    uint32_t *ilen;
     int n;
 };
 
@@ -292,7 +397,7 @@ struct RowShared {
     int32_t *sb;        // claim counts -> per-column fill counters
     uint32_t *sx;       // claimant xor -> pixel class
     uint32_t *locfill;  // row-local fill counter of the local-edge array
-    uint32_t *nruns;
+    uint32_t *nint;     // number of footprint-union intervals of the row
 };
 
 __device__ __forceinline__ size_t tile_index(int Wt, int c, int r)
@@ -371,9 +476,8 @@ __device__ __forceinline__ void column_record(const RowArgs &A, const RowData &D
 // column inside the run's interior spans gets (S = 1, no edges).
 template <bool EMIT>
 __device__ void claimant_walk(const RowArgs &A, const RowData &D, const RowShared &L, int i, int je,
-                              uint64_t rec_base_r)
+                              uint64_t rec_base_r, int W)
 {
-    const int W = A.m.W;
     uint32_t par = 0;
     for (int q = i; q < je; ++q) par ^= (D.f[q] & F_W) ? 1u : 0u;
     auto emit = [&](int col) {
@@ -443,41 +547,42 @@ __device__ void block_plain_scan(uint32_t *a, int n, uint32_t *wtot, Op op)
     __syncthreads();
 }
 
-// Runs every (run, column) item of the row through column_record.
+// Runs every (run, footprint column) item of the row through column_record.
 template <bool EMIT>
 __device__ void all_column_records(const RowArgs &A, const RowData &D, const RowShared &L,
                                    uint64_t rec_base_r, uint64_t loc_base_r, uint64_t part_base_r,
                                    uint64_t &nloc_tot)
 {
-    const int nr = (int)*L.nruns;
-    if (nr == 0) return;
-    const uint32_t total = D.rspan[nr - 1];
+    const int ni = (int)*L.nint;
+    if (ni == 0) return;
+    const uint32_t total = D.ilen[ni - 1];
     for (uint32_t t = threadIdx.x; t < total; t += ROW_THREADS) {
-        int lo = 0, hi = nr - 1;            // first run with rspan > t
+        int lo = 0, hi = ni - 1;            // first interval with prefix > t
         while (lo < hi) {
             const int mid = (lo + hi) >> 1;
-            if (D.rspan[mid] > t) hi = mid; else lo = mid + 1;
+            if (D.ilen[mid] > t) hi = mid; else lo = mid + 1;
         }
-        const int i = (int)D.rhead[lo], je = (int)D.rend[lo];
-        const uint32_t before = lo ? D.rspan[lo - 1] : 0u;
-        const int col = (int)(D.c[i] & 0xffff) + (int)(t - before);
-        column_record<EMIT>(A, D, L, i, je, col, rec_base_r, loc_base_r, part_base_r, nloc_tot);
+        const uint32_t before = lo ? D.ilen[lo - 1] : 0u;
+        const int col = (int)D.icol[lo] + (int)(t - before);
+        column_record<EMIT>(A, D, L, (int)D.ihead[lo], (int)D.iend[lo], col, rec_base_r, loc_base_r,
+                            part_base_r, nloc_tot);
     }
 }
 
 // Dynamic LDS: three padded column arrays, then `cap` staged entries with
-// their auxiliary words, then the run list (at most cap / 2 runs).
+// their auxiliary words and up to `cap` footprint intervals.
 __host__ __device__ inline size_t row_lds_bytes(int W, int cap)
 {
-    return (size_t)3 * col_words(W) * 4 + (size_t)cap * 21 + (size_t)(cap / 2 + 1) * 12 + 32;
+    return (size_t)3 * col_words(W) * 4 + (size_t)cap * 37 + 32;
 }
 
 template <bool EMIT>
-__device__ void process_row(const RowArgs &A, const RowData &D, const RowShared &L, int r,
+__device__ void process_row(const RowArgs &A, const RowData &D, const RowShared &L, int64_t r, int W,
+                            int Wt, uint32_t *cells_q, int r_local,
                             int32_t *wtoti, uint32_t *wtotu, uint32_t *s_nbp, uint32_t *s_multi,
-                            unsigned long long *s_nloc, unsigned long long *s_nrec)
+                            unsigned long long *s_nloc, unsigned long long *s_nrec,
+                            unsigned long long *s_base)
 {
-    const int W = A.m.W;
     const int tid = threadIdx.x;
 
     // phase 1: per run, footprints (boundary counts), interior claims, the
@@ -514,10 +619,18 @@ __device__ void process_row(const RowArgs &A, const RowData &D, const RowShared 
                 atomicXor(&L.sx[cix(lo)], lab); atomicXor(&L.sx[cix(hi + 1)], lab);
             }
         }
-        const uint32_t j = atomicAdd(L.nruns, 1u);
-        D.rhead[j] = (uint32_t)i;
-        D.rend[j] = (uint32_t)je;
-        D.rspan[j] = (uint32_t)((int)mall - c0first);   // columns c0first .. max c1
+        // footprint-union intervals of the run
+        int ulo = c0first, uhi = (int)(D.c[i] >> 16);
+        for (int q = i + 1; q <= je; ++q) {
+            const int c0 = q < je ? (int)(D.c[q] & 0xffff) : W + 1;
+            if (q < je && c0 <= uhi + 1) { uhi = max(uhi, (int)(D.c[q] >> 16)); continue; }
+            const uint32_t j = atomicAdd(L.nint, 1u);
+            D.ihead[j] = (uint32_t)i;
+            D.iend[j] = (uint32_t)je;
+            D.icol[j] = (uint32_t)ulo;
+            D.ilen[j] = (uint32_t)(uhi - ulo + 1);
+            if (q < je) { ulo = c0; uhi = (int)(D.c[q] >> 16); }
+        }
     });
     __syncthreads();
 
@@ -527,7 +640,7 @@ __device__ void process_row(const RowArgs &A, const RowData &D, const RowShared 
     block_scan(L.sb, W, wtoti, [](int32_t a, int32_t b) { return a + b; }, 0);
     block_scan(L.sx, W, wtotu, [](uint32_t a, uint32_t b) { return a ^ b; }, 0u);
     block_plain_scan(D.pre, D.n, wtotu, [](uint32_t a, uint32_t b) { return pre_op(a, b); });
-    block_plain_scan(D.rspan, (int)*L.nruns, wtotu, [](uint32_t a, uint32_t b) { return a + b; });
+    block_plain_scan(D.ilen, (int)*L.nint, wtotu, [](uint32_t a, uint32_t b) { return a + b; });
 
     // phase 3: classify pixels.  sx := 0 (no polygon), label + 1, or for a
     // boundary pixel BFLAG | (label + 1 of its single interior claimant, or 0);
@@ -556,19 +669,38 @@ __device__ void process_row(const RowArgs &A, const RowData &D, const RowShared 
     // phase 4: count records per column (and local-edge totals)
     uint64_t nloc = 0;
     all_column_records<false>(A, D, L, 0, 0, 0, nloc);
-    if (rmulti) for_each_run(D, [&](int i, int je) { claimant_walk<false>(A, D, L, i, je, 0); });
+    if (rmulti) for_each_run(D, [&](int i, int je) { claimant_walk<false>(A, D, L, i, je, 0, W); });
     atomicAdd(s_nloc, (unsigned long long)nloc);
     __syncthreads();
 
-    if (!EMIT) {
+    {
         uint32_t nrec = 0;
         for (int c = tid; c < W; c += ROW_THREADS) nrec += (uint32_t)L.sa[cix(c)];
         atomicAdd(s_nrec, (unsigned long long)nrec);
         __syncthreads();
+    }
+    const uint32_t npart_r = D.n ? (D.pre[D.n - 1] & 0x7fffffffu) : 0u;
+    if (EMIT && A.alloc) {
+        // reserve this row's output ranges; an overflow abandons the row and
+        // the host redoes the canvas with exact sizes
+        if (tid == 0) {
+            s_base[0] = atomicAdd(&A.gctr[0], *s_nrec);
+            s_base[1] = atomicAdd(&A.gctr[1], *s_nloc);
+            s_base[2] = atomicAdd(&A.gctr[2], (unsigned long long)npart_r);
+            atomicAdd(&A.gctr[3], (unsigned long long)*s_nbp);
+            const bool over = s_base[0] + *s_nrec > A.cap_rec || s_base[1] + *s_nloc > A.cap_loc ||
+                              s_base[2] + npart_r > A.cap_part || s_base[0] + *s_nrec >= (unsigned long long)BFLAG;
+            if (over) atomicOr(A.errflags, 32u);
+            s_base[3] = over ? 1ull : 0ull;
+        }
+        __syncthreads();
+        if (s_base[3]) return;
+    }
+    if (!EMIT) {
         if (tid == 0) {
             A.row_nrec[r] = *s_nrec;
             A.row_nloc[r] = *s_nloc;
-            A.row_npart[r] = D.n ? (D.pre[D.n - 1] & 0x7fffffffu) : 0u;
+            A.row_npart[r] = npart_r;
             A.row_nbp[r] = *s_nbp;
         }
         return;
@@ -587,11 +719,13 @@ __device__ void process_row(const RowArgs &A, const RowData &D, const RowShared 
     }
 
     // phase 5: records, local edges, partial spans (in row entry order)
-    const uint64_t rec_base_r = A.rec_base[r], loc_base_r = A.loc_base[r], part_base_r = A.part_base[r];
+    const uint64_t rec_base_r = A.alloc ? s_base[0] : A.rec_base[r];
+    const uint64_t loc_base_r = A.alloc ? s_base[1] : A.loc_base[r];
+    const uint64_t part_base_r = A.alloc ? s_base[2] : A.part_base[r];
     {
         uint64_t dummy = 0;
         all_column_records<true>(A, D, L, rec_base_r, loc_base_r, part_base_r, dummy);
-        if (rmulti) for_each_run(D, [&](int i, int je) { claimant_walk<true>(A, D, L, i, je, rec_base_r); });
+        if (rmulti) for_each_run(D, [&](int i, int je) { claimant_walk<true>(A, D, L, i, je, rec_base_r, W); });
         else
             for (int c = tid; c < W; c += ROW_THREADS) {
                 const uint32_t w = L.sx[cix(c)];
@@ -633,7 +767,7 @@ __device__ void process_row(const RowArgs &A, const RowData &D, const RowShared 
                 word = BFLAG | (uint32_t)base;
             }
         }
-        A.cells[tile_index(A.Wt, c, r)] = word;
+        cells_q[tile_index(Wt, c, r_local)] = word;
     }
 }
 
@@ -643,30 +777,37 @@ __global__ __launch_bounds__(ROW_THREADS) void k_rows(RowArgs A)
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int32_t wtoti[ROW_THREADS / 64];
     __shared__ uint32_t wtotu[ROW_THREADS / 64];
-    __shared__ uint32_t s_locfill, s_nruns, s_nbp, s_multi;
-    __shared__ unsigned long long s_nloc, s_nrec;
-    const int W = A.m.W, H = A.m.H, cap = A.cap;
-    const int cw = col_words(W);
+    __shared__ uint32_t s_locfill, s_nint, s_nbp, s_multi;
+    __shared__ unsigned long long s_nloc, s_nrec, s_base[4];
+    const int cap = A.cap;
+    const int cwmax = col_words(A.maxW);
     RowShared L;
     L.sa = (int32_t *)smem;
-    L.sb = L.sa + cw;
-    L.sx = (uint32_t *)(L.sb + cw);
+    L.sb = L.sa + cwmax;
+    L.sx = (uint32_t *)(L.sb + cwmax);
     L.locfill = &s_locfill;
-    L.nruns = &s_nruns;
-    uint32_t *lpoly = L.sx + cw;
+    L.nint = &s_nint;
+    uint32_t *lpoly = L.sx + cwmax;
     uint32_t *lc = lpoly + cap;
     uint32_t *ledge = lc + cap;
     uint32_t *lpm = ledge + cap;
     uint32_t *lpre = lpm + cap;
-    uint32_t *lrh = lpre + cap;
-    uint32_t *lre = lrh + (cap / 2 + 1);
-    uint32_t *lrs = lre + (cap / 2 + 1);
-    uint8_t *lf = (uint8_t *)(lrs + (cap / 2 + 1));
+    uint32_t *lih = lpre + cap;
+    uint32_t *lie = lih + cap;
+    uint32_t *lic = lie + cap;
+    uint32_t *lil = lic + cap;
+    uint8_t *lf = (uint8_t *)(lil + cap);
     const int tid = threadIdx.x;
 
-    for (int r = blockIdx.x; r < H; r += gridDim.x) {
+    for (int64_t r = blockIdx.x; r < A.Htot; r += gridDim.x) {
         const int s = (int)A.row_off[r], e = (int)A.row_off[r + 1];
         const int n = e - s;
+        if (n < A.min_n || n > A.max_n) continue;
+        const CanvasDesc &cd = A.cds[canvas_of_row(A.cds, A.nc, r)];
+        const int W = cd.W, Wt = cd.Wt;
+        uint32_t *cells_q = A.cells + cd.cell_off;
+        const int r_local = (int)(r - cd.row_base);
+        const int cw = col_words(W);
         if (n <= cap) {
             for (int q = tid; q < n; q += ROW_THREADS) {
                 lpoly[q] = A.spoly[s + q];
@@ -676,45 +817,171 @@ __global__ __launch_bounds__(ROW_THREADS) void k_rows(RowArgs A)
             }
         }
         for (int c = tid; c < cw; c += ROW_THREADS) { L.sa[c] = 0; L.sb[c] = 0; L.sx[c] = 0; }
-        if (tid == 0) { s_locfill = 0; s_nruns = 0; s_nbp = 0; s_multi = 0; s_nloc = 0; s_nrec = 0; }
+        if (tid == 0) { s_locfill = 0; s_nint = 0; s_nbp = 0; s_multi = 0; s_nloc = 0; s_nrec = 0; }
         __syncthreads();
         if (n <= cap) {
-            const RowData D{lpoly, lc, lf, ledge, lpm, lpre, lrh, lre, lrs, n};
-            process_row<EMIT>(A, D, L, r, wtoti, wtotu, &s_nbp, &s_multi, &s_nloc, &s_nrec);
+            const RowData D{lpoly, lc, lf, ledge, lpm, lpre, lih, lie, lic, lil, n};
+            process_row<EMIT>(A, D, L, r, W, Wt, cells_q, r_local, wtoti, wtotu, &s_nbp, &s_multi, &s_nloc,
+                              &s_nrec, s_base);
         } else {
-            uint32_t *g = A.gaux + (size_t)5 * s;
+            uint32_t *g = A.gaux + (size_t)6 * s;
             const RowData D{A.spoly + s, A.sc + s, A.sf + s, A.sedge + s, g, g + n, g + 2 * n, g + 3 * n,
-                            g + 4 * n, n};
-            process_row<EMIT>(A, D, L, r, wtoti, wtotu, &s_nbp, &s_multi, &s_nloc, &s_nrec);
+                            g + 4 * n, g + 5 * n, n};
+            process_row<EMIT>(A, D, L, r, W, Wt, cells_q, r_local, wtoti, wtotu, &s_nbp, &s_multi, &s_nloc,
+                              &s_nrec, s_base);
         }
         __syncthreads();
     }
 }
 
-// Coarse canvas: one 16-bit word per B x B block of pixels (B = 2^blog >= 16),
-// holding the block's common label + 1 (0: in no polygon) when every pixel
-// of the block carries that same non-boundary value, else COARSE_MIXED.  One
-// wavefront per block.
-__global__ __launch_bounds__(256) void k_coarse(int W, int H, int Wt, int blog, int Wc, int Hc,
-                                                const uint32_t *cells, uint16_t *coarse)
+// Spreads the 32 bits of v to the even bit positions of a 64-bit word.
+__device__ __forceinline__ uint64_t spread_bits(uint32_t v)
 {
-    const int lane = threadIdx.x & 63;
+    uint64_t x = v;
+    x = (x | (x << 16)) & 0x0000ffff0000ffffull;
+    x = (x | (x << 8)) & 0x00ff00ff00ff00ffull;
+    x = (x | (x << 4)) & 0x0f0f0f0f0f0f0f0full;
+    x = (x | (x << 2)) & 0x3333333333333333ull;
+    x = (x | (x << 1)) & 0x5555555555555555ull;
+    return x;
+}
+
+// Coarse canvas, mixed-block records and boundary-pixel array (see
+// COARSE_MIXED), one wavefront per coarse block.  Lane l handles pixels
+// l, l + 64, ...; pixel p of a block is (p mod B, p div B).
+// Canvas holding global coarse word g.
+__device__ __forceinline__ int canvas_of_coarse(const CanvasDesc *cds, int nc, int64_t g)
+{
+    int lo = 0, hi = nc - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (cds[mid].coarse_off <= g) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void k_compact(const CanvasDesc *cds, int nc, int64_t ncoarse_tot,
+                                                 const uint32_t *cells_all, uint16_t *coarse_all,
+                                                 uint4 *desc_all, uint32_t *bpix, unsigned int *mcount,
+                                                 unsigned long long *bcount, uint64_t bpix_cap)
+{
+    __shared__ uint32_t s_pre[4][129];
+    const int lane = threadIdx.x & 63, wl = threadIdx.x >> 6;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    const int B = 1 << blog;
-    for (int64_t cell = wave; cell < (int64_t)Wc * Hc; cell += nw) {
+    for (int64_t gcell = wave; gcell < ncoarse_tot; gcell += nw) {
+        const int q = canvas_of_coarse(cds, nc, gcell);
+        const CanvasDesc &cd = cds[q];
+        const int W = cd.W, H = cd.H, Wt = cd.Wt, blog = cd.blog, Wc = cd.Wc;
+        const uint32_t *cells = cells_all + cd.cell_off;
+        uint16_t *coarse = coarse_all + cd.coarse_off;
+        uint4 *desc = desc_all + cd.desc_off;
+        unsigned int *counters = mcount + q;
+        const int B = 1 << blog, P = B * B, J = P / 64, G = P / 32;
+        const int64_t cell = gcell - cd.coarse_off;
+        if (cd.empty) {
+            if (lane == 0) coarse[cell] = 0;
+            continue;
+        }
         const int cy = (int)(cell / Wc), cx = (int)(cell % Wc);
         const int c0 = cx << blog, r0 = cy << blog;
-        const int cw = min(B, W - c0), ch = min(B, H - r0);
+        auto pix_word = [&](int p, bool &valid) -> uint32_t {
+            const int c = c0 + (p & (B - 1)), r = r0 + (p >> blog);
+            valid = c < W && r < H;
+            return valid ? cells[tile_index(Wt, c, r)] : 0u;
+        };
         const uint32_t first = cells[tile_index(Wt, c0, r0)];
         bool same = true;
-        for (int p = lane; p < cw * ch; p += 64) {
-            const int c = c0 + p % cw, r = r0 + p / cw;
-            same &= cells[tile_index(Wt, c, r)] == first;
+        for (int j = 0; j < J; ++j) {
+            bool v;
+            const uint32_t w = pix_word(lane + 64 * j, v);
+            same &= !v || w == first;
         }
-        const bool all = __all(same);
-        if (lane == 0)
-            coarse[cell] = (all && !(first & BFLAG) && first < COARSE_MIXED) ? (uint16_t)first : COARSE_MIXED;
+        if (__all(same) && !(first & BFLAG) && first < COARSE_MIXED) {
+            if (lane == 0) coarse[cell] = (uint16_t)first;
+            continue;
+        }
+        // palette: up to two distinct non-zero non-boundary words <= 0xffff
+        uint32_t pal[2] = {0u, 0u};
+        int npal = 0;
+        bool full = false;
+        while (true) {
+            uint32_t cand = 0;
+            bool has = false;
+            for (int j = 0; j < J && !has; ++j) {
+                bool v;
+                const uint32_t w = pix_word(lane + 64 * j, v);
+                if (v && w != 0u && !(w & BFLAG)) {
+                    bool known = false;
+                    for (int q = 0; q < npal; ++q) known |= (pal[q] == w);
+                    if (!known) { cand = w; has = true; }
+                }
+            }
+            const unsigned long long mask = __ballot(has);
+            if (mask == 0ull) break;
+            const uint32_t v = __shfl(cand, __ffsll((long long)mask) - 1, 64);
+            if (npal == 2 || v > 0xffffu) { full = true; break; }
+            pal[npal++] = v;
+        }
+        uint32_t m = 0;
+        if (!full && lane == 0) m = atomicAdd(&counters[0], 1u);
+        m = __shfl(m, 0, 64);
+        if (full || m >= 0x7fffu) {
+            if (lane == 0) coarse[cell] = COARSE_FULL;
+            continue;
+        }
+        auto code_of = [&](int p, uint32_t &w) -> uint32_t {
+            bool v;
+            w = pix_word(p, v);
+            if (!v || w == 0u) return 2u;
+            if (w & BFLAG) return 3u;
+            return w == pal[0] ? 0u : 1u;
+        };
+        // boundary pixels before every 32-pixel group
+        uint32_t nb = 0;
+        for (int j = 0; j < J; ++j) {
+            uint32_t w;
+            const uint32_t code = code_of(lane + 64 * j, w);
+            const unsigned long long bm = __ballot(code == 3u);
+            if (lane == 0) {
+                s_pre[wl][2 * j] = nb;
+                nb += (uint32_t)__popcll(bm & 0xffffffffull);
+                s_pre[wl][2 * j + 1] = nb;
+                nb += (uint32_t)__popcll(bm >> 32);
+            }
+        }
+        nb = __shfl(nb, 0, 64);
+        uint32_t bbase = 0;
+        if (lane == 0 && nb) bbase = (uint32_t)atomicAdd(bcount, (unsigned long long)nb);
+        bbase = __shfl(bbase, 0, 64);
+        if ((uint64_t)bbase + nb > bpix_cap) {
+            // cannot happen (the array holds every boundary pixel); stay correct
+            if (lane == 0) coarse[cell] = COARSE_FULL;
+            continue;
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (lane == 0) coarse[cell] = (uint16_t)(COARSE_MIXED | m);
+        uint4 *rec = desc + (size_t)m * G;
+        const uint32_t palw = pal[0] | (pal[1] << 16);
+        for (int j = 0; j < J; ++j) {
+            uint32_t w;
+            const uint32_t code = code_of(lane + 64 * j, w);
+            const unsigned long long b0 = __ballot(code & 1u), b1 = __ballot(code & 2u);
+            const unsigned long long bm = b0 & b1;
+            if (lane == 0 || lane == 32) {
+                const int h = lane >> 5;
+                const uint32_t lo = (uint32_t)(b0 >> (32 * h)), hi = (uint32_t)(b1 >> (32 * h));
+                const uint64_t cw = spread_bits(lo) | (spread_bits(hi) << 1);
+                rec[2 * j + h] = make_uint4((uint32_t)cw, (uint32_t)(cw >> 32), bbase + s_pre[wl][2 * j + h], palw);
+            }
+            if (code == 3u) {
+                const int g = 2 * j + (lane >> 5);
+                const uint32_t half = (uint32_t)(bm >> (32 * (lane >> 5)));
+                const uint32_t rank = s_pre[wl][g] + (uint32_t)__popc(half & ((1u << (lane & 31)) - 1u));
+                bpix[(size_t)bbase + rank] = w & ~BFLAG;
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -733,14 +1000,48 @@ static int grid_for(int64_t n, int64_t cap = 65536)
     return (int)std::max<int64_t>(1, std::min<int64_t>(g, cap));
 }
 
-int build_canvas(spade_ctx *ctx, const spade_polys *polys, spade_canvas *cv)
+// Probe view of canvas q of a set (shared arrays + that canvas's map).
+CanvasView view_of(const spade_canvas *cv, int q)
+{
+    const CanvasDesc &d = cv->descs[(size_t)q];
+    CanvasView v{};
+    v.X0 = d.X0; v.Y0 = d.Y0; v.sx = d.sx; v.sy = d.sy;
+    v.bx0 = d.bx0; v.by0 = d.by0; v.bx1 = d.bx1; v.by1 = d.by1;
+    v.W = d.W; v.H = d.H; v.Wt = d.Wt; v.Wc = d.Wc; v.Hc = d.Hc; v.blog = d.blog;
+    v.M = d.M;
+    v.cells = (const uint32_t *)cv->cells.p + d.cell_off;
+    v.coarse = (const uint16_t *)cv->coarse.p + d.coarse_off;
+    v.desc = (const uint4 *)cv->desc.p + d.desc_off;
+    v.bpix = (const uint32_t *)cv->bpix.p;
+    v.cands = (const Cand *)cv->cands.p;
+    v.ledges = (const Edge *)cv->ledges.p;
+    v.pspan = (const double2 *)cv->pspan.p;
+    return v;
+}
+
+static void finish_views(spade_canvas *cv)
+{
+    cv->view = view_of(cv, 0);
+}
+
+// Sizes canvas q of a set: the context's fixed size, else about ctx->ppv
+// pixels per vertex (at most 4096 x 4096 pixels, at least 64 x 64) with
+// square world pixels.
+static void choose_size(const spade_ctx *ctx, double w, double h, int64_t nverts, int &W, int &H)
+{
+    if (ctx->canvas_w > 0 && ctx->canvas_h > 0) { W = ctx->canvas_w; H = ctx->canvas_h; return; }
+    const double target = std::min(4096.0 * 4096.0, std::max(64.0 * 64.0, ctx->ppv * (double)nverts));
+    const double aspect = w / h;
+    W = (int)std::max(1.0, std::min((double)MAXW, std::round(std::sqrt(target * aspect))));
+    H = (int)std::max(1.0, std::min(16384.0, std::round(target / W)));
+}
+
+int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *pbound, spade_canvas *cv)
 {
     hipStream_t st = ctx->stream;
     const int64_t M = polys->n_polys, R = polys->n_rings;
-    CanvasView &view = cv->view;
-    view = CanvasView{};
-    view.M = M;
-    view.bx0 = INFINITY; view.by0 = INFINITY; view.bx1 = -INFINITY; view.by1 = -INFINITY;
+    if (nc < 1) return set_error(ctx, SPADE_E_INVALID, "a canvas set needs at least one canvas");
+    cv->nc = nc;
 
     // vertex count
     int64_t V = 0;
@@ -754,96 +1055,147 @@ int build_canvas(spade_ctx *ctx, const spade_polys *polys, spade_canvas *cv)
         if (V >= (int64_t)0xffffffffLL) return set_error(ctx, SPADE_E_TOO_LARGE, "more than 2^32-1 vertices");
     }
 
-    // validation + ring->polygon + bbox
+    // validation + ring->polygon map
     DevBuf &rp = ctx->scratch[S_RINGPOLY];
     DevBuf &br = ctx->scratch[S_BLOCKRED];
+    const size_t bbbytes = sizeof(unsigned long long) * 4 * (size_t)nc;
     if (ensure(ctx, rp, sizeof(int32_t) * (size_t)std::max<int64_t>(R, 1)) ||
-        ensure(ctx, br, sizeof(double) * 4 * RED_BLOCKS + 64))
+        ensure(ctx, br, sizeof(double) * 4 * RED_BLOCKS + 64 + bbbytes))
         return SPADE_E_NOMEM;
     unsigned *d_err = (unsigned *)((char *)br.p + sizeof(double) * 4 * RED_BLOCKS);
+    unsigned long long *d_bb = (unsigned long long *)((char *)br.p + sizeof(double) * 4 * RED_BLOCKS + 64);
     SPADE_HIP(ctx, hipMemsetAsync(d_err, 0, sizeof(unsigned), st));
+    SPADE_HIP(ctx, hipMemsetAsync(d_bb, 0xff, bbbytes, st));
     if (M > 0 || R > 0 || V > 0) {
         hipLaunchKernelGGL(k_validate, dim3(RED_BLOCKS), dim3(256), 0, st, M, R, polys->poly_ring_off,
                            polys->ring_vtx_off, V, polys->vx, polys->vy, (int32_t *)rp.p,
                            (double *)br.p, d_err);
         SPADE_HIP(ctx, hipGetLastError());
     }
-    double *hred = (double *)ensure_pinned(ctx, sizeof(double) * 4 * RED_BLOCKS + 64);
-    if (!hred) return set_error(ctx, SPADE_E_NOMEM, "pinned staging allocation failed");
-    SPADE_HIP(ctx, hipMemcpyAsync(hred, br.p, sizeof(double) * 4 * RED_BLOCKS + sizeof(unsigned),
-                                  hipMemcpyDeviceToHost, st));
+    unsigned *herr = (unsigned *)ensure_pinned(ctx, 64);
+    if (!herr) return set_error(ctx, SPADE_E_NOMEM, "pinned staging allocation failed");
+    SPADE_HIP(ctx, hipMemcpyAsync(herr, d_err, sizeof(unsigned), hipMemcpyDeviceToHost, st));
     SPADE_HIP(ctx, hipStreamSynchronize(st));
-    unsigned herr = 0;
-    std::memcpy(&herr, (char *)hred + sizeof(double) * 4 * RED_BLOCKS, sizeof(unsigned));
-    if (herr & 1u) return set_error(ctx, SPADE_E_INVALID, "ring_vtx_off must start at 0 and be non-decreasing");
-    if (herr & 2u) return set_error(ctx, SPADE_E_INVALID, "poly_ring_off must start at 0, be non-decreasing and end at n_rings");
-    if (herr & 4u) return set_error(ctx, SPADE_E_INVALID, "non-finite polygon vertex coordinate");
-    double x0 = INFINITY, y0 = INFINITY, x1 = -INFINITY, y1 = -INFINITY;
+    if (herr[0] & 1u) return set_error(ctx, SPADE_E_INVALID, "ring_vtx_off must start at 0 and be non-decreasing");
+    if (herr[0] & 2u) return set_error(ctx, SPADE_E_INVALID, "poly_ring_off must start at 0, be non-decreasing and end at n_rings");
+    if (herr[0] & 4u) return set_error(ctx, SPADE_E_INVALID, "non-finite polygon vertex coordinate");
+
+    // per-canvas polygon ranges and vertex counts (host), bounding boxes (device)
+    std::vector<CanvasDesc> &cds = cv->descs;
+    cds.assign((size_t)nc, CanvasDesc{});
+    for (int q = 0; q < nc; ++q) {
+        cds[q].poly_base = pbound[q];
+        cds[q].M = pbound[q + 1] - pbound[q];
+    }
+    DevBuf &dcd = cv->dcds;
+    if (ensure(ctx, dcd, sizeof(CanvasDesc) * (size_t)nc)) return SPADE_E_NOMEM;
+    CanvasDesc *hcd = (CanvasDesc *)ensure_pinned(ctx, sizeof(CanvasDesc) * (size_t)nc + bbbytes + 64);
+    if (!hcd) return set_error(ctx, SPADE_E_NOMEM, "pinned staging allocation failed");
+    std::memcpy(hcd, cds.data(), sizeof(CanvasDesc) * (size_t)nc);
+    SPADE_HIP(ctx, hipMemcpyAsync(dcd.p, hcd, sizeof(CanvasDesc) * (size_t)nc, hipMemcpyHostToDevice, st));
+    std::vector<int64_t> nverts((size_t)nc, 0);
     if (V > 0) {
-        for (int b = 0; b < RED_BLOCKS; ++b) {
-            x0 = std::min(x0, hred[b * 4 + 0]); x1 = std::max(x1, -hred[b * 4 + 1]);
-            y0 = std::min(y0, hred[b * 4 + 2]); y1 = std::max(y1, -hred[b * 4 + 3]);
-        }
-    }
-
-    // canvas size and map
-    const bool empty = !(V > 0 && x0 < x1 && y0 < y1);
-    int W = 1, H = 1;
-    if (!empty) {
-        if (ctx->canvas_w > 0 && ctx->canvas_h > 0) {
-            W = ctx->canvas_w; H = ctx->canvas_h;
+        hipLaunchKernelGGL(k_canvas_bbox, dim3(grid_for((V + BB_SPAN - 1) / BB_SPAN)), dim3(256), 0, st, R, polys->ring_vtx_off, V,
+                           polys->vx, polys->vy, (const int32_t *)rp.p, (const CanvasDesc *)dcd.p, nc, d_bb);
+        SPADE_HIP(ctx, hipGetLastError());
+        if (nc > 1) {
+            // vertices per canvas from the offsets
+            std::vector<int64_t> pro((size_t)M + 1), rvo((size_t)R + 1);
+            if (polys->poly_ring_off)
+                SPADE_HIP(ctx, hipMemcpyAsync(pro.data(), polys->poly_ring_off, sizeof(int64_t) * (M + 1),
+                                              hipMemcpyDeviceToHost, st));
+            else
+                for (int64_t k = 0; k <= M; ++k) pro[k] = k;
+            SPADE_HIP(ctx, hipMemcpyAsync(rvo.data(), polys->ring_vtx_off, sizeof(int64_t) * (R + 1),
+                                          hipMemcpyDeviceToHost, st));
+            SPADE_HIP(ctx, hipStreamSynchronize(st));
+            for (int q = 0; q < nc; ++q) nverts[q] = rvo[pro[pbound[q + 1]]] - rvo[pro[pbound[q]]];
         } else {
-            const double aspect = (x1 - x0) / (y1 - y0);
-            const double target = 4096.0 * 4096.0;
-            double w = std::sqrt(target * aspect);
-            W = (int)std::max(1.0, std::min((double)MAXW, std::round(w)));
-            H = (int)std::max(1.0, std::min(65535.0, std::round(target / W)));
+            nverts[0] = V;
         }
     }
-    if (W > MAXW || H > 65535) return set_error(ctx, SPADE_E_UNSUPPORTED, "canvas larger than 8192 x 65535");
-    Map m;
-    m.W = W; m.H = H;
-    if (!empty) {
-        m.X0 = x0; m.Y0 = y0;
-        m.sx = (double)W / (x1 - x0);
-        m.sy = (double)H / (y1 - y0);
-        m.hy = (y1 - y0) / (double)H;
-        view.bx0 = x0; view.bx1 = x1; view.by0 = y0; view.by1 = y1;
-    } else {
-        m.X0 = 0; m.Y0 = 0; m.sx = 0; m.sy = 0; m.hy = 0;
-    }
-    view.X0 = m.X0; view.Y0 = m.Y0; view.sx = m.sx; view.sy = m.sy;
-    view.W = W; view.H = H;
+    unsigned long long *hbb = (unsigned long long *)((char *)hcd + sizeof(CanvasDesc) * (size_t)nc + 64);
+    SPADE_HIP(ctx, hipMemcpyAsync(hbb, d_bb, bbbytes, hipMemcpyDeviceToHost, st));
+    SPADE_HIP(ctx, hipStreamSynchronize(st));
+    auto undkey = [](unsigned long long k) {
+        const unsigned long long b = (k & 0x8000000000000000ull) ? (k & 0x7fffffffffffffffull) : ~k;
+        double d;
+        std::memcpy(&d, &b, sizeof d);
+        return d;
+    };
 
-    const int Wt = (W + 15) / 16, Ht = (H + 15) / 16;
-    view.Wt = Wt;
-    const size_t ncells = (size_t)Wt * Ht * 256;
-    if (ensure(ctx, cv->cells, sizeof(uint32_t) * ncells)) return SPADE_E_NOMEM;
-    view.cells = (const uint32_t *)cv->cells.p;
-    // coarse grid: blocks of 2^blog pixels, as fine as the probe's LDS allows
-    int blog = 4;
-    const size_t cbudget = coarse_lds_budget(M);
-    while (blog < 15 && (size_t)((W + (1 << blog) - 1) >> blog) * ((H + (1 << blog) - 1) >> blog) * 2 > cbudget)
-        ++blog;
-    view.blog = blog;
-    view.Wc = (W + (1 << blog) - 1) >> blog;
-    view.Hc = (H + (1 << blog) - 1) >> blog;
-    if (ensure(ctx, cv->coarse, sizeof(uint16_t) * ((size_t)view.Wc * view.Hc + 2))) return SPADE_E_NOMEM;
-    view.coarse = (const uint16_t *)cv->coarse.p;
-    if (ensure(ctx, cv->edges, sizeof(Edge) * (size_t)std::max<int64_t>(V, 1))) return SPADE_E_NOMEM;
+    // canvas maps, sizes and offsets
+    int maxW = 1;
+    int64_t Htot = 0, cells_tot = 0, coarse_tot = 0, desc_tot = 0;
+    bool any = false;
+    for (int q = 0; q < nc; ++q) {
+        CanvasDesc &d = cds[q];
+        double x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY;
+        if (nverts[q] > 0 || (nc == 1 && V > 0)) {
+            x0 = undkey(hbb[4 * q + 0]); x1 = -undkey(hbb[4 * q + 1]);
+            y0 = undkey(hbb[4 * q + 2]); y1 = -undkey(hbb[4 * q + 3]);
+        }
+        d.empty = !(x0 < x1 && y0 < y1);
+        int W = 1, H = 1;
+        if (!d.empty) choose_size(ctx, x1 - x0, y1 - y0, nverts[q], W, H);
+        if (W > MAXW || H > 16384) return set_error(ctx, SPADE_E_UNSUPPORTED, "canvas larger than 8192 x 16384");
+        d.W = W; d.H = H;
+        if (!d.empty) {
+            d.X0 = x0; d.Y0 = y0;
+            d.sx = (double)W / (x1 - x0);
+            d.sy = (double)H / (y1 - y0);
+            d.hy = (y1 - y0) / (double)H;
+            d.bx0 = x0; d.bx1 = x1; d.by0 = y0; d.by1 = y1;
+            any = true;
+        } else {
+            d.X0 = d.Y0 = d.sx = d.sy = d.hy = 0.0;
+            d.bx0 = d.by0 = INFINITY; d.bx1 = d.by1 = -INFINITY;
+        }
+        d.Wt = (W + 15) / 16;
+        const int Ht = (H + 15) / 16;
+        // coarse grid: blocks of 2^blog pixels, as fine as the probe's LDS allows
+        int blog = 4;
+        const size_t cbudget = coarse_lds_budget(d.M);
+        while (blog < 6 && (size_t)((W + (1 << blog) - 1) >> blog) * ((H + (1 << blog) - 1) >> blog) * 2 > cbudget)
+            ++blog;
+        if ((size_t)((W + (1 << blog) - 1) >> blog) * ((H + (1 << blog) - 1) >> blog) * 2 > cbudget)
+            return set_error(ctx, SPADE_E_UNSUPPORTED, "coarse canvas exceeds the probe's LDS; lower the canvas resolution");
+        d.blog = blog;
+        d.Wc = (W + (1 << blog) - 1) >> blog;
+        d.Hc = (H + (1 << blog) - 1) >> blog;
+        d.row_base = Htot;
+        d.cell_off = cells_tot;
+        d.coarse_off = coarse_tot;
+        d.desc_off = desc_tot;
+        Htot += H;
+        cells_tot += (int64_t)d.Wt * Ht * 256;
+        coarse_tot += (int64_t)d.Wc * d.Hc;
+        desc_tot += (int64_t)std::min<int64_t>((int64_t)d.Wc * d.Hc, 0x7fff) * (desc_bytes(blog) / 16);
+        maxW = std::max(maxW, W);
+    }
+    if (Htot > 0x7fffffffLL) return set_error(ctx, SPADE_E_UNSUPPORTED, "canvas set has too many rows");
+    std::memcpy(hcd, cds.data(), sizeof(CanvasDesc) * (size_t)nc);
+    SPADE_HIP(ctx, hipMemcpyAsync(dcd.p, hcd, sizeof(CanvasDesc) * (size_t)nc, hipMemcpyHostToDevice, st));
+    const CanvasDesc *d_cds = (const CanvasDesc *)dcd.p;
+
+    if (ensure(ctx, cv->cells, sizeof(uint32_t) * (size_t)cells_tot) ||
+        ensure(ctx, cv->coarse, sizeof(uint16_t) * ((size_t)coarse_tot + 2)) ||
+        ensure(ctx, cv->desc, 16 * (size_t)desc_tot + 64) ||
+        ensure(ctx, cv->edges, sizeof(Edge) * (size_t)std::max<int64_t>(V, 1)))
+        return SPADE_E_NOMEM;
     cv->n_edges = V;
-    if (empty) {
-        SPADE_HIP(ctx, hipMemsetAsync(cv->cells.p, 0, sizeof(uint32_t) * ncells, st));
-        SPADE_HIP(ctx, hipMemsetAsync(cv->coarse.p, 0, sizeof(uint16_t) * ((size_t)view.Wc * view.Hc + 2), st));
+    if (!any) {
+        SPADE_HIP(ctx, hipMemsetAsync(cv->cells.p, 0, sizeof(uint32_t) * (size_t)cells_tot, st));
+        SPADE_HIP(ctx, hipMemsetAsync(cv->coarse.p, 0, sizeof(uint16_t) * ((size_t)coarse_tot + 2), st));
         if (ensure(ctx, cv->cands, sizeof(Cand)) || ensure(ctx, cv->ledges, sizeof(Edge)) ||
-            ensure(ctx, cv->pspan, sizeof(double2)))
+            ensure(ctx, cv->pspan, sizeof(double2)) || ensure(ctx, cv->bpix, sizeof(uint32_t)))
             return SPADE_E_NOMEM;
-        view.cands = (const Cand *)cv->cands.p;
-        view.ledges = (const Edge *)cv->ledges.p;
-        view.pspan = (const double2 *)cv->pspan.p;
         cv->n_boundary = cv->n_cands = cv->n_elist = 0;
+        finish_views(cv);
         return SPADE_OK;
     }
+    const int W = maxW;
+    const int64_t H = Htot;
 
     // edges + per-edge row counts
     DevBuf &dn = ctx->scratch[S_NROWS];
@@ -858,7 +1210,7 @@ int build_canvas(spade_ctx *ctx, const spade_polys *polys, spade_canvas *cv)
     int32_t *erow0 = (int32_t *)(epoly + Vs);
     uint64_t *eoff = (uint64_t *)(((uintptr_t)(erow0 + Vs) + 7) & ~(uintptr_t)7);
     hipLaunchKernelGGL(k_edges, dim3(grid_for(V)), dim3(256), 0, st, R, polys->ring_vtx_off, V,
-                       polys->vx, polys->vy, (const int32_t *)rp.p, m, (Edge *)cv->edges.p, epoly,
+                       polys->vx, polys->vy, (const int32_t *)rp.p, d_cds, nc, (Edge *)cv->edges.p, epoly,
                        erow0, nrows);
     SPADE_HIP(ctx, hipGetLastError());
     SPADE_HIP(ctx, hipMemsetAsync(nrows + V, 0, sizeof(uint64_t), st));
@@ -875,7 +1227,9 @@ int build_canvas(spade_ctx *ctx, const spade_polys *polys, spade_canvas *cv)
     if (T >= 0x7fffffffULL) return set_error(ctx, SPADE_E_UNSUPPORTED, "too many (edge,row) entries; lower the canvas height");
 
     const int cbits = std::max(1, bits_for((uint64_t)W - 1));
-    const int pbits = std::max(1, bits_for((uint64_t)std::max<int64_t>(M - 1, 0)));
+    int64_t maxM = 1;
+    for (int q = 0; q < nc; ++q) maxM = std::max<int64_t>(maxM, cds[q].M);
+    const int pbits = std::max(1, bits_for((uint64_t)(maxM - 1)));
     const int rbits = std::max(1, bits_for((uint64_t)H - 1));
     if (cbits + pbits + rbits > 64) return set_error(ctx, SPADE_E_UNSUPPORTED, "sort key exceeds 64 bits");
 
@@ -887,15 +1241,18 @@ int build_canvas(spade_ctx *ctx, const spade_polys *polys, spade_canvas *cv)
     // dc: ent_c[T] | sorted c[T] | perm[T] | perm2[T]; df: ent_f[T] | sorted f[T]
     if (ensure(ctx, dk, 8 * Ts) || ensure(ctx, dk2, 8 * Ts) || ensure(ctx, dv, 4 * Ts) ||
         ensure(ctx, dv2, 4 * Ts) || ensure(ctx, dc, 20 * Ts) || ensure(ctx, df, 2 * Ts + 16) ||
-        ensure(ctx, drow, 4 * ((size_t)H + 1)) ||
-        ensure(ctx, drc, 8 * 8 * ((size_t)H + 1)))
+        ensure(ctx, drow, 8 * ((size_t)H + 1)) ||
+        ensure(ctx, drc, 8 * 8 * ((size_t)H + 1) + 64))
         return SPADE_E_NOMEM;
     uint32_t *ent_c = (uint32_t *)dc.p, *s_c = ent_c + Ts, *perm = s_c + Ts, *perm2 = perm + Ts;
     uint32_t *s_poly = perm2 + Ts;
     uint8_t *ent_f = (uint8_t *)df.p, *s_f = ent_f + Ts;
+    // counters after the per-row arrays: [0..3] row-pass allocation, [4] footprint widths
+    unsigned long long *gctr = (unsigned long long *)((uint64_t *)drc.p + 8 * ((size_t)H + 1));
+    SPADE_HIP(ctx, hipMemsetAsync(gctr, 0, 64, st));
     hipLaunchKernelGGL(k_entries, dim3(grid_for(V)), dim3(256), 0, st, V, (const Edge *)cv->edges.p,
-                       epoly, erow0, nrows, eoff, m, cbits, pbits, (uint64_t *)dk.p, (uint32_t *)dv.p,
-                       ent_c, ent_f);
+                       epoly, erow0, nrows, eoff, d_cds, nc, cbits, pbits, (uint64_t *)dk.p, (uint32_t *)dv.p,
+                       ent_c, ent_f, gctr + 4);
     SPADE_HIP(ctx, hipGetLastError());
     hipLaunchKernelGGL(k_iota, dim3(grid_for((int64_t)T)), dim3(256), 0, st, (int64_t)T, perm);
     SPADE_HIP(ctx, hipGetLastError());
@@ -936,10 +1293,16 @@ int build_canvas(spade_ctx *ctx, const spade_polys *polys, spade_canvas *cv)
     uint64_t *part_base = loc_base + (H + 1);
     uint64_t *bp_scan = part_base + (H + 1);
     SPADE_HIP(ctx, hipMemsetAsync(drc.p, 0, 8 * 8 * ((size_t)H + 1), st));
+    uint64_t *hw = (uint64_t *)ensure_pinned(ctx, 64);
+    SPADE_HIP(ctx, hipMemcpyAsync(hw, gctr + 4, 8, hipMemcpyDeviceToHost, st));
+    SPADE_HIP(ctx, hipStreamSynchronize(st));
+    const uint64_t sumw = hw[0];
 
     RowArgs ra{};
-    ra.m = m;
-    ra.Wt = Wt;
+    ra.cds = d_cds;
+    ra.nc = nc;
+    ra.maxW = W;
+    ra.Htot = H;
     ra.row_off = (const uint32_t *)drow.p;
     ra.spoly = s_poly;
     ra.sedge = s_edge;
@@ -952,52 +1315,112 @@ int build_canvas(spade_ctx *ctx, const spade_polys *polys, spade_canvas *cv)
     // stage up to `cap` entries of a row in LDS; aim for two workgroups per CU
     const size_t col_bytes = row_lds_bytes(W, 0);
     const size_t target = (col_bytes <= 60 * 1024) ? 78 * 1024 : 150 * 1024;
-    ra.cap = (int)std::max<size_t>(256, (target - std::min(target - 256 * 27, col_bytes)) / 27);
+    ra.cap = (int)std::max<size_t>(256, (target - std::min(target - 256 * 37, col_bytes)) / 37);
     if (T > (uint64_t)ra.cap) {
         // some row may exceed the LDS stage: global auxiliary words for it
-        if (ensure(ctx, ctx->scratch[S_NEXTP], sizeof(uint32_t) * 5 * Ts)) return SPADE_E_NOMEM;
+        if (ensure(ctx, ctx->scratch[S_NEXTP], sizeof(uint32_t) * 6 * Ts)) return SPADE_E_NOMEM;
         ra.gaux = (uint32_t *)ctx->scratch[S_NEXTP].p;
     }
     const size_t rlds = row_lds_bytes(W, ra.cap);
-    SPADE_HIP(ctx, hipFuncSetAttribute((const void *)k_rows<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)rlds));
-    SPADE_HIP(ctx, hipFuncSetAttribute((const void *)k_rows<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)rlds));
-    const int rgrid = std::min(H, 8192);
-    hipLaunchKernelGGL(k_rows<false>, dim3(rgrid), dim3(ROW_THREADS), rlds, st, ra);
-    SPADE_HIP(ctx, hipGetLastError());
-
-    // per-row bases (exclusive scans over H+1 entries with a zero tail)
-    tb = 0;
-    SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(nullptr, tb, row_nrec, rec_base, H + 1, st));
-    if (ensure(ctx, cub, tb)) return SPADE_E_NOMEM;
-    SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(cub.p, tb, row_nrec, rec_base, H + 1, st));
-    SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(cub.p, tb, row_nloc, loc_base, H + 1, st));
-    SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(cub.p, tb, row_npart, part_base, H + 1, st));
-    SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(cub.p, tb, row_nbp, bp_scan, H + 1, st));
-    uint64_t *hs = (uint64_t *)ensure_pinned(ctx, 64);
-    SPADE_HIP(ctx, hipMemcpyAsync(hs + 0, rec_base + H, 8, hipMemcpyDeviceToHost, st));
-    SPADE_HIP(ctx, hipMemcpyAsync(hs + 1, loc_base + H, 8, hipMemcpyDeviceToHost, st));
-    SPADE_HIP(ctx, hipMemcpyAsync(hs + 2, part_base + H, 8, hipMemcpyDeviceToHost, st));
-    SPADE_HIP(ctx, hipMemcpyAsync(hs + 3, bp_scan + H, 8, hipMemcpyDeviceToHost, st));
-    SPADE_HIP(ctx, hipStreamSynchronize(st));
-    const uint64_t nrec = hs[0], nloc = hs[1], npart = hs[2], nbp = hs[3];
-    if (nrec >= (uint64_t)BFLAG) return set_error(ctx, SPADE_E_UNSUPPORTED, "boundary index exceeds 2^31 records; lower the canvas resolution");
-    if (nloc >= 0xffffffffULL || npart >= 0xffffffffULL)
-        return set_error(ctx, SPADE_E_UNSUPPORTED, "boundary edge lists exceed 2^32 entries");
-    if (ensure(ctx, cv->cands, sizeof(Cand) * (size_t)std::max<uint64_t>(nrec, 1)) ||
-        ensure(ctx, cv->ledges, sizeof(Edge) * (size_t)std::max<uint64_t>(nloc, 1)) ||
-        ensure(ctx, cv->pspan, sizeof(double2) * (size_t)std::max<uint64_t>(npart, 1)))
-        return SPADE_E_NOMEM;
+    // rows longer than the stage go to a second launch with the largest stage
+    const int cap_big = (int)std::max<size_t>((size_t)ra.cap, (150 * 1024 - std::min<size_t>(150 * 1024 - 256 * 37, col_bytes)) / 37);
+    const size_t rlds_big = row_lds_bytes(W, cap_big);
+    SPADE_HIP(ctx, hipFuncSetAttribute((const void *)k_rows<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)rlds_big));
+    SPADE_HIP(ctx, hipFuncSetAttribute((const void *)k_rows<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)rlds_big));
+    const int rgrid = (int)std::min<int64_t>(H, 8192);
+    auto launch_rows = [&](bool emit) -> hipError_t {
+        RowArgs a1 = ra;
+        a1.min_n = 0;
+        a1.max_n = ra.cap;
+        if (emit) hipLaunchKernelGGL(k_rows<true>, dim3(rgrid), dim3(ROW_THREADS), rlds, st, a1);
+        else hipLaunchKernelGGL(k_rows<false>, dim3(rgrid), dim3(ROW_THREADS), rlds, st, a1);
+        hipError_t e1 = hipGetLastError();
+        if (e1 != hipSuccess || T <= (uint64_t)ra.cap) return e1;
+        RowArgs a2 = ra;
+        a2.cap = cap_big;
+        a2.min_n = ra.cap + 1;
+        a2.max_n = 0x7fffffff;
+        if (emit) hipLaunchKernelGGL(k_rows<true>, dim3(rgrid), dim3(ROW_THREADS), rlds_big, st, a2);
+        else hipLaunchKernelGGL(k_rows<false>, dim3(rgrid), dim3(ROW_THREADS), rlds_big, st, a2);
+        return hipGetLastError();
+    };
     ra.cells = (uint32_t *)cv->cells.p;
-    ra.cands = (Cand *)cv->cands.p;
-    ra.ledges = (Edge *)cv->ledges.p;
-    ra.pspan = (double2 *)cv->pspan.p;
-    hipLaunchKernelGGL(k_rows<true>, dim3(rgrid), dim3(ROW_THREADS), rlds, st, ra);
-    SPADE_HIP(ctx, hipGetLastError());
+
+    // One row pass: rows reserve their output ranges with atomics inside
+    // bounds derived from the entries (records <= 2 * sum of footprint widths
+    // unless interiors overlap, local edges <= that sum, partial spans <= T).
+    bool done_single = false;
+    uint64_t nrec = 0, nloc = 0, npart = 0, nbp = 0;
     {
-        const int64_t ncoarse = (int64_t)view.Wc * view.Hc;
-        const int cgrid = (int)std::max<int64_t>(1, std::min<int64_t>((ncoarse + 3) / 4, 65536));
-        hipLaunchKernelGGL(k_coarse, dim3(cgrid), dim3(256), 0, st, W, H, Wt, blog, view.Wc, view.Hc,
-                           (const uint32_t *)cv->cells.p, (uint16_t *)cv->coarse.p);
+        ra.alloc = 1;
+        ra.gctr = gctr;
+        ra.cap_rec = 2 * sumw + 16;
+        ra.cap_loc = sumw + 16;
+        ra.cap_part = T + 16;
+        if (ensure(ctx, cv->cands, sizeof(Cand) * (size_t)ra.cap_rec) ||
+            ensure(ctx, cv->ledges, sizeof(Edge) * (size_t)ra.cap_loc) ||
+            ensure(ctx, cv->pspan, sizeof(double2) * (size_t)ra.cap_part))
+            return SPADE_E_NOMEM;
+        ra.cands = (Cand *)cv->cands.p;
+        ra.ledges = (Edge *)cv->ledges.p;
+        ra.pspan = (double2 *)cv->pspan.p;
+        SPADE_HIP(ctx, launch_rows(true));
+        uint64_t *hc = (uint64_t *)ensure_pinned(ctx, 64);
+        SPADE_HIP(ctx, hipMemcpyAsync(hc, gctr, 32, hipMemcpyDeviceToHost, st));
+        SPADE_HIP(ctx, hipMemcpyAsync(hc + 4, d_err, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+        SPADE_HIP(ctx, hipStreamSynchronize(st));
+        unsigned ef = 0;
+        std::memcpy(&ef, hc + 4, sizeof(unsigned));
+        if (!(ef & 32u)) {
+            done_single = true;
+            nrec = hc[0]; nloc = hc[1]; npart = hc[2]; nbp = hc[3];
+        } else {
+            // overflow: clear the flag and redo with exact sizes
+            ef &= ~32u;
+            SPADE_HIP(ctx, hipMemcpyAsync(d_err, &ef, sizeof(unsigned), hipMemcpyHostToDevice, st));
+        }
+    }
+    if (!done_single) {
+        ra.alloc = 0;
+        SPADE_HIP(ctx, launch_rows(false));
+        // per-row bases (exclusive scans over H+1 entries with a zero tail)
+        tb = 0;
+        SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(nullptr, tb, row_nrec, rec_base, H + 1, st));
+        if (ensure(ctx, cub, tb)) return SPADE_E_NOMEM;
+        SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(cub.p, tb, row_nrec, rec_base, H + 1, st));
+        SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(cub.p, tb, row_nloc, loc_base, H + 1, st));
+        SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(cub.p, tb, row_npart, part_base, H + 1, st));
+        SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(cub.p, tb, row_nbp, bp_scan, H + 1, st));
+        uint64_t *hs = (uint64_t *)ensure_pinned(ctx, 64);
+        SPADE_HIP(ctx, hipMemcpyAsync(hs + 0, rec_base + H, 8, hipMemcpyDeviceToHost, st));
+        SPADE_HIP(ctx, hipMemcpyAsync(hs + 1, loc_base + H, 8, hipMemcpyDeviceToHost, st));
+        SPADE_HIP(ctx, hipMemcpyAsync(hs + 2, part_base + H, 8, hipMemcpyDeviceToHost, st));
+        SPADE_HIP(ctx, hipMemcpyAsync(hs + 3, bp_scan + H, 8, hipMemcpyDeviceToHost, st));
+        SPADE_HIP(ctx, hipStreamSynchronize(st));
+        nrec = hs[0]; nloc = hs[1]; npart = hs[2]; nbp = hs[3];
+        if (nrec >= (uint64_t)BFLAG) return set_error(ctx, SPADE_E_UNSUPPORTED, "boundary index exceeds 2^31 records; lower the canvas resolution");
+        if (nloc >= 0xffffffffULL || npart >= 0xffffffffULL)
+            return set_error(ctx, SPADE_E_UNSUPPORTED, "boundary edge lists exceed 2^32 entries");
+        if (ensure(ctx, cv->cands, sizeof(Cand) * (size_t)std::max<uint64_t>(nrec, 1)) ||
+            ensure(ctx, cv->ledges, sizeof(Edge) * (size_t)std::max<uint64_t>(nloc, 1)) ||
+            ensure(ctx, cv->pspan, sizeof(double2) * (size_t)std::max<uint64_t>(npart, 1)))
+            return SPADE_E_NOMEM;
+        ra.cands = (Cand *)cv->cands.p;
+        ra.ledges = (Edge *)cv->ledges.p;
+        ra.pspan = (double2 *)cv->pspan.p;
+        SPADE_HIP(ctx, launch_rows(true));
+    }
+    {
+        const int cgrid = (int)std::max<int64_t>(1, std::min<int64_t>((coarse_tot + 3) / 4, 65536));
+        if (ensure(ctx, cv->bpix, sizeof(uint32_t) * (size_t)std::max<uint64_t>(nbp, 1)) ||
+            ensure(ctx, ctx->scratch[S_LOOKBACK], sizeof(unsigned int) * (size_t)nc + 64))
+            return SPADE_E_NOMEM;
+        SPADE_HIP(ctx, hipMemsetAsync(gctr + 5, 0, 8, st));
+        SPADE_HIP(ctx, hipMemsetAsync(ctx->scratch[S_LOOKBACK].p, 0, sizeof(unsigned int) * (size_t)nc, st));
+        hipLaunchKernelGGL(k_compact, dim3(cgrid), dim3(256), 0, st, d_cds, nc, coarse_tot,
+                           (const uint32_t *)cv->cells.p, (uint16_t *)cv->coarse.p, (uint4 *)cv->desc.p,
+                           (uint32_t *)cv->bpix.p, (unsigned int *)ctx->scratch[S_LOOKBACK].p, gctr + 5,
+                           (uint64_t)std::max<uint64_t>(nbp, 1));
         SPADE_HIP(ctx, hipGetLastError());
     }
     unsigned *herr2 = (unsigned *)ensure_pinned(ctx, 64);
@@ -1006,13 +1429,17 @@ int build_canvas(spade_ctx *ctx, const spade_polys *polys, spade_canvas *cv)
     if (herr2[0] & 8u) return set_error(ctx, SPADE_E_HIP, "internal: boundary pixel without candidates");
     if (herr2[0] & 16u)
         return set_error(ctx, SPADE_E_UNSUPPORTED, "a boundary pixel has more than 32767 edges of one polygon; raise the canvas resolution");
-    view.cands = (const Cand *)cv->cands.p;
-    view.ledges = (const Edge *)cv->ledges.p;
-    view.pspan = (const double2 *)cv->pspan.p;
     cv->n_boundary = (int64_t)nbp;
     cv->n_cands = (int64_t)nrec;
     cv->n_elist = (int64_t)(nloc + npart);
+    finish_views(cv);
     return SPADE_OK;
+}
+
+int build_canvas(spade_ctx *ctx, const spade_polys *polys, spade_canvas *cv)
+{
+    const int64_t b[2] = {0, polys->n_polys};
+    return build_set(ctx, polys, 1, b, cv);
 }
 
 }  // namespace spade

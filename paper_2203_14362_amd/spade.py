@@ -34,6 +34,8 @@ EXPORTS = [
     "spade_canvas_build", "spade_canvas_destroy", "spade_canvas_info", "spade_canvas_select",
     "spade_canvas_join_count", "spade_canvas_join_count_async", "spade_canvas_join_pairs",
     "spade_orient_batch", "spade_ctx_set_timing", "spade_ctx_last_timing",
+    "spade_table_create", "spade_table_destroy", "spade_table_info", "spade_batch_build",
+    "spade_batch_select", "spade_batch_join_count", "spade_ctx_set_pixels_per_vertex",
 ]
 
 
@@ -87,6 +89,14 @@ def load_library():
     lib.spade_orient_batch.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp]
     lib.spade_ctx_set_timing.argtypes = [vp, ctypes.c_int]
     lib.spade_ctx_last_timing.argtypes = [vp, P(ctypes.c_float), P(ctypes.c_float)]
+    lib.spade_table_create.argtypes = [vp, P(_Points), P(vp)]
+    lib.spade_table_destroy.argtypes = [vp]
+    lib.spade_table_destroy.restype = None
+    lib.spade_table_info.argtypes = [vp, P(i64), P(i32), P(i64), P(i64)]
+    lib.spade_batch_build.argtypes = [vp, P(_Polys), i32, vp, P(vp)]
+    lib.spade_batch_select.argtypes = [vp, vp, vp, vp, i64, vp]
+    lib.spade_batch_join_count.argtypes = [vp, vp, vp, vp]
+    lib.spade_ctx_set_pixels_per_vertex.argtypes = [vp, ctypes.c_double]
     for name in EXPORTS:
         f = getattr(lib, name)
         if f.restype is ctypes.c_int:
@@ -169,6 +179,41 @@ class Canvas:
             pass
 
 
+class Table:
+    """Device-resident point table clustered by a grid (the library's copy)."""
+
+    def __init__(self, ctx: "Context", handle):
+        self.ctx = ctx
+        self.handle = handle
+
+    def info(self):
+        n, g, c, by = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64()
+        self.ctx.lib.spade_table_info(self.handle, ctypes.byref(n), ctypes.byref(g), ctypes.byref(c),
+                                      ctypes.byref(by))
+        return {"n_points": n.value, "grid": g.value, "chunks": c.value, "device_bytes": by.value}
+
+    def close(self):
+        if self.handle:
+            self.ctx.lib.spade_table_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch(Canvas):
+    """A batch of queries rasterised as one canvas set."""
+
+    def __init__(self, ctx: "Context", handle, qbound):
+        super().__init__(ctx, handle)
+        self.qbound = qbound
+        self.n_queries = len(qbound) - 1
+        self.n_polys = int(qbound[-1])
+
+
 class Context:
     """One spade_ctx bound to a device; calls run on torch's current stream."""
 
@@ -205,8 +250,56 @@ class Context:
         self._check(self.lib.spade_ctx_last_timing(self.handle, ctypes.byref(r), ctypes.byref(p)))
         return float(r.value), float(p.value)
 
+    def set_pixels_per_vertex(self, ppv: float):
+        self._check(self.lib.spade_ctx_set_pixels_per_vertex(self.handle, float(ppv)))
+
     def polys(self, polys):
         return polys if isinstance(polys, DevicePolys) else DevicePolys(polys, self.device)
+
+    # -- resident tables and batches
+    def table(self, x, y) -> Table:
+        self._sync_stream()
+        P = _points(x, y)
+        h = ctypes.c_void_p()
+        self._check(self.lib.spade_table_create(self.handle, ctypes.byref(P), ctypes.byref(h)))
+        return Table(self, h)
+
+    def batch(self, polys, qbound) -> Batch:
+        """Rasterise queries [qbound[q], qbound[q+1]) of ``polys`` as one canvas set."""
+        self._sync_stream()
+        dp = self.polys(polys)
+        qb = np.ascontiguousarray(qbound, dtype=np.int64)
+        h = ctypes.c_void_p()
+        self._check(self.lib.spade_batch_build(self.handle, ctypes.byref(dp.cstruct()), int(qb.size - 1),
+                                               qb.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h)))
+        return Batch(self, h, qb)
+
+    def batch_select(self, batch: Batch, table: Table, cap=None):
+        """(ids int32 tensor, offsets int64 numpy [nq + 1]): query q's ascending
+        point ids are ids[off[q]:off[q+1]]."""
+        off = np.zeros(batch.n_queries + 1, dtype=np.int64)
+        if cap is None:
+            cap = max(table.info()["n_points"], 1)
+        while True:
+            ids = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device)
+            self._sync_stream()
+            rc = self.lib.spade_batch_select(self.handle, batch.handle, table.handle,
+                                             ctypes.c_void_p(ids.data_ptr()), cap,
+                                             off.ctypes.data_as(ctypes.c_void_p))
+            if rc == SPADE_E_CAPACITY:
+                cap = int(off[-1])
+                continue
+            self._check(rc)
+            return ids[:int(off[-1])], off
+
+    def batch_join_count(self, batch: Batch, table: Table, out=None):
+        """Per-polygon counts of the batch's polygon set (int64 tensor)."""
+        self._sync_stream()
+        if out is None:
+            out = torch.empty(batch.n_polys, dtype=torch.int64, device=self.device)
+        self._check(self.lib.spade_batch_join_count(self.handle, batch.handle, table.handle,
+                                                    ctypes.c_void_p(out.data_ptr() if batch.n_polys else 0)))
+        return out
 
     # -- canvases
     def canvas(self, polys) -> Canvas:

@@ -222,6 +222,30 @@ def star_polygon(V: int, area_frac: float, centre, L: float = EXTENT_M, seed: in
     return polys_from_rings([[ring]])
 
 
+def query_stars(nq: int, vmin: int, vmax: int, seed: int = 6, L: float = EXTENT_M,
+                area=(1e-4, 1e-2), data_seed: int = 2, noise: float = 0.3):
+    """A batch of nq star-shaped selection polygons (one per query).
+
+    Vertex counts are log-uniform in [vmin, vmax]; areas are log-uniform in
+    ``area`` (fractions of L^2); centres are drawn from the taxi-like mixture
+    of ``data_seed`` (queries look where the data is).  Returns (polys,
+    qbound) with query q = polygon q.
+    """
+    rng = rng_for(seed, 6)
+    V = np.floor(np.exp(rng.uniform(math.log(vmin), math.log(vmax + 1), size=nq))).astype(np.int64)
+    V = np.clip(V, vmin, vmax)
+    af = np.exp(rng.uniform(math.log(area[0]), math.log(area[1]), size=nq))
+    cx, cy = _mixture_chunk(mixture_params(data_seed, L), nq, rng_for(seed, 7))
+    th_off = rng.uniform(0.0, 2.0 * math.pi, size=nq)
+    rings = []
+    for q in range(nq):
+        R = math.sqrt(af[q] * L * L / math.pi)
+        th = th_off[q] + 2.0 * math.pi * np.arange(V[q]) / V[q]
+        r = R * (1.0 + noise * rng.uniform(-1.0, 1.0, size=V[q]))
+        rings.append([np.stack([cx[q] + r * np.cos(th), cy[q] + r * np.sin(th)], axis=1)])
+    return polys_from_rings(rings), np.arange(nq + 1, dtype=np.int64)
+
+
 # ------------------------------------------------- Voronoi jitter tessellation
 
 def _seg_intersections_ring(ring):
