@@ -15,6 +15,16 @@ entry prices 16 algorithmic bytes per point (two float64 coordinates)
 against the 8 TB/s HBM peak.  ``cpu_baseline`` times the CPU oracle on a
 bounded prefix of the same points with every host core.
 
+The ``serving`` object comes from a second leg (skipped with
+``--serve-seconds 0``): a resident table of 200,000,000 clustered points,
+requests arriving as a Poisson stream at 200 per second for the given
+number of seconds, half selections (one star of 8..20,000 vertices), half
+join-counts (64..40,000 polygons of a 40,000-cell Voronoi-jitter
+tessellation with 4..40 vertices each), served with continuous batching on
+two workers.  It reports p50 / p99 latency from arrival to result-ready and
+the served rate, beside the rate of the same requests run one at a time
+with the plain single-query calls.
+
 Prints one JSON line on stdout; progress goes to stderr.
 """
 import argparse
@@ -58,6 +68,96 @@ def load_traffic(n_points):
     return d.get("hbm_bytes_per_launch")
 
 
+def serving_leg(seconds, qps, n_points, oneshot_max):
+    """Continuous-batching server over a resident table; one-at-a-time baseline."""
+    import numpy as np
+    import torch
+    from workloads import gen
+    from paper_2203_14362_amd import Context
+    from paper_2203_14362_amd.serve import Request, Server, SpadeExecutor, latency_stats, replay
+
+    t = time.time()
+    x, y = gen.mixture_points(n_points, seed=2, L=gen.EXTENT_M)
+    dx = torch.from_numpy(x).cuda()
+    dy = torch.from_numpy(y).cuda()
+    del x, y
+    arrivals = gen.poisson_arrivals(qps, seconds, seed=5)
+    n = arrivals.size
+    stars, _ = gen.query_stars(n, 8, 20000, seed=8, L=gen.EXTENT_M, area=(1e-4, 1e-2), data_seed=2)
+    tess = gen.voronoi_jitter(40000, 4, 40, seed=9, L=gen.EXTENT_M)
+    log("serving inputs: %d points, %d requests, 40000-cell tessellation (%.1fs)" % (n_points, n, time.time() - t))
+    rng = np.random.default_rng(11)
+    srvo, trvo = stars["ring_vtx_off"], tess["ring_vtx_off"]
+    reqs = []
+    for i in range(n):
+        if rng.random() < 0.5:
+            p = {"n_polys": 1, "poly_ring_off": None, "ring_vtx_off": np.array([0, srvo[i + 1] - srvo[i]]),
+                 "vx": stars["vx"][srvo[i]:srvo[i + 1]], "vy": stars["vy"][srvo[i]:srvo[i + 1]]}
+            reqs.append(Request(i, "select", p))
+        else:
+            m = int(np.exp(rng.uniform(np.log(64), np.log(40000))))
+            ks = np.sort(rng.choice(40000, m, replace=False))
+            lens = trvo[ks + 1] - trvo[ks]
+            idx = np.concatenate([np.arange(trvo[k], trvo[k + 1]) for k in ks])
+            p = {"n_polys": m, "poly_ring_off": None,
+                 "ring_vtx_off": np.concatenate([[0], np.cumsum(lens)]).astype(np.int64),
+                 "vx": tess["vx"][idx], "vy": tess["vy"][idx]}
+            reqs.append(Request(i, "count", p))
+
+    ex = SpadeExecutor(dx, dy, n_workers=2)
+    free, _ = torch.cuda.mem_get_info()
+    budget = max(free - (16 << 30), 1 << 30)
+    # warm the workers' contexts and canvas sets
+    warm = [Request(-1 - k, r.kind, r.polys) for k, r in enumerate(reqs[:4])]
+    srv = Server(ex, budget_bytes=budget).start()
+    for r in warm:
+        srv.submit(r)
+    srv.drain()
+    srv.done.clear()
+    srv.batches.clear()
+    wall = replay(srv, reqs, arrivals)
+    srv.stop()
+    errs = [r.error for r in reqs if r.error]
+    if errs:
+        raise SystemExit("served requests failed: %s" % errs[:3])
+    st = latency_stats(reqs)
+    sizes = [len(b) for b in srv.batches]
+    log("served %d requests in %.2fs: p50 %.2f ms, p99 %.2f ms, %d batches (mean %.1f requests)"
+        % (n, wall, st["p50_ms"], st["p99_ms"], len(sizes), float(np.mean(sizes))))
+
+    # one at a time, plain calls on the original arrays (no table, no batching)
+    ctx = Context(0)
+    k = min(oneshot_max, n)
+    for r in reqs[:2]:
+        (ctx.select if r.kind == "select" else ctx.join_count)(dx, dy, r.polys)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in reqs[:k]:
+        (ctx.select if r.kind == "select" else ctx.join_count)(dx, dy, r.polys)
+    torch.cuda.synchronize()
+    one = (time.perf_counter() - t0) / k
+    # served capacity: the same requests submitted at once (no arrival gaps)
+    for r in reqs:
+        r.arrival = r.admitted = r.done = r.result = None
+    srv = Server(ex, budget_bytes=budget).start()
+    t0 = time.perf_counter()
+    for r in reqs:
+        srv.submit(r)
+    srv.stop()
+    burst = time.perf_counter() - t0
+    ex.close()
+    ctx.close()
+    log("capacity: batched %.1f requests/s vs one at a time %.1f requests/s" % (n / burst, 1.0 / one))
+    return {"qps_offered": qps, "seconds": seconds, "requests": n, "table_points": n_points,
+            "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
+            "mean_ms": round(st["mean_ms"], 3), "served_requests_per_s": round(n / wall, 1),
+            "batches": len(sizes), "mean_batch": round(float(np.mean(sizes)), 2),
+            "capacity_batched_requests_per_s": round(n / burst, 1),
+            "capacity_one_at_a_time_requests_per_s": round(1.0 / one, 1),
+            "one_at_a_time_sample": k,
+            "mix": "50% selection (star, 8-20000 vertices), 50% join-count (64-40000 Voronoi cells, 4-40 vertices)"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -68,6 +168,10 @@ def main():
     ap.add_argument("--canvas", type=int, nargs=2, default=(0, 0), metavar=("W", "H"))
     ap.add_argument("--cpu-sample", type=int, default=40_000_000,
                     help="points of the prefix timed with the CPU oracle (0 = skip)")
+    ap.add_argument("--serve-seconds", type=float, default=4.0,
+                    help="length of the served Poisson stream (0 = skip the serving leg)")
+    ap.add_argument("--serve-qps", type=float, default=200.0)
+    ap.add_argument("--serve-points", type=int, default=200_000_000)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="before the timed steps, copy a buffer of this many MiB on the device "
                          "(a reference kernel of known traffic for hardware counter runs)")
@@ -158,6 +262,12 @@ def main():
         if not parity:
             raise SystemExit("GPU counts differ from the oracle on the sample")
 
+    serving = None
+    if args.serve_seconds > 0:
+        del dx, dy
+        torch.cuda.empty_cache()
+        serving = serving_leg(args.serve_seconds, args.serve_qps, args.serve_points, 200)
+
     out = {
         "metric": METRIC,
         "value": round(N / (ms_per_step / 1000.0), 1),
@@ -183,6 +293,7 @@ def main():
                    "counts_sum": int(gpu_counts.sum())},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
 

@@ -199,13 +199,23 @@ int spade_table_info(const spade_table *t, int64_t *n, int32_t *grid, int64_t *c
 int spade_batch_build(spade_ctx *ctx, const spade_polys *polys, int32_t nq, const int64_t *qbound,
                       spade_canvas **out);
 
+/* Rasterise a new batch into an existing canvas set (from spade_batch_build
+ * or spade_canvas_build), reusing its device memory where it is large
+ * enough: a serving loop keeps one set per worker and avoids a device
+ * allocation and free per batch.  Arguments as for spade_batch_build.  The
+ * set must not be in use by queued work; after a failure it holds no valid
+ * canvas (rebuild or destroy it). */
+int spade_batch_rebuild(spade_ctx *ctx, const spade_polys *polys, int32_t nq, const int64_t *qbound,
+                        spade_canvas *set);
+
 /* Selection for every query of a batch (each query must hold exactly one
  * polygon), over a table: the ids of the table points inside, ascending
  * within each query, queries one after another in out_ids [cap] (device).
  * out_off [nq + 1] (host) receives each query's start; out_off[nq] is the
  * total.  If the total exceeds cap, nothing is written to out_ids and
  * SPADE_E_CAPACITY is returned with out_off filled.  Evaluated with the
- * paper's two-step Map (Sec. 5.1): a count pass, then a write pass. */
+ * paper's two-step Map (Sec. 5.1): a count pass, then a write pass.  At most
+ * 2^31 - 1 selected points per batch (SPADE_E_UNSUPPORTED beyond). */
 int spade_batch_select(spade_ctx *ctx, const spade_canvas *set, const spade_table *t,
                        uint32_t *out_ids, int64_t cap, int64_t *out_off);
 

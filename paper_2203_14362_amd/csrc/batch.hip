@@ -234,16 +234,16 @@ struct SetArgs {
 
 // ------------------------------------------------------------ batch select
 
-// Pass 1 (EMIT = false): matches per pair into pcount.  Pass 2 (EMIT): ids
-// of the matching points from pbase[pair] on, in an order the per-query
-// sort that follows makes ascending.
+// Pass 1 (EMIT = false): matches per pair into pcount.  Pass 2 (EMIT): the
+// keys (query << 32 | point id) of the matching points from pbase[pair] on,
+// in an order the key sort that follows makes ascending.
 template <bool EMIT>
 __global__ __launch_bounds__(BT_THREADS) void k_batch_select(SetArgs S, int64_t nfin, int64_t nchunk,
                                                              const double *X, const double *Y,
                                                              const uint32_t *ids, const unsigned int *cbase,
                                                              const uint32_t *plist, const uint32_t *pq,
                                                              uint32_t *pcount, const unsigned long long *pbase,
-                                                             uint32_t *out)
+                                                             unsigned long long *out)
 {
     __shared__ uint32_t wsum[BT_THREADS / 64];
     for (int64_t c = blockIdx.x; c < nchunk; c += gridDim.x) {
@@ -257,7 +257,8 @@ __global__ __launch_bounds__(BT_THREADS) void k_batch_select(SetArgs S, int64_t 
         }
         for (uint32_t t = cbase[c]; t < cbase[c + 1]; ++t) {
             const uint32_t p = plist[t];
-            const CanvasDesc d = S.cds[pq[p]];
+            const uint32_t qy = pq[p];
+            const CanvasDesc d = S.cds[qy];
             const CanvasView v = set_view(d, S.cells, S.coarse, S.desc, S.bpix, S.cands, S.ledges, S.pspan);
             uint32_t hit = 0;
 #pragma unroll
@@ -301,7 +302,8 @@ __global__ __launch_bounds__(BT_THREADS) void k_batch_select(SetArgs S, int64_t 
                 unsigned long long pos = pbase[p] + pre + inc - cnt;
 #pragma unroll
                 for (int u = 0; u < BT_PER; ++u)
-                    if (hit & (1u << u)) out[pos++] = ids[b + (int64_t)u * BT_THREADS + threadIdx.x];
+                    if (hit & (1u << u))
+                        out[pos++] = ((unsigned long long)qy << 32) | ids[b + (int64_t)u * BT_THREADS + threadIdx.x];
             }
         }
     }
@@ -379,6 +381,12 @@ __global__ __launch_bounds__(BT_THREADS) void k_batch_count(SetArgs S, int64_t n
     }
 }
 
+__global__ void k_low32(int64_t n, const unsigned long long *k, uint32_t *out)
+{
+    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += nth) out[i] = (uint32_t)k[i];
+}
+
 __global__ void k_zero64(int64_t n, unsigned long long *p)
 {
     const int64_t nth = (int64_t)gridDim.x * blockDim.x;
@@ -438,7 +446,7 @@ static int make_pairs(spade_ctx *ctx, const spade_canvas *set, const spade_table
     SPADE_HIP(ctx, hipMemcpyAsync(h, qbase + nq, 8, hipMemcpyDeviceToHost, st));
     SPADE_HIP(ctx, hipStreamSynchronize(st));
     const int64_t np = (int64_t)h[0];
-    if (np >= 0xffffffffLL) return set_error(ctx, SPADE_E_UNSUPPORTED, "too many (chunk, query) pairs in one batch");
+    if (np >= (int64_t)INT32_MAX) return set_error(ctx, SPADE_E_UNSUPPORTED, "too many (chunk, query) pairs in one batch");
     DevBuf &bp = ctx->scratch[S_VALS];
     if (ensure(ctx, bp, sizeof(uint32_t) * 3 * (size_t)std::max<int64_t>(np, 1))) return SPADE_E_NOMEM;
     P.np = np;
@@ -587,11 +595,8 @@ int spade_table_info(const spade_table *t, int64_t *n, int32_t *grid, int64_t *c
     return SPADE_OK;
 }
 
-int spade_batch_build(spade_ctx *ctx, const spade_polys *polys, int32_t nq, const int64_t *qbound,
-                      spade_canvas **out)
+static int check_batch_args(spade_ctx *ctx, const spade_polys *polys, int32_t nq, const int64_t *qbound)
 {
-    if (!ctx || !out) return SPADE_E_INVALID;
-    *out = nullptr;
     ctx->err.clear();
     if (hipSetDevice(ctx->device) != hipSuccess) return set_error(ctx, SPADE_E_HIP, "hipSetDevice failed");
     if (!polys || nq < 1 || !qbound) return set_error(ctx, SPADE_E_INVALID, "a batch needs polygons and nq >= 1 queries");
@@ -602,6 +607,16 @@ int spade_batch_build(spade_ctx *ctx, const spade_polys *polys, int32_t nq, cons
     if (qbound[0] != 0 || qbound[nq] != polys->n_polys) return set_error(ctx, SPADE_E_INVALID, "qbound must run from 0 to n_polys");
     for (int q = 0; q < nq; ++q)
         if (qbound[q + 1] < qbound[q]) return set_error(ctx, SPADE_E_INVALID, "qbound must be non-decreasing");
+    return SPADE_OK;
+}
+
+int spade_batch_build(spade_ctx *ctx, const spade_polys *polys, int32_t nq, const int64_t *qbound,
+                      spade_canvas **out)
+{
+    if (!ctx || !out) return SPADE_E_INVALID;
+    *out = nullptr;
+    int rc0 = check_batch_args(ctx, polys, nq, qbound);
+    if (rc0) return rc0;
     spade_canvas *cv = new (std::nothrow) spade_canvas();
     if (!cv) return set_error(ctx, SPADE_E_NOMEM, "host allocation failed");
     cv->device = ctx->device;
@@ -612,6 +627,17 @@ int spade_batch_build(spade_ctx *ctx, const spade_polys *polys, int32_t nq, cons
     }
     *out = cv;
     return SPADE_OK;
+}
+
+int spade_batch_rebuild(spade_ctx *ctx, const spade_polys *polys, int32_t nq, const int64_t *qbound,
+                        spade_canvas *set)
+{
+    if (!ctx || !set) return ctx ? set_error(ctx, SPADE_E_INVALID, "NULL argument") : SPADE_E_INVALID;
+    int rc = check_batch_args(ctx, polys, nq, qbound);
+    if (rc) return rc;
+    if (set->device != ctx->device) return set_error(ctx, SPADE_E_INVALID, "the canvas set lives on another device");
+    if (set == ctx->plain) return set_error(ctx, SPADE_E_INVALID, "not a caller-owned canvas set");
+    return build_set(ctx, polys, nq, qbound, set);
 }
 
 int spade_batch_select(spade_ctx *ctx, const spade_canvas *set, const spade_table *t, uint32_t *out_ids, int64_t cap,
@@ -663,21 +689,30 @@ int spade_batch_select(spade_ctx *ctx, const spade_canvas *set, const spade_tabl
     SPADE_HIP(ctx, hipStreamSynchronize(st));
     for (int q = 0; q <= nq; ++q) out_off[q] = (int64_t)h[q];
     if ((int64_t)total > cap) return set_error(ctx, SPADE_E_CAPACITY, "output capacity too small");
+    if (total > (unsigned long long)INT32_MAX)
+        return set_error(ctx, SPADE_E_UNSUPPORTED, "more than 2^31 - 1 selected points in one batch; split the batch");
     if (total == 0) {
         if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[3], st));
         return SPADE_OK;
     }
-    if (ensure(ctx, bo, sizeof(uint32_t) * (size_t)total)) return SPADE_E_NOMEM;
+    DevBuf &bo2 = ctx->scratch[S_ENTF];
+    if (ensure(ctx, bo, 8 * (size_t)total) || ensure(ctx, bo2, 8 * (size_t)total)) return SPADE_E_NOMEM;
     hipLaunchKernelGGL(k_batch_select<true>, dim3(grid), dim3(BT_THREADS), 0, st, S, t->nfin, t->nchunk,
                        (const double *)t->x.p, (const double *)t->y.p, (const uint32_t *)t->ids.p, P.cbase, P.plist,
-                       P.pq, nullptr, (const unsigned long long *)pbase, (uint32_t *)bo.p);
+                       P.pq, nullptr, (const unsigned long long *)pbase, (unsigned long long *)bo.p);
     SPADE_HIP(ctx, hipGetLastError());
+    // one radix sort of (query, id) keys orders the ids inside every query
+    // (a per-segment sort would give a whole query to one workgroup)
+    const int kbits = 32 + std::max(1, bits_of((uint64_t)(nq - 1)));
     tb = 0;
-    SPADE_HIP(ctx, hipcub::DeviceSegmentedRadixSort::SortKeys(nullptr, tb, (const uint32_t *)bo.p, out_ids, (int)total,
-                                                              nq, qoff, qoff + 1, 0, 32, st));
+    SPADE_HIP(ctx, hipcub::DeviceRadixSort::SortKeys(nullptr, tb, (const unsigned long long *)bo.p,
+                                                     (unsigned long long *)bo2.p, (int)total, 0, kbits, st));
     if (ensure(ctx, cub, tb)) return SPADE_E_NOMEM;
-    SPADE_HIP(ctx, hipcub::DeviceSegmentedRadixSort::SortKeys(cub.p, tb, (const uint32_t *)bo.p, out_ids, (int)total,
-                                                              nq, qoff, qoff + 1, 0, 32, st));
+    SPADE_HIP(ctx, hipcub::DeviceRadixSort::SortKeys(cub.p, tb, (const unsigned long long *)bo.p,
+                                                     (unsigned long long *)bo2.p, (int)total, 0, kbits, st));
+    hipLaunchKernelGGL(k_low32, dim3(grid_of((int64_t)total)), dim3(256), 0, st, (int64_t)total,
+                       (const unsigned long long *)bo2.p, out_ids);
+    SPADE_HIP(ctx, hipGetLastError());
     if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[3], st));
     SPADE_HIP(ctx, hipStreamSynchronize(st));
     return SPADE_OK;

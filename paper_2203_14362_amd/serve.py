@@ -1,0 +1,343 @@
+"""Continuous-batching query server over a device-resident point table.
+
+Requests (a selection with one polygon, or a join-count with a polygon set)
+arrive at any time.  A dispatcher admits them in arrival order while their
+estimated device memory fits the budget left by the requests in flight, and
+hands each admitted group to the next free worker as one batch; requests
+that arrive while batches are running join the next batch (continuous
+batching).  Each worker owns a library context on its own HIP stream, so
+the batches of different workers overlap on the device.  Every request
+records its arrival, admission and completion times; ``latency_stats``
+reports p50 / p99 from arrival to result-ready.
+
+The scheduling logic is independent of the device: ``Server`` drives any
+executor with ``n_workers``, ``estimate(req)`` and ``run(worker, reqs)``.
+``SpadeExecutor`` is the device executor: one canvas set per batch and kind,
+evaluated with the library's batch calls over the shared resident table.
+"""
+from __future__ import annotations
+
+import collections
+import threading
+import time
+from dataclasses import dataclass
+from typing import Any, List, Optional
+
+import numpy as np
+
+
+@dataclass
+class Request:
+    rid: int
+    kind: str                      # "select" (one polygon) or "count"
+    polys: dict                    # host CSR polygon set
+    arrival: Optional[float] = None
+    admitted: Optional[float] = None
+    done: Optional[float] = None
+    batch: Optional[int] = None
+    worker: Optional[int] = None
+    est_bytes: int = 0
+    result: Any = None             # select: int32 ids; count: int64 counts
+    error: Optional[str] = None
+
+    @property
+    def latency(self) -> Optional[float]:
+        return None if self.done is None or self.arrival is None else self.done - self.arrival
+
+
+def n_vertices(polys) -> int:
+    return int(np.asarray(polys["ring_vtx_off"])[-1])
+
+
+def concat_sets(sets):
+    """One CSR polygon set holding `sets` one after another, and the
+    polygon offsets of each input set ([len(sets) + 1])."""
+    pro, rvo, vx, vy = [np.zeros(1, np.int64)], [np.zeros(1, np.int64)], [], []
+    bounds = [0]
+    nr = nv = npoly = 0
+    for p in sets:
+        r = np.asarray(p["ring_vtx_off"], dtype=np.int64)
+        m = int(p["n_polys"])
+        pr = p.get("poly_ring_off")
+        pr = np.arange(m + 1, dtype=np.int64) if pr is None else np.asarray(pr, dtype=np.int64)
+        pro.append(pr[1:] + nr)
+        rvo.append(r[1:] + nv)
+        vx.append(np.asarray(p["vx"], dtype=np.float64))
+        vy.append(np.asarray(p["vy"], dtype=np.float64))
+        nr += r.size - 1
+        nv += int(r[-1])
+        npoly += m
+        bounds.append(npoly)
+    out = {"n_polys": npoly, "poly_ring_off": np.concatenate(pro), "ring_vtx_off": np.concatenate(rvo),
+           "vx": np.concatenate(vx) if vx else np.zeros(0), "vy": np.concatenate(vy) if vy else np.zeros(0)}
+    return out, np.asarray(bounds, dtype=np.int64)
+
+
+class Server:
+    """Arrival-ordered admission by memory budget + continuous batching."""
+
+    def __init__(self, executor, budget_bytes: int, max_batch: int = 1024,
+                 max_batch_vertices: int = 8_000_000, clock=time.perf_counter):
+        self.ex = executor
+        self.budget = int(budget_bytes)
+        self.max_batch = max_batch
+        self.max_batch_vertices = max_batch_vertices
+        self.clock = clock
+        self._cv = threading.Condition()
+        self._pending = collections.deque()
+        self._free = list(range(executor.n_workers))
+        self._reserved = 0
+        self._peak_reserved = 0
+        self._inflight = 0
+        self._stop = False
+        self._nbatch = 0
+        self._work = [collections.deque() for _ in range(executor.n_workers)]
+        self.done: List[Request] = []
+        self.batches: List[List[int]] = []
+        self._threads = []
+
+    # -- public
+    def start(self):
+        self._threads = [threading.Thread(target=self._dispatch, daemon=True)]
+        self._threads += [threading.Thread(target=self._worker, args=(w,), daemon=True)
+                          for w in range(self.ex.n_workers)]
+        for t in self._threads:
+            t.start()
+        return self
+
+    def submit(self, req: Request):
+        if req.arrival is None:
+            req.arrival = self.clock()
+        req.est_bytes = int(self.ex.estimate(req))
+        with self._cv:
+            self._pending.append(req)
+            self._cv.notify_all()
+
+    def drain(self, timeout: float = None):
+        """Wait until every submitted request has completed."""
+        t_end = None if timeout is None else time.monotonic() + timeout
+        with self._cv:
+            while self._pending or self._inflight:
+                left = None if t_end is None else t_end - time.monotonic()
+                if left is not None and left <= 0:
+                    raise TimeoutError("requests still pending")
+                self._cv.wait(left)
+
+    def stop(self):
+        """Finish every submitted request, then end the threads."""
+        self.drain()
+        with self._cv:
+            self._stop = True
+            self._cv.notify_all()
+        for t in self._threads:
+            t.join()
+
+    @property
+    def peak_reserved(self) -> int:
+        return self._peak_reserved
+
+    # -- internals
+    def _take_batch(self):
+        """Requests admitted now, in arrival order (caller holds the lock)."""
+        batch, verts, extra = [], 0, 0
+        while self._pending and len(batch) < self.max_batch:
+            r = self._pending[0]
+            if r.est_bytes > self.budget:
+                self._pending.popleft()
+                r.error = "request needs about %d device bytes, above the budget of %d" % (r.est_bytes, self.budget)
+                r.done = self.clock()
+                self.done.append(r)
+                continue
+            v = n_vertices(r.polys)
+            if self._reserved + extra + r.est_bytes > self.budget:
+                break                      # head waits for memory: no overtaking
+            if batch and verts + v > self.max_batch_vertices:
+                break
+            self._pending.popleft()
+            batch.append(r)
+            verts += v
+            extra += r.est_bytes
+        return batch, extra
+
+    def _dispatch(self):
+        with self._cv:
+            while True:
+                if self._free and self._pending:
+                    batch, extra = self._take_batch()
+                    self._cv.notify_all()      # rejected requests may complete a drain
+                    if batch:
+                        self._launch(batch, extra)
+                        continue
+                    # the head waits for memory held by batches in flight (with
+                    # nothing in flight the head always fits: its estimate was
+                    # checked against the whole budget)
+                if self._stop and not self._pending:
+                    return
+                self._cv.wait()
+
+    def _launch(self, batch, extra):
+        w = self._free.pop(0)
+        now = self.clock()
+        bid = self._nbatch
+        self._nbatch += 1
+        for r in batch:
+            r.admitted, r.batch, r.worker = now, bid, w
+        self._reserved += extra
+        self._peak_reserved = max(self._peak_reserved, self._reserved)
+        self._inflight += len(batch)
+        self.batches.append([r.rid for r in batch])
+        self._work[w].append((batch, extra))
+        self._cv.notify_all()
+
+    def _worker(self, w):
+        while True:
+            with self._cv:
+                while not self._work[w] and not self._stop:
+                    self._cv.wait()
+                if not self._work[w]:
+                    return
+                batch, extra = self._work[w].popleft()
+            try:
+                self.ex.run(w, batch)
+            except Exception as e:          # report per request, keep serving
+                for r in batch:
+                    r.error = "%s: %s" % (type(e).__name__, e)
+            t = self.clock()
+            with self._cv:
+                for r in batch:
+                    r.done = t
+                    self.done.append(r)
+                self._reserved -= extra
+                self._inflight -= len(batch)
+                self._free.append(w)
+                self._cv.notify_all()
+
+
+def replay(server: Server, requests, arrivals, clock=time.perf_counter, sleep=time.sleep):
+    """Submit requests at their arrival offsets (seconds from now), then wait
+    for all of them.  Returns the wall time from the first arrival to the
+    last completion."""
+    t0 = clock()
+    for r, a in zip(requests, arrivals):
+        dt = t0 + a - clock()
+        if dt > 0:
+            sleep(dt)
+        r.arrival = t0 + a
+        server.submit(r)
+    server.drain()
+    return max(r.done for r in requests) - t0
+
+
+def latency_stats(requests):
+    lat = np.array([r.latency for r in requests if r.latency is not None and r.error is None])
+    if lat.size == 0:
+        return {"n": 0}
+    return {"n": int(lat.size), "p50_ms": float(np.percentile(lat, 50) * 1e3),
+            "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3),
+            "max_ms": float(lat.max() * 1e3)}
+
+
+class SpadeExecutor:
+    """Device executor: workers with their own context and stream over one
+    resident table.  A batch becomes at most two canvas sets (its selections,
+    its join-counts) evaluated with the library's batch calls."""
+
+    def __init__(self, x, y, n_workers: int = 2, device: int = 0, pixels_per_vertex: float = None):
+        import torch
+        from .spade import Context
+        self.torch = torch
+        self.n_workers = n_workers
+        self.device = torch.device("cuda", device)
+        self.streams = [torch.cuda.Stream(self.device) for _ in range(n_workers)]
+        self.ctxs = []
+        for s in self.streams:
+            with torch.cuda.stream(s):
+                c = Context(device)
+                if pixels_per_vertex:
+                    c.set_pixels_per_vertex(pixels_per_vertex)
+                self.ctxs.append(c)
+        self.ppv = pixels_per_vertex or 256.0
+        self._sets = [[None, None] for _ in range(n_workers)]
+        with torch.cuda.stream(self.streams[0]):
+            self.table = self.ctxs[0].table(x, y)
+        self.streams[0].synchronize()
+        # coarse point histogram for output-size estimates
+        self.n_points = int(x.numel())
+        fin = torch.isfinite(x) & torch.isfinite(y)
+        if self.n_points and bool(fin.any()):
+            xf, yf = x[fin], y[fin]
+            self.ext = (float(xf.min()), float(xf.max()), float(yf.min()), float(yf.max()))
+            G = 128
+            gx = ((xf - self.ext[0]) / max(self.ext[1] - self.ext[0], 1e-300) * G).clamp(0, G - 1).long()
+            gy = ((yf - self.ext[2]) / max(self.ext[3] - self.ext[2], 1e-300) * G).clamp(0, G - 1).long()
+            h = torch.bincount(gy * G + gx, minlength=G * G).reshape(G, G).cpu().numpy()
+            self.hist = np.cumsum(np.cumsum(h, 0), 1)   # 2-D prefix sums
+            self.G = G
+        else:
+            self.hist = None
+        torch.cuda.synchronize(self.device)
+
+    def _points_in_box(self, x0, x1, y0, y1) -> int:
+        if self.hist is None:
+            return 0
+        X0, X1, Y0, Y1 = self.ext
+        G = self.G
+        c0 = int(np.clip(np.floor((x0 - X0) / max(X1 - X0, 1e-300) * G), 0, G - 1))
+        c1 = int(np.clip(np.floor((x1 - X0) / max(X1 - X0, 1e-300) * G), 0, G - 1))
+        r0 = int(np.clip(np.floor((y0 - Y0) / max(Y1 - Y0, 1e-300) * G), 0, G - 1))
+        r1 = int(np.clip(np.floor((y1 - Y0) / max(Y1 - Y0, 1e-300) * G), 0, G - 1))
+        H = self.hist
+        tot = H[r1, c1]
+        if r0 > 0:
+            tot -= H[r0 - 1, c1]
+        if c0 > 0:
+            tot -= H[r1, c0 - 1]
+        if r0 > 0 and c0 > 0:
+            tot += H[r0 - 1, c0 - 1]
+        return int(tot)
+
+    def estimate(self, req: Request) -> int:
+        """Device bytes a request holds while in flight (upper estimate):
+        canvas words, coarse level and boundary index (about three words per
+        pixel), edges and their row entries, outputs."""
+        V = n_vertices(req.polys)
+        px = min(max(self.ppv * V, 64 * 64), 4096 * 4096)
+        b = 12 * px + 160 * V + (1 << 20)
+        if req.kind == "select":
+            if V:
+                vx, vy = np.asarray(req.polys["vx"]), np.asarray(req.polys["vy"])
+                b += 4 * self._points_in_box(vx.min(), vx.max(), vy.min(), vy.max())
+        else:
+            b += 8 * int(req.polys["n_polys"])
+        return int(b)
+
+    def run(self, w: int, reqs: List[Request]):
+        torch = self.torch
+        ctx, s = self.ctxs[w], self.streams[w]
+        with torch.cuda.stream(s):
+            sel = [r for r in reqs if r.kind == "select"]
+            cnt = [r for r in reqs if r.kind == "count"]
+            # one canvas set per worker and kind, rebuilt in place: no device
+            # allocation or free (which would synchronise the device) per batch
+            if sel:
+                polys, qb = concat_sets([r.polys for r in sel])
+                b = self._sets[w][0] = ctx.batch(polys, qb, into=self._sets[w][0])
+                ids, off = ctx.batch_select(b, self.table)
+                for q, r in enumerate(sel):
+                    r.result = ids[int(off[q]):int(off[q + 1])]
+            if cnt:
+                polys, qb = concat_sets([r.polys for r in cnt])
+                b = self._sets[w][1] = ctx.batch(polys, qb, into=self._sets[w][1])
+                counts = ctx.batch_join_count(b, self.table)
+                for q, r in enumerate(cnt):
+                    r.result = counts[int(qb[q]):int(qb[q + 1])]
+        s.synchronize()
+
+    def close(self):
+        for pair in self._sets:
+            for b in pair:
+                if b is not None:
+                    b.close()
+        self.table.close()
+        for c in self.ctxs:
+            c.close()

@@ -36,6 +36,7 @@ EXPORTS = [
     "spade_orient_batch", "spade_ctx_set_timing", "spade_ctx_last_timing",
     "spade_table_create", "spade_table_destroy", "spade_table_info", "spade_batch_build",
     "spade_batch_select", "spade_batch_join_count", "spade_ctx_set_pixels_per_vertex",
+    "spade_batch_rebuild",
 ]
 
 
@@ -94,6 +95,7 @@ def load_library():
     lib.spade_table_destroy.restype = None
     lib.spade_table_info.argtypes = [vp, P(i64), P(i32), P(i64), P(i64)]
     lib.spade_batch_build.argtypes = [vp, P(_Polys), i32, vp, P(vp)]
+    lib.spade_batch_rebuild.argtypes = [vp, P(_Polys), i32, vp, vp]
     lib.spade_batch_select.argtypes = [vp, vp, vp, vp, i64, vp]
     lib.spade_batch_join_count.argtypes = [vp, vp, vp, vp]
     lib.spade_ctx_set_pixels_per_vertex.argtypes = [vp, ctypes.c_double]
@@ -264,11 +266,20 @@ class Context:
         self._check(self.lib.spade_table_create(self.handle, ctypes.byref(P), ctypes.byref(h)))
         return Table(self, h)
 
-    def batch(self, polys, qbound) -> Batch:
-        """Rasterise queries [qbound[q], qbound[q+1]) of ``polys`` as one canvas set."""
+    def batch(self, polys, qbound, into: "Batch" = None) -> Batch:
+        """Rasterise queries [qbound[q], qbound[q+1]) of ``polys`` as one canvas
+        set (into the memory of an existing set ``into`` when given)."""
         self._sync_stream()
         dp = self.polys(polys)
         qb = np.ascontiguousarray(qbound, dtype=np.int64)
+        if into is not None:
+            rc = self.lib.spade_batch_rebuild(self.handle, ctypes.byref(dp.cstruct()), int(qb.size - 1),
+                                              qb.ctypes.data_as(ctypes.c_void_p), into.handle)
+            if rc != SPADE_OK:
+                into.close()
+                self._check(rc)
+            into.qbound, into.n_queries, into.n_polys = qb, int(qb.size - 1), int(qb[-1])
+            return into
         h = ctypes.c_void_p()
         self._check(self.lib.spade_batch_build(self.handle, ctypes.byref(dp.cstruct()), int(qb.size - 1),
                                                qb.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h)))

@@ -1,0 +1,72 @@
+"""The query server on the device: every served result equals the same
+request evaluated alone (plain single-query call on the original arrays),
+and a sample of them equals the CPU oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from workloads import gen
+
+pytestmark = pytest.mark.gpu
+
+L = gen.EXTENT_M
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def _mixed_requests(n, seed, tess):
+    from paper_2203_14362_amd.serve import Request
+    rng = np.random.default_rng(seed)
+    stars, _ = gen.query_stars(n, 8, 2000, seed=seed, L=L, area=(1e-4, 1e-2), data_seed=3)
+    rvo = stars["ring_vtx_off"]
+    M = tess["n_polys"]
+    trvo = tess["ring_vtx_off"]
+    reqs = []
+    for i in range(n):
+        if i % 2 == 0:
+            p = {"n_polys": 1, "poly_ring_off": None, "ring_vtx_off": np.array([0, rvo[i + 1] - rvo[i]]),
+                 "vx": stars["vx"][rvo[i]:rvo[i + 1]], "vy": stars["vy"][rvo[i]:rvo[i + 1]]}
+            reqs.append(Request(i, "select", p))
+        else:
+            m = int(np.exp(rng.uniform(np.log(16), np.log(M))))
+            ks = np.sort(rng.choice(M, m, replace=False))
+            rings = [[np.stack([tess["vx"][trvo[k]:trvo[k + 1]], tess["vy"][trvo[k]:trvo[k + 1]]], 1)] for k in ks]
+            reqs.append(Request(i, "count", gen.polys_from_rings(rings)))
+    return reqs
+
+
+def test_served_equals_alone(ctx):
+    from paper_2203_14362_amd.serve import SpadeExecutor, Server, latency_stats, replay
+    x, y = gen.mixture_points(2_000_000, seed=3, L=L)
+    tess = gen.voronoi_jitter(600, 4, 40, seed=9, L=L)
+    reqs = _mixed_requests(60, 21, tess)
+    dx, dy = _dev(x), _dev(y)
+    ex = SpadeExecutor(dx, dy, n_workers=2)
+    free, _ = torch.cuda.mem_get_info()
+    srv = Server(ex, budget_bytes=free // 2).start()
+    arrivals = gen.poisson_arrivals(200.0, 10.0, seed=7)[:len(reqs)]
+    replay(srv, reqs, arrivals)
+    srv.stop()
+    assert all(r.error is None for r in reqs), [r.error for r in reqs if r.error][:3]
+    assert max(len(b) for b in srv.batches) >= 1
+    st = latency_stats(reqs)
+    assert st["n"] == len(reqs)
+    for r in reqs:
+        if r.kind == "select":
+            alone = ctx.select(dx, dy, r.polys)
+            assert torch.equal(r.result.cpu(), alone.cpu()), r.rid
+        else:
+            alone = ctx.join_count(dx, dy, r.polys)
+            assert torch.equal(r.result.cpu(), alone.cpu()), r.rid
+    # a sample against the oracle
+    for r in reqs[:6]:
+        if r.kind == "select":
+            want = oracle.select(x, y, r.polys)
+            assert np.array_equal(r.result.cpu().numpy().astype(np.int64).astype(np.uint32), want)
+        else:
+            want = oracle.join_count(x, y, r.polys)
+            assert np.array_equal(r.result.cpu().numpy().astype(np.uint64), want)
+    ex.close()
