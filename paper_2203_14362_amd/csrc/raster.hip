@@ -398,7 +398,14 @@ struct RowShared {
     uint32_t *sx;       // claimant xor -> pixel class
     uint32_t *locfill;  // row-local fill counter of the local-edge array
     uint32_t *nint;     // number of footprint-union intervals of the row
+    uint32_t *nlong;    // long runs deferred to whole waves, and their starts
+    uint32_t *longq;
 };
+
+// Runs longer than this are processed by a whole wave (lane-parallel scans)
+// instead of one thread; up to LONGQ of them per row, the rest serially.
+constexpr int LONG_RUN = 24;
+constexpr int LONGQ = 64;
 
 __device__ __forceinline__ size_t tile_index(int Wt, int c, int r)
 {
@@ -576,6 +583,145 @@ __host__ __device__ inline size_t row_lds_bytes(int W, int cap)
     return (size_t)3 * col_words(W) * 4 + (size_t)cap * 37 + 32;
 }
 
+// Phase 1 for one run by one thread: footprint counts, interior spans with
+// their claimant xor, running footprint maxima, footprint-union intervals.
+__device__ void run_serial(const RowData &D, const RowShared &L, int i, int je, int W)
+{
+    const uint32_t lab = D.poly[i] + 1;
+    uint32_t wtot = 0;
+    for (int q = i; q < je; ++q) wtot ^= (D.f[q] & F_W) ? 1u : 0u;
+    uint32_t par = wtot;
+    int mx = -1;
+    uint32_t mall = 0, mnh = 0;
+    const int c0first = (int)(D.c[i] & 0xffff);
+    if (par && c0first > 0) {
+        atomicAdd(&L.sb[cix(0)], 1); atomicSub(&L.sb[cix(c0first)], 1);
+        atomicXor(&L.sx[cix(0)], lab); atomicXor(&L.sx[cix(c0first)], lab);
+    }
+    for (int q = i; q < je; ++q) {
+        const uint32_t c = D.c[q];
+        const int c0 = (int)(c & 0xffff), c1 = (int)(c >> 16);
+        const uint8_t f = D.f[q];
+        atomicAdd(&L.sa[cix(c0)], 1);
+        atomicSub(&L.sa[cix(c1 + 1)], 1);
+        mx = max(mx, c1);
+        mall = max(mall, (uint32_t)c1 + 1u);
+        if (!(f & F_HORIZ)) mnh = max(mnh, (uint32_t)c1 + 1u);
+        D.pm[q] = mall | (mnh << 16);
+        if (f & F_W) par ^= 1u;
+        const int nc0 = (q + 1 < je) ? (int)(D.c[q + 1] & 0xffff) : W;
+        const int lo = max(c0, mx + 1), hi = nc0 - 1;
+        if (par && lo <= hi) {
+            atomicAdd(&L.sb[cix(lo)], 1); atomicSub(&L.sb[cix(hi + 1)], 1);
+            atomicXor(&L.sx[cix(lo)], lab); atomicXor(&L.sx[cix(hi + 1)], lab);
+        }
+    }
+    // footprint-union intervals of the run
+    int ulo = c0first, uhi = (int)(D.c[i] >> 16);
+    for (int q = i + 1; q <= je; ++q) {
+        const int c0 = q < je ? (int)(D.c[q] & 0xffff) : W + 1;
+        if (q < je && c0 <= uhi + 1) { uhi = max(uhi, (int)(D.c[q] >> 16)); continue; }
+        const uint32_t j = atomicAdd(L.nint, 1u);
+        D.ihead[j] = (uint32_t)i;
+        D.iend[j] = (uint32_t)je;
+        D.icol[j] = (uint32_t)ulo;
+        D.ilen[j] = (uint32_t)(uhi - ulo + 1);
+        if (q < je) { ulo = c0; uhi = (int)(D.c[q] >> 16); }
+    }
+}
+
+__device__ __forceinline__ int wave_incl_max(int v)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int t = __shfl_up(v, d, 64);
+        if (lane >= d) v = max(v, t);
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_incl_xor(uint32_t v)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t t = __shfl_up(v, d, 64);
+        if (lane >= d) v ^= t;
+    }
+    return v;
+}
+
+// Phase 1 for one long run by a whole wave, 64 entries at a time: the
+// serial recurrences (parity after each entry, running maxima, interval
+// starts) become wave scans with carries between chunks.  Same results as
+// run_serial.
+__device__ void run_wave(const RowData &D, const RowShared &L, int i, int W)
+{
+    const int lane = threadIdx.x & 63;
+    const uint32_t k = D.poly[i];
+    const uint32_t lab = k + 1;
+    int je = D.n;
+    for (int b = i;; b += 64) {
+        const int q = b + lane;
+        const bool same = q < D.n && D.poly[q] == k;
+        const unsigned long long m = __ballot(!same);
+        if (m) { je = b + __ffsll((long long)m) - 1; break; }
+    }
+    uint32_t nw = 0;
+    for (int b = i; b < je; b += 64) {
+        const int q = b + lane;
+        nw += (uint32_t)__popcll(__ballot(q < je && (D.f[q] & F_W)));
+    }
+    const uint32_t wtot = nw & 1u;
+    const int c0first = (int)(D.c[i] & 0xffff);
+    if (lane == 0 && wtot && c0first > 0) {
+        atomicAdd(&L.sb[cix(0)], 1); atomicSub(&L.sb[cix(c0first)], 1);
+        atomicXor(&L.sx[cix(0)], lab); atomicXor(&L.sx[cix(c0first)], lab);
+    }
+    uint32_t par_c = wtot;
+    int mx_c = -1, mall_c = 0, mnh_c = 0, ulo_c = c0first;
+    for (int b = i; b < je; b += 64) {
+        const int q = b + lane;
+        const bool valid = q < je;
+        const uint32_t c = valid ? D.c[q] : 0u;
+        const int c0 = (int)(c & 0xffff), c1 = (int)(c >> 16);
+        const uint8_t f = valid ? D.f[q] : (uint8_t)0;
+        if (valid) { atomicAdd(&L.sa[cix(c0)], 1); atomicSub(&L.sa[cix(c1 + 1)], 1); }
+        const uint32_t par = par_c ^ wave_incl_xor((f & F_W) ? 1u : 0u);
+        const int mxs = wave_incl_max(valid ? c1 : -1);
+        const int mx = max(mx_c, mxs);
+        const int mall = max(mall_c, wave_incl_max(valid ? c1 + 1 : 0));
+        const int mnh = max(mnh_c, wave_incl_max(valid && !(f & F_HORIZ) ? c1 + 1 : 0));
+        if (valid) D.pm[q] = (uint32_t)mall | ((uint32_t)mnh << 16);
+        const int nc0 = (q + 1 < je) ? (int)(D.c[q + 1] & 0xffff) : W;
+        const int lo = max(c0, mx + 1), hi = nc0 - 1;
+        if (valid && par && lo <= hi) {
+            atomicAdd(&L.sb[cix(lo)], 1); atomicSub(&L.sb[cix(hi + 1)], 1);
+            atomicXor(&L.sx[cix(lo)], lab); atomicXor(&L.sx[cix(hi + 1)], lab);
+        }
+        // footprint-union intervals: an entry starts one when it begins more
+        // than a column right of every earlier footprint of the run
+        const int prev = __shfl_up(mxs, 1, 64);
+        const int mx_excl = lane ? max(mx_c, prev) : mx_c;
+        const bool start = valid && (q == i || c0 > mx_excl + 1);
+        const int ulo = max(ulo_c, wave_incl_max(start ? c0 : -1));
+        const bool last = valid && (q + 1 == je || nc0 > mx + 1);
+        if (last) {
+            const uint32_t j = atomicAdd(L.nint, 1u);
+            D.ihead[j] = (uint32_t)i;
+            D.iend[j] = (uint32_t)je;
+            D.icol[j] = (uint32_t)ulo;
+            D.ilen[j] = (uint32_t)(mx - ulo + 1);
+        }
+        par_c = __shfl(par, 63, 64);
+        mx_c = __shfl(mx, 63, 64);
+        mall_c = __shfl(mall, 63, 64);
+        mnh_c = __shfl(mnh, 63, 64);
+        ulo_c = __shfl(ulo, 63, 64);
+    }
+}
+
 template <bool EMIT>
 __device__ void process_row(const RowArgs &A, const RowData &D, const RowShared &L, int64_t r, int W,
                             int Wt, uint32_t *cells_q, int r_local,
@@ -590,48 +736,17 @@ __device__ void process_row(const RowArgs &A, const RowData &D, const RowShared 
     //          partial / spanning indicators to be scanned
     for (int q = tid; q < D.n; q += ROW_THREADS) D.pre[q] = pre_own(D.f[q]);
     for_each_run(D, [&](int i, int je) {
-        const uint32_t lab = D.poly[i] + 1;
-        uint32_t wtot = 0;
-        for (int q = i; q < je; ++q) wtot ^= (D.f[q] & F_W) ? 1u : 0u;
-        uint32_t par = wtot;
-        int mx = -1;
-        uint32_t mall = 0, mnh = 0;
-        const int c0first = (int)(D.c[i] & 0xffff);
-        if (par && c0first > 0) {
-            atomicAdd(&L.sb[cix(0)], 1); atomicSub(&L.sb[cix(c0first)], 1);
-            atomicXor(&L.sx[cix(0)], lab); atomicXor(&L.sx[cix(c0first)], lab);
+        if (je - i > LONG_RUN) {
+            const uint32_t j = atomicAdd(L.nlong, 1u);
+            if (j < (uint32_t)LONGQ) { L.longq[j] = (uint32_t)i; return; }
         }
-        for (int q = i; q < je; ++q) {
-            const uint32_t c = D.c[q];
-            const int c0 = (int)(c & 0xffff), c1 = (int)(c >> 16);
-            const uint8_t f = D.f[q];
-            atomicAdd(&L.sa[cix(c0)], 1);
-            atomicSub(&L.sa[cix(c1 + 1)], 1);
-            mx = max(mx, c1);
-            mall = max(mall, (uint32_t)c1 + 1u);
-            if (!(f & F_HORIZ)) mnh = max(mnh, (uint32_t)c1 + 1u);
-            D.pm[q] = mall | (mnh << 16);
-            if (f & F_W) par ^= 1u;
-            const int nc0 = (q + 1 < je) ? (int)(D.c[q + 1] & 0xffff) : W;
-            const int lo = max(c0, mx + 1), hi = nc0 - 1;
-            if (par && lo <= hi) {
-                atomicAdd(&L.sb[cix(lo)], 1); atomicSub(&L.sb[cix(hi + 1)], 1);
-                atomicXor(&L.sx[cix(lo)], lab); atomicXor(&L.sx[cix(hi + 1)], lab);
-            }
-        }
-        // footprint-union intervals of the run
-        int ulo = c0first, uhi = (int)(D.c[i] >> 16);
-        for (int q = i + 1; q <= je; ++q) {
-            const int c0 = q < je ? (int)(D.c[q] & 0xffff) : W + 1;
-            if (q < je && c0 <= uhi + 1) { uhi = max(uhi, (int)(D.c[q] >> 16)); continue; }
-            const uint32_t j = atomicAdd(L.nint, 1u);
-            D.ihead[j] = (uint32_t)i;
-            D.iend[j] = (uint32_t)je;
-            D.icol[j] = (uint32_t)ulo;
-            D.ilen[j] = (uint32_t)(uhi - ulo + 1);
-            if (q < je) { ulo = c0; uhi = (int)(D.c[q] >> 16); }
-        }
+        run_serial(D, L, i, je, W);
     });
+    __syncthreads();
+    {
+        const uint32_t nl = min(*L.nlong, (uint32_t)LONGQ);
+        for (uint32_t k = (uint32_t)(tid >> 6); k < nl; k += ROW_THREADS / 64) run_wave(D, L, (int)L.longq[k], W);
+    }
     __syncthreads();
 
     // phase 2: prefix scans -> per-pixel boundary count, claim count,
@@ -777,7 +892,8 @@ __global__ __launch_bounds__(ROW_THREADS) void k_rows(RowArgs A)
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int32_t wtoti[ROW_THREADS / 64];
     __shared__ uint32_t wtotu[ROW_THREADS / 64];
-    __shared__ uint32_t s_locfill, s_nint, s_nbp, s_multi;
+    __shared__ uint32_t s_locfill, s_nint, s_nbp, s_multi, s_nlong;
+    __shared__ uint32_t s_longq[LONGQ];
     __shared__ unsigned long long s_nloc, s_nrec, s_base[4];
     const int cap = A.cap;
     const int cwmax = col_words(A.maxW);
@@ -787,6 +903,8 @@ __global__ __launch_bounds__(ROW_THREADS) void k_rows(RowArgs A)
     L.sx = (uint32_t *)(L.sb + cwmax);
     L.locfill = &s_locfill;
     L.nint = &s_nint;
+    L.nlong = &s_nlong;
+    L.longq = s_longq;
     uint32_t *lpoly = L.sx + cwmax;
     uint32_t *lc = lpoly + cap;
     uint32_t *ledge = lc + cap;
@@ -817,7 +935,7 @@ __global__ __launch_bounds__(ROW_THREADS) void k_rows(RowArgs A)
             }
         }
         for (int c = tid; c < cw; c += ROW_THREADS) { L.sa[c] = 0; L.sb[c] = 0; L.sx[c] = 0; }
-        if (tid == 0) { s_locfill = 0; s_nint = 0; s_nbp = 0; s_multi = 0; s_nloc = 0; s_nrec = 0; }
+        if (tid == 0) { s_locfill = 0; s_nint = 0; s_nbp = 0; s_multi = 0; s_nloc = 0; s_nrec = 0; s_nlong = 0; }
         __syncthreads();
         if (n <= cap) {
             const RowData D{lpoly, lc, lf, ledge, lpm, lpre, lih, lie, lic, lil, n};

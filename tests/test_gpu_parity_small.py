@@ -76,6 +76,24 @@ def test_resolution_invariance(ctx, c1, wh):
     assert np.array_equal(got, oracle.join_count(x, y, polys))
 
 
+@pytest.mark.parametrize("wh", [(512, 1), (300, 2), (4096, 3)])
+def test_long_runs_in_few_rows(ctx, wh):
+    """Few canvas rows put whole polygons into one row: long runs of entries
+    (processed by whole waves) and more of them than the per-row wave queue
+    holds (the rest processed serially)."""
+    x, y = gen.uniform_points(50_000, seed=31)
+    polys = gen.voronoi_jitter(100, 30, 90, seed=31, L=1.0)
+    ctx.set_canvas_size(*wh)
+    try:
+        got = ctx.join_count(_dev(x), _dev(y), polys).cpu().numpy().astype(np.uint64)
+        pt, pg = ctx.join_pairs(_dev(x), _dev(y), polys)
+    finally:
+        ctx.set_canvas_size(0, 0)
+    assert np.array_equal(got, oracle.join_count(x, y, polys))
+    opt, opg = oracle.join_pairs(x, y, polys)
+    assert np.array_equal(_u32(pt), opt) and np.array_equal(_u32(pg), opg)
+
+
 def test_lattice_rectangles_gpu(ctx):
     h = 2.0 ** -6
     x, y = gen.lattice_points(130, 130, h, x0=-h, y0=-h)
