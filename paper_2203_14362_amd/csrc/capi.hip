@@ -141,7 +141,6 @@ void spade_ctx_destroy(spade_ctx *ctx)
         free_buf(ctx->plain->coarse);
         free_buf(ctx->plain->dcds);
         free_buf(ctx->plain->desc);
-        free_buf(ctx->plain->bpix);
         delete ctx->plain;
     }
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
@@ -229,7 +228,6 @@ void spade_canvas_destroy(spade_canvas *cv)
     free_buf(cv->coarse);
     free_buf(cv->dcds);
     free_buf(cv->desc);
-    free_buf(cv->bpix);
     delete cv;
 }
 

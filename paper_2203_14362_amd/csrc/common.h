@@ -43,15 +43,15 @@ constexpr uint32_t CAND_LAST = 2u;
 // Coarse canvas word (one per 2^blog x 2^blog block of pixels):
 //   label + 1 (0: in no polygon) when every pixel of the block carries that
 //   same non-boundary canvas word;
-//   COARSE_MIXED | m for a mixed block with compact records m;
+//   COARSE_MIXED for a mixed block, described by compact records;
 //   COARSE_FULL when the block must be read from the full canvas.
-// A mixed block has one 16-byte record per 32 pixels (in pixel order, pixel
-// p of a block at (p mod 2^blog, p div 2^blog)): a 2-bit code per pixel
-// (0, 1: palette word 0 or 1, 2: in no polygon, 3: boundary pixel), the
-// boundary-pixel array index of the group's first boundary pixel, and two
-// 16-bit palette canvas words.  The boundary-pixel array holds each boundary
-// pixel's first candidate record.  Blocks with more than two non-zero
-// non-boundary words, or words above 0xffff, are COARSE_FULL.
+// The records of the mixed block with coarse index k (row-major in the
+// coarse grid) start at record k * 2^(2 blog) / 32: one 16-byte record per
+// 32 pixels (in pixel order, pixel p of a block at (p mod 2^blog,
+// p div 2^blog)) holding a 2-bit code per pixel (0, 1: palette word 0 or 1,
+// 2: in no polygon, 3: boundary pixel, whose word is read from the full
+// canvas) and two 16-bit palette canvas words.  Blocks with more than two
+// non-zero non-boundary words, or words above 0xffff, are COARSE_FULL.
 constexpr uint16_t COARSE_MIXED = 0x8000u;
 constexpr uint16_t COARSE_FULL = 0xffffu;
 
@@ -77,7 +77,7 @@ struct CanvasDesc {
     int64_t row_base;             // first global row of the set
     int64_t cell_off;             // first canvas word (tile-major, 16 x 16 tiles)
     int64_t coarse_off;           // first coarse word
-    int64_t desc_off;             // first mixed-block record (in 16-byte units)
+    int64_t desc_off;             // first mixed-block record (16-byte units; Wc * Hc blocks)
 };
 
 // Everything a probe kernel needs, passed by value.
@@ -90,8 +90,7 @@ struct CanvasView {
     int64_t M;                    // number of polygons
     const uint32_t *cells;        // canvas words, tile-major (16 x 16 tiles)
     const uint16_t *coarse;       // Wc * Hc coarse words, row-major
-    const uint4 *desc;            // mixed-block records, 2^(2 blog) / 32 per block
-    const uint32_t *bpix;         // first candidate record of each boundary pixel
+    const uint4 *desc;            // mixed-block records, 2^(2 blog) / 32 per coarse block
     const Cand *cands;
     const Edge *ledges;           // local edges of the records
     const double2 *pspan;         // (ylo, yhi) of partial-right edges
@@ -115,10 +114,10 @@ struct spade_canvas {
     int64_t n_cands = 0;
     int64_t n_elist = 0;
     int64_t n_edges = 0;
-    spade::DevBuf cells, cands, ledges, pspan, edges, coarse, desc, bpix;
+    spade::DevBuf cells, cands, ledges, pspan, edges, coarse, desc;
     size_t bytes() const
     {
-        return cells.cap + cands.cap + ledges.cap + pspan.cap + coarse.cap + desc.cap + bpix.cap;
+        return cells.cap + cands.cap + ledges.cap + pspan.cap + coarse.cap + desc.cap;
     }
 };
 

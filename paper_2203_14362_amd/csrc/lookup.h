@@ -22,8 +22,8 @@ typedef const uint64_t __attribute__((address_space(1))) *gu64p;
 // Canvas lookup state of one point: the word once known, or where to read it.
 struct Look {
     uint32_t word;   // final canvas word when kind == 0
-    uint32_t kind;   // 0: final, 1: mixed-block descriptor, 2: full canvas
-    uint32_t m;      // descriptor index (kind 1)
+    uint32_t kind;   // 0: final, 1: mixed-block records, 2: full canvas
+    uint32_t m;      // coarse block index (kind 1)
     uint32_t pix;    // pixel within its coarse block (kind 1)
     uint32_t fidx;   // full-canvas index (kinds 1 and 2)
 };
@@ -43,7 +43,7 @@ __device__ __forceinline__ Look look_coarse(const CanvasView &cv, const uint16_t
     L.fidx = (uint32_t)tile_index(cv.Wt, c, r);
     if (cw == COARSE_FULL) { L.kind = 2; return L; }
     L.kind = 1;
-    L.m = cw & 0x7fffu;
+    L.m = (uint32_t)((r >> cv.blog) * cv.Wc + (c >> cv.blog));
     const int B = 1 << cv.blog;
     L.pix = (uint32_t)(((r & (B - 1)) << cv.blog) | (c & (B - 1)));
     return L;
@@ -58,8 +58,8 @@ __device__ __forceinline__ uint4 read_group(const CanvasView &cv, const Look &L)
 }
 
 // Level 2: resolve a group record.  Returns true with the final word, or
-// false with `bidx`, the boundary-pixel array index of the pixel.
-__device__ __forceinline__ bool resolve_group(const uint4 &R, Look &L, uint32_t &bidx)
+// false for a boundary pixel (kind becomes 2: read the full canvas).
+__device__ __forceinline__ bool resolve_group(const uint4 &R, Look &L)
 {
     const uint64_t codes = (uint64_t)R.x | ((uint64_t)R.y << 32);
     const uint32_t sh = 2u * (L.pix & 31u);
@@ -69,9 +69,7 @@ __device__ __forceinline__ bool resolve_group(const uint4 &R, Look &L, uint32_t 
         L.kind = 0;
         return true;
     }
-    const uint64_t both = codes & (codes >> 1) & 0x5555555555555555ull;
-    const uint64_t below = sh ? (both & ((1ull << sh) - 1ull)) : 0ull;
-    bidx = R.z + (uint32_t)__popcll(below);
+    L.kind = 2;
     return false;
 }
 
@@ -80,11 +78,7 @@ __device__ __forceinline__ uint32_t lookup(const CanvasView &cv, const uint16_t 
 {
     Look L = look_coarse(cv, coarse, x, y);
     if (L.kind == 0) return L.word;
-    if (L.kind == 1) {
-        uint32_t bidx = 0;
-        if (resolve_group(read_group(cv, L), L, bidx)) return L.word;
-        return BFLAG | ((gu32p)cv.bpix)[bidx];
-    }
+    if (L.kind == 1 && resolve_group(read_group(cv, L), L)) return L.word;
     return ((gu32p)cv.cells)[L.fidx];
 }
 

@@ -120,7 +120,7 @@ __global__ __launch_bounds__(CNT_THREADS) void k_count(CanvasView cv, int64_t n,
         // points of a level before any result is used
         Look lk[CNT_UNROLL];
         uint4 dr[CNT_UNROLL];
-        uint32_t ws[CNT_UNROLL], bidx[CNT_UNROLL];
+        uint32_t ws[CNT_UNROLL];
 #pragma unroll
         for (int u = 0; u < CNT_UNROLL; ++u) lk[u] = look_coarse(cv, coarse, xs[u], ys[u]);
 #pragma unroll
@@ -128,15 +128,12 @@ __global__ __launch_bounds__(CNT_THREADS) void k_count(CanvasView cv, int64_t n,
             if (lk[u].kind == 1) dr[u] = read_group(cv, lk[u]);
 #pragma unroll
         for (int u = 0; u < CNT_UNROLL; ++u) {
-            bidx[u] = 0;
-            if (lk[u].kind == 1) resolve_group(dr[u], lk[u], bidx[u]);
+            if (lk[u].kind == 1) resolve_group(dr[u], lk[u]);
             ws[u] = lk[u].word;
         }
 #pragma unroll
-        for (int u = 0; u < CNT_UNROLL; ++u) {
-            if (lk[u].kind == 1) ws[u] = BFLAG | ((gu32p)cv.bpix)[bidx[u]];
-            else if (lk[u].kind == 2) ws[u] = ((gu32p)cv.cells)[lk[u].fidx];
-        }
+        for (int u = 0; u < CNT_UNROLL; ++u)
+            if (lk[u].kind == 2) ws[u] = ((gu32p)cv.cells)[lk[u].fidx];
 #pragma unroll
         for (int u = 0; u < CNT_UNROLL; ++u) {
             const uint32_t w = ws[u];

@@ -184,14 +184,41 @@ __global__ __launch_bounds__(256) void k_canvas_bbox(int64_t R, const int64_t *r
 
 // ------------------------------------------------------------ edges
 
+// Conservative footprint of an edge in pixel row r: the columns [c0, c1]
+// its part inside the row band, dilated by MARGIN, can touch.  (ulo, vlo)
+// and (uhi, vhi) are the edge's end points in pixel coordinates.
+__device__ __forceinline__ void row_footprint(const CanvasDesc &m, double ulo, double uhi, double vlo, double vhi,
+                                              int32_t r, int32_t &c0, int32_t &c1)
+{
+    const double b0 = (double)r - MARGIN, b1 = (double)r + 1.0 + MARGIN;
+    double xa, xb;
+    if (vlo == vhi) {
+        xa = ulo; xb = uhi;
+    } else {
+        const double dv = vhi - vlo;
+        const double ta = fmin(1.0, fmax(0.0, (b0 - vlo) / dv));
+        const double tb = fmin(1.0, fmax(0.0, (b1 - vlo) / dv));
+        xa = ulo + ta * (uhi - ulo);
+        xb = ulo + tb * (uhi - ulo);
+    }
+    const double xmn = fmin(xa, xb) - SLOP, xmx = fmax(xa, xb) + SLOP;
+    c0 = (int32_t)fmax(0.0, fmin(floor(xmn - MARGIN), (double)(m.W - 1)));
+    c1 = (int32_t)fmax(0.0, fmin(floor(xmx + MARGIN), (double)(m.W - 1)));
+}
+
 __global__ __launch_bounds__(256) void k_edges(int64_t R, const int64_t *rvo, int64_t V,
                                                const double *vx, const double *vy,
                                                const int32_t *ring_poly, const CanvasDesc *cds, int nc,
                                                Edge *edges, uint32_t *epoly, int32_t *erow0,
-                                               uint64_t *nrows)
+                                               uint64_t *nrows, unsigned long long *sumw)
 {
     const int64_t nth = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < V; j += nth) {
+    // every lane runs the same number of iterations (wave sum at the end)
+    const int64_t iters = (V + nth - 1) / nth;
+    unsigned long long wsum = 0;
+    for (int64_t it = 0; it < iters; ++it) {
+        const int64_t j = it * nth + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        if (j >= V) break;
         // ring of vertex j: rvo[r] <= j < rvo[r+1]
         int64_t lo = 0, hi = R;
         while (hi - lo > 1) {
@@ -215,7 +242,17 @@ __global__ __launch_bounds__(256) void k_edges(int64_t R, const int64_t *rvo, in
         int32_t r1 = (int32_t)fmax(0.0, fmin(f1, (double)(m.H - 1)));
         erow0[j] = r0;
         nrows[j] = (uint64_t)(r1 - r0 + 1);
+        // footprint widths over the edge's rows: bounds the boundary index
+        const double ulo = __dmul_rn(__dsub_rn(e.xlo, m.X0), m.sx);
+        const double uhi = __dmul_rn(__dsub_rn(e.xhi, m.X0), m.sx);
+        for (int32_t r = r0; r <= r1; ++r) {
+            int32_t c0, c1;
+            row_footprint(m, ulo, uhi, vlo, vhi, r, c0, c1);
+            wsum += (unsigned long long)(c1 - c0 + 1);
+        }
     }
+    for (int d = 32; d > 0; d >>= 1) wsum += (unsigned long long)__shfl_xor(wsum, d, 64);
+    if ((threadIdx.x & 63) == 0 && wsum) atomicAdd(sumw, wsum);
 }
 
 // ------------------------------------------------------------ (edge,row) entries
@@ -225,7 +262,7 @@ __global__ __launch_bounds__(256) void k_entries(int64_t V, const Edge *edges, c
                                                  const uint64_t *off, const CanvasDesc *cds, int nc,
                                                  int cbits, int pbits,
                                                  uint64_t *keys, uint32_t *vals, uint32_t *ent_c,
-                                                 uint8_t *ent_f, unsigned long long *sumw)
+                                                 uint8_t *ent_f)
 {
     const int64_t nth = (int64_t)gridDim.x * blockDim.x;
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < V; j += nth) {
@@ -240,23 +277,11 @@ __global__ __launch_bounds__(256) void k_entries(int64_t V, const Edge *edges, c
         const double vhi = __dmul_rn(__dsub_rn(e.yhi, m.Y0), m.sy);
         const uint64_t poly = (uint64_t)((int64_t)epoly[j] - m.poly_base);
         const uint64_t base = off[j];
-        unsigned long long wsum = 0;
         for (uint64_t t = 0; t < nr; ++t) {
             const int32_t r = erow0[j] + (int32_t)t;
             const double b0 = (double)r - MARGIN, b1 = (double)r + 1.0 + MARGIN;
-            double xa, xb;
-            if (vlo == vhi) {
-                xa = ulo; xb = uhi;
-            } else {
-                double dv = vhi - vlo;
-                double ta = fmin(1.0, fmax(0.0, (b0 - vlo) / dv));
-                double tb = fmin(1.0, fmax(0.0, (b1 - vlo) / dv));
-                xa = ulo + ta * (uhi - ulo);
-                xb = ulo + tb * (uhi - ulo);
-            }
-            double xmn = fmin(xa, xb) - SLOP, xmx = fmax(xa, xb) + SLOP;
-            int32_t c0 = (int32_t)fmax(0.0, fmin(floor(xmn - MARGIN), (double)(m.W - 1)));
-            int32_t c1 = (int32_t)fmax(0.0, fmin(floor(xmx + MARGIN), (double)(m.W - 1)));
+            int32_t c0, c1;
+            row_footprint(m, ulo, uhi, vlo, vhi, r, c0, c1);
             const bool span = !horiz && vlo <= b0 && vhi >= b1;
             const double yc = m.Y0 + ((double)r + 0.5) * m.hy;
             const bool w = !horiz && straddles(e.ylo, e.yhi, yc);
@@ -265,9 +290,7 @@ __global__ __launch_bounds__(256) void k_entries(int64_t V, const Edge *edges, c
             vals[idx] = (uint32_t)j;
             ent_c[idx] = (uint32_t)c0 | ((uint32_t)c1 << 16);
             ent_f[idx] = (span ? F_SPAN : 0) | (w ? F_W : 0) | (horiz ? F_HORIZ : 0);
-            wsum += (unsigned long long)(c1 - c0 + 1);
         }
-        atomicAdd(sumw, wsum);
     }
 }
 
@@ -964,9 +987,6 @@ __device__ __forceinline__ uint64_t spread_bits(uint32_t v)
     return x;
 }
 
-// Coarse canvas, mixed-block records and boundary-pixel array (see
-// COARSE_MIXED), one wavefront per coarse block.  Lane l handles pixels
-// l, l + 64, ...; pixel p of a block is (p mod B, p div B).
 // Canvas holding global coarse word g.
 __device__ __forceinline__ int canvas_of_coarse(const CanvasDesc *cds, int nc, int64_t g)
 {
@@ -978,13 +998,17 @@ __device__ __forceinline__ int canvas_of_coarse(const CanvasDesc *cds, int nc, i
     return lo;
 }
 
+// Coarse level, one wave per coarse block (lane l handles pixels l, l + 64,
+// ...; pixel p of a block is (p mod B, p div B)): a uniform block stores its word,
+// a mixed block (at most two non-zero interior words up to 0xffff, plus
+// empty and boundary pixels) stores COARSE_MIXED and its compact records at
+// the block's own slot, anything else COARSE_FULL.  Slots are fixed by the
+// block index, so there is no allocation and no global atomic.
 __global__ __launch_bounds__(256) void k_compact(const CanvasDesc *cds, int nc, int64_t ncoarse_tot,
                                                  const uint32_t *cells_all, uint16_t *coarse_all,
-                                                 uint4 *desc_all, uint32_t *bpix, unsigned int *mcount,
-                                                 unsigned long long *bcount, uint64_t bpix_cap)
+                                                 uint4 *desc_all)
 {
-    __shared__ uint32_t s_pre[4][129];
-    const int lane = threadIdx.x & 63, wl = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
     for (int64_t gcell = wave; gcell < ncoarse_tot; gcell += nw) {
@@ -993,8 +1017,6 @@ __global__ __launch_bounds__(256) void k_compact(const CanvasDesc *cds, int nc, 
         const int W = cd.W, H = cd.H, Wt = cd.Wt, blog = cd.blog, Wc = cd.Wc;
         const uint32_t *cells = cells_all + cd.cell_off;
         uint16_t *coarse = coarse_all + cd.coarse_off;
-        uint4 *desc = desc_all + cd.desc_off;
-        unsigned int *counters = mcount + q;
         const int B = 1 << blog, P = B * B, J = P / 64, G = P / 32;
         const int64_t cell = gcell - cd.coarse_off;
         if (cd.empty) {
@@ -1031,7 +1053,7 @@ __global__ __launch_bounds__(256) void k_compact(const CanvasDesc *cds, int nc, 
                 const uint32_t w = pix_word(lane + 64 * j, v);
                 if (v && w != 0u && !(w & BFLAG)) {
                     bool known = false;
-                    for (int q = 0; q < npal; ++q) known |= (pal[q] == w);
+                    for (int t = 0; t < npal; ++t) known |= (pal[t] == w);
                     if (!known) { cand = w; has = true; }
                 }
             }
@@ -1041,65 +1063,25 @@ __global__ __launch_bounds__(256) void k_compact(const CanvasDesc *cds, int nc, 
             if (npal == 2 || v > 0xffffu) { full = true; break; }
             pal[npal++] = v;
         }
-        uint32_t m = 0;
-        if (!full && lane == 0) m = atomicAdd(&counters[0], 1u);
-        m = __shfl(m, 0, 64);
-        if (full || m >= 0x7fffu) {
+        if (full) {
             if (lane == 0) coarse[cell] = COARSE_FULL;
             continue;
         }
-        auto code_of = [&](int p, uint32_t &w) -> uint32_t {
-            bool v;
-            w = pix_word(p, v);
-            if (!v || w == 0u) return 2u;
-            if (w & BFLAG) return 3u;
-            return w == pal[0] ? 0u : 1u;
-        };
-        // boundary pixels before every 32-pixel group
-        uint32_t nb = 0;
-        for (int j = 0; j < J; ++j) {
-            uint32_t w;
-            const uint32_t code = code_of(lane + 64 * j, w);
-            const unsigned long long bm = __ballot(code == 3u);
-            if (lane == 0) {
-                s_pre[wl][2 * j] = nb;
-                nb += (uint32_t)__popcll(bm & 0xffffffffull);
-                s_pre[wl][2 * j + 1] = nb;
-                nb += (uint32_t)__popcll(bm >> 32);
-            }
-        }
-        nb = __shfl(nb, 0, 64);
-        uint32_t bbase = 0;
-        if (lane == 0 && nb) bbase = (uint32_t)atomicAdd(bcount, (unsigned long long)nb);
-        bbase = __shfl(bbase, 0, 64);
-        if ((uint64_t)bbase + nb > bpix_cap) {
-            // cannot happen (the array holds every boundary pixel); stay correct
-            if (lane == 0) coarse[cell] = COARSE_FULL;
-            continue;
-        }
-        __builtin_amdgcn_wave_barrier();
-        if (lane == 0) coarse[cell] = (uint16_t)(COARSE_MIXED | m);
-        uint4 *rec = desc + (size_t)m * G;
+        if (lane == 0) coarse[cell] = COARSE_MIXED;
+        uint4 *rec = desc_all + cd.desc_off + (size_t)cell * G;
         const uint32_t palw = pal[0] | (pal[1] << 16);
         for (int j = 0; j < J; ++j) {
-            uint32_t w;
-            const uint32_t code = code_of(lane + 64 * j, w);
+            bool v;
+            const uint32_t w = pix_word(lane + 64 * j, v);
+            const uint32_t code = (!v || w == 0u) ? 2u : ((w & BFLAG) ? 3u : (w == pal[0] ? 0u : 1u));
             const unsigned long long b0 = __ballot(code & 1u), b1 = __ballot(code & 2u);
-            const unsigned long long bm = b0 & b1;
             if (lane == 0 || lane == 32) {
                 const int h = lane >> 5;
                 const uint32_t lo = (uint32_t)(b0 >> (32 * h)), hi = (uint32_t)(b1 >> (32 * h));
                 const uint64_t cw = spread_bits(lo) | (spread_bits(hi) << 1);
-                rec[2 * j + h] = make_uint4((uint32_t)cw, (uint32_t)(cw >> 32), bbase + s_pre[wl][2 * j + h], palw);
-            }
-            if (code == 3u) {
-                const int g = 2 * j + (lane >> 5);
-                const uint32_t half = (uint32_t)(bm >> (32 * (lane >> 5)));
-                const uint32_t rank = s_pre[wl][g] + (uint32_t)__popc(half & ((1u << (lane & 31)) - 1u));
-                bpix[(size_t)bbase + rank] = w & ~BFLAG;
+                rec[2 * j + h] = make_uint4((uint32_t)cw, (uint32_t)(cw >> 32), 0u, palw);
             }
         }
-        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -1130,7 +1112,6 @@ CanvasView view_of(const spade_canvas *cv, int q)
     v.cells = (const uint32_t *)cv->cells.p + d.cell_off;
     v.coarse = (const uint16_t *)cv->coarse.p + d.coarse_off;
     v.desc = (const uint4 *)cv->desc.p + d.desc_off;
-    v.bpix = (const uint32_t *)cv->bpix.p;
     v.cands = (const Cand *)cv->cands.p;
     v.ledges = (const Edge *)cv->ledges.p;
     v.pspan = (const double2 *)cv->pspan.p;
@@ -1190,13 +1171,16 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
                            (double *)br.p, d_err);
         SPADE_HIP(ctx, hipGetLastError());
     }
-    unsigned *herr = (unsigned *)ensure_pinned(ctx, 64);
-    if (!herr) return set_error(ctx, SPADE_E_NOMEM, "pinned staging allocation failed");
-    SPADE_HIP(ctx, hipMemcpyAsync(herr, d_err, sizeof(unsigned), hipMemcpyDeviceToHost, st));
-    SPADE_HIP(ctx, hipStreamSynchronize(st));
-    if (herr[0] & 1u) return set_error(ctx, SPADE_E_INVALID, "ring_vtx_off must start at 0 and be non-decreasing");
-    if (herr[0] & 2u) return set_error(ctx, SPADE_E_INVALID, "poly_ring_off must start at 0, be non-decreasing and end at n_rings");
-    if (herr[0] & 4u) return set_error(ctx, SPADE_E_INVALID, "non-finite polygon vertex coordinate");
+    // Pinned staging: error flags, canvas descriptors, bounding-box keys.
+    // The bounding boxes are computed before the validation verdict is read
+    // (one synchronisation for both): the box kernel only reads within the
+    // offsets' range even when they are malformed.
+    const size_t desc_stage = sizeof(CanvasDesc) * (size_t)nc;
+    char *pin = (char *)ensure_pinned(ctx, 64 + desc_stage + 64 + bbbytes);
+    if (!pin) return set_error(ctx, SPADE_E_NOMEM, "pinned staging allocation failed");
+    unsigned *herr = (unsigned *)pin;
+    CanvasDesc *hcd = (CanvasDesc *)(pin + 64);
+    unsigned long long *hbb = (unsigned long long *)(pin + 64 + ((desc_stage + 63) & ~(size_t)63));
 
     // per-canvas polygon ranges and vertex counts (host), bounding boxes (device)
     std::vector<CanvasDesc> &cds = cv->descs;
@@ -1207,18 +1191,18 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
     }
     DevBuf &dcd = cv->dcds;
     if (ensure(ctx, dcd, sizeof(CanvasDesc) * (size_t)nc)) return SPADE_E_NOMEM;
-    CanvasDesc *hcd = (CanvasDesc *)ensure_pinned(ctx, sizeof(CanvasDesc) * (size_t)nc + bbbytes + 64);
-    if (!hcd) return set_error(ctx, SPADE_E_NOMEM, "pinned staging allocation failed");
     std::memcpy(hcd, cds.data(), sizeof(CanvasDesc) * (size_t)nc);
     SPADE_HIP(ctx, hipMemcpyAsync(dcd.p, hcd, sizeof(CanvasDesc) * (size_t)nc, hipMemcpyHostToDevice, st));
     std::vector<int64_t> nverts((size_t)nc, 0);
+    std::vector<int64_t> pro, rvo;
     if (V > 0) {
         hipLaunchKernelGGL(k_canvas_bbox, dim3(grid_for((V + BB_SPAN - 1) / BB_SPAN)), dim3(256), 0, st, R, polys->ring_vtx_off, V,
                            polys->vx, polys->vy, (const int32_t *)rp.p, (const CanvasDesc *)dcd.p, nc, d_bb);
         SPADE_HIP(ctx, hipGetLastError());
         if (nc > 1) {
-            // vertices per canvas from the offsets
-            std::vector<int64_t> pro((size_t)M + 1), rvo((size_t)R + 1);
+            // offsets for the vertices per canvas (used once they are validated)
+            pro.resize((size_t)M + 1);
+            rvo.resize((size_t)R + 1);
             if (polys->poly_ring_off)
                 SPADE_HIP(ctx, hipMemcpyAsync(pro.data(), polys->poly_ring_off, sizeof(int64_t) * (M + 1),
                                               hipMemcpyDeviceToHost, st));
@@ -1226,15 +1210,20 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
                 for (int64_t k = 0; k <= M; ++k) pro[k] = k;
             SPADE_HIP(ctx, hipMemcpyAsync(rvo.data(), polys->ring_vtx_off, sizeof(int64_t) * (R + 1),
                                           hipMemcpyDeviceToHost, st));
-            SPADE_HIP(ctx, hipStreamSynchronize(st));
-            for (int q = 0; q < nc; ++q) nverts[q] = rvo[pro[pbound[q + 1]]] - rvo[pro[pbound[q]]];
-        } else {
-            nverts[0] = V;
         }
     }
-    unsigned long long *hbb = (unsigned long long *)((char *)hcd + sizeof(CanvasDesc) * (size_t)nc + 64);
+    SPADE_HIP(ctx, hipMemcpyAsync(herr, d_err, sizeof(unsigned), hipMemcpyDeviceToHost, st));
     SPADE_HIP(ctx, hipMemcpyAsync(hbb, d_bb, bbbytes, hipMemcpyDeviceToHost, st));
     SPADE_HIP(ctx, hipStreamSynchronize(st));
+    if (herr[0] & 1u) return set_error(ctx, SPADE_E_INVALID, "ring_vtx_off must start at 0 and be non-decreasing");
+    if (herr[0] & 2u) return set_error(ctx, SPADE_E_INVALID, "poly_ring_off must start at 0, be non-decreasing and end at n_rings");
+    if (herr[0] & 4u) return set_error(ctx, SPADE_E_INVALID, "non-finite polygon vertex coordinate");
+    if (V > 0) {
+        if (nc > 1)
+            for (int q = 0; q < nc; ++q) nverts[q] = rvo[pro[pbound[q + 1]]] - rvo[pro[pbound[q]]];
+        else
+            nverts[0] = V;
+    }
     auto undkey = [](unsigned long long k) {
         const unsigned long long b = (k & 0x8000000000000000ull) ? (k & 0x7fffffffffffffffull) : ~k;
         double d;
@@ -1288,7 +1277,7 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
         Htot += H;
         cells_tot += (int64_t)d.Wt * Ht * 256;
         coarse_tot += (int64_t)d.Wc * d.Hc;
-        desc_tot += (int64_t)std::min<int64_t>((int64_t)d.Wc * d.Hc, 0x7fff) * (desc_bytes(blog) / 16);
+        desc_tot += (int64_t)d.Wc * d.Hc * (desc_bytes(blog) / 16);
         maxW = std::max(maxW, W);
     }
     if (Htot > 0x7fffffffLL) return set_error(ctx, SPADE_E_UNSUPPORTED, "canvas set has too many rows");
@@ -1306,7 +1295,7 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
         SPADE_HIP(ctx, hipMemsetAsync(cv->cells.p, 0, sizeof(uint32_t) * (size_t)cells_tot, st));
         SPADE_HIP(ctx, hipMemsetAsync(cv->coarse.p, 0, sizeof(uint16_t) * ((size_t)coarse_tot + 2), st));
         if (ensure(ctx, cv->cands, sizeof(Cand)) || ensure(ctx, cv->ledges, sizeof(Edge)) ||
-            ensure(ctx, cv->pspan, sizeof(double2)) || ensure(ctx, cv->bpix, sizeof(uint32_t)))
+            ensure(ctx, cv->pspan, sizeof(double2)))
             return SPADE_E_NOMEM;
         cv->n_boundary = cv->n_cands = cv->n_elist = 0;
         finish_views(cv);
@@ -1327,9 +1316,15 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
     uint32_t *epoly = (uint32_t *)dmisc.p;
     int32_t *erow0 = (int32_t *)(epoly + Vs);
     uint64_t *eoff = (uint64_t *)(((uintptr_t)(erow0 + Vs) + 7) & ~(uintptr_t)7);
+    // per-row counters (8 arrays of H + 1), then the global counters:
+    // [0..3] row-pass allocation, [4] footprint widths, [5] boundary pixels
+    DevBuf &drc = ctx->scratch[S_ROWCNT];
+    if (ensure(ctx, drc, 8 * 8 * ((size_t)H + 1) + 64)) return SPADE_E_NOMEM;
+    unsigned long long *gctr = (unsigned long long *)((uint64_t *)drc.p + 8 * ((size_t)H + 1));
+    SPADE_HIP(ctx, hipMemsetAsync(gctr, 0, 64, st));
     hipLaunchKernelGGL(k_edges, dim3(grid_for(V)), dim3(256), 0, st, R, polys->ring_vtx_off, V,
                        polys->vx, polys->vy, (const int32_t *)rp.p, d_cds, nc, (Edge *)cv->edges.p, epoly,
-                       erow0, nrows);
+                       erow0, nrows, gctr + 4);
     SPADE_HIP(ctx, hipGetLastError());
     SPADE_HIP(ctx, hipMemsetAsync(nrows + V, 0, sizeof(uint64_t), st));
 
@@ -1340,8 +1335,10 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
     SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(cub.p, tb, nrows, eoff, (int)(V + 1), st));
     uint64_t *hT = (uint64_t *)ensure_pinned(ctx, 64);
     SPADE_HIP(ctx, hipMemcpyAsync(hT, eoff + V, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    SPADE_HIP(ctx, hipMemcpyAsync(hT + 1, gctr + 4, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
     SPADE_HIP(ctx, hipStreamSynchronize(st));
     const uint64_t T = hT[0];
+    const uint64_t sumw = hT[1];
     if (T >= 0x7fffffffULL) return set_error(ctx, SPADE_E_UNSUPPORTED, "too many (edge,row) entries; lower the canvas height");
 
     const int cbits = std::max(1, bits_for((uint64_t)W - 1));
@@ -1354,23 +1351,19 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
     DevBuf &dk = ctx->scratch[S_KEYS], &dk2 = ctx->scratch[S_KEYS2];
     DevBuf &dv = ctx->scratch[S_VALS], &dv2 = ctx->scratch[S_VALS2];
     DevBuf &dc = ctx->scratch[S_ENTC], &df = ctx->scratch[S_ENTF];
-    DevBuf &drow = ctx->scratch[S_ROWOFF], &drc = ctx->scratch[S_ROWCNT];
+    DevBuf &drow = ctx->scratch[S_ROWOFF];
     const size_t Ts = (size_t)std::max<uint64_t>(T, 1);
     // dc: ent_c[T] | sorted c[T] | perm[T] | perm2[T]; df: ent_f[T] | sorted f[T]
     if (ensure(ctx, dk, 8 * Ts) || ensure(ctx, dk2, 8 * Ts) || ensure(ctx, dv, 4 * Ts) ||
         ensure(ctx, dv2, 4 * Ts) || ensure(ctx, dc, 20 * Ts) || ensure(ctx, df, 2 * Ts + 16) ||
-        ensure(ctx, drow, 8 * ((size_t)H + 1)) ||
-        ensure(ctx, drc, 8 * 8 * ((size_t)H + 1) + 64))
+        ensure(ctx, drow, 8 * ((size_t)H + 1)))
         return SPADE_E_NOMEM;
     uint32_t *ent_c = (uint32_t *)dc.p, *s_c = ent_c + Ts, *perm = s_c + Ts, *perm2 = perm + Ts;
     uint32_t *s_poly = perm2 + Ts;
     uint8_t *ent_f = (uint8_t *)df.p, *s_f = ent_f + Ts;
-    // counters after the per-row arrays: [0..3] row-pass allocation, [4] footprint widths
-    unsigned long long *gctr = (unsigned long long *)((uint64_t *)drc.p + 8 * ((size_t)H + 1));
-    SPADE_HIP(ctx, hipMemsetAsync(gctr, 0, 64, st));
     hipLaunchKernelGGL(k_entries, dim3(grid_for(V)), dim3(256), 0, st, V, (const Edge *)cv->edges.p,
                        epoly, erow0, nrows, eoff, d_cds, nc, cbits, pbits, (uint64_t *)dk.p, (uint32_t *)dv.p,
-                       ent_c, ent_f, gctr + 4);
+                       ent_c, ent_f);
     SPADE_HIP(ctx, hipGetLastError());
     hipLaunchKernelGGL(k_iota, dim3(grid_for((int64_t)T)), dim3(256), 0, st, (int64_t)T, perm);
     SPADE_HIP(ctx, hipGetLastError());
@@ -1411,10 +1404,6 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
     uint64_t *part_base = loc_base + (H + 1);
     uint64_t *bp_scan = part_base + (H + 1);
     SPADE_HIP(ctx, hipMemsetAsync(drc.p, 0, 8 * 8 * ((size_t)H + 1), st));
-    uint64_t *hw = (uint64_t *)ensure_pinned(ctx, 64);
-    SPADE_HIP(ctx, hipMemcpyAsync(hw, gctr + 4, 8, hipMemcpyDeviceToHost, st));
-    SPADE_HIP(ctx, hipStreamSynchronize(st));
-    const uint64_t sumw = hw[0];
 
     RowArgs ra{};
     ra.cds = d_cds;
@@ -1464,11 +1453,23 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
     };
     ra.cells = (uint32_t *)cv->cells.p;
 
+    // Coarse level + compact records of mixed blocks, from the canvas words.
+    auto launch_compact = [&]() -> int {
+        const int cgrid = (int)std::max<int64_t>(1, std::min<int64_t>((coarse_tot + 3) / 4, 65536));
+        hipLaunchKernelGGL(k_compact, dim3(cgrid), dim3(256), 0, st, d_cds, nc, coarse_tot,
+                           (const uint32_t *)cv->cells.p, (uint16_t *)cv->coarse.p, (uint4 *)cv->desc.p);
+        SPADE_HIP(ctx, hipGetLastError());
+        return SPADE_OK;
+    };
+
     // One row pass: rows reserve their output ranges with atomics inside
     // bounds derived from the entries (records <= 2 * sum of footprint widths
     // unless interiors overlap, local edges <= that sum, partial spans <= T).
+    // The coarse level is built right behind it, and one synchronisation
+    // reads the counters and flags of both.
     bool done_single = false;
     uint64_t nrec = 0, nloc = 0, npart = 0, nbp = 0;
+    unsigned ef = 0;
     {
         ra.alloc = 1;
         ra.gctr = gctr;
@@ -1483,11 +1484,12 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
         ra.ledges = (Edge *)cv->ledges.p;
         ra.pspan = (double2 *)cv->pspan.p;
         SPADE_HIP(ctx, launch_rows(true));
+        int rc = launch_compact();
+        if (rc) return rc;
         uint64_t *hc = (uint64_t *)ensure_pinned(ctx, 64);
         SPADE_HIP(ctx, hipMemcpyAsync(hc, gctr, 32, hipMemcpyDeviceToHost, st));
         SPADE_HIP(ctx, hipMemcpyAsync(hc + 4, d_err, sizeof(unsigned), hipMemcpyDeviceToHost, st));
         SPADE_HIP(ctx, hipStreamSynchronize(st));
-        unsigned ef = 0;
         std::memcpy(&ef, hc + 4, sizeof(unsigned));
         if (!(ef & 32u)) {
             done_single = true;
@@ -1527,25 +1529,15 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
         ra.ledges = (Edge *)cv->ledges.p;
         ra.pspan = (double2 *)cv->pspan.p;
         SPADE_HIP(ctx, launch_rows(true));
+        int rc = launch_compact();
+        if (rc) return rc;
+        unsigned *herr2 = (unsigned *)ensure_pinned(ctx, 64);
+        SPADE_HIP(ctx, hipMemcpyAsync(herr2, d_err, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+        SPADE_HIP(ctx, hipStreamSynchronize(st));
+        ef = herr2[0];
     }
-    {
-        const int cgrid = (int)std::max<int64_t>(1, std::min<int64_t>((coarse_tot + 3) / 4, 65536));
-        if (ensure(ctx, cv->bpix, sizeof(uint32_t) * (size_t)std::max<uint64_t>(nbp, 1)) ||
-            ensure(ctx, ctx->scratch[S_LOOKBACK], sizeof(unsigned int) * (size_t)nc + 64))
-            return SPADE_E_NOMEM;
-        SPADE_HIP(ctx, hipMemsetAsync(gctr + 5, 0, 8, st));
-        SPADE_HIP(ctx, hipMemsetAsync(ctx->scratch[S_LOOKBACK].p, 0, sizeof(unsigned int) * (size_t)nc, st));
-        hipLaunchKernelGGL(k_compact, dim3(cgrid), dim3(256), 0, st, d_cds, nc, coarse_tot,
-                           (const uint32_t *)cv->cells.p, (uint16_t *)cv->coarse.p, (uint4 *)cv->desc.p,
-                           (uint32_t *)cv->bpix.p, (unsigned int *)ctx->scratch[S_LOOKBACK].p, gctr + 5,
-                           (uint64_t)std::max<uint64_t>(nbp, 1));
-        SPADE_HIP(ctx, hipGetLastError());
-    }
-    unsigned *herr2 = (unsigned *)ensure_pinned(ctx, 64);
-    SPADE_HIP(ctx, hipMemcpyAsync(herr2, d_err, sizeof(unsigned), hipMemcpyDeviceToHost, st));
-    SPADE_HIP(ctx, hipStreamSynchronize(st));
-    if (herr2[0] & 8u) return set_error(ctx, SPADE_E_HIP, "internal: boundary pixel without candidates");
-    if (herr2[0] & 16u)
+    if (ef & 8u) return set_error(ctx, SPADE_E_HIP, "internal: boundary pixel without candidates");
+    if (ef & 16u)
         return set_error(ctx, SPADE_E_UNSUPPORTED, "a boundary pixel has more than 32767 edges of one polygon; raise the canvas resolution");
     cv->n_boundary = (int64_t)nbp;
     cv->n_cands = (int64_t)nrec;
