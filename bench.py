@@ -8,7 +8,9 @@ jittered to 50..500 vertices (seed 2); output: exact per-polygon counts.
 
 A step is one whole join-count with every input already resident in HBM:
 rasterising the polygons into the canvas and boundary index, then probing
-every point (spade_join_count).  ``value`` is points per second of whole
+every point (spade_join_count).  Before the timed steps the autotuner picks
+the canvas resolution (pixels per polygon vertex) from a few trial queries;
+the choice is reported in ``config.autotune``.  ``value`` is points per second of whole
 steps.  The probe kernel's duration is taken with HIP events on the stream
 it runs on (the library's phase timers) over the timed steps; its roofline
 entry prices 16 algorithmic bytes per point (two float64 coordinates)
@@ -68,6 +70,12 @@ def load_traffic(n_points):
     return d.get("hbm_bytes_per_launch")
 
 
+def _mem(tag):
+    import torch
+    free, total = torch.cuda.mem_get_info()
+    log("device memory %s: %.1f GiB free of %.1f GiB" % (tag, free / 2**30, total / 2**30))
+
+
 def serving_leg(seconds, qps, n_points, oneshot_max):
     """Continuous-batching server over a resident table; one-at-a-time baseline."""
     import numpy as np
@@ -104,7 +112,12 @@ def serving_leg(seconds, qps, n_points, oneshot_max):
                  "vx": tess["vx"][idx], "vy": tess["vy"][idx]}
             reqs.append(Request(i, "count", p))
 
+    _mem("before the table")
     ex = SpadeExecutor(dx, dy, n_workers=2)
+    _mem("with the table")
+    ppv, times = ex.autotune(reqs[:32])
+    _mem("after autotuning")
+    log("serving autotune: %.0f pixels per vertex (trials %s)" % (ppv, {k: round(v, 2) for k, v in times.items()}))
     free, _ = torch.cuda.mem_get_info()
     budget = max(free - (16 << 30), 1 << 30)
     # warm the workers' contexts and canvas sets
@@ -117,6 +130,7 @@ def serving_leg(seconds, qps, n_points, oneshot_max):
     srv.batches.clear()
     wall = replay(srv, reqs, arrivals)
     srv.stop()
+    _mem("after the served stream")
     errs = [r.error for r in reqs if r.error]
     if errs:
         raise SystemExit("served requests failed: %s" % errs[:3])
@@ -155,6 +169,7 @@ def serving_leg(seconds, qps, n_points, oneshot_max):
             "capacity_batched_requests_per_s": round(n / burst, 1),
             "capacity_one_at_a_time_requests_per_s": round(1.0 / one, 1),
             "one_at_a_time_sample": k,
+            "pixels_per_vertex": ppv,
             "mix": "50% selection (star, 8-20000 vertices), 50% join-count (64-40000 Voronoi cells, 4-40 vertices)"}
 
 
@@ -165,7 +180,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--points", type=int, default=100_000_000)
     ap.add_argument("--polygons", type=int, default=260)
-    ap.add_argument("--canvas", type=int, nargs=2, default=(0, 0), metavar=("W", "H"))
+    ap.add_argument("--canvas", type=int, nargs=2, default=(0, 0), metavar=("W", "H"),
+                    help="fixed canvas size (default: automatic, resolution autotuned)")
+    ap.add_argument("--ppv", type=float, default=0.0,
+                    help="fixed pixels per polygon vertex instead of autotuning (0 = autotune)")
     ap.add_argument("--cpu-sample", type=int, default=40_000_000,
                     help="points of the prefix timed with the CPU oracle (0 = skip)")
     ap.add_argument("--serve-seconds", type=float, default=4.0,
@@ -210,6 +228,16 @@ def main():
         torch.cuda.synchronize()
         log("calibration copy: %d MiB read, %d MiB written" % (args.calibrate_copy_mib, args.calibrate_copy_mib))
         del src, dst
+    tuned = None
+    if args.canvas == (0, 0) or list(args.canvas) == [0, 0]:
+        if args.ppv > 0:
+            ctx.set_pixels_per_vertex(args.ppv)
+        else:
+            from paper_2203_14362_amd.autotune import tune_join_count
+            ppv, times = tune_join_count(ctx, dx, dy, dpolys)
+            tuned = {"pixels_per_vertex": ppv, "trial_ms": {str(k): round(v, 3) for k, v in times.items()}}
+            log("autotuned canvas resolution: %.0f pixels per vertex (trials %s)" % (ppv, tuned["trial_ms"]))
+        ctx.set_timing(True)
     for _ in range(args.warmup):
         counts = ctx.join_count(dx, dy, dpolys)
     torch.cuda.synchronize()
@@ -286,6 +314,7 @@ def main():
                    "points": N, "polygons": polys["n_polys"],
                    "vertices": int(info["vertex_counts"].sum()),
                    "canvas": [cinfo["width"], cinfo["height"]],
+                   "autotune": tuned,
                    "boundary_pixels": cinfo["boundary_pixels"],
                    "raster_ms": round(float(np.mean(raster_ms)), 4),
                    "probe_ms": round(float(np.mean(probe_ms)), 4),

@@ -1,0 +1,99 @@
+"""Canvas-resolution autotuner.
+
+The canvas resolution trades rasterisation against probing: a finer canvas
+costs more rows to rasterise and more canvas words to write, a coarser one
+sends more points to the exact boundary test.  The best point depends on
+the polygons (vertex count, shape) and on the points (how many, where), so
+it is measured instead of modelled: a few micro-trials of the real query at
+candidate resolutions (pixels per polygon vertex), timed with the library's
+own phase events, pick the fastest.  Results never depend on the choice
+(every resolution is exact); only the time does.
+
+Choices are cached per workload signature (polygon count, vertex count and
+point count, each rounded to a power of two) in memory and, optionally, in
+a JSON file, so a workload is tuned once.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import threading
+
+DEFAULT_CANDIDATES = (48.0, 96.0, 192.0, 384.0)
+
+
+def _bucket(n: int) -> int:
+    return 0 if n <= 0 else int(round(math.log2(n)))
+
+
+def signature(kind: str, n_polys: int, n_vertices: int, n_points: int) -> str:
+    return "%s/p%d/v%d/n%d" % (kind, _bucket(n_polys), _bucket(n_vertices), _bucket(n_points))
+
+
+class Autotuner:
+    def __init__(self, path: str = None, candidates=DEFAULT_CANDIDATES, repeats: int = 3):
+        self.path = path
+        self.candidates = tuple(float(c) for c in candidates)
+        self.repeats = repeats
+        self._lock = threading.Lock()
+        self.table = {}
+        if path and os.path.exists(path):
+            with open(path) as fh:
+                self.table = json.load(fh)
+
+    def _save(self):
+        if not self.path:
+            return
+        tmp = self.path + ".tmp%d" % os.getpid()
+        with open(tmp, "w") as fh:
+            json.dump(self.table, fh, indent=1, sort_keys=True)
+        os.replace(tmp, self.path)
+
+    def lookup(self, key: str):
+        with self._lock:
+            e = self.table.get(key)
+        return None if e is None else float(e["ppv"])
+
+    def tune(self, key: str, trial, force: bool = False):
+        """Pick the fastest pixels-per-vertex for `key`.  ``trial(ppv)``
+        runs the query once at that setting and returns its device time in
+        milliseconds.  Returns (ppv, {ppv: best ms})."""
+        if not force:
+            hit = self.lookup(key)
+            if hit is not None:
+                return hit, {}
+        times = {}
+        for ppv in self.candidates:
+            trial(ppv)                                   # warm: allocations, caches
+            times[ppv] = min(trial(ppv) for _ in range(self.repeats))
+        best = min(times, key=times.get)
+        with self._lock:
+            self.table[key] = {"ppv": best, "ms": {str(k): round(v, 4) for k, v in times.items()}}
+            self._save()
+        return best, times
+
+
+def tune_join_count(ctx, x, y, polys, tuner: Autotuner = None, force: bool = False):
+    """Tune and set ctx's pixels-per-vertex for join-counts of `polys` over
+    the points (x, y): each trial is a whole join-count (rasterisation plus
+    probe) timed by the library's events.  Returns (ppv, times)."""
+    tuner = tuner or Autotuner()
+    dp = ctx.polys(polys)
+    nv = int(dp.ring_vtx_off[-1].item()) if dp.ring_vtx_off.numel() else 0
+    key = signature("count", dp.n_polys, nv, int(x.numel()))
+    was = ctx.timing_enabled
+
+    def trial(ppv):
+        ctx.set_pixels_per_vertex(ppv)
+        ctx.join_count(x, y, dp)
+        r, p = ctx.last_timing()
+        return r + p
+
+    ctx.set_timing(True)
+    try:
+        ppv, times = tuner.tune(key, trial, force=force)
+    finally:
+        ctx.set_timing(was)
+    ctx.set_pixels_per_vertex(ppv)
+    return ppv, times

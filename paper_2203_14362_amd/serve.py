@@ -323,15 +323,39 @@ class SpadeExecutor:
                 polys, qb = concat_sets([r.polys for r in sel])
                 b = self._sets[w][0] = ctx.batch(polys, qb, into=self._sets[w][0])
                 ids, off = ctx.batch_select(b, self.table)
+                # each result owns its memory: a view would keep the whole
+                # batch's id buffer alive for as long as any result lives
                 for q, r in enumerate(sel):
-                    r.result = ids[int(off[q]):int(off[q + 1])]
+                    r.result = ids[int(off[q]):int(off[q + 1])].clone()
             if cnt:
                 polys, qb = concat_sets([r.polys for r in cnt])
                 b = self._sets[w][1] = ctx.batch(polys, qb, into=self._sets[w][1])
                 counts = ctx.batch_join_count(b, self.table)
                 for q, r in enumerate(cnt):
-                    r.result = counts[int(qb[q]):int(qb[q + 1])]
+                    r.result = counts[int(qb[q]):int(qb[q + 1])].clone()
         s.synchronize()
+
+    def autotune(self, sample: List[Request], candidates=None):
+        """Pick the canvas resolution (pixels per vertex) for every worker
+        from timed batches of `sample` on worker 0; returns (ppv, {ppv: ms})."""
+        import time as _time
+        from .autotune import DEFAULT_CANDIDATES
+        cands = tuple(candidates or DEFAULT_CANDIDATES)
+        times = {}
+        for ppv in cands:
+            self.ctxs[0].set_pixels_per_vertex(ppv)
+            self.run(0, [Request(-1, r.kind, r.polys) for r in sample])   # warm
+            best = None
+            for _ in range(2):
+                t0 = _time.perf_counter()
+                self.run(0, [Request(-1, r.kind, r.polys) for r in sample])
+                dt = (_time.perf_counter() - t0) * 1e3
+                best = dt if best is None else min(best, dt)
+            times[ppv] = best
+        self.ppv = min(times, key=times.get)
+        for c in self.ctxs:
+            c.set_pixels_per_vertex(self.ppv)
+        return self.ppv, times
 
     def close(self):
         for pair in self._sets:

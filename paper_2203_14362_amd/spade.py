@@ -143,6 +143,12 @@ class DevicePolys:
                       self.vy.data_ptr() if self.vy.numel() else 0)
 
 
+def _compact(buf, m):
+    """The first m elements of an output buffer; copied out when they fill
+    less than half of it, so a result never pins a much larger buffer."""
+    return buf[:m] if 2 * m >= buf.numel() else buf[:m].clone()
+
+
 def _points(x, y):
     if x.dtype != torch.float64 or y.dtype != torch.float64:
         raise TypeError("points must be float64 tensors")
@@ -230,6 +236,8 @@ class Context:
         if rc != SPADE_OK:
             raise SpadeError(rc, "spade_ctx_create failed")
         self.handle = h
+        self.timing_enabled = False
+        self._select_cap = 1 << 20
 
     # -- helpers
     def _check(self, rc):
@@ -245,6 +253,7 @@ class Context:
 
     def set_timing(self, on: bool = True):
         self._check(self.lib.spade_ctx_set_timing(self.handle, 1 if on else 0))
+        self.timing_enabled = bool(on)
 
     def last_timing(self):
         """(raster_ms, probe_ms) of the last query (HIP events on its stream)."""
@@ -287,10 +296,12 @@ class Context:
 
     def batch_select(self, batch: Batch, table: Table, cap=None):
         """(ids int32 tensor, offsets int64 numpy [nq + 1]): query q's ascending
-        point ids are ids[off[q]:off[q+1]]."""
+        point ids are ids[off[q]:off[q+1]].  Without an explicit capacity the
+        first attempt uses the largest total seen on this context (at least
+        2^20) and retries once at the reported total."""
         off = np.zeros(batch.n_queries + 1, dtype=np.int64)
         if cap is None:
-            cap = max(table.info()["n_points"], 1)
+            cap = self._select_cap
         while True:
             ids = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device)
             self._sync_stream()
@@ -299,9 +310,10 @@ class Context:
                                              off.ctypes.data_as(ctypes.c_void_p))
             if rc == SPADE_E_CAPACITY:
                 cap = int(off[-1])
+                self._select_cap = max(self._select_cap, cap)
                 continue
             self._check(rc)
-            return ids[:int(off[-1])], off
+            return _compact(ids, int(off[-1])), off
 
     def batch_join_count(self, batch: Batch, table: Table, out=None):
         """Per-polygon counts of the batch's polygon set (int64 tensor)."""
@@ -374,7 +386,7 @@ class Context:
                 continue
             self._check(rc)
             m = int(nout.value)
-            return (pt[:m], pg[:m]) if pairs else pt[:m]
+            return (_compact(pt, m), _compact(pg, m)) if pairs else _compact(pt, m)
 
     def select(self, x, y, poly_or_canvas, cap=None):
         """Ascending ids (int32 tensor) of the points inside the one polygon."""

@@ -54,6 +54,9 @@ def test_served_equals_alone(ctx):
     assert max(len(b) for b in srv.batches) >= 1
     st = latency_stats(reqs)
     assert st["n"] == len(reqs)
+    # results own their memory (no view pinning a batch-sized buffer)
+    for r in reqs:
+        assert r.result.untyped_storage().nbytes() == r.result.numel() * r.result.element_size(), r.rid
     for r in reqs:
         if r.kind == "select":
             alone = ctx.select(dx, dy, r.polys)
