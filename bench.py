@@ -51,21 +51,23 @@ def log(*a):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("probe.hip", "exact.h", "common.h"):
+    for f in ("probe.hip", "lookup.h", "exact.h", "common.h"):
         with open(os.path.join(ROOT, "paper_2203_14362_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def load_traffic(n_points):
+def load_traffic(n_points, canvas):
     """HBM bytes per probe launch from committed rocprofv3 counter runs, if
-    they were taken on the current kernel source; else None."""
+    they were taken on the current kernel source, point count and canvas
+    size; else None."""
     path = os.path.join(ROOT, "profiles", "k_count_join_c100m_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         d = json.load(fh)
-    if d.get("kernel_source_hash") != kernel_source_hash() or int(d.get("n_points", -1)) != n_points:
+    if (d.get("kernel_source_hash") != kernel_source_hash() or int(d.get("n_points", -1)) != n_points
+            or list(d.get("canvas", [])) != list(canvas)):
         return None
     return d.get("hbm_bytes_per_launch")
 
@@ -184,6 +186,8 @@ def main():
                     help="fixed canvas size (default: automatic, resolution autotuned)")
     ap.add_argument("--ppv", type=float, default=0.0,
                     help="fixed pixels per polygon vertex instead of autotuning (0 = autotune)")
+    ap.add_argument("--tune-cache", default="",
+                    help="JSON file of autotuner choices to reuse (and extend) across runs")
     ap.add_argument("--cpu-sample", type=int, default=40_000_000,
                     help="points of the prefix timed with the CPU oracle (0 = skip)")
     ap.add_argument("--serve-seconds", type=float, default=4.0,
@@ -233,9 +237,11 @@ def main():
         if args.ppv > 0:
             ctx.set_pixels_per_vertex(args.ppv)
         else:
-            from paper_2203_14362_amd.autotune import tune_join_count
-            ppv, times = tune_join_count(ctx, dx, dy, dpolys)
-            tuned = {"pixels_per_vertex": ppv, "trial_ms": {str(k): round(v, 3) for k, v in times.items()}}
+            from paper_2203_14362_amd.autotune import Autotuner, tune_join_count
+            tuner = Autotuner(args.tune_cache or None)
+            ppv, times = tune_join_count(ctx, dx, dy, dpolys, tuner)
+            tuned = {"pixels_per_vertex": ppv, "trial_ms": {str(k): round(v, 3) for k, v in times.items()},
+                     "cached": not times}
             log("autotuned canvas resolution: %.0f pixels per vertex (trials %s)" % (ppv, tuned["trial_ms"]))
         ctx.set_timing(True)
     for _ in range(args.warmup):
@@ -267,7 +273,7 @@ def main():
 
     probe_s = float(np.mean(probe_ms)) / 1000.0
     achieved = BYTES_PER_POINT * N / probe_s / 1e9
-    traffic = load_traffic(N)
+    traffic = load_traffic(N, [cinfo["width"], cinfo["height"]])
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
                 "kernel": "k_count", "bytes_per_point": BYTES_PER_POINT,
