@@ -188,8 +188,8 @@ def main():
                     help="fixed pixels per polygon vertex instead of autotuning (0 = autotune)")
     ap.add_argument("--tune-cache", default="",
                     help="JSON file of autotuner choices to reuse (and extend) across runs")
-    ap.add_argument("--cpu-sample", type=int, default=40_000_000,
-                    help="points of the prefix timed with the CPU oracle (0 = skip)")
+    ap.add_argument("--cpu-sample", type=int, default=100_000_000,
+                    help="points of the prefix timed with the CPU oracle (0 = skip; default: all of them)")
     ap.add_argument("--serve-seconds", type=float, default=4.0,
                     help="length of the served Poisson stream (0 = skip the serving leg)")
     ap.add_argument("--serve-qps", type=float, default=200.0)

@@ -214,8 +214,7 @@ int spade_batch_rebuild(spade_ctx *ctx, const spade_polys *polys, int32_t nq, co
  * out_off [nq + 1] (host) receives each query's start; out_off[nq] is the
  * total.  If the total exceeds cap, nothing is written to out_ids and
  * SPADE_E_CAPACITY is returned with out_off filled.  Evaluated with the
- * paper's two-step Map (Sec. 5.1): a count pass, then a write pass.  At most
- * 2^31 - 1 selected points per batch (SPADE_E_UNSUPPORTED beyond). */
+ * paper's two-step Map (Sec. 5.1): a count pass, then a write pass. */
 int spade_batch_select(spade_ctx *ctx, const spade_canvas *set, const spade_table *t,
                        uint32_t *out_ids, int64_t cap, int64_t *out_off);
 

@@ -20,6 +20,8 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <utility>
+#include <vector>
 
 namespace spade {
 
@@ -686,8 +688,6 @@ int spade_batch_select(spade_ctx *ctx, const spade_canvas *set, const spade_tabl
     SPADE_HIP(ctx, hipStreamSynchronize(st));
     for (int q = 0; q <= nq; ++q) out_off[q] = (int64_t)h[q];
     if ((int64_t)total > cap) return set_error(ctx, SPADE_E_CAPACITY, "output capacity too small");
-    if (total > (unsigned long long)INT32_MAX)
-        return set_error(ctx, SPADE_E_UNSUPPORTED, "more than 2^31 - 1 selected points in one batch; split the batch");
     if (total == 0) {
         if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[3], st));
         return SPADE_OK;
@@ -698,15 +698,32 @@ int spade_batch_select(spade_ctx *ctx, const spade_canvas *set, const spade_tabl
                        (const double *)t->x.p, (const double *)t->y.p, (const uint32_t *)t->ids.p, P.cbase, P.plist,
                        P.pq, nullptr, (const unsigned long long *)pbase, (unsigned long long *)bo.p);
     SPADE_HIP(ctx, hipGetLastError());
-    // one radix sort of (query, id) keys orders the ids inside every query
-    // (a per-segment sort would give a whole query to one workgroup)
+    // Radix sorts of (query, id) keys order the ids inside every query (a
+    // per-segment sort would give a whole query to one workgroup).  The keys
+    // are already grouped by query, so runs of consecutive queries are sorted
+    // separately: at most 2^30 keys per sort, or one larger query alone.
     const int kbits = 32 + std::max(1, bits_of((uint64_t)(nq - 1)));
+    const int64_t GROUP = (int64_t)1 << 30;
+    std::vector<std::pair<int64_t, int64_t>> groups;
+    {
+        int64_t gb = 0;
+        for (int q = 0; q < nq; ++q)
+            if (out_off[q + 1] - gb > GROUP && out_off[q] > gb) {
+                groups.push_back({gb, out_off[q]});
+                gb = out_off[q];
+            }
+        if ((int64_t)total > gb) groups.push_back({gb, (int64_t)total});
+    }
+    int64_t gmax = 0;
+    for (const auto &g : groups) gmax = std::max(gmax, g.second - g.first);
     tb = 0;
     SPADE_HIP(ctx, hipcub::DeviceRadixSort::SortKeys(nullptr, tb, (const unsigned long long *)bo.p,
-                                                     (unsigned long long *)bo2.p, (int)total, 0, kbits, st));
+                                                     (unsigned long long *)bo2.p, (int)gmax, 0, kbits, st));
     if (ensure(ctx, cub, tb)) return SPADE_E_NOMEM;
-    SPADE_HIP(ctx, hipcub::DeviceRadixSort::SortKeys(cub.p, tb, (const unsigned long long *)bo.p,
-                                                     (unsigned long long *)bo2.p, (int)total, 0, kbits, st));
+    for (const auto &g : groups)
+        SPADE_HIP(ctx, hipcub::DeviceRadixSort::SortKeys(cub.p, tb, (const unsigned long long *)bo.p + g.first,
+                                                         (unsigned long long *)bo2.p + g.first,
+                                                         (int)(g.second - g.first), 0, kbits, st));
     hipLaunchKernelGGL(k_low32, dim3(grid_of((int64_t)total)), dim3(256), 0, st, (int64_t)total,
                        (const unsigned long long *)bo2.p, out_ids);
     SPADE_HIP(ctx, hipGetLastError());
