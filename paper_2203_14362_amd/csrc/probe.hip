@@ -369,20 +369,26 @@ __global__ __launch_bounds__(EMIT_THREADS) void k_emit(CanvasView cv, int64_t n,
                 }
                 continue;
             }
-            // several polygons contain the point: re-run its candidates in order
+            // several polygons contain the point (the pixel's records are in
+            // no particular order): emit them in ascending polygon order, each
+            // pass taking the smallest matching polygon above the last one
             const double x = X[i], y = Y[i];
-            uint32_t rec = lab[it];
-            while (true) {
-                const Cand cd = cv.cands[rec];
-                if (cand_inside(cv, cd, x, y)) {
-                    if ((int64_t)pos < cap) {
-                        out_pt[pos] = (uint32_t)i;
-                        if (out_poly) out_poly[pos] = cd.poly;
-                    }
-                    ++pos;
+            uint32_t prev = 0;
+            for (uint32_t t = 0; t < cnt[it]; ++t) {
+                uint32_t best = 0xffffffffu;
+                uint32_t rec = lab[it];
+                while (true) {
+                    const Cand cd = cv.cands[rec];
+                    if ((t == 0 || cd.poly > prev) && cd.poly < best && cand_inside(cv, cd, x, y)) best = cd.poly;
+                    if (cd.meta & CAND_LAST) break;
+                    ++rec;
                 }
-                if (cd.meta & CAND_LAST) break;
-                ++rec;
+                if ((int64_t)pos < cap) {
+                    out_pt[pos] = (uint32_t)i;
+                    if (out_poly) out_poly[pos] = best;
+                }
+                ++pos;
+                prev = best;
             }
         }
         __syncthreads();

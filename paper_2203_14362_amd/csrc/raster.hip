@@ -17,15 +17,17 @@
 //
 // Pipeline (all on the context's stream):
 //   k_validate   offsets / finiteness checks, ring -> polygon map, bbox
+//                (k_canvas_bbox: per-canvas boxes of a canvas set)
 //   k_edges      one thread per vertex: edge record, pixel row range
 //   scan         edge -> first (edge,row) entry
 //   k_entries    one (edge,row) entry per row an edge touches: footprint
 //                columns [c0,c1], spanning flag, parity weight at the row centre
 //   radix sort   entries by (row, polygon, c0)
-//   k_row_off    row -> first entry
-//   k_rows<0>    per row, in LDS: count boundary pixels / records / edge ids
-//   scans        per-row bases
-//   k_rows<1>    per row, in LDS: write canvas words, records, edge ids
+//   k_gather     sorted payload, row -> first entry
+//   k_rows<1>    per row, in LDS: write canvas words, records, edge ids into
+//                ranges reserved with atomics (k_rows<0> + scans + k_rows<1>
+//                with exact sizes when the reserved capacity runs out)
+//   k_compact    coarse level over the canvas words
 #include "common.h"
 #include "exact.h"
 
@@ -81,7 +83,8 @@ __device__ __forceinline__ unsigned long long dkey(double v)
 __global__ __launch_bounds__(256) void k_validate(int64_t M, int64_t R, const int64_t *pro,
                                                   const int64_t *rvo, int64_t V, const double *vx,
                                                   const double *vy, int32_t *ring_poly,
-                                                  double *blockred, unsigned *errflags)
+                                                  double *blockred, unsigned *errflags,
+                                                  unsigned long long *bb)
 {
     // (per-canvas boxes are computed by k_canvas_bbox once ring_poly is known)
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -116,6 +119,8 @@ __global__ __launch_bounds__(256) void k_validate(int64_t M, int64_t R, const in
     }
     if (threadIdx.x == 0)
         for (int q = 0; q < 4; ++q) blockred[blockIdx.x * 4 + q] = s[q][0];
+    // one canvas: its box is the box of all vertices (keys as in k_canvas_bbox)
+    if (bb && threadIdx.x < 4) atomicMin(&bb[threadIdx.x], dkey(s[threadIdx.x][0]));
 }
 
 // Per-canvas bounding boxes: bb[4 q + 0..3] = keys of min x, -max x, min y,
@@ -210,15 +215,10 @@ __global__ __launch_bounds__(256) void k_edges(int64_t R, const int64_t *rvo, in
                                                const double *vx, const double *vy,
                                                const int32_t *ring_poly, const CanvasDesc *cds, int nc,
                                                Edge *edges, uint32_t *epoly, int32_t *erow0,
-                                               uint64_t *nrows, unsigned long long *sumw)
+                                               uint64_t *nrows)
 {
     const int64_t nth = (int64_t)gridDim.x * blockDim.x;
-    // every lane runs the same number of iterations (wave sum at the end)
-    const int64_t iters = (V + nth - 1) / nth;
-    unsigned long long wsum = 0;
-    for (int64_t it = 0; it < iters; ++it) {
-        const int64_t j = it * nth + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-        if (j >= V) break;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < V; j += nth) {
         // ring of vertex j: rvo[r] <= j < rvo[r+1]
         int64_t lo = 0, hi = R;
         while (hi - lo > 1) {
@@ -242,32 +242,27 @@ __global__ __launch_bounds__(256) void k_edges(int64_t R, const int64_t *rvo, in
         int32_t r1 = (int32_t)fmax(0.0, fmin(f1, (double)(m.H - 1)));
         erow0[j] = r0;
         nrows[j] = (uint64_t)(r1 - r0 + 1);
-        // footprint widths over the edge's rows: bounds the boundary index
-        const double ulo = __dmul_rn(__dsub_rn(e.xlo, m.X0), m.sx);
-        const double uhi = __dmul_rn(__dsub_rn(e.xhi, m.X0), m.sx);
-        for (int32_t r = r0; r <= r1; ++r) {
-            int32_t c0, c1;
-            row_footprint(m, ulo, uhi, vlo, vhi, r, c0, c1);
-            wsum += (unsigned long long)(c1 - c0 + 1);
-        }
     }
-    for (int d = 32; d > 0; d >>= 1) wsum += (unsigned long long)__shfl_xor(wsum, d, 64);
-    if ((threadIdx.x & 63) == 0 && wsum) atomicAdd(sumw, wsum);
 }
 
 // ------------------------------------------------------------ (edge,row) entries
+
+// One entry per (edge, row): footprint, flags, sort key, edge id and the
+// identity permutation.  Edges spanning few rows are expanded by their own
+// lane; an edge spanning many rows (a long vertical boundary) is expanded by
+// its whole wave, so no lane walks thousands of rows alone.
+constexpr uint64_t LANE_ROWS = 16;
 
 __global__ __launch_bounds__(256) void k_entries(int64_t V, const Edge *edges, const uint32_t *epoly,
                                                  const int32_t *erow0, const uint64_t *nrows,
                                                  const uint64_t *off, const CanvasDesc *cds, int nc,
                                                  int cbits, int pbits,
                                                  uint64_t *keys, uint32_t *vals, uint32_t *ent_c,
-                                                 uint8_t *ent_f)
+                                                 uint8_t *ent_f, uint32_t *perm)
 {
+    const int lane = threadIdx.x & 63;
     const int64_t nth = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < V; j += nth) {
-        const uint64_t nr = nrows[j];
-        if (nr == 0) continue;
+    auto expand = [&](int64_t j, uint64_t t0, uint64_t dt, uint64_t nr) {
         const Edge e = edges[j];
         const bool horiz = (e.ylo == e.yhi);
         const CanvasDesc &m = cds[canvas_of_poly(cds, nc, epoly[j])];
@@ -277,7 +272,7 @@ __global__ __launch_bounds__(256) void k_entries(int64_t V, const Edge *edges, c
         const double vhi = __dmul_rn(__dsub_rn(e.yhi, m.Y0), m.sy);
         const uint64_t poly = (uint64_t)((int64_t)epoly[j] - m.poly_base);
         const uint64_t base = off[j];
-        for (uint64_t t = 0; t < nr; ++t) {
+        for (uint64_t t = t0; t < nr; t += dt) {
             const int32_t r = erow0[j] + (int32_t)t;
             const double b0 = (double)r - MARGIN, b1 = (double)r + 1.0 + MARGIN;
             int32_t c0, c1;
@@ -288,45 +283,47 @@ __global__ __launch_bounds__(256) void k_entries(int64_t V, const Edge *edges, c
             const uint64_t idx = base + t;
             keys[idx] = ((uint64_t)(m.row_base + r) << (pbits + cbits)) | (poly << cbits) | (uint64_t)c0;
             vals[idx] = (uint32_t)j;
+            perm[idx] = (uint32_t)idx;
             ent_c[idx] = (uint32_t)c0 | ((uint32_t)c1 << 16);
             ent_f[idx] = (span ? F_SPAN : 0) | (w ? F_W : 0) | (horiz ? F_HORIZ : 0);
+        }
+    };
+    // every lane runs the same number of iterations (the wave steps below)
+    const int64_t iters = (V + nth - 1) / nth;
+    for (int64_t it = 0; it < iters; ++it) {
+        const int64_t j = it * nth + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        const uint64_t nr = j < V ? nrows[j] : 0;
+        if (nr > 0 && nr <= LANE_ROWS) expand(j, 0, 1, nr);
+        unsigned long long longs = __ballot(nr > LANE_ROWS);
+        while (longs) {
+            const int src = __ffsll((long long)longs) - 1;
+            longs &= longs - 1;
+            const int64_t jj = __shfl(j, src, 64);
+            const uint64_t nn = __shfl(nr, src, 64);
+            expand(jj, (uint64_t)lane, 64, nn);
         }
     }
 }
 
-// After the sort, vals holds the edge id and a second array the permutation;
-// gather the per-entry payload into sorted order.
-__global__ void k_gather_entries(int64_t T, const uint32_t *perm, const uint32_t *ent_c,
-                                 const uint8_t *ent_f, const uint64_t *skeys, int cbits, uint64_t pmask,
-                                 uint32_t *s_c, uint8_t *s_f, uint32_t *s_poly)
-{
-    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < T; i += nth) {
-        uint32_t p = perm[i];
-        s_c[i] = ent_c[p];
-        s_f[i] = ent_f[p];
-        s_poly[i] = (uint32_t)((skeys[i] >> cbits) & pmask);
-    }
-}
-
-__global__ void k_gather_u32(int64_t T, const uint32_t *perm, const uint32_t *src, uint32_t *dst)
-{
-    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < T; i += nth) dst[i] = src[perm[i]];
-}
-
-__global__ void k_iota(int64_t T, uint32_t *v)
-{
-    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < T; i += nth) v[i] = (uint32_t)i;
-}
-
-__global__ void k_row_off(int64_t T, const uint64_t *skeys, int shift, int64_t H, uint32_t *row_off)
+// After the sort: per sorted entry, its footprint, flags, polygon and edge
+// id in sorted order, and the first entry of every row (rows between the
+// previous entry's row and this one's start here).
+__global__ void k_gather(int64_t T, const uint32_t *perm, const uint32_t *ent_c, const uint8_t *ent_f,
+                         const uint32_t *vals, const uint64_t *skeys, int cbits, uint64_t pmask, int rshift,
+                         int64_t H, uint32_t *s_c, uint8_t *s_f, uint32_t *s_poly, uint32_t *s_edge,
+                         uint32_t *row_off)
 {
     const int64_t nth = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= T; i += nth) {
-        int64_t ri = (i < T) ? (int64_t)(skeys[i] >> shift) : (int64_t)H;
-        int64_t rp = (i == 0) ? -1 : (int64_t)(skeys[i - 1] >> shift);
+        if (i < T) {
+            const uint32_t p = perm[i];
+            s_c[i] = ent_c[p];
+            s_f[i] = ent_f[p];
+            s_edge[i] = vals[p];
+            s_poly[i] = (uint32_t)((skeys[i] >> cbits) & pmask);
+        }
+        const int64_t ri = (i < T) ? (int64_t)(skeys[i] >> rshift) : H;
+        const int64_t rp = (i == 0) ? -1 : (int64_t)(skeys[i - 1] >> rshift);
         for (int64_t rr = rp + 1; rr <= ri; ++rr) row_off[rr] = (uint32_t)i;
     }
 }
@@ -423,12 +420,14 @@ struct RowShared {
     uint32_t *nint;     // number of footprint-union intervals of the row
     uint32_t *nlong;    // long runs deferred to whole waves, and their starts
     uint32_t *longq;
+    const unsigned long long *nrec;   // records of the row (set by the count phase)
+    int W;              // width of the row's canvas
 };
 
 // Runs longer than this are processed by a whole wave (lane-parallel scans)
 // instead of one thread; up to LONGQ of them per row, the rest serially.
-constexpr int LONG_RUN = 24;
-constexpr int LONGQ = 64;
+constexpr int LONG_RUN = 8;
+constexpr int LONGQ = 128;
 
 __device__ __forceinline__ size_t tile_index(int Wt, int c, int r)
 {
@@ -453,6 +452,19 @@ __device__ __forceinline__ uint32_t pre_op(uint32_t a, uint32_t b)
 __device__ __forceinline__ uint32_t pre_excl(const RowData &D, int q)
 {
     return q == 0 ? 0u : D.pre[q - 1];
+}
+
+// Slot of a new record of column col (sa holds the exclusive record bases
+// of the row's columns, sb the fill counters), and CAND_LAST when it takes
+// the column's last slot.  A pixel's records are in no particular polygon
+// order; the probes order their matches where order matters.
+__device__ __forceinline__ uint64_t rec_slot(const RowShared &L, int col, uint64_t rec_base_r, uint32_t &last)
+{
+    const int32_t k = atomicAdd(&L.sb[cix(col)], 1);
+    const int32_t b = L.sa[cix(col)];
+    const int32_t e = (col + 1 < L.W) ? L.sa[cix(col + 1)] : (int32_t)*L.nrec;
+    last = (k == e - b - 1) ? CAND_LAST : 0u;
+    return rec_base_r + (uint64_t)b + (uint64_t)k;
 }
 
 // Records of one run at one column.  A point p of the pixel is inside the
@@ -486,7 +498,8 @@ __device__ __forceinline__ void column_record(const RowArgs &A, const RowData &D
         nloc_tot += nloc;
         return;
     }
-    const uint64_t slot = rec_base_r + (uint64_t)L.sa[cix(col)] + (uint64_t)atomicAdd(&L.sb[cix(col)], 1);
+    uint32_t last;
+    const uint64_t slot = rec_slot(L, col, rec_base_r, last);
     uint64_t eoff = 0;
     if (nloc) {
         eoff = loc_base_r + atomicAdd(L.locfill, nloc);
@@ -496,7 +509,7 @@ __device__ __forceinline__ void column_record(const RowArgs &A, const RowData &D
     }
     Cand cd;
     cd.poly = D.poly[i];
-    cd.meta = S | ((nloc & 0x7fffu) << 2) | ((npart & 0x7fffu) << 17);
+    cd.meta = S | last | ((nloc & 0x7fffu) << 2) | ((npart & 0x7fffu) << 17);
     cd.eoff = (uint32_t)eoff;
     cd.poff = (uint32_t)(part_base_r + (ps & 0x7fffffffu));
     A.cands[slot] = cd;
@@ -512,10 +525,11 @@ __device__ void claimant_walk(const RowArgs &A, const RowData &D, const RowShare
     for (int q = i; q < je; ++q) par ^= (D.f[q] & F_W) ? 1u : 0u;
     auto emit = [&](int col) {
         if (!EMIT) { atomicAdd(&L.sa[cix(col)], 1); return; }
-        const uint64_t slot = rec_base_r + (uint64_t)L.sa[cix(col)] + (uint64_t)atomicAdd(&L.sb[cix(col)], 1);
+        uint32_t last;
+        const uint64_t slot = rec_slot(L, col, rec_base_r, last);
         Cand cd;
         cd.poly = D.poly[i];
-        cd.meta = CAND_S;
+        cd.meta = CAND_S | last;
         cd.eoff = 0;
         cd.poff = 0;
         A.cands[slot] = cd;
@@ -868,10 +882,11 @@ __device__ void process_row(const RowArgs &A, const RowData &D, const RowShared 
             for (int c = tid; c < W; c += ROW_THREADS) {
                 const uint32_t w = L.sx[cix(c)];
                 if ((w & BFLAG) && (w & ~BFLAG)) {
-                    const uint64_t slot = rec_base_r + (uint64_t)L.sa[cix(c)] + (uint64_t)atomicAdd(&L.sb[cix(c)], 1);
+                    uint32_t last;
+                    const uint64_t slot = rec_slot(L, c, rec_base_r, last);
                     Cand cd;
                     cd.poly = (w & ~BFLAG) - 1u;
-                    cd.meta = CAND_S;
+                    cd.meta = CAND_S | last;
                     cd.eoff = 0;
                     cd.poff = 0;
                     A.cands[slot] = cd;
@@ -885,25 +900,15 @@ __device__ void process_row(const RowArgs &A, const RowData &D, const RowShared 
     }
     __syncthreads();
 
-    // phase 6: order each pixel's records by polygon, flag the last one,
-    //          write the canvas row (tile-major)
+    // phase 6: write the canvas row (tile-major); a boundary pixel points
+    //          at its first record (the last one carries CAND_LAST)
     for (int c = tid; c < W; c += ROW_THREADS) {
         uint32_t word = L.sx[cix(c)];
         if (word & BFLAG) {
-            const uint64_t base = rec_base_r + (uint64_t)L.sa[cix(c)];
-            const int n = L.sb[cix(c)];
-            if (n <= 0) { atomicOr(A.errflags, 8u); word = 0; }
-            else {
-                Cand *cs = A.cands + base;
-                for (int a = 1; a < n; ++a) {
-                    Cand key = cs[a];
-                    int b = a - 1;
-                    while (b >= 0 && cs[b].poly > key.poly) { cs[b + 1] = cs[b]; --b; }
-                    cs[b + 1] = key;
-                }
-                cs[n - 1].meta |= CAND_LAST;
-                word = BFLAG | (uint32_t)base;
-            }
+            const int32_t b = L.sa[cix(c)];
+            const int32_t e = (c + 1 < W) ? L.sa[cix(c + 1)] : (int32_t)*L.nrec;
+            if (e - b <= 0 || L.sb[cix(c)] != e - b) { atomicOr(A.errflags, 8u); word = 0; }
+            else word = BFLAG | (uint32_t)(rec_base_r + (uint64_t)b);
         }
         cells_q[tile_index(Wt, c, r_local)] = word;
     }
@@ -928,6 +933,7 @@ __global__ __launch_bounds__(ROW_THREADS) void k_rows(RowArgs A)
     L.nint = &s_nint;
     L.nlong = &s_nlong;
     L.longq = s_longq;
+    L.nrec = &s_nrec;
     uint32_t *lpoly = L.sx + cwmax;
     uint32_t *lc = lpoly + cap;
     uint32_t *ledge = lc + cap;
@@ -946,6 +952,7 @@ __global__ __launch_bounds__(ROW_THREADS) void k_rows(RowArgs A)
         if (n < A.min_n || n > A.max_n) continue;
         const CanvasDesc &cd = A.cds[canvas_of_row(A.cds, A.nc, r)];
         const int W = cd.W, Wt = cd.Wt;
+        L.W = W;
         uint32_t *cells_q = A.cells + cd.cell_off;
         const int r_local = (int)(r - cd.row_base);
         const int cw = col_words(W);
@@ -1168,7 +1175,7 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
     if (M > 0 || R > 0 || V > 0) {
         hipLaunchKernelGGL(k_validate, dim3(RED_BLOCKS), dim3(256), 0, st, M, R, polys->poly_ring_off,
                            polys->ring_vtx_off, V, polys->vx, polys->vy, (int32_t *)rp.p,
-                           (double *)br.p, d_err);
+                           (double *)br.p, d_err, nc == 1 ? d_bb : nullptr);
         SPADE_HIP(ctx, hipGetLastError());
     }
     // Pinned staging: error flags, canvas descriptors, bounding-box keys.
@@ -1195,7 +1202,7 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
     SPADE_HIP(ctx, hipMemcpyAsync(dcd.p, hcd, sizeof(CanvasDesc) * (size_t)nc, hipMemcpyHostToDevice, st));
     std::vector<int64_t> nverts((size_t)nc, 0);
     std::vector<int64_t> pro, rvo;
-    if (V > 0) {
+    if (V > 0 && nc > 1) {
         hipLaunchKernelGGL(k_canvas_bbox, dim3(grid_for((V + BB_SPAN - 1) / BB_SPAN)), dim3(256), 0, st, R, polys->ring_vtx_off, V,
                            polys->vx, polys->vy, (const int32_t *)rp.p, (const CanvasDesc *)dcd.p, nc, d_bb);
         SPADE_HIP(ctx, hipGetLastError());
@@ -1317,14 +1324,14 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
     int32_t *erow0 = (int32_t *)(epoly + Vs);
     uint64_t *eoff = (uint64_t *)(((uintptr_t)(erow0 + Vs) + 7) & ~(uintptr_t)7);
     // per-row counters (8 arrays of H + 1), then the global counters:
-    // [0..3] row-pass allocation, [4] footprint widths, [5] boundary pixels
+    // [0..3] row-pass allocation
     DevBuf &drc = ctx->scratch[S_ROWCNT];
     if (ensure(ctx, drc, 8 * 8 * ((size_t)H + 1) + 64)) return SPADE_E_NOMEM;
     unsigned long long *gctr = (unsigned long long *)((uint64_t *)drc.p + 8 * ((size_t)H + 1));
     SPADE_HIP(ctx, hipMemsetAsync(gctr, 0, 64, st));
     hipLaunchKernelGGL(k_edges, dim3(grid_for(V)), dim3(256), 0, st, R, polys->ring_vtx_off, V,
                        polys->vx, polys->vy, (const int32_t *)rp.p, d_cds, nc, (Edge *)cv->edges.p, epoly,
-                       erow0, nrows, gctr + 4);
+                       erow0, nrows);
     SPADE_HIP(ctx, hipGetLastError());
     SPADE_HIP(ctx, hipMemsetAsync(nrows + V, 0, sizeof(uint64_t), st));
 
@@ -1335,10 +1342,8 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
     SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(cub.p, tb, nrows, eoff, (int)(V + 1), st));
     uint64_t *hT = (uint64_t *)ensure_pinned(ctx, 64);
     SPADE_HIP(ctx, hipMemcpyAsync(hT, eoff + V, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
-    SPADE_HIP(ctx, hipMemcpyAsync(hT + 1, gctr + 4, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
     SPADE_HIP(ctx, hipStreamSynchronize(st));
     const uint64_t T = hT[0];
-    const uint64_t sumw = hT[1];
     if (T >= 0x7fffffffULL) return set_error(ctx, SPADE_E_UNSUPPORTED, "too many (edge,row) entries; lower the canvas height");
 
     const int cbits = std::max(1, bits_for((uint64_t)W - 1));
@@ -1363,9 +1368,7 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
     uint8_t *ent_f = (uint8_t *)df.p, *s_f = ent_f + Ts;
     hipLaunchKernelGGL(k_entries, dim3(grid_for(V)), dim3(256), 0, st, V, (const Edge *)cv->edges.p,
                        epoly, erow0, nrows, eoff, d_cds, nc, cbits, pbits, (uint64_t *)dk.p, (uint32_t *)dv.p,
-                       ent_c, ent_f);
-    SPADE_HIP(ctx, hipGetLastError());
-    hipLaunchKernelGGL(k_iota, dim3(grid_for((int64_t)T)), dim3(256), 0, st, (int64_t)T, perm);
+                       ent_c, ent_f, perm);
     SPADE_HIP(ctx, hipGetLastError());
 
     // sort entries by (row, polygon, c0); stable, so ties keep edge order.
@@ -1381,18 +1384,12 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
                                                           (uint64_t *)dk2.p, (const uint32_t *)perm,
                                                           perm2, (int)T, 0, kbits, st));
     }
-    // sorted edge ids: vals[perm2[i]]
-    hipLaunchKernelGGL(k_gather_entries, dim3(grid_for((int64_t)T)), dim3(256), 0, st, (int64_t)T,
-                       perm2, ent_c, ent_f, (const uint64_t *)dk2.p, cbits,
-                       (pbits >= 64) ? ~0ULL : ((1ULL << pbits) - 1), s_c, s_f, s_poly);
-    SPADE_HIP(ctx, hipGetLastError());
+    // sorted payload, edge ids and row starts
     uint32_t *s_edge = (uint32_t *)dv2.p;
-    hipLaunchKernelGGL(k_gather_u32, dim3(grid_for((int64_t)T)), dim3(256), 0, st, (int64_t)T,
-                       (const uint32_t *)perm2, (const uint32_t *)dv.p, s_edge);
-    SPADE_HIP(ctx, hipGetLastError());
-    const int rshift = cbits + pbits;
-    hipLaunchKernelGGL(k_row_off, dim3(grid_for((int64_t)T + 1)), dim3(256), 0, st, (int64_t)T,
-                       (const uint64_t *)dk2.p, rshift, H, (uint32_t *)drow.p);
+    hipLaunchKernelGGL(k_gather, dim3(grid_for((int64_t)T + 1)), dim3(256), 0, st, (int64_t)T, perm2, ent_c,
+                       ent_f, (const uint32_t *)dv.p, (const uint64_t *)dk2.p, cbits,
+                       (pbits >= 64) ? ~0ULL : ((1ULL << pbits) - 1), cbits + pbits, H, s_c, s_f, s_poly, s_edge,
+                       (uint32_t *)drow.p);
     SPADE_HIP(ctx, hipGetLastError());
 
     uint64_t *row_nrec = (uint64_t *)drc.p;
@@ -1462,24 +1459,26 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
         return SPADE_OK;
     };
 
-    // One row pass: rows reserve their output ranges with atomics inside
-    // bounds derived from the entries (records <= 2 * sum of footprint widths
-    // unless interiors overlap, local edges <= that sum, partial spans <= T).
-    // The coarse level is built right behind it, and one synchronisation
-    // reads the counters and flags of both.
+    // One row pass: rows reserve their output ranges with atomics inside the
+    // capacity the canvas already holds (at least a guess from the entry
+    // count; partial spans <= T exactly).  A row that would overflow is
+    // abandoned and the host redoes the canvas with exact sizes (which then
+    // stay allocated for the next build).  The coarse level is built right
+    // behind the pass, and one synchronisation reads the counters and flags
+    // of both.
     bool done_single = false;
     uint64_t nrec = 0, nloc = 0, npart = 0, nbp = 0;
     unsigned ef = 0;
     {
         ra.alloc = 1;
         ra.gctr = gctr;
-        ra.cap_rec = 2 * sumw + 16;
-        ra.cap_loc = sumw + 16;
-        ra.cap_part = T + 16;
-        if (ensure(ctx, cv->cands, sizeof(Cand) * (size_t)ra.cap_rec) ||
-            ensure(ctx, cv->ledges, sizeof(Edge) * (size_t)ra.cap_loc) ||
-            ensure(ctx, cv->pspan, sizeof(double2) * (size_t)ra.cap_part))
+        if (ensure(ctx, cv->cands, sizeof(Cand) * (size_t)(2 * T + 1024)) ||
+            ensure(ctx, cv->ledges, sizeof(Edge) * (size_t)(2 * T + 1024)) ||
+            ensure(ctx, cv->pspan, sizeof(double2) * (size_t)(T + 16)))
             return SPADE_E_NOMEM;
+        ra.cap_rec = std::min<uint64_t>(cv->cands.cap / sizeof(Cand), (uint64_t)BFLAG - 1);
+        ra.cap_loc = std::min<uint64_t>(cv->ledges.cap / sizeof(Edge), 0xffffffffULL);
+        ra.cap_part = std::min<uint64_t>(cv->pspan.cap / sizeof(double2), 0xffffffffULL);
         ra.cands = (Cand *)cv->cands.p;
         ra.ledges = (Edge *)cv->ledges.p;
         ra.pspan = (double2 *)cv->pspan.p;
