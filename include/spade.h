@@ -77,7 +77,10 @@ typedef struct {
  *   vx, vy        [ring_vtx_off[n_rings]]: vertex coordinates; a ring is
  *                  closed implicitly (do not repeat the first vertex; a
  *                  repeated one is a zero-length edge and is ignored).
- * n_rings is passed explicitly so that the offsets can be validated. */
+ * n_rings is passed explicitly so that the offsets can be validated.
+ * n_vertices: the vertex count ring_vtx_off[n_rings] when the caller knows it
+ * (saves reading it back from the device); <= 0 means unknown.  A positive
+ * value that differs from ring_vtx_off[n_rings] is SPADE_E_INVALID. */
 typedef struct {
     int64_t n_polys;
     int64_t n_rings;
@@ -85,6 +88,7 @@ typedef struct {
     const int64_t *ring_vtx_off;
     const double *vx;
     const double *vy;
+    int64_t n_vertices;
 } spade_polys;
 
 typedef struct spade_ctx spade_ctx;

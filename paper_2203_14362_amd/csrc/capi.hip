@@ -99,6 +99,8 @@ static int check_polys(spade_ctx *ctx, const spade_polys *p)
         return set_error(ctx, SPADE_E_INVALID, "ring_vtx_off is NULL");
     if (p->n_rings > 0 && (!p->ring_vtx_off || !p->vx || !p->vy))
         return set_error(ctx, SPADE_E_INVALID, "ring_vtx_off / vx / vy is NULL");
+    if (p->n_polys > 0 && !p->ring_vtx_off)
+        return set_error(ctx, SPADE_E_INVALID, "ring_vtx_off is NULL");
     if (p->n_polys > 0 && p->poly_ring_off == nullptr && p->n_rings == 0)
         return set_error(ctx, SPADE_E_INVALID, "polygons without rings");
     return SPADE_OK;
@@ -146,6 +148,9 @@ void spade_ctx_destroy(spade_ctx *ctx)
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     for (auto &e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
+    if (ctx->fork) (void)hipEventDestroy(ctx->fork);
+    if (ctx->join) (void)hipEventDestroy(ctx->join);
+    if (ctx->side) (void)hipStreamDestroy(ctx->side);
     delete ctx;
 }
 

@@ -134,6 +134,8 @@ struct spade_ctx {
     bool timed_raster = false;              // last query rasterised under timing
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     size_t pinned_cap = 0;
+    hipStream_t side = nullptr;             // internal stream for overlapped launches
+    hipEvent_t fork = nullptr, join = nullptr;
 };
 
 namespace spade {

@@ -80,6 +80,17 @@ __device__ __forceinline__ unsigned long long dkey(double v)
 
 // ------------------------------------------------------------ validation
 
+// Clears the build's flags and counters in one launch: error flags, the
+// per-canvas box keys (to the maximum key), the row-pass counters.
+__global__ void k_init(unsigned *errflags, unsigned long long *bb, int64_t nbb, unsigned long long *gctr)
+{
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    if (tid == 0) *errflags = 0u;
+    if (tid < 8) gctr[tid] = 0ull;
+    for (int64_t i = tid; i < nbb; i += nth) bb[i] = ~0ull;
+}
+
 __global__ __launch_bounds__(256) void k_validate(int64_t M, int64_t R, const int64_t *pro,
                                                   const int64_t *rvo, int64_t V, const double *vx,
                                                   const double *vy, int32_t *ring_poly,
@@ -89,6 +100,11 @@ __global__ __launch_bounds__(256) void k_validate(int64_t M, int64_t R, const in
     // (per-canvas boxes are computed by k_canvas_bbox once ring_poly is known)
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    // the vertex arrays hold ring_vtx_off[R] entries: never read past them,
+    // whatever the caller's count says (a mismatch is reported)
+    const int64_t Vend = rvo[R];
+    if (tid == 0 && Vend != V) atomicOr(errflags, 64u);
+    V = min(V, Vend);
     for (int64_t k = tid; k < M; k += nth) {
         int64_t r0 = pro ? pro[k] : k, r1 = pro ? pro[k + 1] : k + 1;
         if (r0 < 0 || r1 < r0 || r1 > R) { atomicOr(errflags, 2u); continue; }
@@ -144,6 +160,7 @@ __global__ __launch_bounds__(256) void k_canvas_bbox(int64_t R, const int64_t *r
                                                      int nc, unsigned long long *bb)
 {
     const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    V = min(V, rvo[R]);
     const int64_t nspan = (V + BB_SPAN - 1) / BB_SPAN;
     // every lane runs the same number of iterations (the wave merge below)
     const int64_t iters = (nspan + nth - 1) / nth;
@@ -218,6 +235,7 @@ __global__ __launch_bounds__(256) void k_edges(int64_t R, const int64_t *rvo, in
                                                uint64_t *nrows)
 {
     const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    if (blockIdx.x == 0 && threadIdx.x == 0) nrows[V] = 0;   // zero tail of the row-count scan
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < V; j += nth) {
         // ring of vertex j: rvo[r] <= j < rvo[r+1]
         int64_t lo = 0, hi = R;
@@ -1149,9 +1167,14 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
     if (nc < 1) return set_error(ctx, SPADE_E_INVALID, "a canvas set needs at least one canvas");
     cv->nc = nc;
 
-    // vertex count
+    // vertex count: the caller's (checked on the device), else read back
     int64_t V = 0;
-    if (R > 0) {
+    if (R == 0 && polys->n_vertices > 0)
+        return set_error(ctx, SPADE_E_INVALID, "n_vertices does not match ring_vtx_off[n_rings]");
+    if (R > 0 && polys->n_vertices > 0) {
+        V = polys->n_vertices;
+        if (V >= (int64_t)0xffffffffLL) return set_error(ctx, SPADE_E_TOO_LARGE, "more than 2^32-1 vertices");
+    } else if (R > 0) {
         int64_t *h = (int64_t *)ensure_pinned(ctx, 64);
         if (!h) return set_error(ctx, SPADE_E_NOMEM, "pinned staging allocation failed");
         SPADE_HIP(ctx, hipMemcpyAsync(h, polys->ring_vtx_off + R, sizeof(int64_t), hipMemcpyDeviceToHost, st));
@@ -1166,12 +1189,15 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
     DevBuf &br = ctx->scratch[S_BLOCKRED];
     const size_t bbbytes = sizeof(unsigned long long) * 4 * (size_t)nc;
     if (ensure(ctx, rp, sizeof(int32_t) * (size_t)std::max<int64_t>(R, 1)) ||
-        ensure(ctx, br, sizeof(double) * 4 * RED_BLOCKS + 64 + bbbytes))
+        ensure(ctx, br, sizeof(double) * 4 * RED_BLOCKS + 64 + bbbytes + 64))
         return SPADE_E_NOMEM;
     unsigned *d_err = (unsigned *)((char *)br.p + sizeof(double) * 4 * RED_BLOCKS);
     unsigned long long *d_bb = (unsigned long long *)((char *)br.p + sizeof(double) * 4 * RED_BLOCKS + 64);
-    SPADE_HIP(ctx, hipMemsetAsync(d_err, 0, sizeof(unsigned), st));
-    SPADE_HIP(ctx, hipMemsetAsync(d_bb, 0xff, bbbytes, st));
+    // counters of the row pass: [0..3] allocation
+    unsigned long long *gctr = d_bb + 4 * (size_t)nc;
+    hipLaunchKernelGGL(k_init, dim3((unsigned)std::min<int64_t>((4 * (int64_t)nc + 255) / 256 + 1, 1024)), dim3(256), 0,
+                       st, d_err, d_bb, 4 * (int64_t)nc, gctr);
+    SPADE_HIP(ctx, hipGetLastError());
     if (M > 0 || R > 0 || V > 0) {
         hipLaunchKernelGGL(k_validate, dim3(RED_BLOCKS), dim3(256), 0, st, M, R, polys->poly_ring_off,
                            polys->ring_vtx_off, V, polys->vx, polys->vy, (int32_t *)rp.p,
@@ -1225,6 +1251,7 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
     if (herr[0] & 1u) return set_error(ctx, SPADE_E_INVALID, "ring_vtx_off must start at 0 and be non-decreasing");
     if (herr[0] & 2u) return set_error(ctx, SPADE_E_INVALID, "poly_ring_off must start at 0, be non-decreasing and end at n_rings");
     if (herr[0] & 4u) return set_error(ctx, SPADE_E_INVALID, "non-finite polygon vertex coordinate");
+    if (herr[0] & 64u) return set_error(ctx, SPADE_E_INVALID, "n_vertices does not match ring_vtx_off[n_rings]");
     if (V > 0) {
         if (nc > 1)
             for (int q = 0; q < nc; ++q) nverts[q] = rvo[pro[pbound[q + 1]]] - rvo[pro[pbound[q]]];
@@ -1323,17 +1350,13 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
     uint32_t *epoly = (uint32_t *)dmisc.p;
     int32_t *erow0 = (int32_t *)(epoly + Vs);
     uint64_t *eoff = (uint64_t *)(((uintptr_t)(erow0 + Vs) + 7) & ~(uintptr_t)7);
-    // per-row counters (8 arrays of H + 1), then the global counters:
-    // [0..3] row-pass allocation
+    // per-row counters of the exact path (8 arrays of H + 1)
     DevBuf &drc = ctx->scratch[S_ROWCNT];
-    if (ensure(ctx, drc, 8 * 8 * ((size_t)H + 1) + 64)) return SPADE_E_NOMEM;
-    unsigned long long *gctr = (unsigned long long *)((uint64_t *)drc.p + 8 * ((size_t)H + 1));
-    SPADE_HIP(ctx, hipMemsetAsync(gctr, 0, 64, st));
+    if (ensure(ctx, drc, 8 * 8 * ((size_t)H + 1))) return SPADE_E_NOMEM;
     hipLaunchKernelGGL(k_edges, dim3(grid_for(V)), dim3(256), 0, st, R, polys->ring_vtx_off, V,
                        polys->vx, polys->vy, (const int32_t *)rp.p, d_cds, nc, (Edge *)cv->edges.p, epoly,
                        erow0, nrows);
     SPADE_HIP(ctx, hipGetLastError());
-    SPADE_HIP(ctx, hipMemsetAsync(nrows + V, 0, sizeof(uint64_t), st));
 
     DevBuf &cub = ctx->scratch[S_CUBTMP];
     size_t tb = 0;
@@ -1400,7 +1423,6 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
     uint64_t *loc_base = rec_base + (H + 1);
     uint64_t *part_base = loc_base + (H + 1);
     uint64_t *bp_scan = part_base + (H + 1);
-    SPADE_HIP(ctx, hipMemsetAsync(drc.p, 0, 8 * 8 * ((size_t)H + 1), st));
 
     RowArgs ra{};
     ra.cds = d_cds;
@@ -1432,21 +1454,37 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
     SPADE_HIP(ctx, hipFuncSetAttribute((const void *)k_rows<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)rlds_big));
     SPADE_HIP(ctx, hipFuncSetAttribute((const void *)k_rows<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)rlds_big));
     const int rgrid = (int)std::min<int64_t>(H, 8192);
+    // Rows longer than the stage run in a second launch with the largest
+    // stage, on the context's internal stream beside the first launch (a
+    // few long border rows would otherwise add their whole latency).
+    const bool big = T > (uint64_t)ra.cap;
+    if (big && !ctx->side) {
+        SPADE_HIP(ctx, hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+        SPADE_HIP(ctx, hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
+        SPADE_HIP(ctx, hipEventCreateWithFlags(&ctx->join, hipEventDisableTiming));
+    }
     auto launch_rows = [&](bool emit) -> hipError_t {
+        hipError_t e;
+        if (big) {
+            RowArgs a2 = ra;
+            a2.cap = cap_big;
+            a2.min_n = ra.cap + 1;
+            a2.max_n = 0x7fffffff;
+            if ((e = hipEventRecord(ctx->fork, st)) != hipSuccess) return e;
+            if ((e = hipStreamWaitEvent(ctx->side, ctx->fork, 0)) != hipSuccess) return e;
+            if (emit) hipLaunchKernelGGL(k_rows<true>, dim3(rgrid), dim3(ROW_THREADS), rlds_big, ctx->side, a2);
+            else hipLaunchKernelGGL(k_rows<false>, dim3(rgrid), dim3(ROW_THREADS), rlds_big, ctx->side, a2);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            if ((e = hipEventRecord(ctx->join, ctx->side)) != hipSuccess) return e;
+        }
         RowArgs a1 = ra;
         a1.min_n = 0;
         a1.max_n = ra.cap;
         if (emit) hipLaunchKernelGGL(k_rows<true>, dim3(rgrid), dim3(ROW_THREADS), rlds, st, a1);
         else hipLaunchKernelGGL(k_rows<false>, dim3(rgrid), dim3(ROW_THREADS), rlds, st, a1);
-        hipError_t e1 = hipGetLastError();
-        if (e1 != hipSuccess || T <= (uint64_t)ra.cap) return e1;
-        RowArgs a2 = ra;
-        a2.cap = cap_big;
-        a2.min_n = ra.cap + 1;
-        a2.max_n = 0x7fffffff;
-        if (emit) hipLaunchKernelGGL(k_rows<true>, dim3(rgrid), dim3(ROW_THREADS), rlds_big, st, a2);
-        else hipLaunchKernelGGL(k_rows<false>, dim3(rgrid), dim3(ROW_THREADS), rlds_big, st, a2);
-        return hipGetLastError();
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (big) return hipStreamWaitEvent(st, ctx->join, 0);
+        return hipSuccess;
     };
     ra.cells = (uint32_t *)cv->cells.p;
 
@@ -1501,6 +1539,7 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
     }
     if (!done_single) {
         ra.alloc = 0;
+        SPADE_HIP(ctx, hipMemsetAsync(drc.p, 0, 8 * 8 * ((size_t)H + 1), st));
         SPADE_HIP(ctx, launch_rows(false));
         // per-row bases (exclusive scans over H+1 entries with a zero tail)
         tb = 0;

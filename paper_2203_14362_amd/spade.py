@@ -53,7 +53,7 @@ class _Points(ctypes.Structure):
 class _Polys(ctypes.Structure):
     _fields_ = [("n_polys", ctypes.c_int64), ("n_rings", ctypes.c_int64),
                 ("poly_ring_off", ctypes.c_void_p), ("ring_vtx_off", ctypes.c_void_p),
-                ("vx", ctypes.c_void_p), ("vy", ctypes.c_void_p)]
+                ("vx", ctypes.c_void_p), ("vy", ctypes.c_void_p), ("n_vertices", ctypes.c_int64)]
 
 
 _lib = None
@@ -140,7 +140,8 @@ class DevicePolys:
                       0 if self.poly_ring_off is None else self.poly_ring_off.data_ptr(),
                       self.ring_vtx_off.data_ptr() if self.ring_vtx_off.numel() else 0,
                       self.vx.data_ptr() if self.vx.numel() else 0,
-                      self.vy.data_ptr() if self.vy.numel() else 0)
+                      self.vy.data_ptr() if self.vy.numel() else 0,
+                      int(self.vx.numel()))
 
 
 def _compact(buf, m):
