@@ -20,7 +20,7 @@ import math
 import os
 import threading
 
-DEFAULT_CANDIDATES = (48.0, 96.0, 192.0, 384.0)
+DEFAULT_CANDIDATES = (32.0, 40.0, 48.0, 56.0, 64.0, 96.0, 128.0, 192.0, 384.0)
 
 
 def _bucket(n: int) -> int:

@@ -1295,7 +1295,7 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
         d.Wt = (W + 15) / 16;
         const int Ht = (H + 15) / 16;
         // coarse grid: blocks of 2^blog pixels, as fine as the probe's LDS allows
-        int blog = 4;
+        int blog = 3;
         const size_t cbudget = coarse_lds_budget(d.M);
         while (blog < 6 && (size_t)((W + (1 << blog) - 1) >> blog) * ((H + (1 << blog) - 1) >> blog) * 2 > cbudget)
             ++blog;

@@ -339,8 +339,7 @@ class SpadeExecutor:
         """Pick the canvas resolution (pixels per vertex) for every worker
         from timed batches of `sample` on worker 0; returns (ppv, {ppv: ms})."""
         import time as _time
-        from .autotune import DEFAULT_CANDIDATES
-        cands = tuple(candidates or DEFAULT_CANDIDATES)
+        cands = tuple(candidates or (48.0, 96.0, 192.0, 384.0))
         times = {}
         for ppv in cands:
             self.ctxs[0].set_pixels_per_vertex(ppv)
