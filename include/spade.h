@@ -116,6 +116,15 @@ const char *spade_last_error(const spade_ctx *ctx);
  * 1 <= width <= 8192, 1 <= height <= 16384. */
 int spade_ctx_set_canvas_size(spade_ctx *ctx, int32_t width, int32_t height);
 
+/* Graph replay of canvas builds (default on).  A canvas rebuilt with the
+ * same launch parameters as its previous build (same sizes, same buffers:
+ * typically the same polygon set again) replays the build's kernel launches
+ * from a HIP graph captured on the second such build instead of launching
+ * them one by one; every kernel still runs.  on == 0 launches eagerly. */
+int spade_ctx_set_graphs(spade_ctx *ctx, int on);
+/* Graphs captured and replays launched on ctx so far (either may be NULL). */
+int spade_ctx_graph_stats(const spade_ctx *ctx, int64_t *captures, int64_t *replays);
+
 /* Phase timing (tracing aid).  on != 0 makes later query calls record HIP
  * events on ctx's stream around the rasterisation and around the probe
  * kernel; spade_ctx_last_timing waits for the last probe and returns both

@@ -143,6 +143,7 @@ void spade_ctx_destroy(spade_ctx *ctx)
         free_buf(ctx->plain->coarse);
         free_buf(ctx->plain->dcds);
         free_buf(ctx->plain->desc);
+        drop_graph(ctx->plain);
         delete ctx->plain;
     }
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
@@ -151,6 +152,7 @@ void spade_ctx_destroy(spade_ctx *ctx)
     if (ctx->fork) (void)hipEventDestroy(ctx->fork);
     if (ctx->join) (void)hipEventDestroy(ctx->join);
     if (ctx->side) (void)hipStreamDestroy(ctx->side);
+    if (ctx->capture) (void)hipStreamDestroy(ctx->capture);
     delete ctx;
 }
 
@@ -174,6 +176,22 @@ int spade_ctx_set_canvas_size(spade_ctx *ctx, int32_t width, int32_t height)
         return set_error(ctx, SPADE_E_INVALID, "canvas size must be 0x0 or within 1..8192 x 1..16384");
     ctx->canvas_w = width;
     ctx->canvas_h = height;
+    return SPADE_OK;
+}
+
+int spade_ctx_set_graphs(spade_ctx *ctx, int on)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    ctx->graphs = on != 0;
+    return SPADE_OK;
+}
+
+int spade_ctx_graph_stats(const spade_ctx *ctx, int64_t *captures, int64_t *replays)
+{
+    if (!ctx) return SPADE_E_INVALID;
+    if (captures) *captures = ctx->graph_captures;
+    if (replays) *replays = ctx->graph_replays;
     return SPADE_OK;
 }
 
@@ -233,6 +251,7 @@ void spade_canvas_destroy(spade_canvas *cv)
     free_buf(cv->coarse);
     free_buf(cv->dcds);
     free_buf(cv->desc);
+    drop_graph(cv);
     delete cv;
 }
 

@@ -115,6 +115,8 @@ struct spade_canvas {
     int64_t n_elist = 0;
     int64_t n_edges = 0;
     spade::DevBuf cells, cands, ledges, pspan, edges, coarse, desc;
+    std::vector<uint64_t> gkey;               // launch parameters of the last build
+    hipGraphExec_t gexec = nullptr;           // its captured launches (second build on)
     size_t bytes() const
     {
         return cells.cap + cands.cap + ledges.cap + pspan.cap + coarse.cap + desc.cap;
@@ -136,6 +138,9 @@ struct spade_ctx {
     size_t pinned_cap = 0;
     hipStream_t side = nullptr;             // internal stream for overlapped launches
     hipEvent_t fork = nullptr, join = nullptr;
+    hipStream_t capture = nullptr;          // internal stream graphs are captured on
+    bool graphs = true;                     // replay repeated canvas builds from graphs
+    int64_t graph_captures = 0, graph_replays = 0;
 };
 
 namespace spade {
@@ -153,6 +158,7 @@ void *ensure_pinned(spade_ctx *ctx, size_t bytes);
 void free_buf(DevBuf &b);
 
 int build_canvas(spade_ctx *ctx, const spade_polys *polys, spade_canvas *cv);
+void drop_graph(spade_canvas *cv);
 // Rasterises polygons [pbound[q], pbound[q+1]) into canvas q, q < nc.
 int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *pbound, spade_canvas *cv);
 CanvasView view_of(const spade_canvas *cv, int q);

@@ -1119,6 +1119,66 @@ static int bits_for(uint64_t v)   // bits needed to store values 0..v
     return b;
 }
 
+void drop_graph(spade_canvas *cv)
+{
+    if (cv->gexec) (void)hipGraphExecDestroy(cv->gexec);
+    cv->gexec = nullptr;
+    cv->gkey.clear();
+}
+
+// Runs `enqueue` (a fixed sequence of launches on ctx's stream) for a canvas
+// build whose launch parameters are `key`.  The first build with a key runs
+// eagerly and remembers it; the second captures the launches into a graph;
+// later builds with the same key replay the graph.  Any capture failure falls
+// back to eager launches.  The graph holds no memory-set nodes (buffers are
+// cleared by kernels), so replays match eager runs.
+// The capture runs on an internal stream (the caller's may be the null
+// stream, which cannot be captured): `qs`, the stream the launches go to,
+// points there during the capture; the graph is then launched on ctx's stream.
+template <typename F>
+static hipError_t run_captured(spade_ctx *ctx, spade_canvas *cv, const std::vector<uint64_t> &key,
+                               hipStream_t &qs, F &&enqueue)
+{
+    hipStream_t st = ctx->stream;
+    qs = st;
+    if (!ctx->graphs) return enqueue();
+    if (cv->gexec && cv->gkey == key) {
+        ++ctx->graph_replays;
+        return hipGraphLaunch(cv->gexec, st);
+    }
+    if (cv->gkey != key) {
+        drop_graph(cv);
+        cv->gkey = key;
+        return enqueue();
+    }
+    if (!ctx->capture && hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        ctx->capture = nullptr;
+        return enqueue();
+    }
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        return enqueue();
+    }
+    qs = ctx->capture;
+    const hipError_t e1 = enqueue();
+    const hipError_t e2 = hipStreamEndCapture(ctx->capture, &g);
+    qs = st;
+    hipGraphExec_t ex = nullptr;
+    hipError_t e3 = hipErrorUnknown;
+    if (e1 == hipSuccess && e2 == hipSuccess && g) e3 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (e3 != hipSuccess) {
+        (void)hipGetLastError();
+        cv->gkey.clear();
+        return enqueue();
+    }
+    cv->gexec = ex;
+    ++ctx->graph_captures;
+    return hipGraphLaunch(ex, st);
+}
+
 static int grid_for(int64_t n, int64_t cap = 65536)
 {
     int64_t g = (n + 255) / 256;
@@ -1389,31 +1449,32 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
     uint32_t *ent_c = (uint32_t *)dc.p, *s_c = ent_c + Ts, *perm = s_c + Ts, *perm2 = perm + Ts;
     uint32_t *s_poly = perm2 + Ts;
     uint8_t *ent_f = (uint8_t *)df.p, *s_f = ent_f + Ts;
-    hipLaunchKernelGGL(k_entries, dim3(grid_for(V)), dim3(256), 0, st, V, (const Edge *)cv->edges.p,
-                       epoly, erow0, nrows, eoff, d_cds, nc, cbits, pbits, (uint64_t *)dk.p, (uint32_t *)dv.p,
-                       ent_c, ent_f, perm);
-    SPADE_HIP(ctx, hipGetLastError());
-
-    // sort entries by (row, polygon, c0); stable, so ties keep edge order.
+    // sort entries by (row, polygon, c0) with the identity permutation as
+    // values, then gather edge ids and payload
     const int kbits = cbits + pbits + rbits;
-    {
-        // sort (key, perm) to get the permutation, then gather edge ids and payload
-        size_t tbytes = 0;
-        SPADE_HIP(ctx, hipcub::DeviceRadixSort::SortPairs(nullptr, tbytes, (const uint64_t *)dk.p,
-                                                          (uint64_t *)dk2.p, (const uint32_t *)perm,
-                                                          perm2, (int)T, 0, kbits, st));
-        if (ensure(ctx, cub, tbytes)) return SPADE_E_NOMEM;
-        SPADE_HIP(ctx, hipcub::DeviceRadixSort::SortPairs(cub.p, tbytes, (const uint64_t *)dk.p,
-                                                          (uint64_t *)dk2.p, (const uint32_t *)perm,
-                                                          perm2, (int)T, 0, kbits, st));
-    }
-    // sorted payload, edge ids and row starts
+    hipStream_t qs = st;   // stream of the build's launches (see run_captured)
+    size_t tbytes = 0;
+    SPADE_HIP(ctx, hipcub::DeviceRadixSort::SortPairs(nullptr, tbytes, (const uint64_t *)dk.p,
+                                                      (uint64_t *)dk2.p, (const uint32_t *)perm,
+                                                      perm2, (int)T, 0, kbits, st));
+    if (ensure(ctx, cub, tbytes)) return SPADE_E_NOMEM;
     uint32_t *s_edge = (uint32_t *)dv2.p;
-    hipLaunchKernelGGL(k_gather, dim3(grid_for((int64_t)T + 1)), dim3(256), 0, st, (int64_t)T, perm2, ent_c,
-                       ent_f, (const uint32_t *)dv.p, (const uint64_t *)dk2.p, cbits,
-                       (pbits >= 64) ? ~0ULL : ((1ULL << pbits) - 1), cbits + pbits, H, s_c, s_f, s_poly, s_edge,
-                       (uint32_t *)drow.p);
-    SPADE_HIP(ctx, hipGetLastError());
+    auto enqueue_entries = [&]() -> hipError_t {
+        hipLaunchKernelGGL(k_entries, dim3(grid_for(V)), dim3(256), 0, qs, V, (const Edge *)cv->edges.p,
+                           epoly, erow0, nrows, eoff, d_cds, nc, cbits, pbits, (uint64_t *)dk.p, (uint32_t *)dv.p,
+                           ent_c, ent_f, perm);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        size_t tb2 = tbytes;
+        e = hipcub::DeviceRadixSort::SortPairs(cub.p, tb2, (const uint64_t *)dk.p, (uint64_t *)dk2.p,
+                                               (const uint32_t *)perm, perm2, (int)T, 0, kbits, qs);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_gather, dim3(grid_for((int64_t)T + 1)), dim3(256), 0, qs, (int64_t)T, perm2, ent_c,
+                           ent_f, (const uint32_t *)dv.p, (const uint64_t *)dk2.p, cbits,
+                           (pbits >= 64) ? ~0ULL : ((1ULL << pbits) - 1), cbits + pbits, H, s_c, s_f, s_poly,
+                           s_edge, (uint32_t *)drow.p);
+        return hipGetLastError();
+    };
 
     uint64_t *row_nrec = (uint64_t *)drc.p;
     uint64_t *row_nloc = row_nrec + (H + 1);
@@ -1470,7 +1531,7 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
             a2.cap = cap_big;
             a2.min_n = ra.cap + 1;
             a2.max_n = 0x7fffffff;
-            if ((e = hipEventRecord(ctx->fork, st)) != hipSuccess) return e;
+            if ((e = hipEventRecord(ctx->fork, qs)) != hipSuccess) return e;
             if ((e = hipStreamWaitEvent(ctx->side, ctx->fork, 0)) != hipSuccess) return e;
             if (emit) hipLaunchKernelGGL(k_rows<true>, dim3(rgrid), dim3(ROW_THREADS), rlds_big, ctx->side, a2);
             else hipLaunchKernelGGL(k_rows<false>, dim3(rgrid), dim3(ROW_THREADS), rlds_big, ctx->side, a2);
@@ -1480,21 +1541,20 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
         RowArgs a1 = ra;
         a1.min_n = 0;
         a1.max_n = ra.cap;
-        if (emit) hipLaunchKernelGGL(k_rows<true>, dim3(rgrid), dim3(ROW_THREADS), rlds, st, a1);
-        else hipLaunchKernelGGL(k_rows<false>, dim3(rgrid), dim3(ROW_THREADS), rlds, st, a1);
+        if (emit) hipLaunchKernelGGL(k_rows<true>, dim3(rgrid), dim3(ROW_THREADS), rlds, qs, a1);
+        else hipLaunchKernelGGL(k_rows<false>, dim3(rgrid), dim3(ROW_THREADS), rlds, qs, a1);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        if (big) return hipStreamWaitEvent(st, ctx->join, 0);
+        if (big) return hipStreamWaitEvent(qs, ctx->join, 0);
         return hipSuccess;
     };
     ra.cells = (uint32_t *)cv->cells.p;
 
     // Coarse level + compact records of mixed blocks, from the canvas words.
-    auto launch_compact = [&]() -> int {
+    auto launch_compact = [&]() -> hipError_t {
         const int cgrid = (int)std::max<int64_t>(1, std::min<int64_t>((coarse_tot + 3) / 4, 65536));
-        hipLaunchKernelGGL(k_compact, dim3(cgrid), dim3(256), 0, st, d_cds, nc, coarse_tot,
+        hipLaunchKernelGGL(k_compact, dim3(cgrid), dim3(256), 0, qs, d_cds, nc, coarse_tot,
                            (const uint32_t *)cv->cells.p, (uint16_t *)cv->coarse.p, (uint4 *)cv->desc.p);
-        SPADE_HIP(ctx, hipGetLastError());
-        return SPADE_OK;
+        return hipGetLastError();
     };
 
     // One row pass: rows reserve their output ranges with atomics inside the
@@ -1520,9 +1580,28 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
         ra.cands = (Cand *)cv->cands.p;
         ra.ledges = (Edge *)cv->ledges.p;
         ra.pspan = (double2 *)cv->pspan.p;
-        SPADE_HIP(ctx, launch_rows(true));
-        int rc = launch_compact();
-        if (rc) return rc;
+        auto enqueue = [&]() -> hipError_t {
+            hipError_t e = enqueue_entries();
+            if (e == hipSuccess) e = launch_rows(true);
+            if (e == hipSuccess) e = launch_compact();
+            return e;
+        };
+        // The launches from the entries to the coarse level depend only on
+        // the values below: a canvas rebuilt with the same ones replays them
+        // from a captured graph instead of launching some thirty kernels.
+        std::vector<uint64_t> key;
+        auto put = [&](uint64_t v) { key.push_back(v); };
+        auto putp = [&](const void *p) { key.push_back((uint64_t)(uintptr_t)p); };
+        put(T); put((uint64_t)V); put((uint64_t)H); put((uint64_t)W); put((uint64_t)nc); put((uint64_t)coarse_tot);
+        put((uint64_t)cbits); put((uint64_t)pbits); put((uint64_t)kbits); put(tbytes);
+        put((uint64_t)ra.cap); put((uint64_t)cap_big); put(rlds); put(rlds_big); put((uint64_t)rgrid);
+        put(ra.cap_rec); put(ra.cap_loc); put(ra.cap_part); put(big ? 1 : 0);
+        putp(cv->edges.p); putp(epoly); putp(erow0); putp(nrows); putp(eoff); putp(d_cds);
+        putp(dk.p); putp(dk2.p); putp(dv.p); putp(dv2.p); putp(dc.p); putp(df.p); putp(drow.p); putp(cub.p);
+        putp(ra.gaux); putp(gctr); putp(d_err); putp(drc.p);
+        putp(cv->cells.p); putp(cv->cands.p); putp(cv->ledges.p); putp(cv->pspan.p); putp(cv->coarse.p);
+        putp(cv->desc.p); putp(ctx->side); putp(ctx->fork); putp(ctx->join);
+        SPADE_HIP(ctx, run_captured(ctx, cv, key, qs, enqueue));
         uint64_t *hc = (uint64_t *)ensure_pinned(ctx, 64);
         SPADE_HIP(ctx, hipMemcpyAsync(hc, gctr, 32, hipMemcpyDeviceToHost, st));
         SPADE_HIP(ctx, hipMemcpyAsync(hc + 4, d_err, sizeof(unsigned), hipMemcpyDeviceToHost, st));
@@ -1567,8 +1646,7 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
         ra.ledges = (Edge *)cv->ledges.p;
         ra.pspan = (double2 *)cv->pspan.p;
         SPADE_HIP(ctx, launch_rows(true));
-        int rc = launch_compact();
-        if (rc) return rc;
+        SPADE_HIP(ctx, launch_compact());
         unsigned *herr2 = (unsigned *)ensure_pinned(ctx, 64);
         SPADE_HIP(ctx, hipMemcpyAsync(herr2, d_err, sizeof(unsigned), hipMemcpyDeviceToHost, st));
         SPADE_HIP(ctx, hipStreamSynchronize(st));

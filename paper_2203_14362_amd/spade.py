@@ -36,7 +36,7 @@ EXPORTS = [
     "spade_orient_batch", "spade_ctx_set_timing", "spade_ctx_last_timing",
     "spade_table_create", "spade_table_destroy", "spade_table_info", "spade_batch_build",
     "spade_batch_select", "spade_batch_join_count", "spade_ctx_set_pixels_per_vertex",
-    "spade_batch_rebuild",
+    "spade_batch_rebuild", "spade_ctx_set_graphs", "spade_ctx_graph_stats",
 ]
 
 
@@ -99,6 +99,8 @@ def load_library():
     lib.spade_batch_select.argtypes = [vp, vp, vp, vp, i64, vp]
     lib.spade_batch_join_count.argtypes = [vp, vp, vp, vp]
     lib.spade_ctx_set_pixels_per_vertex.argtypes = [vp, ctypes.c_double]
+    lib.spade_ctx_set_graphs.argtypes = [vp, ctypes.c_int]
+    lib.spade_ctx_graph_stats.argtypes = [vp, P(i64), P(i64)]
     for name in EXPORTS:
         f = getattr(lib, name)
         if f.restype is ctypes.c_int:
@@ -261,6 +263,15 @@ class Context:
         r, p = ctypes.c_float(), ctypes.c_float()
         self._check(self.lib.spade_ctx_last_timing(self.handle, ctypes.byref(r), ctypes.byref(p)))
         return float(r.value), float(p.value)
+
+    def set_graphs(self, on: bool = True):
+        self._check(self.lib.spade_ctx_set_graphs(self.handle, 1 if on else 0))
+
+    def graph_stats(self):
+        """(graphs captured, replays launched) on this context."""
+        c, r = ctypes.c_int64(), ctypes.c_int64()
+        self._check(self.lib.spade_ctx_graph_stats(self.handle, ctypes.byref(c), ctypes.byref(r)))
+        return c.value, r.value
 
     def set_pixels_per_vertex(self, ppv: float):
         self._check(self.lib.spade_ctx_set_pixels_per_vertex(self.handle, float(ppv)))
