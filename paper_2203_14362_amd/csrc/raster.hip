@@ -472,15 +472,15 @@ __device__ __forceinline__ uint32_t pre_excl(const RowData &D, int q)
     return q == 0 ? 0u : D.pre[q - 1];
 }
 
-// Slot of a new record of column col (sa holds the exclusive record bases
-// of the row's columns, sb the fill counters), and CAND_LAST when it takes
-// the column's last slot.  A pixel's records are in no particular polygon
-// order; the probes order their matches where order matters.
+// Slot of a new record of column col (sa holds the inclusive prefix of the
+// row's per-column record counts, sb the fill counters), and CAND_LAST when
+// it takes the column's last slot.  A pixel's records are in no particular
+// polygon order; the probes order their matches where order matters.
 __device__ __forceinline__ uint64_t rec_slot(const RowShared &L, int col, uint64_t rec_base_r, uint32_t &last)
 {
     const int32_t k = atomicAdd(&L.sb[cix(col)], 1);
-    const int32_t b = L.sa[cix(col)];
-    const int32_t e = (col + 1 < L.W) ? L.sa[cix(col + 1)] : (int32_t)*L.nrec;
+    const int32_t b = col ? L.sa[cix(col - 1)] : 0;
+    const int32_t e = L.sa[cix(col)];
     last = (k == e - b - 1) ? CAND_LAST : 0u;
     return rec_base_r + (uint64_t)b + (uint64_t)k;
 }
@@ -876,17 +876,11 @@ __device__ void process_row(const RowArgs &A, const RowData &D, const RowShared 
         return;
     }
 
-    // exclusive column bases for the records of this row
+    // record ranges of the row's columns: sa := inclusive prefix of the
+    // per-column record counts (column c owns [sa[c-1], sa[c])), sb := 0
     block_scan(L.sa, W, wtoti, [](int32_t a, int32_t b) { return a + b; }, 0);
-    {
-        int32_t mine[MAXW / ROW_THREADS];
-        int cnt = 0;
-        for (int c = tid; c < W; c += ROW_THREADS) mine[cnt++] = (c == 0) ? 0 : L.sa[cix(c - 1)];
-        __syncthreads();
-        cnt = 0;
-        for (int c = tid; c < W; c += ROW_THREADS) { L.sa[cix(c)] = mine[cnt++]; L.sb[cix(c)] = 0; }
-        __syncthreads();
-    }
+    for (int c = tid; c < W; c += ROW_THREADS) L.sb[cix(c)] = 0;
+    __syncthreads();
 
     // phase 5: records, local edges, partial spans (in row entry order)
     const uint64_t rec_base_r = A.alloc ? s_base[0] : A.rec_base[r];
@@ -923,8 +917,8 @@ __device__ void process_row(const RowArgs &A, const RowData &D, const RowShared 
     for (int c = tid; c < W; c += ROW_THREADS) {
         uint32_t word = L.sx[cix(c)];
         if (word & BFLAG) {
-            const int32_t b = L.sa[cix(c)];
-            const int32_t e = (c + 1 < W) ? L.sa[cix(c + 1)] : (int32_t)*L.nrec;
+            const int32_t b = c ? L.sa[cix(c - 1)] : 0;
+            const int32_t e = L.sa[cix(c)];
             if (e - b <= 0 || L.sb[cix(c)] != e - b) { atomicOr(A.errflags, 8u); word = 0; }
             else word = BFLAG | (uint32_t)(rec_base_r + (uint64_t)b);
         }
@@ -1499,9 +1493,10 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
     ra.row_nrec = row_nrec; ra.row_nloc = row_nloc; ra.row_npart = row_npart; ra.row_nbp = row_nbp;
     ra.rec_base = rec_base; ra.loc_base = loc_base; ra.part_base = part_base;
     ra.errflags = d_err;
-    // stage up to `cap` entries of a row in LDS; aim for two workgroups per CU
+    // stage up to `cap` entries of a row in LDS: narrow canvases aim for
+    // three or four workgroups per CU, wider ones for two (measured best)
     const size_t col_bytes = row_lds_bytes(W, 0);
-    const size_t target = (col_bytes <= 60 * 1024) ? 78 * 1024 : 150 * 1024;
+    const size_t target = (col_bytes <= 40 * 1024) ? 38 * 1024 : (col_bytes <= 60 * 1024) ? 78 * 1024 : 150 * 1024;
     ra.cap = (int)std::max<size_t>(256, (target - std::min(target - 256 * 37, col_bytes)) / 37);
     if (T > (uint64_t)ra.cap) {
         // some row may exceed the LDS stage: global auxiliary words for it
