@@ -199,9 +199,16 @@ class Server:
                 batch, extra = self._work[w].popleft()
             try:
                 self.ex.run(w, batch)
-            except Exception as e:          # report per request, keep serving
+            except Exception as e:
+                # one bad request must not fail its batch: run them one by one
                 for r in batch:
-                    r.error = "%s: %s" % (type(e).__name__, e)
+                    try:
+                        if len(batch) == 1:
+                            raise e
+                        self.ex.run(w, [r])
+                    except Exception as e1:
+                        r.error = "%s: %s" % (type(e1).__name__, e1)
+                        r.result = None
             t = self.clock()
             with self._cv:
                 for r in batch:

@@ -115,15 +115,16 @@ def test_oversized_request_is_rejected_alone():
     assert all(r.error is None and r.result == FakeExecutor.answer(r) for r in reqs)
 
 
-def test_executor_failure_is_reported_per_batch():
+def test_executor_failure_is_isolated_to_its_request():
     ex = FakeExecutor(n_workers=1, fail_on=3)
     reqs = _requests(12, seed=5)
-    srv = Server(ex, budget_bytes=10**12, max_batch=1).start()
+    srv = Server(ex, budget_bytes=10**12).start()
     for r in reqs:
         srv.submit(r)
     srv.stop()
     assert reqs[3].error is not None and "planted" in reqs[3].error
-    assert all(r.error is None for r in reqs if r.rid != 3)
+    # the others, also those batched with it, are answered
+    assert all(r.error is None and r.result == FakeExecutor.answer(r) for r in reqs if r.rid != 3)
 
 
 def test_vertex_cap_splits_batches():
