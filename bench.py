@@ -188,6 +188,8 @@ def main():
                     help="fixed pixels per polygon vertex instead of autotuning (0 = autotune)")
     ap.add_argument("--tune-cache", default="",
                     help="JSON file of autotuner choices to reuse (and extend) across runs")
+    ap.add_argument("--retune", action="store_true",
+                    help="measure the canvas resolution again instead of taking a cached or preset choice")
     ap.add_argument("--cpu-sample", type=int, default=100_000_000,
                     help="points of the prefix timed with the CPU oracle (0 = skip; default: all of them)")
     ap.add_argument("--serve-seconds", type=float, default=4.0,
@@ -239,9 +241,9 @@ def main():
         else:
             from paper_2203_14362_amd.autotune import Autotuner, tune_join_count
             tuner = Autotuner(args.tune_cache or None)
-            ppv, times = tune_join_count(ctx, dx, dy, dpolys, tuner)
+            ppv, times = tune_join_count(ctx, dx, dy, dpolys, tuner, force=args.retune)
             tuned = {"pixels_per_vertex": ppv, "trial_ms": {str(k): round(v, 3) for k, v in times.items()},
-                     "cached": not times}
+                     "source": tuner.last_source}
             log("autotuned canvas resolution: %.0f pixels per vertex (trials %s)" % (ppv, tuned["trial_ms"]))
         ctx.set_timing(True)
     for _ in range(args.warmup):

@@ -11,7 +11,10 @@ own phase events, pick the fastest.  Results never depend on the choice
 
 Choices are cached per workload signature (polygon count, vertex count and
 point count, each rounded to a power of two) in memory and, optionally, in
-a JSON file, so a workload is tuned once.
+a JSON file, so a workload is tuned once.  A read-only preset table of
+choices measured on MI355X ships with the package (``tuned_mi355x.json``);
+entries of the writable cache take precedence over it, and ``force``
+re-measures either.
 """
 from __future__ import annotations
 
@@ -21,6 +24,7 @@ import os
 import threading
 
 DEFAULT_CANDIDATES = (32.0, 40.0, 48.0, 56.0, 64.0, 96.0, 128.0, 192.0, 384.0)
+PRESET_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_mi355x.json")
 
 
 def _bucket(n: int) -> int:
@@ -32,15 +36,21 @@ def signature(kind: str, n_polys: int, n_vertices: int, n_points: int) -> str:
 
 
 class Autotuner:
-    def __init__(self, path: str = None, candidates=DEFAULT_CANDIDATES, repeats: int = 3):
+    def __init__(self, path: str = None, candidates=DEFAULT_CANDIDATES, repeats: int = 3,
+                 preset: str = PRESET_PATH):
         self.path = path
         self.candidates = tuple(float(c) for c in candidates)
         self.repeats = repeats
         self._lock = threading.Lock()
         self.table = {}
+        self.preset = {}
+        self.last_source = None
         if path and os.path.exists(path):
             with open(path) as fh:
                 self.table = json.load(fh)
+        if preset and os.path.exists(preset):
+            with open(preset) as fh:
+                self.preset = json.load(fh)
 
     def _save(self):
         if not self.path:
@@ -52,7 +62,7 @@ class Autotuner:
 
     def lookup(self, key: str):
         with self._lock:
-            e = self.table.get(key)
+            e = self.table.get(key, self.preset.get(key))
         return None if e is None else float(e["ppv"])
 
     def tune(self, key: str, trial, force: bool = False):
@@ -60,6 +70,8 @@ class Autotuner:
         runs the query once at that setting and returns its device time in
         milliseconds.  Returns (ppv, {ppv: best ms})."""
         if not force:
+            with self._lock:
+                self.last_source = "cache" if key in self.table else "preset" if key in self.preset else None
             hit = self.lookup(key)
             if hit is not None:
                 return hit, {}
@@ -69,6 +81,7 @@ class Autotuner:
             times[ppv] = min(trial(ppv) for _ in range(self.repeats))
         best = min(times, key=times.get)
         with self._lock:
+            self.last_source = "measured"
             self.table[key] = {"ppv": best, "ms": {str(k): round(v, 4) for k, v in times.items()}}
             self._save()
         return best, times
