@@ -129,7 +129,7 @@ struct spade_ctx {
     std::string err;
     int32_t canvas_w = 0, canvas_h = 0;     // 0 = automatic
     double ppv = 256.0;                     // automatic sizing: pixels per vertex
-    spade::DevBuf scratch[16];              // reusable scratch slots
+    spade::DevBuf scratch[17];              // reusable scratch slots
     void *pinned = nullptr;                 // small pinned host staging area
     spade_canvas *plain = nullptr;          // canvas reused by the plain query calls
     bool timing = false;                    // record phase events (raster, probe)
@@ -148,7 +148,7 @@ namespace spade {
 // Scratch slot ids inside a context.
 enum Slot {
     S_BLOCKRED = 0, S_RINGPOLY, S_NROWS, S_ROWOFF, S_KEYS, S_KEYS2, S_VALS, S_VALS2,
-    S_ENTC, S_ENTF, S_CUBTMP, S_ROWCNT, S_NEXTP, S_PROBE, S_LOOKBACK, S_MISC
+    S_ENTC, S_ENTF, S_CUBTMP, S_ROWCNT, S_NEXTP, S_PROBE, S_LOOKBACK, S_MISC, S_ROWSCAN
 };
 
 int set_error(spade_ctx *ctx, int code, const std::string &msg);

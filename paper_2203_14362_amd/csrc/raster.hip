@@ -232,7 +232,7 @@ __global__ __launch_bounds__(256) void k_edges(int64_t R, const int64_t *rvo, in
                                                const double *vx, const double *vy,
                                                const int32_t *ring_poly, const CanvasDesc *cds, int nc,
                                                Edge *edges, uint32_t *epoly, int32_t *erow0,
-                                               uint64_t *nrows)
+                                               uint64_t *nrows, int32_t *rdiff)
 {
     const int64_t nth = (int64_t)gridDim.x * blockDim.x;
     if (blockIdx.x == 0 && threadIdx.x == 0) nrows[V] = 0;   // zero tail of the row-count scan
@@ -260,6 +260,79 @@ __global__ __launch_bounds__(256) void k_edges(int64_t R, const int64_t *rvo, in
         int32_t r1 = (int32_t)fmax(0.0, fmin(f1, (double)(m.H - 1)));
         erow0[j] = r0;
         nrows[j] = (uint64_t)(r1 - r0 + 1);
+        // row histogram as a difference array: +1 on rows r0..r1
+        atomicAdd(&rdiff[m.row_base + r0], 1);
+        atomicSub(&rdiff[m.row_base + r1 + 1], 1);
+    }
+}
+
+__global__ void k_zero_i32(int64_t n, int32_t *p)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+// ------------------------------------------------------------ row buckets
+
+constexpr int SCAN_THREADS = 1024;
+
+// Exclusive prefix sum over the block of one value per thread.
+__device__ long long block_excl_sum(long long v, long long *wtot)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    long long inc = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const long long t = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += t;
+    }
+    if (lane == 63) wtot[wv] = inc;
+    __syncthreads();
+    long long pre = 0;
+    for (int q = 0; q < wv; ++q) pre += wtot[q];
+    __syncthreads();
+    return pre + inc - v;
+}
+
+// One block: entry count of every row from the difference array, the row
+// offsets (row_off[Htot] = total), insertion cursors starting at the
+// offsets, and the list of rows with more than `cap` entries.
+// info = {total entries, longest row, number of listed rows}.
+__global__ __launch_bounds__(SCAN_THREADS) void k_rowscan(int64_t Htot, const int32_t *rdiff, int cap,
+                                                          uint32_t *row_off, uint32_t *cursor,
+                                                          uint32_t *longrows, unsigned long long *info)
+{
+    __shared__ long long wtot[SCAN_THREADS / 64];
+    __shared__ unsigned s_nlong;
+    __shared__ int s_max;
+    const int tid = threadIdx.x;
+    if (tid == 0) { s_nlong = 0; s_max = 0; }
+    const int64_t per = (Htot + SCAN_THREADS - 1) / SCAN_THREADS;
+    const int64_t b = min(Htot, (int64_t)tid * per), e = min(Htot, b + per);
+    long long d = 0;
+    for (int64_t r = b; r < e; ++r) d += rdiff[r];
+    const long long cnt0 = block_excl_sum(d, wtot);      // entries of row b-1 (0 for b = 0)
+    long long cnt = cnt0, tot = 0;
+    for (int64_t r = b; r < e; ++r) { cnt += rdiff[r]; tot += cnt; }
+    const long long off0 = block_excl_sum(tot, wtot);
+    long long off = off0;
+    int mx = 0;
+    cnt = cnt0;
+    for (int64_t r = b; r < e; ++r) {
+        cnt += rdiff[r];
+        row_off[r] = (uint32_t)off;
+        cursor[r] = (uint32_t)off;
+        off += cnt;
+        mx = max(mx, (int)min(cnt, (long long)0x7fffffff));
+        if (cnt > cap) longrows[atomicAdd(&s_nlong, 1u)] = (uint32_t)r;
+    }
+    atomicMax(&s_max, mx);
+    __syncthreads();
+    if (tid == SCAN_THREADS - 1) {
+        row_off[Htot] = (uint32_t)off;
+        info[0] = (unsigned long long)off;
+        info[1] = (unsigned long long)s_max;
+        info[2] = s_nlong;
     }
 }
 
@@ -320,6 +393,128 @@ __global__ __launch_bounds__(256) void k_entries(int64_t V, const Edge *edges, c
             const uint64_t nn = __shfl(nr, src, 64);
             expand(jj, (uint64_t)lane, 64, nn);
         }
+    }
+}
+
+// Entries written straight into their row's bucket (slot from the row's
+// insertion cursor, so unordered within the row) with the key
+// (polygon, first column, edge id) that orders them inside the row.
+__global__ __launch_bounds__(256) void k_entries_rows(int64_t V, const Edge *edges, const uint32_t *epoly,
+                                                      const int32_t *erow0, const uint64_t *nrows,
+                                                      const CanvasDesc *cds, int nc, int ebits,
+                                                      int ckshift, uint32_t *cursor, uint64_t *ukey,
+                                                      uint32_t *uc, uint8_t *uf)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    auto entry = [&](int64_t j, const CanvasDesc &m, double ulo, double uhi, double vlo, double vhi,
+                     bool horiz, const Edge &e, uint64_t poly, int32_t r, uint32_t pos) {
+        const double b0 = (double)r - MARGIN, b1 = (double)r + 1.0 + MARGIN;
+        int32_t c0, c1;
+        row_footprint(m, ulo, uhi, vlo, vhi, r, c0, c1);
+        const bool span = !horiz && vlo <= b0 && vhi >= b1;
+        const double yc = m.Y0 + ((double)r + 0.5) * m.hy;
+        const bool w = !horiz && straddles(e.ylo, e.yhi, yc);
+        ukey[pos] = (poly << ckshift) | ((uint64_t)c0 << ebits) | (uint64_t)j;
+        uc[pos] = (uint32_t)c0 | ((uint32_t)c1 << 16);
+        uf[pos] = (span ? F_SPAN : 0) | (w ? F_W : 0) | (horiz ? F_HORIZ : 0);
+    };
+    const int64_t iters = (V + nth - 1) / nth;
+    for (int64_t it = 0; it < iters; ++it) {
+        const int64_t j = it * nth + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        const uint64_t nr = j < V ? nrows[j] : 0;
+        if (nr > 0 && nr <= LANE_ROWS) {
+            const Edge e = edges[j];
+            const CanvasDesc &m = cds[canvas_of_poly(cds, nc, epoly[j])];
+            const int64_t g0 = m.row_base + erow0[j];
+            // all slots first: the cursor atomics overlap instead of queueing
+            uint32_t pos[LANE_ROWS];
+#pragma unroll
+            for (int t = 0; t < (int)LANE_ROWS; ++t)
+                if (t < (int)nr) pos[t] = atomicAdd(&cursor[g0 + t], 1u);
+            const bool horiz = (e.ylo == e.yhi);
+            const double ulo = __dmul_rn(__dsub_rn(e.xlo, m.X0), m.sx);
+            const double uhi = __dmul_rn(__dsub_rn(e.xhi, m.X0), m.sx);
+            const double vlo = __dmul_rn(__dsub_rn(e.ylo, m.Y0), m.sy);
+            const double vhi = __dmul_rn(__dsub_rn(e.yhi, m.Y0), m.sy);
+            const uint64_t poly = (uint64_t)((int64_t)epoly[j] - m.poly_base);
+#pragma unroll
+            for (int t = 0; t < (int)LANE_ROWS; ++t)
+                if (t < (int)nr) entry(j, m, ulo, uhi, vlo, vhi, horiz, e, poly, erow0[j] + t, pos[t]);
+        }
+        unsigned long long longs = __ballot(nr > LANE_ROWS);
+        while (longs) {
+            const int src = __ffsll((long long)longs) - 1;
+            longs &= longs - 1;
+            const int64_t jj = __shfl(j, src, 64);
+            const uint64_t nn = __shfl(nr, src, 64);
+            const Edge e = edges[jj];
+            const CanvasDesc &m = cds[canvas_of_poly(cds, nc, epoly[jj])];
+            const bool horiz = (e.ylo == e.yhi);
+            const double ulo = __dmul_rn(__dsub_rn(e.xlo, m.X0), m.sx);
+            const double uhi = __dmul_rn(__dsub_rn(e.xhi, m.X0), m.sx);
+            const double vlo = __dmul_rn(__dsub_rn(e.ylo, m.Y0), m.sy);
+            const double vhi = __dmul_rn(__dsub_rn(e.yhi, m.Y0), m.sy);
+            const uint64_t poly = (uint64_t)((int64_t)epoly[jj] - m.poly_base);
+            for (uint64_t t = (uint64_t)lane; t < nn; t += 64) {
+                const int32_t r = erow0[jj] + (int32_t)t;
+                const uint32_t pos = atomicAdd(&cursor[m.row_base + r], 1u);
+                entry(jj, m, ulo, uhi, vlo, vhi, horiz, e, poly, r, pos);
+            }
+        }
+    }
+}
+
+// Longest row the in-row sort takes (its keys and source slots in LDS).
+constexpr int ROWSORT_MAX = 4096;
+constexpr int SORT_THREADS = 256;
+
+// Sorts every row's entries by key in LDS (bitonic network over the next
+// power of two, padded with the largest key) and writes them in that order:
+// polygon and edge from the key, footprint and flags from the source slot.
+__global__ __launch_bounds__(SORT_THREADS) void k_rowsort(int64_t Htot, const uint32_t *row_off,
+                                                          const uint64_t *ukey, const uint32_t *uc,
+                                                          const uint8_t *uf, int pshift, uint64_t emask,
+                                                          uint32_t *s_poly, uint32_t *s_edge, uint32_t *s_c,
+                                                          uint8_t *s_f, int pmax)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint64_t *kk = (uint64_t *)smem;
+    uint16_t *ix = (uint16_t *)(kk + pmax);
+    const int tid = threadIdx.x;
+    for (int64_t r = blockIdx.x; r < Htot; r += gridDim.x) {
+        const uint32_t s = row_off[r];
+        const int n = (int)(row_off[r + 1] - s);
+        if (n == 0) continue;
+        int P = 1;
+        while (P < n) P <<= 1;
+        for (int q = tid; q < P; q += SORT_THREADS) {
+            kk[q] = q < n ? ukey[s + q] : ~0ull;
+            ix[q] = (uint16_t)q;
+        }
+        __syncthreads();
+        for (int k = 2; k <= P; k <<= 1)
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int t = tid; t < (P >> 1); t += SORT_THREADS) {
+                    const int i = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+                    const int l = i | j;
+                    const uint64_t a = kk[i], b = kk[l];
+                    if ((a > b) == ((i & k) == 0)) {
+                        kk[i] = b; kk[l] = a;
+                        const uint16_t x = ix[i]; ix[i] = ix[l]; ix[l] = x;
+                    }
+                }
+                __syncthreads();
+            }
+        for (int q = tid; q < n; q += SORT_THREADS) {
+            const uint64_t key = kk[q];
+            const uint32_t src = s + ix[q];
+            s_poly[s + q] = (uint32_t)(key >> pshift);
+            s_edge[s + q] = (uint32_t)(key & emask);
+            s_c[s + q] = uc[src];
+            s_f[s + q] = uf[src];
+        }
+        __syncthreads();
     }
 }
 
@@ -396,6 +591,8 @@ struct RowArgs {
     uint32_t *gaux;          // 6 words per entry for rows too long to stage
     int min_n;               // this launch handles rows with min_n <= entries (<= max_n)
     int max_n;
+    const uint32_t *rows;    // rows of this launch (nullptr: all rows)
+    int64_t nlist;
     // single-pass allocation: per-row output ranges reserved with atomics
     int alloc;
     unsigned long long *gctr;    // [0] records, [1] local edges, [2] partial spans, [3] boundary pixels
@@ -958,7 +1155,9 @@ __global__ __launch_bounds__(ROW_THREADS) void k_rows(RowArgs A)
     uint8_t *lf = (uint8_t *)(lil + cap);
     const int tid = threadIdx.x;
 
-    for (int64_t r = blockIdx.x; r < A.Htot; r += gridDim.x) {
+    const int64_t nr = A.rows ? A.nlist : A.Htot;
+    for (int64_t k = blockIdx.x; k < nr; k += gridDim.x) {
+        const int64_t r = A.rows ? (int64_t)A.rows[k] : k;
         const int s = (int)A.row_off[r], e = (int)A.row_off[r + 1];
         const int n = e - s;
         if (n < A.min_n || n > A.max_n) continue;
@@ -1392,35 +1591,50 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
     const int W = maxW;
     const int64_t H = Htot;
 
-    // edges + per-edge row counts
+    // edges, per-edge row spans and the row histogram
     DevBuf &dn = ctx->scratch[S_NROWS];
     DevBuf &dmisc = ctx->scratch[S_MISC];
+    DevBuf &drs = ctx->scratch[S_ROWSCAN];
+    DevBuf &drow = ctx->scratch[S_ROWOFF];
     const size_t Vs = (size_t)V;
     // misc: epoly[V] u32 | erow0[V] i32 | off[V+1] u64
+    // rowscan: rdiff[H+1] i32 | cursor[H] u32 | longrows[H] u32 | info[4] u64
     if (ensure(ctx, dn, sizeof(uint64_t) * (Vs + 1)) ||
-        ensure(ctx, dmisc, sizeof(uint32_t) * Vs * 2 + sizeof(uint64_t) * (Vs + 2)))
+        ensure(ctx, dmisc, sizeof(uint32_t) * Vs * 2 + sizeof(uint64_t) * (Vs + 2)) ||
+        ensure(ctx, drs, 12 * (size_t)H + 64) || ensure(ctx, drow, 8 * ((size_t)H + 1)))
         return SPADE_E_NOMEM;
     uint64_t *nrows = (uint64_t *)dn.p;
     uint32_t *epoly = (uint32_t *)dmisc.p;
     int32_t *erow0 = (int32_t *)(epoly + Vs);
     uint64_t *eoff = (uint64_t *)(((uintptr_t)(erow0 + Vs) + 7) & ~(uintptr_t)7);
+    int32_t *rdiff = (int32_t *)drs.p;
+    uint32_t *cursor = (uint32_t *)(rdiff + H + 1);
+    uint32_t *longrows = cursor + H;
+    unsigned long long *rinfo = (unsigned long long *)(((uintptr_t)(longrows + H) + 7) & ~(uintptr_t)7);
+    uint32_t *row_off = (uint32_t *)drow.p;
     // per-row counters of the exact path (8 arrays of H + 1)
     DevBuf &drc = ctx->scratch[S_ROWCNT];
     if (ensure(ctx, drc, 8 * 8 * ((size_t)H + 1))) return SPADE_E_NOMEM;
+
+    // LDS stage of the row kernel: up to `cap` entries of a row; narrow
+    // canvases aim for three or four workgroups per CU, wider ones for two
+    // (measured best).  Longer rows go to a second launch over a row list.
+    const size_t col_bytes = row_lds_bytes(W, 0);
+    const size_t target = (col_bytes <= 40 * 1024) ? 38 * 1024 : (col_bytes <= 60 * 1024) ? 78 * 1024 : 150 * 1024;
+    const int cap = (int)std::max<size_t>(256, (target - std::min(target - 256 * 37, col_bytes)) / 37);
+
+    hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(H + 1, 1024)), dim3(256), 0, st, H + 1, rdiff);
     hipLaunchKernelGGL(k_edges, dim3(grid_for(V)), dim3(256), 0, st, R, polys->ring_vtx_off, V,
                        polys->vx, polys->vy, (const int32_t *)rp.p, d_cds, nc, (Edge *)cv->edges.p, epoly,
-                       erow0, nrows);
+                       erow0, nrows, rdiff);
     SPADE_HIP(ctx, hipGetLastError());
-
-    DevBuf &cub = ctx->scratch[S_CUBTMP];
-    size_t tb = 0;
-    SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(nullptr, tb, nrows, eoff, (int)(V + 1), st));
-    if (ensure(ctx, cub, tb)) return SPADE_E_NOMEM;
-    SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(cub.p, tb, nrows, eoff, (int)(V + 1), st));
+    hipLaunchKernelGGL(k_rowscan, dim3(1), dim3(SCAN_THREADS), 0, st, H, (const int32_t *)rdiff, cap, row_off,
+                       cursor, longrows, rinfo);
+    SPADE_HIP(ctx, hipGetLastError());
     uint64_t *hT = (uint64_t *)ensure_pinned(ctx, 64);
-    SPADE_HIP(ctx, hipMemcpyAsync(hT, eoff + V, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    SPADE_HIP(ctx, hipMemcpyAsync(hT, rinfo, 3 * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
     SPADE_HIP(ctx, hipStreamSynchronize(st));
-    const uint64_t T = hT[0];
+    const uint64_t T = hT[0], maxrow = hT[1], nlong = hT[2];
     if (T >= 0x7fffffffULL) return set_error(ctx, SPADE_E_UNSUPPORTED, "too many (edge,row) entries; lower the canvas height");
 
     const int cbits = std::max(1, bits_for((uint64_t)W - 1));
@@ -1428,37 +1642,62 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
     for (int q = 0; q < nc; ++q) maxM = std::max<int64_t>(maxM, cds[q].M);
     const int pbits = std::max(1, bits_for((uint64_t)(maxM - 1)));
     const int rbits = std::max(1, bits_for((uint64_t)H - 1));
-    if (cbits + pbits + rbits > 64) return set_error(ctx, SPADE_E_UNSUPPORTED, "sort key exceeds 64 bits");
+    const int ebits = std::max(1, bits_for((uint64_t)V - 1));
+    // Entries go straight into row buckets and each row is sorted in LDS by
+    // (polygon, first column, edge); rows longer than the LDS sort, or keys
+    // wider than 63 bits (the top bit stays clear so that real keys sort
+    // before the padding), take one device-wide sort of (row, polygon, first
+    // column) instead.  Both give the same order.
+    const bool bucketed = maxrow <= (uint64_t)ROWSORT_MAX && pbits + cbits + ebits <= 63;
+    if (!bucketed && cbits + pbits + rbits > 64) return set_error(ctx, SPADE_E_UNSUPPORTED, "sort key exceeds 64 bits");
 
     DevBuf &dk = ctx->scratch[S_KEYS], &dk2 = ctx->scratch[S_KEYS2];
     DevBuf &dv = ctx->scratch[S_VALS], &dv2 = ctx->scratch[S_VALS2];
     DevBuf &dc = ctx->scratch[S_ENTC], &df = ctx->scratch[S_ENTF];
-    DevBuf &drow = ctx->scratch[S_ROWOFF];
     const size_t Ts = (size_t)std::max<uint64_t>(T, 1);
-    // dc: ent_c[T] | sorted c[T] | perm[T] | perm2[T]; df: ent_f[T] | sorted f[T]
-    if (ensure(ctx, dk, 8 * Ts) || ensure(ctx, dk2, 8 * Ts) || ensure(ctx, dv, 4 * Ts) ||
-        ensure(ctx, dv2, 4 * Ts) || ensure(ctx, dc, 20 * Ts) || ensure(ctx, df, 2 * Ts + 16) ||
-        ensure(ctx, drow, 8 * ((size_t)H + 1)))
+    // dc: ent_c[T] | sorted c[T] | perm[T] | perm2[T] | sorted poly[T]; df: ent_f[T] | sorted f[T]
+    if (ensure(ctx, dk, 8 * Ts) || ensure(ctx, dv2, 4 * Ts) || ensure(ctx, dc, 20 * Ts) ||
+        ensure(ctx, df, 2 * Ts + 16))
         return SPADE_E_NOMEM;
+    if (!bucketed && (ensure(ctx, dk2, 8 * Ts) || ensure(ctx, dv, 4 * Ts))) return SPADE_E_NOMEM;
     uint32_t *ent_c = (uint32_t *)dc.p, *s_c = ent_c + Ts, *perm = s_c + Ts, *perm2 = perm + Ts;
     uint32_t *s_poly = perm2 + Ts;
     uint8_t *ent_f = (uint8_t *)df.p, *s_f = ent_f + Ts;
-    // sort entries by (row, polygon, c0) with the identity permutation as
-    // values, then gather edge ids and payload
+    uint32_t *s_edge = (uint32_t *)dv2.p;
     const int kbits = cbits + pbits + rbits;
     hipStream_t qs = st;   // stream of the build's launches (see run_captured)
-    size_t tbytes = 0;
-    SPADE_HIP(ctx, hipcub::DeviceRadixSort::SortPairs(nullptr, tbytes, (const uint64_t *)dk.p,
-                                                      (uint64_t *)dk2.p, (const uint32_t *)perm,
-                                                      perm2, (int)T, 0, kbits, st));
-    if (ensure(ctx, cub, tbytes)) return SPADE_E_NOMEM;
-    uint32_t *s_edge = (uint32_t *)dv2.p;
+    DevBuf &cub = ctx->scratch[S_CUBTMP];
+    size_t tbytes = 0, tscan = 0;
+    int pmax = 1;
+    while ((uint64_t)pmax < maxrow) pmax <<= 1;
+    const size_t sort_lds = (size_t)pmax * 10 + 16;
+    if (!bucketed) {
+        SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(nullptr, tscan, nrows, eoff, (int)(V + 1), st));
+        SPADE_HIP(ctx, hipcub::DeviceRadixSort::SortPairs(nullptr, tbytes, (const uint64_t *)dk.p,
+                                                          (uint64_t *)dk2.p, (const uint32_t *)perm,
+                                                          perm2, (int)T, 0, kbits, st));
+        if (ensure(ctx, cub, std::max(tbytes, tscan))) return SPADE_E_NOMEM;
+    }
     auto enqueue_entries = [&]() -> hipError_t {
+        hipError_t e;
+        if (bucketed) {
+            hipLaunchKernelGGL(k_entries_rows, dim3(grid_for(V)), dim3(256), 0, qs, V, (const Edge *)cv->edges.p,
+                               epoly, erow0, nrows, d_cds, nc, ebits, cbits + ebits, cursor, (uint64_t *)dk.p,
+                               ent_c, ent_f);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            hipLaunchKernelGGL(k_rowsort, dim3((unsigned)std::min<int64_t>(H, 8192)), dim3(SORT_THREADS), sort_lds,
+                               qs, H, (const uint32_t *)row_off, (const uint64_t *)dk.p, (const uint32_t *)ent_c,
+                               (const uint8_t *)ent_f, cbits + ebits, (1ULL << ebits) - 1, s_poly, s_edge, s_c,
+                               s_f, pmax);
+            return hipGetLastError();
+        }
+        size_t tb1 = tscan;
+        e = hipcub::DeviceScan::ExclusiveSum(cub.p, tb1, nrows, eoff, (int)(V + 1), qs);
+        if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_entries, dim3(grid_for(V)), dim3(256), 0, qs, V, (const Edge *)cv->edges.p,
                            epoly, erow0, nrows, eoff, d_cds, nc, cbits, pbits, (uint64_t *)dk.p, (uint32_t *)dv.p,
                            ent_c, ent_f, perm);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
+        if ((e = hipGetLastError()) != hipSuccess) return e;
         size_t tb2 = tbytes;
         e = hipcub::DeviceRadixSort::SortPairs(cub.p, tb2, (const uint64_t *)dk.p, (uint64_t *)dk2.p,
                                                (const uint32_t *)perm, perm2, (int)T, 0, kbits, qs);
@@ -1466,7 +1705,7 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
         hipLaunchKernelGGL(k_gather, dim3(grid_for((int64_t)T + 1)), dim3(256), 0, qs, (int64_t)T, perm2, ent_c,
                            ent_f, (const uint32_t *)dv.p, (const uint64_t *)dk2.p, cbits,
                            (pbits >= 64) ? ~0ULL : ((1ULL << pbits) - 1), cbits + pbits, H, s_c, s_f, s_poly,
-                           s_edge, (uint32_t *)drow.p);
+                           s_edge, row_off);
         return hipGetLastError();
     };
 
@@ -1484,7 +1723,7 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
     ra.nc = nc;
     ra.maxW = W;
     ra.Htot = H;
-    ra.row_off = (const uint32_t *)drow.p;
+    ra.row_off = row_off;
     ra.spoly = s_poly;
     ra.sedge = s_edge;
     ra.sc = s_c;
@@ -1493,27 +1732,24 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
     ra.row_nrec = row_nrec; ra.row_nloc = row_nloc; ra.row_npart = row_npart; ra.row_nbp = row_nbp;
     ra.rec_base = rec_base; ra.loc_base = loc_base; ra.part_base = part_base;
     ra.errflags = d_err;
-    // stage up to `cap` entries of a row in LDS: narrow canvases aim for
-    // three or four workgroups per CU, wider ones for two (measured best)
-    const size_t col_bytes = row_lds_bytes(W, 0);
-    const size_t target = (col_bytes <= 40 * 1024) ? 38 * 1024 : (col_bytes <= 60 * 1024) ? 78 * 1024 : 150 * 1024;
-    ra.cap = (int)std::max<size_t>(256, (target - std::min(target - 256 * 37, col_bytes)) / 37);
-    if (T > (uint64_t)ra.cap) {
-        // some row may exceed the LDS stage: global auxiliary words for it
+    ra.cap = cap;
+    const size_t rlds = row_lds_bytes(W, ra.cap);
+    // the listed long rows: a stage for the longest of them, up to 150 KB
+    const int cap_stage = (int)std::max<size_t>((size_t)ra.cap, (150 * 1024 - std::min<size_t>(150 * 1024 - 256 * 37, col_bytes)) / 37);
+    const int cap_big = (int)std::max<uint64_t>((uint64_t)ra.cap, std::min<uint64_t>((uint64_t)cap_stage, maxrow));
+    const size_t rlds_big = row_lds_bytes(W, cap_big);
+    if (maxrow > (uint64_t)cap_big) {
+        // some row exceeds every stage: global auxiliary words for it
         if (ensure(ctx, ctx->scratch[S_NEXTP], sizeof(uint32_t) * 6 * Ts)) return SPADE_E_NOMEM;
         ra.gaux = (uint32_t *)ctx->scratch[S_NEXTP].p;
     }
-    const size_t rlds = row_lds_bytes(W, ra.cap);
-    // rows longer than the stage go to a second launch with the largest stage
-    const int cap_big = (int)std::max<size_t>((size_t)ra.cap, (150 * 1024 - std::min<size_t>(150 * 1024 - 256 * 37, col_bytes)) / 37);
-    const size_t rlds_big = row_lds_bytes(W, cap_big);
-    SPADE_HIP(ctx, hipFuncSetAttribute((const void *)k_rows<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)rlds_big));
-    SPADE_HIP(ctx, hipFuncSetAttribute((const void *)k_rows<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)rlds_big));
+    SPADE_HIP(ctx, hipFuncSetAttribute((const void *)k_rows<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)std::max(rlds, rlds_big)));
+    SPADE_HIP(ctx, hipFuncSetAttribute((const void *)k_rows<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)std::max(rlds, rlds_big)));
     const int rgrid = (int)std::min<int64_t>(H, 8192);
-    // Rows longer than the stage run in a second launch with the largest
-    // stage, on the context's internal stream beside the first launch (a
-    // few long border rows would otherwise add their whole latency).
-    const bool big = T > (uint64_t)ra.cap;
+    // The long rows run in a second launch, one workgroup per listed row, on
+    // the context's internal stream beside the first launch (a few long
+    // border rows would otherwise add their whole latency).
+    const bool big = nlong > 0;
     if (big && !ctx->side) {
         SPADE_HIP(ctx, hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
         SPADE_HIP(ctx, hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
@@ -1526,10 +1762,13 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
             a2.cap = cap_big;
             a2.min_n = ra.cap + 1;
             a2.max_n = 0x7fffffff;
+            a2.rows = longrows;
+            a2.nlist = (int64_t)nlong;
+            const int bgrid = (int)std::min<uint64_t>(nlong, 8192);
             if ((e = hipEventRecord(ctx->fork, qs)) != hipSuccess) return e;
             if ((e = hipStreamWaitEvent(ctx->side, ctx->fork, 0)) != hipSuccess) return e;
-            if (emit) hipLaunchKernelGGL(k_rows<true>, dim3(rgrid), dim3(ROW_THREADS), rlds_big, ctx->side, a2);
-            else hipLaunchKernelGGL(k_rows<false>, dim3(rgrid), dim3(ROW_THREADS), rlds_big, ctx->side, a2);
+            if (emit) hipLaunchKernelGGL(k_rows<true>, dim3(bgrid), dim3(ROW_THREADS), rlds_big, ctx->side, a2);
+            else hipLaunchKernelGGL(k_rows<false>, dim3(bgrid), dim3(ROW_THREADS), rlds_big, ctx->side, a2);
             if ((e = hipGetLastError()) != hipSuccess) return e;
             if ((e = hipEventRecord(ctx->join, ctx->side)) != hipSuccess) return e;
         }
@@ -1588,12 +1827,13 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
         auto put = [&](uint64_t v) { key.push_back(v); };
         auto putp = [&](const void *p) { key.push_back((uint64_t)(uintptr_t)p); };
         put(T); put((uint64_t)V); put((uint64_t)H); put((uint64_t)W); put((uint64_t)nc); put((uint64_t)coarse_tot);
-        put((uint64_t)cbits); put((uint64_t)pbits); put((uint64_t)kbits); put(tbytes);
+        put((uint64_t)cbits); put((uint64_t)pbits); put((uint64_t)kbits); put(tbytes); put(tscan);
+        put(bucketed ? 1 : 0); put((uint64_t)ebits); put(sort_lds); put(nlong);
         put((uint64_t)ra.cap); put((uint64_t)cap_big); put(rlds); put(rlds_big); put((uint64_t)rgrid);
         put(ra.cap_rec); put(ra.cap_loc); put(ra.cap_part); put(big ? 1 : 0);
         putp(cv->edges.p); putp(epoly); putp(erow0); putp(nrows); putp(eoff); putp(d_cds);
         putp(dk.p); putp(dk2.p); putp(dv.p); putp(dv2.p); putp(dc.p); putp(df.p); putp(drow.p); putp(cub.p);
-        putp(ra.gaux); putp(gctr); putp(d_err); putp(drc.p);
+        putp(ra.gaux); putp(gctr); putp(d_err); putp(drc.p); putp(drs.p);
         putp(cv->cells.p); putp(cv->cands.p); putp(cv->ledges.p); putp(cv->pspan.p); putp(cv->coarse.p);
         putp(cv->desc.p); putp(ctx->side); putp(ctx->fork); putp(ctx->join);
         SPADE_HIP(ctx, run_captured(ctx, cv, key, qs, enqueue));
@@ -1616,7 +1856,7 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
         SPADE_HIP(ctx, hipMemsetAsync(drc.p, 0, 8 * 8 * ((size_t)H + 1), st));
         SPADE_HIP(ctx, launch_rows(false));
         // per-row bases (exclusive scans over H+1 entries with a zero tail)
-        tb = 0;
+        size_t tb = 0;
         SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(nullptr, tb, row_nrec, rec_base, H + 1, st));
         if (ensure(ctx, cub, tb)) return SPADE_E_NOMEM;
         SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(cub.p, tb, row_nrec, rec_base, H + 1, st));
