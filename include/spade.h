@@ -80,7 +80,14 @@ typedef struct {
  * n_rings is passed explicitly so that the offsets can be validated.
  * n_vertices: the vertex count ring_vtx_off[n_rings] when the caller knows it
  * (saves reading it back from the device); <= 0 means unknown.  A positive
- * value that differs from ring_vtx_off[n_rings] is SPADE_E_INVALID. */
+ * value that differs from ring_vtx_off[n_rings] is SPADE_E_INVALID.
+ * bbox: optional HOST array {x_min, x_max, y_min, y_max} of the vertices
+ * (NULL: computed on the device and read back).  With it, the plain calls
+ * and spade_canvas_build size the canvas without waiting for the device;
+ * the device still validates the offsets and the box before any kernel
+ * depends on them, and a box that does not contain every vertex, like any
+ * other invalid input, fails the call with SPADE_E_INVALID.  Canvas sets
+ * (the batch calls) ignore it. */
 typedef struct {
     int64_t n_polys;
     int64_t n_rings;
@@ -89,6 +96,7 @@ typedef struct {
     const double *vx;
     const double *vy;
     int64_t n_vertices;
+    const double *bbox;
 } spade_polys;
 
 typedef struct spade_ctx spade_ctx;

@@ -147,11 +147,14 @@ void spade_ctx_destroy(spade_ctx *ctx)
         delete ctx->plain;
     }
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    if (ctx->pend) (void)hipHostFree(ctx->pend);
     for (auto &e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
     if (ctx->fork) (void)hipEventDestroy(ctx->fork);
     if (ctx->join) (void)hipEventDestroy(ctx->join);
+    if (ctx->join2) (void)hipEventDestroy(ctx->join2);
     if (ctx->side) (void)hipStreamDestroy(ctx->side);
+    if (ctx->side2) (void)hipStreamDestroy(ctx->side2);
     if (ctx->capture) (void)hipStreamDestroy(ctx->capture);
     delete ctx;
 }
@@ -321,7 +324,7 @@ int spade_canvas_join_pairs(spade_ctx *ctx, const spade_canvas *cv, const spade_
 }
 
 // Plain calls: rasterise into the context's own canvas, then probe.
-static int plain_build(spade_ctx *ctx, const spade_polys *polys, spade_canvas **cvo)
+static int plain_build(spade_ctx *ctx, const spade_polys *polys, spade_canvas **cvo, bool defer)
 {
     int rc = check_ctx(ctx);
     if (rc) return rc;
@@ -332,12 +335,32 @@ static int plain_build(spade_ctx *ctx, const spade_polys *polys, spade_canvas **
         ctx->plain->device = ctx->device;
     }
     if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[0], ctx->stream));
-    rc = build_canvas(ctx, polys, ctx->plain);
+    rc = build_canvas(ctx, polys, ctx->plain, defer);
     if (rc) return rc;
     if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[1], ctx->stream));
     ctx->timed_raster = ctx->timing;
     *cvo = ctx->plain;
     return SPADE_OK;
+}
+
+// The probe is queued right behind the build, whose counters and flags are
+// read at the probe's own synchronisation: a build that ran out of
+// capacity is redone (with room to spare) and probed again; an invalid
+// input fails the call whatever the probe returned.
+extern "C++" template <typename F>
+static int plain_query(spade_ctx *ctx, const spade_polys *polys, F &&probe)
+{
+    spade_canvas *cv = nullptr;
+    int rc = plain_build(ctx, polys, &cv, true);
+    if (rc) return rc;
+    const int rp = probe(cv);
+    SPADE_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    const int rf = build_finish(ctx, cv);
+    if (rf == BUILD_AGAIN) {
+        if ((rc = plain_build(ctx, polys, &cv, false))) return rc;
+        return probe(cv);
+    }
+    return rf ? rf : rp;
 }
 
 int spade_select(spade_ctx *ctx, const spade_points *pts, const spade_polys *poly, uint32_t *out_ids,
@@ -348,9 +371,9 @@ int spade_select(spade_ctx *ctx, const spade_points *pts, const spade_polys *pol
     if (poly && poly->n_polys != 1) return set_error(ctx, SPADE_E_INVALID, "selection needs exactly one polygon");
     int rc = check_points(ctx, pts);
     if (rc) return rc;
-    spade_canvas *cv = nullptr;
-    if ((rc = plain_build(ctx, poly, &cv))) return rc;
-    return spade_canvas_select(ctx, cv, pts, out_ids, cap, n_out);
+    return plain_query(ctx, poly, [&](spade_canvas *cv) {
+        return spade_canvas_select(ctx, cv, pts, out_ids, cap, n_out);
+    });
 }
 
 int spade_join_count(spade_ctx *ctx, const spade_points *pts, const spade_polys *polys, uint64_t *out_counts)
@@ -358,9 +381,9 @@ int spade_join_count(spade_ctx *ctx, const spade_points *pts, const spade_polys 
     if (!ctx) return SPADE_E_INVALID;
     int rc = check_points(ctx, pts);
     if (rc) return rc;
-    spade_canvas *cv = nullptr;
-    if ((rc = plain_build(ctx, polys, &cv))) return rc;
-    return spade_canvas_join_count(ctx, cv, pts, out_counts);
+    return plain_query(ctx, polys, [&](spade_canvas *cv) {
+        return spade_canvas_join_count_async(ctx, cv, pts, out_counts);
+    });
 }
 
 int spade_join_pairs(spade_ctx *ctx, const spade_points *pts, const spade_polys *polys, uint32_t *out_pt,
@@ -370,9 +393,9 @@ int spade_join_pairs(spade_ctx *ctx, const spade_points *pts, const spade_polys 
     if (n_out) *n_out = 0;
     int rc = check_points(ctx, pts);
     if (rc) return rc;
-    spade_canvas *cv = nullptr;
-    if ((rc = plain_build(ctx, polys, &cv))) return rc;
-    return spade_canvas_join_pairs(ctx, cv, pts, out_pt, out_poly, cap, n_out);
+    return plain_query(ctx, polys, [&](spade_canvas *cv) {
+        return spade_canvas_join_pairs(ctx, cv, pts, out_pt, out_poly, cap, n_out);
+    });
 }
 
 // ---- exact predicate, exposed for isolated testing

@@ -117,6 +117,7 @@ struct spade_canvas {
     spade::DevBuf cells, cands, ledges, pspan, edges, coarse, desc;
     std::vector<uint64_t> gkey;               // launch parameters of the last build
     hipGraphExec_t gexec = nullptr;           // its captured launches (second build on)
+    bool pending = false;                     // built, counters and flags not yet read
     size_t bytes() const
     {
         return cells.cap + cands.cap + ledges.cap + pspan.cap + coarse.cap + desc.cap;
@@ -131,13 +132,15 @@ struct spade_ctx {
     double ppv = 256.0;                     // automatic sizing: pixels per vertex
     spade::DevBuf scratch[17];              // reusable scratch slots
     void *pinned = nullptr;                 // small pinned host staging area
+    void *pend = nullptr;                   // pinned counters and flags of a deferred build
     spade_canvas *plain = nullptr;          // canvas reused by the plain query calls
     bool timing = false;                    // record phase events (raster, probe)
     bool timed_raster = false;              // last query rasterised under timing
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     size_t pinned_cap = 0;
-    hipStream_t side = nullptr;             // internal stream for overlapped launches
-    hipEvent_t fork = nullptr, join = nullptr;
+    hipStream_t side = nullptr;             // internal streams for overlapped launches
+    hipStream_t side2 = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr, join2 = nullptr;
     hipStream_t capture = nullptr;          // internal stream graphs are captured on
     bool graphs = true;                     // replay repeated canvas builds from graphs
     int64_t graph_captures = 0, graph_replays = 0;
@@ -157,10 +160,17 @@ int ensure(spade_ctx *ctx, DevBuf &b, size_t bytes);
 void *ensure_pinned(spade_ctx *ctx, size_t bytes);
 void free_buf(DevBuf &b);
 
-int build_canvas(spade_ctx *ctx, const spade_polys *polys, spade_canvas *cv);
+// `defer`: leave the build's counters and flags in flight (read by
+// build_finish after the caller's next synchronisation) instead of waiting.
+int build_canvas(spade_ctx *ctx, const spade_polys *polys, spade_canvas *cv, bool defer = false);
+// Completes a deferred build; returns BUILD_AGAIN when the single row pass
+// ran out of capacity (grown by now: build again, non-deferred).
+constexpr int BUILD_AGAIN = 1;
+int build_finish(spade_ctx *ctx, spade_canvas *cv);
 void drop_graph(spade_canvas *cv);
 // Rasterises polygons [pbound[q], pbound[q+1]) into canvas q, q < nc.
-int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *pbound, spade_canvas *cv);
+int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *pbound, spade_canvas *cv,
+              bool defer = false);
 CanvasView view_of(const spade_canvas *cv, int q);
 
 // LDS bytes the count probe leaves for the coarse canvas, given the polygon

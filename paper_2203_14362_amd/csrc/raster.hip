@@ -209,17 +209,18 @@ __global__ __launch_bounds__(256) void k_canvas_bbox(int64_t R, const int64_t *r
 // Conservative footprint of an edge in pixel row r: the columns [c0, c1]
 // its part inside the row band, dilated by MARGIN, can touch.  (ulo, vlo)
 // and (uhi, vhi) are the edge's end points in pixel coordinates.
+// inv_dv = 1 / (vhi - vlo), computed once per edge: the product differs
+// from the quotient by a few units in the last place of t, far below SLOP.
 __device__ __forceinline__ void row_footprint(const CanvasDesc &m, double ulo, double uhi, double vlo, double vhi,
-                                              int32_t r, int32_t &c0, int32_t &c1)
+                                              double inv_dv, int32_t r, int32_t &c0, int32_t &c1)
 {
     const double b0 = (double)r - MARGIN, b1 = (double)r + 1.0 + MARGIN;
     double xa, xb;
     if (vlo == vhi) {
         xa = ulo; xb = uhi;
     } else {
-        const double dv = vhi - vlo;
-        const double ta = fmin(1.0, fmax(0.0, (b0 - vlo) / dv));
-        const double tb = fmin(1.0, fmax(0.0, (b1 - vlo) / dv));
+        const double ta = fmin(1.0, fmax(0.0, (b0 - vlo) * inv_dv));
+        const double tb = fmin(1.0, fmax(0.0, (b1 - vlo) * inv_dv));
         xa = ulo + ta * (uhi - ulo);
         xb = ulo + tb * (uhi - ulo);
     }
@@ -228,48 +229,155 @@ __device__ __forceinline__ void row_footprint(const CanvasDesc &m, double ulo, d
     c1 = (int32_t)fmax(0.0, fmin(floor(xmx + MARGIN), (double)(m.W - 1)));
 }
 
+constexpr int ROW_WIN = 4096;   // rows of a workgroup's LDS row window
+constexpr int LANE_ROWS_W = 16; // rows an edge's own lane walks; longer edges are walked by the wave
+
+// Calls fn(row) for every row of the (edge, row) entries of this thread's
+// edge (rows g0 .. g0 + nr - 1); edges of more than LANE_ROWS_W rows are
+// walked by their whole wave.
+template <typename Fn>
+__device__ __forceinline__ void for_entry_rows(int64_t g0, int nr, Fn fn)
+{
+    const int lane = threadIdx.x & 63;
+    if (nr > 0 && nr <= LANE_ROWS_W)
+        for (int t = 0; t < nr; ++t) fn(g0 + t);
+    unsigned long long longs = __ballot(nr > LANE_ROWS_W);
+    while (longs) {
+        const int src = __ffsll((long long)longs) - 1;
+        longs &= longs - 1;
+        const int64_t gg = __shfl(g0, src, 64);
+        const int nn = __shfl(nr, src, 64);
+        for (int t = lane; t < nn; t += 64) fn(gg + t);
+    }
+}
+
+// Per-row entry counts of a workgroup's edges added to global counters
+// (one every rstride words): counted in LDS over the rows the workgroup
+// touches, then one global atomic per touched row.  Returns true with the
+// counters' old values (each touched row's first slot for this workgroup)
+// in hist[row - *s_lo].  When the rows span more than ROW_WIN it returns
+// false having added nothing if `base`, per entry otherwise.  Every thread
+// of the block calls it (barriers).
+__device__ bool block_row_counts(int64_t g0, int nr, uint32_t *ctr, int rstride, uint32_t *hist,
+                                 int *s_lo, int *s_hi, bool base)
+{
+    const int tid = threadIdx.x;
+    if (tid == 0) { *s_lo = 0x7fffffff; *s_hi = -1; }
+    __syncthreads();
+    if (nr > 0) { atomicMin(s_lo, (int)g0); atomicMax(s_hi, (int)(g0 + nr - 1)); }
+    __syncthreads();
+    const int lo = *s_lo, n = *s_hi - *s_lo + 1;
+    if (n > 0 && n <= ROW_WIN) {
+        for (int k = tid; k < n; k += blockDim.x) hist[k] = 0u;
+        __syncthreads();
+        for_entry_rows(g0, nr, [&](int64_t g) { atomicAdd(&hist[g - lo], 1u); });
+        __syncthreads();
+        for (int k = tid; k < n; k += blockDim.x) {
+            const uint32_t c = hist[k];
+            if (c) {
+                const uint32_t old = atomicAdd(&ctr[(int64_t)(lo + k) * rstride], c);
+                if (base) hist[k] = old;
+            }
+        }
+        __syncthreads();
+        return true;
+    }
+    if (n > 0 && !base) for_entry_rows(g0, nr, [&](int64_t g) { atomicAdd(&ctr[g * rstride], 1u); });
+    __syncthreads();
+    return false;
+}
+
+__device__ __forceinline__ double undkey(unsigned long long k)
+{
+    const unsigned long long b = (k & 0x8000000000000000ull) ? (k & 0x7fffffffffffffffull) : ~k;
+    return __longlong_as_double((long long)b);
+}
+
+// Edges, their canvas rows and the row histogram.  With `guard` (a canvas
+// sized from the caller's bounding box before the validation was read), the
+// kernel first checks the validation flags and that the vertices' box lies
+// inside the given one; otherwise it flags 128 and emits no entries, so
+// nothing downstream reads the polygon arrays.
 __global__ __launch_bounds__(256) void k_edges(int64_t R, const int64_t *rvo, int64_t V,
                                                const double *vx, const double *vy,
                                                const int32_t *ring_poly, const CanvasDesc *cds, int nc,
                                                Edge *edges, uint32_t *epoly, int32_t *erow0,
-                                               uint64_t *nrows, int32_t *rdiff)
+                                               uint64_t *nrows, uint32_t *rcount, int rstride, int guard,
+                                               unsigned *errflags, const unsigned long long *bbk,
+                                               double hx0, double hx1, double hy0, double hy1)
 {
     const int64_t nth = (int64_t)gridDim.x * blockDim.x;
     if (blockIdx.x == 0 && threadIdx.x == 0) nrows[V] = 0;   // zero tail of the row-count scan
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < V; j += nth) {
-        // ring of vertex j: rvo[r] <= j < rvo[r+1]
-        int64_t lo = 0, hi = R;
-        while (hi - lo > 1) {
-            int64_t mid = (lo + hi) >> 1;
-            if (rvo[mid] <= j) lo = mid; else hi = mid;
+    if (guard) {
+        __shared__ int s_ok;
+        if (threadIdx.x == 0) {
+            const unsigned f = __hip_atomic_load(errflags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            bool ok = !(f & (1u | 2u | 4u | 64u));
+            if (ok && V > 0) {
+                const double x0 = undkey(bbk[0]), x1 = -undkey(bbk[1]);
+                const double y0 = undkey(bbk[2]), y1 = -undkey(bbk[3]);
+                ok = x0 >= hx0 && x1 <= hx1 && y0 >= hy0 && y1 <= hy1;
+                if (!ok && blockIdx.x == 0) atomicOr(errflags, 128u);
+            }
+            s_ok = ok ? 1 : 0;
         }
-        const int64_t r = lo;
-        const int64_t nx = (j + 1 < rvo[r + 1]) ? j + 1 : rvo[r];
-        double ax = vx[j], ay = vy[j], bx = vx[nx], by = vy[nx];
-        epoly[j] = (uint32_t)ring_poly[r];
-        const CanvasDesc &m = cds[canvas_of_poly(cds, nc, ring_poly[r])];
-        Edge e;
-        if (ay <= by) { e.xlo = ax; e.ylo = ay; e.xhi = bx; e.yhi = by; }
-        else          { e.xlo = bx; e.ylo = by; e.xhi = ax; e.yhi = ay; }
-        edges[j] = e;
-        if ((ax == bx && ay == by) || m.empty) { nrows[j] = 0; erow0[j] = 0; continue; }   // zero length
-        double vlo = __dmul_rn(__dsub_rn(e.ylo, m.Y0), m.sy);
-        double vhi = __dmul_rn(__dsub_rn(e.yhi, m.Y0), m.sy);
-        double f0 = floor(vlo - MARGIN), f1 = floor(vhi + MARGIN);
-        int32_t r0 = (int32_t)fmax(0.0, fmin(f0, (double)(m.H - 1)));
-        int32_t r1 = (int32_t)fmax(0.0, fmin(f1, (double)(m.H - 1)));
-        erow0[j] = r0;
-        nrows[j] = (uint64_t)(r1 - r0 + 1);
-        // row histogram as a difference array: +1 on rows r0..r1
-        atomicAdd(&rdiff[m.row_base + r0], 1);
-        atomicSub(&rdiff[m.row_base + r1 + 1], 1);
+        __syncthreads();
+        if (!s_ok) {
+            for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < V; j += nth) {
+                nrows[j] = 0;
+                erow0[j] = 0;
+            }
+            return;
+        }
+    }
+    __shared__ uint32_t hist[ROW_WIN];
+    __shared__ int s_lo, s_hi;
+    const int64_t iters = (V + nth - 1) / nth;   // the same for every thread (block barriers)
+    for (int64_t it = 0; it < iters; ++it) {
+        const int64_t j = it * nth + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        int64_t g0 = 0;
+        int nr = 0;
+        if (j < V) {
+            // ring of vertex j: rvo[r] <= j < rvo[r+1]
+            int64_t lo = 0, hi = R;
+            while (hi - lo > 1) {
+                int64_t mid = (lo + hi) >> 1;
+                if (rvo[mid] <= j) lo = mid; else hi = mid;
+            }
+            const int64_t r = lo;
+            const int64_t nx = (j + 1 < rvo[r + 1]) ? j + 1 : rvo[r];
+            double ax = vx[j], ay = vy[j], bx = vx[nx], by = vy[nx];
+            epoly[j] = (uint32_t)ring_poly[r];
+            const CanvasDesc &m = cds[canvas_of_poly(cds, nc, ring_poly[r])];
+            Edge e;
+            if (ay <= by) { e.xlo = ax; e.ylo = ay; e.xhi = bx; e.yhi = by; }
+            else          { e.xlo = bx; e.ylo = by; e.xhi = ax; e.yhi = ay; }
+            edges[j] = e;
+            if ((ax == bx && ay == by) || m.empty) {   // zero length
+                nrows[j] = 0;
+                erow0[j] = 0;
+            } else {
+                double vlo = __dmul_rn(__dsub_rn(e.ylo, m.Y0), m.sy);
+                double vhi = __dmul_rn(__dsub_rn(e.yhi, m.Y0), m.sy);
+                double f0 = floor(vlo - MARGIN), f1 = floor(vhi + MARGIN);
+                int32_t r0 = (int32_t)fmax(0.0, fmin(f0, (double)(m.H - 1)));
+                int32_t r1 = (int32_t)fmax(0.0, fmin(f1, (double)(m.H - 1)));
+                erow0[j] = r0;
+                nrows[j] = (uint64_t)(r1 - r0 + 1);
+                g0 = m.row_base + r0;
+                nr = r1 - r0 + 1;
+            }
+        }
+        // one entry per row r0..r1: counted per row of the block's window
+        // in LDS, then one global atomic per row the block touches
+        (void)block_row_counts(g0, nr, rcount, rstride, hist, &s_lo, &s_hi, false);
     }
 }
 
-__global__ void k_zero_i32(int64_t n, int32_t *p)
+__global__ void k_zero_u32(int64_t n, uint32_t *p)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = 0;
+        p[i] = 0u;
 }
 
 // ------------------------------------------------------------ row buckets
@@ -294,37 +402,37 @@ __device__ long long block_excl_sum(long long v, long long *wtot)
     return pre + inc - v;
 }
 
-// One block: entry count of every row from the difference array, the row
-// offsets (row_off[Htot] = total), insertion cursors starting at the
-// offsets, and the list of rows with more than `cap` entries.
-// info = {total entries, longest row, number of listed rows}.
-__global__ __launch_bounds__(SCAN_THREADS) void k_rowscan(int64_t Htot, const int32_t *rdiff, int cap,
-                                                          uint32_t *row_off, uint32_t *cursor,
-                                                          uint32_t *longrows, unsigned long long *info)
+// One block: from the per-row entry counts (one word every `rstride`, so
+// that the edges' atomics spread over cache lines) the row offsets
+// (row_off[Htot] = total), insertion cursors starting at the offsets (same
+// stride), and two row lists: rows with more than capA and at most capB
+// entries (longrows[0..)), rows with more than capB entries
+// (longrows[Htot..)).
+// info = {total entries, longest row, rows of the first list, of the second}.
+__global__ __launch_bounds__(SCAN_THREADS) void k_rowscan(int64_t Htot, const uint32_t *rcount, int rstride,
+                                                          int capA, int capB, uint32_t *row_off,
+                                                          uint32_t *cursor, uint32_t *longrows,
+                                                          unsigned long long *info)
 {
     __shared__ long long wtot[SCAN_THREADS / 64];
-    __shared__ unsigned s_nlong;
+    __shared__ unsigned s_nb, s_nc;
     __shared__ int s_max;
     const int tid = threadIdx.x;
-    if (tid == 0) { s_nlong = 0; s_max = 0; }
+    if (tid == 0) { s_nb = 0; s_nc = 0; s_max = 0; }
     const int64_t per = (Htot + SCAN_THREADS - 1) / SCAN_THREADS;
     const int64_t b = min(Htot, (int64_t)tid * per), e = min(Htot, b + per);
-    long long d = 0;
-    for (int64_t r = b; r < e; ++r) d += rdiff[r];
-    const long long cnt0 = block_excl_sum(d, wtot);      // entries of row b-1 (0 for b = 0)
-    long long cnt = cnt0, tot = 0;
-    for (int64_t r = b; r < e; ++r) { cnt += rdiff[r]; tot += cnt; }
-    const long long off0 = block_excl_sum(tot, wtot);
-    long long off = off0;
+    long long tot = 0;
+    for (int64_t r = b; r < e; ++r) tot += rcount[r * rstride];
+    long long off = block_excl_sum(tot, wtot);
     int mx = 0;
-    cnt = cnt0;
     for (int64_t r = b; r < e; ++r) {
-        cnt += rdiff[r];
+        const long long cnt = rcount[r * rstride];
         row_off[r] = (uint32_t)off;
-        cursor[r] = (uint32_t)off;
+        cursor[r * rstride] = (uint32_t)off;
         off += cnt;
         mx = max(mx, (int)min(cnt, (long long)0x7fffffff));
-        if (cnt > cap) longrows[atomicAdd(&s_nlong, 1u)] = (uint32_t)r;
+        if (cnt > capB) longrows[Htot + atomicAdd(&s_nc, 1u)] = (uint32_t)r;
+        else if (cnt > capA) longrows[atomicAdd(&s_nb, 1u)] = (uint32_t)r;
     }
     atomicMax(&s_max, mx);
     __syncthreads();
@@ -332,7 +440,8 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_rowscan(int64_t Htot, const in
         row_off[Htot] = (uint32_t)off;
         info[0] = (unsigned long long)off;
         info[1] = (unsigned long long)s_max;
-        info[2] = s_nlong;
+        info[2] = s_nb;
+        info[3] = s_nc;
     }
 }
 
@@ -361,13 +470,14 @@ __global__ __launch_bounds__(256) void k_entries(int64_t V, const Edge *edges, c
         const double uhi = __dmul_rn(__dsub_rn(e.xhi, m.X0), m.sx);
         const double vlo = __dmul_rn(__dsub_rn(e.ylo, m.Y0), m.sy);
         const double vhi = __dmul_rn(__dsub_rn(e.yhi, m.Y0), m.sy);
+        const double inv = vhi > vlo ? 1.0 / (vhi - vlo) : 0.0;
         const uint64_t poly = (uint64_t)((int64_t)epoly[j] - m.poly_base);
         const uint64_t base = off[j];
         for (uint64_t t = t0; t < nr; t += dt) {
             const int32_t r = erow0[j] + (int32_t)t;
             const double b0 = (double)r - MARGIN, b1 = (double)r + 1.0 + MARGIN;
             int32_t c0, c1;
-            row_footprint(m, ulo, uhi, vlo, vhi, r, c0, c1);
+            row_footprint(m, ulo, uhi, vlo, vhi, inv, r, c0, c1);
             const bool span = !horiz && vlo <= b0 && vhi >= b1;
             const double yc = m.Y0 + ((double)r + 0.5) * m.hy;
             const bool w = !horiz && straddles(e.ylo, e.yhi, yc);
@@ -396,22 +506,26 @@ __global__ __launch_bounds__(256) void k_entries(int64_t V, const Edge *edges, c
     }
 }
 
-// Entries written straight into their row's bucket (slot from the row's
-// insertion cursor, so unordered within the row) with the key
-// (polygon, first column, edge id) that orders them inside the row.
+// Entries written straight into their row's bucket with the key
+// (polygon, first column, edge id) that orders them inside the row.  A
+// workgroup reserves, per row it touches, one range of slots with one
+// global atomic on the row's cursor and hands them out from LDS (so the
+// order inside a row is arbitrary until the row sort).
 __global__ __launch_bounds__(256) void k_entries_rows(int64_t V, const Edge *edges, const uint32_t *epoly,
                                                       const int32_t *erow0, const uint64_t *nrows,
                                                       const CanvasDesc *cds, int nc, int ebits,
-                                                      int ckshift, uint32_t *cursor, uint64_t *ukey,
-                                                      uint32_t *uc, uint8_t *uf)
+                                                      int ckshift, uint32_t *cursor, int rstride,
+                                                      uint64_t *ukey, uint32_t *uc, uint8_t *uf)
 {
+    __shared__ uint32_t hist[ROW_WIN];
+    __shared__ int s_lo, s_hi;
     const int lane = threadIdx.x & 63;
     const int64_t nth = (int64_t)gridDim.x * blockDim.x;
     auto entry = [&](int64_t j, const CanvasDesc &m, double ulo, double uhi, double vlo, double vhi,
-                     bool horiz, const Edge &e, uint64_t poly, int32_t r, uint32_t pos) {
+                     double inv, bool horiz, const Edge &e, uint64_t poly, int32_t r, uint32_t pos) {
         const double b0 = (double)r - MARGIN, b1 = (double)r + 1.0 + MARGIN;
         int32_t c0, c1;
-        row_footprint(m, ulo, uhi, vlo, vhi, r, c0, c1);
+        row_footprint(m, ulo, uhi, vlo, vhi, inv, r, c0, c1);
         const bool span = !horiz && vlo <= b0 && vhi >= b1;
         const double yc = m.Y0 + ((double)r + 0.5) * m.hy;
         const bool w = !horiz && straddles(e.ylo, e.yhi, yc);
@@ -419,100 +533,137 @@ __global__ __launch_bounds__(256) void k_entries_rows(int64_t V, const Edge *edg
         uc[pos] = (uint32_t)c0 | ((uint32_t)c1 << 16);
         uf[pos] = (span ? F_SPAN : 0) | (w ? F_W : 0) | (horiz ? F_HORIZ : 0);
     };
-    const int64_t iters = (V + nth - 1) / nth;
+    const int64_t iters = (V + nth - 1) / nth;   // the same for every thread (block barriers)
     for (int64_t it = 0; it < iters; ++it) {
         const int64_t j = it * nth + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-        const uint64_t nr = j < V ? nrows[j] : 0;
-        if (nr > 0 && nr <= LANE_ROWS) {
+        const int nr = j < V ? (int)nrows[j] : 0;
+        int64_t g0 = 0;
+        int q = 0;
+        if (nr > 0) {
+            q = canvas_of_poly(cds, nc, epoly[j]);
+            g0 = cds[q].row_base + erow0[j];
+        }
+        const bool win = block_row_counts(g0, nr, cursor, rstride, hist, &s_lo, &s_hi, true);
+        const int lo = s_lo;
+        auto slot = [&](int64_t g) -> uint32_t {
+            return win ? atomicAdd(&hist[g - lo], 1u) : atomicAdd(&cursor[g * rstride], 1u);
+        };
+        if (nr > 0 && nr <= LANE_ROWS_W) {
             const Edge e = edges[j];
-            const CanvasDesc &m = cds[canvas_of_poly(cds, nc, epoly[j])];
-            const int64_t g0 = m.row_base + erow0[j];
-            // all slots first: the cursor atomics overlap instead of queueing
-            uint32_t pos[LANE_ROWS];
+            const CanvasDesc &m = cds[q];
+            // all slots first: the atomics overlap instead of queueing
+            uint32_t pos[LANE_ROWS_W];
 #pragma unroll
-            for (int t = 0; t < (int)LANE_ROWS; ++t)
-                if (t < (int)nr) pos[t] = atomicAdd(&cursor[g0 + t], 1u);
+            for (int t = 0; t < LANE_ROWS_W; ++t)
+                if (t < nr) pos[t] = slot(g0 + t);
             const bool horiz = (e.ylo == e.yhi);
             const double ulo = __dmul_rn(__dsub_rn(e.xlo, m.X0), m.sx);
             const double uhi = __dmul_rn(__dsub_rn(e.xhi, m.X0), m.sx);
             const double vlo = __dmul_rn(__dsub_rn(e.ylo, m.Y0), m.sy);
             const double vhi = __dmul_rn(__dsub_rn(e.yhi, m.Y0), m.sy);
+            const double inv = vhi > vlo ? 1.0 / (vhi - vlo) : 0.0;
             const uint64_t poly = (uint64_t)((int64_t)epoly[j] - m.poly_base);
 #pragma unroll
-            for (int t = 0; t < (int)LANE_ROWS; ++t)
-                if (t < (int)nr) entry(j, m, ulo, uhi, vlo, vhi, horiz, e, poly, erow0[j] + t, pos[t]);
+            for (int t = 0; t < LANE_ROWS_W; ++t)
+                if (t < nr) entry(j, m, ulo, uhi, vlo, vhi, inv, horiz, e, poly, erow0[j] + t, pos[t]);
         }
-        unsigned long long longs = __ballot(nr > LANE_ROWS);
+        // long edges are walked by their whole wave
+        unsigned long long longs = __ballot(nr > LANE_ROWS_W);
         while (longs) {
             const int src = __ffsll((long long)longs) - 1;
             longs &= longs - 1;
             const int64_t jj = __shfl(j, src, 64);
-            const uint64_t nn = __shfl(nr, src, 64);
+            const int nn = __shfl(nr, src, 64);
+            const int qq = __shfl(q, src, 64);
             const Edge e = edges[jj];
-            const CanvasDesc &m = cds[canvas_of_poly(cds, nc, epoly[jj])];
+            const CanvasDesc &m = cds[qq];
             const bool horiz = (e.ylo == e.yhi);
             const double ulo = __dmul_rn(__dsub_rn(e.xlo, m.X0), m.sx);
             const double uhi = __dmul_rn(__dsub_rn(e.xhi, m.X0), m.sx);
             const double vlo = __dmul_rn(__dsub_rn(e.ylo, m.Y0), m.sy);
             const double vhi = __dmul_rn(__dsub_rn(e.yhi, m.Y0), m.sy);
+            const double inv = vhi > vlo ? 1.0 / (vhi - vlo) : 0.0;
             const uint64_t poly = (uint64_t)((int64_t)epoly[jj] - m.poly_base);
-            for (uint64_t t = (uint64_t)lane; t < nn; t += 64) {
-                const int32_t r = erow0[jj] + (int32_t)t;
-                const uint32_t pos = atomicAdd(&cursor[m.row_base + r], 1u);
-                entry(jj, m, ulo, uhi, vlo, vhi, horiz, e, poly, r, pos);
+            const int32_t r0 = erow0[jj];
+            for (int t = lane; t < nn; t += 64) {
+                const uint32_t pos = slot(m.row_base + r0 + t);
+                entry(jj, m, ulo, uhi, vlo, vhi, inv, horiz, e, poly, r0 + t, pos);
             }
         }
+        __syncthreads();   // the window's slots are handed out before the next round
     }
 }
 
-// Longest row the in-row sort takes (its keys and source slots in LDS).
+// Longest row the in-row sort takes (its keys twice in LDS).
 constexpr int ROWSORT_MAX = 4096;
 constexpr int SORT_THREADS = 256;
+constexpr int SORT_CHUNKS = ROWSORT_MAX / SORT_THREADS;
 
-// Sorts every row's entries by key in LDS (bitonic network over the next
-// power of two, padded with the largest key) and writes them in that order:
-// polygon and edge from the key, footprint and flags from the source slot.
+// Sorts every row's entries by key and writes them in that order: polygon
+// and edge from the key, footprint and flags from the source slot.  Keys
+// are unique.  The row is cut into chunks of one key per thread; a key's
+// rank in its chunk is the count of smaller keys there (the chunk is then
+// stored sorted), and its rank in the row adds, for every other chunk, the
+// count of smaller keys found by binary search.  The listed long rows
+// (nB + nC of them, with more than `cap` entries) come first, so that the
+// longest sorts do not start last.
 __global__ __launch_bounds__(SORT_THREADS) void k_rowsort(int64_t Htot, const uint32_t *row_off,
                                                           const uint64_t *ukey, const uint32_t *uc,
                                                           const uint8_t *uf, int pshift, uint64_t emask,
                                                           uint32_t *s_poly, uint32_t *s_edge, uint32_t *s_c,
-                                                          uint8_t *s_f, int pmax)
+                                                          uint8_t *s_f, int pmax, const uint32_t *longrows,
+                                                          int64_t nB, int64_t nC, int cap)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    uint64_t *kk = (uint64_t *)smem;
-    uint16_t *ix = (uint16_t *)(kk + pmax);
+    uint64_t *kk = (uint64_t *)smem;      // keys in bucket order
+    uint64_t *sk = kk + pmax;             // keys, each chunk sorted
     const int tid = threadIdx.x;
-    for (int64_t r = blockIdx.x; r < Htot; r += gridDim.x) {
+    const int64_t items = nC + nB + Htot;
+    for (int64_t k = blockIdx.x; k < items; k += gridDim.x) {
+        const int64_t r = k < nC ? (int64_t)longrows[Htot + k] : k < nC + nB ? (int64_t)longrows[k - nC] : k - nC - nB;
         const uint32_t s = row_off[r];
         const int n = (int)(row_off[r + 1] - s);
-        if (n == 0) continue;
-        int P = 1;
-        while (P < n) P <<= 1;
-        for (int q = tid; q < P; q += SORT_THREADS) {
-            kk[q] = q < n ? ukey[s + q] : ~0ull;
-            ix[q] = (uint16_t)q;
+        if (n == 0 || (k >= nC + nB && n > cap)) continue;
+        const int C = (n + SORT_THREADS - 1) / SORT_THREADS;
+        for (int i = tid; i < n; i += SORT_THREADS) kk[i] = ukey[s + i];
+        __syncthreads();
+        int lr[SORT_CHUNKS];
+#pragma unroll
+        for (int c = 0; c < SORT_CHUNKS; ++c) {
+            const int i = c * SORT_THREADS + tid;
+            lr[c] = 0;
+            if (c < C && i < n) {
+                const uint64_t x = kk[i];
+                const int cb = c * SORT_THREADS, ce = min(n, cb + SORT_THREADS);
+                int rank = 0;
+#pragma unroll 8
+                for (int q = cb; q < ce; ++q) rank += (kk[q] < x) ? 1 : 0;
+                lr[c] = rank;
+                sk[cb + rank] = x;
+            }
         }
         __syncthreads();
-        for (int k = 2; k <= P; k <<= 1)
-            for (int j = k >> 1; j > 0; j >>= 1) {
-                for (int t = tid; t < (P >> 1); t += SORT_THREADS) {
-                    const int i = ((t & ~(j - 1)) << 1) | (t & (j - 1));
-                    const int l = i | j;
-                    const uint64_t a = kk[i], b = kk[l];
-                    if ((a > b) == ((i & k) == 0)) {
-                        kk[i] = b; kk[l] = a;
-                        const uint16_t x = ix[i]; ix[i] = ix[l]; ix[l] = x;
+#pragma unroll
+        for (int c = 0; c < SORT_CHUNKS; ++c) {
+            const int i = c * SORT_THREADS + tid;
+            if (c < C && i < n) {
+                const uint64_t x = kk[i];
+                int g = lr[c];
+                for (int o = 0; o < C; ++o) {
+                    if (o == c) continue;
+                    int lo = o * SORT_THREADS, hi = min(n, lo + SORT_THREADS);
+                    const int b = lo;
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        if (sk[mid] < x) lo = mid + 1; else hi = mid;
                     }
+                    g += lo - b;
                 }
-                __syncthreads();
+                s_poly[s + g] = (uint32_t)(x >> pshift);
+                s_edge[s + g] = (uint32_t)(x & emask);
+                s_c[s + g] = uc[s + i];
+                s_f[s + g] = uf[s + i];
             }
-        for (int q = tid; q < n; q += SORT_THREADS) {
-            const uint64_t key = kk[q];
-            const uint32_t src = s + ix[q];
-            s_poly[s + q] = (uint32_t)(key >> pshift);
-            s_edge[s + q] = (uint32_t)(key & emask);
-            s_c[s + q] = uc[src];
-            s_f[s + q] = uf[src];
         }
         __syncthreads();
     }
@@ -1061,7 +1212,12 @@ __device__ void process_row(const RowArgs &A, const RowData &D, const RowShared 
             s_base[3] = over ? 1ull : 0ull;
         }
         __syncthreads();
-        if (s_base[3]) return;
+        if (s_base[3]) {
+            // abandoned: an empty row, so that a probe run before the host
+            // has seen the flag reads no stale record index
+            for (int c = tid; c < W; c += ROW_THREADS) cells_q[tile_index(Wt, c, r_local)] = 0u;
+            return;
+        }
     }
     if (!EMIT) {
         if (tid == 0) {
@@ -1413,9 +1569,65 @@ static void choose_size(const spade_ctx *ctx, double w, double h, int64_t nverts
     H = (int)std::max(1.0, std::min(16384.0, std::round(target / W)));
 }
 
-int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *pbound, spade_canvas *cv)
+// First error among the build's device flags (0 if none).
+static int flag_error(spade_ctx *ctx, unsigned ef)
+{
+    if (ef & 1u) return set_error(ctx, SPADE_E_INVALID, "ring_vtx_off must start at 0 and be non-decreasing");
+    if (ef & 2u) return set_error(ctx, SPADE_E_INVALID, "poly_ring_off must start at 0, be non-decreasing and end at n_rings");
+    if (ef & 4u) return set_error(ctx, SPADE_E_INVALID, "non-finite polygon vertex coordinate");
+    if (ef & 64u) return set_error(ctx, SPADE_E_INVALID, "n_vertices does not match ring_vtx_off[n_rings]");
+    if (ef & 128u) return set_error(ctx, SPADE_E_INVALID, "a polygon vertex lies outside the given bounding box");
+    if (ef & 8u) return set_error(ctx, SPADE_E_HIP, "internal: boundary pixel without candidates");
+    if (ef & 16u)
+        return set_error(ctx, SPADE_E_UNSUPPORTED, "a boundary pixel has more than 32767 edges of one polygon; raise the canvas resolution");
+    return SPADE_OK;
+}
+
+// Leaves the build's counters and flags on their way to pinned memory;
+// build_finish reads them after the caller's next synchronisation.
+static int defer_counters(spade_ctx *ctx, spade_canvas *cv, const unsigned long long *gctr, const unsigned *d_err)
+{
+    if (!ctx->pend && hipHostMalloc(&ctx->pend, 64, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        ctx->pend = nullptr;
+        return set_error(ctx, SPADE_E_NOMEM, "pinned staging allocation failed");
+    }
+    uint64_t *hc = (uint64_t *)ctx->pend;
+    SPADE_HIP(ctx, hipMemcpyAsync(hc, gctr, 32, hipMemcpyDeviceToHost, ctx->stream));
+    SPADE_HIP(ctx, hipMemcpyAsync(hc + 4, d_err, sizeof(unsigned), hipMemcpyDeviceToHost, ctx->stream));
+    cv->pending = true;
+    return SPADE_OK;
+}
+
+int build_finish(spade_ctx *ctx, spade_canvas *cv)
+{
+    if (!cv->pending) return SPADE_OK;
+    cv->pending = false;
+    const uint64_t *hc = (const uint64_t *)ctx->pend;
+    unsigned ef;
+    std::memcpy(&ef, hc + 4, sizeof(unsigned));
+    if (ef & (1u | 2u | 4u | 64u | 128u)) return flag_error(ctx, ef);
+    if (ef & 32u) {
+        // the row pass counted every row: with that much room the next
+        // single pass fits
+        if (ensure(ctx, cv->cands, sizeof(Cand) * (size_t)(hc[0] + 1024)) ||
+            ensure(ctx, cv->ledges, sizeof(Edge) * (size_t)(hc[1] + 1024)) ||
+            ensure(ctx, cv->pspan, sizeof(double2) * (size_t)(hc[2] + 16)))
+            return SPADE_E_NOMEM;
+        return BUILD_AGAIN;
+    }
+    if (int rc = flag_error(ctx, ef)) return rc;
+    cv->n_boundary = (int64_t)hc[3];
+    cv->n_cands = (int64_t)hc[0];
+    cv->n_elist = (int64_t)(hc[1] + hc[2]);
+    return SPADE_OK;
+}
+
+int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *pbound, spade_canvas *cv,
+              bool defer)
 {
     hipStream_t st = ctx->stream;
+    cv->pending = false;
     const int64_t M = polys->n_polys, R = polys->n_rings;
     if (nc < 1) return set_error(ctx, SPADE_E_INVALID, "a canvas set needs at least one canvas");
     cv->nc = nc;
@@ -1436,6 +1648,11 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
         if (V < 0) return set_error(ctx, SPADE_E_INVALID, "ring_vtx_off[n_rings] is negative");
         if (V >= (int64_t)0xffffffffLL) return set_error(ctx, SPADE_E_TOO_LARGE, "more than 2^32-1 vertices");
     }
+
+    // With the caller's box (one canvas, vertex count known) the canvas is
+    // sized without waiting for the validation: the edge kernel checks the
+    // flags and the box before anything reads the polygon arrays.
+    const bool hinted = polys->bbox != nullptr && nc == 1 && (R == 0 || polys->n_vertices > 0);
 
     // validation + ring->polygon map
     DevBuf &rp = ctx->scratch[S_RINGPOLY];
@@ -1477,8 +1694,10 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
     }
     DevBuf &dcd = cv->dcds;
     if (ensure(ctx, dcd, sizeof(CanvasDesc) * (size_t)nc)) return SPADE_E_NOMEM;
-    std::memcpy(hcd, cds.data(), sizeof(CanvasDesc) * (size_t)nc);
-    SPADE_HIP(ctx, hipMemcpyAsync(dcd.p, hcd, sizeof(CanvasDesc) * (size_t)nc, hipMemcpyHostToDevice, st));
+    if (!hinted) {
+        std::memcpy(hcd, cds.data(), sizeof(CanvasDesc) * (size_t)nc);
+        SPADE_HIP(ctx, hipMemcpyAsync(dcd.p, hcd, sizeof(CanvasDesc) * (size_t)nc, hipMemcpyHostToDevice, st));
+    }
     std::vector<int64_t> nverts((size_t)nc, 0);
     std::vector<int64_t> pro, rvo;
     if (V > 0 && nc > 1) {
@@ -1498,13 +1717,12 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
                                           hipMemcpyDeviceToHost, st));
         }
     }
-    SPADE_HIP(ctx, hipMemcpyAsync(herr, d_err, sizeof(unsigned), hipMemcpyDeviceToHost, st));
-    SPADE_HIP(ctx, hipMemcpyAsync(hbb, d_bb, bbbytes, hipMemcpyDeviceToHost, st));
-    SPADE_HIP(ctx, hipStreamSynchronize(st));
-    if (herr[0] & 1u) return set_error(ctx, SPADE_E_INVALID, "ring_vtx_off must start at 0 and be non-decreasing");
-    if (herr[0] & 2u) return set_error(ctx, SPADE_E_INVALID, "poly_ring_off must start at 0, be non-decreasing and end at n_rings");
-    if (herr[0] & 4u) return set_error(ctx, SPADE_E_INVALID, "non-finite polygon vertex coordinate");
-    if (herr[0] & 64u) return set_error(ctx, SPADE_E_INVALID, "n_vertices does not match ring_vtx_off[n_rings]");
+    if (!hinted) {
+        SPADE_HIP(ctx, hipMemcpyAsync(herr, d_err, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+        SPADE_HIP(ctx, hipMemcpyAsync(hbb, d_bb, bbbytes, hipMemcpyDeviceToHost, st));
+        SPADE_HIP(ctx, hipStreamSynchronize(st));
+        if (int rc = flag_error(ctx, herr[0])) return rc;
+    }
     if (V > 0) {
         if (nc > 1)
             for (int q = 0; q < nc; ++q) nverts[q] = rvo[pro[pbound[q + 1]]] - rvo[pro[pbound[q]]];
@@ -1525,7 +1743,11 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
     for (int q = 0; q < nc; ++q) {
         CanvasDesc &d = cds[q];
         double x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY;
-        if (nverts[q] > 0 || (nc == 1 && V > 0)) {
+        if (hinted && V > 0) {
+            x0 = polys->bbox[0]; x1 = polys->bbox[1];
+            y0 = polys->bbox[2]; y1 = polys->bbox[3];
+            if (!(x0 <= x1 && y0 <= y1)) return set_error(ctx, SPADE_E_INVALID, "bounding box is not ordered");
+        } else if (nverts[q] > 0 || (nc == 1 && V > 0)) {
             x0 = undkey(hbb[4 * q + 0]); x1 = -undkey(hbb[4 * q + 1]);
             y0 = undkey(hbb[4 * q + 2]); y1 = -undkey(hbb[4 * q + 3]);
         }
@@ -1586,6 +1808,14 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
             return SPADE_E_NOMEM;
         cv->n_boundary = cv->n_cands = cv->n_elist = 0;
         finish_views(cv);
+        if (hinted) {
+            // the validation verdict is still to be read
+            if (defer) return defer_counters(ctx, cv, gctr, d_err);
+            unsigned *hf = (unsigned *)ensure_pinned(ctx, 64);
+            SPADE_HIP(ctx, hipMemcpyAsync(hf, d_err, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+            SPADE_HIP(ctx, hipStreamSynchronize(st));
+            return flag_error(ctx, hf[0]);
+        }
         return SPADE_OK;
     }
     const int W = maxW;
@@ -1598,19 +1828,24 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
     DevBuf &drow = ctx->scratch[S_ROWOFF];
     const size_t Vs = (size_t)V;
     // misc: epoly[V] u32 | erow0[V] i32 | off[V+1] u64
-    // rowscan: rdiff[H+1] i32 | cursor[H] u32 | longrows[H] u32 | info[4] u64
+    // rowscan: rcount[(H+1)*rs] u32 | cursor[H*rs] u32 | longrows[2H] u32 | info[4] u64,
+    // with one counter per cache line (rs words apart) unless the set has
+    // very many rows
+    const int rstride = (H <= 65536) ? 32 : 1;
+    const size_t rs = (size_t)rstride;
     if (ensure(ctx, dn, sizeof(uint64_t) * (Vs + 1)) ||
         ensure(ctx, dmisc, sizeof(uint32_t) * Vs * 2 + sizeof(uint64_t) * (Vs + 2)) ||
-        ensure(ctx, drs, 12 * (size_t)H + 64) || ensure(ctx, drow, 8 * ((size_t)H + 1)))
+        ensure(ctx, drs, 4 * rs * (2 * (size_t)H + 1) + 8 * (size_t)H + 96) ||
+        ensure(ctx, drow, 8 * ((size_t)H + 1)))
         return SPADE_E_NOMEM;
     uint64_t *nrows = (uint64_t *)dn.p;
     uint32_t *epoly = (uint32_t *)dmisc.p;
     int32_t *erow0 = (int32_t *)(epoly + Vs);
     uint64_t *eoff = (uint64_t *)(((uintptr_t)(erow0 + Vs) + 7) & ~(uintptr_t)7);
-    int32_t *rdiff = (int32_t *)drs.p;
-    uint32_t *cursor = (uint32_t *)(rdiff + H + 1);
-    uint32_t *longrows = cursor + H;
-    unsigned long long *rinfo = (unsigned long long *)(((uintptr_t)(longrows + H) + 7) & ~(uintptr_t)7);
+    uint32_t *rcount = (uint32_t *)drs.p;
+    uint32_t *cursor = rcount + (H + 1) * rs;
+    uint32_t *longrows = cursor + H * rs;
+    unsigned long long *rinfo = (unsigned long long *)(((uintptr_t)(longrows + 2 * H) + 7) & ~(uintptr_t)7);
     uint32_t *row_off = (uint32_t *)drow.p;
     // per-row counters of the exact path (8 arrays of H + 1)
     DevBuf &drc = ctx->scratch[S_ROWCNT];
@@ -1618,23 +1853,29 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
 
     // LDS stage of the row kernel: up to `cap` entries of a row; narrow
     // canvases aim for three or four workgroups per CU, wider ones for two
-    // (measured best).  Longer rows go to a second launch over a row list.
+    // (measured best).  Longer rows go to launches over row lists: those up
+    // to capB entries with a stage for two workgroups per CU, the rest with
+    // the largest stage.
     const size_t col_bytes = row_lds_bytes(W, 0);
     const size_t target = (col_bytes <= 40 * 1024) ? 38 * 1024 : (col_bytes <= 60 * 1024) ? 78 * 1024 : 150 * 1024;
     const int cap = (int)std::max<size_t>(256, (target - std::min(target - 256 * 37, col_bytes)) / 37);
+    const int capB = (col_bytes <= 40 * 1024)
+                         ? (int)std::max<size_t>((size_t)cap, (78 * 1024 - col_bytes) / 37) : cap;
 
-    hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(H + 1, 1024)), dim3(256), 0, st, H + 1, rdiff);
+    hipLaunchKernelGGL(k_zero_u32, dim3(grid_for((H + 1) * rstride, 1024)), dim3(256), 0, st, (H + 1) * rstride, rcount);
     hipLaunchKernelGGL(k_edges, dim3(grid_for(V)), dim3(256), 0, st, R, polys->ring_vtx_off, V,
                        polys->vx, polys->vy, (const int32_t *)rp.p, d_cds, nc, (Edge *)cv->edges.p, epoly,
-                       erow0, nrows, rdiff);
+                       erow0, nrows, rcount, rstride, hinted ? 1 : 0, d_err, (const unsigned long long *)d_bb,
+                       hinted ? polys->bbox[0] : 0.0, hinted ? polys->bbox[1] : 0.0,
+                       hinted ? polys->bbox[2] : 0.0, hinted ? polys->bbox[3] : 0.0);
     SPADE_HIP(ctx, hipGetLastError());
-    hipLaunchKernelGGL(k_rowscan, dim3(1), dim3(SCAN_THREADS), 0, st, H, (const int32_t *)rdiff, cap, row_off,
-                       cursor, longrows, rinfo);
+    hipLaunchKernelGGL(k_rowscan, dim3(1), dim3(SCAN_THREADS), 0, st, H, (const uint32_t *)rcount, rstride, cap, capB,
+                       row_off, cursor, longrows, rinfo);
     SPADE_HIP(ctx, hipGetLastError());
     uint64_t *hT = (uint64_t *)ensure_pinned(ctx, 64);
-    SPADE_HIP(ctx, hipMemcpyAsync(hT, rinfo, 3 * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    SPADE_HIP(ctx, hipMemcpyAsync(hT, rinfo, 4 * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
     SPADE_HIP(ctx, hipStreamSynchronize(st));
-    const uint64_t T = hT[0], maxrow = hT[1], nlong = hT[2];
+    const uint64_t T = hT[0], maxrow = hT[1], nlistB = hT[2], nlistC = hT[3];
     if (T >= 0x7fffffffULL) return set_error(ctx, SPADE_E_UNSUPPORTED, "too many (edge,row) entries; lower the canvas height");
 
     const int cbits = std::max(1, bits_for((uint64_t)W - 1));
@@ -1649,6 +1890,10 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
     // before the padding), take one device-wide sort of (row, polygon, first
     // column) instead.  Both give the same order.
     const bool bucketed = maxrow <= (uint64_t)ROWSORT_MAX && pbits + cbits + ebits <= 63;
+    // stage of the longest rows' launch: the longest row, up to 150 KB
+    const int cap_stage = (int)std::max<size_t>((size_t)capB, (150 * 1024 - std::min<size_t>(150 * 1024 - 256 * 37, col_bytes)) / 37);
+    const int cap_big = (int)std::max<uint64_t>((uint64_t)capB, std::min<uint64_t>((uint64_t)cap_stage, maxrow));
+
     if (!bucketed && cbits + pbits + rbits > 64) return set_error(ctx, SPADE_E_UNSUPPORTED, "sort key exceeds 64 bits");
 
     DevBuf &dk = ctx->scratch[S_KEYS], &dk2 = ctx->scratch[S_KEYS2];
@@ -1668,9 +1913,10 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
     hipStream_t qs = st;   // stream of the build's launches (see run_captured)
     DevBuf &cub = ctx->scratch[S_CUBTMP];
     size_t tbytes = 0, tscan = 0;
-    int pmax = 1;
-    while ((uint64_t)pmax < maxrow) pmax <<= 1;
-    const size_t sort_lds = (size_t)pmax * 10 + 16;
+    const int pmax = (int)std::max<uint64_t>(1, maxrow);
+    const size_t sort_lds = (size_t)pmax * 16 + 16;
+    if (bucketed)
+        SPADE_HIP(ctx, hipFuncSetAttribute((const void *)k_rowsort, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sort_lds));
     if (!bucketed) {
         SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(nullptr, tscan, nrows, eoff, (int)(V + 1), st));
         SPADE_HIP(ctx, hipcub::DeviceRadixSort::SortPairs(nullptr, tbytes, (const uint64_t *)dk.p,
@@ -1682,13 +1928,14 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
         hipError_t e;
         if (bucketed) {
             hipLaunchKernelGGL(k_entries_rows, dim3(grid_for(V)), dim3(256), 0, qs, V, (const Edge *)cv->edges.p,
-                               epoly, erow0, nrows, d_cds, nc, ebits, cbits + ebits, cursor, (uint64_t *)dk.p,
-                               ent_c, ent_f);
+                               epoly, erow0, nrows, d_cds, nc, ebits, cbits + ebits, cursor, rstride,
+                               (uint64_t *)dk.p, ent_c, ent_f);
             if ((e = hipGetLastError()) != hipSuccess) return e;
-            hipLaunchKernelGGL(k_rowsort, dim3((unsigned)std::min<int64_t>(H, 8192)), dim3(SORT_THREADS), sort_lds,
+            const int64_t sort_items = H + (int64_t)nlistB + (int64_t)nlistC;
+            hipLaunchKernelGGL(k_rowsort, dim3((unsigned)std::min<int64_t>(sort_items, 65535)), dim3(SORT_THREADS), sort_lds,
                                qs, H, (const uint32_t *)row_off, (const uint64_t *)dk.p, (const uint32_t *)ent_c,
                                (const uint8_t *)ent_f, cbits + ebits, (1ULL << ebits) - 1, s_poly, s_edge, s_c,
-                               s_f, pmax);
+                               s_f, pmax, (const uint32_t *)longrows, (int64_t)nlistB, (int64_t)nlistC, cap);
             return hipGetLastError();
         }
         size_t tb1 = tscan;
@@ -1734,9 +1981,8 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
     ra.errflags = d_err;
     ra.cap = cap;
     const size_t rlds = row_lds_bytes(W, ra.cap);
-    // the listed long rows: a stage for the longest of them, up to 150 KB
-    const int cap_stage = (int)std::max<size_t>((size_t)ra.cap, (150 * 1024 - std::min<size_t>(150 * 1024 - 256 * 37, col_bytes)) / 37);
-    const int cap_big = (int)std::max<uint64_t>((uint64_t)ra.cap, std::min<uint64_t>((uint64_t)cap_stage, maxrow));
+    const size_t rlds_mid = row_lds_bytes(W, capB);
+    // the longest rows: a stage for the longest of them, up to 150 KB
     const size_t rlds_big = row_lds_bytes(W, cap_big);
     if (maxrow > (uint64_t)cap_big) {
         // some row exceeds every stage: global auxiliary words for it
@@ -1746,39 +1992,52 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
     SPADE_HIP(ctx, hipFuncSetAttribute((const void *)k_rows<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)std::max(rlds, rlds_big)));
     SPADE_HIP(ctx, hipFuncSetAttribute((const void *)k_rows<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)std::max(rlds, rlds_big)));
     const int rgrid = (int)std::min<int64_t>(H, 8192);
-    // The long rows run in a second launch, one workgroup per listed row, on
-    // the context's internal stream beside the first launch (a few long
-    // border rows would otherwise add their whole latency).
-    const bool big = nlong > 0;
-    if (big && !ctx->side) {
-        SPADE_HIP(ctx, hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
-        SPADE_HIP(ctx, hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
-        SPADE_HIP(ctx, hipEventCreateWithFlags(&ctx->join, hipEventDisableTiming));
+    // The listed rows run in launches of their own, one workgroup per row,
+    // on the context's internal streams beside the launch over all rows (a
+    // few long border rows would otherwise add their whole latency, and the
+    // larger stages would hold back the short rows).
+    const bool midrows = nlistB > 0, bigrows = nlistC > 0;
+    if ((midrows || bigrows) && !ctx->side2) {
+        if (!ctx->side) SPADE_HIP(ctx, hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+        SPADE_HIP(ctx, hipStreamCreateWithFlags(&ctx->side2, hipStreamNonBlocking));
+        if (!ctx->fork) SPADE_HIP(ctx, hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
+        if (!ctx->join) SPADE_HIP(ctx, hipEventCreateWithFlags(&ctx->join, hipEventDisableTiming));
+        SPADE_HIP(ctx, hipEventCreateWithFlags(&ctx->join2, hipEventDisableTiming));
     }
+    auto launch_list = [&](bool emit, hipStream_t s2, hipEvent_t done, const uint32_t *list, uint64_t n,
+                           int stage, size_t lds, int min_n, int max_n) -> hipError_t {
+        RowArgs a2 = ra;
+        a2.cap = stage;
+        a2.min_n = min_n;
+        a2.max_n = max_n;
+        a2.rows = list;
+        a2.nlist = (int64_t)n;
+        const int bgrid = (int)std::min<uint64_t>(n, 8192);
+        hipError_t e = hipStreamWaitEvent(s2, ctx->fork, 0);
+        if (e != hipSuccess) return e;
+        if (emit) hipLaunchKernelGGL(k_rows<true>, dim3(bgrid), dim3(ROW_THREADS), lds, s2, a2);
+        else hipLaunchKernelGGL(k_rows<false>, dim3(bgrid), dim3(ROW_THREADS), lds, s2, a2);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        return hipEventRecord(done, s2);
+    };
     auto launch_rows = [&](bool emit) -> hipError_t {
         hipError_t e;
-        if (big) {
-            RowArgs a2 = ra;
-            a2.cap = cap_big;
-            a2.min_n = ra.cap + 1;
-            a2.max_n = 0x7fffffff;
-            a2.rows = longrows;
-            a2.nlist = (int64_t)nlong;
-            const int bgrid = (int)std::min<uint64_t>(nlong, 8192);
+        if (midrows || bigrows)
             if ((e = hipEventRecord(ctx->fork, qs)) != hipSuccess) return e;
-            if ((e = hipStreamWaitEvent(ctx->side, ctx->fork, 0)) != hipSuccess) return e;
-            if (emit) hipLaunchKernelGGL(k_rows<true>, dim3(bgrid), dim3(ROW_THREADS), rlds_big, ctx->side, a2);
-            else hipLaunchKernelGGL(k_rows<false>, dim3(bgrid), dim3(ROW_THREADS), rlds_big, ctx->side, a2);
-            if ((e = hipGetLastError()) != hipSuccess) return e;
-            if ((e = hipEventRecord(ctx->join, ctx->side)) != hipSuccess) return e;
-        }
+        if (bigrows && (e = launch_list(emit, ctx->side2, ctx->join2, longrows + H, nlistC, cap_big, rlds_big,
+                                        capB + 1, 0x7fffffff)) != hipSuccess)
+            return e;
+        if (midrows && (e = launch_list(emit, ctx->side, ctx->join, longrows, nlistB, capB, rlds_mid,
+                                        ra.cap + 1, capB)) != hipSuccess)
+            return e;
         RowArgs a1 = ra;
         a1.min_n = 0;
         a1.max_n = ra.cap;
         if (emit) hipLaunchKernelGGL(k_rows<true>, dim3(rgrid), dim3(ROW_THREADS), rlds, qs, a1);
         else hipLaunchKernelGGL(k_rows<false>, dim3(rgrid), dim3(ROW_THREADS), rlds, qs, a1);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        if (big) return hipStreamWaitEvent(qs, ctx->join, 0);
+        if (midrows && (e = hipStreamWaitEvent(qs, ctx->join, 0)) != hipSuccess) return e;
+        if (bigrows && (e = hipStreamWaitEvent(qs, ctx->join2, 0)) != hipSuccess) return e;
         return hipSuccess;
     };
     ra.cells = (uint32_t *)cv->cells.p;
@@ -1828,20 +2087,26 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
         auto putp = [&](const void *p) { key.push_back((uint64_t)(uintptr_t)p); };
         put(T); put((uint64_t)V); put((uint64_t)H); put((uint64_t)W); put((uint64_t)nc); put((uint64_t)coarse_tot);
         put((uint64_t)cbits); put((uint64_t)pbits); put((uint64_t)kbits); put(tbytes); put(tscan);
-        put(bucketed ? 1 : 0); put((uint64_t)ebits); put(sort_lds); put(nlong);
+        put(bucketed ? 1 : 0); put((uint64_t)ebits); put(sort_lds); put(nlistB); put(nlistC);
+        put((uint64_t)capB); put(rlds_mid); put((uint64_t)rstride);
         put((uint64_t)ra.cap); put((uint64_t)cap_big); put(rlds); put(rlds_big); put((uint64_t)rgrid);
-        put(ra.cap_rec); put(ra.cap_loc); put(ra.cap_part); put(big ? 1 : 0);
+        put(ra.cap_rec); put(ra.cap_loc); put(ra.cap_part);
         putp(cv->edges.p); putp(epoly); putp(erow0); putp(nrows); putp(eoff); putp(d_cds);
         putp(dk.p); putp(dk2.p); putp(dv.p); putp(dv2.p); putp(dc.p); putp(df.p); putp(drow.p); putp(cub.p);
         putp(ra.gaux); putp(gctr); putp(d_err); putp(drc.p); putp(drs.p);
         putp(cv->cells.p); putp(cv->cands.p); putp(cv->ledges.p); putp(cv->pspan.p); putp(cv->coarse.p);
-        putp(cv->desc.p); putp(ctx->side); putp(ctx->fork); putp(ctx->join);
+        putp(cv->desc.p); putp(ctx->side); putp(ctx->side2); putp(ctx->fork); putp(ctx->join); putp(ctx->join2);
         SPADE_HIP(ctx, run_captured(ctx, cv, key, qs, enqueue));
+        if (defer) {
+            finish_views(cv);
+            return defer_counters(ctx, cv, gctr, d_err);
+        }
         uint64_t *hc = (uint64_t *)ensure_pinned(ctx, 64);
         SPADE_HIP(ctx, hipMemcpyAsync(hc, gctr, 32, hipMemcpyDeviceToHost, st));
         SPADE_HIP(ctx, hipMemcpyAsync(hc + 4, d_err, sizeof(unsigned), hipMemcpyDeviceToHost, st));
         SPADE_HIP(ctx, hipStreamSynchronize(st));
         std::memcpy(&ef, hc + 4, sizeof(unsigned));
+        if (ef & (1u | 2u | 4u | 64u | 128u)) return flag_error(ctx, ef);   // a hinted build's verdict
         if (!(ef & 32u)) {
             done_single = true;
             nrec = hc[0]; nloc = hc[1]; npart = hc[2]; nbp = hc[3];
@@ -1887,9 +2152,7 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
         SPADE_HIP(ctx, hipStreamSynchronize(st));
         ef = herr2[0];
     }
-    if (ef & 8u) return set_error(ctx, SPADE_E_HIP, "internal: boundary pixel without candidates");
-    if (ef & 16u)
-        return set_error(ctx, SPADE_E_UNSUPPORTED, "a boundary pixel has more than 32767 edges of one polygon; raise the canvas resolution");
+    if (int rc = flag_error(ctx, ef)) return rc;
     cv->n_boundary = (int64_t)nbp;
     cv->n_cands = (int64_t)nrec;
     cv->n_elist = (int64_t)(nloc + npart);
@@ -1897,10 +2160,10 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
     return SPADE_OK;
 }
 
-int build_canvas(spade_ctx *ctx, const spade_polys *polys, spade_canvas *cv)
+int build_canvas(spade_ctx *ctx, const spade_polys *polys, spade_canvas *cv, bool defer)
 {
     const int64_t b[2] = {0, polys->n_polys};
-    return build_set(ctx, polys, 1, b, cv);
+    return build_set(ctx, polys, 1, b, cv, defer);
 }
 
 }  // namespace spade

@@ -53,7 +53,8 @@ class _Points(ctypes.Structure):
 class _Polys(ctypes.Structure):
     _fields_ = [("n_polys", ctypes.c_int64), ("n_rings", ctypes.c_int64),
                 ("poly_ring_off", ctypes.c_void_p), ("ring_vtx_off", ctypes.c_void_p),
-                ("vx", ctypes.c_void_p), ("vy", ctypes.c_void_p), ("n_vertices", ctypes.c_int64)]
+                ("vx", ctypes.c_void_p), ("vy", ctypes.c_void_p), ("n_vertices", ctypes.c_int64),
+                ("bbox", ctypes.c_void_p)]
 
 
 _lib = None
@@ -136,6 +137,15 @@ class DevicePolys:
         self.poly_ring_off = None if pro is None else _dev_i64(pro, device)
         self.vx = _dev_f64(polys["vx"], device)
         self.vy = _dev_f64(polys["vy"], device)
+        # bounding box of host vertex arrays (the library checks it on the
+        # device); device arrays are left to the library
+        self.bbox = None
+        hx, hy = polys["vx"], polys["vy"]
+        if not isinstance(hx, torch.Tensor) and not isinstance(hy, torch.Tensor):
+            hx = np.asarray(hx, dtype=np.float64)
+            hy = np.asarray(hy, dtype=np.float64)
+            if hx.size and hx.size == hy.size and np.all(np.isfinite(hx)) and np.all(np.isfinite(hy)):
+                self.bbox = np.array([hx.min(), hx.max(), hy.min(), hy.max()], dtype=np.float64)
 
     def cstruct(self):
         return _Polys(self.n_polys, self.n_rings,
@@ -143,7 +153,8 @@ class DevicePolys:
                       self.ring_vtx_off.data_ptr() if self.ring_vtx_off.numel() else 0,
                       self.vx.data_ptr() if self.vx.numel() else 0,
                       self.vy.data_ptr() if self.vy.numel() else 0,
-                      int(self.vx.numel()))
+                      int(self.vx.numel()),
+                      None if self.bbox is None else self.bbox.ctypes.data)
 
 
 def _compact(buf, m):
