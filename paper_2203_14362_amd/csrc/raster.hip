@@ -82,12 +82,21 @@ __device__ __forceinline__ unsigned long long dkey(double v)
 
 // Clears the build's flags and counters in one launch: error flags, the
 // per-canvas box keys (to the maximum key), the row-pass counters.
+// Output ranges of the single row pass come from NSHARD independent
+// allocators (row r uses allocator r mod NSHARD, each owning an equal slice
+// of every output array), each counter on a cache line of its own, so that
+// the rows' reservations do not queue on one address.
+constexpr int NSHARD = 16;
+constexpr int GSTRIDE = 16;                        // words between counters
+constexpr int NGCTR = NSHARD * 4 * GSTRIDE;        // counter block, 8 KB
+__host__ __device__ inline int gctr_at(int shard, int c) { return (shard * 4 + c) * GSTRIDE; }
+
 __global__ void k_init(unsigned *errflags, unsigned long long *bb, int64_t nbb, unsigned long long *gctr)
 {
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nth = (int64_t)gridDim.x * blockDim.x;
     if (tid == 0) *errflags = 0u;
-    if (tid < 8) gctr[tid] = 0ull;
+    for (int64_t i = tid; i < NGCTR; i += nth) gctr[i] = 0ull;
     for (int64_t i = tid; i < nbb; i += nth) bb[i] = ~0ull;
 }
 
@@ -746,8 +755,8 @@ struct RowArgs {
     int64_t nlist;
     // single-pass allocation: per-row output ranges reserved with atomics
     int alloc;
-    unsigned long long *gctr;    // [0] records, [1] local edges, [2] partial spans, [3] boundary pixels
-    unsigned long long cap_rec, cap_loc, cap_part;
+    unsigned long long *gctr;    // per shard: records, local edges, partial spans, boundary pixels
+    unsigned long long cap_rec, cap_loc, cap_part;   // per shard
     // count pass
     uint64_t *row_nrec, *row_nloc, *row_npart, *row_nbp;
     // emit pass
@@ -1202,13 +1211,16 @@ __device__ void process_row(const RowArgs &A, const RowData &D, const RowShared 
         // reserve this row's output ranges; an overflow abandons the row and
         // the host redoes the canvas with exact sizes
         if (tid == 0) {
-            s_base[0] = atomicAdd(&A.gctr[0], *s_nrec);
-            s_base[1] = atomicAdd(&A.gctr[1], *s_nloc);
-            s_base[2] = atomicAdd(&A.gctr[2], (unsigned long long)npart_r);
-            atomicAdd(&A.gctr[3], (unsigned long long)*s_nbp);
-            const bool over = s_base[0] + *s_nrec > A.cap_rec || s_base[1] + *s_nloc > A.cap_loc ||
-                              s_base[2] + npart_r > A.cap_part || s_base[0] + *s_nrec >= (unsigned long long)BFLAG;
+            const int sh = (int)(r % NSHARD);
+            const unsigned long long b0 = atomicAdd(&A.gctr[gctr_at(sh, 0)], *s_nrec);
+            const unsigned long long b1 = atomicAdd(&A.gctr[gctr_at(sh, 1)], *s_nloc);
+            const unsigned long long b2 = atomicAdd(&A.gctr[gctr_at(sh, 2)], (unsigned long long)npart_r);
+            atomicAdd(&A.gctr[gctr_at(sh, 3)], (unsigned long long)*s_nbp);
+            const bool over = b0 + *s_nrec > A.cap_rec || b1 + *s_nloc > A.cap_loc || b2 + npart_r > A.cap_part;
             if (over) atomicOr(A.errflags, 32u);
+            s_base[0] = (unsigned long long)sh * A.cap_rec + b0;
+            s_base[1] = (unsigned long long)sh * A.cap_loc + b1;
+            s_base[2] = (unsigned long long)sh * A.cap_part + b2;
             s_base[3] = over ? 1ull : 0ull;
         }
         __syncthreads();
@@ -1583,18 +1595,39 @@ static int flag_error(spade_ctx *ctx, unsigned ef)
     return SPADE_OK;
 }
 
+// Host copy of the row pass's counter block and flags: NGCTR words, then
+// the flags word.
+constexpr size_t COUNTER_COPY = sizeof(uint64_t) * NGCTR + 64;
+
+static hipError_t copy_counters(uint64_t *hc, const unsigned long long *gctr, const unsigned *d_err, hipStream_t st)
+{
+    hipError_t e = hipMemcpyAsync(hc, gctr, sizeof(uint64_t) * NGCTR, hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return e;
+    return hipMemcpyAsync(hc + NGCTR, d_err, sizeof(unsigned), hipMemcpyDeviceToHost, st);
+}
+
+// Totals over the shards of counter c, and the largest shard's.
+static uint64_t counter_total(const uint64_t *hc, int c, uint64_t *largest = nullptr)
+{
+    uint64_t t = 0, m = 0;
+    for (int k = 0; k < NSHARD; ++k) {
+        t += hc[gctr_at(k, c)];
+        m = std::max<uint64_t>(m, hc[gctr_at(k, c)]);
+    }
+    if (largest) *largest = m;
+    return t;
+}
+
 // Leaves the build's counters and flags on their way to pinned memory;
 // build_finish reads them after the caller's next synchronisation.
 static int defer_counters(spade_ctx *ctx, spade_canvas *cv, const unsigned long long *gctr, const unsigned *d_err)
 {
-    if (!ctx->pend && hipHostMalloc(&ctx->pend, 64, hipHostMallocDefault) != hipSuccess) {
+    if (!ctx->pend && hipHostMalloc(&ctx->pend, COUNTER_COPY, hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
         ctx->pend = nullptr;
         return set_error(ctx, SPADE_E_NOMEM, "pinned staging allocation failed");
     }
-    uint64_t *hc = (uint64_t *)ctx->pend;
-    SPADE_HIP(ctx, hipMemcpyAsync(hc, gctr, 32, hipMemcpyDeviceToHost, ctx->stream));
-    SPADE_HIP(ctx, hipMemcpyAsync(hc + 4, d_err, sizeof(unsigned), hipMemcpyDeviceToHost, ctx->stream));
+    SPADE_HIP(ctx, copy_counters((uint64_t *)ctx->pend, gctr, d_err, ctx->stream));
     cv->pending = true;
     return SPADE_OK;
 }
@@ -1605,21 +1638,24 @@ int build_finish(spade_ctx *ctx, spade_canvas *cv)
     cv->pending = false;
     const uint64_t *hc = (const uint64_t *)ctx->pend;
     unsigned ef;
-    std::memcpy(&ef, hc + 4, sizeof(unsigned));
+    std::memcpy(&ef, hc + NGCTR, sizeof(unsigned));
     if (ef & (1u | 2u | 4u | 64u | 128u)) return flag_error(ctx, ef);
+    uint64_t mrec, mloc, mpart;
+    const uint64_t nrec = counter_total(hc, 0, &mrec), nloc = counter_total(hc, 1, &mloc);
+    const uint64_t npart = counter_total(hc, 2, &mpart);
     if (ef & 32u) {
-        // the row pass counted every row: with that much room the next
-        // single pass fits
-        if (ensure(ctx, cv->cands, sizeof(Cand) * (size_t)(hc[0] + 1024)) ||
-            ensure(ctx, cv->ledges, sizeof(Edge) * (size_t)(hc[1] + 1024)) ||
-            ensure(ctx, cv->pspan, sizeof(double2) * (size_t)(hc[2] + 16)))
+        // the row pass counted every row: with room for every shard's
+        // count the next single pass fits
+        if (ensure(ctx, cv->cands, sizeof(Cand) * (size_t)(NSHARD * (mrec + 64))) ||
+            ensure(ctx, cv->ledges, sizeof(Edge) * (size_t)(NSHARD * (mloc + 64))) ||
+            ensure(ctx, cv->pspan, sizeof(double2) * (size_t)(NSHARD * (mpart + 1))))
             return SPADE_E_NOMEM;
         return BUILD_AGAIN;
     }
     if (int rc = flag_error(ctx, ef)) return rc;
-    cv->n_boundary = (int64_t)hc[3];
-    cv->n_cands = (int64_t)hc[0];
-    cv->n_elist = (int64_t)(hc[1] + hc[2]);
+    cv->n_boundary = (int64_t)counter_total(hc, 3);
+    cv->n_cands = (int64_t)nrec;
+    cv->n_elist = (int64_t)(nloc + npart);
     return SPADE_OK;
 }
 
@@ -1659,12 +1695,12 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
     DevBuf &br = ctx->scratch[S_BLOCKRED];
     const size_t bbbytes = sizeof(unsigned long long) * 4 * (size_t)nc;
     if (ensure(ctx, rp, sizeof(int32_t) * (size_t)std::max<int64_t>(R, 1)) ||
-        ensure(ctx, br, sizeof(double) * 4 * RED_BLOCKS + 64 + bbbytes + 64))
+        ensure(ctx, br, sizeof(double) * 4 * RED_BLOCKS + 64 + bbbytes + 128 + sizeof(uint64_t) * NGCTR))
         return SPADE_E_NOMEM;
     unsigned *d_err = (unsigned *)((char *)br.p + sizeof(double) * 4 * RED_BLOCKS);
     unsigned long long *d_bb = (unsigned long long *)((char *)br.p + sizeof(double) * 4 * RED_BLOCKS + 64);
-    // counters of the row pass: [0..3] allocation
-    unsigned long long *gctr = d_bb + 4 * (size_t)nc;
+    // allocation counters of the row pass (cache-line aligned)
+    unsigned long long *gctr = (unsigned long long *)(((uintptr_t)(d_bb + 4 * (size_t)nc) + 127) & ~(uintptr_t)127);
     hipLaunchKernelGGL(k_init, dim3((unsigned)std::min<int64_t>((4 * (int64_t)nc + 255) / 256 + 1, 1024)), dim3(256), 0,
                        st, d_err, d_bb, 4 * (int64_t)nc, gctr);
     SPADE_HIP(ctx, hipGetLastError());
@@ -2067,9 +2103,9 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
             ensure(ctx, cv->ledges, sizeof(Edge) * (size_t)(2 * T + 1024)) ||
             ensure(ctx, cv->pspan, sizeof(double2) * (size_t)(T + 16)))
             return SPADE_E_NOMEM;
-        ra.cap_rec = std::min<uint64_t>(cv->cands.cap / sizeof(Cand), (uint64_t)BFLAG - 1);
-        ra.cap_loc = std::min<uint64_t>(cv->ledges.cap / sizeof(Edge), 0xffffffffULL);
-        ra.cap_part = std::min<uint64_t>(cv->pspan.cap / sizeof(double2), 0xffffffffULL);
+        ra.cap_rec = std::min<uint64_t>(cv->cands.cap / sizeof(Cand), (uint64_t)BFLAG - 1) / NSHARD;
+        ra.cap_loc = std::min<uint64_t>(cv->ledges.cap / sizeof(Edge), 0xffffffffULL) / NSHARD;
+        ra.cap_part = std::min<uint64_t>(cv->pspan.cap / sizeof(double2), 0xffffffffULL) / NSHARD;
         ra.cands = (Cand *)cv->cands.p;
         ra.ledges = (Edge *)cv->ledges.p;
         ra.pspan = (double2 *)cv->pspan.p;
@@ -2101,15 +2137,16 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
             finish_views(cv);
             return defer_counters(ctx, cv, gctr, d_err);
         }
-        uint64_t *hc = (uint64_t *)ensure_pinned(ctx, 64);
-        SPADE_HIP(ctx, hipMemcpyAsync(hc, gctr, 32, hipMemcpyDeviceToHost, st));
-        SPADE_HIP(ctx, hipMemcpyAsync(hc + 4, d_err, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+        uint64_t *hc = (uint64_t *)ensure_pinned(ctx, COUNTER_COPY);
+        if (!hc) return set_error(ctx, SPADE_E_NOMEM, "pinned staging allocation failed");
+        SPADE_HIP(ctx, copy_counters(hc, gctr, d_err, st));
         SPADE_HIP(ctx, hipStreamSynchronize(st));
-        std::memcpy(&ef, hc + 4, sizeof(unsigned));
+        std::memcpy(&ef, hc + NGCTR, sizeof(unsigned));
         if (ef & (1u | 2u | 4u | 64u | 128u)) return flag_error(ctx, ef);   // a hinted build's verdict
         if (!(ef & 32u)) {
             done_single = true;
-            nrec = hc[0]; nloc = hc[1]; npart = hc[2]; nbp = hc[3];
+            nrec = counter_total(hc, 0); nloc = counter_total(hc, 1);
+            npart = counter_total(hc, 2); nbp = counter_total(hc, 3);
         } else {
             // overflow: clear the flag and redo with exact sizes
             ef &= ~32u;
