@@ -605,7 +605,7 @@ __global__ __launch_bounds__(256) void k_entries_rows(int64_t V, const Edge *edg
 
 // Longest row the in-row sort takes (its keys twice in LDS).
 constexpr int ROWSORT_MAX = 4096;
-constexpr int SORT_THREADS = 256;
+constexpr int SORT_THREADS = 1024;
 constexpr int SORT_CHUNKS = ROWSORT_MAX / SORT_THREADS;
 
 // Sorts every row's entries by key and writes them in that order: polygon
@@ -660,7 +660,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_rowsort(int64_t Htot, const ui
                 int g = lr[c];
                 for (int o = 0; o < C; ++o) {
                     if (o == c) continue;
-                    int lo = o * SORT_THREADS, hi = min(n, lo + SORT_THREADS);
+                    int lo = o * SORT_THREADS, hi = min(n, lo + SORT_THREADS);   // at most 1024 keys
                     const int b = lo;
                     while (lo < hi) {
                         const int mid = (lo + hi) >> 1;
