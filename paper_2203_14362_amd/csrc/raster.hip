@@ -753,6 +753,8 @@ struct RowArgs {
     int max_n;
     const uint32_t *rows;    // rows of this launch (nullptr: all rows)
     int64_t nlist;
+    const uint32_t *first;   // with rows == nullptr: nfirst rows taken before all others,
+    int64_t nfirst;          // which then skip those of more than `cap` entries
     // single-pass allocation: per-row output ranges reserved with atomics
     int alloc;
     unsigned long long *gctr;    // per shard: records, local edges, partial spans, boundary pixels
@@ -1323,12 +1325,13 @@ __global__ __launch_bounds__(ROW_THREADS) void k_rows(RowArgs A)
     uint8_t *lf = (uint8_t *)(lil + cap);
     const int tid = threadIdx.x;
 
-    const int64_t nr = A.rows ? A.nlist : A.Htot;
+    const int64_t nr = A.rows ? A.nlist : A.nfirst + A.Htot;
     for (int64_t k = blockIdx.x; k < nr; k += gridDim.x) {
-        const int64_t r = A.rows ? (int64_t)A.rows[k] : k;
+        const int64_t r = A.rows ? (int64_t)A.rows[k] : k < A.nfirst ? (int64_t)A.first[k] : k - A.nfirst;
         const int s = (int)A.row_off[r], e = (int)A.row_off[r + 1];
         const int n = e - s;
         if (n < A.min_n || n > A.max_n) continue;
+        if (!A.rows && k >= A.nfirst && n > cap) continue;   // taken first
         const CanvasDesc &cd = A.cds[canvas_of_row(A.cds, A.nc, r)];
         const int W = cd.W, Wt = cd.Wt;
         L.W = W;
@@ -1889,14 +1892,14 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
 
     // LDS stage of the row kernel: up to `cap` entries of a row; narrow
     // canvases aim for three or four workgroups per CU, wider ones for two
-    // (measured best).  Longer rows go to launches over row lists: those up
-    // to capB entries with a stage for two workgroups per CU, the rest with
-    // the largest stage.
+    // (measured best).
     const size_t col_bytes = row_lds_bytes(W, 0);
     const size_t target = (col_bytes <= 40 * 1024) ? 38 * 1024 : (col_bytes <= 60 * 1024) ? 78 * 1024 : 150 * 1024;
     const int cap = (int)std::max<size_t>(256, (target - std::min(target - 256 * 37, col_bytes)) / 37);
-    const int capB = (col_bytes <= 40 * 1024)
-                         ? (int)std::max<size_t>((size_t)cap, (78 * 1024 - col_bytes) / 37) : cap;
+    // rows up to capB entries run in the launch over all rows, taken first,
+    // their entries and auxiliary words in global memory; longer ones get a
+    // launch of their own with a stage for the longest
+    const int capB = std::max(cap, 640);
 
     hipLaunchKernelGGL(k_zero_u32, dim3(grid_for((H + 1) * rstride, 1024)), dim3(256), 0, st, (H + 1) * rstride, rcount);
     hipLaunchKernelGGL(k_edges, dim3(grid_for(V)), dim3(256), 0, st, R, polys->ring_vtx_off, V,
@@ -2017,23 +2020,22 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
     ra.errflags = d_err;
     ra.cap = cap;
     const size_t rlds = row_lds_bytes(W, ra.cap);
-    const size_t rlds_mid = row_lds_bytes(W, capB);
     // the longest rows: a stage for the longest of them, up to 150 KB
     const size_t rlds_big = row_lds_bytes(W, cap_big);
-    if (maxrow > (uint64_t)cap_big) {
-        // some row exceeds every stage: global auxiliary words for it
+    if (maxrow > (uint64_t)cap_big || nlistB > 0) {
+        // rows without a stage: global auxiliary words for them
         if (ensure(ctx, ctx->scratch[S_NEXTP], sizeof(uint32_t) * 6 * Ts)) return SPADE_E_NOMEM;
         ra.gaux = (uint32_t *)ctx->scratch[S_NEXTP].p;
     }
     SPADE_HIP(ctx, hipFuncSetAttribute((const void *)k_rows<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)std::max(rlds, rlds_big)));
     SPADE_HIP(ctx, hipFuncSetAttribute((const void *)k_rows<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)std::max(rlds, rlds_big)));
-    const int rgrid = (int)std::min<int64_t>(H, 8192);
-    // The listed rows run in launches of their own, one workgroup per row,
-    // on the context's internal streams beside the launch over all rows (a
-    // few long border rows would otherwise add their whole latency, and the
-    // larger stages would hold back the short rows).
-    const bool midrows = nlistB > 0, bigrows = nlistC > 0;
-    if ((midrows || bigrows) && !ctx->side2) {
+    // The longest rows run in a launch of their own, one workgroup per row
+    // with a stage for the longest, on an internal stream beside the launch
+    // over all rows (a few long border rows would otherwise add their whole
+    // latency).  That launch takes the mid-length rows first, so that their
+    // slower global-memory passes start at once.
+    const bool bigrows = nlistC > 0;
+    if (bigrows && !ctx->side2) {
         if (!ctx->side) SPADE_HIP(ctx, hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
         SPADE_HIP(ctx, hipStreamCreateWithFlags(&ctx->side2, hipStreamNonBlocking));
         if (!ctx->fork) SPADE_HIP(ctx, hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
@@ -2058,21 +2060,19 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
     };
     auto launch_rows = [&](bool emit) -> hipError_t {
         hipError_t e;
-        if (midrows || bigrows)
-            if ((e = hipEventRecord(ctx->fork, qs)) != hipSuccess) return e;
+        if (bigrows && (e = hipEventRecord(ctx->fork, qs)) != hipSuccess) return e;
         if (bigrows && (e = launch_list(emit, ctx->side2, ctx->join2, longrows + H, nlistC, cap_big, rlds_big,
                                         capB + 1, 0x7fffffff)) != hipSuccess)
             return e;
-        if (midrows && (e = launch_list(emit, ctx->side, ctx->join, longrows, nlistB, capB, rlds_mid,
-                                        ra.cap + 1, capB)) != hipSuccess)
-            return e;
         RowArgs a1 = ra;
         a1.min_n = 0;
-        a1.max_n = ra.cap;
-        if (emit) hipLaunchKernelGGL(k_rows<true>, dim3(rgrid), dim3(ROW_THREADS), rlds, qs, a1);
-        else hipLaunchKernelGGL(k_rows<false>, dim3(rgrid), dim3(ROW_THREADS), rlds, qs, a1);
+        a1.max_n = capB;
+        a1.first = longrows;
+        a1.nfirst = (int64_t)nlistB;
+        const int g1 = (int)std::min<int64_t>(H + (int64_t)nlistB, 8192);
+        if (emit) hipLaunchKernelGGL(k_rows<true>, dim3(g1), dim3(ROW_THREADS), rlds, qs, a1);
+        else hipLaunchKernelGGL(k_rows<false>, dim3(g1), dim3(ROW_THREADS), rlds, qs, a1);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        if (midrows && (e = hipStreamWaitEvent(qs, ctx->join, 0)) != hipSuccess) return e;
         if (bigrows && (e = hipStreamWaitEvent(qs, ctx->join2, 0)) != hipSuccess) return e;
         return hipSuccess;
     };
@@ -2124,8 +2124,8 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
         put(T); put((uint64_t)V); put((uint64_t)H); put((uint64_t)W); put((uint64_t)nc); put((uint64_t)coarse_tot);
         put((uint64_t)cbits); put((uint64_t)pbits); put((uint64_t)kbits); put(tbytes); put(tscan);
         put(bucketed ? 1 : 0); put((uint64_t)ebits); put(sort_lds); put(nlistB); put(nlistC);
-        put((uint64_t)capB); put(rlds_mid); put((uint64_t)rstride);
-        put((uint64_t)ra.cap); put((uint64_t)cap_big); put(rlds); put(rlds_big); put((uint64_t)rgrid);
+        put((uint64_t)capB); put((uint64_t)rstride);
+        put((uint64_t)ra.cap); put((uint64_t)cap_big); put(rlds); put(rlds_big);
         put(ra.cap_rec); put(ra.cap_loc); put(ra.cap_part);
         putp(cv->edges.p); putp(epoly); putp(erow0); putp(nrows); putp(eoff); putp(d_cds);
         putp(dk.p); putp(dk2.p); putp(dv.p); putp(dv2.p); putp(dc.p); putp(df.p); putp(drow.p); putp(cub.p);
