@@ -557,33 +557,28 @@ __global__ __launch_bounds__(256) void k_entries_rows(int64_t V, const Edge *edg
         auto slot = [&](int64_t g) -> uint32_t {
             return win ? atomicAdd(&hist[g - lo], 1u) : atomicAdd(&cursor[g * rstride], 1u);
         };
-        if (nr > 0 && nr <= LANE_ROWS_W) {
-            const Edge e = edges[j];
-            const CanvasDesc &m = cds[q];
-            // all slots first: the atomics overlap instead of queueing
-            uint32_t pos[LANE_ROWS_W];
+        // the wave's entries spread evenly over its lanes: entry k of the
+        // wave belongs to the lane whose inclusive row-count prefix first
+        // exceeds k (found by a binary search over the lanes)
+        int incl = nr;
 #pragma unroll
-            for (int t = 0; t < LANE_ROWS_W; ++t)
-                if (t < nr) pos[t] = slot(g0 + t);
-            const bool horiz = (e.ylo == e.yhi);
-            const double ulo = __dmul_rn(__dsub_rn(e.xlo, m.X0), m.sx);
-            const double uhi = __dmul_rn(__dsub_rn(e.xhi, m.X0), m.sx);
-            const double vlo = __dmul_rn(__dsub_rn(e.ylo, m.Y0), m.sy);
-            const double vhi = __dmul_rn(__dsub_rn(e.yhi, m.Y0), m.sy);
-            const double inv = vhi > vlo ? 1.0 / (vhi - vlo) : 0.0;
-            const uint64_t poly = (uint64_t)((int64_t)epoly[j] - m.poly_base);
-#pragma unroll
-            for (int t = 0; t < LANE_ROWS_W; ++t)
-                if (t < nr) entry(j, m, ulo, uhi, vlo, vhi, inv, horiz, e, poly, erow0[j] + t, pos[t]);
+        for (int d = 1; d < 64; d <<= 1) {
+            const int t = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += t;
         }
-        // long edges are walked by their whole wave
-        unsigned long long longs = __ballot(nr > LANE_ROWS_W);
-        while (longs) {
-            const int src = __ffsll((long long)longs) - 1;
-            longs &= longs - 1;
+        const int E = __shfl(incl, 63, 64);
+        for (int k = lane; k - lane < E; k += 64) {
+            int src = 0;
+#pragma unroll
+            for (int b = 32; b > 0; b >>= 1) {
+                const int probe = __shfl(incl, src + b - 1, 64);
+                if (probe <= k) src += b;
+            }
+            const int before = __shfl(incl, src, 64) - __shfl(nr, src, 64);
             const int64_t jj = __shfl(j, src, 64);
-            const int nn = __shfl(nr, src, 64);
             const int qq = __shfl(q, src, 64);
+            if (k >= E) continue;
+            const int t = k - before;
             const Edge e = edges[jj];
             const CanvasDesc &m = cds[qq];
             const bool horiz = (e.ylo == e.yhi);
@@ -593,11 +588,8 @@ __global__ __launch_bounds__(256) void k_entries_rows(int64_t V, const Edge *edg
             const double vhi = __dmul_rn(__dsub_rn(e.yhi, m.Y0), m.sy);
             const double inv = vhi > vlo ? 1.0 / (vhi - vlo) : 0.0;
             const uint64_t poly = (uint64_t)((int64_t)epoly[jj] - m.poly_base);
-            const int32_t r0 = erow0[jj];
-            for (int t = lane; t < nn; t += 64) {
-                const uint32_t pos = slot(m.row_base + r0 + t);
-                entry(jj, m, ulo, uhi, vlo, vhi, inv, horiz, e, poly, r0 + t, pos);
-            }
+            const int32_t r = erow0[jj] + t;
+            entry(jj, m, ulo, uhi, vlo, vhi, inv, horiz, e, poly, r, slot(m.row_base + r));
         }
         __syncthreads();   // the window's slots are handed out before the next round
     }
