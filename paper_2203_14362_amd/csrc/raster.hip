@@ -542,11 +542,12 @@ __global__ __launch_bounds__(256) void k_entries_rows(int64_t V, const Edge *edg
         uc[pos] = (uint32_t)c0 | ((uint32_t)c1 << 16);
         uf[pos] = (span ? F_SPAN : 0) | (w ? F_W : 0) | (horiz ? F_HORIZ : 0);
     };
-    // one edge per even lane: twice the waves, half the entries per wave
-    const int64_t per = nth >> 1;
+    // one edge per fourth lane: four times the waves, a quarter of the
+    // entries per wave
+    const int64_t per = nth >> 2;
     const int64_t iters = (V + per - 1) / per;   // the same for every thread (block barriers)
     for (int64_t it = 0; it < iters; ++it) {
-        const int64_t j = (lane & 1) ? V : it * per + (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 1);
+        const int64_t j = (lane & 3) ? V : it * per + (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 2);
         const int nr = j < V ? (int)nrows[j] : 0;
         int64_t g0 = 0;
         int q = 0;
@@ -1960,7 +1961,7 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
     auto enqueue_entries = [&]() -> hipError_t {
         hipError_t e;
         if (bucketed) {
-            hipLaunchKernelGGL(k_entries_rows, dim3(grid_for(2 * V)), dim3(256), 0, qs, V, (const Edge *)cv->edges.p,
+            hipLaunchKernelGGL(k_entries_rows, dim3(grid_for(4 * V)), dim3(256), 0, qs, V, (const Edge *)cv->edges.p,
                                epoly, erow0, nrows, d_cds, nc, ebits, cbits + ebits, cursor, rstride,
                                (uint64_t *)dk.p, ent_c, ent_f);
             if ((e = hipGetLastError()) != hipSuccess) return e;
