@@ -336,14 +336,16 @@ __global__ __launch_bounds__(256) void k_edges(int64_t R, const int64_t *rvo, in
                 nrows[j] = 0;
                 erow0[j] = 0;
             }
-            return;
+            return;   // (every block returns: the verdict is the same for all)
         }
     }
     __shared__ uint32_t hist[ROW_WIN];
     __shared__ int s_lo, s_hi;
-    const int64_t iters = (V + nth - 1) / nth;   // the same for every thread (block barriers)
+    // one edge per even lane: twice the waves for the latency-bound work
+    const int64_t per = nth >> 1;
+    const int64_t iters = (V + per - 1) / per;   // the same for every thread (block barriers)
     for (int64_t it = 0; it < iters; ++it) {
-        const int64_t j = it * nth + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        const int64_t j = (threadIdx.x & 1) ? V : it * per + (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 1);
         int64_t g0 = 0;
         int nr = 0;
         if (j < V) {
@@ -1897,7 +1899,7 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
     const int capB = std::max(cap, 640);
 
     hipLaunchKernelGGL(k_zero_u32, dim3(grid_for((H + 1) * rstride, 1024)), dim3(256), 0, st, (H + 1) * rstride, rcount);
-    hipLaunchKernelGGL(k_edges, dim3(grid_for(V)), dim3(256), 0, st, R, polys->ring_vtx_off, V,
+    hipLaunchKernelGGL(k_edges, dim3(grid_for(2 * V)), dim3(256), 0, st, R, polys->ring_vtx_off, V,
                        polys->vx, polys->vy, (const int32_t *)rp.p, d_cds, nc, (Edge *)cv->edges.p, epoly,
                        erow0, nrows, rcount, rstride, hinted ? 1 : 0, d_err, (const unsigned long long *)d_bb,
                        hinted ? polys->bbox[0] : 0.0, hinted ? polys->bbox[1] : 0.0,
