@@ -965,6 +965,62 @@ __device__ void block_plain_scan(uint32_t *a, int n, uint32_t *wtot, Op op)
     __syncthreads();
 }
 
+// The five inclusive scans of phase 2 in one pass: footprint counts (sum),
+// claim counts (sum) and claimant xor over the row's columns, the per-entry
+// partial/spanning prefix (pre_op) and the interval lengths (sum).  Each
+// thread takes a contiguous chunk of every array: chunk totals first (loads
+// only, so they overlap), wave scans of the five totals, one barrier, then
+// the chunks rewritten from their running prefixes.  wt holds 5 words per
+// wave.
+__device__ void row_scans(int32_t *sa, int32_t *sb, uint32_t *sx, int W, uint32_t *pre, int n,
+                          uint32_t *ilen, int ni, uint32_t *wt)
+{
+    constexpr int NW = ROW_THREADS / 64;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int pc = (W + ROW_THREADS - 1) / ROW_THREADS, pp = (n + ROW_THREADS - 1) / ROW_THREADS;
+    const int pi = (ni + ROW_THREADS - 1) / ROW_THREADS;
+    const int cb = min(W, tid * pc), ce = min(W, cb + pc);
+    const int qb = min(n, tid * pp), qe = min(n, qb + pp);
+    const int ib = min(ni, tid * pi), ie = min(ni, ib + pi);
+    uint32_t ta = 0, tb = 0, tx = 0, tp = 0, ti = 0;
+    for (int c = cb; c < ce; ++c) {
+        ta += (uint32_t)sa[cix(c)];
+        tb += (uint32_t)sb[cix(c)];
+        tx ^= sx[cix(c)];
+    }
+    for (int q = qb; q < qe; ++q) tp = pre_op(tp, pre[q]);
+    for (int q = ib; q < ie; ++q) ti += ilen[q];
+    // inclusive wave scans of the chunk totals
+    uint32_t ia = ta, ibb = tb, ix = tx, ip = tp, ii = ti;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t a = __shfl_up(ia, d, 64), b = __shfl_up(ibb, d, 64), x = __shfl_up(ix, d, 64);
+        const uint32_t pq = __shfl_up(ip, d, 64), iq = __shfl_up(ii, d, 64);
+        if (lane >= d) { ia += a; ibb += b; ix ^= x; ip = pre_op(ip, pq); ii += iq; }
+    }
+    if (lane == 63) {
+        wt[0 * NW + wv] = ia; wt[1 * NW + wv] = ibb; wt[2 * NW + wv] = ix;
+        wt[3 * NW + wv] = ip; wt[4 * NW + wv] = ii;
+    }
+    __syncthreads();
+    // exclusive prefix of this thread's chunks
+    uint32_t ra = ia - ta, rb = ibb - tb, rx = ix ^ tx, ri = ii - ti;
+    uint32_t rp = __shfl_up(ip, 1, 64);
+    if (lane == 0) rp = 0u;
+    for (int w = 0; w < wv; ++w) {
+        ra += wt[0 * NW + w]; rb += wt[1 * NW + w]; rx ^= wt[2 * NW + w];
+        rp = pre_op(wt[3 * NW + w], rp); ri += wt[4 * NW + w];
+    }
+    for (int c = cb; c < ce; ++c) {
+        const uint32_t a = (uint32_t)sa[cix(c)], b = (uint32_t)sb[cix(c)], x = sx[cix(c)];
+        ra += a; rb += b; rx ^= x;
+        sa[cix(c)] = (int32_t)ra; sb[cix(c)] = (int32_t)rb; sx[cix(c)] = rx;
+    }
+    for (int q = qb; q < qe; ++q) { rp = pre_op(rp, pre[q]); pre[q] = rp; }
+    for (int q = ib; q < ie; ++q) { ri += ilen[q]; ilen[q] = ri; }
+    __syncthreads();
+}
+
 // Runs every (run, footprint column) item of the row through column_record.
 template <bool EMIT>
 __device__ void all_column_records(const RowArgs &A, const RowData &D, const RowShared &L,
@@ -1162,11 +1218,7 @@ __device__ void process_row(const RowArgs &A, const RowData &D, const RowShared 
 
     // phase 2: prefix scans -> per-pixel boundary count, claim count,
     //          claimant; per-entry partial/spanning prefixes; run spans
-    block_scan(L.sa, W, wtoti, [](int32_t a, int32_t b) { return a + b; }, 0);
-    block_scan(L.sb, W, wtoti, [](int32_t a, int32_t b) { return a + b; }, 0);
-    block_scan(L.sx, W, wtotu, [](uint32_t a, uint32_t b) { return a ^ b; }, 0u);
-    block_plain_scan(D.pre, D.n, wtotu, [](uint32_t a, uint32_t b) { return pre_op(a, b); });
-    block_plain_scan(D.ilen, (int)*L.nint, wtotu, [](uint32_t a, uint32_t b) { return a + b; });
+    row_scans(L.sa, L.sb, L.sx, W, D.pre, D.n, D.ilen, (int)*L.nint, wtotu);
 
     // phase 3: classify pixels.  sx := 0 (no polygon), label + 1, or for a
     // boundary pixel BFLAG | (label + 1 of its single interior claimant, or 0);
@@ -1295,7 +1347,7 @@ __global__ __launch_bounds__(ROW_THREADS) void k_rows(RowArgs A)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int32_t wtoti[ROW_THREADS / 64];
-    __shared__ uint32_t wtotu[ROW_THREADS / 64];
+    __shared__ uint32_t wtotu[5 * (ROW_THREADS / 64)];
     __shared__ uint32_t s_locfill, s_nint, s_nbp, s_multi, s_nlong;
     __shared__ uint32_t s_longq[LONGQ];
     __shared__ unsigned long long s_nloc, s_nrec, s_base[4];
