@@ -716,7 +716,7 @@ __device__ void block_scan(T *a, int n, T *wtot, Op op, T ident)
     const int per = (n + ROW_THREADS - 1) / ROW_THREADS;
     const int b = min(n, tid * per), e = min(n, b + per);
     T acc = ident;
-    for (int i = b; i < e; ++i) { acc = op(acc, a[cix(i)]); a[cix(i)] = acc; }
+    for (int i = b; i < e; ++i) acc = op(acc, a[cix(i)]);   // chunk total: loads only
     T inc = acc;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
@@ -729,7 +729,7 @@ __device__ void block_scan(T *a, int n, T *wtot, Op op, T ident)
     for (int q = 0; q < wv; ++q) pre = op(pre, wtot[q]);
     T prev = __shfl_up(inc, 1, 64);
     if (lane > 0) pre = op(pre, prev);
-    for (int i = b; i < e; ++i) a[cix(i)] = op(pre, a[cix(i)]);
+    for (int i = b; i < e; ++i) { pre = op(pre, a[cix(i)]); a[cix(i)] = pre; }
     __syncthreads();
 }
 
@@ -864,8 +864,12 @@ __device__ __forceinline__ void column_record(const RowArgs &A, const RowData &D
     const uint32_t S = ((pe ^ ps) >> 31) & 1u;
     const uint32_t npart = (pe & 0x7fffffffu) - (ps & 0x7fffffffu);
     uint32_t nloc = 0;
+    uint32_t id0 = 0, id1 = 0, id2 = 0, id3 = 0;   // the last four local edges met
     for (int q = sp - 1; q >= i && (int)(D.pm[q] >> 16) > col; --q)
-        if ((int)(D.c[q] >> 16) >= col && !(D.f[q] & F_HORIZ)) ++nloc;
+        if ((int)(D.c[q] >> 16) >= col && !(D.f[q] & F_HORIZ)) {
+            if (EMIT) { id3 = id2; id2 = id1; id1 = id0; id0 = D.edge[q]; }
+            ++nloc;
+        }
     if (nloc > 0x7fffu || npart > 0x7fffu) atomicOr(A.errflags, 16u);
     if (!EMIT) {
         atomicAdd(&L.sa[cix(col)], 1);
@@ -877,9 +881,22 @@ __device__ __forceinline__ void column_record(const RowArgs &A, const RowData &D
     uint64_t eoff = 0;
     if (nloc) {
         eoff = loc_base_r + atomicAdd(L.locfill, nloc);
-        uint64_t o = eoff;
-        for (int q = sp - 1; q >= i && (int)(D.pm[q] >> 16) > col; --q)
-            if ((int)(D.c[q] >> 16) >= col && !(D.f[q] & F_HORIZ)) A.ledges[o++] = A.edges[D.edge[q]];
+        if (nloc <= 4) {
+            // up to four edges: all loads in flight before the stores (a
+            // pixel's local edges are tested in any order)
+            const Edge e0 = A.edges[id0];
+            const Edge e1 = A.edges[nloc > 1 ? id1 : id0];
+            const Edge e2 = A.edges[nloc > 2 ? id2 : id0];
+            const Edge e3 = A.edges[nloc > 3 ? id3 : id0];
+            A.ledges[eoff] = e0;
+            if (nloc > 1) A.ledges[eoff + 1] = e1;
+            if (nloc > 2) A.ledges[eoff + 2] = e2;
+            if (nloc > 3) A.ledges[eoff + 3] = e3;
+        } else {
+            uint64_t o = eoff;
+            for (int q = sp - 1; q >= i && (int)(D.pm[q] >> 16) > col; --q)
+                if ((int)(D.c[q] >> 16) >= col && !(D.f[q] & F_HORIZ)) A.ledges[o++] = A.edges[D.edge[q]];
+        }
     }
     Cand cd;
     cd.poly = D.poly[i];
