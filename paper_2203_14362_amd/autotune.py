@@ -23,7 +23,7 @@ import math
 import os
 import threading
 
-DEFAULT_CANDIDATES = (32.0, 40.0, 48.0, 56.0, 64.0, 96.0, 128.0, 192.0, 384.0)
+DEFAULT_CANDIDATES = (32.0, 40.0, 48.0, 56.0, 64.0, 80.0, 96.0, 112.0, 128.0, 160.0, 192.0, 384.0)
 PRESET_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_mi355x.json")
 
 
