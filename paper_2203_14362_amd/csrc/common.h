@@ -30,14 +30,22 @@ constexpr uint32_t BFLAG = 0x80000000u;
 // entirely to its right but end inside the pixel row, and S is the parity of
 // the edges entirely to the right that span the whole row.  Local edges are
 // stored with their coordinates (contiguous from eoff); partial-right edges
-// only need their y-range (contiguous from poff).
+// only need their y-range (contiguous from poff).  The first of each is
+// repeated inside the record, so that a record of one local edge and at
+// most one partial-right range is a single 64-byte read.
+struct Edge {
+    double xlo, ylo, xhi, yhi;
+};
 struct Cand {
     uint32_t poly;
     uint32_t meta;   // bit 0: S, bit 1: last record of the pixel,
                      // bits 2..16: n_local, bits 17..31: n_partial
     uint32_t eoff;   // first local edge in the local-edge array
     uint32_t poff;   // first partial-right y-range in the span array
+    Edge e0;         // local edge eoff (when n_local > 0)
+    double2 s0;      // partial-right range poff (when n_partial > 0)
 };
+static_assert(sizeof(Cand) == 64, "a candidate record is one 64-byte read");
 constexpr uint32_t CAND_S = 1u;
 constexpr uint32_t CAND_LAST = 2u;
 // Coarse canvas word (one per 2^blog x 2^blog block of pixels):
@@ -59,10 +67,6 @@ constexpr uint16_t COARSE_FULL = 0xffffu;
 __host__ __device__ inline uint32_t desc_bytes(int blog) { return (1u << (2 * blog)) / 2u; }
 
 // Edge in world coordinates with lo.y <= hi.y.
-struct Edge {
-    double xlo, ylo, xhi, yhi;
-};
-
 // One canvas of a canvas set: its world->pixel map, bounding box, size and
 // where its words live in the set's shared arrays.  A set rasterises many
 // polygon groups (one per canvas) in the same kernel launches; canvas q owns

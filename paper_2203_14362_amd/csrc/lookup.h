@@ -87,13 +87,15 @@ __device__ __forceinline__ bool cand_inside(const CanvasView &cv, const Cand &cd
     bool in = (cd.meta & CAND_S) != 0;
     const uint32_t nloc = (cd.meta >> 2) & 0x7fffu;
     const uint32_t npart = cd.meta >> 17;
+    if (nloc > 0) in ^= crosses(cd.e0.xlo, cd.e0.ylo, cd.e0.xhi, cd.e0.yhi, x, y);
+    if (npart > 0) in ^= straddles(cd.s0.x, cd.s0.y, y);
     const Edge *le = cv.ledges + cd.eoff;
-    for (uint32_t t = 0; t < nloc; ++t) {
+    for (uint32_t t = 1; t < nloc; ++t) {
         const Edge e = le[t];
         in ^= crosses(e.xlo, e.ylo, e.xhi, e.yhi, x, y);
     }
     const double2 *ps = cv.pspan + cd.poff;
-    for (uint32_t t = 0; t < npart; ++t) {
+    for (uint32_t t = 1; t < npart; ++t) {
         const double2 s = ps[t];
         in ^= straddles(s.x, s.y, y);
     }

@@ -879,6 +879,15 @@ __device__ __forceinline__ void column_record(const RowArgs &A, const RowData &D
     uint32_t last;
     const uint64_t slot = rec_slot(L, col, rec_base_r, last);
     uint64_t eoff = 0;
+    Cand cd{};
+    // the record repeats its first partial-right range: that of the run's
+    // first partial entry from sp on
+    uint32_t pid = 0;
+    if (npart) {
+        int q = sp;
+        while (!is_partial(D.f[q])) ++q;
+        pid = D.edge[q];
+    }
     if (nloc) {
         eoff = loc_base_r + atomicAdd(L.locfill, nloc);
         if (nloc <= 4) {
@@ -888,17 +897,27 @@ __device__ __forceinline__ void column_record(const RowArgs &A, const RowData &D
             const Edge e1 = A.edges[nloc > 1 ? id1 : id0];
             const Edge e2 = A.edges[nloc > 2 ? id2 : id0];
             const Edge e3 = A.edges[nloc > 3 ? id3 : id0];
+            const Edge ep = A.edges[pid];
             A.ledges[eoff] = e0;
             if (nloc > 1) A.ledges[eoff + 1] = e1;
             if (nloc > 2) A.ledges[eoff + 2] = e2;
             if (nloc > 3) A.ledges[eoff + 3] = e3;
+            cd.e0 = e0;
+            if (npart) cd.s0 = make_double2(ep.ylo, ep.yhi);
         } else {
             uint64_t o = eoff;
             for (int q = sp - 1; q >= i && (int)(D.pm[q] >> 16) > col; --q)
-                if ((int)(D.c[q] >> 16) >= col && !(D.f[q] & F_HORIZ)) A.ledges[o++] = A.edges[D.edge[q]];
+                if ((int)(D.c[q] >> 16) >= col && !(D.f[q] & F_HORIZ)) {
+                    const Edge e = A.edges[D.edge[q]];
+                    if (o == eoff) cd.e0 = e;
+                    A.ledges[o++] = e;
+                }
         }
     }
-    Cand cd;
+    if (npart && !(nloc && nloc <= 4)) {
+        const Edge ep = A.edges[pid];
+        cd.s0 = make_double2(ep.ylo, ep.yhi);
+    }
     cd.poly = D.poly[i];
     cd.meta = S | last | ((nloc & 0x7fffu) << 2) | ((npart & 0x7fffu) << 17);
     cd.eoff = (uint32_t)eoff;
@@ -918,7 +937,7 @@ __device__ void claimant_walk(const RowArgs &A, const RowData &D, const RowShare
         if (!EMIT) { atomicAdd(&L.sa[cix(col)], 1); return; }
         uint32_t last;
         const uint64_t slot = rec_slot(L, col, rec_base_r, last);
-        Cand cd;
+        Cand cd{};
         cd.poly = D.poly[i];
         cd.meta = CAND_S | last;
         cd.eoff = 0;
@@ -1329,7 +1348,7 @@ __device__ void process_row(const RowArgs &A, const RowData &D, const RowShared 
                 if ((w & BFLAG) && (w & ~BFLAG)) {
                     uint32_t last;
                     const uint64_t slot = rec_slot(L, c, rec_base_r, last);
-                    Cand cd;
+                    Cand cd{};
                     cd.poly = (w & ~BFLAG) - 1u;
                     cd.meta = CAND_S | last;
                     cd.eoff = 0;

@@ -305,11 +305,12 @@ class SpadeExecutor:
 
     def estimate(self, req: Request) -> int:
         """Device bytes a request holds while in flight (upper estimate):
-        canvas words, coarse level and boundary index (about three words per
-        pixel), edges and their row entries, outputs."""
+        canvas words and coarse level (about three words per pixel), edges,
+        their row entries and the boundary index sized from them (64-byte
+        records), outputs."""
         V = n_vertices(req.polys)
         px = min(max(self.ppv * V, 64 * 64), 4096 * 4096)
-        b = 12 * px + 160 * V + (1 << 20)
+        b = 12 * px + 1024 * V + (1 << 20)
         if req.kind == "select":
             if V:
                 vx, vy = np.asarray(req.polys["vx"]), np.asarray(req.polys["vy"])
