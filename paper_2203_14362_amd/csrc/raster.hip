@@ -975,32 +975,6 @@ __device__ __forceinline__ void for_each_run(const RowData &D, Fn fn)
     }
 }
 
-// Block-wide in-place inclusive scan of a[0..n) under an associative,
-// commutative operator.
-template <typename Op>
-__device__ void block_plain_scan(uint32_t *a, int n, uint32_t *wtot, Op op)
-{
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int per = (n + ROW_THREADS - 1) / ROW_THREADS;
-    const int b = min(n, tid * per), e = min(n, b + per);
-    uint32_t acc = 0;
-    for (int q = b; q < e; ++q) { acc = op(acc, a[q]); a[q] = acc; }
-    uint32_t inc = acc;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        uint32_t t = __shfl_up(inc, d, 64);
-        if (lane >= d) inc = op(inc, t);
-    }
-    if (lane == 63) wtot[wv] = inc;
-    __syncthreads();
-    uint32_t pre = 0;
-    for (int q = 0; q < wv; ++q) pre = op(pre, wtot[q]);
-    uint32_t prev = __shfl_up(inc, 1, 64);
-    if (lane > 0) pre = op(pre, prev);
-    for (int q = b; q < e; ++q) a[q] = op(pre, a[q]);
-    __syncthreads();
-}
-
 // The five inclusive scans of phase 2 in one pass: footprint counts (sum),
 // claim counts (sum) and claimant xor over the row's columns, the per-entry
 // partial/spanning prefix (pre_op) and the interval lengths (sum).  Each
