@@ -85,12 +85,17 @@ __global__ __launch_bounds__(CNT_THREADS) void k_count(CanvasView cv, int64_t n,
         __builtin_amdgcn_wave_barrier();
         if (lane < qn) {
             const double x = qx[lane], y = qy[lane];
+            // a pixel's records two at a time (most pixels have two; the
+            // slot after the last record exists and is never used)
             uint32_t rec = qr[lane];
             while (true) {
-                const Cand cd = cv.cands[rec];
-                if (cand_inside(cv, cd, x, y)) add(cd.poly);
-                if (cd.meta & CAND_LAST) break;
-                ++rec;
+                const Cand c0 = cv.cands[rec];
+                const Cand c1 = cv.cands[rec + 1];
+                if (cand_inside(cv, c0, x, y)) add(c0.poly);
+                if (c0.meta & CAND_LAST) break;
+                if (cand_inside(cv, c1, x, y)) add(c1.poly);
+                if (c1.meta & CAND_LAST) break;
+                rec += 2;
             }
         }
         __builtin_amdgcn_wave_barrier();

@@ -1901,7 +1901,7 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
     if (!any) {
         SPADE_HIP(ctx, hipMemsetAsync(cv->cells.p, 0, sizeof(uint32_t) * (size_t)cells_tot, st));
         SPADE_HIP(ctx, hipMemsetAsync(cv->coarse.p, 0, sizeof(uint16_t) * ((size_t)coarse_tot + 2), st));
-        if (ensure(ctx, cv->cands, sizeof(Cand)) || ensure(ctx, cv->ledges, sizeof(Edge)) ||
+        if (ensure(ctx, cv->cands, 2 * sizeof(Cand)) || ensure(ctx, cv->ledges, sizeof(Edge)) ||
             ensure(ctx, cv->pspan, sizeof(double2)))
             return SPADE_E_NOMEM;
         cv->n_boundary = cv->n_cands = cv->n_elist = 0;
@@ -2162,7 +2162,9 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
             ensure(ctx, cv->ledges, sizeof(Edge) * (size_t)(2 * T + 1024)) ||
             ensure(ctx, cv->pspan, sizeof(double2) * (size_t)(T + 16)))
             return SPADE_E_NOMEM;
-        ra.cap_rec = std::min<uint64_t>(cv->cands.cap / sizeof(Cand), (uint64_t)BFLAG - 1) / NSHARD;
+        // the slot after the last record stays unused: the count probe reads
+        // a pixel's records two at a time
+        ra.cap_rec = std::min<uint64_t>(cv->cands.cap / sizeof(Cand) - 1, (uint64_t)BFLAG - 1) / NSHARD;
         ra.cap_loc = std::min<uint64_t>(cv->ledges.cap / sizeof(Edge), 0xffffffffULL) / NSHARD;
         ra.cap_part = std::min<uint64_t>(cv->pspan.cap / sizeof(double2), 0xffffffffULL) / NSHARD;
         ra.cands = (Cand *)cv->cands.p;
@@ -2234,7 +2236,7 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
         if (nrec >= (uint64_t)BFLAG) return set_error(ctx, SPADE_E_UNSUPPORTED, "boundary index exceeds 2^31 records; lower the canvas resolution");
         if (nloc >= 0xffffffffULL || npart >= 0xffffffffULL)
             return set_error(ctx, SPADE_E_UNSUPPORTED, "boundary edge lists exceed 2^32 entries");
-        if (ensure(ctx, cv->cands, sizeof(Cand) * (size_t)std::max<uint64_t>(nrec, 1)) ||
+        if (ensure(ctx, cv->cands, sizeof(Cand) * (size_t)(nrec + 1)) ||
             ensure(ctx, cv->ledges, sizeof(Edge) * (size_t)std::max<uint64_t>(nloc, 1)) ||
             ensure(ctx, cv->pspan, sizeof(double2) * (size_t)std::max<uint64_t>(npart, 1)))
             return SPADE_E_NOMEM;
