@@ -153,6 +153,7 @@ void spade_ctx_destroy(spade_ctx *ctx)
     if (ctx->fork) (void)hipEventDestroy(ctx->fork);
     if (ctx->join) (void)hipEventDestroy(ctx->join);
     if (ctx->join2) (void)hipEventDestroy(ctx->join2);
+    if (ctx->evinfo) (void)hipEventDestroy(ctx->evinfo);
     if (ctx->side) (void)hipStreamDestroy(ctx->side);
     if (ctx->side2) (void)hipStreamDestroy(ctx->side2);
     if (ctx->capture) (void)hipStreamDestroy(ctx->capture);

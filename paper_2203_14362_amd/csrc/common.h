@@ -145,6 +145,7 @@ struct spade_ctx {
     hipStream_t side = nullptr;             // internal streams for overlapped launches
     hipStream_t side2 = nullptr;
     hipEvent_t fork = nullptr, join = nullptr, join2 = nullptr;
+    hipEvent_t evinfo = nullptr;            // a build's row totals reached the host
     hipStream_t capture = nullptr;          // internal stream graphs are captured on
     bool graphs = true;                     // replay repeated canvas builds from graphs
     int64_t graph_captures = 0, graph_replays = 0;

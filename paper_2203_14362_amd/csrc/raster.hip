@@ -526,8 +526,12 @@ __global__ __launch_bounds__(256) void k_entries_rows(int64_t V, const Edge *edg
                                                       const int32_t *erow0, const uint64_t *nrows,
                                                       const CanvasDesc *cds, int nc, int ebits,
                                                       int ckshift, uint32_t *cursor, int rstride,
-                                                      uint64_t *ukey, uint32_t *uc, uint8_t *uf)
+                                                      uint64_t *ukey, uint32_t *uc, uint8_t *uf,
+                                                      const unsigned long long *tinfo, uint64_t tcap)
 {
+    // launched before the host has read the entry total: buffers hold tcap
+    // entries, and a larger total leaves everything to a later launch
+    if (tinfo && tinfo[0] > tcap) return;
     __shared__ uint32_t hist[ROW_WIN];
     __shared__ int s_lo, s_hi;
     const int lane = threadIdx.x & 63;
@@ -1972,9 +1976,8 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
     SPADE_HIP(ctx, hipGetLastError());
     uint64_t *hT = (uint64_t *)ensure_pinned(ctx, 64);
     SPADE_HIP(ctx, hipMemcpyAsync(hT, rinfo, 4 * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
-    SPADE_HIP(ctx, hipStreamSynchronize(st));
-    const uint64_t T = hT[0], maxrow = hT[1], nlistB = hT[2], nlistC = hT[3];
-    if (T >= 0x7fffffffULL) return set_error(ctx, SPADE_E_UNSUPPORTED, "too many (edge,row) entries; lower the canvas height");
+    if (!ctx->evinfo) SPADE_HIP(ctx, hipEventCreateWithFlags(&ctx->evinfo, hipEventDisableTiming));
+    SPADE_HIP(ctx, hipEventRecord(ctx->evinfo, st));
 
     const int cbits = std::max(1, bits_for((uint64_t)W - 1));
     int64_t maxM = 1;
@@ -1982,6 +1985,24 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
     const int pbits = std::max(1, bits_for((uint64_t)(maxM - 1)));
     const int rbits = std::max(1, bits_for((uint64_t)H - 1));
     const int ebits = std::max(1, bits_for((uint64_t)V - 1));
+    DevBuf &dk = ctx->scratch[S_KEYS], &dk2 = ctx->scratch[S_KEYS2];
+    DevBuf &dv = ctx->scratch[S_VALS], &dv2 = ctx->scratch[S_VALS2];
+    DevBuf &dc = ctx->scratch[S_ENTC], &df = ctx->scratch[S_ENTF];
+    // While the host waits for the totals, the entries go into the buffers
+    // of earlier builds when the total fits them (the kernel checks); the
+    // room is counted so that no buffer below grows under it.
+    const uint64_t tcap = std::min(std::min(dk.cap / 8, dc.cap / 20), df.cap >= 16 ? (df.cap - 16) / 2 : 0);
+    const bool spec = tcap > 0 && pbits + cbits + ebits <= 63;
+    if (spec) {
+        hipLaunchKernelGGL(k_entries_rows, dim3(grid_for(4 * V)), dim3(256), 0, st, V, (const Edge *)cv->edges.p,
+                           epoly, erow0, nrows, d_cds, nc, ebits, cbits + ebits, cursor, rstride,
+                           (uint64_t *)dk.p, (uint32_t *)dc.p, (uint8_t *)df.p,
+                           (const unsigned long long *)rinfo, tcap);
+        SPADE_HIP(ctx, hipGetLastError());
+    }
+    SPADE_HIP(ctx, hipEventSynchronize(ctx->evinfo));
+    const uint64_t T = hT[0], maxrow = hT[1], nlistB = hT[2], nlistC = hT[3];
+    if (T >= 0x7fffffffULL) return set_error(ctx, SPADE_E_UNSUPPORTED, "too many (edge,row) entries; lower the canvas height");
     // Entries go straight into row buckets and each row is sorted in LDS by
     // (polygon, first column, edge); rows longer than the LDS sort, or keys
     // wider than 63 bits (the top bit stays clear so that real keys sort
@@ -1994,9 +2015,8 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
 
     if (!bucketed && cbits + pbits + rbits > 64) return set_error(ctx, SPADE_E_UNSUPPORTED, "sort key exceeds 64 bits");
 
-    DevBuf &dk = ctx->scratch[S_KEYS], &dk2 = ctx->scratch[S_KEYS2];
-    DevBuf &dv = ctx->scratch[S_VALS], &dv2 = ctx->scratch[S_VALS2];
-    DevBuf &dc = ctx->scratch[S_ENTC], &df = ctx->scratch[S_ENTF];
+    // the speculative entries stand when the rows are sorted per row
+    const bool entries_done = spec && bucketed && T <= tcap;
     const size_t Ts = (size_t)std::max<uint64_t>(T, 1);
     // dc: ent_c[T] | sorted c[T] | perm[T] | perm2[T] | sorted poly[T]; df: ent_f[T] | sorted f[T]
     if (ensure(ctx, dk, 8 * Ts) || ensure(ctx, dv2, 4 * Ts) || ensure(ctx, dc, 20 * Ts) ||
@@ -2025,10 +2045,13 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
     auto enqueue_entries = [&]() -> hipError_t {
         hipError_t e;
         if (bucketed) {
-            hipLaunchKernelGGL(k_entries_rows, dim3(grid_for(4 * V)), dim3(256), 0, qs, V, (const Edge *)cv->edges.p,
-                               epoly, erow0, nrows, d_cds, nc, ebits, cbits + ebits, cursor, rstride,
-                               (uint64_t *)dk.p, ent_c, ent_f);
-            if ((e = hipGetLastError()) != hipSuccess) return e;
+            if (!entries_done) {
+                hipLaunchKernelGGL(k_entries_rows, dim3(grid_for(4 * V)), dim3(256), 0, qs, V,
+                                   (const Edge *)cv->edges.p, epoly, erow0, nrows, d_cds, nc, ebits, cbits + ebits,
+                                   cursor, rstride, (uint64_t *)dk.p, ent_c, ent_f,
+                                   (const unsigned long long *)nullptr, (uint64_t)0);
+                if ((e = hipGetLastError()) != hipSuccess) return e;
+            }
             const int64_t sort_items = H + (int64_t)nlistB + (int64_t)nlistC;
             hipLaunchKernelGGL(k_rowsort, dim3((unsigned)std::min<int64_t>(sort_items, 65535)), dim3(SORT_THREADS), sort_lds,
                                qs, H, (const uint32_t *)row_off, (const uint64_t *)dk.p, (const uint32_t *)ent_c,
@@ -2184,7 +2207,7 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
         auto putp = [&](const void *p) { key.push_back((uint64_t)(uintptr_t)p); };
         put(T); put((uint64_t)V); put((uint64_t)H); put((uint64_t)W); put((uint64_t)nc); put((uint64_t)coarse_tot);
         put((uint64_t)cbits); put((uint64_t)pbits); put((uint64_t)kbits); put(tbytes); put(tscan);
-        put(bucketed ? 1 : 0); put((uint64_t)ebits); put(sort_lds); put(nlistB); put(nlistC);
+        put(bucketed ? 1 : 0); put(entries_done ? 1 : 0); put((uint64_t)ebits); put(sort_lds); put(nlistB); put(nlistC);
         put((uint64_t)capB); put((uint64_t)rstride);
         put((uint64_t)ra.cap); put((uint64_t)cap_big); put(rlds); put(rlds_big);
         put(ra.cap_rec); put(ra.cap_loc); put(ra.cap_part);
