@@ -139,6 +139,7 @@ class DevicePolys:
         self.vy = _dev_f64(polys["vy"], device)
         # bounding box of host vertex arrays (the library checks it on the
         # device); device arrays are left to the library
+        self._cs = None
         self.bbox = None
         hx, hy = polys["vx"], polys["vy"]
         if not isinstance(hx, torch.Tensor) and not isinstance(hy, torch.Tensor):
@@ -147,14 +148,25 @@ class DevicePolys:
             if hx.size and hx.size == hy.size and np.all(np.isfinite(hx)) and np.all(np.isfinite(hy)):
                 self.bbox = np.array([hx.min(), hx.max(), hy.min(), hy.max()], dtype=np.float64)
 
+    @property
+    def bbox(self):
+        return self._bbox
+
+    @bbox.setter
+    def bbox(self, b):
+        self._bbox = None if b is None else np.ascontiguousarray(b, dtype=np.float64)
+        self._cs = None
+
     def cstruct(self):
-        return _Polys(self.n_polys, self.n_rings,
-                      0 if self.poly_ring_off is None else self.poly_ring_off.data_ptr(),
-                      self.ring_vtx_off.data_ptr() if self.ring_vtx_off.numel() else 0,
-                      self.vx.data_ptr() if self.vx.numel() else 0,
-                      self.vy.data_ptr() if self.vy.numel() else 0,
-                      int(self.vx.numel()),
-                      None if self.bbox is None else self.bbox.ctypes.data)
+        if self._cs is None:
+            self._cs = _Polys(self.n_polys, self.n_rings,
+                              0 if self.poly_ring_off is None else self.poly_ring_off.data_ptr(),
+                              self.ring_vtx_off.data_ptr() if self.ring_vtx_off.numel() else 0,
+                              self.vx.data_ptr() if self.vx.numel() else 0,
+                              self.vy.data_ptr() if self.vy.numel() else 0,
+                              int(self.vx.numel()),
+                              None if self._bbox is None else self._bbox.ctypes.data)
+        return self._cs
 
 
 def _compact(buf, m):
