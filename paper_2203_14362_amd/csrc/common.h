@@ -29,10 +29,11 @@ constexpr uint32_t BFLAG = 0x80000000u;
 // where local edges touch the (margin-dilated) pixel, partial-right edges lie
 // entirely to its right but end inside the pixel row, and S is the parity of
 // the edges entirely to the right that span the whole row.  Local edges are
-// stored with their coordinates (contiguous from eoff); partial-right edges
-// only need their y-range (contiguous from poff).  The first of each is
-// repeated inside the record, so that a record of one local edge and at
-// most one partial-right range is a single 64-byte read.
+// stored with their coordinates: the first inside the record, the others
+// contiguous from eoff; partial-right edges only need their y-range
+// (contiguous from poff, the first repeated inside the record).  A record of
+// one local edge and at most one partial-right range is a single 64-byte
+// read.
 struct Edge {
     double xlo, ylo, xhi, yhi;
 };
@@ -40,9 +41,9 @@ struct Cand {
     uint32_t poly;
     uint32_t meta;   // bit 0: S, bit 1: last record of the pixel,
                      // bits 2..16: n_local, bits 17..31: n_partial
-    uint32_t eoff;   // first local edge in the local-edge array
+    uint32_t eoff;   // second local edge in the local-edge array
     uint32_t poff;   // first partial-right y-range in the span array
-    Edge e0;         // local edge eoff (when n_local > 0)
+    Edge e0;         // the first local edge (when n_local > 0)
     double2 s0;      // partial-right range poff (when n_partial > 0)
 };
 static_assert(sizeof(Cand) == 64, "a candidate record is one 64-byte read");

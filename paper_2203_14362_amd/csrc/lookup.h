@@ -89,9 +89,9 @@ __device__ __forceinline__ bool cand_inside(const CanvasView &cv, const Cand &cd
     const uint32_t npart = cd.meta >> 17;
     if (nloc > 0) in ^= crosses(cd.e0.xlo, cd.e0.ylo, cd.e0.xhi, cd.e0.yhi, x, y);
     if (npart > 0) in ^= straddles(cd.s0.x, cd.s0.y, y);
-    const Edge *le = cv.ledges + cd.eoff;
+    const Edge *le = cv.ledges + cd.eoff;   // local edges after the first
     for (uint32_t t = 1; t < nloc; ++t) {
-        const Edge e = le[t];
+        const Edge e = le[t - 1];
         in ^= crosses(e.xlo, e.ylo, e.xhi, e.yhi, x, y);
     }
     const double2 *ps = cv.pspan + cd.poff;

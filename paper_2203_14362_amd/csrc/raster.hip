@@ -877,7 +877,7 @@ __device__ __forceinline__ void column_record(const RowArgs &A, const RowData &D
     if (nloc > 0x7fffu || npart > 0x7fffu) atomicOr(A.errflags, 16u);
     if (!EMIT) {
         atomicAdd(&L.sa[cix(col)], 1);
-        nloc_tot += nloc;
+        nloc_tot += nloc ? nloc - 1 : 0;   // the first local edge lives in the record
         return;
     }
     uint32_t last;
@@ -893,7 +893,9 @@ __device__ __forceinline__ void column_record(const RowArgs &A, const RowData &D
         pid = D.edge[q];
     }
     if (nloc) {
-        eoff = loc_base_r + atomicAdd(L.locfill, nloc);
+        // the first local edge goes into the record, the others to the
+        // local-edge array from eoff
+        if (nloc > 1) eoff = loc_base_r + atomicAdd(L.locfill, nloc - 1);
         if (nloc <= 4) {
             // up to four edges: all loads in flight before the stores (a
             // pixel's local edges are tested in any order)
@@ -902,19 +904,20 @@ __device__ __forceinline__ void column_record(const RowArgs &A, const RowData &D
             const Edge e2 = A.edges[nloc > 2 ? id2 : id0];
             const Edge e3 = A.edges[nloc > 3 ? id3 : id0];
             const Edge ep = A.edges[pid];
-            A.ledges[eoff] = e0;
-            if (nloc > 1) A.ledges[eoff + 1] = e1;
-            if (nloc > 2) A.ledges[eoff + 2] = e2;
-            if (nloc > 3) A.ledges[eoff + 3] = e3;
+            if (nloc > 1) A.ledges[eoff] = e1;
+            if (nloc > 2) A.ledges[eoff + 1] = e2;
+            if (nloc > 3) A.ledges[eoff + 2] = e3;
             cd.e0 = e0;
             if (npart) cd.s0 = make_double2(ep.ylo, ep.yhi);
         } else {
             uint64_t o = eoff;
+            bool first = true;
             for (int q = sp - 1; q >= i && (int)(D.pm[q] >> 16) > col; --q)
                 if ((int)(D.c[q] >> 16) >= col && !(D.f[q] & F_HORIZ)) {
                     const Edge e = A.edges[D.edge[q]];
-                    if (o == eoff) cd.e0 = e;
-                    A.ledges[o++] = e;
+                    if (first) cd.e0 = e;
+                    else A.ledges[o++] = e;
+                    first = false;
                 }
         }
     }
