@@ -212,6 +212,7 @@ __device__ __forceinline__ CanvasView set_view(const CanvasDesc &d, const uint32
     v.X0 = d.X0; v.Y0 = d.Y0; v.sx = d.sx; v.sy = d.sy;
     v.bx0 = d.bx0; v.by0 = d.by0; v.bx1 = d.bx1; v.by1 = d.by1;
     v.W = d.W; v.H = d.H; v.Wt = d.Wt; v.Wc = d.Wc; v.Hc = d.Hc; v.blog = d.blog;
+    v.cbyte = d.cbyte;
     v.M = d.M;
     v.cells = cells + d.cell_off;
     v.coarse = coarse + d.coarse_off;

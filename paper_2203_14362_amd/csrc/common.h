@@ -63,6 +63,13 @@ constexpr uint32_t CAND_LAST = 2u;
 // non-zero non-boundary words, or words above 0xffff, are COARSE_FULL.
 constexpr uint16_t COARSE_MIXED = 0x8000u;
 constexpr uint16_t COARSE_FULL = 0xffffu;
+// A single canvas of at most COARSE_BYTE_MAXM polygons stores its coarse
+// words as bytes, half the LDS for the same block size: label + 1 below
+// COARSE_BYTE_MIXED, then the two flags.  A uniform block of a larger label
+// is stored as mixed (its records say so pixel by pixel).
+constexpr uint32_t COARSE_BYTE_MIXED = 254u;
+constexpr uint32_t COARSE_BYTE_FULL = 255u;
+constexpr int64_t COARSE_BYTE_MAXM = 512;
 
 // Bytes of the compact records of one mixed block of 2^blog pixels a side.
 __host__ __device__ inline uint32_t desc_bytes(int blog) { return (1u << (2 * blog)) / 2u; }
@@ -77,7 +84,7 @@ struct CanvasDesc {
     double bx0, by0, bx1, by1;    // half-open bounding box of the canvas's polygons
     int32_t W, H, Wt, Wc, Hc, blog;
     int32_t empty;                // no polygon area: every point is outside
-    int32_t pad;
+    int32_t cbyte;                // coarse words are bytes (see COARSE_BYTE_*)
     int64_t poly_base, M;
     int64_t row_base;             // first global row of the set
     int64_t cell_off;             // first canvas word (tile-major, 16 x 16 tiles)
@@ -92,6 +99,7 @@ struct CanvasView {
     int32_t W, H;
     int32_t Wt;                   // 16 x 16 pixel tiles per canvas row
     int32_t Wc, Hc, blog;         // coarse grid: one word per 2^blog x 2^blog pixels
+    int32_t cbyte;                // coarse words are bytes (see COARSE_BYTE_*)
     int64_t M;                    // number of polygons
     const uint32_t *cells;        // canvas words, tile-major (16 x 16 tiles)
     const uint16_t *coarse;       // Wc * Hc coarse words, row-major

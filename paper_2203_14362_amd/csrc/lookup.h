@@ -38,12 +38,19 @@ __device__ __forceinline__ Look look_coarse(const CanvasView &cv, const uint16_t
     const double v = __dmul_rn(__dsub_rn(y, cv.Y0), cv.sy);
     const int c = min((int)u, cv.W - 1);
     const int r = min((int)v, cv.H - 1);
-    const uint16_t cw = coarse[(r >> cv.blog) * cv.Wc + (c >> cv.blog)];
+    const int ci = (r >> cv.blog) * cv.Wc + (c >> cv.blog);
+    uint32_t cw;
+    if (cv.cbyte) {
+        const uint32_t b = ((const uint8_t *)coarse)[ci];
+        cw = b < COARSE_BYTE_MIXED ? b : (b == COARSE_BYTE_MIXED ? COARSE_MIXED : COARSE_FULL);
+    } else {
+        cw = coarse[ci];
+    }
     if (!(cw & COARSE_MIXED)) { L.word = cw; return L; }
     L.fidx = (uint32_t)tile_index(cv.Wt, c, r);
     if (cw == COARSE_FULL) { L.kind = 2; return L; }
     L.kind = 1;
-    L.m = (uint32_t)((r >> cv.blog) * cv.Wc + (c >> cv.blog));
+    L.m = (uint32_t)ci;
     const int B = 1 << cv.blog;
     L.pix = (uint32_t)(((r & (B - 1)) << cv.blog) | (c & (B - 1)));
     return L;
@@ -102,15 +109,15 @@ __device__ __forceinline__ bool cand_inside(const CanvasView &cv, const Cand &cd
     return in;
 }
 
-// Cooperative copy of the coarse canvas into LDS.
+// Cooperative copy of the coarse canvas into LDS (whole 32-bit words; the
+// device array is padded to them).
 __device__ __forceinline__ void load_coarse(const CanvasView &cv, uint16_t *dst, int nthreads)
 {
     const int n = cv.Wc * cv.Hc;
-    const int n2 = n >> 1;
-    const uint32_t *src2 = (const uint32_t *)cv.coarse;
-    uint32_t *dst2 = (uint32_t *)dst;
-    for (int i = threadIdx.x; i < n2; i += nthreads) dst2[i] = src2[i];
-    if ((n & 1) && threadIdx.x == 0) dst[n - 1] = cv.coarse[n - 1];
+    const int nw = cv.cbyte ? (n + 3) >> 2 : (n + 1) >> 1;
+    const uint32_t *src = (const uint32_t *)cv.coarse;
+    uint32_t *d = (uint32_t *)dst;
+    for (int i = threadIdx.x; i < nw; i += nthreads) d[i] = src[i];
 }
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63; }

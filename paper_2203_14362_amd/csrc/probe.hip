@@ -60,7 +60,7 @@ __global__ __launch_bounds__(CNT_THREADS) void k_count(CanvasView cv, int64_t n,
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ bool s_last;
     const int M = (int)cv.M;
-    const size_t coarse_bytes = ((size_t)cv.Wc * cv.Hc * 2 + 15) & ~(size_t)15;
+    const size_t coarse_bytes = ((size_t)cv.Wc * cv.Hc * (cv.cbyte ? 1 : 2) + 15) & ~(size_t)15;
     uint16_t *coarse = (uint16_t *)smem;
     uint32_t *hist = (uint32_t *)(smem + coarse_bytes);
     const size_t hist_bytes = LDSHIST ? (((size_t)M * 4 + 15) & ~(size_t)15) : 0;
@@ -214,7 +214,7 @@ static int count_acc(spade_ctx *ctx, int64_t M, unsigned long long **acc, unsign
 
 static size_t coarse_bytes_of(const CanvasView &v)
 {
-    return ((size_t)v.Wc * v.Hc * 2 + 15) & ~(size_t)15;
+    return ((size_t)v.Wc * v.Hc * (v.cbyte ? 1 : 2) + 15) & ~(size_t)15;
 }
 
 int probe_count(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts, uint64_t *out_counts)
@@ -233,7 +233,10 @@ int probe_count(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts,
     if (lds + LDS_RESERVE > LDS_TOTAL) return set_error(ctx, SPADE_E_HIP, "internal: probe LDS budget exceeded");
     const int per_cu = std::max<int>(1, (int)(LDS_TOTAL / (lds + LDS_RESERVE)));
     const int64_t need = std::max<int64_t>(1, (pts->n + CNT_THREADS * CNT_UNROLL - 1) / (CNT_THREADS * CNT_UNROLL));
-    const int grid = (int)std::min<int64_t>(need, (int64_t)cus * std::min(per_cu, 2));
+    // one workgroup per CU: a second one slows the stream down (measured),
+    // so spare LDS goes to a finer coarse level instead
+    (void)per_cu;
+    const int grid = (int)std::min<int64_t>(need, (int64_t)cus);
     if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[2], st));
     if (ldshist) {
         SPADE_HIP(ctx, hipFuncSetAttribute((const void *)k_count<true>,

@@ -1474,8 +1474,18 @@ __global__ __launch_bounds__(256) void k_compact(const CanvasDesc *cds, int nc, 
         uint16_t *coarse = coarse_all + cd.coarse_off;
         const int B = 1 << blog, P = B * B, J = P / 64, G = P / 32;
         const int64_t cell = gcell - cd.coarse_off;
+        // the block's coarse word: a uniform word (< COARSE_MIXED), COARSE_MIXED
+        // or COARSE_FULL; a byte-sized canvas stores a word it cannot hold as FULL
+        auto put = [&](uint32_t v) {
+            if (lane != 0) return;
+            if (cd.cbyte)
+                ((uint8_t *)coarse)[cell] = (uint8_t)(v == COARSE_MIXED ? COARSE_BYTE_MIXED
+                                                      : (v == COARSE_FULL || v >= COARSE_BYTE_MIXED) ? COARSE_BYTE_FULL : v);
+            else
+                coarse[cell] = (uint16_t)v;
+        };
         if (cd.empty) {
-            if (lane == 0) coarse[cell] = 0;
+            put(0u);
             continue;
         }
         const int cy = (int)(cell / Wc), cx = (int)(cell % Wc);
@@ -1492,8 +1502,8 @@ __global__ __launch_bounds__(256) void k_compact(const CanvasDesc *cds, int nc, 
             const uint32_t w = pix_word(lane + 64 * j, v);
             same &= !v || w == first;
         }
-        if (__all(same) && !(first & BFLAG) && first < COARSE_MIXED) {
-            if (lane == 0) coarse[cell] = (uint16_t)first;
+        if (__all(same) && !(first & BFLAG) && first < (cd.cbyte ? COARSE_BYTE_MIXED : COARSE_MIXED)) {
+            put(first);
             continue;
         }
         // palette: up to two distinct non-zero non-boundary words <= 0xffff
@@ -1519,10 +1529,10 @@ __global__ __launch_bounds__(256) void k_compact(const CanvasDesc *cds, int nc, 
             pal[npal++] = v;
         }
         if (full) {
-            if (lane == 0) coarse[cell] = COARSE_FULL;
+            put(COARSE_FULL);
             continue;
         }
-        if (lane == 0) coarse[cell] = COARSE_MIXED;
+        put(COARSE_MIXED);
         uint4 *rec = desc_all + cd.desc_off + (size_t)cell * G;
         const uint32_t palw = pal[0] | (pal[1] << 16);
         for (int j = 0; j < J; ++j) {
@@ -1623,6 +1633,7 @@ CanvasView view_of(const spade_canvas *cv, int q)
     v.X0 = d.X0; v.Y0 = d.Y0; v.sx = d.sx; v.sy = d.sy;
     v.bx0 = d.bx0; v.by0 = d.by0; v.bx1 = d.bx1; v.by1 = d.by1;
     v.W = d.W; v.H = d.H; v.Wt = d.Wt; v.Wc = d.Wc; v.Hc = d.Hc; v.blog = d.blog;
+    v.cbyte = d.cbyte;
     v.M = d.M;
     v.cells = (const uint32_t *)cv->cells.p + d.cell_off;
     v.coarse = (const uint16_t *)cv->coarse.p + d.coarse_off;
@@ -1874,12 +1885,15 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
         }
         d.Wt = (W + 15) / 16;
         const int Ht = (H + 15) / 16;
-        // coarse grid: blocks of 2^blog pixels, as fine as the probe's LDS allows
+        // coarse grid: blocks of 2^blog pixels, as fine as the probe's LDS
+        // allows; a single canvas of few polygons has byte-sized words
+        d.cbyte = (nc == 1 && d.M <= COARSE_BYTE_MAXM) ? 1 : 0;
+        const size_t cw_bytes = d.cbyte ? 1 : 2;
         int blog = 3;
         const size_t cbudget = coarse_lds_budget(d.M);
-        while (blog < 6 && (size_t)((W + (1 << blog) - 1) >> blog) * ((H + (1 << blog) - 1) >> blog) * 2 > cbudget)
+        while (blog < 6 && (size_t)((W + (1 << blog) - 1) >> blog) * ((H + (1 << blog) - 1) >> blog) * cw_bytes > cbudget)
             ++blog;
-        if ((size_t)((W + (1 << blog) - 1) >> blog) * ((H + (1 << blog) - 1) >> blog) * 2 > cbudget)
+        if ((size_t)((W + (1 << blog) - 1) >> blog) * ((H + (1 << blog) - 1) >> blog) * cw_bytes > cbudget)
             return set_error(ctx, SPADE_E_UNSUPPORTED, "coarse canvas exceeds the probe's LDS; lower the canvas resolution");
         d.blog = blog;
         d.Wc = (W + (1 << blog) - 1) >> blog;

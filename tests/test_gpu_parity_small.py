@@ -201,3 +201,21 @@ def test_invalid_polygon_sets(ctx):
     polys = gen.voronoi_jitter(8, 5, 12, seed=3, L=1.0)
     assert np.array_equal(ctx.join_count(_dev(x), _dev(y), polys).cpu().numpy().astype(np.uint64),
                           oracle.join_count(x, y, polys))
+
+
+@pytest.mark.parametrize("wh", [(0, 0), (700, 700), (2048, 2048)])
+def test_byte_coarse_large_labels(ctx, wh):
+    """More than 253 polygons in one canvas: byte-sized coarse words cannot
+    hold the larger labels, whose uniform blocks then go through the
+    mixed-block records."""
+    x, y = gen.uniform_points(200_000, seed=61)
+    polys = gen.voronoi_jitter(400, 5, 20, seed=61, L=1.0)
+    ctx.set_canvas_size(*wh)
+    try:
+        got = ctx.join_count(_dev(x), _dev(y), polys).cpu().numpy().astype(np.uint64)
+        pt, pg = ctx.join_pairs(_dev(x), _dev(y), polys)
+    finally:
+        ctx.set_canvas_size(0, 0)
+    assert np.array_equal(got, oracle.join_count(x, y, polys))
+    opt, opg = oracle.join_pairs(x, y, polys)
+    assert np.array_equal(_u32(pt), opt) and np.array_equal(_u32(pg), opg)
