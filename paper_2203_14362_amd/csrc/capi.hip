@@ -355,6 +355,7 @@ static int plain_query(spade_ctx *ctx, const spade_polys *polys, F &&probe)
     int rc = plain_build(ctx, polys, &cv, true);
     if (rc) return rc;
     const int rp = probe(cv);
+    if ((rc = build_flush(ctx, cv))) return rc;
     SPADE_HIP(ctx, hipStreamSynchronize(ctx->stream));
     const int rf = build_finish(ctx, cv);
     if (rf == BUILD_AGAIN) {

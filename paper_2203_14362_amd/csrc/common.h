@@ -131,6 +131,7 @@ struct spade_canvas {
     std::vector<uint64_t> gkey;               // launch parameters of the last build
     hipGraphExec_t gexec = nullptr;           // its captured launches (second build on)
     bool pending = false;                     // built, counters and flags not yet read
+    const void *pend_src = nullptr;           // their device block, until build_flush copies it
     size_t bytes() const
     {
         return cells.cap + cands.cap + ledges.cap + pspan.cap + coarse.cap + desc.cap;
@@ -174,9 +175,12 @@ int ensure(spade_ctx *ctx, DevBuf &b, size_t bytes);
 void *ensure_pinned(spade_ctx *ctx, size_t bytes);
 void free_buf(DevBuf &b);
 
-// `defer`: leave the build's counters and flags in flight (read by
-// build_finish after the caller's next synchronisation) instead of waiting.
+// `defer`: leave the build's counters and flags on the device instead of
+// waiting for them; build_flush queues their copy to the host (after the
+// caller's own launches) and build_finish reads it after the caller's next
+// synchronisation.
 int build_canvas(spade_ctx *ctx, const spade_polys *polys, spade_canvas *cv, bool defer = false);
+int build_flush(spade_ctx *ctx, spade_canvas *cv);
 // Completes a deferred build; returns BUILD_AGAIN when the single row pass
 // ran out of capacity (grown by now: build again, non-deferred).
 constexpr int BUILD_AGAIN = 1;

@@ -231,11 +231,10 @@ int probe_count(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts,
     const bool ldshist = M <= HIST_MAX;
     const size_t lds = coarse_bytes_of(v) + (ldshist ? (((size_t)M * 4 + 15) & ~(size_t)15) : 0) + QUEUE_BYTES;
     if (lds + LDS_RESERVE > LDS_TOTAL) return set_error(ctx, SPADE_E_HIP, "internal: probe LDS budget exceeded");
-    const int per_cu = std::max<int>(1, (int)(LDS_TOTAL / (lds + LDS_RESERVE)));
     const int64_t need = std::max<int64_t>(1, (pts->n + CNT_THREADS * CNT_UNROLL - 1) / (CNT_THREADS * CNT_UNROLL));
-    // one workgroup per CU: a second one slows the stream down (measured),
-    // so spare LDS goes to a finer coarse level instead
-    (void)per_cu;
+    // one workgroup per CU even where the LDS would hold two: a second one
+    // slows the stream down (measured), so spare LDS goes to a finer coarse
+    // level instead
     const int grid = (int)std::min<int64_t>(need, (int64_t)cus);
     if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[2], st));
     if (ldshist) {

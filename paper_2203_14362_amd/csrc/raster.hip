@@ -1675,20 +1675,28 @@ static int flag_error(spade_ctx *ctx, unsigned ef)
     return SPADE_OK;
 }
 
-// Host copy of the row pass's counter block and flags: NGCTR words, then
-// the flags word.
-constexpr size_t COUNTER_COPY = sizeof(uint64_t) * NGCTR + 64;
+// The flags word and the row pass's counters sit in one device block (the
+// flags at its start, the NGCTR counter words from byte CTR_HEAD), copied
+// to the host in one piece.
+constexpr size_t CTR_HEAD = 128;
+constexpr size_t COUNTER_COPY = CTR_HEAD + sizeof(uint64_t) * NGCTR;
 
-static hipError_t copy_counters(uint64_t *hc, const unsigned long long *gctr, const unsigned *d_err, hipStream_t st)
+static hipError_t copy_counters(void *hc, const unsigned *d_ctr, hipStream_t st)
 {
-    hipError_t e = hipMemcpyAsync(hc, gctr, sizeof(uint64_t) * NGCTR, hipMemcpyDeviceToHost, st);
-    if (e != hipSuccess) return e;
-    return hipMemcpyAsync(hc + NGCTR, d_err, sizeof(unsigned), hipMemcpyDeviceToHost, st);
+    return hipMemcpyAsync(hc, d_ctr, COUNTER_COPY, hipMemcpyDeviceToHost, st);
+}
+
+static unsigned counter_flags(const void *hc)
+{
+    unsigned ef;
+    std::memcpy(&ef, hc, sizeof(unsigned));
+    return ef;
 }
 
 // Totals over the shards of counter c, and the largest shard's.
-static uint64_t counter_total(const uint64_t *hc, int c, uint64_t *largest = nullptr)
+static uint64_t counter_total(const void *hcb, int c, uint64_t *largest = nullptr)
 {
+    const uint64_t *hc = (const uint64_t *)((const char *)hcb + CTR_HEAD);
     uint64_t t = 0, m = 0;
     for (int k = 0; k < NSHARD; ++k) {
         t += hc[gctr_at(k, c)];
@@ -1698,17 +1706,28 @@ static uint64_t counter_total(const uint64_t *hc, int c, uint64_t *largest = nul
     return t;
 }
 
-// Leaves the build's counters and flags on their way to pinned memory;
-// build_finish reads them after the caller's next synchronisation.
-static int defer_counters(spade_ctx *ctx, spade_canvas *cv, const unsigned long long *gctr, const unsigned *d_err)
+// Leaves the build's counters and flags on the device; build_flush queues
+// their copy to pinned memory (after the caller's probe, so the copy does
+// not delay it) and build_finish reads them after the caller's next
+// synchronisation.
+static int defer_counters(spade_ctx *ctx, spade_canvas *cv, const unsigned *d_ctr)
 {
     if (!ctx->pend && hipHostMalloc(&ctx->pend, COUNTER_COPY, hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
         ctx->pend = nullptr;
         return set_error(ctx, SPADE_E_NOMEM, "pinned staging allocation failed");
     }
-    SPADE_HIP(ctx, copy_counters((uint64_t *)ctx->pend, gctr, d_err, ctx->stream));
+    cv->pend_src = d_ctr;
     cv->pending = true;
+    return SPADE_OK;
+}
+
+int build_flush(spade_ctx *ctx, spade_canvas *cv)
+{
+    if (!cv->pending || !cv->pend_src) return SPADE_OK;
+    const unsigned *src = (const unsigned *)cv->pend_src;
+    cv->pend_src = nullptr;
+    SPADE_HIP(ctx, copy_counters(ctx->pend, src, ctx->stream));
     return SPADE_OK;
 }
 
@@ -1716,9 +1735,9 @@ int build_finish(spade_ctx *ctx, spade_canvas *cv)
 {
     if (!cv->pending) return SPADE_OK;
     cv->pending = false;
-    const uint64_t *hc = (const uint64_t *)ctx->pend;
-    unsigned ef;
-    std::memcpy(&ef, hc + NGCTR, sizeof(unsigned));
+    if (cv->pend_src) return set_error(ctx, SPADE_E_HIP, "internal: deferred build counters never copied");
+    const void *hc = ctx->pend;
+    const unsigned ef = counter_flags(hc);
     if (ef & (1u | 2u | 4u | 64u | 128u)) return flag_error(ctx, ef);
     uint64_t mrec, mloc, mpart;
     const uint64_t nrec = counter_total(hc, 0, &mrec), nloc = counter_total(hc, 1, &mloc);
@@ -1744,6 +1763,7 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
 {
     hipStream_t st = ctx->stream;
     cv->pending = false;
+    cv->pend_src = nullptr;
     const int64_t M = polys->n_polys, R = polys->n_rings;
     if (nc < 1) return set_error(ctx, SPADE_E_INVALID, "a canvas set needs at least one canvas");
     cv->nc = nc;
@@ -1775,12 +1795,13 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
     DevBuf &br = ctx->scratch[S_BLOCKRED];
     const size_t bbbytes = sizeof(unsigned long long) * 4 * (size_t)nc;
     if (ensure(ctx, rp, sizeof(int32_t) * (size_t)std::max<int64_t>(R, 1)) ||
-        ensure(ctx, br, sizeof(double) * 4 * RED_BLOCKS + 64 + bbbytes + 128 + sizeof(uint64_t) * NGCTR))
+        ensure(ctx, br, sizeof(double) * 4 * RED_BLOCKS + bbbytes + 128 + COUNTER_COPY))
         return SPADE_E_NOMEM;
-    unsigned *d_err = (unsigned *)((char *)br.p + sizeof(double) * 4 * RED_BLOCKS);
-    unsigned long long *d_bb = (unsigned long long *)((char *)br.p + sizeof(double) * 4 * RED_BLOCKS + 64);
-    // allocation counters of the row pass (cache-line aligned)
-    unsigned long long *gctr = (unsigned long long *)(((uintptr_t)(d_bb + 4 * (size_t)nc) + 127) & ~(uintptr_t)127);
+    unsigned long long *d_bb = (unsigned long long *)((char *)br.p + sizeof(double) * 4 * RED_BLOCKS);
+    // the flags word, then the allocation counters of the row pass (one
+    // cache-line-aligned block)
+    unsigned *d_err = (unsigned *)(((uintptr_t)(d_bb + 4 * (size_t)nc) + 127) & ~(uintptr_t)127);
+    unsigned long long *gctr = (unsigned long long *)((char *)d_err + CTR_HEAD);
     hipLaunchKernelGGL(k_init, dim3((unsigned)std::min<int64_t>((4 * (int64_t)nc + 255) / 256 + 1, 1024)), dim3(256), 0,
                        st, d_err, d_bb, 4 * (int64_t)nc, gctr);
     SPADE_HIP(ctx, hipGetLastError());
@@ -1929,7 +1950,7 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
         finish_views(cv);
         if (hinted) {
             // the validation verdict is still to be read
-            if (defer) return defer_counters(ctx, cv, gctr, d_err);
+            if (defer) return defer_counters(ctx, cv, d_err);
             unsigned *hf = (unsigned *)ensure_pinned(ctx, 64);
             SPADE_HIP(ctx, hipMemcpyAsync(hf, d_err, sizeof(unsigned), hipMemcpyDeviceToHost, st));
             SPADE_HIP(ctx, hipStreamSynchronize(st));
@@ -2236,13 +2257,13 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
         SPADE_HIP(ctx, run_captured(ctx, cv, key, qs, enqueue));
         if (defer) {
             finish_views(cv);
-            return defer_counters(ctx, cv, gctr, d_err);
+            return defer_counters(ctx, cv, d_err);
         }
-        uint64_t *hc = (uint64_t *)ensure_pinned(ctx, COUNTER_COPY);
+        void *hc = ensure_pinned(ctx, COUNTER_COPY);
         if (!hc) return set_error(ctx, SPADE_E_NOMEM, "pinned staging allocation failed");
-        SPADE_HIP(ctx, copy_counters(hc, gctr, d_err, st));
+        SPADE_HIP(ctx, copy_counters(hc, d_err, st));
         SPADE_HIP(ctx, hipStreamSynchronize(st));
-        std::memcpy(&ef, hc + NGCTR, sizeof(unsigned));
+        ef = counter_flags(hc);
         if (ef & (1u | 2u | 4u | 64u | 128u)) return flag_error(ctx, ef);   // a hinted build's verdict
         if (!(ef & 32u)) {
             done_single = true;
