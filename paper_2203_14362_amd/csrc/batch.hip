@@ -205,7 +205,7 @@ __global__ void k_pair_chunk_fill(int64_t np, const uint32_t *pc, const unsigned
 
 // Canvas q of a set as a probe view (descriptor in device memory).
 __device__ __forceinline__ CanvasView set_view(const CanvasDesc &d, const uint32_t *cells, const uint16_t *coarse,
-                                               const uint4 *desc, const Cand *cands,
+                                               const Cand *cands,
                                                const Edge *ledges, const double2 *pspan)
 {
     CanvasView v;
@@ -216,7 +216,6 @@ __device__ __forceinline__ CanvasView set_view(const CanvasDesc &d, const uint32
     v.M = d.M;
     v.cells = cells + d.cell_off;
     v.coarse = coarse + d.coarse_off;
-    v.desc = desc + d.desc_off;
     v.cands = cands;
     v.ledges = ledges;
     v.pspan = pspan;
@@ -227,7 +226,6 @@ struct SetArgs {
     const CanvasDesc *cds;
     const uint32_t *cells;
     const uint16_t *coarse;
-    const uint4 *desc;
     const Cand *cands;
     const Edge *ledges;
     const double2 *pspan;
@@ -260,7 +258,7 @@ __global__ __launch_bounds__(BT_THREADS) void k_batch_select(SetArgs S, int64_t 
             const uint32_t p = plist[t];
             const uint32_t qy = pq[p];
             const CanvasDesc d = S.cds[qy];
-            const CanvasView v = set_view(d, S.cells, S.coarse, S.desc, S.cands, S.ledges, S.pspan);
+            const CanvasView v = set_view(d, S.cells, S.coarse, S.cands, S.ledges, S.pspan);
             uint32_t hit = 0;
 #pragma unroll
             for (int u = 0; u < BT_PER; ++u) {
@@ -347,7 +345,7 @@ __global__ __launch_bounds__(BT_THREADS) void k_batch_count(SetArgs S, int64_t n
         for (uint32_t t = cbase[c]; t < cbase[c + 1]; ++t) {
             const uint32_t p = plist[t];
             const CanvasDesc d = S.cds[pq[p]];
-            const CanvasView v = set_view(d, S.cells, S.coarse, S.desc, S.cands, S.ledges, S.pspan);
+            const CanvasView v = set_view(d, S.cells, S.coarse, S.cands, S.ledges, S.pspan);
             auto add = [&](uint32_t label) {
                 const unsigned long long key = (unsigned long long)(d.poly_base + label) + 1ull;
                 uint32_t h = (uint32_t)(key * 0x9E3779B97F4A7C15ull >> 55) & (HSLOTS - 1);
@@ -479,7 +477,6 @@ static SetArgs set_args(const spade_canvas *set)
     S.cds = (const CanvasDesc *)set->dcds.p;
     S.cells = (const uint32_t *)set->cells.p;
     S.coarse = (const uint16_t *)set->coarse.p;
-    S.desc = (const uint4 *)set->desc.p;
     S.cands = (const Cand *)set->cands.p;
     S.ledges = (const Edge *)set->ledges.p;
     S.pspan = (const double2 *)set->pspan.p;

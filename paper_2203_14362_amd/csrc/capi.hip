@@ -142,7 +142,6 @@ void spade_ctx_destroy(spade_ctx *ctx)
         free_buf(ctx->plain->edges);
         free_buf(ctx->plain->coarse);
         free_buf(ctx->plain->dcds);
-        free_buf(ctx->plain->desc);
         drop_graph(ctx->plain);
         delete ctx->plain;
     }
@@ -254,7 +253,6 @@ void spade_canvas_destroy(spade_canvas *cv)
     free_buf(cv->edges);
     free_buf(cv->coarse);
     free_buf(cv->dcds);
-    free_buf(cv->desc);
     drop_graph(cv);
     delete cv;
 }

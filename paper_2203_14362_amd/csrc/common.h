@@ -52,27 +52,16 @@ constexpr uint32_t CAND_LAST = 2u;
 // Coarse canvas word (one per 2^blog x 2^blog block of pixels):
 //   label + 1 (0: in no polygon) when every pixel of the block carries that
 //   same non-boundary canvas word;
-//   COARSE_MIXED for a mixed block, described by compact records;
-//   COARSE_FULL when the block must be read from the full canvas.
-// The records of the mixed block with coarse index k (row-major in the
-// coarse grid) start at record k * 2^(2 blog) / 32: one 16-byte record per
-// 32 pixels (in pixel order, pixel p of a block at (p mod 2^blog,
-// p div 2^blog)) holding a 2-bit code per pixel (0, 1: palette word 0 or 1,
-// 2: in no polygon, 3: boundary pixel, whose word is read from the full
-// canvas) and two 16-bit palette canvas words.  Blocks with more than two
-// non-zero non-boundary words, or words above 0xffff, are COARSE_FULL.
-constexpr uint16_t COARSE_MIXED = 0x8000u;
+//   COARSE_FULL otherwise: the point's word is read from the full canvas.
+// (An intermediate level of per-pixel codes for blocks of few labels costs
+// every wave that meets one a further dependent read; it measured slower
+// than reading the full canvas word directly.)
 constexpr uint16_t COARSE_FULL = 0xffffu;
 // A single canvas of at most COARSE_BYTE_MAXM polygons stores its coarse
 // words as bytes, half the LDS for the same block size: label + 1 below
-// COARSE_BYTE_MIXED, then the two flags.  A uniform block of a larger label
-// is stored as mixed (its records say so pixel by pixel).
-constexpr uint32_t COARSE_BYTE_MIXED = 254u;
+// COARSE_BYTE_FULL.  A uniform block of a larger label is stored as full.
 constexpr uint32_t COARSE_BYTE_FULL = 255u;
 constexpr int64_t COARSE_BYTE_MAXM = 512;
-
-// Bytes of the compact records of one mixed block of 2^blog pixels a side.
-__host__ __device__ inline uint32_t desc_bytes(int blog) { return (1u << (2 * blog)) / 2u; }
 
 // Edge in world coordinates with lo.y <= hi.y.
 // One canvas of a canvas set: its world->pixel map, bounding box, size and
@@ -89,7 +78,6 @@ struct CanvasDesc {
     int64_t row_base;             // first global row of the set
     int64_t cell_off;             // first canvas word (tile-major, 16 x 16 tiles)
     int64_t coarse_off;           // first coarse word
-    int64_t desc_off;             // first mixed-block record (16-byte units; Wc * Hc blocks)
 };
 
 // Everything a probe kernel needs, passed by value.
@@ -103,7 +91,6 @@ struct CanvasView {
     int64_t M;                    // number of polygons
     const uint32_t *cells;        // canvas words, tile-major (16 x 16 tiles)
     const uint16_t *coarse;       // Wc * Hc coarse words, row-major
-    const uint4 *desc;            // mixed-block records, 2^(2 blog) / 32 per coarse block
     const Cand *cands;
     const Edge *ledges;           // local edges of the records
     const double2 *pspan;         // (ylo, yhi) of partial-right edges
@@ -127,14 +114,14 @@ struct spade_canvas {
     int64_t n_cands = 0;
     int64_t n_elist = 0;
     int64_t n_edges = 0;
-    spade::DevBuf cells, cands, ledges, pspan, edges, coarse, desc;
+    spade::DevBuf cells, cands, ledges, pspan, edges, coarse;
     std::vector<uint64_t> gkey;               // launch parameters of the last build
     hipGraphExec_t gexec = nullptr;           // its captured launches (second build on)
     bool pending = false;                     // built, counters and flags not yet read
     const void *pend_src = nullptr;           // their device block, until build_flush copies it
     size_t bytes() const
     {
-        return cells.cap + cands.cap + ledges.cap + pspan.cap + coarse.cap + desc.cap;
+        return cells.cap + cands.cap + ledges.cap + pspan.cap + coarse.cap;
     }
 };
 

@@ -1,6 +1,6 @@
 // Device-side canvas lookup shared by the probe kernels (single canvas and
-// canvas sets): pixel mapping, the coarse / mixed-block / full canvas
-// levels, and the exact test of one boundary-index record.
+// canvas sets): pixel mapping, the coarse and full canvas levels, and the
+// exact test of one boundary-index record.
 #pragma once
 
 #include "common.h"
@@ -21,17 +21,15 @@ typedef const uint64_t __attribute__((address_space(1))) *gu64p;
 
 // Canvas lookup state of one point: the word once known, or where to read it.
 struct Look {
-    uint32_t word;   // final canvas word when kind == 0
-    uint32_t kind;   // 0: final, 1: mixed-block records, 2: full canvas
-    uint32_t m;      // coarse block index (kind 1)
-    uint32_t pix;    // pixel within its coarse block (kind 1)
-    uint32_t fidx;   // full-canvas index (kinds 1 and 2)
+    uint32_t word;   // final canvas word when !full
+    uint32_t full;   // the word is read from the full canvas
+    uint32_t fidx;   // full-canvas index (full)
 };
 
 // Level 1: bbox test, pixel mapping, coarse word from LDS.
 __device__ __forceinline__ Look look_coarse(const CanvasView &cv, const uint16_t *coarse, double x, double y)
 {
-    Look L{0u, 0u, 0u, 0u, 0u};
+    Look L{0u, 0u, 0u};
     // exact half-open bbox test; NaN fails every comparison
     if (!(cv.bx0 <= x && x < cv.bx1 && cv.by0 <= y && y < cv.by1)) return L;
     const double u = __dmul_rn(__dsub_rn(x, cv.X0), cv.sx);
@@ -39,54 +37,18 @@ __device__ __forceinline__ Look look_coarse(const CanvasView &cv, const uint16_t
     const int c = min((int)u, cv.W - 1);
     const int r = min((int)v, cv.H - 1);
     const int ci = (r >> cv.blog) * cv.Wc + (c >> cv.blog);
-    uint32_t cw;
-    if (cv.cbyte) {
-        const uint32_t b = ((const uint8_t *)coarse)[ci];
-        cw = b < COARSE_BYTE_MIXED ? b : (b == COARSE_BYTE_MIXED ? COARSE_MIXED : COARSE_FULL);
-    } else {
-        cw = coarse[ci];
-    }
-    if (!(cw & COARSE_MIXED)) { L.word = cw; return L; }
+    const uint32_t cw = cv.cbyte ? ((const uint8_t *)coarse)[ci] : coarse[ci];
+    if (cw != (cv.cbyte ? COARSE_BYTE_FULL : (uint32_t)COARSE_FULL)) { L.word = cw; return L; }
+    L.full = 1u;
     L.fidx = (uint32_t)tile_index(cv.Wt, c, r);
-    if (cw == COARSE_FULL) { L.kind = 2; return L; }
-    L.kind = 1;
-    L.m = (uint32_t)ci;
-    const int B = 1 << cv.blog;
-    L.pix = (uint32_t)(((r & (B - 1)) << cv.blog) | (c & (B - 1)));
     return L;
-}
-
-// The compact record of the 32-pixel group holding a mixed-block pixel.
-__device__ __forceinline__ uint4 read_group(const CanvasView &cv, const Look &L)
-{
-    const uint32_t G = 1u << (2 * cv.blog - 5);
-    const gu32p q = (gu32p)(cv.desc + (size_t)L.m * G + (L.pix >> 5));
-    return make_uint4(q[0], q[1], q[2], q[3]);
-}
-
-// Level 2: resolve a group record.  Returns true with the final word, or
-// false for a boundary pixel (kind becomes 2: read the full canvas).
-__device__ __forceinline__ bool resolve_group(const uint4 &R, Look &L)
-{
-    const uint64_t codes = (uint64_t)R.x | ((uint64_t)R.y << 32);
-    const uint32_t sh = 2u * (L.pix & 31u);
-    const uint32_t code = (uint32_t)(codes >> sh) & 3u;
-    if (code < 3u) {
-        L.word = code == 0u ? (R.w & 0xffffu) : (code == 1u ? (R.w >> 16) : 0u);
-        L.kind = 0;
-        return true;
-    }
-    L.kind = 2;
-    return false;
 }
 
 // Canvas word of (x, y): 0, label + 1, or BFLAG | first candidate record.
 __device__ __forceinline__ uint32_t lookup(const CanvasView &cv, const uint16_t *coarse, double x, double y)
 {
-    Look L = look_coarse(cv, coarse, x, y);
-    if (L.kind == 0) return L.word;
-    if (L.kind == 1 && resolve_group(read_group(cv, L), L)) return L.word;
-    return ((gu32p)cv.cells)[L.fidx];
+    const Look L = look_coarse(cv, coarse, x, y);
+    return L.full ? ((gu32p)cv.cells)[L.fidx] : L.word;
 }
 
 __device__ __forceinline__ bool cand_inside(const CanvasView &cv, const Cand &cd, double x, double y)

@@ -6,7 +6,7 @@
 // non-temporal), rejected if it lies outside the half-open bounding box of
 // the polygons and mapped to its pixel.  The pixel is classified in two
 // levels: a coarse canvas held in LDS by every workgroup answers directly
-// for blocks whose pixels share one label; points in mixed blocks read their
+// for blocks whose pixels share one label; points in any other block read their
 // canvas word from the tile-major canvas in global memory (L2 / MALL).  A
 // label is final; a boundary pixel needs the exact test of each candidate
 // polygon.  Boundary points are compacted per wavefront (ballot + prefix
@@ -121,24 +121,15 @@ __global__ __launch_bounds__(CNT_THREADS) void k_count(CanvasView cv, int64_t n,
 #pragma unroll
         for (int u = 0; u < CNT_UNROLL; ++u) { xs[u] = xn[u]; ys[u] = yn[u]; }
         if (base + step < n) fetch(base + step);
-        // the canvas reads of this iteration are issued level by level, all
-        // points of a level before any result is used
+        // the coarse words of all points of this iteration first, then
+        // their full-canvas reads, all issued before any result is used
         Look lk[CNT_UNROLL];
-        uint4 dr[CNT_UNROLL];
         uint32_t ws[CNT_UNROLL];
 #pragma unroll
         for (int u = 0; u < CNT_UNROLL; ++u) lk[u] = look_coarse(cv, coarse, xs[u], ys[u]);
 #pragma unroll
         for (int u = 0; u < CNT_UNROLL; ++u)
-            if (lk[u].kind == 1) dr[u] = read_group(cv, lk[u]);
-#pragma unroll
-        for (int u = 0; u < CNT_UNROLL; ++u) {
-            if (lk[u].kind == 1) resolve_group(dr[u], lk[u]);
-            ws[u] = lk[u].word;
-        }
-#pragma unroll
-        for (int u = 0; u < CNT_UNROLL; ++u)
-            if (lk[u].kind == 2) ws[u] = ((gu32p)cv.cells)[lk[u].fidx];
+            ws[u] = lk[u].full ? ((gu32p)cv.cells)[lk[u].fidx] : lk[u].word;
 #pragma unroll
         for (int u = 0; u < CNT_UNROLL; ++u) {
             const uint32_t w = ws[u];

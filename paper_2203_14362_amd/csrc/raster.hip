@@ -1430,18 +1430,6 @@ __global__ __launch_bounds__(ROW_THREADS) void k_rows(RowArgs A)
     }
 }
 
-// Spreads the 32 bits of v to the even bit positions of a 64-bit word.
-__device__ __forceinline__ uint64_t spread_bits(uint32_t v)
-{
-    uint64_t x = v;
-    x = (x | (x << 16)) & 0x0000ffff0000ffffull;
-    x = (x | (x << 8)) & 0x00ff00ff00ff00ffull;
-    x = (x | (x << 4)) & 0x0f0f0f0f0f0f0f0full;
-    x = (x | (x << 2)) & 0x3333333333333333ull;
-    x = (x | (x << 1)) & 0x5555555555555555ull;
-    return x;
-}
-
 // Canvas holding global coarse word g.
 __device__ __forceinline__ int canvas_of_coarse(const CanvasDesc *cds, int nc, int64_t g)
 {
@@ -1454,14 +1442,11 @@ __device__ __forceinline__ int canvas_of_coarse(const CanvasDesc *cds, int nc, i
 }
 
 // Coarse level, one wave per coarse block (lane l handles pixels l, l + 64,
-// ...; pixel p of a block is (p mod B, p div B)): a uniform block stores its word,
-// a mixed block (at most two non-zero interior words up to 0xffff, plus
-// empty and boundary pixels) stores COARSE_MIXED and its compact records at
-// the block's own slot, anything else COARSE_FULL.  Slots are fixed by the
-// block index, so there is no allocation and no global atomic.
+// ...): a block whose pixels all carry the same non-boundary word that the
+// coarse word can hold stores it, any other block COARSE_FULL.  No
+// allocation and no global atomic.
 __global__ __launch_bounds__(256) void k_compact(const CanvasDesc *cds, int nc, int64_t ncoarse_tot,
-                                                 const uint32_t *cells_all, uint16_t *coarse_all,
-                                                 uint4 *desc_all)
+                                                 const uint32_t *cells_all, uint16_t *coarse_all)
 {
     const int lane = threadIdx.x & 63;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -1472,80 +1457,25 @@ __global__ __launch_bounds__(256) void k_compact(const CanvasDesc *cds, int nc, 
         const int W = cd.W, H = cd.H, Wt = cd.Wt, blog = cd.blog, Wc = cd.Wc;
         const uint32_t *cells = cells_all + cd.cell_off;
         uint16_t *coarse = coarse_all + cd.coarse_off;
-        const int B = 1 << blog, P = B * B, J = P / 64, G = P / 32;
+        const int B = 1 << blog, J = (B * B) / 64;
         const int64_t cell = gcell - cd.coarse_off;
-        // the block's coarse word: a uniform word (< COARSE_MIXED), COARSE_MIXED
-        // or COARSE_FULL; a byte-sized canvas stores a word it cannot hold as FULL
-        auto put = [&](uint32_t v) {
-            if (lane != 0) return;
-            if (cd.cbyte)
-                ((uint8_t *)coarse)[cell] = (uint8_t)(v == COARSE_MIXED ? COARSE_BYTE_MIXED
-                                                      : (v == COARSE_FULL || v >= COARSE_BYTE_MIXED) ? COARSE_BYTE_FULL : v);
-            else
-                coarse[cell] = (uint16_t)v;
-        };
-        if (cd.empty) {
-            put(0u);
-            continue;
-        }
-        const int cy = (int)(cell / Wc), cx = (int)(cell % Wc);
-        const int c0 = cx << blog, r0 = cy << blog;
-        auto pix_word = [&](int p, bool &valid) -> uint32_t {
-            const int c = c0 + (p & (B - 1)), r = r0 + (p >> blog);
-            valid = c < W && r < H;
-            return valid ? cells[tile_index(Wt, c, r)] : 0u;
-        };
-        const uint32_t first = cells[tile_index(Wt, c0, r0)];
-        bool same = true;
-        for (int j = 0; j < J; ++j) {
-            bool v;
-            const uint32_t w = pix_word(lane + 64 * j, v);
-            same &= !v || w == first;
-        }
-        if (__all(same) && !(first & BFLAG) && first < (cd.cbyte ? COARSE_BYTE_MIXED : COARSE_MIXED)) {
-            put(first);
-            continue;
-        }
-        // palette: up to two distinct non-zero non-boundary words <= 0xffff
-        uint32_t pal[2] = {0u, 0u};
-        int npal = 0;
-        bool full = false;
-        while (true) {
-            uint32_t cand = 0;
-            bool has = false;
-            for (int j = 0; j < J && !has; ++j) {
-                bool v;
-                const uint32_t w = pix_word(lane + 64 * j, v);
-                if (v && w != 0u && !(w & BFLAG)) {
-                    bool known = false;
-                    for (int t = 0; t < npal; ++t) known |= (pal[t] == w);
-                    if (!known) { cand = w; has = true; }
-                }
+        const uint32_t fullw = cd.cbyte ? COARSE_BYTE_FULL : (uint32_t)COARSE_FULL;
+        uint32_t v = 0u;
+        if (!cd.empty) {
+            const int cy = (int)(cell / Wc), cx = (int)(cell % Wc);
+            const int c0 = cx << blog, r0 = cy << blog;
+            const uint32_t first = cells[tile_index(Wt, c0, r0)];
+            bool same = true;
+            for (int j = 0; j < J; ++j) {
+                const int p = lane + 64 * j;
+                const int c = c0 + (p & (B - 1)), r = r0 + (p >> blog);
+                same &= !(c < W && r < H) || cells[tile_index(Wt, c, r)] == first;
             }
-            const unsigned long long mask = __ballot(has);
-            if (mask == 0ull) break;
-            const uint32_t v = __shfl(cand, __ffsll((long long)mask) - 1, 64);
-            if (npal == 2 || v > 0xffffu) { full = true; break; }
-            pal[npal++] = v;
+            v = (__all(same) && !(first & BFLAG) && first < fullw) ? first : fullw;
         }
-        if (full) {
-            put(COARSE_FULL);
-            continue;
-        }
-        put(COARSE_MIXED);
-        uint4 *rec = desc_all + cd.desc_off + (size_t)cell * G;
-        const uint32_t palw = pal[0] | (pal[1] << 16);
-        for (int j = 0; j < J; ++j) {
-            bool v;
-            const uint32_t w = pix_word(lane + 64 * j, v);
-            const uint32_t code = (!v || w == 0u) ? 2u : ((w & BFLAG) ? 3u : (w == pal[0] ? 0u : 1u));
-            const unsigned long long b0 = __ballot(code & 1u), b1 = __ballot(code & 2u);
-            if (lane == 0 || lane == 32) {
-                const int h = lane >> 5;
-                const uint32_t lo = (uint32_t)(b0 >> (32 * h)), hi = (uint32_t)(b1 >> (32 * h));
-                const uint64_t cw = spread_bits(lo) | (spread_bits(hi) << 1);
-                rec[2 * j + h] = make_uint4((uint32_t)cw, (uint32_t)(cw >> 32), 0u, palw);
-            }
+        if (lane == 0) {
+            if (cd.cbyte) ((uint8_t *)coarse)[cell] = (uint8_t)v;
+            else coarse[cell] = (uint16_t)v;
         }
     }
 }
@@ -1637,7 +1567,6 @@ CanvasView view_of(const spade_canvas *cv, int q)
     v.M = d.M;
     v.cells = (const uint32_t *)cv->cells.p + d.cell_off;
     v.coarse = (const uint16_t *)cv->coarse.p + d.coarse_off;
-    v.desc = (const uint4 *)cv->desc.p + d.desc_off;
     v.cands = (const Cand *)cv->cands.p;
     v.ledges = (const Edge *)cv->ledges.p;
     v.pspan = (const double2 *)cv->pspan.p;
@@ -1875,7 +1804,7 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
 
     // canvas maps, sizes and offsets
     int maxW = 1;
-    int64_t Htot = 0, cells_tot = 0, coarse_tot = 0, desc_tot = 0;
+    int64_t Htot = 0, cells_tot = 0, coarse_tot = 0;
     bool any = false;
     for (int q = 0; q < nc; ++q) {
         CanvasDesc &d = cds[q];
@@ -1922,11 +1851,9 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
         d.row_base = Htot;
         d.cell_off = cells_tot;
         d.coarse_off = coarse_tot;
-        d.desc_off = desc_tot;
         Htot += H;
         cells_tot += (int64_t)d.Wt * Ht * 256;
         coarse_tot += (int64_t)d.Wc * d.Hc;
-        desc_tot += (int64_t)d.Wc * d.Hc * (desc_bytes(blog) / 16);
         maxW = std::max(maxW, W);
     }
     if (Htot > 0x7fffffffLL) return set_error(ctx, SPADE_E_UNSUPPORTED, "canvas set has too many rows");
@@ -1936,7 +1863,6 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
 
     if (ensure(ctx, cv->cells, sizeof(uint32_t) * (size_t)cells_tot) ||
         ensure(ctx, cv->coarse, sizeof(uint16_t) * ((size_t)coarse_tot + 2)) ||
-        ensure(ctx, cv->desc, 16 * (size_t)desc_tot + 64) ||
         ensure(ctx, cv->edges, sizeof(Edge) * (size_t)std::max<int64_t>(V, 1)))
         return SPADE_E_NOMEM;
     cv->n_edges = V;
@@ -2198,11 +2124,11 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
     };
     ra.cells = (uint32_t *)cv->cells.p;
 
-    // Coarse level + compact records of mixed blocks, from the canvas words.
+    // Coarse level from the canvas words.
     auto launch_compact = [&]() -> hipError_t {
         const int cgrid = (int)std::max<int64_t>(1, std::min<int64_t>((coarse_tot + 3) / 4, 65536));
         hipLaunchKernelGGL(k_compact, dim3(cgrid), dim3(256), 0, qs, d_cds, nc, coarse_tot,
-                           (const uint32_t *)cv->cells.p, (uint16_t *)cv->coarse.p, (uint4 *)cv->desc.p);
+                           (const uint32_t *)cv->cells.p, (uint16_t *)cv->coarse.p);
         return hipGetLastError();
     };
 
@@ -2253,7 +2179,7 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
         putp(dk.p); putp(dk2.p); putp(dv.p); putp(dv2.p); putp(dc.p); putp(df.p); putp(drow.p); putp(cub.p);
         putp(ra.gaux); putp(gctr); putp(d_err); putp(drc.p); putp(drs.p);
         putp(cv->cells.p); putp(cv->cands.p); putp(cv->ledges.p); putp(cv->pspan.p); putp(cv->coarse.p);
-        putp(cv->desc.p); putp(ctx->side); putp(ctx->side2); putp(ctx->fork); putp(ctx->join); putp(ctx->join2);
+        putp(ctx->side); putp(ctx->side2); putp(ctx->fork); putp(ctx->join); putp(ctx->join2);
         SPADE_HIP(ctx, run_captured(ctx, cv, key, qs, enqueue));
         if (defer) {
             finish_views(cv);

@@ -206,8 +206,8 @@ def test_invalid_polygon_sets(ctx):
 @pytest.mark.parametrize("wh", [(0, 0), (700, 700), (2048, 2048)])
 def test_byte_coarse_large_labels(ctx, wh):
     """More than 253 polygons in one canvas: byte-sized coarse words cannot
-    hold the larger labels, whose uniform blocks then go through the
-    mixed-block records."""
+    hold the larger labels, whose uniform blocks are then read from the full
+    canvas."""
     x, y = gen.uniform_points(200_000, seed=61)
     polys = gen.voronoi_jitter(400, 5, 20, seed=61, L=1.0)
     ctx.set_canvas_size(*wh)
