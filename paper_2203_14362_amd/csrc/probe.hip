@@ -29,7 +29,7 @@
 namespace spade {
 
 constexpr int CNT_THREADS = 1024;         // count probe workgroup
-constexpr int CNT_UNROLL = 4;             // points per thread per iteration
+constexpr int CNT_UNROLL = 5;             // points per thread per iteration (6 spills)
 constexpr int QCAP = 64;                  // boundary queue entries per wavefront
 constexpr int HIST_MAX = 8192;            // polygons counted in LDS
 constexpr int EMIT_THREADS = 512;
