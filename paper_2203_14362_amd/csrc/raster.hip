@@ -432,18 +432,37 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_rowscan(int64_t Htot, const ui
     if (tid == 0) { s_nb = 0; s_nc = 0; s_max = 0; }
     const int64_t per = (Htot + SCAN_THREADS - 1) / SCAN_THREADS;
     const int64_t b = min(Htot, (int64_t)tid * per), e = min(Htot, b + per);
+    // up to RS_REG counts per thread are loaded together and kept in
+    // registers for the second pass (one memory round trip instead of one
+    // per row and pass)
+    constexpr int RS_REG = 8;
+    uint32_t rc[RS_REG];
+    const bool inreg = per <= RS_REG;
     long long tot = 0;
-    for (int64_t r = b; r < e; ++r) tot += rcount[r * rstride];
+    if (inreg) {
+#pragma unroll
+        for (int k = 0; k < RS_REG; ++k) rc[k] = b + k < e ? rcount[(b + k) * rstride] : 0u;
+#pragma unroll
+        for (int k = 0; k < RS_REG; ++k) tot += rc[k];
+    } else {
+        for (int64_t r = b; r < e; ++r) tot += rcount[r * rstride];
+    }
     long long off = block_excl_sum(tot, wtot);
     int mx = 0;
-    for (int64_t r = b; r < e; ++r) {
-        const long long cnt = rcount[r * rstride];
+    auto visit = [&](int64_t r, long long cnt) {
         row_off[r] = (uint32_t)off;
         cursor[r * rstride] = (uint32_t)off;
         off += cnt;
         mx = max(mx, (int)min(cnt, (long long)0x7fffffff));
         if (cnt > capB) longrows[Htot + atomicAdd(&s_nc, 1u)] = (uint32_t)r;
         else if (cnt > capA) longrows[atomicAdd(&s_nb, 1u)] = (uint32_t)r;
+    };
+    if (inreg) {
+#pragma unroll
+        for (int k = 0; k < RS_REG; ++k)
+            if (b + k < e) visit(b + k, rc[k]);
+    } else {
+        for (int64_t r = b; r < e; ++r) visit(r, rcount[r * rstride]);
     }
     atomicMax(&s_max, mx);
     __syncthreads();
