@@ -43,6 +43,8 @@ constexpr double MARGIN = 1.0 / 4096.0;       // pixels
 constexpr double SLOP = 1.0 / 1073741824.0;   // pixels, covers clipping round-off
 constexpr int MAXW = 8192;
 constexpr int ROW_THREADS = 256;
+constexpr int ROW_THREADS_MAX = 512;
+constexpr size_t ROW_LDS_PER_CU = 160 * 1024;   // LDS of one CU
 constexpr int RED_BLOCKS = 256;
 
 constexpr uint8_t F_SPAN = 1;    // edge spans the whole dilated row band
@@ -728,7 +730,11 @@ __global__ void k_gather(int64_t T, const uint32_t *perm, const uint32_t *ent_c,
 __device__ __forceinline__ int cix(int c) { return c + (c >> 5); }
 __host__ __device__ inline int col_words(int W) { return W + 1 + (W + 1) / 32 + 1; }
 
-// Block-wide in-place inclusive scan of a[cix(0..n)) with ROW_THREADS
+// Threads of a row workgroup: ROW_THREADS, or ROW_THREADS_MAX where the
+// row stage leaves room for at most two workgroups per CU.
+__device__ __forceinline__ int row_threads() { return (int)blockDim.x; }
+
+// Block-wide in-place inclusive scan of a[cix(0..n)) with row_threads()
 // threads: contiguous per-thread chunks, wave-level shuffle scan of the
 // chunk totals, one LDS word per wave.  `op` must be associative and
 // commutative.
@@ -736,7 +742,7 @@ template <typename T, typename Op>
 __device__ void block_scan(T *a, int n, T *wtot, Op op, T ident)
 {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int per = (n + ROW_THREADS - 1) / ROW_THREADS;
+    const int per = (n + row_threads() - 1) / row_threads();
     const int b = min(n, tid * per), e = min(n, b + per);
     T acc = ident;
     for (int i = b; i < e; ++i) acc = op(acc, a[cix(i)]);   // chunk total: loads only
@@ -992,7 +998,7 @@ __device__ void claimant_walk(const RowArgs &A, const RowData &D, const RowShare
 template <typename Fn>
 __device__ __forceinline__ void for_each_run(const RowData &D, Fn fn)
 {
-    for (int i = threadIdx.x; i < D.n; i += ROW_THREADS) {
+    for (int i = threadIdx.x; i < D.n; i += row_threads()) {
         const uint32_t k = D.poly[i];
         if (i != 0 && D.poly[i - 1] == k) continue;
         int je = i + 1;
@@ -1011,10 +1017,10 @@ __device__ __forceinline__ void for_each_run(const RowData &D, Fn fn)
 __device__ void row_scans(int32_t *sa, int32_t *sb, uint32_t *sx, int W, uint32_t *pre, int n,
                           uint32_t *ilen, int ni, uint32_t *wt)
 {
-    constexpr int NW = ROW_THREADS / 64;
+    const int NW = row_threads() >> 6;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int pc = (W + ROW_THREADS - 1) / ROW_THREADS, pp = (n + ROW_THREADS - 1) / ROW_THREADS;
-    const int pi = (ni + ROW_THREADS - 1) / ROW_THREADS;
+    const int pc = (W + row_threads() - 1) / row_threads(), pp = (n + row_threads() - 1) / row_threads();
+    const int pi = (ni + row_threads() - 1) / row_threads();
     const int cb = min(W, tid * pc), ce = min(W, cb + pc);
     const int qb = min(n, tid * pp), qe = min(n, qb + pp);
     const int ib = min(ni, tid * pi), ie = min(ni, ib + pi);
@@ -1066,7 +1072,7 @@ __device__ void all_column_records(const RowArgs &A, const RowData &D, const Row
     const int ni = (int)*L.nint;
     if (ni == 0) return;
     const uint32_t total = D.ilen[ni - 1];
-    for (uint32_t t = threadIdx.x; t < total; t += ROW_THREADS) {
+    for (uint32_t t = threadIdx.x; t < total; t += row_threads()) {
         int lo = 0, hi = ni - 1;            // first interval with prefix > t
         while (lo < hi) {
             const int mid = (lo + hi) >> 1;
@@ -1237,7 +1243,7 @@ __device__ void process_row(const RowArgs &A, const RowData &D, const RowShared 
     // phase 1: per run, footprints (boundary counts), interior claims, the
     //          running footprint maxima and the run list; per entry, the
     //          partial / spanning indicators to be scanned
-    for (int q = tid; q < D.n; q += ROW_THREADS) D.pre[q] = pre_own(D.f[q]);
+    for (int q = tid; q < D.n; q += row_threads()) D.pre[q] = pre_own(D.f[q]);
     for_each_run(D, [&](int i, int je) {
         if (je - i > LONG_RUN) {
             const uint32_t j = atomicAdd(L.nlong, 1u);
@@ -1248,7 +1254,7 @@ __device__ void process_row(const RowArgs &A, const RowData &D, const RowShared 
     __syncthreads();
     {
         const uint32_t nl = min(*L.nlong, (uint32_t)LONGQ);
-        for (uint32_t k = (uint32_t)(tid >> 6); k < nl; k += ROW_THREADS / 64) run_wave(D, L, (int)L.longq[k], W);
+        for (uint32_t k = (uint32_t)(tid >> 6); k < nl; k += (row_threads() >> 6)) run_wave(D, L, (int)L.longq[k], W);
     }
     __syncthreads();
 
@@ -1260,7 +1266,7 @@ __device__ void process_row(const RowArgs &A, const RowData &D, const RowShared 
     // boundary pixel BFLAG | (label + 1 of its single interior claimant, or 0);
     // sa := per-column record counters, starting with the claimant record.
     uint32_t nb = 0, multi = 0;
-    for (int c = tid; c < W; c += ROW_THREADS) {
+    for (int c = tid; c < W; c += row_threads()) {
         const int32_t bc = L.sa[cix(c)], cc = L.sb[cix(c)];
         const uint32_t xc = L.sx[cix(c)];
         const bool bnd = bc > 0 || cc >= 2;
@@ -1276,7 +1282,7 @@ __device__ void process_row(const RowArgs &A, const RowData &D, const RowShared 
     const bool rmulti = *s_multi != 0;
     if (rmulti) {
         // overlapping interiors: every claimant record comes from the run walk
-        for (int c = tid; c < W; c += ROW_THREADS) L.sa[cix(c)] = 0;
+        for (int c = tid; c < W; c += row_threads()) L.sa[cix(c)] = 0;
         __syncthreads();
     }
 
@@ -1289,7 +1295,7 @@ __device__ void process_row(const RowArgs &A, const RowData &D, const RowShared 
 
     {
         uint32_t nrec = 0;
-        for (int c = tid; c < W; c += ROW_THREADS) nrec += (uint32_t)L.sa[cix(c)];
+        for (int c = tid; c < W; c += row_threads()) nrec += (uint32_t)L.sa[cix(c)];
         atomicAdd(s_nrec, (unsigned long long)nrec);
         __syncthreads();
     }
@@ -1314,7 +1320,7 @@ __device__ void process_row(const RowArgs &A, const RowData &D, const RowShared 
         if (s_base[3]) {
             // abandoned: an empty row, so that a probe run before the host
             // has seen the flag reads no stale record index
-            for (int c = tid; c < W; c += ROW_THREADS) cells_q[tile_index(Wt, c, r_local)] = 0u;
+            for (int c = tid; c < W; c += row_threads()) cells_q[tile_index(Wt, c, r_local)] = 0u;
             return;
         }
     }
@@ -1331,7 +1337,7 @@ __device__ void process_row(const RowArgs &A, const RowData &D, const RowShared 
     // record ranges of the row's columns: sa := inclusive prefix of the
     // per-column record counts (column c owns [sa[c-1], sa[c])), sb := 0
     block_scan(L.sa, W, wtoti, [](int32_t a, int32_t b) { return a + b; }, 0);
-    for (int c = tid; c < W; c += ROW_THREADS) L.sb[cix(c)] = 0;
+    for (int c = tid; c < W; c += row_threads()) L.sb[cix(c)] = 0;
     __syncthreads();
 
     // phase 5: records, local edges, partial spans (in row entry order)
@@ -1343,7 +1349,7 @@ __device__ void process_row(const RowArgs &A, const RowData &D, const RowShared 
         all_column_records<true>(A, D, L, rec_base_r, loc_base_r, part_base_r, dummy);
         if (rmulti) for_each_run(D, [&](int i, int je) { claimant_walk<true>(A, D, L, i, je, rec_base_r, W); });
         else
-            for (int c = tid; c < W; c += ROW_THREADS) {
+            for (int c = tid; c < W; c += row_threads()) {
                 const uint32_t w = L.sx[cix(c)];
                 if ((w & BFLAG) && (w & ~BFLAG)) {
                     uint32_t last;
@@ -1356,7 +1362,7 @@ __device__ void process_row(const RowArgs &A, const RowData &D, const RowShared 
                     A.cands[slot] = cd;
                 }
             }
-        for (int q = tid; q < D.n; q += ROW_THREADS)
+        for (int q = tid; q < D.n; q += row_threads())
             if (is_partial(D.f[q])) {
                 const Edge e = A.edges[D.edge[q]];
                 A.pspan[part_base_r + (pre_excl(D, q) & 0x7fffffffu)] = make_double2(e.ylo, e.yhi);
@@ -1366,7 +1372,7 @@ __device__ void process_row(const RowArgs &A, const RowData &D, const RowShared 
 
     // phase 6: write the canvas row (tile-major); a boundary pixel points
     //          at its first record (the last one carries CAND_LAST)
-    for (int c = tid; c < W; c += ROW_THREADS) {
+    for (int c = tid; c < W; c += row_threads()) {
         uint32_t word = L.sx[cix(c)];
         if (word & BFLAG) {
             const int32_t b = c ? L.sa[cix(c - 1)] : 0;
@@ -1379,11 +1385,11 @@ __device__ void process_row(const RowArgs &A, const RowData &D, const RowShared 
 }
 
 template <bool EMIT>
-__global__ __launch_bounds__(ROW_THREADS) void k_rows(RowArgs A)
+__global__ __launch_bounds__(ROW_THREADS_MAX) void k_rows(RowArgs A)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int32_t wtoti[ROW_THREADS / 64];
-    __shared__ uint32_t wtotu[5 * (ROW_THREADS / 64)];
+    __shared__ int32_t wtoti[ROW_THREADS_MAX / 64];
+    __shared__ uint32_t wtotu[5 * (ROW_THREADS_MAX / 64)];
     __shared__ uint32_t s_locfill, s_nint, s_nbp, s_multi, s_nlong;
     __shared__ uint32_t s_longq[LONGQ];
     __shared__ unsigned long long s_nloc, s_nrec, s_base[4];
@@ -1424,14 +1430,14 @@ __global__ __launch_bounds__(ROW_THREADS) void k_rows(RowArgs A)
         const int r_local = (int)(r - cd.row_base);
         const int cw = col_words(W);
         if (n <= cap) {
-            for (int q = tid; q < n; q += ROW_THREADS) {
+            for (int q = tid; q < n; q += row_threads()) {
                 lpoly[q] = A.spoly[s + q];
                 lc[q] = A.sc[s + q];
                 ledge[q] = A.sedge[s + q];
                 lf[q] = A.sf[s + q];
             }
         }
-        for (int c = tid; c < cw; c += ROW_THREADS) { L.sa[c] = 0; L.sb[c] = 0; L.sx[c] = 0; }
+        for (int c = tid; c < cw; c += row_threads()) { L.sa[c] = 0; L.sb[c] = 0; L.sx[c] = 0; }
         if (tid == 0) { s_locfill = 0; s_nint = 0; s_nbp = 0; s_multi = 0; s_nloc = 0; s_nrec = 0; s_nlong = 0; }
         __syncthreads();
         if (n <= cap) {
@@ -2107,6 +2113,11 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
         if (!ctx->join) SPADE_HIP(ctx, hipEventCreateWithFlags(&ctx->join, hipEventDisableTiming));
         SPADE_HIP(ctx, hipEventCreateWithFlags(&ctx->join2, hipEventDisableTiming));
     }
+    // a stage that leaves room for at most two workgroups per CU gets 512
+    // threads per row instead of 256, so the CU still runs 16 waves
+    auto row_threads_for = [](size_t lds) {
+        return (ROW_LDS_PER_CU / std::max<size_t>(lds, 1) <= 2) ? ROW_THREADS_MAX : ROW_THREADS;
+    };
     auto launch_list = [&](bool emit, hipStream_t s2, hipEvent_t done, const uint32_t *list, uint64_t n,
                            int stage, size_t lds, int min_n, int max_n) -> hipError_t {
         RowArgs a2 = ra;
@@ -2118,8 +2129,9 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
         const int bgrid = (int)std::min<uint64_t>(n, 8192);
         hipError_t e = hipStreamWaitEvent(s2, ctx->fork, 0);
         if (e != hipSuccess) return e;
-        if (emit) hipLaunchKernelGGL(k_rows<true>, dim3(bgrid), dim3(ROW_THREADS), lds, s2, a2);
-        else hipLaunchKernelGGL(k_rows<false>, dim3(bgrid), dim3(ROW_THREADS), lds, s2, a2);
+        const int rt = row_threads_for(lds);
+        if (emit) hipLaunchKernelGGL(k_rows<true>, dim3(bgrid), dim3(rt), lds, s2, a2);
+        else hipLaunchKernelGGL(k_rows<false>, dim3(bgrid), dim3(rt), lds, s2, a2);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         return hipEventRecord(done, s2);
     };
@@ -2135,8 +2147,9 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
         a1.first = longrows;
         a1.nfirst = (int64_t)nlistB;
         const int g1 = (int)std::min<int64_t>(H + (int64_t)nlistB, 8192);
-        if (emit) hipLaunchKernelGGL(k_rows<true>, dim3(g1), dim3(ROW_THREADS), rlds, qs, a1);
-        else hipLaunchKernelGGL(k_rows<false>, dim3(g1), dim3(ROW_THREADS), rlds, qs, a1);
+        const int rt = row_threads_for(rlds);
+        if (emit) hipLaunchKernelGGL(k_rows<true>, dim3(g1), dim3(rt), rlds, qs, a1);
+        else hipLaunchKernelGGL(k_rows<false>, dim3(g1), dim3(rt), rlds, qs, a1);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if (bigrows && (e = hipStreamWaitEvent(qs, ctx->join2, 0)) != hipSuccess) return e;
         return hipSuccess;
