@@ -149,6 +149,19 @@ int spade_ctx_last_timing(spade_ctx *ctx, float *raster_ms, float *probe_ms);
 int spade_select(spade_ctx *ctx, const spade_points *pts, const spade_polys *poly,
                  uint32_t *out_ids, int64_t cap, int64_t *n_out);
 
+/* Distance selection from a point (Sec. 4.2, "Canvases for Distance-Based
+ * Queries", and Sec. 5.2, "Distance-Based Queries"): ids of the points whose
+ * Euclidean distance to (cx, cy) is at most r (closed disk), in ascending
+ * order, decided exactly on the FP64 inputs (exact whenever no square of a
+ * coordinate difference, or r^2, overflows or underflows into subnormals).
+ * cx, cy and r must be finite and r >= 0 (else SPADE_E_INVALID); points with
+ * a non-finite coordinate are outside.  out_ids [cap] device buffer; *n_out
+ * (host, may be NULL) receives the number of selected points.  If it exceeds
+ * cap, nothing is written and SPADE_E_CAPACITY is returned (two-step Map,
+ * Sec. 5.1). */
+int spade_select_disk(spade_ctx *ctx, const spade_points *pts, double cx, double cy, double r,
+                      uint32_t *out_ids, int64_t cap, int64_t *n_out);
+
 /* Aggregation (Sec. 5.2, "Spatial Aggregations", plan over point data):
  * out_counts [n_polys] device buffer, overwritten with the number of points
  * inside each polygon.  Overlapping polygons each count the point. */

@@ -363,6 +363,17 @@ static int plain_query(spade_ctx *ctx, const spade_polys *polys, F &&probe)
     return rf ? rf : rp;
 }
 
+int spade_select_disk(spade_ctx *ctx, const spade_points *pts, double cx, double cy, double r,
+                      uint32_t *out_ids, int64_t cap, int64_t *n_out)
+{
+    if (!ctx) return SPADE_E_INVALID;
+    if (n_out) *n_out = 0;
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if ((rc = check_points(ctx, pts))) return rc;
+    return spade::select_disk(ctx, pts, cx, cy, r, out_ids, cap, n_out);
+}
+
 int spade_select(spade_ctx *ctx, const spade_points *pts, const spade_polys *poly, uint32_t *out_ids,
                  int64_t cap, int64_t *n_out)
 {

@@ -184,6 +184,8 @@ size_t coarse_lds_budget(int64_t M);
 
 int probe_count(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts,
                 uint64_t *out_counts);
+int select_disk(spade_ctx *ctx, const spade_points *pts, double cx, double cy, double r, uint32_t *out_ids,
+                int64_t cap, int64_t *n_out);
 int probe_emit(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts,
                uint32_t *out_pt, uint32_t *out_poly, int64_t cap, int64_t *n_out);
 

@@ -36,7 +36,7 @@ EXPORTS = [
     "spade_orient_batch", "spade_ctx_set_timing", "spade_ctx_last_timing",
     "spade_table_create", "spade_table_destroy", "spade_table_info", "spade_batch_build",
     "spade_batch_select", "spade_batch_join_count", "spade_ctx_set_pixels_per_vertex",
-    "spade_batch_rebuild", "spade_ctx_set_graphs", "spade_ctx_graph_stats",
+    "spade_batch_rebuild", "spade_ctx_set_graphs", "spade_ctx_graph_stats", "spade_select_disk",
 ]
 
 
@@ -78,6 +78,8 @@ def load_library():
     lib.spade_last_error.restype = ctypes.c_char_p
     lib.spade_ctx_set_canvas_size.argtypes = [vp, i32, i32]
     lib.spade_select.argtypes = [vp, P(_Points), P(_Polys), vp, i64, P(i64)]
+    lib.spade_select_disk.argtypes = [vp, P(_Points), ctypes.c_double, ctypes.c_double, ctypes.c_double, vp, i64,
+                                      P(i64)]
     lib.spade_join_count.argtypes = [vp, P(_Points), P(_Polys), vp]
     lib.spade_join_pairs.argtypes = [vp, P(_Points), P(_Polys), vp, vp, i64, P(i64)]
     lib.spade_canvas_build.argtypes = [vp, P(_Polys), P(vp)]
@@ -426,6 +428,24 @@ class Context:
     def select(self, x, y, poly_or_canvas, cap=None):
         """Ascending ids (int32 tensor) of the points inside the one polygon."""
         return self._emit(x, y, poly_or_canvas, False, cap)
+
+    def select_disk(self, x, y, cx, cy, r, cap=None):
+        """Ascending ids (int32 tensor) of the points within distance r of
+        (cx, cy), closed disk, decided exactly."""
+        P = _points(x, y)
+        if cap is None:
+            cap = max(P.n, 1)
+        while True:
+            pt = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device)
+            nout = ctypes.c_int64()
+            self._sync_stream()
+            rc = self.lib.spade_select_disk(self.handle, ctypes.byref(P), float(cx), float(cy), float(r),
+                                            ctypes.c_void_p(pt.data_ptr()), cap, ctypes.byref(nout))
+            if rc == SPADE_E_CAPACITY:
+                cap = int(nout.value)
+                continue
+            self._check(rc)
+            return _compact(pt, int(nout.value))
 
     def join_pairs(self, x, y, polys_or_canvas, cap=None):
         """(point ids, polygon ids) int32 tensors, ascending by (point, polygon)."""
