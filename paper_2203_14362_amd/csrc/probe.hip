@@ -17,12 +17,13 @@
 //            (additive blend), flushed into a context accumulator; the last
 //            workgroup copies the counts out and clears the accumulator.
 //   k_emit   ordered output (point ids, or (point, polygon) pairs ascending):
-//            the paper's Map into a null-padded list plus a scan, fused into
-//            one pass with a decoupled look-back prefix over chunks of points
-//            claimed in order.
+//            the paper's two-step Map (a count pass per wavefront segment of
+//            points, a scan of the segment counts, a write pass).
 #include "common.h"
 #include "exact.h"
 #include "lookup.h"
+
+#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 
@@ -32,9 +33,9 @@ constexpr int CNT_THREADS = 1024;         // count probe workgroup
 constexpr int CNT_UNROLL = 5;             // points per thread per iteration (6 spills)
 constexpr int QCAP = 64;                  // boundary queue entries per wavefront
 constexpr int HIST_MAX = 8192;            // polygons counted in LDS
-constexpr int EMIT_THREADS = 512;
-constexpr int EMIT_ITEMS = 8;             // points per thread per chunk
-constexpr int EMIT_CHUNK = EMIT_THREADS * EMIT_ITEMS;
+constexpr int EMIT_THREADS = 1024;
+constexpr int EMIT_SEG = 1024;            // points per wavefront segment
+constexpr int EMIT_GROUP = 4;             // points per lane in flight
 constexpr size_t LDS_TOTAL = 160 * 1024;
 constexpr size_t LDS_RESERVE = 2048;      // static LDS of the kernels
 constexpr size_t QUEUE_BYTES = (size_t)(CNT_THREADS / 64) * QCAP * 20;
@@ -170,12 +171,6 @@ __global__ __launch_bounds__(CNT_THREADS) void k_count(CanvasView cv, int64_t n,
     if (threadIdx.x == 0) *done = 0u;
 }
 
-__global__ void k_zero_u64(int64_t n, unsigned long long *p)
-{
-    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += nth) p[i] = 0ull;
-}
-
 static int num_cus(spade_ctx *ctx)
 {
     static int cached = 0;
@@ -246,152 +241,122 @@ int probe_count(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts,
 
 // ------------------------------------------------------------ ordered emit
 
-constexpr unsigned long long LB_AGG = 1ull << 62;
-constexpr unsigned long long LB_PRE = 2ull << 62;
-constexpr unsigned long long LB_VAL = (1ull << 62) - 1;
+// Matches of one point: 0; 1 with its polygon in `lab`; or m > 1 with the
+// first record of its pixel in `lab` (the polygons are listed again, in
+// ascending order, when they are written).
+struct Match {
+    uint32_t cnt, lab;
+};
 
-// Block-wide exclusive scan of one value per thread (EMIT_THREADS threads).
-__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *wsum, uint32_t &total)
+__device__ __forceinline__ Match match_of(const CanvasView &cv, double x, double y, uint32_t w)
 {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    uint32_t inc = v;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        uint32_t t = __shfl_up(inc, d, 64);
-        if (lane >= d) inc += t;
+    Match r{0u, 0u};
+    if (w == 0u) return r;
+    if (!(w & BFLAG)) return Match{1u, w - 1u};
+    uint32_t rec = w & ~BFLAG, first = 0, m = 0;
+    while (true) {
+        const Cand cd = cv.cands[rec];
+        if (cand_inside(cv, cd, x, y)) {
+            if (m == 0) first = cd.poly;
+            ++m;
+        }
+        if (cd.meta & CAND_LAST) break;
+        ++rec;
     }
-    if (lane == 63) wsum[wv] = inc;
-    __syncthreads();
-    uint32_t pre = 0;
-    total = 0;
-#pragma unroll
-    for (int q = 0; q < EMIT_THREADS / 64; ++q) {
-        uint32_t s = wsum[q];
-        if (q < wv) pre += s;
-        total += s;
-    }
-    __syncthreads();
-    return pre + inc - v;
+    if (m == 1) return Match{1u, first};
+    if (m > 1) return Match{m, w & ~BFLAG};
+    return r;
 }
 
+// Every wavefront owns segments of EMIT_SEG consecutive points (grid-stride
+// over segments), EMIT_GROUP points per lane in flight at a time.
+// WRITE == false: counts[s] = output entries of segment s.
+// WRITE == true:  the entries of segment s, in point order (and ascending
+//                 polygon order for a point in several polygons), from
+//                 position offs[s] on; positions at or beyond cap are not
+//                 written.  No barriers after the coarse canvas is loaded: a
+//                 wavefront ranks its entries with a shuffle scan.
+template <bool WRITE>
 __global__ __launch_bounds__(EMIT_THREADS) void k_emit(CanvasView cv, int64_t n, const double *X,
-                                                       const double *Y, uint32_t *out_pt,
-                                                       uint32_t *out_poly, int64_t cap,
-                                                       unsigned long long *status,
-                                                       unsigned int *chunk_ctr, int64_t nchunks,
-                                                       unsigned long long *total_out)
+                                                       const double *Y, int64_t nseg,
+                                                       unsigned long long *counts,
+                                                       const unsigned long long *offs, uint32_t *out_pt,
+                                                       uint32_t *out_poly, int64_t cap)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ uint32_t s_chunk;
-    __shared__ uint32_t wsum[EMIT_THREADS / 64];
-    __shared__ unsigned long long s_prefix;
     uint16_t *coarse = (uint16_t *)smem;
     load_coarse(cv, coarse, EMIT_THREADS);
     __syncthreads();
-    while (true) {
-        if (threadIdx.x == 0) s_chunk = atomicAdd(chunk_ctr, 1u);
-        __syncthreads();
-        const int64_t chunk = s_chunk;
-        __syncthreads();
-        if (chunk >= nchunks) return;
-        const int64_t base = chunk * EMIT_CHUNK;
-
-        uint32_t lab[EMIT_ITEMS];   // label of a single match, or first record for several
-        uint32_t cnt[EMIT_ITEMS];
+    const int lane = threadIdx.x & 63;
+    const int64_t nwave = ((int64_t)gridDim.x * EMIT_THREADS) >> 6;
+    for (int64_t sg = ((int64_t)blockIdx.x * EMIT_THREADS + threadIdx.x) >> 6; sg < nseg; sg += nwave) {
+        const int64_t i0 = sg * EMIT_SEG + lane;
+        unsigned long long pos = WRITE ? offs[sg] : 0ull;
+        for (int g = 0; g < EMIT_SEG / 64; g += EMIT_GROUP) {
+            // the group's points, then their canvas words, level by level
+            double xs[EMIT_GROUP], ys[EMIT_GROUP];
 #pragma unroll
-        for (int it = 0; it < EMIT_ITEMS; ++it) {
-            const int64_t i = base + (int64_t)it * EMIT_THREADS + threadIdx.x;
-            cnt[it] = 0;
-            lab[it] = 0;
-            if (i >= n) continue;
-            const double x = __builtin_nontemporal_load(X + i), y = __builtin_nontemporal_load(Y + i);
-            const uint32_t w = lookup(cv, coarse, x, y);
-            if (w == 0u) continue;
-            if (!(w & BFLAG)) { cnt[it] = 1; lab[it] = w - 1u; continue; }
-            uint32_t rec = w & ~BFLAG, first = 0, m = 0;
-            while (true) {
-                const Cand cd = cv.cands[rec];
-                if (cand_inside(cv, cd, x, y)) { if (m == 0) first = cd.poly; ++m; }
-                if (cd.meta & CAND_LAST) break;
-                ++rec;
+            for (int k = 0; k < EMIT_GROUP; ++k) {
+                const int64_t i = i0 + 64 * (g + k);
+                xs[k] = i < n ? __builtin_nontemporal_load(X + i) : NAN;   // NaN: outside
+                ys[k] = i < n ? __builtin_nontemporal_load(Y + i) : NAN;
             }
-            if (m == 1) { cnt[it] = 1; lab[it] = first; }
-            else if (m > 1) { cnt[it] = m; lab[it] = w & ~BFLAG; }
-        }
-        // counts in point order: item-major, thread-minor
-        uint32_t excl[EMIT_ITEMS];
-        uint32_t running = 0;
+            uint32_t ws[EMIT_GROUP];
 #pragma unroll
-        for (int it = 0; it < EMIT_ITEMS; ++it) {
-            uint32_t tot;
-            uint32_t e = block_excl_scan(cnt[it], wsum, tot);
-            excl[it] = running + e;
-            running += tot;
-        }
-        // decoupled look-back for the chunk prefix
-        if (threadIdx.x == 0) {
-            unsigned long long prefix = 0;
-            if (chunk == 0) {
-                __hip_atomic_store(&status[0], LB_PRE | (unsigned long long)running, __ATOMIC_RELEASE,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-            } else {
-                __hip_atomic_store(&status[chunk], LB_AGG | (unsigned long long)running, __ATOMIC_RELEASE,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-                int64_t j = chunk - 1;
-                while (true) {
-                    unsigned long long s;
-                    do {
-                        s = __hip_atomic_load(&status[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-                    } while (s == 0ull);
-                    prefix += s & LB_VAL;
-                    if (s & LB_PRE) break;
-                    --j;
-                }
-                __hip_atomic_store(&status[chunk], LB_PRE | (prefix + running), __ATOMIC_RELEASE,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+            for (int k = 0; k < EMIT_GROUP; ++k) {
+                const Look lk = look_coarse(cv, coarse, xs[k], ys[k]);
+                ws[k] = lk.full ? ((gu32p)cv.cells)[lk.fidx] : lk.word;
             }
-            s_prefix = prefix;
-            if (chunk == nchunks - 1) *total_out = prefix + running;
-        }
-        __syncthreads();
-        const unsigned long long prefix = s_prefix;
 #pragma unroll
-        for (int it = 0; it < EMIT_ITEMS; ++it) {
-            if (cnt[it] == 0) continue;
-            const int64_t i = base + (int64_t)it * EMIT_THREADS + threadIdx.x;
-            unsigned long long pos = prefix + excl[it];
-            if (cnt[it] == 1) {
-                if ((int64_t)pos < cap) {
-                    out_pt[pos] = (uint32_t)i;
-                    if (out_poly) out_poly[pos] = lab[it];
+            for (int k = 0; k < EMIT_GROUP; ++k) {
+                const Match mt = match_of(cv, xs[k], ys[k], ws[k]);
+                // inclusive scan of the entry counts across the wavefront
+                uint32_t inc = mt.cnt;
+#pragma unroll
+                for (int d = 1; d < 64; d <<= 1) {
+                    const uint32_t t = __shfl_up(inc, d, 64);
+                    if (lane >= d) inc += t;
                 }
-                continue;
-            }
-            // several polygons contain the point (the pixel's records are in
-            // no particular order): emit them in ascending polygon order, each
-            // pass taking the smallest matching polygon above the last one
-            const double x = X[i], y = Y[i];
-            uint32_t prev = 0;
-            for (uint32_t t = 0; t < cnt[it]; ++t) {
-                uint32_t best = 0xffffffffu;
-                uint32_t rec = lab[it];
-                while (true) {
-                    const Cand cd = cv.cands[rec];
-                    if ((t == 0 || cd.poly > prev) && cd.poly < best && cand_inside(cv, cd, x, y)) best = cd.poly;
-                    if (cd.meta & CAND_LAST) break;
-                    ++rec;
+                const uint32_t tot = __shfl(inc, 63, 64);
+                if (WRITE && mt.cnt) {
+                    const uint32_t pt = (uint32_t)(i0 + 64 * (g + k));
+                    unsigned long long p = pos + (inc - mt.cnt);
+                    if (mt.cnt == 1) {
+                        if ((int64_t)p < cap) {
+                            out_pt[p] = pt;
+                            if (out_poly) out_poly[p] = mt.lab;
+                        }
+                    } else {
+                        // several polygons: each pass takes the smallest
+                        // matching polygon above the last one
+                        uint32_t prev = 0;
+                        for (uint32_t t = 0; t < mt.cnt; ++t) {
+                            uint32_t best = 0xffffffffu;
+                            uint32_t rec = mt.lab;
+                            while (true) {
+                                const Cand cd = cv.cands[rec];
+                                if ((t == 0 || cd.poly > prev) && cd.poly < best && cand_inside(cv, cd, xs[k], ys[k]))
+                                    best = cd.poly;
+                                if (cd.meta & CAND_LAST) break;
+                                ++rec;
+                            }
+                            if ((int64_t)p < cap) {
+                                out_pt[p] = pt;
+                                if (out_poly) out_poly[p] = best;
+                            }
+                            ++p;
+                            prev = best;
+                        }
+                    }
                 }
-                if ((int64_t)pos < cap) {
-                    out_pt[pos] = (uint32_t)i;
-                    if (out_poly) out_poly[pos] = best;
-                }
-                ++pos;
-                prev = best;
+                pos += tot;
             }
         }
-        __syncthreads();
+        if (!WRITE && lane == 0) counts[sg] = pos;
     }
 }
+
+__global__ void k_emit_zero(unsigned long long *p) { *p = 0ull; }
 
 int probe_emit(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts, uint32_t *out_pt,
                uint32_t *out_poly, int64_t cap, int64_t *n_out)
@@ -400,28 +365,37 @@ int probe_emit(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts, 
     const int64_t n = pts->n;
     *n_out = 0;
     if (n == 0 || cv->view.M == 0) return SPADE_OK;
-    const int64_t nchunks = (n + EMIT_CHUNK - 1) / EMIT_CHUNK;
+    const int64_t nseg = (n + EMIT_SEG - 1) / EMIT_SEG;
     DevBuf &lb = ctx->scratch[S_LOOKBACK];
-    if (ensure(ctx, lb, sizeof(unsigned long long) * (size_t)(nchunks + 2) + 64)) return SPADE_E_NOMEM;
-    unsigned long long *status = (unsigned long long *)lb.p;
-    unsigned long long *total = status + nchunks;
-    unsigned int *ctr = (unsigned int *)(status + nchunks + 1);
-    hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)std::min<int64_t>((nchunks + 2 + 255) / 256, 4096)),
-                       dim3(256), 0, st, nchunks + 2, status);
-    SPADE_HIP(ctx, hipGetLastError());
+    if (ensure(ctx, lb, sizeof(unsigned long long) * 2 * (size_t)(nseg + 1))) return SPADE_E_NOMEM;
+    unsigned long long *counts = (unsigned long long *)lb.p;
+    unsigned long long *offs = counts + (nseg + 1);
     const size_t lds = coarse_bytes_of(cv->view);
     const int per_cu = std::max<int>(1, (int)(LDS_TOTAL / (lds + LDS_RESERVE)));
     const int cus = num_cus(ctx);
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(nchunks, (int64_t)cus * std::min(per_cu, 4)));
-    SPADE_HIP(ctx, hipFuncSetAttribute((const void *)k_emit, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    const int64_t wpb = EMIT_THREADS / 64;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((nseg + wpb - 1) / wpb, (int64_t)cus * std::min(per_cu, 2)));
+    SPADE_HIP(ctx, hipFuncSetAttribute((const void *)k_emit<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    SPADE_HIP(ctx, hipFuncSetAttribute((const void *)k_emit<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[2], st));
-    hipLaunchKernelGGL(k_emit, dim3(grid), dim3(EMIT_THREADS), lds, st, cv->view, n, pts->x, pts->y,
-                       out_pt, out_poly, cap, status, ctr, nchunks, total);
+    hipLaunchKernelGGL(k_emit<false>, dim3(grid), dim3(EMIT_THREADS), lds, st, cv->view, n, pts->x, pts->y, nseg,
+                       counts, nullptr, nullptr, nullptr, (int64_t)0);
+    hipLaunchKernelGGL(k_emit_zero, dim3(1), dim3(1), 0, st, counts + nseg);
     SPADE_HIP(ctx, hipGetLastError());
+    DevBuf &cub = ctx->scratch[S_CUBTMP];
+    size_t tb = 0;
+    SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(nullptr, tb, counts, offs, (int)(nseg + 1), st));
+    if (ensure(ctx, cub, std::max<size_t>(tb, 1))) return SPADE_E_NOMEM;
+    SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(cub.p, tb, counts, offs, (int)(nseg + 1), st));
+    if (cap > 0) {
+        hipLaunchKernelGGL(k_emit<true>, dim3(grid), dim3(EMIT_THREADS), lds, st, cv->view, n, pts->x, pts->y, nseg,
+                           nullptr, offs, out_pt, out_poly, cap);
+        SPADE_HIP(ctx, hipGetLastError());
+    }
     if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[3], st));
     unsigned long long *h = (unsigned long long *)ensure_pinned(ctx, 64);
     if (!h) return set_error(ctx, SPADE_E_NOMEM, "pinned staging allocation failed");
-    SPADE_HIP(ctx, hipMemcpyAsync(h, total, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    SPADE_HIP(ctx, hipMemcpyAsync(h, offs + nseg, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
     SPADE_HIP(ctx, hipStreamSynchronize(st));
     *n_out = (int64_t)h[0];
     if (*n_out > cap) return set_error(ctx, SPADE_E_CAPACITY, "output capacity too small");
