@@ -35,7 +35,7 @@ constexpr int QCAP = 64;                  // boundary queue entries per wavefron
 constexpr int HIST_MAX = 8192;            // polygons counted in LDS
 constexpr int EMIT_THREADS = 1024;
 constexpr int EMIT_SEG = 1024;            // points per wavefront segment
-constexpr int EMIT_GROUP = 4;             // points per lane in flight
+constexpr int EMIT_GROUP = 8;             // points per lane in flight
 constexpr size_t LDS_TOTAL = 160 * 1024;
 constexpr size_t LDS_RESERVE = 2048;      // static LDS of the kernels
 constexpr size_t QUEUE_BYTES = (size_t)(CNT_THREADS / 64) * QCAP * 20;
