@@ -356,6 +356,91 @@ __global__ __launch_bounds__(EMIT_THREADS) void k_emit(CanvasView cv, int64_t n,
     }
 }
 
+// Count pass with the boundary points of a wavefront queued in LDS and
+// tested a full wavefront at a time (as in k_count): counts[s] = output
+// entries of segment s.  The same records and the same test as k_emit<true>,
+// so the counts match what the write pass writes.
+__global__ __launch_bounds__(EMIT_THREADS) void k_emit_count(CanvasView cv, int64_t n, const double *X,
+                                                             const double *Y, int64_t nseg,
+                                                             unsigned long long *counts)
+{
+    static_assert(EMIT_THREADS == CNT_THREADS, "the queue area is sized for CNT_THREADS");
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint16_t *coarse = (uint16_t *)smem;
+    const size_t coarse_bytes = ((size_t)cv.Wc * cv.Hc * (cv.cbyte ? 1 : 2) + 15) & ~(size_t)15;
+    unsigned char *qbase = smem + coarse_bytes;
+    const int wv = threadIdx.x >> 6;
+    double *qx = (double *)(qbase) + wv * QCAP;
+    double *qy = (double *)(qbase) + (EMIT_THREADS / 64) * QCAP + wv * QCAP;
+    uint32_t *qr = (uint32_t *)((double *)(qbase) + 2 * (EMIT_THREADS / 64) * QCAP) + wv * QCAP;
+    load_coarse(cv, coarse, EMIT_THREADS);
+    __syncthreads();
+    const uint32_t lane = lane_id();
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const int64_t nwave = ((int64_t)gridDim.x * EMIT_THREADS) >> 6;
+    for (int64_t sg = ((int64_t)blockIdx.x * EMIT_THREADS + threadIdx.x) >> 6; sg < nseg; sg += nwave) {
+        const int64_t i0 = sg * EMIT_SEG + lane;
+        unsigned long long total = 0;   // wave-uniform
+        uint32_t qn = 0;                // wave-uniform queue length
+        auto drain = [&]() {
+            __builtin_amdgcn_wave_barrier();
+            uint32_t m = 0;
+            if (lane < qn) {
+                const double x = qx[lane], y = qy[lane];
+                uint32_t rec = qr[lane];
+                while (true) {   // two records at a time (the slot after the last exists)
+                    const Cand c0 = cv.cands[rec];
+                    const Cand c1 = cv.cands[rec + 1];
+                    m += cand_inside(cv, c0, x, y) ? 1u : 0u;
+                    if (c0.meta & CAND_LAST) break;
+                    m += cand_inside(cv, c1, x, y) ? 1u : 0u;
+                    if (c1.meta & CAND_LAST) break;
+                    rec += 2;
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) m += __shfl_xor(m, d, 64);
+            total += m;
+            qn = 0;
+        };
+        for (int g = 0; g < EMIT_SEG / 64; g += EMIT_GROUP) {
+            double xs[EMIT_GROUP], ys[EMIT_GROUP];
+#pragma unroll
+            for (int k = 0; k < EMIT_GROUP; ++k) {
+                const int64_t i = i0 + 64 * (g + k);
+                xs[k] = i < n ? __builtin_nontemporal_load(X + i) : NAN;   // NaN: outside
+                ys[k] = i < n ? __builtin_nontemporal_load(Y + i) : NAN;
+            }
+            uint32_t ws[EMIT_GROUP];
+#pragma unroll
+            for (int k = 0; k < EMIT_GROUP; ++k) {
+                const Look lk = look_coarse(cv, coarse, xs[k], ys[k]);
+                ws[k] = lk.full ? ((gu32p)cv.cells)[lk.fidx] : lk.word;
+            }
+#pragma unroll
+            for (int k = 0; k < EMIT_GROUP; ++k) {
+                const uint32_t w = ws[k];
+                const bool bnd = (w & BFLAG) != 0;
+                total += (unsigned long long)__popcll(__ballot(w != 0u && !bnd));
+                const unsigned long long mask = __ballot(bnd);
+                const uint32_t nnew = (uint32_t)__popcll(mask);
+                if (nnew == 0) continue;
+                if (qn + nnew > QCAP) drain();
+                if (bnd) {
+                    const uint32_t slot = qn + (uint32_t)__popcll(mask & below);
+                    qx[slot] = xs[k];
+                    qy[slot] = ys[k];
+                    qr[slot] = w & ~BFLAG;
+                }
+                qn += nnew;
+            }
+        }
+        if (qn) drain();
+        if (lane == 0) counts[sg] = total;
+    }
+}
+
 __global__ void k_emit_zero(unsigned long long *p) { *p = 0ull; }
 
 int probe_emit(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts, uint32_t *out_pt,
@@ -371,15 +456,18 @@ int probe_emit(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts, 
     unsigned long long *counts = (unsigned long long *)lb.p;
     unsigned long long *offs = counts + (nseg + 1);
     const size_t lds = coarse_bytes_of(cv->view);
+    if (lds + QUEUE_BYTES + LDS_RESERVE > LDS_TOTAL)
+        return set_error(ctx, SPADE_E_HIP, "internal: emit probe LDS budget exceeded");
     const int per_cu = std::max<int>(1, (int)(LDS_TOTAL / (lds + LDS_RESERVE)));
     const int cus = num_cus(ctx);
     const int64_t wpb = EMIT_THREADS / 64;
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((nseg + wpb - 1) / wpb, (int64_t)cus * std::min(per_cu, 2)));
-    SPADE_HIP(ctx, hipFuncSetAttribute((const void *)k_emit<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    SPADE_HIP(ctx, hipFuncSetAttribute((const void *)k_emit_count, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)(lds + QUEUE_BYTES)));
     SPADE_HIP(ctx, hipFuncSetAttribute((const void *)k_emit<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[2], st));
-    hipLaunchKernelGGL(k_emit<false>, dim3(grid), dim3(EMIT_THREADS), lds, st, cv->view, n, pts->x, pts->y, nseg,
-                       counts, nullptr, nullptr, nullptr, (int64_t)0);
+    hipLaunchKernelGGL(k_emit_count, dim3(grid), dim3(EMIT_THREADS), lds + QUEUE_BYTES, st, cv->view, n, pts->x,
+                       pts->y, nseg, counts);
     hipLaunchKernelGGL(k_emit_zero, dim3(1), dim3(1), 0, st, counts + nseg);
     SPADE_HIP(ctx, hipGetLastError());
     DevBuf &cub = ctx->scratch[S_CUBTMP];
