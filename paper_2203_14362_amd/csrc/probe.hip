@@ -35,7 +35,8 @@ constexpr int QCAP = 64;                  // boundary queue entries per wavefron
 constexpr int HIST_MAX = 8192;            // polygons counted in LDS
 constexpr int EMIT_THREADS = 1024;
 constexpr int EMIT_SEG = 1024;            // points per wavefront segment
-constexpr int EMIT_GROUP = 8;             // points per lane in flight
+constexpr int EMIT_GROUP = 8;             // points per lane in flight (count pass)
+constexpr int EMIT_WGROUP = 4;            // points per lane in flight (write pass)
 constexpr size_t LDS_TOTAL = 160 * 1024;
 constexpr size_t LDS_RESERVE = 2048;      // static LDS of the kernels
 constexpr size_t QUEUE_BYTES = (size_t)(CNT_THREADS / 64) * QCAP * 20;
@@ -241,98 +242,134 @@ int probe_count(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts,
 
 // ------------------------------------------------------------ ordered emit
 
-// Matches of one point: 0; 1 with its polygon in `lab`; or m > 1 with the
-// first record of its pixel in `lab` (the polygons are listed again, in
-// ascending order, when they are written).
-struct Match {
-    uint32_t cnt, lab;
-};
-
-__device__ __forceinline__ Match match_of(const CanvasView &cv, double x, double y, uint32_t w)
-{
-    Match r{0u, 0u};
-    if (w == 0u) return r;
-    if (!(w & BFLAG)) return Match{1u, w - 1u};
-    uint32_t rec = w & ~BFLAG, first = 0, m = 0;
-    while (true) {
-        const Cand cd = cv.cands[rec];
-        if (cand_inside(cv, cd, x, y)) {
-            if (m == 0) first = cd.poly;
-            ++m;
-        }
-        if (cd.meta & CAND_LAST) break;
-        ++rec;
-    }
-    if (m == 1) return Match{1u, first};
-    if (m > 1) return Match{m, w & ~BFLAG};
-    return r;
-}
-
-// Every wavefront owns segments of EMIT_SEG consecutive points (grid-stride
-// over segments), EMIT_GROUP points per lane in flight at a time.
-// WRITE == false: counts[s] = output entries of segment s.
-// WRITE == true:  the entries of segment s, in point order (and ascending
-//                 polygon order for a point in several polygons), from
-//                 position offs[s] on; positions at or beyond cap are not
-//                 written.  No barriers after the coarse canvas is loaded: a
-//                 wavefront ranks its entries with a shuffle scan.
-template <bool WRITE>
+// Write pass.  Every wavefront owns segments of EMIT_SEG consecutive points
+// (grid-stride over segments), EMIT_WGROUP points per lane in flight at a
+// time.  The boundary points of a group are queued in LDS and tested a full
+// wavefront at a time (as in k_count); each lane then takes the results of
+// its own queued points back with a shuffle.  The entries of segment s are
+// written in point order (ascending polygon order for a point in several
+// polygons) from position offs[s] on; positions at or beyond cap are not
+// written.  No barriers after the coarse canvas is loaded.
 __global__ __launch_bounds__(EMIT_THREADS) void k_emit(CanvasView cv, int64_t n, const double *X,
                                                        const double *Y, int64_t nseg,
-                                                       unsigned long long *counts,
                                                        const unsigned long long *offs, uint32_t *out_pt,
                                                        uint32_t *out_poly, int64_t cap)
 {
+    static_assert(EMIT_THREADS == CNT_THREADS, "the queue area is sized for CNT_THREADS");
     extern __shared__ __align__(16) unsigned char smem[];
     uint16_t *coarse = (uint16_t *)smem;
+    const size_t coarse_bytes = ((size_t)cv.Wc * cv.Hc * (cv.cbyte ? 1 : 2) + 15) & ~(size_t)15;
+    unsigned char *qbase = smem + coarse_bytes;
+    const int wv = threadIdx.x >> 6;
+    double *qx = (double *)(qbase) + wv * QCAP;
+    double *qy = (double *)(qbase) + (EMIT_THREADS / 64) * QCAP + wv * QCAP;
+    uint32_t *qr = (uint32_t *)((double *)(qbase) + 2 * (EMIT_THREADS / 64) * QCAP) + wv * QCAP;
     load_coarse(cv, coarse, EMIT_THREADS);
     __syncthreads();
     const int lane = threadIdx.x & 63;
+    const unsigned long long below = (1ull << lane) - 1ull;
     const int64_t nwave = ((int64_t)gridDim.x * EMIT_THREADS) >> 6;
     for (int64_t sg = ((int64_t)blockIdx.x * EMIT_THREADS + threadIdx.x) >> 6; sg < nseg; sg += nwave) {
         const int64_t i0 = sg * EMIT_SEG + lane;
-        unsigned long long pos = WRITE ? offs[sg] : 0ull;
-        for (int g = 0; g < EMIT_SEG / 64; g += EMIT_GROUP) {
+        unsigned long long pos = offs[sg];
+        for (int g = 0; g < EMIT_SEG / 64; g += EMIT_WGROUP) {
             // the group's points, then their canvas words, level by level
-            double xs[EMIT_GROUP], ys[EMIT_GROUP];
+            double xs[EMIT_WGROUP], ys[EMIT_WGROUP];
 #pragma unroll
-            for (int k = 0; k < EMIT_GROUP; ++k) {
+            for (int k = 0; k < EMIT_WGROUP; ++k) {
                 const int64_t i = i0 + 64 * (g + k);
                 xs[k] = i < n ? __builtin_nontemporal_load(X + i) : NAN;   // NaN: outside
                 ys[k] = i < n ? __builtin_nontemporal_load(Y + i) : NAN;
             }
-            uint32_t ws[EMIT_GROUP];
+            uint32_t ws[EMIT_WGROUP];
 #pragma unroll
-            for (int k = 0; k < EMIT_GROUP; ++k) {
+            for (int k = 0; k < EMIT_WGROUP; ++k) {
                 const Look lk = look_coarse(cv, coarse, xs[k], ys[k]);
                 ws[k] = lk.full ? ((gu32p)cv.cells)[lk.fidx] : lk.word;
             }
+            // matches of every point: interior words at once, boundary
+            // points through the queue
+            uint32_t cnt[EMIT_WGROUP], lab[EMIT_WGROUP], slot[EMIT_WGROUP];
+            uint32_t qn = 0, pend = 0;   // wave-uniform: queue length, rounds queued
+            uint32_t mine = 0;           // rounds whose point of this lane is queued
+            auto drain = [&]() {
+                __builtin_amdgcn_wave_barrier();
+                uint32_t m = 0, first = 0, rec0 = 0;
+                if (lane < (int)qn) {
+                    const double x = qx[lane], y = qy[lane];
+                    rec0 = qr[lane];
+                    uint32_t rec = rec0;
+                    while (true) {   // two records at a time (the slot after the last exists)
+                        const Cand c0 = cv.cands[rec];
+                        const Cand c1 = cv.cands[rec + 1];
+                        if (cand_inside(cv, c0, x, y)) { if (m == 0) first = c0.poly; ++m; }
+                        if (c0.meta & CAND_LAST) break;
+                        if (cand_inside(cv, c1, x, y)) { if (m == 0) first = c1.poly; ++m; }
+                        if (c1.meta & CAND_LAST) break;
+                        rec += 2;
+                    }
+                }
+                __builtin_amdgcn_wave_barrier();
+                const uint32_t rl = m == 1 ? first : (m > 1 ? rec0 : 0u);
 #pragma unroll
-            for (int k = 0; k < EMIT_GROUP; ++k) {
-                const Match mt = match_of(cv, xs[k], ys[k], ws[k]);
+                for (int k = 0; k < EMIT_WGROUP; ++k) {
+                    if (!(pend & (1u << k))) continue;
+                    const uint32_t c = (uint32_t)__shfl((int)m, (int)slot[k], 64);
+                    const uint32_t l = (uint32_t)__shfl((int)rl, (int)slot[k], 64);
+                    if (mine & (1u << k)) { cnt[k] = c; lab[k] = l; }
+                }
+                pend = 0;
+                mine = 0;
+                qn = 0;
+            };
+#pragma unroll
+            for (int k = 0; k < EMIT_WGROUP; ++k) {
+                const uint32_t w = ws[k];
+                const bool bnd = (w & BFLAG) != 0;
+                cnt[k] = (w != 0u && !bnd) ? 1u : 0u;
+                lab[k] = (w != 0u && !bnd) ? w - 1u : 0u;
+                slot[k] = 0;
+                const unsigned long long mask = __ballot(bnd);
+                const uint32_t nnew = (uint32_t)__popcll(mask);
+                if (nnew == 0) continue;
+                if (qn + nnew > QCAP) drain();
+                if (bnd) {
+                    const uint32_t sl = qn + (uint32_t)__popcll(mask & below);
+                    qx[sl] = xs[k];
+                    qy[sl] = ys[k];
+                    qr[sl] = w & ~BFLAG;
+                    slot[k] = sl;
+                    mine |= 1u << k;
+                }
+                qn += nnew;
+                pend |= 1u << k;
+            }
+            if (qn) drain();
+#pragma unroll
+            for (int k = 0; k < EMIT_WGROUP; ++k) {
                 // inclusive scan of the entry counts across the wavefront
-                uint32_t inc = mt.cnt;
+                uint32_t inc = cnt[k];
 #pragma unroll
                 for (int d = 1; d < 64; d <<= 1) {
                     const uint32_t t = __shfl_up(inc, d, 64);
                     if (lane >= d) inc += t;
                 }
                 const uint32_t tot = __shfl(inc, 63, 64);
-                if (WRITE && mt.cnt) {
+                if (cnt[k]) {
                     const uint32_t pt = (uint32_t)(i0 + 64 * (g + k));
-                    unsigned long long p = pos + (inc - mt.cnt);
-                    if (mt.cnt == 1) {
+                    unsigned long long p = pos + (inc - cnt[k]);
+                    if (cnt[k] == 1) {
                         if ((int64_t)p < cap) {
                             out_pt[p] = pt;
-                            if (out_poly) out_poly[p] = mt.lab;
+                            if (out_poly) out_poly[p] = lab[k];
                         }
                     } else {
                         // several polygons: each pass takes the smallest
                         // matching polygon above the last one
                         uint32_t prev = 0;
-                        for (uint32_t t = 0; t < mt.cnt; ++t) {
+                        for (uint32_t t = 0; t < cnt[k]; ++t) {
                             uint32_t best = 0xffffffffu;
-                            uint32_t rec = mt.lab;
+                            uint32_t rec = lab[k];
                             while (true) {
                                 const Cand cd = cv.cands[rec];
                                 if ((t == 0 || cd.poly > prev) && cd.poly < best && cand_inside(cv, cd, xs[k], ys[k]))
@@ -352,13 +389,12 @@ __global__ __launch_bounds__(EMIT_THREADS) void k_emit(CanvasView cv, int64_t n,
                 pos += tot;
             }
         }
-        if (!WRITE && lane == 0) counts[sg] = pos;
     }
 }
 
 // Count pass with the boundary points of a wavefront queued in LDS and
 // tested a full wavefront at a time (as in k_count): counts[s] = output
-// entries of segment s.  The same records and the same test as k_emit<true>,
+// entries of segment s.  The same records and the same test as k_emit,
 // so the counts match what the write pass writes.
 __global__ __launch_bounds__(EMIT_THREADS) void k_emit_count(CanvasView cv, int64_t n, const double *X,
                                                              const double *Y, int64_t nseg,
@@ -464,7 +500,8 @@ int probe_emit(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts, 
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((nseg + wpb - 1) / wpb, (int64_t)cus * std::min(per_cu, 2)));
     SPADE_HIP(ctx, hipFuncSetAttribute((const void *)k_emit_count, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)(lds + QUEUE_BYTES)));
-    SPADE_HIP(ctx, hipFuncSetAttribute((const void *)k_emit<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    SPADE_HIP(ctx, hipFuncSetAttribute((const void *)k_emit, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)(lds + QUEUE_BYTES)));
     if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[2], st));
     hipLaunchKernelGGL(k_emit_count, dim3(grid), dim3(EMIT_THREADS), lds + QUEUE_BYTES, st, cv->view, n, pts->x,
                        pts->y, nseg, counts);
@@ -476,8 +513,8 @@ int probe_emit(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts, 
     if (ensure(ctx, cub, std::max<size_t>(tb, 1))) return SPADE_E_NOMEM;
     SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(cub.p, tb, counts, offs, (int)(nseg + 1), st));
     if (cap > 0) {
-        hipLaunchKernelGGL(k_emit<true>, dim3(grid), dim3(EMIT_THREADS), lds, st, cv->view, n, pts->x, pts->y, nseg,
-                           nullptr, offs, out_pt, out_poly, cap);
+        hipLaunchKernelGGL(k_emit, dim3(grid), dim3(EMIT_THREADS), lds + QUEUE_BYTES, st, cv->view, n, pts->x,
+                           pts->y, nseg, offs, out_pt, out_poly, cap);
         SPADE_HIP(ctx, hipGetLastError());
     }
     if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[3], st));
