@@ -51,6 +51,10 @@ def _load():
     lib.orc_orient_sign.restype = i32
     lib.orc_set_filter.argtypes = [i32]
     lib.orc_set_filter.restype = None
+    lib.orc_set_grid.argtypes = [i32]
+    lib.orc_set_grid.restype = None
+    lib.orc_filter_grid.argtypes = [i64, p, p, p, p]
+    lib.orc_filter_grid.restype = i32
     lib.orc_num_threads.argtypes = []
     lib.orc_num_threads.restype = i32
     lib.orc_inside.argtypes = [d, d, i64, p, p, p, p, i64]
@@ -102,6 +106,18 @@ def orient_sign(ax, ay, bx, by, cx, cy) -> int:
 def set_filter(on: bool) -> None:
     """Test hook: False sends every orientation through the big-integer path."""
     _load().orc_set_filter(1 if on else 0)
+
+
+def set_grid(on: bool) -> None:
+    """Test hook: False replaces the uniform-grid candidate filter by one
+    cell that lists every polygon (bounding-box rejects only)."""
+    _load().orc_set_grid(1 if on else 0)
+
+
+def filter_grid(polys) -> int:
+    """Side of the candidate grid the oracle builds for a polygon set."""
+    P = _Polys(polys)
+    return int(_load().orc_filter_grid(*P.args()))
 
 
 def num_threads() -> int:

@@ -216,6 +216,12 @@ int orc_inside(double px, double py, int64_t n_polys, const int64_t *poly_ring_o
 /* Candidate filter: half-open bounding boxes + uniform grid           */
 /* ------------------------------------------------------------------ */
 
+static int g_use_grid = 1;
+
+/* Test hook: 0 makes every candidate filter a single cell listing every
+ * polygon (bounding-box rejects only), so the grid can be checked against it. */
+void orc_set_grid(int on) { g_use_grid = on; }
+
 typedef struct {
     double *xmin, *xmax, *ymin, *ymax;  /* per polygon */
     int G;                              /* grid is G x G over the union bbox */
@@ -251,7 +257,7 @@ static void filter_build(const orc_polys *P, orc_filter *F)
     }
     /* Grid only pays for many polygons; G == 1 lists every polygon. */
     int G = 1;
-    if (M > 64 && ux0 < ux1 && uy0 < uy1) {
+    if (g_use_grid && M > 64 && ux0 < ux1 && uy0 < uy1) {
         double g = sqrt((double)M);
         G = (int)(g < 1024 ? g : 1024);
         if (G < 1) G = 1;
@@ -299,6 +305,18 @@ static void filter_free(orc_filter *F)
 {
     free(F->xmin); free(F->xmax); free(F->ymin); free(F->ymax);
     free(F->cell_off); free(F->cell_items);
+}
+
+/* Grid side the candidate filter uses for a polygon set (test hook). */
+int orc_filter_grid(int64_t n_polys, const int64_t *poly_ring_off, const int64_t *ring_vtx_off,
+                    const double *vx, const double *vy)
+{
+    orc_polys P = { n_polys, poly_ring_off, ring_vtx_off, vx, vy };
+    orc_filter F;
+    filter_build(&P, &F);
+    int G = F.G;
+    filter_free(&F);
+    return G;
 }
 
 /* Candidate polygons for a point: returns the grid cell, or -1 if the point

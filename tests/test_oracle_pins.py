@@ -275,3 +275,123 @@ def test_area_sanity_statistical():
         sd = math.sqrt(x.size * area * (1 - area))
         assert abs(int(c[k]) - x.size * area) < 5 * sd + 1
     assert abs(info["area_sum"] - 1.0) < 1e-12
+
+
+# ------------------------------------------------ uniform-grid candidate filter
+#
+# With more than 64 polygons the oracle lists candidates from a uniform grid
+# over the polygons' bounding boxes.  Two pins hold it: the tessellation
+# property (each point of the half-open extent in exactly one cell, none
+# outside), which a dropped candidate would break, and agreement with the
+# same oracle with the grid switched off (one cell listing every polygon,
+# bounding-box rejects only, which the lattice closed forms above pin).
+
+def _boundary_points(polys, rng, n_mid=200_000):
+    """Every vertex of the set plus FP64 midpoints of randomly chosen edges:
+    points on or within an ulp of the shared boundaries."""
+    vx, vy = polys["vx"], polys["vy"]
+    rvo = polys["ring_vtx_off"]
+    nxt = np.arange(vx.size) + 1
+    nxt[rvo[1:] - 1] = rvo[:-1]          # last vertex of a ring wraps to its first
+    e = rng.integers(0, vx.size, min(n_mid, vx.size))
+    mx = 0.5 * (vx[e] + vx[nxt[e]])
+    my = 0.5 * (vy[e] + vy[nxt[e]])
+    return np.concatenate([vx, mx]), np.concatenate([vy, my])
+
+
+def _check_tessellation_once(x, y, polys, L):
+    nm = oracle.point_nmatch(x, y, polys)
+    inside_extent = (x >= 0) & (x < L) & (y >= 0) & (y < L)
+    assert np.array_equal(nm, inside_extent.astype(np.int32))
+    counts = oracle.join_count(x, y, polys)
+    assert int(counts.sum()) == int(inside_extent.sum())
+
+
+def test_grid_filter_tessellation_c2_cells():
+    """260 Voronoi-jitter cells (50-500 vertices) over the 60 km extent: the
+    grid filter is active and every point, including points on shared
+    vertices and edge midpoints, lies in exactly one cell."""
+    L = gen.EXTENT_M
+    polys = gen.voronoi_jitter(260, 50, 500, seed=2, L=L)
+    assert oracle.filter_grid(polys) > 1
+    rng = np.random.default_rng(21)
+    bx, by = _boundary_points(polys, rng)
+    mx, my = gen.mixture_points(300_000, seed=2, L=L)
+    x = np.concatenate([bx, mx, rng.uniform(0, L, 50_000)])
+    y = np.concatenate([by, my, rng.uniform(0, L, 50_000)])
+    _check_tessellation_once(x, y, polys, L)
+
+
+@pytest.fixture(scope="module")
+def census_40k():
+    return gen.census_cells(40_000, 4, 40, seed=9, data_seed=4, L=gen.EXTENT_M)
+
+
+def test_grid_filter_tessellation_40k_census_cells(census_40k):
+    """40,000 mixture-seeded census-like cells (4-40 vertices): every point
+    (vertices, edge midpoints, clustered and uniform points) in exactly one."""
+    L = gen.EXTENT_M
+    polys = census_40k
+    assert oracle.filter_grid(polys) == 200
+    rng = np.random.default_rng(22)
+    bx, by = _boundary_points(polys, rng)
+    mx, my = gen.mixture_points(300_000, seed=4, L=L)
+    x = np.concatenate([bx, mx, rng.uniform(0, L, 100_000)])
+    y = np.concatenate([by, my, rng.uniform(0, L, 100_000)])
+    _check_tessellation_once(x, y, polys, L)
+
+
+def _filtered_vs_unfiltered(x, y, polys):
+    try:
+        oracle.set_grid(True)
+        a_counts = oracle.join_count(x, y, polys)
+        a_nm = oracle.point_nmatch(x, y, polys)
+        a_pt, a_pg = oracle.join_pairs(x, y, polys)
+        oracle.set_grid(False)
+        assert oracle.filter_grid(polys) == 1
+        b_counts = oracle.join_count(x, y, polys)
+        b_nm = oracle.point_nmatch(x, y, polys)
+        b_pt, b_pg = oracle.join_pairs(x, y, polys)
+    finally:
+        oracle.set_grid(True)
+    assert np.array_equal(a_counts, b_counts)
+    assert np.array_equal(a_nm, b_nm)
+    assert np.array_equal(a_pt, b_pt) and np.array_equal(a_pg, b_pg)
+    return a_counts
+
+
+def test_grid_filter_matches_unfiltered_overlapping_stars():
+    """300 overlapping stars (pairs of points with several polygons): the grid
+    lists every candidate the plain bounding-box scan finds."""
+    L = gen.EXTENT_M
+    stars, _ = gen.query_stars(300, 8, 400, seed=23, L=L, area=(1e-4, 2e-2), data_seed=2)
+    assert oracle.filter_grid(stars) > 1
+    x, y = gen.mixture_points(20_000, seed=2, L=L)
+    rng = np.random.default_rng(24)
+    bx, by = _boundary_points(stars, rng, n_mid=5_000)
+    counts = _filtered_vs_unfiltered(np.concatenate([x, bx]), np.concatenate([y, by]), stars)
+    assert counts.sum() > x.size        # overlaps: points with several polygons
+
+
+def test_grid_filter_matches_unfiltered_40k(census_40k):
+    L = gen.EXTENT_M
+    x, y = gen.mixture_points(5_000, seed=4, L=L)
+    rng = np.random.default_rng(25)
+    bx, by = _boundary_points(census_40k, rng, n_mid=2_000)
+    _filtered_vs_unfiltered(np.concatenate([x, bx[:3000]]), np.concatenate([y, by[:3000]]), census_40k)
+
+
+def test_offset_frame_tessellation():
+    """The Web-Mercator-like offset frame keeps the tessellation exact: every
+    kept point in exactly one cell (rounded vertices, shared bit-identically)."""
+    L = gen.EXTENT_M
+    polys = gen.voronoi_jitter(260, 50, 500, seed=2, L=L)
+    x, y = gen.mixture_points(200_000, seed=2, L=L)
+    rng = np.random.default_rng(26)
+    bx, by = _boundary_points(polys, rng, n_mid=50_000)
+    ox, oy, opolys = gen.offset_frame(np.concatenate([x, bx]), np.concatenate([y, by]), polys)
+    o = gen.WEB_MERCATOR_ORIGIN
+    nm = oracle.point_nmatch(ox, oy, opolys)
+    assert np.array_equal(nm, np.ones(ox.size, np.int32))
+    assert ox.size > 200_000
+    assert np.all(ox >= o[0]) and np.all(ox < o[0] + L)

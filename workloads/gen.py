@@ -38,6 +38,7 @@ __all__ = [
     "rng_for", "uniform_points", "mixture_params", "mixture_points",
     "voronoi_jitter", "star_polygon", "lattice_points", "rect_grid",
     "right_triangle", "poisson_arrivals", "polys_from_rings", "concat_polys",
+    "census_cells", "offset_frame", "WEB_MERCATOR_ORIGIN",
     "poly_vertex_counts", "EXTENT_M",
 ]
 
@@ -244,6 +245,38 @@ def query_stars(nq: int, vmin: int, vmax: int, seed: int = 6, L: float = EXTENT_
         r = R * (1.0 + noise * rng.uniform(-1.0, 1.0, size=V[q]))
         rings.append([np.stack([cx[q] + r * np.cos(th), cy[q] + r * np.sin(th)], axis=1)])
     return polys_from_rings(rings), np.arange(nq + 1, dtype=np.int64)
+
+
+def census_cells(M: int, vmin: int, vmax: int, seed: int, data_seed: int, L: float = EXTENT_M,
+                 return_info: bool = False):
+    """Census-block-like tessellation: a Voronoi-jitter tessellation whose
+    cell seeds are drawn from the taxi-like mixture of ``data_seed``, so the
+    cells are small where the points are dense."""
+    sx, sy = _mixture_chunk(mixture_params(data_seed, L), M, rng_for(seed, 9))
+    return voronoi_jitter(M, vmin, vmax, seed, L, seed_points=np.stack([sx, sy], 1), return_info=return_info)
+
+
+WEB_MERCATOR_ORIGIN = (-8.27e6, 4.94e6)   # metres; a New-York-like offset frame
+
+
+def offset_frame(x, y, polys, L: float = EXTENT_M, origin=WEB_MERCATOR_ORIGIN):
+    """Points and polygons of a [0, L)^2 workload moved to a large offset
+    frame (coordinates of Web-Mercator size), each coordinate rounded once.
+
+    Shared vertices stay bit-identical (the same addition of the same
+    values), and the extent sides move to exactly representable values, so a
+    tessellation of the extent stays an exact tiling.  Points whose rounded
+    coordinates leave the half-open shifted extent are dropped, so every
+    remaining point lies in exactly one cell of such a tessellation.
+    """
+    ox, oy = float(origin[0]), float(origin[1])
+    xs = np.asarray(x, dtype=np.float64) + ox
+    ys = np.asarray(y, dtype=np.float64) + oy
+    keep = (xs >= ox) & (xs < ox + L) & (ys >= oy) & (ys < oy + L)
+    out = dict(polys)
+    out["vx"] = np.asarray(polys["vx"], dtype=np.float64) + ox
+    out["vy"] = np.asarray(polys["vy"], dtype=np.float64) + oy
+    return np.ascontiguousarray(xs[keep]), np.ascontiguousarray(ys[keep]), out
 
 
 # ------------------------------------------------- Voronoi jitter tessellation
