@@ -133,6 +133,17 @@ int spade_ctx_set_graphs(spade_ctx *ctx, int on);
 /* Graphs captured and replays launched on ctx so far (either may be NULL). */
 int spade_ctx_graph_stats(const spade_ctx *ctx, int64_t *captures, int64_t *replays);
 
+/* Plain-call canvas builds on ctx so far, and how many of them were redone
+ * because the first row pass ran out of record capacity (either may be
+ * NULL).  A redone build is probed again before the call returns. */
+int spade_ctx_build_stats(const spade_ctx *ctx, int64_t *builds, int64_t *rebuilds);
+
+/* Device memory facts for admission control (any pointer may be NULL):
+ * free and total bytes of ctx's device (hipMemGetInfo) and the bytes of
+ * device scratch that ctx itself holds for reuse (plain-call canvas and
+ * scratch slots; tables and canvases are reported by their own info calls). */
+int spade_mem_info(spade_ctx *ctx, size_t *free_bytes, size_t *total_bytes, size_t *ctx_bytes);
+
 /* Phase timing (tracing aid).  on != 0 makes later query calls record HIP
  * events on ctx's stream around the rasterisation and around the probe
  * kernel; spade_ctx_last_timing waits for the last probe and returns both
@@ -157,8 +168,8 @@ int spade_select(spade_ctx *ctx, const spade_points *pts, const spade_polys *pol
  * cx, cy and r must be finite and r >= 0 (else SPADE_E_INVALID); points with
  * a non-finite coordinate are outside.  out_ids [cap] device buffer; *n_out
  * (host, may be NULL) receives the number of selected points.  If it exceeds
- * cap, nothing is written and SPADE_E_CAPACITY is returned (two-step Map,
- * Sec. 5.1). */
+ * cap, the first cap ids are written and SPADE_E_CAPACITY is returned
+ * (two-step Map, Sec. 5.1). */
 int spade_select_disk(spade_ctx *ctx, const spade_points *pts, double cx, double cy, double r,
                       uint32_t *out_ids, int64_t cap, int64_t *n_out);
 
@@ -205,6 +216,7 @@ int spade_canvas_join_count_async(spade_ctx *ctx, const spade_canvas *cv,
 int spade_canvas_join_pairs(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts,
                             uint32_t *out_pt, uint32_t *out_poly, int64_t cap, int64_t *n_out);
 
+
 /* ---- Resident point tables and query batches.  Many queries share one
  * pass over a resident, spatially clustered point table (the data stays in
  * HBM; each table chunk is read once for all queries whose bounding box
@@ -246,22 +258,74 @@ int spade_batch_rebuild(spade_ctx *ctx, const spade_polys *polys, int32_t nq, co
  * polygon), over a table: the ids of the table points inside, ascending
  * within each query, queries one after another in out_ids [cap] (device).
  * out_off [nq + 1] (host) receives each query's start; out_off[nq] is the
- * total.  If the total exceeds cap, nothing is written to out_ids and
- * SPADE_E_CAPACITY is returned with out_off filled.  Evaluated with the
- * paper's two-step Map (Sec. 5.1): a count pass, then a write pass. */
+ * total.  If the total exceeds cap, the first cap ids of that order are
+ * written and SPADE_E_CAPACITY is returned with out_off filled.  Evaluated
+ * with the paper's two-step Map (Sec. 5.1): a count pass, then a write pass. */
 int spade_batch_select(spade_ctx *ctx, const spade_canvas *set, const spade_table *t,
                        uint32_t *out_ids, int64_t cap, int64_t *out_off);
 
 /* Join-count for every query of a batch over a table: out_counts [n_polys
  * of the batch] (device) receives, for each polygon of the batch polygon
- * set, the number of table points inside it. */
+ * set, the number of table points inside it (for a layered set: indexed by
+ * the caller's polygon ids). */
 int spade_batch_join_count(spade_ctx *ctx, const spade_canvas *set, const spade_table *t,
                            uint64_t *out_counts);
+
+/* Join pairs over a table for every polygon of a canvas set (a batch from
+ * spade_batch_build, or a layered set from spade_layered_build): every pair
+ * (point id, polygon id) with the table point inside the polygon, ascending
+ * by point id then polygon id, as two device arrays of capacity cap (the
+ * paper's polygon-point join, Sec. 5.2 "Spatial Joins" case (1)).  Point ids
+ * are the table's input positions; polygon ids are positions in the polygon
+ * set the canvas set was built from (for a batch, the concatenated set).
+ * *n_out (host) receives the number of pairs; beyond cap the first cap
+ * pairs are written and SPADE_E_CAPACITY is returned. */
+int spade_batch_join_pairs(spade_ctx *ctx, const spade_canvas *set, const spade_table *t, uint32_t *out_pt,
+                           uint32_t *out_poly, int64_t cap, int64_t *n_out);
+
+/* ---- Layer index (Sec. 4.3 "Layer Index", created as in Sec. 5.5).  The
+ * polygons are split into layers such that no two polygons of a layer cover
+ * the same pixel centre of a res x res grid (aspect kept; res 0 = 1024, at
+ * most 4096) over the set's bounding box.  Built by the paper's iteration:
+ * each pixel keeps the highest id of the polygons not yet placed (multiway
+ * blend), every such polygon whose pixels all kept its own id joins the
+ * next layer (blend + mask), the others wait.  Polygons covering no pixel
+ * centre join layer 0.  A tessellation is one layer.  Layers change only how
+ * fast a join runs, never its result. */
+
+/* out_layer [n_polys] (device int32) receives each polygon's layer, 0-based;
+ * *n_layers (host) the number of layers. */
+int spade_layer_index(spade_ctx *ctx, const spade_polys *polys, int32_t res, int32_t *out_layer,
+                      int32_t *n_layers);
+
+/* Rasterise each layer of `polys` into its own canvas of a new canvas set
+ * (Sec. 5.2, "Spatial Joins" case (1): one selection per layer).  The set
+ * is queried with spade_batch_join_count and spade_batch_join_pairs over a
+ * table, which report the caller's polygon ids.  *n_layers may be NULL.
+ * The polygon arrays may be freed after the call returns. */
+int spade_layered_build(spade_ctx *ctx, const spade_polys *polys, int32_t res, spade_canvas **out,
+                        int32_t *n_layers);
 
 /* Canvas sizing for later builds when no fixed size is set: about `ppv`
  * pixels per polygon vertex, between 64 x 64 and 4096 x 4096 pixels per
  * canvas (default 256).  The autotuner sets this. */
 int spade_ctx_set_pixels_per_vertex(spade_ctx *ctx, double ppv);
+
+/* Where the join-count runs the exact tests of points in boundary pixels
+ * (default: inline).  deferred != 0: the point stream queues them in
+ * device memory (20 bytes per point, room for up to 2^27 points; longer
+ * streams are probed in passes of that many) and a second kernel tests them
+ * after the stream; 0: each wavefront tests its queued boundary points
+ * itself whenever 64 have gathered (default).  Results are identical either
+ * way. */
+int spade_ctx_set_exact_mode(spade_ctx *ctx, int deferred);
+
+/* Measurement aid: reads both coordinates of every point once and adds
+ * their sum to *out_sum (device double, not cleared), with the count
+ * probe's launch shape (shape 0: one 1024-thread workgroup per compute
+ * unit, 8 points per thread in flight) or with 256-thread workgroups, eight
+ * per compute unit (shape 1).  Timed by the phase timer as a probe. */
+int spade_stream_read(spade_ctx *ctx, const spade_points *pts, int shape, double *out_sum);
 
 /* Device-side exact predicate, exposed for testing the arithmetic in
  * isolation: for n triples (a, b, c) stored as 6 device arrays, writes

@@ -229,20 +229,28 @@ struct SetArgs {
     const Cand *cands;
     const Edge *ledges;
     const double2 *pspan;
+    const uint32_t *pid;          // layered set: caller's id of set polygon g (else g itself)
 };
+
+__device__ __forceinline__ uint32_t caller_id(const SetArgs &S, int64_t g)
+{
+    return S.pid ? S.pid[g] : (uint32_t)g;
+}
 
 // ------------------------------------------------------------ batch select
 
-// Pass 1 (EMIT = false): matches per pair into pcount.  Pass 2 (EMIT): the
-// keys (query << 32 | point id) of the matching points from pbase[pair] on,
-// in an order the key sort that follows makes ascending.
+// Pass 1 (EMIT = false): matches per pair into pcount.  Pass 2 (EMIT): for
+// the pairs of queries q0 <= q < q1 only, the keys (query << 32 | point id)
+// of the matching points from pbase[pair] - kbase on, in an order the key
+// sort that follows makes ascending.
 template <bool EMIT>
 __global__ __launch_bounds__(BT_THREADS) void k_batch_select(SetArgs S, int64_t nfin, int64_t nchunk,
                                                              const double *X, const double *Y,
                                                              const uint32_t *ids, const unsigned int *cbase,
                                                              const uint32_t *plist, const uint32_t *pq,
                                                              uint32_t *pcount, const unsigned long long *pbase,
-                                                             unsigned long long *out)
+                                                             unsigned long long *out, uint32_t q0, uint32_t q1,
+                                                             unsigned long long kbase)
 {
     __shared__ uint32_t wsum[BT_THREADS / 64];
     for (int64_t c = blockIdx.x; c < nchunk; c += gridDim.x) {
@@ -257,6 +265,7 @@ __global__ __launch_bounds__(BT_THREADS) void k_batch_select(SetArgs S, int64_t 
         for (uint32_t t = cbase[c]; t < cbase[c + 1]; ++t) {
             const uint32_t p = plist[t];
             const uint32_t qy = pq[p];
+            if (EMIT && (qy < q0 || qy >= q1)) continue;   // uniform over the workgroup
             const CanvasDesc d = S.cds[qy];
             const CanvasView v = set_view(d, S.cells, S.coarse, S.cands, S.ledges, S.pspan);
             uint32_t hit = 0;
@@ -298,13 +307,119 @@ __global__ __launch_bounds__(BT_THREADS) void k_batch_select(SetArgs S, int64_t 
             if (!EMIT) {
                 if (threadIdx.x == 0) pcount[p] = tot;
             } else if (hit) {
-                unsigned long long pos = pbase[p] + pre + inc - cnt;
+                unsigned long long pos = pbase[p] - kbase + pre + inc - cnt;
 #pragma unroll
                 for (int u = 0; u < BT_PER; ++u)
                     if (hit & (1u << u))
                         out[pos++] = ((unsigned long long)qy << 32) | ids[b + (int64_t)u * BT_THREADS + threadIdx.x];
             }
         }
+    }
+}
+
+// ------------------------------------------------------------ batch join pairs
+
+constexpr int PAIR_RANGES = 64;   // point-id ranges the pairs are counted in
+
+// Pairs (point id, polygon id) of the table with a canvas set.  COUNT:
+// matches per range of point ids (id >> rshift) into rcount.  Otherwise the
+// keys (id << pbits | polygon) of the matches with id >> rshift in
+// [r0, r1) are appended to keys (one reservation per workgroup and pair;
+// their order is fixed by the sort that follows).
+template <bool COUNT>
+__global__ __launch_bounds__(BT_THREADS) void k_batch_pairs(SetArgs S, int64_t nfin, int64_t nchunk,
+                                                            const double *X, const double *Y, const uint32_t *ids,
+                                                            const unsigned int *cbase, const uint32_t *plist,
+                                                            const uint32_t *pq, int rshift, int pbits,
+                                                            unsigned long long *rcount, uint32_t r0, uint32_t r1,
+                                                            unsigned long long *cursor, unsigned long long *keys)
+{
+    __shared__ unsigned long long s_cnt[PAIR_RANGES];
+    __shared__ uint32_t wsum[BT_THREADS / 64];
+    __shared__ unsigned long long s_at;
+    if (COUNT)
+        for (int k = threadIdx.x; k < PAIR_RANGES; k += BT_THREADS) s_cnt[k] = 0ull;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int64_t c = blockIdx.x; c < nchunk; c += gridDim.x) {
+        const int64_t b = c * CHUNK;
+        double xs[BT_PER], ys[BT_PER];
+        uint32_t pid[BT_PER];
+#pragma unroll
+        for (int u = 0; u < BT_PER; ++u) {
+            const int64_t i = b + (int64_t)u * BT_THREADS + threadIdx.x;
+            xs[u] = i < nfin ? X[i] : NAN;
+            ys[u] = i < nfin ? Y[i] : NAN;
+            pid[u] = i < nfin ? ids[i] : 0u;
+        }
+        for (uint32_t t = cbase[c]; t < cbase[c + 1]; ++t) {
+            const uint32_t p = plist[t];
+            const CanvasDesc d = S.cds[pq[p]];
+            const CanvasView v = set_view(d, S.cells, S.coarse, S.cands, S.ledges, S.pspan);
+            uint32_t mine = 0;
+            // the matches of this thread's points, in two sweeps: count, write
+            auto sweep = [&](auto &&emit) {
+#pragma unroll
+                for (int u = 0; u < BT_PER; ++u) {
+                    if (!COUNT) {
+                        const uint32_t r = pid[u] >> rshift;
+                        if (r < r0 || r >= r1) continue;
+                    }
+                    const uint32_t w = lookup(v, v.coarse, xs[u], ys[u]);
+                    if (w == 0u) continue;
+                    if (!(w & BFLAG)) { emit(u, w - 1u); continue; }
+                    uint32_t rec = w & ~BFLAG;
+                    while (true) {
+                        const Cand cd = v.cands[rec];
+                        if (cand_inside(v, cd, xs[u], ys[u])) emit(u, cd.poly);
+                        if (cd.meta & CAND_LAST) break;
+                        ++rec;
+                    }
+                }
+            };
+            if (COUNT) {
+                sweep([&](int u, uint32_t) { atomicAdd(&s_cnt[pid[u] >> rshift], 1ull); });
+                continue;
+            }
+            sweep([&](int, uint32_t) { ++mine; });
+            // workgroup-wide exclusive scan of the match counts, one reservation
+            uint32_t inc = mine;
+#pragma unroll
+            for (int dd = 1; dd < 64; dd <<= 1) {
+                const uint32_t tt = __shfl_up(inc, dd, 64);
+                if (lane >= dd) inc += tt;
+            }
+            if (lane == 63) wsum[wv] = inc;
+            __syncthreads();
+            uint32_t pre = 0, tot = 0;
+#pragma unroll
+            for (int q = 0; q < BT_THREADS / 64; ++q) {
+                if (q < wv) pre += wsum[q];
+                tot += wsum[q];
+            }
+            if (threadIdx.x == 0) s_at = tot ? atomicAdd(cursor, (unsigned long long)tot) : 0ull;
+            __syncthreads();
+            unsigned long long pos = s_at + pre + inc - mine;
+            sweep([&](int u, uint32_t label) {
+                keys[pos++] = ((unsigned long long)pid[u] << pbits) | caller_id(S, d.poly_base + label);
+            });
+            __syncthreads();
+        }
+    }
+    if (COUNT) {
+        __syncthreads();
+        for (int k = threadIdx.x; k < PAIR_RANGES; k += BT_THREADS)
+            if (s_cnt[k]) atomicAdd(&rcount[k], s_cnt[k]);
+    }
+}
+
+__global__ void k_split_pairs(int64_t n, const unsigned long long *keys, int pbits, uint32_t *pt, uint32_t *pg)
+{
+    const unsigned long long m = (1ull << pbits) - 1ull;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const unsigned long long k = keys[i];
+        pt[i] = (uint32_t)(k >> pbits);
+        pg[i] = (uint32_t)(k & m);
     }
 }
 
@@ -347,7 +462,7 @@ __global__ __launch_bounds__(BT_THREADS) void k_batch_count(SetArgs S, int64_t n
             const CanvasDesc d = S.cds[pq[p]];
             const CanvasView v = set_view(d, S.cells, S.coarse, S.cands, S.ledges, S.pspan);
             auto add = [&](uint32_t label) {
-                const unsigned long long key = (unsigned long long)(d.poly_base + label) + 1ull;
+                const unsigned long long key = (unsigned long long)caller_id(S, d.poly_base + label) + 1ull;
                 uint32_t h = (uint32_t)(key * 0x9E3779B97F4A7C15ull >> 55) & (HSLOTS - 1);
                 for (int probe = 0; probe < 8; ++probe, h = (h + 1) & (HSLOTS - 1)) {
                     unsigned long long cur = hkey[h];
@@ -480,6 +595,7 @@ static SetArgs set_args(const spade_canvas *set)
     S.cands = (const Cand *)set->cands.p;
     S.ledges = (const Edge *)set->ledges.p;
     S.pspan = (const double2 *)set->pspan.p;
+    S.pid = set->layered ? (const uint32_t *)set->pid.p : nullptr;
     return S;
 }
 
@@ -634,6 +750,8 @@ int spade_batch_rebuild(spade_ctx *ctx, const spade_polys *polys, int32_t nq, co
     if (rc) return rc;
     if (set->device != ctx->device) return set_error(ctx, SPADE_E_INVALID, "the canvas set lives on another device");
     if (set == ctx->plain) return set_error(ctx, SPADE_E_INVALID, "not a caller-owned canvas set");
+    set->layered = false;
+    set->n_layers = 0;
     return build_set(ctx, polys, nq, qbound, set);
 }
 
@@ -644,6 +762,7 @@ int spade_batch_select(spade_ctx *ctx, const spade_canvas *set, const spade_tabl
     ctx->err.clear();
     if (hipSetDevice(ctx->device) != hipSuccess) return set_error(ctx, SPADE_E_HIP, "hipSetDevice failed");
     const int nq = set->nc;
+    if (set->layered) return set_error(ctx, SPADE_E_INVALID, "a layered set is queried with join calls");
     for (int q = 0; q < nq; ++q)
         if (set->descs[q].M != 1) return set_error(ctx, SPADE_E_INVALID, "batch selection needs exactly one polygon per query");
     if (cap < 0 || (cap > 0 && !out_ids)) return set_error(ctx, SPADE_E_INVALID, "bad output buffer");
@@ -668,7 +787,7 @@ int spade_batch_select(spade_ctx *ctx, const spade_canvas *set, const spade_tabl
     if (np > 0) {
         hipLaunchKernelGGL(k_batch_select<false>, dim3(grid), dim3(BT_THREADS), 0, st, S, t->nfin, t->nchunk,
                            (const double *)t->x.p, (const double *)t->y.p, (const uint32_t *)t->ids.p, P.cbase,
-                           P.plist, P.pq, pcount, nullptr, nullptr);
+                           P.plist, P.pq, pcount, nullptr, nullptr, 0u, (uint32_t)nq, 0ull);
         SPADE_HIP(ctx, hipGetLastError());
     }
     DevBuf &cub = ctx->scratch[S_CUBTMP];
@@ -685,48 +804,60 @@ int spade_batch_select(spade_ctx *ctx, const spade_canvas *set, const spade_tabl
     SPADE_HIP(ctx, hipMemcpyAsync(h, qoff, sizeof(unsigned long long) * (size_t)(nq + 1), hipMemcpyDeviceToHost, st));
     SPADE_HIP(ctx, hipStreamSynchronize(st));
     for (int q = 0; q <= nq; ++q) out_off[q] = (int64_t)h[q];
-    if ((int64_t)total > cap) return set_error(ctx, SPADE_E_CAPACITY, "output capacity too small");
-    if (total == 0) {
+    // a buffer that is too small still receives the first cap ids in the
+    // canonical order (two-step Map); the call then reports the shortfall
+    const bool short_cap = (int64_t)total > cap;
+    if (total == 0 || cap == 0) {
+        if (short_cap) return set_error(ctx, SPADE_E_CAPACITY, "output capacity too small");
         if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[3], st));
         return SPADE_OK;
     }
-    DevBuf &bo2 = ctx->scratch[S_ENTF];
-    if (ensure(ctx, bo, 8 * (size_t)total) || ensure(ctx, bo2, 8 * (size_t)total)) return SPADE_E_NOMEM;
-    hipLaunchKernelGGL(k_batch_select<true>, dim3(grid), dim3(BT_THREADS), 0, st, S, t->nfin, t->nchunk,
-                       (const double *)t->x.p, (const double *)t->y.p, (const uint32_t *)t->ids.p, P.cbase, P.plist,
-                       P.pq, nullptr, (const unsigned long long *)pbase, (unsigned long long *)bo.p);
-    SPADE_HIP(ctx, hipGetLastError());
-    // Radix sorts of (query, id) keys order the ids inside every query (a
-    // per-segment sort would give a whole query to one workgroup).  The keys
-    // are already grouped by query, so runs of consecutive queries are sorted
-    // separately: at most 2^30 keys per sort, or one larger query alone.
+    // Runs of consecutive queries with at most 2^30 keys (or one larger
+    // query alone) are written and sorted one at a time, so the key buffers
+    // stay bounded whatever the batch's total; runs that start at or beyond
+    // cap are not evaluated.  A radix sort of (query, id) keys orders each
+    // query's ids (a per-segment sort would give a whole query to one
+    // workgroup).
     const int kbits = 32 + std::max(1, bits_of((uint64_t)(nq - 1)));
     const int64_t GROUP = (int64_t)1 << 30;
-    std::vector<std::pair<int64_t, int64_t>> groups;
+    struct Run { int q0, q1; int64_t k0, k1; };
+    std::vector<Run> runs;
     {
-        int64_t gb = 0;
+        int qb = 0;
         for (int q = 0; q < nq; ++q)
-            if (out_off[q + 1] - gb > GROUP && out_off[q] > gb) {
-                groups.push_back({gb, out_off[q]});
-                gb = out_off[q];
+            if (out_off[q + 1] - out_off[qb] > GROUP && q > qb) {
+                runs.push_back({qb, q, out_off[qb], out_off[q]});
+                qb = q;
             }
-        if ((int64_t)total > gb) groups.push_back({gb, (int64_t)total});
+        if (out_off[nq] > out_off[qb]) runs.push_back({qb, nq, out_off[qb], out_off[nq]});
     }
     int64_t gmax = 0;
-    for (const auto &g : groups) gmax = std::max(gmax, g.second - g.first);
+    for (const auto &r : runs)
+        if (r.k0 < cap) gmax = std::max(gmax, r.k1 - r.k0);
+    DevBuf &bo2 = ctx->scratch[S_ENTF];
+    if (ensure(ctx, bo, 8 * (size_t)gmax) || ensure(ctx, bo2, 8 * (size_t)gmax)) return SPADE_E_NOMEM;
     tb = 0;
     SPADE_HIP(ctx, hipcub::DeviceRadixSort::SortKeys(nullptr, tb, (const unsigned long long *)bo.p,
                                                      (unsigned long long *)bo2.p, (int)gmax, 0, kbits, st));
     if (ensure(ctx, cub, tb)) return SPADE_E_NOMEM;
-    for (const auto &g : groups)
-        SPADE_HIP(ctx, hipcub::DeviceRadixSort::SortKeys(cub.p, tb, (const unsigned long long *)bo.p + g.first,
-                                                         (unsigned long long *)bo2.p + g.first,
-                                                         (int)(g.second - g.first), 0, kbits, st));
-    hipLaunchKernelGGL(k_low32, dim3(grid_of((int64_t)total)), dim3(256), 0, st, (int64_t)total,
-                       (const unsigned long long *)bo2.p, out_ids);
-    SPADE_HIP(ctx, hipGetLastError());
+    for (const auto &r : runs) {
+        if (r.k0 >= cap) break;
+        hipLaunchKernelGGL(k_batch_select<true>, dim3(grid), dim3(BT_THREADS), 0, st, S, t->nfin, t->nchunk,
+                           (const double *)t->x.p, (const double *)t->y.p, (const uint32_t *)t->ids.p, P.cbase,
+                           P.plist, P.pq, nullptr, (const unsigned long long *)pbase, (unsigned long long *)bo.p,
+                           (uint32_t)r.q0, (uint32_t)r.q1, (unsigned long long)r.k0);
+        SPADE_HIP(ctx, hipGetLastError());
+        SPADE_HIP(ctx, hipcub::DeviceRadixSort::SortKeys(cub.p, tb, (const unsigned long long *)bo.p,
+                                                         (unsigned long long *)bo2.p, (int)(r.k1 - r.k0), 0, kbits,
+                                                         st));
+        const int64_t nwrite = std::min<int64_t>(r.k1, cap) - r.k0;
+        hipLaunchKernelGGL(k_low32, dim3(grid_of(nwrite)), dim3(256), 0, st, nwrite,
+                           (const unsigned long long *)bo2.p, out_ids + r.k0);
+        SPADE_HIP(ctx, hipGetLastError());
+    }
     if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[3], st));
     SPADE_HIP(ctx, hipStreamSynchronize(st));
+    if (short_cap) return set_error(ctx, SPADE_E_CAPACITY, "output capacity too small");
     return SPADE_OK;
 }
 
@@ -758,6 +889,103 @@ int spade_batch_join_count(spade_ctx *ctx, const spade_canvas *set, const spade_
     }
     if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[3], st));
     SPADE_HIP(ctx, hipStreamSynchronize(st));
+    return SPADE_OK;
+}
+
+int spade_batch_join_pairs(spade_ctx *ctx, const spade_canvas *set, const spade_table *t, uint32_t *out_pt,
+                           uint32_t *out_poly, int64_t cap, int64_t *n_out)
+{
+    if (!ctx || !set || !t || !n_out) return ctx ? set_error(ctx, SPADE_E_INVALID, "NULL argument") : SPADE_E_INVALID;
+    ctx->err.clear();
+    *n_out = 0;
+    if (hipSetDevice(ctx->device) != hipSuccess) return set_error(ctx, SPADE_E_HIP, "hipSetDevice failed");
+    if (cap < 0 || (cap > 0 && (!out_pt || !out_poly))) return set_error(ctx, SPADE_E_INVALID, "bad output buffers");
+    int64_t M = 0;
+    for (const auto &d : set->descs) M += d.M;
+    hipStream_t st = ctx->stream;
+    ctx->timed_raster = false;
+    if (M == 0 || t->nchunk == 0) return SPADE_OK;
+    Pairs P;
+    int rc = make_pairs(ctx, set, t, P);
+    if (rc) return rc;
+    const SetArgs S = set_args(set);
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(t->nchunk, (int64_t)num_cus_of(ctx->device) * 8));
+    const int pbits = std::max(1, bits_of((uint64_t)(M - 1)));
+    const int idbits = std::max(1, bits_of((uint64_t)(t->n - 1)));
+    if (pbits + idbits > 64) return set_error(ctx, SPADE_E_UNSUPPORTED, "too many polygons and points for 64-bit keys");
+    int rshift = 0;
+    while (((uint64_t)(t->n - 1) >> rshift) >= (uint64_t)PAIR_RANGES) ++rshift;
+    DevBuf &bc = ctx->scratch[S_VALS2];
+    if (ensure(ctx, bc, sizeof(unsigned long long) * (PAIR_RANGES + 8))) return SPADE_E_NOMEM;
+    unsigned long long *rcount = (unsigned long long *)bc.p;
+    unsigned long long *cursor = rcount + PAIR_RANGES;
+    hipLaunchKernelGGL(k_zero64, dim3(1), dim3(64), 0, st, (int64_t)(PAIR_RANGES + 1), rcount);
+    if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[2], st));
+    if (P.np > 0) {
+        hipLaunchKernelGGL(k_batch_pairs<true>, dim3(grid), dim3(BT_THREADS), 0, st, S, t->nfin, t->nchunk,
+                           (const double *)t->x.p, (const double *)t->y.p, (const uint32_t *)t->ids.p, P.cbase,
+                           P.plist, P.pq, rshift, pbits, rcount, 0u, 0u, nullptr, nullptr);
+        SPADE_HIP(ctx, hipGetLastError());
+    }
+    unsigned long long *h = (unsigned long long *)ensure_pinned(ctx, sizeof(unsigned long long) * PAIR_RANGES);
+    if (!h) return set_error(ctx, SPADE_E_NOMEM, "pinned staging allocation failed");
+    SPADE_HIP(ctx, hipMemcpyAsync(h, rcount, sizeof(unsigned long long) * PAIR_RANGES, hipMemcpyDeviceToHost, st));
+    SPADE_HIP(ctx, hipStreamSynchronize(st));
+    std::vector<unsigned long long> rc_h(h, h + PAIR_RANGES);
+    unsigned long long total = 0;
+    for (auto v : rc_h) total += v;
+    *n_out = (int64_t)total;
+    // runs of consecutive id ranges with at most 2^30 pairs each are written,
+    // sorted and split one at a time (output order is by point id first)
+    const int64_t GROUP = (int64_t)1 << 30;
+    struct Run { uint32_t r0, r1; int64_t k0, k1; };
+    std::vector<Run> runs;
+    {
+        uint32_t rb = 0;
+        int64_t kb = 0, acc = 0;
+        for (uint32_t r = 0; r < PAIR_RANGES; ++r) {
+            if (acc + (int64_t)rc_h[r] > GROUP && r > rb) {
+                runs.push_back({rb, r, kb, kb + acc});
+                kb += acc;
+                acc = 0;
+                rb = r;
+            }
+            acc += (int64_t)rc_h[r];
+        }
+        if (acc > 0) runs.push_back({rb, (uint32_t)PAIR_RANGES, kb, kb + acc});
+    }
+    int64_t gmax = 0;
+    for (const auto &r : runs)
+        if (r.k0 < cap) gmax = std::max(gmax, r.k1 - r.k0);
+    if (gmax >= (int64_t)INT32_MAX) return set_error(ctx, SPADE_E_UNSUPPORTED, "too many pairs for one point-id range");
+    if (gmax > 0) {
+        DevBuf &bo = ctx->scratch[S_ENTC], &bo2 = ctx->scratch[S_ENTF];
+        if (ensure(ctx, bo, 8 * (size_t)gmax) || ensure(ctx, bo2, 8 * (size_t)gmax)) return SPADE_E_NOMEM;
+        DevBuf &cub = ctx->scratch[S_CUBTMP];
+        size_t tb = 0;
+        SPADE_HIP(ctx, hipcub::DeviceRadixSort::SortKeys(nullptr, tb, (const unsigned long long *)bo.p,
+                                                         (unsigned long long *)bo2.p, (int)gmax, 0, pbits + idbits, st));
+        if (ensure(ctx, cub, std::max<size_t>(tb, 1))) return SPADE_E_NOMEM;
+        for (const auto &r : runs) {
+            if (r.k0 >= cap) break;
+            hipLaunchKernelGGL(k_zero64, dim3(1), dim3(64), 0, st, (int64_t)1, cursor);
+            hipLaunchKernelGGL(k_batch_pairs<false>, dim3(grid), dim3(BT_THREADS), 0, st, S, t->nfin, t->nchunk,
+                               (const double *)t->x.p, (const double *)t->y.p, (const uint32_t *)t->ids.p, P.cbase,
+                               P.plist, P.pq, rshift, pbits, nullptr, r.r0, r.r1, cursor,
+                               (unsigned long long *)bo.p);
+            SPADE_HIP(ctx, hipGetLastError());
+            SPADE_HIP(ctx, hipcub::DeviceRadixSort::SortKeys(cub.p, tb, (const unsigned long long *)bo.p,
+                                                             (unsigned long long *)bo2.p, (int)(r.k1 - r.k0), 0,
+                                                             pbits + idbits, st));
+            const int64_t nw = std::min<int64_t>(r.k1, cap) - r.k0;
+            hipLaunchKernelGGL(k_split_pairs, dim3(grid_of(nw)), dim3(256), 0, st, nw,
+                               (const unsigned long long *)bo2.p, pbits, out_pt + r.k0, out_poly + r.k0);
+            SPADE_HIP(ctx, hipGetLastError());
+        }
+    }
+    if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[3], st));
+    SPADE_HIP(ctx, hipStreamSynchronize(st));
+    if ((int64_t)total > cap) return set_error(ctx, SPADE_E_CAPACITY, "output capacity too small");
     return SPADE_OK;
 }
 

@@ -142,6 +142,7 @@ void spade_ctx_destroy(spade_ctx *ctx)
         free_buf(ctx->plain->edges);
         free_buf(ctx->plain->coarse);
         free_buf(ctx->plain->dcds);
+        free_buf(ctx->plain->pid);
         drop_graph(ctx->plain);
         delete ctx->plain;
     }
@@ -195,6 +196,29 @@ int spade_ctx_graph_stats(const spade_ctx *ctx, int64_t *captures, int64_t *repl
     if (!ctx) return SPADE_E_INVALID;
     if (captures) *captures = ctx->graph_captures;
     if (replays) *replays = ctx->graph_replays;
+    return SPADE_OK;
+}
+
+int spade_ctx_build_stats(const spade_ctx *ctx, int64_t *builds, int64_t *rebuilds)
+{
+    if (!ctx) return SPADE_E_INVALID;
+    if (builds) *builds = ctx->builds;
+    if (rebuilds) *rebuilds = ctx->rebuilds;
+    return SPADE_OK;
+}
+
+int spade_mem_info(spade_ctx *ctx, size_t *free_bytes, size_t *total_bytes, size_t *ctx_bytes)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    size_t fr = 0, tot = 0;
+    SPADE_HIP(ctx, hipMemGetInfo(&fr, &tot));
+    size_t held = 0;
+    for (const auto &b : ctx->scratch) held += b.cap;
+    if (ctx->plain) held += ctx->plain->bytes() + ctx->plain->edges.cap + ctx->plain->dcds.cap;
+    if (free_bytes) *free_bytes = fr;
+    if (total_bytes) *total_bytes = tot;
+    if (ctx_bytes) *ctx_bytes = held;
     return SPADE_OK;
 }
 
@@ -253,6 +277,7 @@ void spade_canvas_destroy(spade_canvas *cv)
     free_buf(cv->edges);
     free_buf(cv->coarse);
     free_buf(cv->dcds);
+    free_buf(cv->pid);
     drop_graph(cv);
     delete cv;
 }
@@ -268,6 +293,41 @@ int spade_canvas_info(const spade_canvas *cv, int32_t *width, int32_t *height, i
     if (n_polys) *n_polys = m;
     if (n_boundary_pixels) *n_boundary_pixels = cv->n_boundary;
     if (device_bytes) *device_bytes = (int64_t)cv->bytes();
+    return SPADE_OK;
+}
+
+int spade_layer_index(spade_ctx *ctx, const spade_polys *polys, int32_t res, int32_t *out_layer, int32_t *n_layers)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!n_layers) return set_error(ctx, SPADE_E_INVALID, "n_layers is NULL");
+    *n_layers = 0;
+    if ((rc = check_polys(ctx, polys))) return rc;
+    if (res < 0 || res > 4096) return set_error(ctx, SPADE_E_INVALID, "res must be 0 (automatic) or 1..4096");
+    if (polys->n_polys > 0 && !out_layer) return set_error(ctx, SPADE_E_INVALID, "out_layer is NULL");
+    return layer_index(ctx, polys, res, out_layer, n_layers, nullptr, nullptr);
+}
+
+int spade_layered_build(spade_ctx *ctx, const spade_polys *polys, int32_t res, spade_canvas **out, int32_t *n_layers)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!out) return set_error(ctx, SPADE_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if ((rc = check_polys(ctx, polys))) return rc;
+    if (res < 0 || res > 4096) return set_error(ctx, SPADE_E_INVALID, "res must be 0 (automatic) or 1..4096");
+    spade_canvas *cv = new (std::nothrow) spade_canvas();
+    if (!cv) return set_error(ctx, SPADE_E_NOMEM, "host allocation failed");
+    cv->device = ctx->device;
+    int32_t L = 0;
+    rc = layered_build(ctx, polys, res, cv, &L);
+    if (rc) {
+        spade_canvas_destroy(cv);
+        return rc;
+    }
+    cv->n_layers = L;
+    if (n_layers) *n_layers = L;
+    *out = cv;
     return SPADE_OK;
 }
 
@@ -336,6 +396,7 @@ static int plain_build(spade_ctx *ctx, const spade_polys *polys, spade_canvas **
     if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[0], ctx->stream));
     rc = build_canvas(ctx, polys, ctx->plain, defer);
     if (rc) return rc;
+    ctx->builds++;
     if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[1], ctx->stream));
     ctx->timed_raster = ctx->timing;
     *cvo = ctx->plain;
@@ -358,7 +419,12 @@ static int plain_query(spade_ctx *ctx, const spade_polys *polys, F &&probe)
     const int rf = build_finish(ctx, cv);
     if (rf == BUILD_AGAIN) {
         if ((rc = plain_build(ctx, polys, &cv, false))) return rc;
-        return probe(cv);
+        ctx->rebuilds++;
+        rc = probe(cv);
+        // the probe may only have been queued (join-count): the plain calls
+        // return complete results, so wait for it here as on the first path
+        SPADE_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        return rc;
     }
     return rf ? rf : rp;
 }
@@ -407,6 +473,25 @@ int spade_join_pairs(spade_ctx *ctx, const spade_points *pts, const spade_polys 
     return plain_query(ctx, polys, [&](spade_canvas *cv) {
         return spade_canvas_join_pairs(ctx, cv, pts, out_pt, out_poly, cap, n_out);
     });
+}
+
+int spade_ctx_set_exact_mode(spade_ctx *ctx, int deferred)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    ctx->defer_exact = deferred != 0;
+    return SPADE_OK;
+}
+
+int spade_stream_read(spade_ctx *ctx, const spade_points *pts, int shape, double *out_sum)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if ((rc = check_points(ctx, pts))) return rc;
+    if (!out_sum) return set_error(ctx, SPADE_E_INVALID, "out_sum is NULL");
+    if (shape != 0 && shape != 1) return set_error(ctx, SPADE_E_INVALID, "shape must be 0 or 1");
+    ctx->timed_raster = false;
+    return spade::stream_read(ctx, pts, shape, out_sum);
 }
 
 // ---- exact predicate, exposed for isolated testing

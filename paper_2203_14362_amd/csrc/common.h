@@ -115,6 +115,9 @@ struct spade_canvas {
     int64_t n_elist = 0;
     int64_t n_edges = 0;
     spade::DevBuf cells, cands, ledges, pspan, edges, coarse;
+    spade::DevBuf pid;                        // layered set: caller's polygon id of each set polygon
+    bool layered = false;
+    int32_t n_layers = 0;
     std::vector<uint64_t> gkey;               // launch parameters of the last build
     hipGraphExec_t gexec = nullptr;           // its captured launches (second build on)
     bool pending = false;                     // built, counters and flags not yet read
@@ -131,7 +134,7 @@ struct spade_ctx {
     std::string err;
     int32_t canvas_w = 0, canvas_h = 0;     // 0 = automatic
     double ppv = 256.0;                     // automatic sizing: pixels per vertex
-    spade::DevBuf scratch[17];              // reusable scratch slots
+    spade::DevBuf scratch[18];              // reusable scratch slots (spade::S_NSLOTS)
     void *pinned = nullptr;                 // small pinned host staging area
     void *pend = nullptr;                   // pinned counters and flags of a deferred build
     spade_canvas *plain = nullptr;          // canvas reused by the plain query calls
@@ -146,6 +149,8 @@ struct spade_ctx {
     hipStream_t capture = nullptr;          // internal stream graphs are captured on
     bool graphs = true;                     // replay repeated canvas builds from graphs
     int64_t graph_captures = 0, graph_replays = 0;
+    int64_t builds = 0, rebuilds = 0;       // plain-call canvas builds, and those redone for capacity
+    bool defer_exact = false;               // join-count: boundary points tested after the stream
 };
 
 namespace spade {
@@ -153,8 +158,10 @@ namespace spade {
 // Scratch slot ids inside a context.
 enum Slot {
     S_BLOCKRED = 0, S_RINGPOLY, S_NROWS, S_ROWOFF, S_KEYS, S_KEYS2, S_VALS, S_VALS2,
-    S_ENTC, S_ENTF, S_CUBTMP, S_ROWCNT, S_NEXTP, S_PROBE, S_LOOKBACK, S_MISC, S_ROWSCAN
+    S_ENTC, S_ENTF, S_CUBTMP, S_ROWCNT, S_NEXTP, S_PROBE, S_LOOKBACK, S_MISC, S_ROWSCAN, S_EXQ, S_NSLOTS
 };
+
+static_assert(S_NSLOTS == 18, "scratch slot count of spade_ctx");
 
 int set_error(spade_ctx *ctx, int code, const std::string &msg);
 int hip_fail(spade_ctx *ctx, hipError_t e, const char *what);
@@ -177,6 +184,12 @@ void drop_graph(spade_canvas *cv);
 int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *pbound, spade_canvas *cv,
               bool defer = false);
 CanvasView view_of(const spade_canvas *cv, int q);
+// Layer index of a polygon set (layer of each polygon in d_layer, device)
+// and a canvas set with one canvas per layer.
+struct HostSet;
+int layer_index(spade_ctx *ctx, const spade_polys *polys, int res, int32_t *d_layer, int32_t *n_layers,
+                std::vector<int32_t> *host_layer, HostSet *hs_out);
+int layered_build(spade_ctx *ctx, const spade_polys *polys, int res, spade_canvas *cv, int32_t *n_layers);
 
 // LDS bytes the count probe leaves for the coarse canvas, given the polygon
 // count (its histogram shares the LDS).
@@ -184,6 +197,9 @@ size_t coarse_lds_budget(int64_t M);
 
 int probe_count(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts,
                 uint64_t *out_counts);
+// Plain read of every point (bandwidth reference for the probe).
+int stream_read(spade_ctx *ctx, const spade_points *pts, int shape, double *out);
+
 int select_disk(spade_ctx *ctx, const spade_points *pts, double cx, double cy, double r, uint32_t *out_ids,
                 int64_t cap, int64_t *n_out);
 int probe_emit(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts,

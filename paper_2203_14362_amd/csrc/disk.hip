@@ -78,11 +78,13 @@ __device__ __forceinline__ bool in_disk(double x, double y, double cx, double cy
 // Every wavefront owns segments of DISK_SEG consecutive points (grid-stride
 // over segments).  WRITE == false: counts[s] = selected points of segment s.
 // WRITE == true: the ids of segment s's selected points, ascending, from
-// out[offs[s]] on.  No barriers: a wavefront ranks its points by ballot.
+// out[offs[s]] on; positions at or beyond cap are not written.  No barriers:
+// a wavefront ranks its points by ballot.
 template <bool WRITE>
 __global__ __launch_bounds__(DISK_THREADS) void k_disk(int64_t n, const double *X, const double *Y, double cx,
                                                        double cy, double r, double r2, int64_t nseg,
-                                                       uint32_t *counts, const uint32_t *offs, uint32_t *out)
+                                                       uint32_t *counts, const uint32_t *offs, uint32_t *out,
+                                                       int64_t cap)
 {
     const int lane = threadIdx.x & 63;
     const unsigned long long below = (1ull << lane) - 1ull;
@@ -102,7 +104,10 @@ __global__ __launch_bounds__(DISK_THREADS) void k_disk(int64_t n, const double *
         for (int k = 0; k < DISK_ROUNDS; ++k) {
             const bool in = in_disk(xs[k], ys[k], cx, cy, r, r2);   // NaN padding is outside
             const unsigned long long m = __ballot(in);
-            if (WRITE && in) out[pos + (uint32_t)__popcll(m & below)] = (uint32_t)(i0 + 64 * k);
+            if (WRITE && in) {
+                const uint32_t at = pos + (uint32_t)__popcll(m & below);
+                if ((int64_t)at < cap) out[at] = (uint32_t)(i0 + 64 * k);
+            }
             pos += (uint32_t)__popcll(m);
         }
         if (!WRITE && lane == 0) counts[sg] = pos;
@@ -135,7 +140,7 @@ int select_disk(spade_ctx *ctx, const spade_points *pts, double cx, double cy, d
     const int grid = (int)std::min<int64_t>((nseg + DISK_THREADS / 64 - 1) / (DISK_THREADS / 64), (int64_t)cus * 8);
     const double r2 = r * r;
     hipLaunchKernelGGL(k_disk<false>, dim3(grid), dim3(DISK_THREADS), 0, st, n, pts->x, pts->y, cx, cy, r, r2,
-                       nseg, counts, nullptr, nullptr);
+                       nseg, counts, nullptr, nullptr, (int64_t)0);
     hipLaunchKernelGGL(k_disk_zero, dim3(1), dim3(1), 0, st, counts + nseg);
     SPADE_HIP(ctx, hipGetLastError());
     DevBuf &cub = ctx->scratch[S_CUBTMP];
@@ -149,12 +154,15 @@ int select_disk(spade_ctx *ctx, const spade_points *pts, double cx, double cy, d
     SPADE_HIP(ctx, hipStreamSynchronize(st));
     const int64_t total = (int64_t)h[0];
     if (n_out) *n_out = total;
-    if (total > cap) return set_error(ctx, SPADE_E_CAPACITY, "output capacity too small for the selection");
-    if (total > 0) {
+    // the write pass also runs when the buffer is too small: the first cap
+    // ids are written (two-step Map), the call then reports the shortfall
+    if (total > 0 && cap > 0) {
         hipLaunchKernelGGL(k_disk<true>, dim3(grid), dim3(DISK_THREADS), 0, st, n, pts->x, pts->y, cx, cy, r, r2,
-                           nseg, nullptr, offs, out_ids);
+                           nseg, nullptr, offs, out_ids, cap);
         SPADE_HIP(ctx, hipGetLastError());
+        SPADE_HIP(ctx, hipStreamSynchronize(st));
     }
+    if (total > cap) return set_error(ctx, SPADE_E_CAPACITY, "output capacity too small for the selection");
     return SPADE_OK;
 }
 

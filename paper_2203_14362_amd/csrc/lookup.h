@@ -51,24 +51,30 @@ __device__ __forceinline__ uint32_t lookup(const CanvasView &cv, const uint16_t 
     return L.full ? ((gu32p)cv.cells)[L.fidx] : L.word;
 }
 
-__device__ __forceinline__ bool cand_inside(const CanvasView &cv, const Cand &cd, double x, double y)
+__device__ __forceinline__ bool cand_inside(const Edge *ledges, const double2 *pspan, const Cand &cd, double x,
+                                            double y)
 {
     bool in = (cd.meta & CAND_S) != 0;
     const uint32_t nloc = (cd.meta >> 2) & 0x7fffu;
     const uint32_t npart = cd.meta >> 17;
     if (nloc > 0) in ^= crosses(cd.e0.xlo, cd.e0.ylo, cd.e0.xhi, cd.e0.yhi, x, y);
     if (npart > 0) in ^= straddles(cd.s0.x, cd.s0.y, y);
-    const Edge *le = cv.ledges + cd.eoff;   // local edges after the first
+    const Edge *le = ledges + cd.eoff;   // local edges after the first
     for (uint32_t t = 1; t < nloc; ++t) {
         const Edge e = le[t - 1];
         in ^= crosses(e.xlo, e.ylo, e.xhi, e.yhi, x, y);
     }
-    const double2 *ps = cv.pspan + cd.poff;
+    const double2 *ps = pspan + cd.poff;
     for (uint32_t t = 1; t < npart; ++t) {
         const double2 s = ps[t];
         in ^= straddles(s.x, s.y, y);
     }
     return in;
+}
+
+__device__ __forceinline__ bool cand_inside(const CanvasView &cv, const Cand &cd, double x, double y)
+{
+    return cand_inside(cv.ledges, cv.pspan, cd, x, y);
 }
 
 // Cooperative copy of the coarse canvas into LDS (whole 32-bit words; the

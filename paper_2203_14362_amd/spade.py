@@ -37,6 +37,9 @@ EXPORTS = [
     "spade_table_create", "spade_table_destroy", "spade_table_info", "spade_batch_build",
     "spade_batch_select", "spade_batch_join_count", "spade_ctx_set_pixels_per_vertex",
     "spade_batch_rebuild", "spade_ctx_set_graphs", "spade_ctx_graph_stats", "spade_select_disk",
+    "spade_ctx_build_stats", "spade_mem_info",
+    "spade_ctx_set_exact_mode", "spade_stream_read", "spade_batch_join_pairs", "spade_layer_index",
+    "spade_layered_build",
 ]
 
 
@@ -104,6 +107,13 @@ def load_library():
     lib.spade_ctx_set_pixels_per_vertex.argtypes = [vp, ctypes.c_double]
     lib.spade_ctx_set_graphs.argtypes = [vp, ctypes.c_int]
     lib.spade_ctx_graph_stats.argtypes = [vp, P(i64), P(i64)]
+    lib.spade_ctx_build_stats.argtypes = [vp, P(i64), P(i64)]
+    lib.spade_ctx_set_exact_mode.argtypes = [vp, ctypes.c_int]
+    lib.spade_batch_join_pairs.argtypes = [vp, vp, vp, vp, vp, i64, P(i64)]
+    lib.spade_layer_index.argtypes = [vp, P(_Polys), i32, vp, P(i32)]
+    lib.spade_layered_build.argtypes = [vp, P(_Polys), i32, P(vp), P(i32)]
+    lib.spade_stream_read.argtypes = [vp, P(_Points), ctypes.c_int, vp]
+    lib.spade_mem_info.argtypes = [vp, P(ctypes.c_size_t), P(ctypes.c_size_t), P(ctypes.c_size_t)]
     for name in EXPORTS:
         f = getattr(lib, name)
         if f.restype is ctypes.c_int:
@@ -175,6 +185,14 @@ def _compact(buf, m):
     """The first m elements of an output buffer; copied out when they fill
     less than half of it, so a result never pins a much larger buffer."""
     return buf[:m] if 2 * m >= buf.numel() else buf[:m].clone()
+
+
+def _ids(t, n):
+    """Point ids come back as uint32; tensors of more than 2^31 - 1 points
+    return them widened to int64 so that no id reads as negative."""
+    if n <= 0x7FFFFFFF:
+        return t
+    return t.to(torch.int64) & 0xFFFFFFFF
 
 
 def _points(x, y):
@@ -298,6 +316,34 @@ class Context:
         self._check(self.lib.spade_ctx_graph_stats(self.handle, ctypes.byref(c), ctypes.byref(r)))
         return c.value, r.value
 
+    def set_exact_mode(self, deferred: bool = True):
+        """Join-count exact tests deferred to a second kernel (default) or
+        run inline by the point stream."""
+        self._check(self.lib.spade_ctx_set_exact_mode(self.handle, 1 if deferred else 0))
+
+    def stream_read(self, x, y, shape: int = 0):
+        """Sum of all coordinates via one plain read of the points (bandwidth
+        reference; time it with the phase timer)."""
+        self._sync_stream()
+        P = _points(x, y)
+        out = torch.zeros(1, dtype=torch.float64, device=self.device)
+        self._check(self.lib.spade_stream_read(self.handle, ctypes.byref(P), int(shape),
+                                               ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def build_stats(self):
+        """(plain-call canvas builds, builds redone for record capacity)."""
+        b, r = ctypes.c_int64(), ctypes.c_int64()
+        self._check(self.lib.spade_ctx_build_stats(self.handle, ctypes.byref(b), ctypes.byref(r)))
+        return b.value, r.value
+
+    def mem_info(self):
+        """{'free', 'total', 'ctx'}: device bytes free and in total, and the
+        scratch bytes this context holds."""
+        f, t, c = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+        self._check(self.lib.spade_mem_info(self.handle, ctypes.byref(f), ctypes.byref(t), ctypes.byref(c)))
+        return {"free": f.value, "total": t.value, "ctx": c.value}
+
     def set_pixels_per_vertex(self, ppv: float):
         self._check(self.lib.spade_ctx_set_pixels_per_vertex(self.handle, float(ppv)))
 
@@ -335,10 +381,10 @@ class Context:
         """(ids int32 tensor, offsets int64 numpy [nq + 1]): query q's ascending
         point ids are ids[off[q]:off[q+1]].  Without an explicit capacity the
         first attempt uses the largest total seen on this context (at least
-        2^20) and retries once at the reported total."""
+        2^20, at most 2^28) and retries once at the reported total."""
         off = np.zeros(batch.n_queries + 1, dtype=np.int64)
         if cap is None:
-            cap = self._select_cap
+            cap = min(self._select_cap, 1 << 28)
         while True:
             ids = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device)
             self._sync_stream()
@@ -351,6 +397,51 @@ class Context:
                 continue
             self._check(rc)
             return _compact(ids, int(off[-1])), off
+
+    def batch_join_pairs(self, batch: Batch, table: Table, cap=None):
+        """(point ids, polygon ids) int32 tensors of every pair of a table
+        point inside a polygon of the canvas set, ascending by (point,
+        polygon); polygon ids of a layered set are the caller's."""
+        if cap is None:
+            cap = min(self._select_cap, 1 << 28)
+        while True:
+            pt = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device)
+            pg = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device)
+            nout = ctypes.c_int64()
+            self._sync_stream()
+            rc = self.lib.spade_batch_join_pairs(self.handle, batch.handle, table.handle,
+                                                 ctypes.c_void_p(pt.data_ptr()), ctypes.c_void_p(pg.data_ptr()),
+                                                 cap, ctypes.byref(nout))
+            if rc == SPADE_E_CAPACITY:
+                cap = int(nout.value)
+                self._select_cap = max(self._select_cap, cap)
+                continue
+            self._check(rc)
+            m = int(nout.value)
+            return _compact(pt, m), _compact(pg, m)
+
+    def layer_index(self, polys, res: int = 0):
+        """(layer of each polygon as an int32 tensor, number of layers)."""
+        self._sync_stream()
+        dp = self.polys(polys)
+        out = torch.empty(max(dp.n_polys, 1), dtype=torch.int32, device=self.device)
+        n = ctypes.c_int32()
+        self._check(self.lib.spade_layer_index(self.handle, ctypes.byref(dp.cstruct()), int(res),
+                                               ctypes.c_void_p(out.data_ptr()), ctypes.byref(n)))
+        return out[:dp.n_polys], int(n.value)
+
+    def layered(self, polys, res: int = 0) -> "Batch":
+        """A canvas set with one canvas per layer of the polygon set, for the
+        batch join calls over a table."""
+        self._sync_stream()
+        dp = self.polys(polys)
+        h = ctypes.c_void_p()
+        n = ctypes.c_int32()
+        self._check(self.lib.spade_layered_build(self.handle, ctypes.byref(dp.cstruct()), int(res), ctypes.byref(h),
+                                                 ctypes.byref(n)))
+        b = Batch(self, h, np.array([0, dp.n_polys], dtype=np.int64))
+        b.n_layers = int(n.value)
+        return b
 
     def batch_join_count(self, batch: Batch, table: Table, out=None):
         """Per-polygon counts of the batch's polygon set (int64 tensor)."""
@@ -423,10 +514,11 @@ class Context:
                 continue
             self._check(rc)
             m = int(nout.value)
-            return (_compact(pt, m), _compact(pg, m)) if pairs else _compact(pt, m)
+            return (_ids(_compact(pt, m), n), _compact(pg, m)) if pairs else _ids(_compact(pt, m), n)
 
     def select(self, x, y, poly_or_canvas, cap=None):
-        """Ascending ids (int32 tensor) of the points inside the one polygon."""
+        """Ascending ids of the points inside the one polygon (int32 tensor;
+        int64 when there are more than 2^31 - 1 points)."""
         return self._emit(x, y, poly_or_canvas, False, cap)
 
     def select_disk(self, x, y, cx, cy, r, cap=None):
@@ -445,7 +537,7 @@ class Context:
                 cap = int(nout.value)
                 continue
             self._check(rc)
-            return _compact(pt, int(nout.value))
+            return _ids(_compact(pt, int(nout.value)), P.n)
 
     def join_pairs(self, x, y, polys_or_canvas, cap=None):
         """(point ids, polygon ids) int32 tensors, ascending by (point, polygon)."""

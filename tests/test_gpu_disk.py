@@ -71,16 +71,17 @@ def test_empty_input_capacity_and_invalid_arguments(ctx):
     dx, dy = _dev(x), _dev(y)
     assert ctx.select_disk(dx[:0], dy[:0], 0.5, 0.5, 0.3).numel() == 0
     want = disk.select_disk(x, y, 0.5, 0.5, 0.3)
-    # too small a buffer: the call reports the size and writes nothing; the
-    # binding retries with it
+    # too small a buffer: the call reports the size and writes the first
+    # cap ids (two-step Map); the binding retries with the size
     P = _points(dx, dy)
-    buf = torch.full((10,), -1, dtype=torch.int32, device="cuda")
+    buf = torch.full((11,), -1, dtype=torch.int32, device="cuda")
     nout = ctypes.c_int64()
     rc = ctx.lib.spade_select_disk(ctx.handle, ctypes.byref(P), 0.5, 0.5, 0.3, ctypes.c_void_p(buf.data_ptr()),
                                    10, ctypes.byref(nout))
     torch.cuda.synchronize()
     assert rc == SPADE_E_CAPACITY and nout.value == want.size
-    assert (buf.cpu() == -1).all()
+    got = buf.cpu().numpy()
+    assert np.array_equal(got[:10].astype(np.uint32), want[:10]) and got[10] == -1
     assert np.array_equal(_ids(ctx.select_disk(dx, dy, 0.5, 0.5, 0.3, cap=10)), want)
     for bad in [(0.5, 0.5, -1.0), (np.nan, 0.5, 0.1), (0.5, np.inf, 0.1), (0.5, 0.5, np.inf)]:
         with pytest.raises(SpadeError):

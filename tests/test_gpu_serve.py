@@ -47,11 +47,17 @@ def test_served_equals_alone(ctx):
     ex = SpadeExecutor(dx, dy, n_workers=2)
     free, _ = torch.cuda.mem_get_info()
     srv = Server(ex, budget_bytes=free // 2).start()
-    arrivals = gen.poisson_arrivals(200.0, 10.0, seed=7)[:len(reqs)]
-    replay(srv, reqs, arrivals)
+    # the first few arrive as a Poisson stream, the rest in one burst: the
+    # burst queues behind the batches in flight and forms mixed batches
+    arrivals = gen.poisson_arrivals(200.0, 10.0, seed=7)[:8]
+    replay(srv, reqs[:8], arrivals)
+    for r in reqs[8:]:
+        srv.submit(r)
     srv.stop()
     assert all(r.error is None for r in reqs), [r.error for r in reqs if r.error][:3]
-    assert max(len(b) for b in srv.batches) >= 1
+    kind = {r.rid: r.kind for r in reqs}
+    assert max(len(b) for b in srv.batches) > 1
+    assert any(len({kind[i] for i in b}) == 2 for b in srv.batches), srv.batches
     st = latency_stats(reqs)
     assert st["n"] == len(reqs)
     # results own their memory (no view pinning a batch-sized buffer)
