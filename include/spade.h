@@ -216,6 +216,20 @@ int spade_canvas_join_count_async(spade_ctx *ctx, const spade_canvas *cv,
 int spade_canvas_join_pairs(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts,
                             uint32_t *out_pt, uint32_t *out_poly, int64_t cap, int64_t *n_out);
 
+/* Join-count against a prebuilt canvas that allocates nothing, for callers
+ * that cannot allocate device memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation.  Same result as
+ * spade_canvas_join_count_async (counts complete when ctx's stream reaches
+ * that point; no synchronisation, no hipMalloc / hipFree, no allocating
+ * library routine).  Its scratch (one u64 accumulator per polygon and a
+ * counter) is a fixed device array of the library, one per GPU, held until
+ * the process ends: at most 65536 polygons (SPADE_E_UNSUPPORTED beyond).
+ * Every call on a GPU shares that GPU's array, so calls that overlap on one
+ * GPU (other streams, other contexts, other host threads) race and must be
+ * serialised by the caller.  The canvas must have been built beforehand
+ * (spade_canvas_build). */
+int spade_canvas_join_count_noalloc(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts,
+                                    uint64_t *out_counts);
 
 /* ---- Resident point tables and query batches.  Many queries share one
  * pass over a resident, spatially clustered point table (the data stays in

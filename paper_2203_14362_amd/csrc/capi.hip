@@ -124,6 +124,10 @@ int spade_ctx_create(int device, void *stream, spade_ctx **out)
     if (!c) return SPADE_E_NOMEM;
     c->device = device;
     c->stream = (hipStream_t)stream;
+    // the device address of the no-allocation probe's scratch, once per
+    // device (a failure is reported by that entry point)
+    (void)noalloc_init(c);
+    c->err.clear();
     *out = c;
     return SPADE_OK;
 }
@@ -342,6 +346,20 @@ int spade_canvas_join_count_async(spade_ctx *ctx, const spade_canvas *cv, const 
     if (cv->view.M > 0 && !out_counts) return set_error(ctx, SPADE_E_INVALID, "out_counts is NULL");
     if (cv != ctx->plain) ctx->timed_raster = false;
     return probe_count(ctx, cv, pts, out_counts);
+}
+
+int spade_canvas_join_count_noalloc(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts,
+                                    uint64_t *out_counts)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!cv) return set_error(ctx, SPADE_E_INVALID, "canvas is NULL");
+    if (cv->nc != 1) return set_error(ctx, SPADE_E_INVALID, "a batch canvas set is queried with the batch calls");
+    if (cv->pending) return set_error(ctx, SPADE_E_INVALID, "the canvas's build has not completed");
+    if ((rc = check_points(ctx, pts))) return rc;
+    if (cv->view.M > 0 && !out_counts) return set_error(ctx, SPADE_E_INVALID, "out_counts is NULL");
+    if (cv != ctx->plain) ctx->timed_raster = false;
+    return probe_count_noalloc(ctx, cv, pts, out_counts);
 }
 
 int spade_canvas_join_count(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts,

@@ -199,7 +199,11 @@ int probe_count(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts,
                 uint64_t *out_counts);
 // Plain read of every point (bandwidth reference for the probe).
 int stream_read(spade_ctx *ctx, const spade_points *pts, int shape, double *out);
-
+// The same probe with its scratch in a fixed device array (no allocation);
+// noalloc_init looks the array's address up for ctx's device.
+int noalloc_init(spade_ctx *ctx);
+int probe_count_noalloc(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts,
+                        uint64_t *out_counts);
 int select_disk(spade_ctx *ctx, const spade_points *pts, double cx, double cy, double r, uint32_t *out_ids,
                 int64_t cap, int64_t *n_out);
 int probe_emit(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts,

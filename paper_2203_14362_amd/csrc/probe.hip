@@ -449,6 +449,66 @@ int stream_read(spade_ctx *ctx, const spade_points *pts, int shape, double *out)
     return SPADE_OK;
 }
 
+// ------------------------------------------------- join-count without allocation
+//
+// The count probe's only scratch is its accumulator (one u64 per polygon)
+// and finish counter.  For callers that cannot allocate device memory they
+// live in a fixed array of this source file instead of a context slot.  Its
+// device address differs per GPU and is looked up once per device when a
+// context is created there; host code passes that address, never the
+// array's own name.  Calls that overlap on one GPU share the array and race.
+constexpr int64_t NOALLOC_MAX_POLYS = 65536;
+static __device__ __align__(256) unsigned long long scratch[NOALLOC_MAX_POLYS + 1];
+constexpr int MAX_DEVICES = 64;
+static void *g_scratch_ptr[MAX_DEVICES];
+static std::mutex g_scratch_mu;
+
+int noalloc_init(spade_ctx *ctx)
+{
+    if (ctx->device < 0 || ctx->device >= MAX_DEVICES)
+        return set_error(ctx, SPADE_E_UNSUPPORTED, "device index beyond the library's table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[ctx->device]) return SPADE_OK;
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        return set_error(ctx, SPADE_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    }
+    g_scratch_ptr[ctx->device] = p;
+    return SPADE_OK;
+}
+
+__global__ void k_fill_u64(int64_t n, unsigned long long *p)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0ull;
+}
+
+int probe_count_noalloc(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts, uint64_t *out_counts)
+{
+    const int64_t M = cv->view.M;
+    if (M > NOALLOC_MAX_POLYS)
+        return set_error(ctx, SPADE_E_UNSUPPORTED,
+                         "join-count without allocation supports at most 65536 polygons");
+    if (M == 0) return SPADE_OK;
+    void *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        base = g_scratch_ptr[ctx->device];
+    }
+    if (!base) return set_error(ctx, SPADE_E_HIP, "scratch address of the device was not looked up");
+    unsigned long long *acc = (unsigned long long *)base;
+    unsigned int *done = (unsigned int *)(acc + M);
+    // the array keeps the last call's contents: clear what must start at
+    // zero with a kernel (no memset node, so the call can be captured)
+    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)std::min<int64_t>((M + 256) / 256, 256)), dim3(256), 0,
+                       ctx->stream, M + 1, acc);
+    SPADE_HIP(ctx, hipGetLastError());
+    // no exact queue: each wavefront tests its own boundary points
+    return launch_count(ctx, cv, pts, out_counts, acc, done, ExactQueue{nullptr, nullptr, nullptr, nullptr, 0ull});
+}
+
 // ------------------------------------------------------------ ordered emit
 
 // Write pass.  Every wavefront owns segments of EMIT_SEG consecutive points

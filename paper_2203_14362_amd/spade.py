@@ -37,7 +37,7 @@ EXPORTS = [
     "spade_table_create", "spade_table_destroy", "spade_table_info", "spade_batch_build",
     "spade_batch_select", "spade_batch_join_count", "spade_ctx_set_pixels_per_vertex",
     "spade_batch_rebuild", "spade_ctx_set_graphs", "spade_ctx_graph_stats", "spade_select_disk",
-    "spade_ctx_build_stats", "spade_mem_info",
+    "spade_ctx_build_stats", "spade_mem_info", "spade_canvas_join_count_noalloc",
     "spade_ctx_set_exact_mode", "spade_stream_read", "spade_batch_join_pairs", "spade_layer_index",
     "spade_layered_build",
 ]
@@ -92,6 +92,7 @@ def load_library():
     lib.spade_canvas_select.argtypes = [vp, vp, P(_Points), vp, i64, P(i64)]
     lib.spade_canvas_join_count.argtypes = [vp, vp, P(_Points), vp]
     lib.spade_canvas_join_count_async.argtypes = [vp, vp, P(_Points), vp]
+    lib.spade_canvas_join_count_noalloc.argtypes = [vp, vp, P(_Points), vp]
     lib.spade_canvas_join_pairs.argtypes = [vp, vp, P(_Points), vp, vp, i64, P(i64)]
     lib.spade_orient_batch.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp]
     lib.spade_ctx_set_timing.argtypes = [vp, ctypes.c_int]
