@@ -325,15 +325,6 @@ int spade_layered_build(spade_ctx *ctx, const spade_polys *polys, int32_t res, s
  * canvas (default 256).  The autotuner sets this. */
 int spade_ctx_set_pixels_per_vertex(spade_ctx *ctx, double ppv);
 
-/* Where the join-count runs the exact tests of points in boundary pixels
- * (default: inline).  deferred != 0: the point stream queues them in
- * device memory (20 bytes per point, room for up to 2^27 points; longer
- * streams are probed in passes of that many) and a second kernel tests them
- * after the stream; 0: each wavefront tests its queued boundary points
- * itself whenever 64 have gathered (default).  Results are identical either
- * way. */
-int spade_ctx_set_exact_mode(spade_ctx *ctx, int deferred);
-
 /* Measurement aid: reads both coordinates of every point once and adds
  * their sum to *out_sum (device double, not cleared), with the count
  * probe's launch shape (shape 0: one 1024-thread workgroup per compute

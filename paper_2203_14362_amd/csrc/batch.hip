@@ -239,7 +239,8 @@ __device__ __forceinline__ uint32_t caller_id(const SetArgs &S, int64_t g)
 
 // ------------------------------------------------------------ batch select
 
-// Pass 1 (EMIT = false): matches per pair into pcount.  Pass 2 (EMIT): for
+// Pass 1 (EMIT = false): matches per pair into pcount (64-bit, so that the
+// scan of the counts accumulates in 64 bits).  Pass 2 (EMIT): for
 // the pairs of queries q0 <= q < q1 only, the keys (query << 32 | point id)
 // of the matching points from pbase[pair] - kbase on, in an order the key
 // sort that follows makes ascending.
@@ -248,7 +249,7 @@ __global__ __launch_bounds__(BT_THREADS) void k_batch_select(SetArgs S, int64_t 
                                                              const double *X, const double *Y,
                                                              const uint32_t *ids, const unsigned int *cbase,
                                                              const uint32_t *plist, const uint32_t *pq,
-                                                             uint32_t *pcount, const unsigned long long *pbase,
+                                                             unsigned long long *pcount, const unsigned long long *pbase,
                                                              unsigned long long *out, uint32_t q0, uint32_t q1,
                                                              unsigned long long kbase)
 {
@@ -774,15 +775,17 @@ int spade_batch_select(spade_ctx *ctx, const spade_canvas *set, const spade_tabl
     const int64_t np = P.np;
     DevBuf &bc = ctx->scratch[S_VALS2];
     DevBuf &bo = ctx->scratch[S_ENTC];
-    if (ensure(ctx, bc, sizeof(uint32_t) * (size_t)(np + 1) + sizeof(unsigned long long) * (size_t)(np + 1) +
+    if (ensure(ctx, bc, sizeof(unsigned long long) * (size_t)(np + 1) + sizeof(unsigned long long) * (size_t)(np + 1) +
                             sizeof(unsigned long long) * (size_t)(nq + 2) + 64))
         return SPADE_E_NOMEM;
-    uint32_t *pcount = (uint32_t *)bc.p;
-    unsigned long long *pbase = (unsigned long long *)(((uintptr_t)(pcount + np + 1) + 7) & ~(uintptr_t)7);
+    // 64-bit counts: hipCUB's scan accumulates in the input's type, and a
+    // batch may select more than 2^32 ids in total
+    unsigned long long *pcount = (unsigned long long *)bc.p;
+    unsigned long long *pbase = pcount + (np + 1);
     unsigned long long *qoff = pbase + (np + 1);
     const SetArgs S = set_args(set);
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(t->nchunk, (int64_t)num_cus_of(ctx->device) * 8));
-    hipLaunchKernelGGL(k_zero32, dim3(1), dim3(64), 0, st, (int64_t)1, (unsigned int *)(pcount + np));
+    hipLaunchKernelGGL(k_zero64, dim3(1), dim3(64), 0, st, (int64_t)1, pcount + np);
     if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[2], st));
     if (np > 0) {
         hipLaunchKernelGGL(k_batch_select<false>, dim3(grid), dim3(BT_THREADS), 0, st, S, t->nfin, t->nchunk,

@@ -493,14 +493,6 @@ int spade_join_pairs(spade_ctx *ctx, const spade_points *pts, const spade_polys 
     });
 }
 
-int spade_ctx_set_exact_mode(spade_ctx *ctx, int deferred)
-{
-    int rc = check_ctx(ctx);
-    if (rc) return rc;
-    ctx->defer_exact = deferred != 0;
-    return SPADE_OK;
-}
-
 int spade_stream_read(spade_ctx *ctx, const spade_points *pts, int shape, double *out_sum)
 {
     int rc = check_ctx(ctx);

@@ -76,7 +76,7 @@ __device__ __forceinline__ void edge_rows(double va, double vb, int H, int &r0, 
 template <bool FILL>
 __global__ __launch_bounds__(256) void k_layer_entries(int64_t V, int64_t R, const int64_t *rvo, const int64_t *pro,
                                                        int64_t M, const double *vx, const double *vy, LayerGrid g,
-                                                       uint32_t *count, const unsigned long long *off,
+                                                       unsigned long long *count, const unsigned long long *off,
                                                        unsigned long long *keys)
 {
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < V; j += (int64_t)gridDim.x * blockDim.x) {
@@ -94,7 +94,7 @@ __global__ __launch_bounds__(256) void k_layer_entries(int64_t V, int64_t R, con
         int r0, r1;
         edge_rows(va, vb, g.H, r0, r1);
         if (!FILL) {
-            count[j] = (uint32_t)max(0, r1 - r0);
+            count[j] = (unsigned long long)max(0, r1 - r0);
             continue;
         }
         if (r1 <= r0) continue;
@@ -183,8 +183,6 @@ __global__ void k_layer_init(int64_t M, int32_t *layer, int32_t *cropped)
         cropped[p] = 0;
     }
 }
-
-__global__ void k_zero_u32_at(uint32_t *p) { *p = 0u; }
 
 __global__ void k_fill_zero64(int64_t n, unsigned long long *p)
 {
@@ -333,15 +331,16 @@ int layer_index(spade_ctx *ctx, const spade_polys *polys, int res, int32_t *d_la
     Span *spans = nullptr;
     if (V > 0 && g.sx > 0 && g.sy > 0) {
         DevBuf &bc = ctx->scratch[S_NROWS], &bo = ctx->scratch[S_ROWOFF];
-        if (ensure(ctx, bc, sizeof(uint32_t) * (size_t)(V + 1)) ||
+        if (ensure(ctx, bc, sizeof(unsigned long long) * (size_t)(V + 1)) ||
             ensure(ctx, bo, sizeof(unsigned long long) * (size_t)(V + 1)))
             return SPADE_E_NOMEM;
-        uint32_t *cnt = (uint32_t *)bc.p;
+        // 64-bit counts: the scan accumulates in the input's type
+        unsigned long long *cnt = (unsigned long long *)bc.p;
         unsigned long long *off = (unsigned long long *)bo.p;
         const int64_t *pro_d = polys->poly_ring_off;
         hipLaunchKernelGGL(k_layer_entries<false>, dim3(grid_n(V)), dim3(256), 0, st, V, R, polys->ring_vtx_off,
                            pro_d, M, polys->vx, polys->vy, g, cnt, nullptr, nullptr);
-        hipLaunchKernelGGL(k_zero_u32_at, dim3(1), dim3(1), 0, st, cnt + V);   // the scan's total slot
+        hipLaunchKernelGGL(k_fill_zero64, dim3(1), dim3(64), 0, st, (int64_t)1, cnt + V);   // the scan's total slot
         SPADE_HIP(ctx, hipGetLastError());
         DevBuf &cub = ctx->scratch[S_CUBTMP];
         size_t tb = 0;

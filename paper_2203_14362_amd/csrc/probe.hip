@@ -32,8 +32,7 @@
 namespace spade {
 
 constexpr int CNT_THREADS = 1024;         // count probe workgroup
-constexpr int CNT_UNROLL = 5;             // points per thread per iteration, exact tests inline (6 spill)
-constexpr int CNT_UNROLL_D = 8;           // the same with the exact tests deferred
+constexpr int CNT_UNROLL = 5;             // points per thread per iteration (6 spills)
 constexpr int QCAP = 64;                  // boundary queue entries per wavefront
 constexpr int HIST_MAX = 8192;            // polygons counted in LDS
 constexpr int EMIT_THREADS = 1024;
@@ -52,16 +51,6 @@ size_t coarse_lds_budget(int64_t M)
 }
 
 // ------------------------------------------------------------ join-count
-
-// Boundary points whose exact tests are deferred to k_exact: SoA arrays of
-// cap entries and the number of entries written so far.  The host launches
-// k_count over at most cap points at a time, so the queue never overflows.
-struct ExactQueue {
-    double *x, *y;
-    uint32_t *rec;
-    unsigned long long *n;
-    unsigned long long cap;
-};
 
 // Exact test of a point against the records of its boundary pixel, two
 // records at a time (most pixels have two; the slot after the last record
@@ -83,15 +72,12 @@ __device__ __forceinline__ void test_records(const CanvasView &cv, uint32_t rec,
 // Counts accumulate in a context-owned accumulator `acc` that is all zero
 // between calls: the last workgroup to finish (found with a counter, after a
 // device-scope fence) copies acc into the caller's output and clears acc and
-// the counter again, so a query needs no memset.  DEFER: boundary points
-// go to the exact queue (one reservation per 64 of them) and k_exact, run
-// next, finishes the counts; otherwise each wavefront tests its queued
-// boundary points itself whenever 64 have gathered.
-template <bool LDSHIST, bool DEFER, int UNROLL>
+// the counter again, so a query needs no memset.  Each wavefront tests its
+// queued boundary points itself whenever 64 have gathered.
+template <bool LDSHIST, int UNROLL>
 __global__ __launch_bounds__(CNT_THREADS) void k_count(CanvasView cv, int64_t n, const double *X,
                                                        const double *Y, unsigned long long *acc,
-                                                       unsigned int *done, unsigned long long *out,
-                                                       ExactQueue eq)
+                                                       unsigned int *done, unsigned long long *out)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ bool s_last;
@@ -124,27 +110,9 @@ __global__ __launch_bounds__(CNT_THREADS) void k_count(CanvasView cv, int64_t n,
         __builtin_amdgcn_wave_barrier();
         qn = 0;
     };
-    // the queued points to the exact queue, one reservation per wavefront
-    auto flush = [&]() {
-        __builtin_amdgcn_wave_barrier();
-        unsigned long long at = 0;
-        if (lane == 0) at = atomicAdd(eq.n, (unsigned long long)qn);
-        const uint32_t alo = __builtin_amdgcn_readfirstlane((uint32_t)at);
-        const uint32_t ahi = __builtin_amdgcn_readfirstlane((uint32_t)(at >> 32));
-        at = ((unsigned long long)ahi << 32) | alo;
-        if (lane < qn) {
-            eq.x[at + lane] = qx[lane];
-            eq.y[at + lane] = qy[lane];
-            eq.rec[at + lane] = qr[lane];
-        }
-        __builtin_amdgcn_wave_barrier();
-        qn = 0;
-    };
 
     // software pipeline: the next iteration's points are in flight while the
-    // current ones are classified.  The full-canvas reads of an iteration are
-    // issued before the next iteration's point loads, so waiting for them
-    // does not wait for those loads too.
+    // current ones are classified
     const int64_t step = (int64_t)gridDim.x * CNT_THREADS * UNROLL;
     double xn[UNROLL], yn[UNROLL];
     auto fetch = [&](int64_t b) {
@@ -161,8 +129,9 @@ __global__ __launch_bounds__(CNT_THREADS) void k_count(CanvasView cv, int64_t n,
         double xs[UNROLL], ys[UNROLL];
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) { xs[u] = xn[u]; ys[u] = yn[u]; }
+        if (base + step < n) fetch(base + step);
         // the coarse words of all points of this iteration first, then
-        // their full-canvas reads, then the next points
+        // their full-canvas reads, all issued before any result is used
         Look lk[UNROLL];
         uint32_t ws[UNROLL];
 #pragma unroll
@@ -170,7 +139,6 @@ __global__ __launch_bounds__(CNT_THREADS) void k_count(CanvasView cv, int64_t n,
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u)
             ws[u] = lk[u].full ? ((gu32p)cv.cells)[lk[u].fidx] : lk[u].word;
-        if (base + step < n) fetch(base + step);
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
             const uint32_t w = ws[u];
@@ -179,10 +147,7 @@ __global__ __launch_bounds__(CNT_THREADS) void k_count(CanvasView cv, int64_t n,
             const unsigned long long mask = __ballot(bnd);
             const uint32_t nnew = (uint32_t)__popcll(mask);
             if (nnew == 0) continue;
-            if (qn + nnew > QCAP) {
-                if constexpr (DEFER) flush();
-                else drain(0);
-            }
+            if (qn + nnew > QCAP) drain(0);
             if (bnd) {
                 const uint32_t slot = qn + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
                 qx[slot] = xs[u];
@@ -192,10 +157,7 @@ __global__ __launch_bounds__(CNT_THREADS) void k_count(CanvasView cv, int64_t n,
             qn += nnew;
         }
     }
-    if (qn) {
-        if constexpr (DEFER) flush();
-        else drain(0);
-    }
+    if (qn) drain(0);
 
     if (LDSHIST) {
         __syncthreads();
@@ -204,7 +166,6 @@ __global__ __launch_bounds__(CNT_THREADS) void k_count(CanvasView cv, int64_t n,
             if (c) atomicAdd(&acc[k], (unsigned long long)c);
         }
     }
-    if (DEFER) return;   // k_exact completes the counts
     __threadfence();
     __syncthreads();
     if (threadIdx.x == 0) s_last = (atomicAdd(done, 1u) == gridDim.x - 1);
@@ -216,56 +177,6 @@ __global__ __launch_bounds__(CNT_THREADS) void k_count(CanvasView cv, int64_t n,
         acc[k] = 0ull;
     }
     if (threadIdx.x == 0) *done = 0u;
-}
-
-constexpr int EX_THREADS = 512;
-
-// Exact tests of the deferred boundary points (one point per thread,
-// grid-stride over the queue), counted in an LDS histogram; the last
-// workgroup copies the counts out and clears the accumulator, the finish
-// counter and the queue.
-template <bool LDSHIST>
-__global__ __launch_bounds__(EX_THREADS) void k_exact(CanvasView cv, ExactQueue eq, unsigned long long *acc,
-                                                      unsigned int *done, unsigned long long *out, int fin)
-{
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ bool s_last;
-    const int M = (int)cv.M;
-    uint32_t *hist = (uint32_t *)smem;
-    if (LDSHIST) {
-        for (int k = threadIdx.x; k < M; k += EX_THREADS) hist[k] = 0;
-        __syncthreads();
-    }
-    auto add = [&](uint32_t k) {
-        if (LDSHIST) atomicAdd(&hist[k], 1u);
-        else atomicAdd(&acc[k], 1ull);
-    };
-    const unsigned long long nq = *eq.n;
-    for (unsigned long long i = (unsigned long long)blockIdx.x * EX_THREADS + threadIdx.x; i < nq;
-         i += (unsigned long long)gridDim.x * EX_THREADS)
-        test_records(cv, eq.rec[i], eq.x[i], eq.y[i], add);
-    if (LDSHIST) {
-        __syncthreads();
-        for (int k = threadIdx.x; k < M; k += EX_THREADS) {
-            const uint32_t c = hist[k];
-            if (c) atomicAdd(&acc[k], (unsigned long long)c);
-        }
-    }
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) s_last = (atomicAdd(done, 1u) == gridDim.x - 1);
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    if (fin)   // the last pass of the query: counts out, accumulator cleared
-        for (int k = threadIdx.x; k < M; k += EX_THREADS) {
-            out[k] = __hip_atomic_load(&acc[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            acc[k] = 0ull;
-        }
-    if (threadIdx.x == 0) {
-        *done = 0u;
-        *eq.n = 0ull;
-    }
 }
 
 static int num_cus(spade_ctx *ctx)
@@ -301,18 +212,15 @@ static size_t coarse_bytes_of(const CanvasView &v)
 }
 
 // Launches the count probe with the accumulator acc[M] and the finish
-// counter *done, both zero on entry and left zero by the kernels.  With an
-// exact queue (eq.cap > 0, *eq.n zero on entry and left zero) the boundary
-// points' exact tests run in k_exact after the stream.
+// counter *done, both zero on entry and left zero by the kernel.
 static int launch_count(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts, uint64_t *out_counts,
-                        unsigned long long *acc, unsigned int *done, ExactQueue eq)
+                        unsigned long long *acc, unsigned int *done)
 {
     hipStream_t st = ctx->stream;
     const CanvasView &v = cv->view;
     const int64_t M = v.M;
     const int cus = num_cus(ctx);
     const bool ldshist = M <= HIST_MAX;
-    const bool defer = eq.cap > 0;
     const size_t lds = coarse_bytes_of(v) + (ldshist ? (((size_t)M * 4 + 15) & ~(size_t)15) : 0) + QUEUE_BYTES;
     if (lds + LDS_RESERVE > LDS_TOTAL) return set_error(ctx, SPADE_E_HIP, "internal: probe LDS budget exceeded");
     const int64_t need = std::max<int64_t>(1, (pts->n + CNT_THREADS * CNT_UNROLL - 1) / (CNT_THREADS * CNT_UNROLL));
@@ -321,65 +229,16 @@ static int launch_count(spade_ctx *ctx, const spade_canvas *cv, const spade_poin
     // level instead
     const int grid = (int)std::min<int64_t>(need, (int64_t)cus);
     unsigned long long *o = (unsigned long long *)out_counts;
-    auto go = [&](auto kern, int64_t n, const double *X, const double *Y, int g) -> int {
+    auto go = [&](auto kern) -> int {
         SPADE_HIP(ctx, hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        hipLaunchKernelGGL(kern, dim3(g), dim3(CNT_THREADS), lds, st, v, n, X, Y, acc, done, o, eq);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(CNT_THREADS), lds, st, v, pts->n, pts->x, pts->y, acc, done, o);
         SPADE_HIP(ctx, hipGetLastError());
         return SPADE_OK;
     };
     if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[2], st));
-    if (!defer) {
-        int rc = ldshist ? go(k_count<true, false, CNT_UNROLL>, pts->n, pts->x, pts->y, grid)
-                         : go(k_count<false, false, CNT_UNROLL>, pts->n, pts->x, pts->y, grid);
-        if (rc) return rc;
-    } else {
-        // at most eq.cap points per pass, so every boundary point has a slot
-        const size_t hl = std::max<size_t>(ldshist ? (size_t)M * 4 : 0, 16);
-        const int eg = cus * 2;
-        for (int64_t b = 0; b < std::max<int64_t>(pts->n, 1); b += (int64_t)eq.cap) {
-            const int64_t m = std::min<int64_t>(pts->n - b, (int64_t)eq.cap);
-            const int fin = b + (int64_t)eq.cap >= pts->n ? 1 : 0;
-            const int g = (int)std::min<int64_t>(std::max<int64_t>(1, (m + CNT_THREADS * CNT_UNROLL_D - 1) /
-                                                                             (CNT_THREADS * CNT_UNROLL_D)), cus);
-            const double *X = m > 0 ? pts->x + b : pts->x, *Y = m > 0 ? pts->y + b : pts->y;
-            int rc = ldshist ? go(k_count<true, true, CNT_UNROLL_D>, std::max<int64_t>(m, 0), X, Y, g)
-                             : go(k_count<false, true, CNT_UNROLL_D>, std::max<int64_t>(m, 0), X, Y, g);
-            if (rc) return rc;
-            if (ldshist) {
-                SPADE_HIP(ctx, hipFuncSetAttribute((const void *)k_exact<true>,
-                                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)hl));
-                hipLaunchKernelGGL(k_exact<true>, dim3(eg), dim3(EX_THREADS), hl, st, v, eq, acc, done, o, fin);
-            } else {
-                hipLaunchKernelGGL(k_exact<false>, dim3(eg), dim3(EX_THREADS), 16, st, v, eq, acc, done, o, fin);
-            }
-            SPADE_HIP(ctx, hipGetLastError());
-        }
-    }
+    int rc = ldshist ? go(k_count<true, CNT_UNROLL>) : go(k_count<false, CNT_UNROLL>);
+    if (rc) return rc;
     if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[3], st));
-    return SPADE_OK;
-}
-
-// The exact queue of a context: room for as many points as the query has
-// (20 bytes each), at most EXQ_MAX (longer streams are probed in passes of
-// that many points); the counter lives after the arrays, zeroed when the slot
-// is (re)allocated and left zero by k_exact.
-constexpr int64_t EXQ_MAX = (int64_t)1 << 27;
-
-static int exact_queue(spade_ctx *ctx, int64_t n, ExactQueue &eq)
-{
-    const int64_t cap = std::min<int64_t>(std::max<int64_t>(n, 1 << 16), EXQ_MAX);
-    DevBuf &b = ctx->scratch[S_EXQ];
-    const size_t need = (size_t)cap * 20 + 64;
-    if (b.cap < need) {
-        if (ensure(ctx, b, need)) return SPADE_E_NOMEM;
-        SPADE_HIP(ctx, hipMemsetAsync(b.p, 0, b.cap, ctx->stream));
-    }
-    const int64_t room = (int64_t)((b.cap - 64) / 20);
-    eq.x = (double *)b.p;
-    eq.y = eq.x + room;
-    eq.rec = (uint32_t *)(eq.y + room);
-    eq.n = (unsigned long long *)(((uintptr_t)(eq.rec + room) + 7) & ~(uintptr_t)7);
-    eq.cap = (unsigned long long)room;
     return SPADE_OK;
 }
 
@@ -391,9 +250,7 @@ int probe_count(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts,
     unsigned int *done = nullptr;
     int rc = count_acc(ctx, M, &acc, &done);
     if (rc) return rc;
-    ExactQueue eq{nullptr, nullptr, nullptr, nullptr, 0ull};
-    if (ctx->defer_exact && (rc = exact_queue(ctx, pts->n, eq))) return rc;
-    return launch_count(ctx, cv, pts, out_counts, acc, done, eq);
+    return launch_count(ctx, cv, pts, out_counts, acc, done);
 }
 
 // ------------------------------------------------- stream-read reference
@@ -505,8 +362,7 @@ int probe_count_noalloc(spade_ctx *ctx, const spade_canvas *cv, const spade_poin
     hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)std::min<int64_t>((M + 256) / 256, 256)), dim3(256), 0,
                        ctx->stream, M + 1, acc);
     SPADE_HIP(ctx, hipGetLastError());
-    // no exact queue: each wavefront tests its own boundary points
-    return launch_count(ctx, cv, pts, out_counts, acc, done, ExactQueue{nullptr, nullptr, nullptr, nullptr, 0ull});
+    return launch_count(ctx, cv, pts, out_counts, acc, done);
 }
 
 // ------------------------------------------------------------ ordered emit

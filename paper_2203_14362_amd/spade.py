@@ -38,7 +38,7 @@ EXPORTS = [
     "spade_batch_select", "spade_batch_join_count", "spade_ctx_set_pixels_per_vertex",
     "spade_batch_rebuild", "spade_ctx_set_graphs", "spade_ctx_graph_stats", "spade_select_disk",
     "spade_ctx_build_stats", "spade_mem_info", "spade_canvas_join_count_noalloc",
-    "spade_ctx_set_exact_mode", "spade_stream_read", "spade_batch_join_pairs", "spade_layer_index",
+    "spade_stream_read", "spade_batch_join_pairs", "spade_layer_index",
     "spade_layered_build",
 ]
 
@@ -109,7 +109,6 @@ def load_library():
     lib.spade_ctx_set_graphs.argtypes = [vp, ctypes.c_int]
     lib.spade_ctx_graph_stats.argtypes = [vp, P(i64), P(i64)]
     lib.spade_ctx_build_stats.argtypes = [vp, P(i64), P(i64)]
-    lib.spade_ctx_set_exact_mode.argtypes = [vp, ctypes.c_int]
     lib.spade_batch_join_pairs.argtypes = [vp, vp, vp, vp, vp, i64, P(i64)]
     lib.spade_layer_index.argtypes = [vp, P(_Polys), i32, vp, P(i32)]
     lib.spade_layered_build.argtypes = [vp, P(_Polys), i32, P(vp), P(i32)]
@@ -316,11 +315,6 @@ class Context:
         c, r = ctypes.c_int64(), ctypes.c_int64()
         self._check(self.lib.spade_ctx_graph_stats(self.handle, ctypes.byref(c), ctypes.byref(r)))
         return c.value, r.value
-
-    def set_exact_mode(self, deferred: bool = True):
-        """Join-count exact tests deferred to a second kernel (default) or
-        run inline by the point stream."""
-        self._check(self.lib.spade_ctx_set_exact_mode(self.handle, 1 if deferred else 0))
 
     def stream_read(self, x, y, shape: int = 0):
         """Sum of all coordinates via one plain read of the points (bandwidth
