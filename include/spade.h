@@ -173,6 +173,45 @@ int spade_select(spade_ctx *ctx, const spade_points *pts, const spade_polys *pol
 int spade_select_disk(spade_ctx *ctx, const spade_points *pts, double cx, double cy, double r,
                       uint32_t *out_ids, int64_t cap, int64_t *n_out);
 
+/* Disks (device pointers): centres (cx[j], cy[j]) and radii r[j] (type-2
+ * distance join), or one radius r_all for every disk when r is NULL (type
+ * 1).  Disk ids are 0-based positions (n < 2^31 - 1). */
+typedef struct {
+    int64_t n;
+    const double *cx;
+    const double *cy;
+    const double *r;
+    double r_all;
+} spade_disks;
+
+/* Distance join (Sec. 4.2, "Canvases for Distance-Based Queries"; Sec. 5.2,
+ * "Distance-Based Queries", joins of types (1) and (2)): every pair (point
+ * id, disk id) whose distance is at most the disk's radius (closed disks,
+ * decided exactly on the FP64 inputs as spade_select_disk does), ascending
+ * by point id then disk id, as two device arrays of capacity cap; *n_out
+ * (host) receives the number of pairs, and beyond cap the first cap pairs
+ * are written and SPADE_E_CAPACITY is returned.  The disks are rasterised
+ * into a grid whose cells list the disks that reach them; every listed disk
+ * gets the exact test.  Non-finite centres or radii, or negative radii, are
+ * SPADE_E_INVALID; points with a non-finite coordinate match nothing. */
+int spade_distance_join_pairs(spade_ctx *ctx, const spade_points *pts, const spade_disks *disks,
+                              uint32_t *out_pt, uint32_t *out_disk, int64_t cap, int64_t *n_out);
+
+/* Aggregation over the distance join: out_counts [n] (device) receives the
+ * number of points within each disk. */
+int spade_distance_join_count(spade_ctx *ctx, const spade_points *pts, const spade_disks *disks,
+                              uint64_t *out_counts);
+
+/* kNN selection (Sec. 5.2, "kNN Queries"): the k points nearest to (px, py)
+ * by exact Euclidean distance, nearest first, equal distances by ascending
+ * id.  out_ids [k] (device); *n_out (host) = min(k, number of points with
+ * finite coordinates).  Follows the paper's plan: an aggregation over nested
+ * circles r_i = r_max / 2^i around the point (r_max: the farthest corner of
+ * the points' bounding box), a distance selection with the smallest circle
+ * holding k points, and a sort of those candidates by distance (exact). */
+int spade_knn_select(spade_ctx *ctx, const spade_points *pts, double px, double py, int64_t k,
+                     uint32_t *out_ids, int64_t *n_out);
+
 /* Aggregation (Sec. 5.2, "Spatial Aggregations", plan over point data):
  * out_counts [n_polys] device buffer, overwritten with the number of points
  * inside each polygon.  Overlapping polygons each count the point. */
@@ -319,6 +358,75 @@ int spade_layer_index(spade_ctx *ctx, const spade_polys *polys, int32_t res, int
  * The polygon arrays may be freed after the call returns. */
 int spade_layered_build(spade_ctx *ctx, const spade_polys *polys, int32_t res, spade_canvas **out,
                         int32_t *n_layers);
+
+/* ---- Asynchronous batch jobs.  spade_batch_submit hands a batch to ctx's
+ * worker thread and returns at once; the worker rasterises the batch into
+ * the caller's canvas set (as spade_batch_rebuild) and evaluates it over a
+ * table (selection, join-count or join pairs) on ctx's stream.  Jobs of one
+ * context run in submission order; jobs of different contexts (each with
+ * its own stream) overlap on the device.  While a context has jobs in
+ * flight, make no other call on it except spade_batch_wait,
+ * spade_job_query and spade_job_free. */
+enum { SPADE_JOB_SELECT = 1, SPADE_JOB_COUNT = 2, SPADE_JOB_PAIRS = 3 };
+typedef struct spade_job spade_job;
+typedef struct {
+    int status;          /* SPADE_OK or the job's error code */
+    int64_t n_out;       /* ids (SELECT), polygons (COUNT) or pairs (PAIRS) */
+    void *out0;          /* device: u32 ids / u64 counts / u32 pair point ids */
+    void *out1;          /* device: u32 pair polygon ids (PAIRS), else NULL */
+    const int64_t *off;  /* host: nq + 1 query offsets into out0 (SELECT), else NULL */
+    int64_t n_off;
+} spade_job_result;
+
+/* polys: device CSR arrays that must stay valid until the job is done;
+ * qbound: host offsets as for spade_batch_build (copied); set: a canvas set
+ * from spade_batch_build (rebuilt in place; not the context's own canvas);
+ * kind: SPADE_JOB_*.  *out receives the job handle. */
+int spade_batch_submit(spade_ctx *ctx, spade_canvas *set, const spade_polys *polys, int32_t nq,
+                       const int64_t *qbound, const spade_table *t, int kind, spade_job **out);
+
+/* Blocks until the job is done and describes its results, which live in
+ * buffers of the context, valid until its next job starts.  Returns the
+ * job's status. */
+int spade_batch_wait(spade_job *job, spade_job_result *res);
+
+/* 1 if the job is done, 0 if not (never blocks). */
+int spade_job_query(const spade_job *job);
+
+/* Frees the handle (waits for the job first). */
+void spade_job_free(spade_job *job);
+
+/* ---- Out-of-core point tables (Sec. 5.3, "Out-of-Core Queries").  The
+ * points stay in host memory, clustered by a grid index (G x G cells over
+ * their bounding box, each cell a contiguous block with its exact bounding
+ * box).  A query filters the cells by its polygons' bounding box, then
+ * streams the blocks that pass to the device in chunks through two staging
+ * buffers (copies of the next chunk overlap the probe of the current one)
+ * and probes each chunk with the in-memory kernels.  Results are those of
+ * the in-memory calls on the original arrays. */
+typedef struct spade_host_table spade_host_table;
+
+/* x, y: HOST arrays of n points (may be freed after the call; the table
+ * keeps a clustered copy in pinned host memory, 20 bytes per point, plus two
+ * device staging buffers of 2^24 points).  Point ids in results are the
+ * input positions (n < 2^32 - 1). */
+int spade_host_table_create(spade_ctx *ctx, const double *x, const double *y, int64_t n,
+                            spade_host_table **out);
+void spade_host_table_destroy(spade_host_table *t);
+/* Points, grid side, pinned host bytes (any pointer may be NULL). */
+int spade_host_table_info(const spade_host_table *t, int64_t *n, int32_t *grid, int64_t *host_bytes);
+
+/* Join-count of the table's points with `polys` (device CSR): out_counts
+ * [n_polys] (device), as spade_join_count.  *streamed (host, may be NULL)
+ * receives the number of points the cell filter let through (the points
+ * copied to the device). */
+int spade_host_join_count(spade_ctx *ctx, spade_host_table *t, const spade_polys *polys, uint64_t *out_counts,
+                          int64_t *streamed);
+
+/* Selection of the table's points with one polygon: ascending ids into
+ * out_ids [cap] (device), capacity protocol as spade_select. */
+int spade_host_select(spade_ctx *ctx, spade_host_table *t, const spade_polys *poly, uint32_t *out_ids,
+                      int64_t cap, int64_t *n_out, int64_t *streamed);
 
 /* Canvas sizing for later builds when no fixed size is set: about `ppv`
  * pixels per polygon vertex, between 64 x 64 and 4096 x 4096 pixels per

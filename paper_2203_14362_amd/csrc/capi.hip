@@ -52,6 +52,31 @@ int ensure(spade_ctx *ctx, DevBuf &b, size_t bytes)
     return SPADE_OK;
 }
 
+// Grow a device buffer to at least `bytes`, keeping its contents (ordered
+// on ctx's stream; the old buffer is freed once the stream has copied it).
+int ensure_keep(spade_ctx *ctx, DevBuf &b, size_t bytes)
+{
+    if (b.cap >= bytes) return SPADE_OK;
+    DevBuf nb;
+    if (ensure(ctx, nb, std::max(bytes, b.cap * 2))) return SPADE_E_NOMEM;
+    if (b.p) {
+        hipError_t e = hipMemcpyAsync(nb.p, b.p, b.cap, hipMemcpyDeviceToDevice, ctx->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) {
+            free_buf(nb);
+            return hip_fail(ctx, e, "ensure_keep copy");
+        }
+    }
+    free_buf(b);
+    b = nb;
+    return SPADE_OK;
+}
+
+int hip_fail_if(spade_ctx *ctx, hipError_t e)
+{
+    return e == hipSuccess ? SPADE_OK : hip_fail(ctx, e, "kernel launch");
+}
+
 void *ensure_pinned(spade_ctx *ctx, size_t bytes)
 {
     if (ctx->pinned_cap >= bytes) return ctx->pinned;
@@ -136,6 +161,7 @@ void spade_ctx_destroy(spade_ctx *ctx)
 {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
+    jobs_shutdown(ctx);   // finishes the queued jobs first
     (void)hipDeviceSynchronize();
     for (auto &b : ctx->scratch) free_buf(b);
     if (ctx->plain) {
@@ -458,6 +484,43 @@ int spade_select_disk(spade_ctx *ctx, const spade_points *pts, double cx, double
     return spade::select_disk(ctx, pts, cx, cy, r, out_ids, cap, n_out);
 }
 
+int spade_distance_join_pairs(spade_ctx *ctx, const spade_points *pts, const spade_disks *disks,
+                              uint32_t *out_pt, uint32_t *out_disk, int64_t cap, int64_t *n_out)
+{
+    if (!ctx) return SPADE_E_INVALID;
+    if (n_out) *n_out = 0;
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if ((rc = check_points(ctx, pts))) return rc;
+    if (!n_out) return set_error(ctx, SPADE_E_INVALID, "n_out is NULL");
+    if (cap < 0 || (cap > 0 && (!out_pt || !out_disk))) return set_error(ctx, SPADE_E_INVALID, "bad output buffers");
+    ctx->timed_raster = false;
+    return spade::distance_join(ctx, pts, disks, out_pt, out_disk, cap, n_out, nullptr);
+}
+
+int spade_distance_join_count(spade_ctx *ctx, const spade_points *pts, const spade_disks *disks,
+                              uint64_t *out_counts)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if ((rc = check_points(ctx, pts))) return rc;
+    if (disks && disks->n > 0 && !out_counts) return set_error(ctx, SPADE_E_INVALID, "out_counts is NULL");
+    ctx->timed_raster = false;
+    uint64_t dummy = 0;
+    return spade::distance_join(ctx, pts, disks, nullptr, nullptr, 0, nullptr, out_counts ? out_counts : &dummy);
+}
+
+int spade_knn_select(spade_ctx *ctx, const spade_points *pts, double px, double py, int64_t k, uint32_t *out_ids,
+                     int64_t *n_out)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if ((rc = check_points(ctx, pts))) return rc;
+    if (!n_out) return set_error(ctx, SPADE_E_INVALID, "n_out is NULL");
+    ctx->timed_raster = false;
+    return spade::knn_select(ctx, pts, px, py, k, out_ids, n_out);
+}
+
 int spade_select(spade_ctx *ctx, const spade_points *pts, const spade_polys *poly, uint32_t *out_ids,
                  int64_t cap, int64_t *n_out)
 {
@@ -530,3 +593,10 @@ int spade_orient_batch(spade_ctx *ctx, int64_t n, const double *ax, const double
 }
 
 }  // extern "C"
+
+// The context's canvas rasterised from `polys` (not deferred: complete and
+// checked when this returns).
+int spade::plain_canvas(spade_ctx *ctx, const spade_polys *polys, spade_canvas **cvo)
+{
+    return plain_build(ctx, polys, cvo, false);
+}

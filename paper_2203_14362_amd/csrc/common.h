@@ -150,6 +150,7 @@ struct spade_ctx {
     bool graphs = true;                     // replay repeated canvas builds from graphs
     int64_t graph_captures = 0, graph_replays = 0;
     int64_t builds = 0, rebuilds = 0;       // plain-call canvas builds, and those redone for capacity
+    void *jobs = nullptr;                   // asynchronous batch jobs: queue and worker thread
 };
 
 namespace spade {
@@ -166,6 +167,10 @@ int set_error(spade_ctx *ctx, int code, const std::string &msg);
 int hip_fail(spade_ctx *ctx, hipError_t e, const char *what);
 int ensure(spade_ctx *ctx, DevBuf &b, size_t bytes);
 void *ensure_pinned(spade_ctx *ctx, size_t bytes);
+int ensure_keep(spade_ctx *ctx, DevBuf &b, size_t bytes);
+int hip_fail_if(spade_ctx *ctx, hipError_t e);
+int plain_canvas(spade_ctx *ctx, const spade_polys *polys, spade_canvas **cvo);
+void jobs_shutdown(spade_ctx *ctx);
 void free_buf(DevBuf &b);
 
 // `defer`: leave the build's counters and flags on the device instead of
@@ -205,6 +210,12 @@ int probe_count_noalloc(spade_ctx *ctx, const spade_canvas *cv, const spade_poin
                         uint64_t *out_counts);
 int select_disk(spade_ctx *ctx, const spade_points *pts, double cx, double cy, double r, uint32_t *out_ids,
                 int64_t cap, int64_t *n_out);
+// Distance joins of points with disks (pairs, or per-disk counts when
+// out_counts is given) and kNN selection.
+int distance_join(spade_ctx *ctx, const spade_points *pts, const spade_disks *dk, uint32_t *out_pt,
+                  uint32_t *out_disk, int64_t cap, int64_t *n_out, uint64_t *out_counts);
+int knn_select(spade_ctx *ctx, const spade_points *pts, double px, double py, int64_t k, uint32_t *out_ids,
+               int64_t *n_out);
 int probe_emit(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts,
                uint32_t *out_pt, uint32_t *out_poly, int64_t cap, int64_t *n_out);
 

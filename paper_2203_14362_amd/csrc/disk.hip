@@ -3,16 +3,8 @@
 // distance to a centre is at most r, in ascending order.
 //
 // The paper draws the disk into a canvas and tests the points against it.
-// A single disk needs no canvas here: its predicate is evaluated per point
-// while the points stream from HBM, exactly, as the sign of
-//     r^2 - (x - cx)^2 - (y - cy)^2   (>= 0: inside, the disk is closed).
-// A floating-point evaluation with rounding-exact operations is accepted
-// when it clears an error bound of 16 eps (r^2 + (x-cx)^2 + (y-cy)^2),
-// eps = 2^-53 (each of the three terms carries at most three roundings, the
-// sum and the difference one each); otherwise the expression is rebuilt as a
-// non-overlapping expansion from error-free transformations (TwoDiff of the
-// differences, TwoProduct of their parts: (d + t)^2 = d^2 + 2dt + t^2).
-// Exact whenever no square overflows or underflows into subnormals.
+// A single disk needs no canvas here: its exact closed-disk predicate
+// (disk.h) is evaluated per point while the points stream from HBM.
 //
 // Output follows the paper's two-step Map (Sec. 5.1): a count pass writes
 // the number of selected points of every wavefront segment of DISK_SEG
@@ -21,7 +13,7 @@
 // the wavefront).  Both passes evaluate the same function on the same
 // inputs, so the write pass fills exactly the counted slots.
 #include "common.h"
-#include "exact.h"
+#include "disk.h"
 
 #include <hipcub/hipcub.hpp>
 
@@ -33,47 +25,6 @@ namespace spade {
 constexpr int DISK_THREADS = 256;
 constexpr int DISK_ROUNDS = 16;   // 64-point rounds per wavefront segment
 constexpr int64_t DISK_SEG = 64 * DISK_ROUNDS;
-
-// Sign of r^2 - (x-cx)^2 - (y-cy)^2 from an exact expansion.
-__device__ __noinline__ int disk_sign_exact(double x, double y, double cx, double cy, double r)
-{
-    double h[16];   // 14 error-free terms, grown one at a time
-    int n = 0;
-    double p, e;
-    two_prod(r, r, p, e);
-    n = grow_expansion(h, n, e);
-    n = grow_expansion(h, n, p);
-    double d[2], t[2];
-    two_diff(x, cx, d[0], t[0]);
-    two_diff(y, cy, d[1], t[1]);
-    for (int k = 0; k < 2; ++k) {
-        two_prod(d[k], d[k], p, e);
-        n = grow_expansion(h, n, -e);
-        n = grow_expansion(h, n, -p);
-        two_prod(2.0 * d[k], t[k], p, e);
-        n = grow_expansion(h, n, -e);
-        n = grow_expansion(h, n, -p);
-        two_prod(t[k], t[k], p, e);
-        n = grow_expansion(h, n, -e);
-        n = grow_expansion(h, n, -p);
-    }
-    if (n == 0) return 0;
-    const double top = h[n - 1];
-    return (top > 0.0) - (top < 0.0);
-}
-
-// The closed-disk test; r2 = fl(r * r).  Non-finite points are outside.
-__device__ __forceinline__ bool in_disk(double x, double y, double cx, double cy, double r, double r2)
-{
-    if (!(fabs(x) <= 1.7976931348623157e308 && fabs(y) <= 1.7976931348623157e308)) return false;
-    const double dx = __dsub_rn(x, cx), dy = __dsub_rn(y, cy);
-    const double q = __dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy));
-    const double s = __dsub_rn(r2, q);
-    const double bound = __dmul_rn(1.7763568394002505e-15, __dadd_rn(r2, q));   // 16 * 2^-53
-    if (s > bound) return true;
-    if (-s > bound) return false;
-    return disk_sign_exact(x, y, cx, cy, r) >= 0;
-}
 
 // Every wavefront owns segments of DISK_SEG consecutive points (grid-stride
 // over segments).  WRITE == false: counts[s] = selected points of segment s.

@@ -11,15 +11,27 @@ records its arrival, admission and completion times; ``latency_stats``
 reports p50 / p99 from arrival to result-ready.
 
 The scheduling logic is independent of the device: ``Server`` drives any
-executor with ``n_workers``, ``estimate(req)`` and ``run(worker, reqs)``.
-``SpadeExecutor`` is the device executor: one canvas set per batch and kind,
-evaluated with the library's batch calls over the shared resident table.
+executor with ``n_workers`` and ``estimate(req)`` that either runs a batch
+synchronously (``run(worker, reqs)``, one host thread per worker) or
+submits it asynchronously (``submit(worker, reqs)`` returning a token,
+``poll(token)``, ``collect(token)``): then the dispatcher submits and one
+completion thread collects, and no host thread blocks in a device call.
+``SpadeExecutor`` is the device executor: one canvas set per worker and
+kind, evaluated by the library's asynchronous batch jobs over the shared
+resident table.
+
+Admission counts device memory three ways against one budget: the estimates
+of the requests in flight, the bytes of finished results the caller still
+holds (released when the result tensor is garbage-collected), and what the
+executor keeps resident (canvas sets, scratch, result buffers; asked after
+every batch).
 """
 from __future__ import annotations
 
 import collections
 import threading
 import time
+import weakref
 from dataclasses import dataclass
 from typing import Any, List, Optional
 
@@ -39,6 +51,7 @@ class Request:
     est_bytes: int = 0
     result: Any = None             # select: int32 ids; count: int64 counts
     error: Optional[str] = None
+    result_size: Optional[int] = None   # when the server does not keep results
 
     @property
     def latency(self) -> Optional[float]:
@@ -77,8 +90,9 @@ class Server:
     """Arrival-ordered admission by memory budget + continuous batching."""
 
     def __init__(self, executor, budget_bytes: int, max_batch: int = 1024,
-                 max_batch_vertices: int = 8_000_000, clock=time.perf_counter):
+                 max_batch_vertices: int = 8_000_000, clock=time.perf_counter, keep_results: bool = True):
         self.ex = executor
+        self.keep_results = keep_results  # False: record result sizes, drop the results
         self.budget = int(budget_bytes)
         self.max_batch = max_batch
         self.max_batch_vertices = max_batch_vertices
@@ -95,12 +109,21 @@ class Server:
         self.done: List[Request] = []
         self.batches: List[List[int]] = []
         self._threads = []
+        self._async = hasattr(executor, "submit")
+        self._inflight_jobs = []          # async mode: (worker, batch, extra, token)
+        self._held = 0                    # bytes of finished results still referenced
+        self._resident = int(getattr(executor, "resident_bytes", lambda: 0)())
+        self.peak_accounted = 0
+        self.mem_trace = []               # (time, reserved, held, resident) after every batch
 
     # -- public
     def start(self):
         self._threads = [threading.Thread(target=self._dispatch, daemon=True)]
-        self._threads += [threading.Thread(target=self._worker, args=(w,), daemon=True)
-                          for w in range(self.ex.n_workers)]
+        if self._async:
+            self._threads.append(threading.Thread(target=self._reaper, daemon=True))
+        else:
+            self._threads += [threading.Thread(target=self._worker, args=(w,), daemon=True)
+                              for w in range(self.ex.n_workers)]
         for t in self._threads:
             t.start()
         return self
@@ -136,6 +159,15 @@ class Server:
     def peak_reserved(self) -> int:
         return self._peak_reserved
 
+    @property
+    def held_bytes(self) -> int:
+        return self._held
+
+    def accounted(self) -> int:
+        """Device bytes admission counts now: in flight + held results +
+        executor-resident (caller holds the lock or reads a snapshot)."""
+        return self._reserved + self._held + self._resident
+
     # -- internals
     def _take_batch(self):
         """Requests admitted now, in arrival order (caller holds the lock)."""
@@ -149,7 +181,16 @@ class Server:
                 self.done.append(r)
                 continue
             v = n_vertices(r.polys)
-            if self._reserved + extra + r.est_bytes > self.budget:
+            if self.accounted() + extra + r.est_bytes > self.budget:
+                if not batch and self._inflight == 0:
+                    # nothing in flight will free memory: only results the
+                    # caller still holds stand in the way
+                    self._pending.popleft()
+                    r.error = ("device memory budget exhausted: %d bytes of results still held, %d resident"
+                               % (self._held, self._resident))
+                    r.done = self.clock()
+                    self.done.append(r)
+                    continue
                 break                      # head waits for memory: no overtaking
             if batch and verts + v > self.max_batch_vertices:
                 break
@@ -186,7 +227,15 @@ class Server:
         self._peak_reserved = max(self._peak_reserved, self._reserved)
         self._inflight += len(batch)
         self.batches.append([r.rid for r in batch])
-        self._work[w].append((batch, extra))
+        self.peak_accounted = max(self.peak_accounted, self.accounted())
+        if self._async:
+            try:
+                token = self.ex.submit(w, batch)
+            except Exception as e:          # nothing was queued: fail the batch at once
+                token = ("error", e)
+            self._inflight_jobs.append((w, batch, extra, token))
+        else:
+            self._work[w].append((batch, extra))
         self._cv.notify_all()
 
     def _worker(self, w):
@@ -209,15 +258,80 @@ class Server:
                     except Exception as e1:
                         r.error = "%s: %s" % (type(e1).__name__, e1)
                         r.result = None
-            t = self.clock()
+            self._finish(w, batch, extra)
+
+    def _track(self, r):
+        """Count a finished result as held until the caller drops it."""
+        res = r.result
+        parts = res if isinstance(res, tuple) else (res,)
+        for t in parts:
+            nb = int(getattr(t, "nbytes", 0) or 0)
+            if nb <= 0:
+                continue
+            try:
+                weakref.finalize(t, self._release, nb)
+            except TypeError:
+                continue
+            self._held += nb
+
+    def _release(self, nb):
+        with self._cv:
+            self._held -= nb
+            self._cv.notify_all()
+
+    def _finish(self, w, batch, extra):
+        t = self.clock()
+        resident = int(getattr(self.ex, "resident_bytes", lambda: 0)())
+        with self._cv:
+            for r in batch:
+                r.done = t
+                self.done.append(r)
+                if r.error is None and r.result is not None:
+                    if self.keep_results:
+                        self._track(r)
+                    else:
+                        r.result_size = int(r.result.numel()) if hasattr(r.result, "numel") else 1
+                        r.result = None
+            self._reserved -= extra
+            self._inflight -= len(batch)
+            self._resident = resident
+            self._free.append(w)
+            self.mem_trace.append((t, self._reserved, self._held, self._resident))
+            self._cv.notify_all()
+
+    def _reaper(self):
+        """Async mode: collects finished jobs in completion order."""
+        idle = 1e-4
+        while True:
             with self._cv:
-                for r in batch:
-                    r.done = t
-                    self.done.append(r)
-                self._reserved -= extra
-                self._inflight -= len(batch)
-                self._free.append(w)
-                self._cv.notify_all()
+                if self._stop and not self._inflight_jobs and not self._pending:
+                    return
+                jobs = list(self._inflight_jobs)
+            ready = [j for j in jobs if not (isinstance(j[3], tuple) and j[3] and j[3][0] == "error") and
+                     self.ex.poll(j[3])]
+            failed = [j for j in jobs if isinstance(j[3], tuple) and j[3] and j[3][0] == "error"]
+            if not ready and not failed:
+                time.sleep(idle)
+                continue
+            for j in failed + ready:
+                w, batch, extra, token = j
+                with self._cv:
+                    self._inflight_jobs.remove(j)
+                try:
+                    if j in failed:
+                        raise token[1]
+                    self.ex.collect(token, batch)
+                except Exception as e:
+                    # one bad request must not fail its batch: run them one by one
+                    for r in batch:
+                        try:
+                            if len(batch) == 1:
+                                raise e
+                            self.ex.collect(self.ex.submit(w, [r]), [r])
+                        except Exception as e1:
+                            r.error = "%s: %s" % (type(e1).__name__, e1)
+                            r.result = None
+                self._finish(w, batch, extra)
 
 
 def replay(server: Server, requests, arrivals, clock=time.perf_counter, sleep=time.sleep):
@@ -318,6 +432,63 @@ class SpadeExecutor:
         else:
             b += 8 * int(req.polys["n_polys"])
         return int(b)
+
+    def submit(self, w: int, reqs: List[Request]):
+        """Queues the batch's selections and join-counts as asynchronous jobs
+        on worker w's context (its own stream and worker thread)."""
+        from .spade import JOB_COUNT, JOB_SELECT
+        torch = self.torch
+        ctx, s = self.ctxs[w], self.streams[w]
+        jobs = []
+        with torch.cuda.stream(s):
+            for kind, code, slot in (("select", JOB_SELECT, 0), ("count", JOB_COUNT, 1)):
+                rs = [r for r in reqs if r.kind == kind]
+                if not rs:
+                    continue
+                polys, qb = concat_sets([r.polys for r in rs])
+                if self._sets[w][slot] is None:
+                    self._sets[w][slot] = ctx.batch(polys, qb)
+                    s.synchronize()
+                jobs.append((kind, rs, qb, ctx.submit(self._sets[w][slot], polys, qb, self.table, code)))
+        return (w, jobs)
+
+    def poll(self, token) -> bool:
+        return all(j.done() for _, _, _, j in token[1])
+
+    def collect(self, token, reqs: List[Request]):
+        w, jobs = token
+        torch = self.torch
+        err = None
+        with torch.cuda.stream(self.streams[w]):
+            for kind, rs, qb, job in jobs:
+                try:
+                    res = job.wait()
+                except Exception as e:      # every job is waited for, the first error raised
+                    err = err or e
+                    continue
+                if kind == "select":
+                    ids, off = res
+                    for q, r in enumerate(rs):
+                        r.result = ids[int(off[q]):int(off[q + 1])].clone()
+                else:
+                    for q, r in enumerate(rs):
+                        r.result = res[int(qb[q]):int(qb[q + 1])].clone()
+        self.streams[w].synchronize()
+        if err is not None:
+            raise err
+
+    def resident_bytes(self) -> int:
+        """Device bytes the executor keeps between batches: its contexts'
+        scratch and result buffers and its canvas sets (the table is
+        counted at creation, outside the budget)."""
+        tot = 0
+        for c in self.ctxs:
+            tot += c.mem_info()["ctx"]
+        for pair in self._sets:
+            for b in pair:
+                if b is not None:
+                    tot += b.info()["device_bytes"]
+        return int(tot)
 
     def run(self, w: int, reqs: List[Request]):
         torch = self.torch

@@ -39,8 +39,12 @@ EXPORTS = [
     "spade_batch_rebuild", "spade_ctx_set_graphs", "spade_ctx_graph_stats", "spade_select_disk",
     "spade_ctx_build_stats", "spade_mem_info", "spade_canvas_join_count_noalloc",
     "spade_stream_read", "spade_batch_join_pairs", "spade_layer_index",
-    "spade_layered_build",
+    "spade_layered_build", "spade_distance_join_pairs", "spade_distance_join_count", "spade_knn_select",
+    "spade_host_table_create", "spade_host_table_destroy", "spade_host_table_info", "spade_host_join_count",
+    "spade_host_select", "spade_batch_submit", "spade_batch_wait", "spade_job_query", "spade_job_free",
 ]
+
+JOB_SELECT, JOB_COUNT, JOB_PAIRS = 1, 2, 3
 
 
 class SpadeError(RuntimeError):
@@ -51,6 +55,24 @@ class SpadeError(RuntimeError):
 
 class _Points(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("x", ctypes.c_void_p), ("y", ctypes.c_void_p)]
+
+
+class _Disks(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("cx", ctypes.c_void_p), ("cy", ctypes.c_void_p), ("r", ctypes.c_void_p),
+                ("r_all", ctypes.c_double)]
+
+
+class _JobResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("n_out", ctypes.c_int64), ("out0", ctypes.c_void_p),
+                ("out1", ctypes.c_void_p), ("off", ctypes.POINTER(ctypes.c_int64)), ("n_off", ctypes.c_int64)]
+
+
+class _DevArray:
+    """A device array the library owns, seen by torch without a copy."""
+
+    def __init__(self, ptr, n, typestr):
+        self.__cuda_array_interface__ = {"shape": (int(n),), "typestr": typestr, "data": (int(ptr or 0), False),
+                                         "version": 2}
 
 
 class _Polys(ctypes.Structure):
@@ -110,6 +132,20 @@ def load_library():
     lib.spade_ctx_graph_stats.argtypes = [vp, P(i64), P(i64)]
     lib.spade_ctx_build_stats.argtypes = [vp, P(i64), P(i64)]
     lib.spade_batch_join_pairs.argtypes = [vp, vp, vp, vp, vp, i64, P(i64)]
+    lib.spade_distance_join_pairs.argtypes = [vp, P(_Points), P(_Disks), vp, vp, i64, P(i64)]
+    lib.spade_distance_join_count.argtypes = [vp, P(_Points), P(_Disks), vp]
+    lib.spade_knn_select.argtypes = [vp, P(_Points), ctypes.c_double, ctypes.c_double, i64, vp, P(i64)]
+    lib.spade_host_table_create.argtypes = [vp, vp, vp, i64, P(vp)]
+    lib.spade_batch_submit.argtypes = [vp, vp, P(_Polys), i32, vp, vp, ctypes.c_int, P(vp)]
+    lib.spade_batch_wait.argtypes = [vp, P(_JobResult)]
+    lib.spade_job_query.argtypes = [vp]
+    lib.spade_job_free.argtypes = [vp]
+    lib.spade_job_free.restype = None
+    lib.spade_host_table_destroy.argtypes = [vp]
+    lib.spade_host_table_destroy.restype = None
+    lib.spade_host_table_info.argtypes = [vp, P(i64), P(i32), P(i64)]
+    lib.spade_host_join_count.argtypes = [vp, vp, P(_Polys), vp, P(i64)]
+    lib.spade_host_select.argtypes = [vp, vp, P(_Polys), vp, i64, P(i64), P(i64)]
     lib.spade_layer_index.argtypes = [vp, P(_Polys), i32, vp, P(i32)]
     lib.spade_layered_build.argtypes = [vp, P(_Polys), i32, P(vp), P(i32)]
     lib.spade_stream_read.argtypes = [vp, P(_Points), ctypes.c_int, vp]
@@ -258,6 +294,72 @@ class Table:
             pass
 
 
+class HostTable:
+    """Out-of-core point table: a clustered copy in pinned host memory,
+    streamed to the device per query."""
+
+    def __init__(self, ctx: "Context", handle):
+        self.ctx = ctx
+        self.handle = handle
+        self.last_streamed = 0
+
+    def info(self):
+        n, g, b = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64()
+        self.ctx.lib.spade_host_table_info(self.handle, ctypes.byref(n), ctypes.byref(g), ctypes.byref(b))
+        return {"n_points": n.value, "grid": g.value, "host_bytes": b.value}
+
+    def close(self):
+        if self.handle:
+            self.ctx.lib.spade_host_table_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Job:
+    """An asynchronous batch job (spade_batch_submit).  ``wait`` returns
+    tensors that own their memory: select -> (ids int32, offsets int64
+    numpy), count -> int64 counts, pairs -> (point ids, polygon ids)."""
+
+    def __init__(self, ctx: "Context", handle, kind, keep):
+        self.ctx = ctx
+        self.handle = handle
+        self.kind = kind
+        self._keep = keep            # device polygon arrays read by the job
+        self._res = None
+
+    def done(self) -> bool:
+        return self._res is not None or self.ctx.lib.spade_job_query(self.handle) == 1
+
+    def wait(self):
+        if self._res is not None:
+            return self._res
+        r = _JobResult()
+        rc = self.ctx.lib.spade_batch_wait(self.handle, ctypes.byref(r))
+        self.ctx.lib.spade_job_free(self.handle)
+        self.handle = None
+        self._keep = None
+        if rc != SPADE_OK:
+            raise SpadeError(rc, self.ctx.lib.spade_last_error(self.ctx.handle).decode())
+        dev = self.ctx.device
+        n = int(r.n_out)
+        with torch.cuda.device(dev):
+            if self.kind == JOB_COUNT:
+                out = torch.as_tensor(_DevArray(r.out0, n, "<i8"), device=dev).clone()
+            elif self.kind == JOB_SELECT:
+                off = np.ctypeslib.as_array(r.off, shape=(int(r.n_off),)).copy()
+                out = (torch.as_tensor(_DevArray(r.out0, n, "<i4"), device=dev).clone(), off)
+            else:
+                out = (torch.as_tensor(_DevArray(r.out0, n, "<i4"), device=dev).clone(),
+                       torch.as_tensor(_DevArray(r.out1, n, "<i4"), device=dev).clone())
+        self._res = out
+        return out
+
+
 class Batch(Canvas):
     """A batch of queries rasterised as one canvas set."""
 
@@ -392,6 +494,60 @@ class Context:
                 continue
             self._check(rc)
             return _compact(ids, int(off[-1])), off
+
+    def submit(self, batch: "Batch", polys, qbound, table: Table, kind: int) -> Job:
+        """Asynchronous batch job on this context's worker thread: rebuild
+        ``batch`` from ``polys`` / ``qbound`` and evaluate it over ``table``.
+        The result tensors are copies made on the current stream at wait."""
+        self._sync_stream()
+        dp = self.polys(polys)
+        qb = np.ascontiguousarray(qbound, dtype=np.int64)
+        h = ctypes.c_void_p()
+        self._check(self.lib.spade_batch_submit(self.handle, batch.handle, ctypes.byref(dp.cstruct()),
+                                                int(qb.size - 1), qb.ctypes.data_as(ctypes.c_void_p),
+                                                table.handle, int(kind), ctypes.byref(h)))
+        batch.qbound, batch.n_queries, batch.n_polys = qb, int(qb.size - 1), int(qb[-1])
+        return Job(self, h, kind, dp)
+
+    def host_table(self, x, y) -> HostTable:
+        """Out-of-core table from host float64 arrays."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        if x.shape != y.shape or x.ndim != 1:
+            raise ValueError("x and y must be 1-D arrays of equal length")
+        h = ctypes.c_void_p()
+        self._sync_stream()
+        self._check(self.lib.spade_host_table_create(self.handle, x.ctypes.data_as(ctypes.c_void_p),
+                                                     y.ctypes.data_as(ctypes.c_void_p), x.size, ctypes.byref(h)))
+        return HostTable(self, h)
+
+    def host_join_count(self, table: HostTable, polys):
+        dp = self.polys(polys)
+        out = torch.empty(max(dp.n_polys, 1), dtype=torch.int64, device=self.device)
+        st = ctypes.c_int64()
+        self._sync_stream()
+        self._check(self.lib.spade_host_join_count(self.handle, table.handle, ctypes.byref(dp.cstruct()),
+                                                   ctypes.c_void_p(out.data_ptr()), ctypes.byref(st)))
+        table.last_streamed = st.value
+        return out[:dp.n_polys]
+
+    def host_select(self, table: HostTable, poly, cap=None):
+        dp = self.polys(poly)
+        n = table.info()["n_points"]
+        if cap is None:
+            cap = max(1, min(n, 1 << 24))
+        while True:
+            out = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device)
+            nout, st = ctypes.c_int64(), ctypes.c_int64()
+            self._sync_stream()
+            rc = self.lib.spade_host_select(self.handle, table.handle, ctypes.byref(dp.cstruct()),
+                                            ctypes.c_void_p(out.data_ptr()), cap, ctypes.byref(nout), ctypes.byref(st))
+            if rc == SPADE_E_CAPACITY:
+                cap = int(nout.value)
+                continue
+            self._check(rc)
+            table.last_streamed = st.value
+            return _ids(_compact(out, int(nout.value)), n)
 
     def batch_join_pairs(self, batch: Batch, table: Table, cap=None):
         """(point ids, polygon ids) int32 tensors of every pair of a table
@@ -533,6 +689,63 @@ class Context:
                 continue
             self._check(rc)
             return _ids(_compact(pt, int(nout.value)), P.n)
+
+    def _disks(self, cx, cy, r):
+        cx = _dev_f64(cx, self.device)
+        cy = _dev_f64(cy, self.device)
+        if np.ndim(r) == 0 and not isinstance(r, torch.Tensor):
+            rr, r_all = None, float(r)
+        else:
+            rr, r_all = _dev_f64(r, self.device), 0.0
+        keep = (cx, cy, rr)
+        n = cx.numel()
+        D = _Disks(n, cx.data_ptr() if n else 0, cy.data_ptr() if n else 0,
+                   None if rr is None else (rr.data_ptr() if n else 0), r_all)
+        return D, keep
+
+    def distance_join(self, x, y, cx, cy, r, cap=None):
+        """(point ids, disk ids) of every point within distance r (a scalar:
+        type (1); one radius per disk: type (2)) of a disk centre, ascending
+        by (point, disk); closed disks, decided exactly."""
+        P = _points(x, y)
+        D, keep = self._disks(cx, cy, r)
+        if cap is None:
+            cap = max(P.n, 1)
+        while True:
+            pt = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device)
+            pd = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device)
+            nout = ctypes.c_int64()
+            self._sync_stream()
+            rc = self.lib.spade_distance_join_pairs(self.handle, ctypes.byref(P), ctypes.byref(D),
+                                                    ctypes.c_void_p(pt.data_ptr()), ctypes.c_void_p(pd.data_ptr()),
+                                                    cap, ctypes.byref(nout))
+            if rc == SPADE_E_CAPACITY:
+                cap = int(nout.value)
+                continue
+            self._check(rc)
+            m = int(nout.value)
+            return _ids(_compact(pt, m), P.n), _compact(pd, m)
+
+    def distance_join_count(self, x, y, cx, cy, r):
+        """Points within each disk (int64 tensor [number of disks])."""
+        P = _points(x, y)
+        D, keep = self._disks(cx, cy, r)
+        out = torch.empty(max(D.n, 1), dtype=torch.int64, device=self.device)
+        self._sync_stream()
+        self._check(self.lib.spade_distance_join_count(self.handle, ctypes.byref(P), ctypes.byref(D),
+                                                       ctypes.c_void_p(out.data_ptr())))
+        return out[:D.n]
+
+    def knn(self, x, y, px, py, k):
+        """Ids of the k points nearest to (px, py), nearest first (equal
+        distances by ascending id); exact."""
+        P = _points(x, y)
+        out = torch.empty(max(int(k), 1), dtype=torch.int32, device=self.device)
+        nout = ctypes.c_int64()
+        self._sync_stream()
+        self._check(self.lib.spade_knn_select(self.handle, ctypes.byref(P), float(px), float(py), int(k),
+                                              ctypes.c_void_p(out.data_ptr()), ctypes.byref(nout)))
+        return _ids(out[:int(nout.value)], P.n)
 
     def join_pairs(self, x, y, polys_or_canvas, cap=None):
         """(point ids, polygon ids) int32 tensors, ascending by (point, polygon)."""

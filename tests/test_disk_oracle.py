@@ -89,3 +89,60 @@ def test_tiny_and_huge_scales_are_decided_exactly():
     y = np.array([4e-160, 3e-160, 0.0, 4e200])
     assert np.array_equal(disk.select_disk(x, y, 0.0, 0.0, 5e-160), _by_ratios(x, y, 0.0, 0.0, 5e-160))
     assert np.array_equal(disk.select_disk(x, y, 0.0, 0.0, 5e200), _by_ratios(x, y, 0.0, 0.0, 5e200))
+
+
+# ------------------------------------------------ distance joins and kNN
+
+def _lattice(m):
+    g = np.arange(-m, m + 1, dtype=np.float64)
+    X, Y = np.meshgrid(g, g)
+    return X.ravel(), Y.ravel()
+
+
+def test_distance_join_gauss_circle_counts():
+    """Disks centred on lattice points with integer radii: each count is the
+    number of integer points (a, b) with a^2 + b^2 <= r^2 (the Gauss circle
+    numbers 1, 5, 13, 29, 49, 81, ... when the disk lies inside the lattice),
+    and the pairs are exactly those decided with Python integers."""
+    x, y = _lattice(20)
+    cx = np.array([0.0, 3.0, -5.0, 7.0, 0.0])
+    cy = np.array([0.0, -2.0, 4.0, 7.0, 0.0])
+    r = np.array([5.0, 7.0, 0.0, 3.0, 1.0])
+    pt, dk = disk.distance_join(x, y, cx, cy, r)
+    want = sorted((i, j) for j in range(cx.size) for i in range(x.size)
+                  if (int(x[i]) - int(cx[j])) ** 2 + (int(y[i]) - int(cy[j])) ** 2 <= int(r[j]) ** 2)
+    assert list(zip(pt.tolist(), dk.tolist())) == want
+    counts = disk.distance_join_count(x, y, cx, cy, r)
+    assert counts.tolist() == [81, 149, 1, 29, 5]
+    # type (1): one radius for every disk
+    c1 = disk.distance_join_count(x, y, cx, cy, 4.0)
+    assert c1.tolist() == [49] * 5
+
+
+def test_knn_lattice_order_and_ties():
+    """Lattice points around a lattice centre: distances are square roots of
+    integers, so the nearest-first order is the order of the integer
+    a^2 + b^2, equal values by ascending id."""
+    x, y = _lattice(15)
+    for (px, py, k) in [(0.0, 0.0, 1), (0.0, 0.0, 37), (2.0, -3.0, 200), (15.0, 15.0, 961)]:
+        key = sorted(((int(x[i]) - int(px)) ** 2 + (int(y[i]) - int(py)) ** 2, i) for i in range(x.size))
+        want = [i for _, i in key[:k]]
+        assert disk.knn(x, y, px, py, k).tolist() == want
+
+
+def test_knn_one_ulp_apart_and_non_finite():
+    """Two points one ulp apart in distance are ordered by the exact
+    distance, not by FP64 rounding; non-finite points are never chosen;
+    k beyond the finite points returns them all."""
+    px, py = 0.1, 0.2
+    d = 0.3
+    a = (px + d, py)
+    b = (np.nextafter(px + d, np.inf), py)
+    x = np.array([b[0], a[0], np.nan, px - d, np.inf])
+    y = np.array([b[1], a[1], 0.0, py, 0.0])
+    got = disk.knn(x, y, px, py, 10)
+    from fractions import Fraction
+    key = sorted(((Fraction(float(x[i])) - Fraction(px)) ** 2 + (Fraction(float(y[i])) - Fraction(py)) ** 2, i)
+                 for i in (0, 1, 3))
+    assert [i for _, i in key][1:] == [1, 0]      # a is nearer than b by one ulp
+    assert got.tolist() == [i for _, i in key]

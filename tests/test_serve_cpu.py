@@ -136,3 +136,102 @@ def test_vertex_cap_splits_batches():
     srv.stop()
     for b in srv.batches:
         assert len(b) == 1 or sum(n_vertices(reqs[i].polys) for i in b) <= 2500
+
+
+class FakeAsyncExecutor(FakeExecutor):
+    """The same work on a timer thread: submit returns at once, poll and
+    collect follow the asynchronous executor protocol."""
+
+    def submit(self, w, reqs):
+        box = {"done": False, "err": None}
+
+        def work():
+            try:
+                self.run(w, reqs)
+            except Exception as e:      # delivered by collect
+                box["err"] = e
+            box["done"] = True
+        th = threading.Thread(target=work, daemon=True)
+        th.start()
+        return (th, box)
+
+    def poll(self, token):
+        return token[1]["done"]
+
+    def collect(self, token, reqs):
+        token[0].join()
+        if token[1]["err"] is not None:
+            raise token[1]["err"]
+
+
+def test_async_executor_results_and_overlap():
+    ex = FakeAsyncExecutor(n_workers=3)
+    srv = Server(ex, budget_bytes=10 ** 9, max_batch=8).start()
+    reqs = _requests(80, seed=5)
+    for r in reqs:
+        srv.submit(r)
+    srv.stop()
+    assert all(r.error is None for r in reqs)
+    assert all(r.result == FakeExecutor.answer(r) for r in reqs)
+    assert ex.max_active >= 2
+    assert max(len(b) for b in srv.batches) > 1
+
+
+def test_async_failure_isolated():
+    ex = FakeAsyncExecutor(n_workers=2, fail_on=7)
+    srv = Server(ex, budget_bytes=10 ** 9).start()
+    reqs = _requests(20, seed=6)
+    for r in reqs:
+        srv.submit(r)
+    srv.stop()
+    assert reqs[7].error and "planted" in reqs[7].error
+    assert all(r.error is None for r in reqs if r.rid != 7)
+
+
+class _Held:
+    """A result object with a size, like a device tensor."""
+
+    def __init__(self, nbytes):
+        self.nbytes = nbytes
+
+
+class HeldExecutor(FakeExecutor):
+    def run(self, w, reqs):
+        for r in reqs:
+            r.result = _Held(self.bpv * n_vertices(r.polys))
+
+
+def test_held_results_count_against_the_budget():
+    """Finished results the caller keeps count against the budget until they
+    are dropped; with nothing in flight a request that cannot fit because of
+    them is refused instead of waiting forever."""
+    import gc
+    ex = HeldExecutor(n_workers=1, bytes_per_vertex=1000)
+    budget = 1000 * 3000
+    srv = Server(ex, budget_bytes=budget).start()
+    a = Request(0, "count", _poly(2000, 0))
+    srv.submit(a)
+    srv.drain()
+    assert srv.held_bytes == 1000 * 2000
+    b = Request(1, "count", _poly(1500, 1))          # 1.5 MB more: above the budget while a is held
+    srv.submit(b)
+    srv.drain()
+    assert b.error and "held" in b.error
+    a.result = None                                  # the caller drops a's result
+    gc.collect()
+    assert srv.held_bytes == 0
+    c = Request(2, "count", _poly(1500, 2))
+    srv.submit(c)
+    srv.stop()
+    assert c.error is None
+
+
+def test_results_not_kept():
+    ex = HeldExecutor(n_workers=2)
+    srv = Server(ex, budget_bytes=10 ** 9, keep_results=False).start()
+    reqs = _requests(10, seed=8)
+    for r in reqs:
+        srv.submit(r)
+    srv.stop()
+    assert all(r.result is None and r.result_size == 1 for r in reqs)
+    assert srv.held_bytes == 0

@@ -69,7 +69,8 @@ def mixture_params(seed: int, L: float = EXTENT_M, K: int = 32):
     rng = rng_for(seed, 1)
     w = rng.dirichlet(np.ones(K))
     c = rng.uniform(0.1 * L, 0.9 * L, size=(K, 2))
-    s = rng.uniform(200.0, 3000.0, size=(K, 2))
+    # sigmas of 200..3000 m on the 60 km extent, scaled with the extent
+    s = rng.uniform(200.0, 3000.0, size=(K, 2)) * (float(L) / EXTENT_M)
     th = rng.uniform(0.0, math.pi, size=K)
     return {"w": w, "c": c, "s": s, "th": th, "L": float(L)}
 
