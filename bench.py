@@ -200,7 +200,7 @@ def leg_c2_pairs(ctx, dx, dy, dp, N):
             "gpu_matches_oracle_digest": parity}
 
 
-def leg_c3(ctx, with_host, extra):
+def leg_c3(ctx, with_host, extra, restore_ppv):
     import numpy as np
     import torch
     from workloads import configs
@@ -208,12 +208,12 @@ def leg_c3(ctx, with_host, extra):
     x, y = configs.c3_points()
     N = x.size
     dx, dy = dev(x), dev(y)
-    if with_host:
-        extra["host"] = leg_host(ctx, x, y)
-    del x, y
     star = configs.c3_star()
     dp = ctx.polys(star)
     log("c3 inputs: %d points (%.1fs)" % (N, time.time() - t))
+    from paper_2203_14362_amd.autotune import Autotuner, SELECT_CANDIDATES, tune_select
+    ppv, trials = tune_select(ctx, dx, dy, dp, Autotuner(candidates=SELECT_CANDIDATES), force=True)
+    log("c3 autotune: %.0f pixels per vertex (trials %s)" % (ppv, {k: round(v, 2) for k, v in trials.items()}))
     ctx.set_timing(True)
     ms, probe, ids = [], [], None
     for i in range(6):
@@ -232,8 +232,13 @@ def leg_c3(ctx, with_host, extra):
     del dx, dy, ids
     torch.cuda.empty_cache()
     pm = float(np.mean(probe))
+    if with_host:   # the same points and star, kept in host memory
+        extra["host"] = leg_host(ctx, x, y)
+    del x, y
+    ctx.set_pixels_per_vertex(restore_ppv)
     return {"workload": "selection: 500M clustered points x one 10k-vertex star (~15% of the extent)",
-            "points": N, "ids": n_ids, "ms_per_call": round(float(np.mean(ms)), 3), "probe_ms": round(pm, 3),
+            "points": N, "ids": n_ids, "autotune": {"pixels_per_vertex": ppv,
+                                                    "trial_ms": {str(k): round(v, 3) for k, v in trials.items()}}, "ms_per_call": round(float(np.mean(ms)), 3), "probe_ms": round(pm, 3),
             "points_per_s": round(N / (float(np.mean(ms)) / 1e3), 1),
             "roofline": roofline("k_emit_count + k_emit", 16.0 * N + 4.0 * n_ids, pm,
                                  bytes_rule="16 B/point + 4 B/id"),
@@ -684,7 +689,8 @@ def main():
     run_leg("next", lambda: leg_next(ctx, dx, dy, N))
     del dx, dy, dpolys
     torch.cuda.empty_cache()
-    run_leg("c3", lambda: leg_c3(ctx, "host" in legs, extra))
+    ppv_main = tuned["pixels_per_vertex"] if tuned else (args.ppv if args.ppv > 0 else 256.0)
+    run_leg("c3", lambda: leg_c3(ctx, "host" in legs, extra, ppv_main))
     if "c4" in legs or "serve" in legs:
         t = time.time()
         x4, y4 = configs.c4_points()

@@ -140,8 +140,9 @@ int spade_ctx_build_stats(const spade_ctx *ctx, int64_t *builds, int64_t *rebuil
 
 /* Device memory facts for admission control (any pointer may be NULL):
  * free and total bytes of ctx's device (hipMemGetInfo) and the bytes of
- * device scratch that ctx itself holds for reuse (plain-call canvas and
- * scratch slots; tables and canvases are reported by their own info calls). */
+ * device scratch that ctx itself holds for reuse (plain-call canvas, scratch
+ * slots, job result buffers; tables and canvases are reported by their own
+ * info calls).  Not while ctx has jobs in flight. */
 int spade_mem_info(spade_ctx *ctx, size_t *free_bytes, size_t *total_bytes, size_t *ctx_bytes);
 
 /* Phase timing (tracing aid).  on != 0 makes later query calls record HIP
@@ -386,8 +387,8 @@ int spade_batch_submit(spade_ctx *ctx, spade_canvas *set, const spade_polys *pol
                        const int64_t *qbound, const spade_table *t, int kind, spade_job **out);
 
 /* Blocks until the job is done and describes its results, which live in
- * buffers of the context, valid until its next job starts.  Returns the
- * job's status. */
+ * buffers of the context (one set per job kind), valid until its next job of
+ * the same kind starts.  Returns the job's status. */
 int spade_batch_wait(spade_job *job, spade_job_result *res);
 
 /* 1 if the job is done, 0 if not (never blocks). */

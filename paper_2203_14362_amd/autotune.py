@@ -110,3 +110,32 @@ def tune_join_count(ctx, x, y, polys, tuner: Autotuner = None, force: bool = Fal
         ctx.set_timing(was)
     ctx.set_pixels_per_vertex(ppv)
     return ppv, times
+
+
+SELECT_CANDIDATES = (96.0, 192.0, 384.0, 768.0, 1600.0)
+
+
+def tune_select(ctx, x, y, poly, tuner: Autotuner = None, force: bool = False):
+    """Tune and set ctx's pixels-per-vertex for selections with the one
+    polygon `poly` over the points (x, y): each trial is a whole selection
+    (rasterisation plus both probe passes) timed by the library's events.
+    Returns (ppv, times)."""
+    tuner = tuner or Autotuner(candidates=SELECT_CANDIDATES)
+    dp = ctx.polys(poly)
+    nv = int(dp.ring_vtx_off[-1].item()) if dp.ring_vtx_off.numel() else 0
+    key = signature("select", dp.n_polys, nv, int(x.numel()))
+    was = ctx.timing_enabled
+
+    def trial(ppv):
+        ctx.set_pixels_per_vertex(ppv)
+        ctx.select(x, y, dp)
+        r, p = ctx.last_timing()
+        return r + p
+
+    ctx.set_timing(True)
+    try:
+        ppv, times = tuner.tune(key, trial, force=force)
+    finally:
+        ctx.set_timing(was)
+    ctx.set_pixels_per_vertex(ppv)
+    return ppv, times

@@ -246,6 +246,7 @@ int spade_mem_info(spade_ctx *ctx, size_t *free_bytes, size_t *total_bytes, size
     size_t held = 0;
     for (const auto &b : ctx->scratch) held += b.cap;
     if (ctx->plain) held += ctx->plain->bytes() + ctx->plain->edges.cap + ctx->plain->dcds.cap;
+    held += jobs_bytes(ctx);
     if (free_bytes) *free_bytes = fr;
     if (total_bytes) *total_bytes = tot;
     if (ctx_bytes) *ctx_bytes = held;

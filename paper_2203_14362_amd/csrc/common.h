@@ -171,6 +171,7 @@ int ensure_keep(spade_ctx *ctx, DevBuf &b, size_t bytes);
 int hip_fail_if(spade_ctx *ctx, hipError_t e);
 int plain_canvas(spade_ctx *ctx, const spade_polys *polys, spade_canvas **cvo);
 void jobs_shutdown(spade_ctx *ctx);
+size_t jobs_bytes(const spade_ctx *ctx);
 void free_buf(DevBuf &b);
 
 // `defer`: leave the build's counters and flags on the device instead of

@@ -6,9 +6,9 @@
 // on the context's stream, and spade_batch_wait blocks until the job is done.
 // Jobs of one context run one after another in submission order; jobs of
 // different contexts (each with its own stream and worker) overlap on the
-// device.  Results live in buffers the context keeps and reuses, valid until
-// the context's next job starts, so a serving loop neither allocates nor
-// frees device memory per batch.
+// device.  Results live in buffers the context keeps and reuses, one set per
+// job kind, valid until the context's next job of the same kind starts, so
+// a serving loop neither allocates nor frees device memory per batch.
 #include "common.h"
 
 #include <condition_variable>
@@ -42,7 +42,7 @@ struct JobQueue {
     std::deque<spade_job *> q;
     std::thread worker;
     bool stop = false;
-    DevBuf res0, res1;           // result buffers, reused job after job
+    DevBuf rcount, rsel, rpt, rpg;   // result buffers per job kind, reused job after job
     int64_t guess = 1 << 20;     // first output capacity tried
 };
 
@@ -54,43 +54,43 @@ static void run_job(JobQueue *jq, spade_job *j)
         const int nq = (int)j->qbound.size() - 1;
         if (j->kind == SPADE_JOB_COUNT) {
             const int64_t M = j->qbound.back();
-            if (ensure(ctx, jq->res0, sizeof(uint64_t) * (size_t)std::max<int64_t>(M, 1))) rc = SPADE_E_NOMEM;
-            else rc = spade_batch_join_count(ctx, j->set, j->table, (uint64_t *)jq->res0.p);
-            j->out0 = jq->res0.p;
+            if (ensure(ctx, jq->rcount, sizeof(uint64_t) * (size_t)std::max<int64_t>(M, 1))) rc = SPADE_E_NOMEM;
+            else rc = spade_batch_join_count(ctx, j->set, j->table, (uint64_t *)jq->rcount.p);
+            j->out0 = jq->rcount.p;
             j->n_out = M;
         } else if (j->kind == SPADE_JOB_SELECT) {
             j->off.assign((size_t)nq + 1, 0);
             int64_t cap = jq->guess;
             for (int attempt = 0; attempt < 2; ++attempt) {
-                if (ensure(ctx, jq->res0, sizeof(uint32_t) * (size_t)std::max<int64_t>(cap, 1))) {
+                if (ensure(ctx, jq->rsel, sizeof(uint32_t) * (size_t)std::max<int64_t>(cap, 1))) {
                     rc = SPADE_E_NOMEM;
                     break;
                 }
-                cap = (int64_t)(jq->res0.cap / sizeof(uint32_t));
-                rc = spade_batch_select(ctx, j->set, j->table, (uint32_t *)jq->res0.p, cap, j->off.data());
+                cap = (int64_t)(jq->rsel.cap / sizeof(uint32_t));
+                rc = spade_batch_select(ctx, j->set, j->table, (uint32_t *)jq->rsel.p, cap, j->off.data());
                 if (rc != SPADE_E_CAPACITY) break;
                 cap = j->off.back();
                 jq->guess = std::max(jq->guess, cap);
             }
-            j->out0 = jq->res0.p;
+            j->out0 = jq->rsel.p;
             j->n_out = j->off.empty() ? 0 : j->off.back();
         } else {
             int64_t cap = jq->guess, n = 0;
             for (int attempt = 0; attempt < 2; ++attempt) {
-                if (ensure(ctx, jq->res0, sizeof(uint32_t) * (size_t)std::max<int64_t>(cap, 1)) ||
-                    ensure(ctx, jq->res1, sizeof(uint32_t) * (size_t)std::max<int64_t>(cap, 1))) {
+                if (ensure(ctx, jq->rpt, sizeof(uint32_t) * (size_t)std::max<int64_t>(cap, 1)) ||
+                    ensure(ctx, jq->rpg, sizeof(uint32_t) * (size_t)std::max<int64_t>(cap, 1))) {
                     rc = SPADE_E_NOMEM;
                     break;
                 }
-                cap = (int64_t)(std::min(jq->res0.cap, jq->res1.cap) / sizeof(uint32_t));
-                rc = spade_batch_join_pairs(ctx, j->set, j->table, (uint32_t *)jq->res0.p, (uint32_t *)jq->res1.p,
+                cap = (int64_t)(std::min(jq->rpt.cap, jq->rpg.cap) / sizeof(uint32_t));
+                rc = spade_batch_join_pairs(ctx, j->set, j->table, (uint32_t *)jq->rpt.p, (uint32_t *)jq->rpg.p,
                                             cap, &n);
                 if (rc != SPADE_E_CAPACITY) break;
                 cap = n;
                 jq->guess = std::max(jq->guess, cap);
             }
-            j->out0 = jq->res0.p;
-            j->out1 = jq->res1.p;
+            j->out0 = jq->rpt.p;
+            j->out1 = jq->rpg.p;
             j->n_out = n;
         }
     }
@@ -119,6 +119,12 @@ static void worker_loop(JobQueue *jq, int device)
     }
 }
 
+size_t jobs_bytes(const spade_ctx *ctx)
+{
+    const JobQueue *jq = (const JobQueue *)ctx->jobs;
+    return jq ? jq->rcount.cap + jq->rsel.cap + jq->rpt.cap + jq->rpg.cap : 0;
+}
+
 void jobs_shutdown(spade_ctx *ctx)
 {
     JobQueue *jq = (JobQueue *)ctx->jobs;
@@ -129,8 +135,10 @@ void jobs_shutdown(spade_ctx *ctx)
     }
     jq->cv.notify_all();
     if (jq->worker.joinable()) jq->worker.join();
-    free_buf(jq->res0);
-    free_buf(jq->res1);
+    free_buf(jq->rcount);
+    free_buf(jq->rsel);
+    free_buf(jq->rpt);
+    free_buf(jq->rpg);
     delete jq;
     ctx->jobs = nullptr;
 }

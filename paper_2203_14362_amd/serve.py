@@ -379,6 +379,7 @@ class SpadeExecutor:
                 self.ctxs.append(c)
         self.ppv = pixels_per_vertex or 256.0
         self._sets = [[None, None] for _ in range(n_workers)]
+        self._resident_w = [0] * n_workers
         with torch.cuda.stream(self.streams[0]):
             self.table = self.ctxs[0].table(x, y)
         self.streams[0].synchronize()
@@ -474,21 +475,24 @@ class SpadeExecutor:
                     for q, r in enumerate(rs):
                         r.result = res[int(qb[q]):int(qb[q + 1])].clone()
         self.streams[w].synchronize()
+        self._measure_resident(w)
         if err is not None:
             raise err
 
+    def _measure_resident(self, w: int):
+        """Worker w's resident device bytes (its context is idle): scratch,
+        job result buffers and canvas sets."""
+        tot = self.ctxs[w].mem_info()["ctx"]
+        for b in self._sets[w]:
+            if b is not None:
+                tot += b.info()["device_bytes"]
+        self._resident_w[w] = int(tot)
+
     def resident_bytes(self) -> int:
-        """Device bytes the executor keeps between batches: its contexts'
-        scratch and result buffers and its canvas sets (the table is
-        counted at creation, outside the budget)."""
-        tot = 0
-        for c in self.ctxs:
-            tot += c.mem_info()["ctx"]
-        for pair in self._sets:
-            for b in pair:
-                if b is not None:
-                    tot += b.info()["device_bytes"]
-        return int(tot)
+        """Device bytes the executor keeps between batches (the table is
+        counted at creation, outside the budget); each worker's share is
+        measured when its last batch was collected."""
+        return int(sum(self._resident_w))
 
     def run(self, w: int, reqs: List[Request]):
         torch = self.torch
