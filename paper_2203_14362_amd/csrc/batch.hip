@@ -8,8 +8,9 @@
 // every query that can contain one of them, so a chunk is read from HBM once
 // per pass for the whole batch.  Selection output uses the paper's two-step
 // Map (Sec. 5.1): a count pass sizes every (chunk, query) pair, a scan places
-// the pairs query by query, a write pass stores the ids, and a segmented
-// radix sort orders each query's ids.
+// the pairs query by query, a write pass stores the ids, and a radix sort of
+// (query, id) keys orders each query's ids.  The join-count needs no pair
+// list: its single probe launch finds each chunk's queries itself.
 #include "common.h"
 #include "exact.h"
 #include "lookup.h"
@@ -439,16 +440,37 @@ __global__ void k_query_off(int nq, const unsigned long long *qbase, const unsig
 
 constexpr int HSLOTS = 512;   // LDS hash slots per workgroup
 
-template <bool dummy>
-__global__ __launch_bounds__(BT_THREADS) void k_batch_count(SetArgs S, int64_t nfin, int64_t nchunk,
-                                                            const double *X, const double *Y,
-                                                            const unsigned int *cbase, const uint32_t *plist,
-                                                            const uint32_t *pq, unsigned long long *counts)
+// Whole-batch join-count in one launch, with no pair list: every workgroup
+// takes table chunks (grid-stride), lists in LDS the canvases whose box meets
+// the chunk's box (from qbox, a window of QL_MAX canvases at a time) and
+// probes its points against them, counting per polygon in an LDS hash
+// flushed with atomics per chunk.  Nothing is read back on the host between
+// launches, so the call's
+// launches are captured into a graph and replayed batch after batch, each
+// replay reading the canvas set's descriptors as rebuilt for that batch.
+constexpr int QL_MAX = 1024;
+
+__global__ void k_qbox(int nq, const CanvasDesc *cds, double4 *qbox)
+{
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += gridDim.x * blockDim.x) {
+        const CanvasDesc d = cds[q];
+        qbox[q] = d.empty ? make_double4(INFINITY, INFINITY, -INFINITY, -INFINITY)
+                          : make_double4(d.bx0, d.by0, d.bx1, d.by1);
+    }
+}
+
+__global__ __launch_bounds__(BT_THREADS) void k_batch_count_direct(SetArgs S, int nq, int64_t nfin, int64_t nchunk,
+                                                                   const double *X, const double *Y,
+                                                                   const double4 *chunk_bb, const double4 *qbox,
+                                                                   unsigned long long *counts)
 {
     __shared__ unsigned long long hkey[HSLOTS];   // polygon id + 1 (0: empty)
     __shared__ uint32_t hval[HSLOTS];
+    __shared__ uint32_t qlist[QL_MAX];
+    __shared__ uint32_t s_nq;
     for (int64_t c = blockIdx.x; c < nchunk; c += gridDim.x) {
         const int64_t b = c * CHUNK;
+        const double4 cb = chunk_bb[c];
         double xs[BT_PER], ys[BT_PER];
 #pragma unroll
         for (int u = 0; u < BT_PER; ++u) {
@@ -457,39 +479,48 @@ __global__ __launch_bounds__(BT_THREADS) void k_batch_count(SetArgs S, int64_t n
             ys[u] = i < nfin ? Y[i] : NAN;
         }
         for (int s = threadIdx.x; s < HSLOTS; s += BT_THREADS) { hkey[s] = 0ull; hval[s] = 0u; }
-        __syncthreads();
-        for (uint32_t t = cbase[c]; t < cbase[c + 1]; ++t) {
-            const uint32_t p = plist[t];
-            const CanvasDesc d = S.cds[pq[p]];
-            const CanvasView v = set_view(d, S.cells, S.coarse, S.cands, S.ledges, S.pspan);
-            auto add = [&](uint32_t label) {
-                const unsigned long long key = (unsigned long long)caller_id(S, d.poly_base + label) + 1ull;
-                uint32_t h = (uint32_t)(key * 0x9E3779B97F4A7C15ull >> 55) & (HSLOTS - 1);
-                for (int probe = 0; probe < 8; ++probe, h = (h + 1) & (HSLOTS - 1)) {
-                    unsigned long long cur = hkey[h];
-                    if (cur == 0ull) {
-                        cur = atomicCAS(&hkey[h], 0ull, key);
-                        if (cur == 0ull) cur = key;
+        for (int q0 = 0; q0 < nq; q0 += QL_MAX) {
+            if (threadIdx.x == 0) s_nq = 0u;
+            __syncthreads();
+            for (int q = q0 + threadIdx.x; q < min(nq, q0 + QL_MAX); q += BT_THREADS) {
+                const double4 qb = qbox[q];
+                // the chunk's closed point box meets the canvas's half-open box
+                if (cb.z >= qb.x && cb.x < qb.z && cb.w >= qb.y && cb.y < qb.w) qlist[atomicAdd(&s_nq, 1u)] = (uint32_t)q;
+            }
+            __syncthreads();
+            const uint32_t nl = s_nq;
+            for (uint32_t t = 0; t < nl; ++t) {
+                const CanvasDesc d = S.cds[qlist[t]];
+                const CanvasView v = set_view(d, S.cells, S.coarse, S.cands, S.ledges, S.pspan);
+                auto add = [&](uint32_t label) {
+                    const unsigned long long key = (unsigned long long)caller_id(S, d.poly_base + label) + 1ull;
+                    uint32_t h = (uint32_t)(key * 0x9E3779B97F4A7C15ull >> 55) & (HSLOTS - 1);
+                    for (int probe = 0; probe < 8; ++probe, h = (h + 1) & (HSLOTS - 1)) {
+                        unsigned long long cur = hkey[h];
+                        if (cur == 0ull) {
+                            cur = atomicCAS(&hkey[h], 0ull, key);
+                            if (cur == 0ull) cur = key;
+                        }
+                        if (cur == key) { atomicAdd(&hval[h], 1u); return; }
                     }
-                    if (cur == key) { atomicAdd(&hval[h], 1u); return; }
-                }
-                atomicAdd(&counts[key - 1ull], 1ull);
-            };
+                    atomicAdd(&counts[key - 1ull], 1ull);
+                };
 #pragma unroll
-            for (int u = 0; u < BT_PER; ++u) {
-                const uint32_t w = lookup(v, v.coarse, xs[u], ys[u]);
-                if (w == 0u) continue;
-                if (!(w & BFLAG)) { add(w - 1u); continue; }
-                uint32_t rec = w & ~BFLAG;
-                while (true) {
-                    const Cand cd = v.cands[rec];
-                    if (cand_inside(v, cd, xs[u], ys[u])) add(cd.poly);
-                    if (cd.meta & CAND_LAST) break;
-                    ++rec;
+                for (int u = 0; u < BT_PER; ++u) {
+                    const uint32_t w = lookup(v, v.coarse, xs[u], ys[u]);
+                    if (w == 0u) continue;
+                    if (!(w & BFLAG)) { add(w - 1u); continue; }
+                    uint32_t rec = w & ~BFLAG;
+                    while (true) {
+                        const Cand cd = v.cands[rec];
+                        if (cand_inside(v, cd, xs[u], ys[u])) add(cd.poly);
+                        if (cd.meta & CAND_LAST) break;
+                        ++rec;
+                    }
                 }
             }
+            __syncthreads();
         }
-        __syncthreads();
         for (int s = threadIdx.x; s < HSLOTS; s += BT_THREADS)
             if (hkey[s]) atomicAdd(&counts[hkey[s] - 1ull], (unsigned long long)hval[s]);
         __syncthreads();
@@ -864,6 +895,39 @@ int spade_batch_select(spade_ctx *ctx, const spade_canvas *set, const spade_tabl
     return SPADE_OK;
 }
 
+}  // extern "C"
+
+namespace spade {
+
+void drop_batch_graph(spade_canvas *cv)
+{
+    if (cv->bexec) (void)hipGraphExecDestroy(cv->bexec);
+    cv->bexec = nullptr;
+    cv->bkey.clear();
+}
+
+// The batch join-count's launches (clear the counts, the canvas boxes, the
+// one-pass probe) for the current buffers; all parameters are in `key`.
+static hipError_t batch_count_launches(spade_ctx *ctx, const spade_canvas *set, const spade_table *t, int64_t M,
+                                       uint64_t *out_counts, hipStream_t s)
+{
+    const int nq = set->nc;
+    if (M > 0) hipLaunchKernelGGL(k_zero64, dim3(grid_of(M, 4096)), dim3(256), 0, s, M, (unsigned long long *)out_counts);
+    hipLaunchKernelGGL(k_qbox, dim3((nq + 255) / 256), dim3(256), 0, s, nq, (const CanvasDesc *)set->dcds.p,
+                       (double4 *)set->qbox.p);
+    const SetArgs S = set_args(set);
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(t->nchunk, (int64_t)num_cus_of(ctx->device) * 8));
+    if (t->nchunk > 0 && M > 0)
+        hipLaunchKernelGGL(k_batch_count_direct, dim3(grid), dim3(BT_THREADS), 0, s, S, nq, t->nfin, t->nchunk,
+                           (const double *)t->x.p, (const double *)t->y.p, (const double4 *)t->chunk_bb.p,
+                           (const double4 *)set->qbox.p, (unsigned long long *)out_counts);
+    return hipGetLastError();
+}
+
+}  // namespace spade
+
+extern "C" {
+
 int spade_batch_join_count(spade_ctx *ctx, const spade_canvas *set, const spade_table *t, uint64_t *out_counts)
 {
     if (!ctx || !set || !t) return ctx ? set_error(ctx, SPADE_E_INVALID, "NULL argument") : SPADE_E_INVALID;
@@ -874,22 +938,56 @@ int spade_batch_join_count(spade_ctx *ctx, const spade_canvas *set, const spade_
     if (M > 0 && !out_counts) return set_error(ctx, SPADE_E_INVALID, "out_counts is NULL");
     hipStream_t st = ctx->stream;
     ctx->timed_raster = false;
-    Pairs P;
-    int rc = make_pairs(ctx, set, t, P);
-    if (rc) return rc;
-    if (M > 0) {
-        hipLaunchKernelGGL(k_zero64, dim3(grid_of(M, 4096)), dim3(256), 0, st, M, (unsigned long long *)out_counts);
-        SPADE_HIP(ctx, hipGetLastError());
-    }
-    const SetArgs S = set_args(set);
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(t->nchunk, (int64_t)num_cus_of(ctx->device) * 8));
+    spade_canvas *cv = const_cast<spade_canvas *>(set);
+    if (ensure(ctx, cv->qbox, sizeof(double4) * (size_t)std::max(set->nc, 1))) return SPADE_E_NOMEM;
+    // The launches depend only on these values: a call with the same ones
+    // (the same set and table memory, typically a rebuilt batch) replays the
+    // graph captured on the second such call.
+    const std::vector<uint64_t> key = {
+        (uint64_t)(uintptr_t)set->dcds.p, (uint64_t)(uintptr_t)set->cells.p, (uint64_t)(uintptr_t)set->coarse.p,
+        (uint64_t)(uintptr_t)set->cands.p, (uint64_t)(uintptr_t)set->ledges.p, (uint64_t)(uintptr_t)set->pspan.p,
+        (uint64_t)(uintptr_t)set->qbox.p, (uint64_t)(uintptr_t)(set->layered ? set->pid.p : nullptr),
+        (uint64_t)set->nc, (uint64_t)M, (uint64_t)(uintptr_t)t, (uint64_t)(uintptr_t)t->x.p, (uint64_t)t->nchunk,
+        (uint64_t)(uintptr_t)out_counts};
     if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[2], st));
-    if (P.np > 0) {
-        hipLaunchKernelGGL(k_batch_count<true>, dim3(grid), dim3(BT_THREADS), 0, st, S, t->nfin, t->nchunk,
-                           (const double *)t->x.p, (const double *)t->y.p, P.cbase, P.plist, P.pq,
-                           (unsigned long long *)out_counts);
-        SPADE_HIP(ctx, hipGetLastError());
+    hipError_t e;
+    if (!ctx->graphs) {
+        e = batch_count_launches(ctx, set, t, M, out_counts, st);
+    } else if (cv->bexec && cv->bkey == key) {
+        ++ctx->graph_replays;
+        e = hipGraphLaunch(cv->bexec, st);
+    } else if (cv->bkey != key) {
+        drop_batch_graph(cv);
+        cv->bkey = key;
+        e = batch_count_launches(ctx, set, t, M, out_counts, st);
+    } else {
+        // second call with these parameters: capture (on an internal stream,
+        // the caller's may be the null stream), then launch the graph
+        e = hipSuccess;
+        if (!ctx->capture && (e = hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking)) != hipSuccess) {
+            (void)hipGetLastError();
+            ctx->capture = nullptr;
+        }
+        hipGraph_t g = nullptr;
+        hipGraphExec_t ex = nullptr;
+        if (ctx->capture && hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+            const hipError_t e1 = batch_count_launches(ctx, set, t, M, out_counts, ctx->capture);
+            const hipError_t e2 = hipStreamEndCapture(ctx->capture, &g);
+            if (e1 == hipSuccess && e2 == hipSuccess && g &&
+                hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) == hipSuccess) {
+                cv->bexec = ex;
+                ++ctx->graph_captures;
+            }
+            if (g) (void)hipGraphDestroy(g);
+        }
+        (void)hipGetLastError();
+        if (cv->bexec) e = hipGraphLaunch(cv->bexec, st);
+        else {
+            cv->bkey.clear();
+            e = batch_count_launches(ctx, set, t, M, out_counts, st);
+        }
     }
+    if (e != hipSuccess) return hip_fail(ctx, e, "batch join-count launches");
     if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[3], st));
     SPADE_HIP(ctx, hipStreamSynchronize(st));
     return SPADE_OK;

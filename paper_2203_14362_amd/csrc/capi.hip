@@ -173,7 +173,9 @@ void spade_ctx_destroy(spade_ctx *ctx)
         free_buf(ctx->plain->coarse);
         free_buf(ctx->plain->dcds);
         free_buf(ctx->plain->pid);
+        free_buf(ctx->plain->qbox);
         drop_graph(ctx->plain);
+        drop_batch_graph(ctx->plain);
         delete ctx->plain;
     }
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
@@ -309,7 +311,9 @@ void spade_canvas_destroy(spade_canvas *cv)
     free_buf(cv->coarse);
     free_buf(cv->dcds);
     free_buf(cv->pid);
+    free_buf(cv->qbox);
     drop_graph(cv);
+    drop_batch_graph(cv);
     delete cv;
 }
 

@@ -120,6 +120,9 @@ struct spade_canvas {
     int32_t n_layers = 0;
     std::vector<uint64_t> gkey;               // launch parameters of the last build
     hipGraphExec_t gexec = nullptr;           // its captured launches (second build on)
+    std::vector<uint64_t> bkey;               // batch join-count: launch parameters of the last call
+    hipGraphExec_t bexec = nullptr;           // its captured launches (second call on)
+    spade::DevBuf qbox;                       // per-canvas boxes for the batch join-count
     bool pending = false;                     // built, counters and flags not yet read
     const void *pend_src = nullptr;           // their device block, until build_flush copies it
     size_t bytes() const
@@ -185,6 +188,7 @@ int build_flush(spade_ctx *ctx, spade_canvas *cv);
 constexpr int BUILD_AGAIN = 1;
 int build_finish(spade_ctx *ctx, spade_canvas *cv);
 void drop_graph(spade_canvas *cv);
+void drop_batch_graph(spade_canvas *cv);
 // Rasterises polygons [pbound[q], pbound[q+1]) into canvas q, q < nc.
 int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *pbound, spade_canvas *cv,
               bool defer = false);

@@ -340,22 +340,27 @@ class Job:
             return self._res
         r = _JobResult()
         rc = self.ctx.lib.spade_batch_wait(self.handle, ctypes.byref(r))
-        self.ctx.lib.spade_job_free(self.handle)
-        self.handle = None
-        self._keep = None
-        if rc != SPADE_OK:
-            raise SpadeError(rc, self.ctx.lib.spade_last_error(self.ctx.handle).decode())
-        dev = self.ctx.device
-        n = int(r.n_out)
-        with torch.cuda.device(dev):
-            if self.kind == JOB_COUNT:
-                out = torch.as_tensor(_DevArray(r.out0, n, "<i8"), device=dev).clone()
-            elif self.kind == JOB_SELECT:
-                off = np.ctypeslib.as_array(r.off, shape=(int(r.n_off),)).copy()
-                out = (torch.as_tensor(_DevArray(r.out0, n, "<i4"), device=dev).clone(), off)
-            else:
-                out = (torch.as_tensor(_DevArray(r.out0, n, "<i4"), device=dev).clone(),
-                       torch.as_tensor(_DevArray(r.out1, n, "<i4"), device=dev).clone())
+        try:
+            if rc != SPADE_OK:
+                raise SpadeError(rc, self.ctx.lib.spade_last_error(self.ctx.handle).decode())
+            dev = self.ctx.device
+            n = int(r.n_out)
+            # copies of the results first: the offsets live in the job handle,
+            # the arrays in the context's buffers
+            with torch.cuda.device(dev):
+                if self.kind == JOB_COUNT:
+                    out = torch.as_tensor(_DevArray(r.out0, n, "<i8"), device=dev).clone()
+                elif self.kind == JOB_SELECT:
+                    off = np.ctypeslib.as_array(r.off, shape=(int(r.n_off),)).copy()
+                    out = (torch.as_tensor(_DevArray(r.out0, n, "<i4"), device=dev).clone(), off)
+                else:
+                    out = (torch.as_tensor(_DevArray(r.out0, n, "<i4"), device=dev).clone(),
+                           torch.as_tensor(_DevArray(r.out1, n, "<i4"), device=dev).clone())
+                torch.cuda.current_stream(dev).synchronize()
+        finally:
+            self.ctx.lib.spade_job_free(self.handle)
+            self.handle = None
+            self._keep = None
         self._res = out
         return out
 

@@ -79,3 +79,32 @@ def test_replays_with_overflowing_row_pass(ctx):
         assert np.array_equal(got, want), k
         pt, pg = ctx.join_pairs(dx, dy, polys)
         assert np.array_equal(_u32(pt), opt) and np.array_equal(_u32(pg), opg), k
+
+
+def test_batch_join_count_graph_replays(ctx):
+    """The batch join-count's launches are captured on the second call with
+    the same set and table memory and replayed afterwards, each replay
+    reading the rebuilt set's descriptors: every replay equals the oracle,
+    with other device work between replays."""
+    import oracle
+    from workloads import gen
+    L = gen.EXTENT_M
+    x, y = gen.mixture_points(500_000, seed=95, L=L)
+    t = ctx.table(torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda())
+    cap0, rep0 = ctx.graph_stats()
+    b = None
+    base, _ = gen.query_stars(16, 8, 300, seed=96, L=L, area=(1e-3, 3e-2), data_seed=95)
+    for k in range(6):
+        # the same queries moved a little each time: same sizes, new descriptors
+        stars = dict(base)
+        stars["vx"] = base["vx"] + 256.0 * k
+        stars["vy"] = base["vy"] - 128.0 * k
+        qb = np.arange(17)
+        b = ctx.batch(stars, qb, into=b)
+        got = ctx.batch_join_count(b, t).cpu().numpy().astype(np.uint64)
+        assert np.array_equal(got, oracle.join_count(x, y, stars)), k
+        torch.randn(1 << 20, device="cuda").sum().item()      # other work between replays
+    cap1, rep1 = ctx.graph_stats()
+    assert cap1 - cap0 >= 1 and rep1 - rep0 >= 2
+    b.close()
+    t.close()
