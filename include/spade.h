@@ -39,7 +39,9 @@
  *     a NaN or infinite coordinate lie in no polygon.
  *   - Point ids are 0-based indices into the point arrays (uint32: n < 2^32);
  *     polygon ids are 0-based positions in the polygon set (< 2^31 - 1).
- *   - One context per host thread; contexts are independent.
+ *   - Calls on one context are serialised by a lock the context holds
+ *     (its job worker takes it too, per job); a call made from another
+ *     thread waits.  Contexts are independent: use one per stream of work.
  */
 #ifndef SPADE_H
 #define SPADE_H
@@ -365,9 +367,10 @@ int spade_layered_build(spade_ctx *ctx, const spade_polys *polys, int32_t res, s
  * the caller's canvas set (as spade_batch_rebuild) and evaluates it over a
  * table (selection, join-count or join pairs) on ctx's stream.  Jobs of one
  * context run in submission order; jobs of different contexts (each with
- * its own stream) overlap on the device.  While a context has jobs in
- * flight, make no other call on it except spade_batch_wait,
- * spade_job_query and spade_job_free. */
+ * its own stream) overlap on the device.  Another call on a context whose
+ * worker is running a job waits until that job is done (calls queued
+ * behind it keep their order only per thread).  A job's canvas set, table
+ * and polygon arrays must stay alive until the job is done. */
 enum { SPADE_JOB_SELECT = 1, SPADE_JOB_COUNT = 2, SPADE_JOB_PAIRS = 3 };
 typedef struct spade_job spade_job;
 typedef struct {
@@ -386,15 +389,18 @@ typedef struct {
 int spade_batch_submit(spade_ctx *ctx, spade_canvas *set, const spade_polys *polys, int32_t nq,
                        const int64_t *qbound, const spade_table *t, int kind, spade_job **out);
 
-/* Blocks until the job is done and describes its results, which live in
- * buffers of the context (one set per job kind), valid until its next job of
- * the same kind starts.  Returns the job's status. */
+/* Blocks until the job is done and describes its results, which live in a
+ * device buffer the context lends the job until spade_job_free (buffers
+ * come back to a pool per job kind and are reused, so a loop that frees
+ * each job before its next one of the kind allocates nothing per job).
+ * Returns the job's status. */
 int spade_batch_wait(spade_job *job, spade_job_result *res);
 
 /* 1 if the job is done, 0 if not (never blocks). */
 int spade_job_query(const spade_job *job);
 
-/* Frees the handle (waits for the job first). */
+/* Frees the handle (waits for the job first) and returns its result buffer
+ * to the context.  Free every job of a context before destroying it. */
 void spade_job_free(spade_job *job);
 
 /* ---- Out-of-core point tables (Sec. 5.3, "Out-of-Core Queries").  The

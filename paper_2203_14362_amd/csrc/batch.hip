@@ -640,6 +640,7 @@ extern "C" {
 int spade_ctx_set_pixels_per_vertex(spade_ctx *ctx, double ppv)
 {
     if (!ctx) return SPADE_E_INVALID;
+    SPADE_CTX_LOCK(ctx);
     if (!(ppv >= 1.0 && ppv <= 1e7)) return set_error(ctx, SPADE_E_INVALID, "pixels per vertex must be in [1, 1e7]");
     ctx->ppv = ppv;
     return SPADE_OK;
@@ -647,6 +648,8 @@ int spade_ctx_set_pixels_per_vertex(spade_ctx *ctx, double ppv)
 
 int spade_table_create(spade_ctx *ctx, const spade_points *pts, spade_table **out)
 {
+    if (!ctx) return SPADE_E_INVALID;
+    SPADE_CTX_LOCK(ctx);
     if (!ctx || !out) return SPADE_E_INVALID;
     *out = nullptr;
     ctx->err.clear();
@@ -758,6 +761,8 @@ static int check_batch_args(spade_ctx *ctx, const spade_polys *polys, int32_t nq
 int spade_batch_build(spade_ctx *ctx, const spade_polys *polys, int32_t nq, const int64_t *qbound,
                       spade_canvas **out)
 {
+    if (!ctx) return SPADE_E_INVALID;
+    SPADE_CTX_LOCK(ctx);
     if (!ctx || !out) return SPADE_E_INVALID;
     *out = nullptr;
     int rc0 = check_batch_args(ctx, polys, nq, qbound);
@@ -777,6 +782,8 @@ int spade_batch_build(spade_ctx *ctx, const spade_polys *polys, int32_t nq, cons
 int spade_batch_rebuild(spade_ctx *ctx, const spade_polys *polys, int32_t nq, const int64_t *qbound,
                         spade_canvas *set)
 {
+    if (!ctx) return SPADE_E_INVALID;
+    SPADE_CTX_LOCK(ctx);
     if (!ctx || !set) return ctx ? set_error(ctx, SPADE_E_INVALID, "NULL argument") : SPADE_E_INVALID;
     int rc = check_batch_args(ctx, polys, nq, qbound);
     if (rc) return rc;
@@ -790,6 +797,8 @@ int spade_batch_rebuild(spade_ctx *ctx, const spade_polys *polys, int32_t nq, co
 int spade_batch_select(spade_ctx *ctx, const spade_canvas *set, const spade_table *t, uint32_t *out_ids, int64_t cap,
                        int64_t *out_off)
 {
+    if (!ctx) return SPADE_E_INVALID;
+    SPADE_CTX_LOCK(ctx);
     if (!ctx || !set || !t || !out_off) return ctx ? set_error(ctx, SPADE_E_INVALID, "NULL argument") : SPADE_E_INVALID;
     ctx->err.clear();
     if (hipSetDevice(ctx->device) != hipSuccess) return set_error(ctx, SPADE_E_HIP, "hipSetDevice failed");
@@ -930,6 +939,8 @@ extern "C" {
 
 int spade_batch_join_count(spade_ctx *ctx, const spade_canvas *set, const spade_table *t, uint64_t *out_counts)
 {
+    if (!ctx) return SPADE_E_INVALID;
+    SPADE_CTX_LOCK(ctx);
     if (!ctx || !set || !t) return ctx ? set_error(ctx, SPADE_E_INVALID, "NULL argument") : SPADE_E_INVALID;
     ctx->err.clear();
     if (hipSetDevice(ctx->device) != hipSuccess) return set_error(ctx, SPADE_E_HIP, "hipSetDevice failed");
@@ -940,15 +951,16 @@ int spade_batch_join_count(spade_ctx *ctx, const spade_canvas *set, const spade_
     ctx->timed_raster = false;
     spade_canvas *cv = const_cast<spade_canvas *>(set);
     if (ensure(ctx, cv->qbox, sizeof(double4) * (size_t)std::max(set->nc, 1))) return SPADE_E_NOMEM;
-    // The launches depend only on these values: a call with the same ones
-    // (the same set and table memory, typically a rebuilt batch) replays the
-    // graph captured on the second such call.
+    // The launches depend only on these values (every pointer and size they
+    // take): a call with the same ones (the same set and table memory,
+    // typically a rebuilt batch) replays the graph captured on the second
+    // such call.
     const std::vector<uint64_t> key = {
         (uint64_t)(uintptr_t)set->dcds.p, (uint64_t)(uintptr_t)set->cells.p, (uint64_t)(uintptr_t)set->coarse.p,
         (uint64_t)(uintptr_t)set->cands.p, (uint64_t)(uintptr_t)set->ledges.p, (uint64_t)(uintptr_t)set->pspan.p,
         (uint64_t)(uintptr_t)set->qbox.p, (uint64_t)(uintptr_t)(set->layered ? set->pid.p : nullptr),
-        (uint64_t)set->nc, (uint64_t)M, (uint64_t)(uintptr_t)t, (uint64_t)(uintptr_t)t->x.p, (uint64_t)t->nchunk,
-        (uint64_t)(uintptr_t)out_counts};
+        (uint64_t)set->nc, (uint64_t)M, (uint64_t)(uintptr_t)t->x.p, (uint64_t)(uintptr_t)t->y.p,
+        (uint64_t)(uintptr_t)t->chunk_bb.p, (uint64_t)t->nfin, (uint64_t)t->nchunk, (uint64_t)(uintptr_t)out_counts};
     if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[2], st));
     hipError_t e;
     if (!ctx->graphs) {
@@ -996,6 +1008,8 @@ int spade_batch_join_count(spade_ctx *ctx, const spade_canvas *set, const spade_
 int spade_batch_join_pairs(spade_ctx *ctx, const spade_canvas *set, const spade_table *t, uint32_t *out_pt,
                            uint32_t *out_poly, int64_t cap, int64_t *n_out)
 {
+    if (!ctx) return SPADE_E_INVALID;
+    SPADE_CTX_LOCK(ctx);
     if (!ctx || !set || !t || !n_out) return ctx ? set_error(ctx, SPADE_E_INVALID, "NULL argument") : SPADE_E_INVALID;
     ctx->err.clear();
     *n_out = 0;

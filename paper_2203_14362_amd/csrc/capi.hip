@@ -195,6 +195,7 @@ void spade_ctx_destroy(spade_ctx *ctx)
 int spade_ctx_set_stream(spade_ctx *ctx, void *stream)
 {
     if (!ctx) return SPADE_E_INVALID;
+    SPADE_CTX_LOCK(ctx);
     ctx->stream = (hipStream_t)stream;
     return SPADE_OK;
 }
@@ -207,6 +208,7 @@ const char *spade_last_error(const spade_ctx *ctx)
 int spade_ctx_set_canvas_size(spade_ctx *ctx, int32_t width, int32_t height)
 {
     if (!ctx) return SPADE_E_INVALID;
+    SPADE_CTX_LOCK(ctx);
     if (width == 0 && height == 0) { ctx->canvas_w = ctx->canvas_h = 0; return SPADE_OK; }
     if (width < 1 || width > 8192 || height < 1 || height > 16384)
         return set_error(ctx, SPADE_E_INVALID, "canvas size must be 0x0 or within 1..8192 x 1..16384");
@@ -217,6 +219,8 @@ int spade_ctx_set_canvas_size(spade_ctx *ctx, int32_t width, int32_t height)
 
 int spade_ctx_set_graphs(spade_ctx *ctx, int on)
 {
+    if (!ctx) return SPADE_E_INVALID;
+    SPADE_CTX_LOCK(ctx);
     int rc = check_ctx(ctx);
     if (rc) return rc;
     ctx->graphs = on != 0;
@@ -226,6 +230,7 @@ int spade_ctx_set_graphs(spade_ctx *ctx, int on)
 int spade_ctx_graph_stats(const spade_ctx *ctx, int64_t *captures, int64_t *replays)
 {
     if (!ctx) return SPADE_E_INVALID;
+    SPADE_CTX_LOCK(ctx);
     if (captures) *captures = ctx->graph_captures;
     if (replays) *replays = ctx->graph_replays;
     return SPADE_OK;
@@ -234,6 +239,7 @@ int spade_ctx_graph_stats(const spade_ctx *ctx, int64_t *captures, int64_t *repl
 int spade_ctx_build_stats(const spade_ctx *ctx, int64_t *builds, int64_t *rebuilds)
 {
     if (!ctx) return SPADE_E_INVALID;
+    SPADE_CTX_LOCK(ctx);
     if (builds) *builds = ctx->builds;
     if (rebuilds) *rebuilds = ctx->rebuilds;
     return SPADE_OK;
@@ -241,6 +247,8 @@ int spade_ctx_build_stats(const spade_ctx *ctx, int64_t *builds, int64_t *rebuil
 
 int spade_mem_info(spade_ctx *ctx, size_t *free_bytes, size_t *total_bytes, size_t *ctx_bytes)
 {
+    if (!ctx) return SPADE_E_INVALID;
+    SPADE_CTX_LOCK(ctx);
     int rc = check_ctx(ctx);
     if (rc) return rc;
     size_t fr = 0, tot = 0;
@@ -257,6 +265,8 @@ int spade_mem_info(spade_ctx *ctx, size_t *free_bytes, size_t *total_bytes, size
 
 int spade_ctx_set_timing(spade_ctx *ctx, int on)
 {
+    if (!ctx) return SPADE_E_INVALID;
+    SPADE_CTX_LOCK(ctx);
     int rc = check_ctx(ctx);
     if (rc) return rc;
     if (on && !ctx->ev[0])
@@ -268,6 +278,8 @@ int spade_ctx_set_timing(spade_ctx *ctx, int on)
 
 int spade_ctx_last_timing(spade_ctx *ctx, float *raster_ms, float *probe_ms)
 {
+    if (!ctx) return SPADE_E_INVALID;
+    SPADE_CTX_LOCK(ctx);
     int rc = check_ctx(ctx);
     if (rc) return rc;
     if (!ctx->timing) return set_error(ctx, SPADE_E_INVALID, "timing is not enabled");
@@ -282,6 +294,8 @@ int spade_ctx_last_timing(spade_ctx *ctx, float *raster_ms, float *probe_ms)
 
 int spade_canvas_build(spade_ctx *ctx, const spade_polys *polys, spade_canvas **out)
 {
+    if (!ctx) return SPADE_E_INVALID;
+    SPADE_CTX_LOCK(ctx);
     int rc = check_ctx(ctx);
     if (rc) return rc;
     if (!out) return set_error(ctx, SPADE_E_INVALID, "out is NULL");
@@ -333,6 +347,8 @@ int spade_canvas_info(const spade_canvas *cv, int32_t *width, int32_t *height, i
 
 int spade_layer_index(spade_ctx *ctx, const spade_polys *polys, int32_t res, int32_t *out_layer, int32_t *n_layers)
 {
+    if (!ctx) return SPADE_E_INVALID;
+    SPADE_CTX_LOCK(ctx);
     int rc = check_ctx(ctx);
     if (rc) return rc;
     if (!n_layers) return set_error(ctx, SPADE_E_INVALID, "n_layers is NULL");
@@ -345,6 +361,8 @@ int spade_layer_index(spade_ctx *ctx, const spade_polys *polys, int32_t res, int
 
 int spade_layered_build(spade_ctx *ctx, const spade_polys *polys, int32_t res, spade_canvas **out, int32_t *n_layers)
 {
+    if (!ctx) return SPADE_E_INVALID;
+    SPADE_CTX_LOCK(ctx);
     int rc = check_ctx(ctx);
     if (rc) return rc;
     if (!out) return set_error(ctx, SPADE_E_INVALID, "out is NULL");
@@ -369,6 +387,8 @@ int spade_layered_build(spade_ctx *ctx, const spade_polys *polys, int32_t res, s
 int spade_canvas_join_count_async(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts,
                                   uint64_t *out_counts)
 {
+    if (!ctx) return SPADE_E_INVALID;
+    SPADE_CTX_LOCK(ctx);
     int rc = check_ctx(ctx);
     if (rc) return rc;
     if (!cv) return set_error(ctx, SPADE_E_INVALID, "canvas is NULL");
@@ -382,6 +402,8 @@ int spade_canvas_join_count_async(spade_ctx *ctx, const spade_canvas *cv, const 
 int spade_canvas_join_count_noalloc(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts,
                                     uint64_t *out_counts)
 {
+    if (!ctx) return SPADE_E_INVALID;
+    SPADE_CTX_LOCK(ctx);
     int rc = check_ctx(ctx);
     if (rc) return rc;
     if (!cv) return set_error(ctx, SPADE_E_INVALID, "canvas is NULL");
@@ -396,6 +418,8 @@ int spade_canvas_join_count_noalloc(spade_ctx *ctx, const spade_canvas *cv, cons
 int spade_canvas_join_count(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts,
                             uint64_t *out_counts)
 {
+    if (!ctx) return SPADE_E_INVALID;
+    SPADE_CTX_LOCK(ctx);
     int rc = spade_canvas_join_count_async(ctx, cv, pts, out_counts);
     if (rc) return rc;
     SPADE_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -420,6 +444,8 @@ static int emit_common(spade_ctx *ctx, const spade_canvas *cv, const spade_point
 int spade_canvas_select(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts,
                         uint32_t *out_ids, int64_t cap, int64_t *n_out)
 {
+    if (!ctx) return SPADE_E_INVALID;
+    SPADE_CTX_LOCK(ctx);
     if (cv && cv->nc == 1 && cv->view.M != 1) return set_error(ctx, SPADE_E_INVALID, "selection needs exactly one polygon");
     return emit_common(ctx, cv, pts, out_ids, nullptr, cap, n_out);
 }
@@ -427,6 +453,8 @@ int spade_canvas_select(spade_ctx *ctx, const spade_canvas *cv, const spade_poin
 int spade_canvas_join_pairs(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts,
                             uint32_t *out_pt, uint32_t *out_poly, int64_t cap, int64_t *n_out)
 {
+    if (!ctx) return SPADE_E_INVALID;
+    SPADE_CTX_LOCK(ctx);
     if (cap > 0 && !out_poly) return set_error(ctx, SPADE_E_INVALID, "out_poly is NULL");
     return emit_common(ctx, cv, pts, out_pt, out_poly, cap, n_out);
 }
@@ -482,6 +510,7 @@ int spade_select_disk(spade_ctx *ctx, const spade_points *pts, double cx, double
                       uint32_t *out_ids, int64_t cap, int64_t *n_out)
 {
     if (!ctx) return SPADE_E_INVALID;
+    SPADE_CTX_LOCK(ctx);
     if (n_out) *n_out = 0;
     int rc = check_ctx(ctx);
     if (rc) return rc;
@@ -493,6 +522,7 @@ int spade_distance_join_pairs(spade_ctx *ctx, const spade_points *pts, const spa
                               uint32_t *out_pt, uint32_t *out_disk, int64_t cap, int64_t *n_out)
 {
     if (!ctx) return SPADE_E_INVALID;
+    SPADE_CTX_LOCK(ctx);
     if (n_out) *n_out = 0;
     int rc = check_ctx(ctx);
     if (rc) return rc;
@@ -506,6 +536,8 @@ int spade_distance_join_pairs(spade_ctx *ctx, const spade_points *pts, const spa
 int spade_distance_join_count(spade_ctx *ctx, const spade_points *pts, const spade_disks *disks,
                               uint64_t *out_counts)
 {
+    if (!ctx) return SPADE_E_INVALID;
+    SPADE_CTX_LOCK(ctx);
     int rc = check_ctx(ctx);
     if (rc) return rc;
     if ((rc = check_points(ctx, pts))) return rc;
@@ -518,6 +550,8 @@ int spade_distance_join_count(spade_ctx *ctx, const spade_points *pts, const spa
 int spade_knn_select(spade_ctx *ctx, const spade_points *pts, double px, double py, int64_t k, uint32_t *out_ids,
                      int64_t *n_out)
 {
+    if (!ctx) return SPADE_E_INVALID;
+    SPADE_CTX_LOCK(ctx);
     int rc = check_ctx(ctx);
     if (rc) return rc;
     if ((rc = check_points(ctx, pts))) return rc;
@@ -530,6 +564,7 @@ int spade_select(spade_ctx *ctx, const spade_points *pts, const spade_polys *pol
                  int64_t cap, int64_t *n_out)
 {
     if (!ctx) return SPADE_E_INVALID;
+    SPADE_CTX_LOCK(ctx);
     if (n_out) *n_out = 0;
     if (poly && poly->n_polys != 1) return set_error(ctx, SPADE_E_INVALID, "selection needs exactly one polygon");
     int rc = check_points(ctx, pts);
@@ -542,6 +577,7 @@ int spade_select(spade_ctx *ctx, const spade_points *pts, const spade_polys *pol
 int spade_join_count(spade_ctx *ctx, const spade_points *pts, const spade_polys *polys, uint64_t *out_counts)
 {
     if (!ctx) return SPADE_E_INVALID;
+    SPADE_CTX_LOCK(ctx);
     int rc = check_points(ctx, pts);
     if (rc) return rc;
     return plain_query(ctx, polys, [&](spade_canvas *cv) {
@@ -553,6 +589,7 @@ int spade_join_pairs(spade_ctx *ctx, const spade_points *pts, const spade_polys 
                      uint32_t *out_poly, int64_t cap, int64_t *n_out)
 {
     if (!ctx) return SPADE_E_INVALID;
+    SPADE_CTX_LOCK(ctx);
     if (n_out) *n_out = 0;
     int rc = check_points(ctx, pts);
     if (rc) return rc;
@@ -563,6 +600,8 @@ int spade_join_pairs(spade_ctx *ctx, const spade_points *pts, const spade_polys 
 
 int spade_stream_read(spade_ctx *ctx, const spade_points *pts, int shape, double *out_sum)
 {
+    if (!ctx) return SPADE_E_INVALID;
+    SPADE_CTX_LOCK(ctx);
     int rc = check_ctx(ctx);
     if (rc) return rc;
     if ((rc = check_points(ctx, pts))) return rc;
@@ -585,6 +624,8 @@ __global__ void k_orient(int64_t n, const double *ax, const double *ay, const do
 int spade_orient_batch(spade_ctx *ctx, int64_t n, const double *ax, const double *ay, const double *bx,
                        const double *by, const double *cx, const double *cy, int32_t *out)
 {
+    if (!ctx) return SPADE_E_INVALID;
+    SPADE_CTX_LOCK(ctx);
     int rc = check_ctx(ctx);
     if (rc) return rc;
     if (n < 0) return set_error(ctx, SPADE_E_INVALID, "negative count");

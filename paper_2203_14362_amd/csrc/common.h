@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -154,7 +155,13 @@ struct spade_ctx {
     int64_t graph_captures = 0, graph_replays = 0;
     int64_t builds = 0, rebuilds = 0;       // plain-call canvas builds, and those redone for capacity
     void *jobs = nullptr;                   // asynchronous batch jobs: queue and worker thread
+    // Held by every call that uses the context's stream, scratch or state,
+    // and by the job worker while it runs a job: a call made while a job
+    // runs waits for it instead of sharing scratch buffers with it.
+    mutable std::recursive_mutex mu;
 };
+
+#define SPADE_CTX_LOCK(c) std::lock_guard<std::recursive_mutex> spade_ctx_guard_((c)->mu)
 
 namespace spade {
 

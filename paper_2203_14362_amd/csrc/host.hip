@@ -347,6 +347,8 @@ extern "C" {
 
 int spade_host_table_create(spade_ctx *ctx, const double *x, const double *y, int64_t n, spade_host_table **out)
 {
+    if (!ctx) return SPADE_E_INVALID;
+    SPADE_CTX_LOCK(ctx);
     if (!ctx || !out) return SPADE_E_INVALID;
     *out = nullptr;
     ctx->err.clear();
@@ -386,6 +388,7 @@ int spade_host_join_count(spade_ctx *ctx, spade_host_table *t, const spade_polys
                           int64_t *streamed)
 {
     if (!ctx) return SPADE_E_INVALID;
+    SPADE_CTX_LOCK(ctx);
     if (streamed) *streamed = 0;
     if (!t) return set_error(ctx, SPADE_E_INVALID, "table is NULL");
     spade_canvas *cv = nullptr;
@@ -401,6 +404,7 @@ int spade_host_select(spade_ctx *ctx, spade_host_table *t, const spade_polys *po
                       int64_t *n_out, int64_t *streamed)
 {
     if (!ctx) return SPADE_E_INVALID;
+    SPADE_CTX_LOCK(ctx);
     if (streamed) *streamed = 0;
     if (n_out) *n_out = 0;
     if (!t || !n_out) return set_error(ctx, SPADE_E_INVALID, "table or n_out is NULL");

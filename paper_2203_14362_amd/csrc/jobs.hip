@@ -6,9 +6,10 @@
 // on the context's stream, and spade_batch_wait blocks until the job is done.
 // Jobs of one context run one after another in submission order; jobs of
 // different contexts (each with its own stream and worker) overlap on the
-// device.  Results live in buffers the context keeps and reuses, one set per
-// job kind, valid until the context's next job of the same kind starts, so
-// a serving loop neither allocates nor frees device memory per batch.
+// device.  A job's results live in a result buffer the context lends it
+// until the job handle is freed; freed buffers go back to a pool per job
+// kind, so a serving loop that frees each job before the next one of its
+// kind neither allocates nor frees device memory per batch.
 #include "common.h"
 
 #include <condition_variable>
@@ -17,6 +18,12 @@
 #include <new>
 #include <thread>
 #include <vector>
+
+namespace spade {
+struct ResBuf {
+    DevBuf a, b;   // ids / counts / pair point ids; pair polygon ids
+};
+}  // namespace spade
 
 struct spade_job {
     spade_ctx *ctx = nullptr;
@@ -32,6 +39,7 @@ struct spade_job {
     int64_t n_out = 0;
     std::vector<int64_t> off;
     void *out0 = nullptr, *out1 = nullptr;
+    spade::ResBuf *rb = nullptr;   // lent by the context until the handle is freed
 };
 
 namespace spade {
@@ -42,55 +50,74 @@ struct JobQueue {
     std::deque<spade_job *> q;
     std::thread worker;
     bool stop = false;
-    DevBuf rcount, rsel, rpt, rpg;   // result buffers per job kind, reused job after job
-    int64_t guess = 1 << 20;     // first output capacity tried
+    std::vector<ResBuf *> all;       // every result buffer of the context
+    std::vector<ResBuf *> idle[4];   // returned ones, per job kind
+    int64_t guess = 1 << 20;         // first output capacity tried
 };
+
+// A result buffer for a job of `kind`: a returned one of that kind (its
+// memory sized by an earlier job) or a new, empty one.
+static ResBuf *take_buf(JobQueue *jq, int kind)
+{
+    std::lock_guard<std::mutex> lk(jq->mu);
+    auto &v = jq->idle[kind];
+    if (!v.empty()) {
+        ResBuf *b = v.back();
+        v.pop_back();
+        return b;
+    }
+    ResBuf *b = new (std::nothrow) ResBuf();
+    if (b) jq->all.push_back(b);
+    return b;
+}
 
 static void run_job(JobQueue *jq, spade_job *j)
 {
     spade_ctx *ctx = j->ctx;
-    int rc = spade_batch_rebuild(ctx, &j->polys, (int32_t)(j->qbound.size() - 1), j->qbound.data(), j->set);
+    ResBuf *rb = j->rb = take_buf(jq, j->kind);
+    int rc = rb ? spade_batch_rebuild(ctx, &j->polys, (int32_t)(j->qbound.size() - 1), j->qbound.data(), j->set)
+                : set_error(ctx, SPADE_E_NOMEM, "host allocation failed");
     if (rc == SPADE_OK) {
         const int nq = (int)j->qbound.size() - 1;
         if (j->kind == SPADE_JOB_COUNT) {
             const int64_t M = j->qbound.back();
-            if (ensure(ctx, jq->rcount, sizeof(uint64_t) * (size_t)std::max<int64_t>(M, 1))) rc = SPADE_E_NOMEM;
-            else rc = spade_batch_join_count(ctx, j->set, j->table, (uint64_t *)jq->rcount.p);
-            j->out0 = jq->rcount.p;
+            if (ensure(ctx, rb->a, sizeof(uint64_t) * (size_t)std::max<int64_t>(M, 1))) rc = SPADE_E_NOMEM;
+            else rc = spade_batch_join_count(ctx, j->set, j->table, (uint64_t *)rb->a.p);
+            j->out0 = rb->a.p;
             j->n_out = M;
         } else if (j->kind == SPADE_JOB_SELECT) {
             j->off.assign((size_t)nq + 1, 0);
             int64_t cap = jq->guess;
             for (int attempt = 0; attempt < 2; ++attempt) {
-                if (ensure(ctx, jq->rsel, sizeof(uint32_t) * (size_t)std::max<int64_t>(cap, 1))) {
+                if (ensure(ctx, rb->a, sizeof(uint32_t) * (size_t)std::max<int64_t>(cap, 1))) {
                     rc = SPADE_E_NOMEM;
                     break;
                 }
-                cap = (int64_t)(jq->rsel.cap / sizeof(uint32_t));
-                rc = spade_batch_select(ctx, j->set, j->table, (uint32_t *)jq->rsel.p, cap, j->off.data());
+                cap = (int64_t)(rb->a.cap / sizeof(uint32_t));
+                rc = spade_batch_select(ctx, j->set, j->table, (uint32_t *)rb->a.p, cap, j->off.data());
                 if (rc != SPADE_E_CAPACITY) break;
                 cap = j->off.back();
                 jq->guess = std::max(jq->guess, cap);
             }
-            j->out0 = jq->rsel.p;
+            j->out0 = rb->a.p;
             j->n_out = j->off.empty() ? 0 : j->off.back();
         } else {
             int64_t cap = jq->guess, n = 0;
             for (int attempt = 0; attempt < 2; ++attempt) {
-                if (ensure(ctx, jq->rpt, sizeof(uint32_t) * (size_t)std::max<int64_t>(cap, 1)) ||
-                    ensure(ctx, jq->rpg, sizeof(uint32_t) * (size_t)std::max<int64_t>(cap, 1))) {
+                if (ensure(ctx, rb->a, sizeof(uint32_t) * (size_t)std::max<int64_t>(cap, 1)) ||
+                    ensure(ctx, rb->b, sizeof(uint32_t) * (size_t)std::max<int64_t>(cap, 1))) {
                     rc = SPADE_E_NOMEM;
                     break;
                 }
-                cap = (int64_t)(std::min(jq->rpt.cap, jq->rpg.cap) / sizeof(uint32_t));
-                rc = spade_batch_join_pairs(ctx, j->set, j->table, (uint32_t *)jq->rpt.p, (uint32_t *)jq->rpg.p,
+                cap = (int64_t)(std::min(rb->a.cap, rb->b.cap) / sizeof(uint32_t));
+                rc = spade_batch_join_pairs(ctx, j->set, j->table, (uint32_t *)rb->a.p, (uint32_t *)rb->b.p,
                                             cap, &n);
                 if (rc != SPADE_E_CAPACITY) break;
                 cap = n;
                 jq->guess = std::max(jq->guess, cap);
             }
-            j->out0 = jq->rpt.p;
-            j->out1 = jq->rpg.p;
+            j->out0 = rb->a.p;
+            j->out1 = rb->b.p;
             j->n_out = n;
         }
     }
@@ -109,7 +136,10 @@ static void worker_loop(JobQueue *jq, int device)
             if (jq->q.empty()) return;
             j = jq->q.front();
         }
-        run_job(jq, j);
+        {
+            SPADE_CTX_LOCK(j->ctx);
+            run_job(jq, j);
+        }
         {
             std::lock_guard<std::mutex> lk(jq->mu);
             jq->q.pop_front();
@@ -121,8 +151,12 @@ static void worker_loop(JobQueue *jq, int device)
 
 size_t jobs_bytes(const spade_ctx *ctx)
 {
-    const JobQueue *jq = (const JobQueue *)ctx->jobs;
-    return jq ? jq->rcount.cap + jq->rsel.cap + jq->rpt.cap + jq->rpg.cap : 0;
+    JobQueue *jq = (JobQueue *)ctx->jobs;
+    if (!jq) return 0;
+    std::lock_guard<std::mutex> lk(jq->mu);
+    size_t b = 0;
+    for (const ResBuf *r : jq->all) b += r->a.cap + r->b.cap;
+    return b;
 }
 
 void jobs_shutdown(spade_ctx *ctx)
@@ -135,10 +169,11 @@ void jobs_shutdown(spade_ctx *ctx)
     }
     jq->cv.notify_all();
     if (jq->worker.joinable()) jq->worker.join();
-    free_buf(jq->rcount);
-    free_buf(jq->rsel);
-    free_buf(jq->rpt);
-    free_buf(jq->rpg);
+    for (ResBuf *r : jq->all) {
+        free_buf(r->a);
+        free_buf(r->b);
+        delete r;
+    }
     delete jq;
     ctx->jobs = nullptr;
 }
@@ -225,6 +260,7 @@ void spade_job_free(spade_job *j)
     if (jq) {
         std::unique_lock<std::mutex> lk(jq->mu);
         jq->cv.wait(lk, [&] { return j->done; });
+        if (j->rb) jq->idle[j->kind].push_back(j->rb);
     }
     delete j;
 }

@@ -442,14 +442,19 @@ class SpadeExecutor:
         ctx, s = self.ctxs[w], self.streams[w]
         jobs = []
         with torch.cuda.stream(s):
+            work = []
             for kind, code, slot in (("select", JOB_SELECT, 0), ("count", JOB_COUNT, 1)):
                 rs = [r for r in reqs if r.kind == kind]
-                if not rs:
-                    continue
-                polys, qb = concat_sets([r.polys for r in rs])
+                if rs:
+                    polys, qb = concat_sets([r.polys for r in rs])
+                    work.append((kind, code, slot, rs, polys, qb))
+            # sets this worker lacks are built before its first job is queued
+            # (a call on a context waits for the job it is running)
+            for kind, code, slot, rs, polys, qb in work:
                 if self._sets[w][slot] is None:
                     self._sets[w][slot] = ctx.batch(polys, qb)
-                    s.synchronize()
+            s.synchronize()
+            for kind, code, slot, rs, polys, qb in work:
                 jobs.append((kind, rs, qb, ctx.submit(self._sets[w][slot], polys, qb, self.table, code)))
         return (w, jobs)
 

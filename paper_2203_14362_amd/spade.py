@@ -329,11 +329,19 @@ class Job:
         self.ctx = ctx
         self.handle = handle
         self.kind = kind
-        self._keep = keep            # device polygon arrays read by the job
+        self._keep = keep            # polygon arrays, canvas set and table the job reads
         self._res = None
 
     def done(self) -> bool:
         return self._res is not None or self.ctx.lib.spade_job_query(self.handle) == 1
+
+    def __del__(self):
+        # a job dropped without wait: free the handle (after the job is done)
+        # so its result buffer goes back to the context
+        h = getattr(self, "handle", None)
+        if h is not None and getattr(self.ctx, "handle", None) is not None:
+            self.ctx.lib.spade_job_free(h)
+            self.handle = None
 
     def wait(self):
         if self._res is not None:
@@ -346,7 +354,7 @@ class Job:
             dev = self.ctx.device
             n = int(r.n_out)
             # copies of the results first: the offsets live in the job handle,
-            # the arrays in the context's buffers
+            # the arrays in a buffer the context lends the job until it is freed
             with torch.cuda.device(dev):
                 if self.kind == JOB_COUNT:
                     out = torch.as_tensor(_DevArray(r.out0, n, "<i8"), device=dev).clone()
@@ -512,7 +520,7 @@ class Context:
                                                 int(qb.size - 1), qb.ctypes.data_as(ctypes.c_void_p),
                                                 table.handle, int(kind), ctypes.byref(h)))
         batch.qbound, batch.n_queries, batch.n_polys = qb, int(qb.size - 1), int(qb[-1])
-        return Job(self, h, kind, dp)
+        return Job(self, h, kind, (dp, batch, table))
 
     def host_table(self, x, y) -> HostTable:
         """Out-of-core table from host float64 arrays."""
