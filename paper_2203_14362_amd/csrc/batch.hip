@@ -242,17 +242,20 @@ __device__ __forceinline__ uint32_t caller_id(const SetArgs &S, int64_t g)
 
 // Pass 1 (EMIT = false): matches per pair into pcount (64-bit, so that the
 // scan of the counts accumulates in 64 bits).  Pass 2 (EMIT): for
-// the pairs of queries q0 <= q < q1 only, the keys (query << 32 | point id)
-// of the matching points from pbase[pair] - kbase on, in an order the key
-// sort that follows makes ascending.
+// the pairs of queries q0 <= q < q1 only, the 32-bit keys
+// ((query - qrun0[query]) << idbits | point id) of the matching points at
+// out[pbase[pair] - kbase ...]: every query's keys land in its own output
+// range, and a sort of each run of queries (qrun0: a query's run's first
+// query) orders them.
 template <bool EMIT>
 __global__ __launch_bounds__(BT_THREADS) void k_batch_select(SetArgs S, int64_t nfin, int64_t nchunk,
                                                              const double *X, const double *Y,
                                                              const uint32_t *ids, const unsigned int *cbase,
                                                              const uint32_t *plist, const uint32_t *pq,
                                                              unsigned long long *pcount, const unsigned long long *pbase,
-                                                             unsigned long long *out, uint32_t q0, uint32_t q1,
-                                                             unsigned long long kbase)
+                                                             uint32_t *out, uint32_t q0, uint32_t q1,
+                                                             unsigned long long kbase, const uint32_t *qrun0,
+                                                             int idbits)
 {
     __shared__ uint32_t wsum[BT_THREADS / 64];
     for (int64_t c = blockIdx.x; c < nchunk; c += gridDim.x) {
@@ -310,10 +313,10 @@ __global__ __launch_bounds__(BT_THREADS) void k_batch_select(SetArgs S, int64_t 
                 if (threadIdx.x == 0) pcount[p] = tot;
             } else if (hit) {
                 unsigned long long pos = pbase[p] - kbase + pre + inc - cnt;
+                const uint32_t qk = (qy - qrun0[qy]) << idbits;
 #pragma unroll
                 for (int u = 0; u < BT_PER; ++u)
-                    if (hit & (1u << u))
-                        out[pos++] = ((unsigned long long)qy << 32) | ids[b + (int64_t)u * BT_THREADS + threadIdx.x];
+                    if (hit & (1u << u)) out[pos++] = qk | ids[b + (int64_t)u * BT_THREADS + threadIdx.x];
             }
         }
     }
@@ -527,10 +530,11 @@ __global__ __launch_bounds__(BT_THREADS) void k_batch_count_direct(SetArgs S, in
     }
 }
 
-__global__ void k_low32(int64_t n, const unsigned long long *k, uint32_t *out)
+// out[i] = k[i] & mask (in place when out == k)
+__global__ void k_mask32(int64_t n, const uint32_t *k, uint32_t mask, uint32_t *out)
 {
     const int64_t nth = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += nth) out[i] = (uint32_t)k[i];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += nth) out[i] = k[i] & mask;
 }
 
 __global__ void k_zero64(int64_t n, unsigned long long *p)
@@ -830,7 +834,7 @@ int spade_batch_select(spade_ctx *ctx, const spade_canvas *set, const spade_tabl
     if (np > 0) {
         hipLaunchKernelGGL(k_batch_select<false>, dim3(grid), dim3(BT_THREADS), 0, st, S, t->nfin, t->nchunk,
                            (const double *)t->x.p, (const double *)t->y.p, (const uint32_t *)t->ids.p, P.cbase,
-                           P.plist, P.pq, pcount, nullptr, nullptr, 0u, (uint32_t)nq, 0ull);
+                           P.plist, P.pq, pcount, nullptr, nullptr, 0u, (uint32_t)nq, 0ull, nullptr, 0);
         SPADE_HIP(ctx, hipGetLastError());
     }
     DevBuf &cub = ctx->scratch[S_CUBTMP];
@@ -855,48 +859,89 @@ int spade_batch_select(spade_ctx *ctx, const spade_canvas *set, const spade_tabl
         if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[3], st));
         return SPADE_OK;
     }
-    // Runs of consecutive queries with at most 2^30 keys (or one larger
-    // query alone) are written and sorted one at a time, so the key buffers
-    // stay bounded whatever the batch's total; runs that start at or beyond
-    // cap are not evaluated.  A radix sort of (query, id) keys orders each
-    // query's ids (a per-segment sort would give a whole query to one
-    // workgroup).
-    const int kbits = 32 + std::max(1, bits_of((uint64_t)(nq - 1)));
+    // Each query's ids are ordered by a radix sort of 32-bit keys
+    // ((query - first query of its run) << idbits | id) over runs of
+    // consecutive queries: at most 2^(32 - idbits) queries and 2^30 keys a
+    // run (a larger query alone).  One write pass puts every key of the
+    // runs that end within cap at its final position in out_ids, and each
+    // such run is then sorted in place (the sort's second buffer is
+    // scratch) and masked down to the ids.  The run that crosses cap, if
+    // any, is written to scratch by a pass of its own, sorted there, and its
+    // first ids copied; runs from cap on are not evaluated.
+    const int idbits = std::max(1, bits_of((uint64_t)std::max<int64_t>(t->n - 1, 1)));
+    const int64_t QMAX = (int64_t)1 << (32 - idbits);
     const int64_t GROUP = (int64_t)1 << 30;
+    const uint32_t idmask = (idbits >= 32) ? 0xffffffffu : ((1u << idbits) - 1u);
     struct Run { int q0, q1; int64_t k0, k1; };
     std::vector<Run> runs;
     {
         int qb = 0;
         for (int q = 0; q < nq; ++q)
-            if (out_off[q + 1] - out_off[qb] > GROUP && q > qb) {
+            if (q > qb && (q - qb >= QMAX || out_off[q + 1] - out_off[qb] > GROUP)) {
                 runs.push_back({qb, q, out_off[qb], out_off[q]});
                 qb = q;
             }
-        if (out_off[nq] > out_off[qb]) runs.push_back({qb, nq, out_off[qb], out_off[nq]});
+        runs.push_back({qb, nq, out_off[qb], out_off[nq]});
     }
-    int64_t gmax = 0;
-    for (const auto &r : runs)
-        if (r.k0 < cap) gmax = std::max(gmax, r.k1 - r.k0);
+    std::vector<uint32_t> hrun0((size_t)nq);
+    int qdone = 0;                       // queries of the runs that end within cap
+    int64_t gmax = 0, cross = -1;        // largest run sorted; index of the run crossing cap
+    for (size_t r = 0; r < runs.size(); ++r) {
+        const Run &R = runs[r];
+        for (int q = R.q0; q < R.q1; ++q) hrun0[(size_t)q] = (uint32_t)R.q0;
+        if (R.k1 <= cap) qdone = R.q1;
+        else if (R.k0 < cap && cross < 0) cross = (int64_t)r;
+        if (R.k0 < cap) gmax = std::max(gmax, R.k1 - R.k0);
+    }
+    DevBuf &br = ctx->scratch[S_LOOKBACK];
     DevBuf &bo2 = ctx->scratch[S_ENTF];
-    if (ensure(ctx, bo, 8 * (size_t)gmax) || ensure(ctx, bo2, 8 * (size_t)gmax)) return SPADE_E_NOMEM;
+    const int64_t nbo = cross >= 0 ? runs[(size_t)cross].k1 - runs[(size_t)cross].k0 : 0;
+    if (ensure(ctx, br, sizeof(uint32_t) * (size_t)nq) || ensure(ctx, bo2, 4 * (size_t)std::max<int64_t>(gmax, 1)) ||
+        ensure(ctx, bo, 4 * (size_t)std::max<int64_t>(nbo, 1)))
+        return SPADE_E_NOMEM;
+    const uint32_t *qrun0 = (const uint32_t *)br.p;
+    SPADE_HIP(ctx, hipMemcpyAsync(br.p, hrun0.data(), sizeof(uint32_t) * (size_t)nq, hipMemcpyHostToDevice, st));
     tb = 0;
-    SPADE_HIP(ctx, hipcub::DeviceRadixSort::SortKeys(nullptr, tb, (const unsigned long long *)bo.p,
-                                                     (unsigned long long *)bo2.p, (int)gmax, 0, kbits, st));
+    {
+        hipcub::DoubleBuffer<uint32_t> kb(out_ids, (uint32_t *)bo2.p);
+        SPADE_HIP(ctx, hipcub::DeviceRadixSort::SortKeys(nullptr, tb, kb, (int)std::max<int64_t>(gmax, 1), 0, 32, st));
+    }
     if (ensure(ctx, cub, tb)) return SPADE_E_NOMEM;
-    for (const auto &r : runs) {
-        if (r.k0 >= cap) break;
+    // sorts keys[0, n) of run R with buf as the second buffer; the ids end
+    // in dst[0, nwrite)
+    auto sort_run = [&](const Run &R, uint32_t *keys, uint32_t *buf, uint32_t *dst, int64_t nwrite) -> int {
+        const int64_t n = R.k1 - R.k0;
+        const int ebits = idbits + (R.q1 - R.q0 > 1 ? bits_of((uint64_t)(R.q1 - R.q0 - 1)) : 0);
+        hipcub::DoubleBuffer<uint32_t> kb(keys, buf);
+        size_t tb2 = tb;
+        SPADE_HIP(ctx, hipcub::DeviceRadixSort::SortKeys(cub.p, tb2, kb, (int)n, 0, ebits, st));
+        const uint32_t *sorted = kb.Current();
+        if (sorted != dst || R.q1 - R.q0 > 1) {
+            hipLaunchKernelGGL(k_mask32, dim3(grid_of(nwrite)), dim3(256), 0, st, nwrite, sorted, idmask, dst);
+            SPADE_HIP(ctx, hipGetLastError());
+        }
+        return SPADE_OK;
+    };
+    if (qdone > 0) {
         hipLaunchKernelGGL(k_batch_select<true>, dim3(grid), dim3(BT_THREADS), 0, st, S, t->nfin, t->nchunk,
                            (const double *)t->x.p, (const double *)t->y.p, (const uint32_t *)t->ids.p, P.cbase,
-                           P.plist, P.pq, nullptr, (const unsigned long long *)pbase, (unsigned long long *)bo.p,
-                           (uint32_t)r.q0, (uint32_t)r.q1, (unsigned long long)r.k0);
+                           P.plist, P.pq, nullptr, (const unsigned long long *)pbase, out_ids, 0u, (uint32_t)qdone,
+                           0ull, qrun0, idbits);
         SPADE_HIP(ctx, hipGetLastError());
-        SPADE_HIP(ctx, hipcub::DeviceRadixSort::SortKeys(cub.p, tb, (const unsigned long long *)bo.p,
-                                                         (unsigned long long *)bo2.p, (int)(r.k1 - r.k0), 0, kbits,
-                                                         st));
-        const int64_t nwrite = std::min<int64_t>(r.k1, cap) - r.k0;
-        hipLaunchKernelGGL(k_low32, dim3(grid_of(nwrite)), dim3(256), 0, st, nwrite,
-                           (const unsigned long long *)bo2.p, out_ids + r.k0);
+        for (const auto &R : runs) {
+            if (R.q1 > qdone) break;
+            if (R.k1 > R.k0 && (rc = sort_run(R, out_ids + R.k0, (uint32_t *)bo2.p, out_ids + R.k0, R.k1 - R.k0)))
+                return rc;
+        }
+    }
+    if (cross >= 0) {
+        const Run &R = runs[(size_t)cross];
+        hipLaunchKernelGGL(k_batch_select<true>, dim3(grid), dim3(BT_THREADS), 0, st, S, t->nfin, t->nchunk,
+                           (const double *)t->x.p, (const double *)t->y.p, (const uint32_t *)t->ids.p, P.cbase,
+                           P.plist, P.pq, nullptr, (const unsigned long long *)pbase, (uint32_t *)bo.p,
+                           (uint32_t)R.q0, (uint32_t)R.q1, (unsigned long long)R.k0, qrun0, idbits);
         SPADE_HIP(ctx, hipGetLastError());
+        if ((rc = sort_run(R, (uint32_t *)bo.p, (uint32_t *)bo2.p, out_ids + R.k0, cap - R.k0))) return rc;
     }
     if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[3], st));
     SPADE_HIP(ctx, hipStreamSynchronize(st));

@@ -381,6 +381,7 @@ class Batch(Canvas):
         self.qbound = qbound
         self.n_queries = len(qbound) - 1
         self.n_polys = int(qbound[-1])
+        self.last_total = None       # results of the last selection or join pairs over this set
 
 
 class Context:
@@ -490,11 +491,12 @@ class Context:
     def batch_select(self, batch: Batch, table: Table, cap=None):
         """(ids int32 tensor, offsets int64 numpy [nq + 1]): query q's ascending
         point ids are ids[off[q]:off[q+1]].  Without an explicit capacity the
-        first attempt uses the largest total seen on this context (at least
-        2^20, at most 2^28) and retries once at the reported total."""
+        first attempt uses this set's last total (a rebuilt batch often
+        selects as many), else the largest total seen on this context (at
+        least 2^20, at most 2^28), and retries once at the reported total."""
         off = np.zeros(batch.n_queries + 1, dtype=np.int64)
         if cap is None:
-            cap = min(self._select_cap, 1 << 28)
+            cap = getattr(batch, "last_total", None) or min(self._select_cap, 1 << 28)
         while True:
             ids = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device)
             self._sync_stream()
@@ -506,6 +508,7 @@ class Context:
                 self._select_cap = max(self._select_cap, cap)
                 continue
             self._check(rc)
+            batch.last_total = int(off[-1])
             return _compact(ids, int(off[-1])), off
 
     def submit(self, batch: "Batch", polys, qbound, table: Table, kind: int) -> Job:
@@ -565,9 +568,10 @@ class Context:
     def batch_join_pairs(self, batch: Batch, table: Table, cap=None):
         """(point ids, polygon ids) int32 tensors of every pair of a table
         point inside a polygon of the canvas set, ascending by (point,
-        polygon); polygon ids of a layered set are the caller's."""
+        polygon); polygon ids of a layered set are the caller's.  The first
+        capacity tried is chosen as in batch_select."""
         if cap is None:
-            cap = min(self._select_cap, 1 << 28)
+            cap = getattr(batch, "last_total", None) or min(self._select_cap, 1 << 28)
         while True:
             pt = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device)
             pg = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device)
@@ -582,6 +586,7 @@ class Context:
                 continue
             self._check(rc)
             m = int(nout.value)
+            batch.last_total = m
             return _compact(pt, m), _compact(pg, m)
 
     def layer_index(self, polys, res: int = 0):

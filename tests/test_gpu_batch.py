@@ -5,6 +5,8 @@ grid-clustered point table once per (chunk, query) overlap.  Every query's
 result must equal the oracle's for that query alone, and the result of a
 query must not depend on the other queries of its batch.
 """
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -167,5 +169,43 @@ def test_batch_invalid(ctx, table_pts):
         ctx.join_count(_dev(x), _dev(y), b)  # a set is not a single canvas
     got = ctx.batch_join_count(b, t).cpu().numpy().astype(np.uint64)
     assert np.array_equal(got, oracle.join_count(x, y, v))
+    b.close()
+    t.close()
+
+
+def test_batch_select_many_runs(ctx):
+    """Point ids above 2^27 (28 bits): a run of the selection's sort holds
+    at most 16 queries (32-bit keys), so 97 queries make seven runs, the
+    last of one query; the finite points sit at spread ids among non-finite
+    ones.  Also with a capacity that ends inside the fifth run."""
+    rng = np.random.default_rng(41)
+    n = (1 << 27) + 5
+    xf, yf = gen.mixture_points(200_000, seed=42, L=L)
+    pos = np.sort(rng.choice(n, xf.size, replace=False))
+    pos[-1] = n - 1
+    x = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+    y = torch.zeros(n, dtype=torch.float64, device="cuda")
+    x[torch.from_numpy(pos).cuda()] = _dev(xf)
+    y[torch.from_numpy(pos).cuda()] = _dev(yf)
+    polys, qb = gen.query_stars(97, 8, 1500, seed=43, L=L, area=(1e-3, 3e-2), data_seed=42)
+    t = ctx.table(x, y)
+    del x, y
+    b = ctx.batch(polys, qb)
+    ids, off = ctx.batch_select(b, t)
+    ids = ids.cpu().numpy().astype(np.int64)
+    for q in range(97):
+        want = pos[oracle.select(xf, yf, polys, q).astype(np.int64)]
+        assert np.array_equal(ids[off[q]:off[q + 1]], want), "query %d" % q
+    # first-cap semantics with the cap inside the fifth run (queries 64..79)
+    cap = int((off[70] + off[71]) // 2)
+    if cap > 0:
+        buf = torch.full((cap,), -1, dtype=torch.int32, device="cuda")
+        off2 = np.zeros(98, dtype=np.int64)
+        ctx._sync_stream()
+        rc = ctx.lib.spade_batch_select(ctx.handle, b.handle, t.handle, ctypes.c_void_p(buf.data_ptr()), cap,
+                                        off2.ctypes.data_as(ctypes.c_void_p))
+        from paper_2203_14362_amd import SPADE_E_CAPACITY
+        assert rc == SPADE_E_CAPACITY and np.array_equal(off2, off)
+        assert np.array_equal(buf.cpu().numpy().astype(np.int64), ids[:cap])
     b.close()
     t.close()
