@@ -315,8 +315,13 @@ int spade_batch_rebuild(spade_ctx *ctx, const spade_polys *polys, int32_t nq, co
  * within each query, queries one after another in out_ids [cap] (device).
  * out_off [nq + 1] (host) receives each query's start; out_off[nq] is the
  * total.  If the total exceeds cap, the first cap ids of that order are
- * written and SPADE_E_CAPACITY is returned with out_off filled.  Evaluated
- * with the paper's two-step Map (Sec. 5.1): a count pass, then a write pass. */
+ * written and SPADE_E_CAPACITY is returned with out_off filled (cap == 0:
+ * the count pass alone).  Evaluated with the paper's two-step Map
+ * (Sec. 5.1): a count pass, then a write pass.  The count pass keeps each
+ * (table chunk, query) overlap's match bits (512 bytes per overlap) so that
+ * the write pass needs no second probe, unless they would exceed the byte
+ * count in the environment variable SPADE_HIT_MASK_LIMIT (default 16 GiB;
+ * 0: always probe twice). */
 int spade_batch_select(spade_ctx *ctx, const spade_canvas *set, const spade_table *t,
                        uint32_t *out_ids, int64_t cap, int64_t *out_off);
 

@@ -18,6 +18,7 @@
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -241,7 +242,9 @@ __device__ __forceinline__ uint32_t caller_id(const SetArgs &S, int64_t g)
 // ------------------------------------------------------------ batch select
 
 // Pass 1 (EMIT = false): matches per pair into pcount (64-bit, so that the
-// scan of the counts accumulates in 64 bits).  Pass 2 (EMIT): for
+// scan of the counts accumulates in 64 bits) and, when hits is given, each
+// thread's matches as a bit mask (hits[pair * BT_THREADS + thread], bit u
+// for the thread's point u).  Pass 2 (EMIT): for
 // the pairs of queries q0 <= q < q1 only, the 32-bit keys
 // ((query - qrun0[query]) << idbits | point id) of the matching points at
 // out[pbase[pair] - kbase ...]: every query's keys land in its own output
@@ -255,8 +258,9 @@ __global__ __launch_bounds__(BT_THREADS) void k_batch_select(SetArgs S, int64_t 
                                                              unsigned long long *pcount, const unsigned long long *pbase,
                                                              uint32_t *out, uint32_t q0, uint32_t q1,
                                                              unsigned long long kbase, const uint32_t *qrun0,
-                                                             int idbits)
+                                                             int idbits, uint16_t *hits)
 {
+    static_assert(BT_PER <= 16, "a thread's matches are kept as 16 bits");
     __shared__ uint32_t wsum[BT_THREADS / 64];
     for (int64_t c = blockIdx.x; c < nchunk; c += gridDim.x) {
         const int64_t b = c * CHUNK;
@@ -311,6 +315,7 @@ __global__ __launch_bounds__(BT_THREADS) void k_batch_select(SetArgs S, int64_t 
             __syncthreads();
             if (!EMIT) {
                 if (threadIdx.x == 0) pcount[p] = tot;
+                if (hits) hits[(size_t)p * BT_THREADS + threadIdx.x] = (uint16_t)hit;
             } else if (hit) {
                 unsigned long long pos = pbase[p] - kbase + pre + inc - cnt;
                 const uint32_t qk = (qy - qrun0[qy]) << idbits;
@@ -319,6 +324,52 @@ __global__ __launch_bounds__(BT_THREADS) void k_batch_select(SetArgs S, int64_t 
                     if (hit & (1u << u)) out[pos++] = qk | ids[b + (int64_t)u * BT_THREADS + threadIdx.x];
             }
         }
+    }
+}
+
+// The write pass from the count pass's match masks: no second probe.  Each
+// workgroup takes pairs p0 <= p < p1 (the pairs of a run of queries, which
+// are contiguous in query-major order), gathers the keys of its matches
+// into LDS and stores them as one contiguous block at out[pbase[p] - kbase].
+__global__ __launch_bounds__(BT_THREADS) void k_batch_emit_hits(int64_t p0, int64_t p1, const uint32_t *pq,
+                                                                const uint32_t *pc, const uint16_t *hits,
+                                                                const unsigned long long *pbase, const uint32_t *ids,
+                                                                const uint32_t *qrun0, int idbits, uint32_t *out,
+                                                                unsigned long long kbase)
+{
+    __shared__ uint32_t stage[CHUNK];
+    __shared__ uint32_t wsum[BT_THREADS / 64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int64_t p = p0 + blockIdx.x; p < p1; p += gridDim.x) {
+        const uint32_t hit = hits[(size_t)p * BT_THREADS + threadIdx.x];
+        const uint32_t cnt = (uint32_t)__popc(hit);
+        uint32_t inc = cnt;
+#pragma unroll
+        for (int dd = 1; dd < 64; dd <<= 1) {
+            const uint32_t tt = __shfl_up(inc, dd, 64);
+            if (lane >= dd) inc += tt;
+        }
+        if (lane == 63) wsum[wv] = inc;
+        __syncthreads();
+        uint32_t pre = 0, tot = 0;
+#pragma unroll
+        for (int q = 0; q < BT_THREADS / 64; ++q) {
+            if (q < wv) pre += wsum[q];
+            tot += wsum[q];
+        }
+        if (tot) {
+            const uint32_t qy = pq[p];
+            const uint32_t qk = (qy - qrun0[qy]) << idbits;
+            const int64_t b = (int64_t)pc[p] * CHUNK;
+            uint32_t at = pre + inc - cnt;
+#pragma unroll
+            for (int u = 0; u < BT_PER; ++u)
+                if (hit & (1u << u)) stage[at++] = qk | ids[b + (int64_t)u * BT_THREADS + threadIdx.x];
+            __syncthreads();
+            uint32_t *dst = out + (pbase[p] - kbase);
+            for (uint32_t i = threadIdx.x; i < tot; i += BT_THREADS) dst[i] = stage[i];
+        }
+        __syncthreads();
     }
 }
 
@@ -428,12 +479,14 @@ __global__ void k_split_pairs(int64_t n, const unsigned long long *keys, int pbi
     }
 }
 
-// Query starts from pair bases: qoff[q] = pbase[first pair of q], qoff[nq] = total.
+// Query starts from pair bases: qoff[q] = pbase[first pair of q], qoff[nq] =
+// pbase[np] = the total.
 __global__ void k_query_off(int nq, const unsigned long long *qbase, const unsigned long long *pbase, int64_t np,
-                            unsigned long long total, unsigned long long *qoff)
+                            unsigned long long *qoff)
 {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q > nq) return;
+    const unsigned long long total = pbase[np];
     if (q == nq) { qoff[nq] = total; return; }
     const unsigned long long p = qbase[q];
     qoff[q] = (p < (unsigned long long)np) ? pbase[p] : total;
@@ -829,12 +882,24 @@ int spade_batch_select(spade_ctx *ctx, const spade_canvas *set, const spade_tabl
     unsigned long long *qoff = pbase + (np + 1);
     const SetArgs S = set_args(set);
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(t->nchunk, (int64_t)num_cus_of(ctx->device) * 8));
+    // the count pass keeps every pair's match masks (2 bytes per point slot)
+    // when they fit the limit (SPADE_HIT_MASK_LIMIT bytes, default 16 GiB);
+    // the write pass then reads them instead of probing again
+    size_t hits_max = (size_t)16 << 30;
+    if (const char *e = getenv("SPADE_HIT_MASK_LIMIT")) hits_max = (size_t)strtoull(e, nullptr, 10);
+    DevBuf &bh = ctx->scratch[S_KEYS2];
+    const size_t hbytes = sizeof(uint16_t) * BT_THREADS * (size_t)std::max<int64_t>(np, 1);
+    uint16_t *hits = nullptr;
+    if (cap > 0 && hbytes <= hits_max) {
+        if (ensure(ctx, bh, hbytes) == SPADE_OK) hits = (uint16_t *)bh.p;
+        else ctx->err.clear();   // probe twice instead
+    }
     hipLaunchKernelGGL(k_zero64, dim3(1), dim3(64), 0, st, (int64_t)1, pcount + np);
     if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[2], st));
     if (np > 0) {
         hipLaunchKernelGGL(k_batch_select<false>, dim3(grid), dim3(BT_THREADS), 0, st, S, t->nfin, t->nchunk,
                            (const double *)t->x.p, (const double *)t->y.p, (const uint32_t *)t->ids.p, P.cbase,
-                           P.plist, P.pq, pcount, nullptr, nullptr, 0u, (uint32_t)nq, 0ull, nullptr, 0);
+                           P.plist, P.pq, pcount, nullptr, nullptr, 0u, (uint32_t)nq, 0ull, nullptr, 0, hits);
         SPADE_HIP(ctx, hipGetLastError());
     }
     DevBuf &cub = ctx->scratch[S_CUBTMP];
@@ -842,15 +907,19 @@ int spade_batch_select(spade_ctx *ctx, const spade_canvas *set, const spade_tabl
     SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(nullptr, tb, pcount, pbase, (int)(np + 1), st));
     if (ensure(ctx, cub, tb)) return SPADE_E_NOMEM;
     SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(cub.p, tb, pcount, pbase, (int)(np + 1), st));
-    unsigned long long *h = (unsigned long long *)ensure_pinned(ctx, sizeof(unsigned long long) * (size_t)(nq + 2) + 64);
-    SPADE_HIP(ctx, hipMemcpyAsync(h, pbase + np, 8, hipMemcpyDeviceToHost, st));
-    SPADE_HIP(ctx, hipStreamSynchronize(st));
-    const unsigned long long total = h[0];
-    hipLaunchKernelGGL(k_query_off, dim3((nq + 1 + 255) / 256), dim3(256), 0, st, nq, P.qbase, pbase, np, total, qoff);
+    // one readback: the queries' output offsets and their first pairs
+    unsigned long long *h =
+        (unsigned long long *)ensure_pinned(ctx, sizeof(unsigned long long) * 2 * (size_t)(nq + 1) + 64);
+    if (!h) return set_error(ctx, SPADE_E_NOMEM, "pinned staging allocation failed");
+    hipLaunchKernelGGL(k_query_off, dim3((nq + 1 + 255) / 256), dim3(256), 0, st, nq, P.qbase, pbase, np, qoff);
     SPADE_HIP(ctx, hipGetLastError());
     SPADE_HIP(ctx, hipMemcpyAsync(h, qoff, sizeof(unsigned long long) * (size_t)(nq + 1), hipMemcpyDeviceToHost, st));
+    SPADE_HIP(ctx, hipMemcpyAsync(h + nq + 1, P.qbase, sizeof(unsigned long long) * (size_t)(nq + 1),
+                                  hipMemcpyDeviceToHost, st));
     SPADE_HIP(ctx, hipStreamSynchronize(st));
     for (int q = 0; q <= nq; ++q) out_off[q] = (int64_t)h[q];
+    const unsigned long long total = h[nq];
+    const std::vector<unsigned long long> hq(h + nq + 1, h + 2 * (nq + 1));
     // a buffer that is too small still receives the first cap ids in the
     // canonical order (two-step Map); the call then reports the shortfall
     const bool short_cap = (int64_t)total > cap;
@@ -922,12 +991,27 @@ int spade_batch_select(spade_ctx *ctx, const spade_canvas *set, const spade_tabl
         }
         return SPADE_OK;
     };
-    if (qdone > 0) {
-        hipLaunchKernelGGL(k_batch_select<true>, dim3(grid), dim3(BT_THREADS), 0, st, S, t->nfin, t->nchunk,
-                           (const double *)t->x.p, (const double *)t->y.p, (const uint32_t *)t->ids.p, P.cbase,
-                           P.plist, P.pq, nullptr, (const unsigned long long *)pbase, out_ids, 0u, (uint32_t)qdone,
-                           0ull, qrun0, idbits);
+    // the keys of queries [q0, q1) at out[pbase[pair] - kbase ...]
+    auto write_keys = [&](int q0, int q1, uint32_t *out, int64_t kbase) -> int {
+        if (hits) {
+            const int64_t p0 = (int64_t)hq[q0], p1 = (int64_t)hq[q1];
+            if (p1 > p0) {
+                const int eg = (int)std::min<int64_t>(p1 - p0, (int64_t)num_cus_of(ctx->device) * 8);
+                hipLaunchKernelGGL(k_batch_emit_hits, dim3(eg), dim3(BT_THREADS), 0, st, p0, p1, P.pq, P.pc, hits,
+                                   (const unsigned long long *)pbase, (const uint32_t *)t->ids.p, qrun0, idbits,
+                                   out, (unsigned long long)kbase);
+            }
+        } else {
+            hipLaunchKernelGGL(k_batch_select<true>, dim3(grid), dim3(BT_THREADS), 0, st, S, t->nfin, t->nchunk,
+                               (const double *)t->x.p, (const double *)t->y.p, (const uint32_t *)t->ids.p, P.cbase,
+                               P.plist, P.pq, nullptr, (const unsigned long long *)pbase, out, (uint32_t)q0,
+                               (uint32_t)q1, (unsigned long long)kbase, qrun0, idbits, nullptr);
+        }
         SPADE_HIP(ctx, hipGetLastError());
+        return SPADE_OK;
+    };
+    if (qdone > 0) {
+        if ((rc = write_keys(0, qdone, out_ids, 0))) return rc;
         for (const auto &R : runs) {
             if (R.q1 > qdone) break;
             if (R.k1 > R.k0 && (rc = sort_run(R, out_ids + R.k0, (uint32_t *)bo2.p, out_ids + R.k0, R.k1 - R.k0)))
@@ -936,11 +1020,7 @@ int spade_batch_select(spade_ctx *ctx, const spade_canvas *set, const spade_tabl
     }
     if (cross >= 0) {
         const Run &R = runs[(size_t)cross];
-        hipLaunchKernelGGL(k_batch_select<true>, dim3(grid), dim3(BT_THREADS), 0, st, S, t->nfin, t->nchunk,
-                           (const double *)t->x.p, (const double *)t->y.p, (const uint32_t *)t->ids.p, P.cbase,
-                           P.plist, P.pq, nullptr, (const unsigned long long *)pbase, (uint32_t *)bo.p,
-                           (uint32_t)R.q0, (uint32_t)R.q1, (unsigned long long)R.k0, qrun0, idbits);
-        SPADE_HIP(ctx, hipGetLastError());
+        if ((rc = write_keys(R.q0, R.q1, (uint32_t *)bo.p, R.k0))) return rc;
         if ((rc = sort_run(R, (uint32_t *)bo.p, (uint32_t *)bo2.p, out_ids + R.k0, cap - R.k0))) return rc;
     }
     if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[3], st));

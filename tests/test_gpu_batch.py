@@ -209,3 +209,30 @@ def test_batch_select_many_runs(ctx):
         assert np.array_equal(buf.cpu().numpy().astype(np.int64), ids[:cap])
     b.close()
     t.close()
+
+
+def test_batch_select_without_hit_masks(ctx, table_pts, stars, monkeypatch):
+    """The write pass that probes again (match masks over their limit) gives
+    the same ids, also for a capacity that ends inside the batch."""
+    x, y = table_pts
+    polys, qb = stars
+    t = ctx.table(_dev(x), _dev(y))
+    b = ctx.batch(polys, qb)
+    ids, off = ctx.batch_select(b, t)
+    monkeypatch.setenv("SPADE_HIT_MASK_LIMIT", "0")
+    ids2, off2 = ctx.batch_select(b, t)
+    assert np.array_equal(off, off2) and torch.equal(ids, ids2)
+    cap = int(off[-1]) // 2
+    buf = torch.full((max(cap, 1),), -1, dtype=torch.int32, device="cuda")
+    off3 = np.zeros(off.size, dtype=np.int64)
+    ctx._sync_stream()
+    rc = ctx.lib.spade_batch_select(ctx.handle, b.handle, t.handle, ctypes.c_void_p(buf.data_ptr()), cap,
+                                    off3.ctypes.data_as(ctypes.c_void_p))
+    from paper_2203_14362_amd import SPADE_E_CAPACITY
+    assert rc == SPADE_E_CAPACITY and np.array_equal(off3, off)
+    assert torch.equal(buf[:cap], ids[:cap])
+    monkeypatch.delenv("SPADE_HIT_MASK_LIMIT")
+    for q in (0, 11, 47):
+        assert np.array_equal(_u32(ids2)[off[q]:off[q + 1]], oracle.select(x, y, polys, q)), q
+    b.close()
+    t.close()
