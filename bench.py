@@ -51,6 +51,7 @@ if ROOT not in sys.path:
 METRIC = "points/sec for PIP join-count (bit-exact) + % HBM peak; p50/p99 served query latency"
 PEAK_HBM_GBS = 8000.0
 BYTES_PER_POINT = 16.0
+CHUNK_POINTS = 4096              # points per table chunk of the batch calls
 GOLDEN = os.path.join(ROOT, "tests", "golden", "full_size.json")
 ALL_LEGS = "c1,c2p,c3,host,c4,next,serve"
 
@@ -265,6 +266,8 @@ def leg_c4(ctx, dx, dy, table):
     torch.cuda.synchronize()
     tb = time.perf_counter() - t0
     total = int(off[-1])
+    count_ms = float(ctx.last_timing()[1])        # the selection's count pass
+    overlaps = ctx.batch_stats()
     # parity on the oracle's 2M-point subsample (per-query counts and digest)
     g = golden("c4_select_subsample")
     parity = None
@@ -300,7 +303,12 @@ def leg_c4(ctx, dx, dy, table):
     one_q = float(np.mean(one))
     res["select_batched"] = {"queries": nq, "ids": total, "seconds": round(tb, 4),
                              "queries_per_s": round(nq / tb, 1), "points_queries_per_s": round(N * nq / tb, 1),
-                             "gpu_matches_oracle_subsample": parity}
+                             "gpu_matches_oracle_subsample": parity,
+                             "chunk_query_overlaps": overlaps,
+                             "roofline": roofline("k_batch_select (count pass)", BYTES_PER_POINT * CHUNK_POINTS * overlaps,
+                                                  count_ms,
+                                                  bytes_rule="16 B per point-query test: every overlap of a 4096-point "
+                                                             "table chunk with a query's canvas box")}
     res["select_one_at_a_time"] = {"queries_timed": len(sample), "seconds_per_query": round(one_q, 5),
                                    "queries_per_s": round(1.0 / one_q, 1),
                                    "points_queries_per_s": round(N / one_q, 1)}
@@ -310,6 +318,7 @@ def leg_c4(ctx, dx, dy, table):
     cnt = ctx.batch_join_count(bj, table)
     torch.cuda.synchronize()
     tj = timed(lambda: ctx.batch_join_count(bj, table), 5, warmup=1)
+    count_direct_ms = float(ctx.last_timing()[1])
     dcells = ctx.polys(cells)
     tp = timed(lambda: ctx.join_count(dx, dy, dcells), 5, warmup=1)
     g = golden("c4_join_40k")
@@ -320,7 +329,10 @@ def leg_c4(ctx, dx, dy, table):
     res["join_40k"] = {"batched_ms": round(float(np.median(tj)), 3), "plain_ms": round(float(np.median(tp)), 3),
                        "batched_points_per_s": round(N / (float(np.median(tj)) / 1e3), 1),
                        "plain_points_per_s": round(N / (float(np.median(tp)) / 1e3), 1),
-                       "gpu_matches_oracle_digest": jparity, "plain_equals_batched": bool(np.array_equal(plain, c))}
+                       "gpu_matches_oracle_digest": jparity, "plain_equals_batched": bool(np.array_equal(plain, c)),
+                       "roofline": roofline("k_batch_count_direct", BYTES_PER_POINT * N, count_direct_ms,
+                                            bytes_rule="16 B per table point (one canvas: every chunk meets it "
+                                                       "at most once)")}
     return res
 
 

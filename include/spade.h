@@ -140,18 +140,24 @@ int spade_ctx_graph_stats(const spade_ctx *ctx, int64_t *captures, int64_t *repl
  * NULL).  A redone build is probed again before the call returns. */
 int spade_ctx_build_stats(const spade_ctx *ctx, int64_t *builds, int64_t *rebuilds);
 
+/* (table chunk, query) overlaps that the last batch selection or batch join
+ * pairs on ctx evaluated (each one tests the chunk's points, 4096 but in the
+ * table's last chunk, against one query's canvas). */
+int spade_ctx_batch_stats(const spade_ctx *ctx, int64_t *overlaps);
+
 /* Device memory facts for admission control (any pointer may be NULL):
  * free and total bytes of ctx's device (hipMemGetInfo) and the bytes of
  * device scratch that ctx itself holds for reuse (plain-call canvas, scratch
  * slots, job result buffers; tables and canvases are reported by their own
- * info calls).  Not while ctx has jobs in flight. */
+ * info calls).  A call while the context's worker runs a job waits for it. */
 int spade_mem_info(spade_ctx *ctx, size_t *free_bytes, size_t *total_bytes, size_t *ctx_bytes);
 
 /* Phase timing (tracing aid).  on != 0 makes later query calls record HIP
  * events on ctx's stream around the rasterisation and around the probe
- * kernel; spade_ctx_last_timing waits for the last probe and returns both
- * durations in milliseconds (raster_ms is 0 when the last query used a
- * prebuilt canvas).  Either out-pointer may be NULL. */
+ * kernel (for a batch selection: its count pass; for a batch join-count or
+ * join pairs: the whole evaluation); spade_ctx_last_timing waits for the
+ * last probe and returns both durations in milliseconds (raster_ms is 0 when
+ * the last query used a prebuilt canvas).  Either out-pointer may be NULL. */
 int spade_ctx_set_timing(spade_ctx *ctx, int on);
 int spade_ctx_last_timing(spade_ctx *ctx, float *raster_ms, float *probe_ms);
 

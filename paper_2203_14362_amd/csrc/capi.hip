@@ -245,6 +245,14 @@ int spade_ctx_build_stats(const spade_ctx *ctx, int64_t *builds, int64_t *rebuil
     return SPADE_OK;
 }
 
+int spade_ctx_batch_stats(const spade_ctx *ctx, int64_t *overlaps)
+{
+    if (!ctx) return SPADE_E_INVALID;
+    SPADE_CTX_LOCK(ctx);
+    if (overlaps) *overlaps = ctx->batch_overlaps;
+    return SPADE_OK;
+}
+
 int spade_mem_info(spade_ctx *ctx, size_t *free_bytes, size_t *total_bytes, size_t *ctx_bytes)
 {
     if (!ctx) return SPADE_E_INVALID;

@@ -154,6 +154,7 @@ struct spade_ctx {
     bool graphs = true;                     // replay repeated canvas builds from graphs
     int64_t graph_captures = 0, graph_replays = 0;
     int64_t builds = 0, rebuilds = 0;       // plain-call canvas builds, and those redone for capacity
+    int64_t batch_overlaps = 0;             // last batch selection / join pairs: (chunk, query) overlaps
     void *jobs = nullptr;                   // asynchronous batch jobs: queue and worker thread
     // Held by every call that uses the context's stream, scratch or state,
     // and by the job worker while it runs a job: a call made while a job

@@ -37,7 +37,7 @@ EXPORTS = [
     "spade_table_create", "spade_table_destroy", "spade_table_info", "spade_batch_build",
     "spade_batch_select", "spade_batch_join_count", "spade_ctx_set_pixels_per_vertex",
     "spade_batch_rebuild", "spade_ctx_set_graphs", "spade_ctx_graph_stats", "spade_select_disk",
-    "spade_ctx_build_stats", "spade_mem_info", "spade_canvas_join_count_noalloc",
+    "spade_ctx_build_stats", "spade_ctx_batch_stats", "spade_mem_info", "spade_canvas_join_count_noalloc",
     "spade_stream_read", "spade_batch_join_pairs", "spade_layer_index",
     "spade_layered_build", "spade_distance_join_pairs", "spade_distance_join_count", "spade_knn_select",
     "spade_host_table_create", "spade_host_table_destroy", "spade_host_table_info", "spade_host_join_count",
@@ -131,6 +131,7 @@ def load_library():
     lib.spade_ctx_set_graphs.argtypes = [vp, ctypes.c_int]
     lib.spade_ctx_graph_stats.argtypes = [vp, P(i64), P(i64)]
     lib.spade_ctx_build_stats.argtypes = [vp, P(i64), P(i64)]
+    lib.spade_ctx_batch_stats.argtypes = [vp, P(i64)]
     lib.spade_batch_join_pairs.argtypes = [vp, vp, vp, vp, vp, i64, P(i64)]
     lib.spade_distance_join_pairs.argtypes = [vp, P(_Points), P(_Disks), vp, vp, i64, P(i64)]
     lib.spade_distance_join_count.argtypes = [vp, P(_Points), P(_Disks), vp]
@@ -447,6 +448,13 @@ class Context:
         b, r = ctypes.c_int64(), ctypes.c_int64()
         self._check(self.lib.spade_ctx_build_stats(self.handle, ctypes.byref(b), ctypes.byref(r)))
         return b.value, r.value
+
+    def batch_stats(self) -> int:
+        """(table chunk, query) overlaps of the last batch selection or join
+        pairs on this context."""
+        o = ctypes.c_int64()
+        self._check(self.lib.spade_ctx_batch_stats(self.handle, ctypes.byref(o)))
+        return o.value
 
     def mem_info(self):
         """{'free', 'total', 'ctx'}: device bytes free and in total, and the
