@@ -97,17 +97,30 @@ __global__ __launch_bounds__(256) void k_pt_bbox(int64_t n, const double *X, con
 }
 
 // Grid cell key of every point (non-finite points: G * G, sorted last).
+// The bits of v (< 2^16) spread to the even bit positions.
+__device__ __forceinline__ uint32_t spread_bits(uint32_t v)
+{
+    v = (v | (v << 8)) & 0x00ff00ffu;
+    v = (v | (v << 4)) & 0x0f0f0f0fu;
+    v = (v | (v << 2)) & 0x33333333u;
+    v = (v | (v << 1)) & 0x55555555u;
+    return v;
+}
+
+// Sort key of each point: the Z-order (Morton) index of its cell of the
+// G x G grid, so that runs of consecutive cells, and hence table chunks,
+// are compact in space; nonfinite points get nfkey, after every cell.
 __global__ void k_pt_key(int64_t n, const double *X, const double *Y, double X0, double Y0, double sx,
-                         double sy, int G, uint32_t *keys, uint32_t *idx)
+                         double sy, int G, uint32_t nfkey, uint32_t *keys, uint32_t *idx)
 {
     const int64_t nth = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += nth) {
         const double x = X[i], y = Y[i];
-        uint32_t k = (uint32_t)G * (uint32_t)G;
+        uint32_t k = nfkey;
         if (isfinite(x) && isfinite(y)) {
             const int cx = (int)fmin((double)(G - 1), fmax(0.0, floor((x - X0) * sx)));
             const int cy = (int)fmin((double)(G - 1), fmax(0.0, floor((y - Y0) * sy)));
-            k = (uint32_t)cy * (uint32_t)G + (uint32_t)cx;
+            k = spread_bits((uint32_t)cx) | (spread_bits((uint32_t)cy) << 1);
         }
         keys[i] = k;
         idx[i] = (uint32_t)i;
@@ -125,7 +138,7 @@ __global__ void k_pt_gather(int64_t n, const uint32_t *perm, const double *X, co
     }
 }
 
-// cell_off[c] = first sorted point of cell c (c = 0 .. G*G + 1).
+// cell_off[c] = first sorted point of cell code c (c = 0 .. ncell + 1).
 __global__ void k_cell_off(int64_t n, const uint32_t *skeys, int64_t ncell, uint32_t *cell_off)
 {
     const int64_t nth = (int64_t)gridDim.x * blockDim.x;
@@ -239,6 +252,33 @@ __device__ __forceinline__ uint32_t caller_id(const SetArgs &S, int64_t g)
     return S.pid ? S.pid[g] : (uint32_t)g;
 }
 
+constexpr uint32_t NO_WORD = 0xffffffffu;
+
+// The canvas word of every point of a table chunk, when one word holds for
+// all of them: the chunk's exact box lies inside the canvas's half-open box
+// and every coarse block its pixels can fall in is uniform with that word
+// (0, or an interior label + 1; the pixel map is monotonic, so the box's
+// corner pixels bound every point's pixel).  Else NO_WORD.  Called by the
+// whole workgroup (it synchronises).
+__device__ uint32_t chunk_word(const CanvasView &v, const double4 cb)
+{
+    if (!(v.bx0 <= cb.x && cb.z < v.bx1 && v.by0 <= cb.y && cb.w < v.by1)) return NO_WORD;
+    auto col = [&](double x) { return min((int)__dmul_rn(__dsub_rn(x, v.X0), v.sx), v.W - 1) >> v.blog; };
+    auto row = [&](double y) { return min((int)__dmul_rn(__dsub_rn(y, v.Y0), v.sy), v.H - 1) >> v.blog; };
+    const int c0 = col(cb.x), c1 = col(cb.z), r0 = row(cb.y), r1 = row(cb.w);
+    const int nbx = c1 - c0 + 1, nb = nbx * (r1 - r0 + 1);
+    if (nb > BT_THREADS) return NO_WORD;
+    auto word = [&](int bx, int by) -> uint32_t {
+        const int i = by * v.Wc + bx;
+        return v.cbyte ? (uint32_t)((const uint8_t *)v.coarse)[i] : (uint32_t)v.coarse[i];
+    };
+    const uint32_t w0 = word(c0, r0);
+    const int t = (int)threadIdx.x;
+    const int same = (t >= nb) || word(c0 + t % nbx, r0 + t / nbx) == w0;
+    const uint32_t full = v.cbyte ? COARSE_BYTE_FULL : (uint32_t)COARSE_FULL;
+    return (__syncthreads_and(same) && w0 != full) ? w0 : NO_WORD;
+}
+
 // ------------------------------------------------------------ batch select
 
 // Pass 1 (EMIT = false): matches per pair into pcount (64-bit, so that the
@@ -258,7 +298,7 @@ __global__ __launch_bounds__(BT_THREADS) void k_batch_select(SetArgs S, int64_t 
                                                              unsigned long long *pcount, const unsigned long long *pbase,
                                                              uint32_t *out, uint32_t q0, uint32_t q1,
                                                              unsigned long long kbase, const uint32_t *qrun0,
-                                                             int idbits, uint16_t *hits)
+                                                             int idbits, uint16_t *hits, const double4 *chunk_bb)
 {
     static_assert(BT_PER <= 16, "a thread's matches are kept as 16 bits");
     __shared__ uint32_t wsum[BT_THREADS / 64];
@@ -278,22 +318,32 @@ __global__ __launch_bounds__(BT_THREADS) void k_batch_select(SetArgs S, int64_t 
             const CanvasDesc d = S.cds[qy];
             const CanvasView v = set_view(d, S.cells, S.coarse, S.cands, S.ledges, S.pspan);
             uint32_t hit = 0;
+            const uint32_t cw = chunk_word(v, chunk_bb[c]);
+            if (cw != NO_WORD) {
+                // one word for the whole chunk: all of its points or none
+                if (cw != 0u) {
 #pragma unroll
-            for (int u = 0; u < BT_PER; ++u) {
-                const uint32_t w = lookup(v, v.coarse, xs[u], ys[u]);
-                bool in = false;
-                if (w & BFLAG) {
-                    uint32_t rec = w & ~BFLAG;
-                    while (true) {
-                        const Cand cd = v.cands[rec];
-                        if (cand_inside(v, cd, xs[u], ys[u])) in = true;
-                        if (cd.meta & CAND_LAST) break;
-                        ++rec;
-                    }
-                } else {
-                    in = w != 0u;
+                    for (int u = 0; u < BT_PER; ++u)
+                        if (b + (int64_t)u * BT_THREADS + threadIdx.x < nfin) hit |= 1u << u;
                 }
-                hit |= (in ? 1u : 0u) << u;
+            } else {
+#pragma unroll
+                for (int u = 0; u < BT_PER; ++u) {
+                    const uint32_t w = lookup(v, v.coarse, xs[u], ys[u]);
+                    bool in = false;
+                    if (w & BFLAG) {
+                        uint32_t rec = w & ~BFLAG;
+                        while (true) {
+                            const Cand cd = v.cands[rec];
+                            if (cand_inside(v, cd, xs[u], ys[u])) in = true;
+                            if (cd.meta & CAND_LAST) break;
+                            ++rec;
+                        }
+                    } else {
+                        in = w != 0u;
+                    }
+                    hit |= (in ? 1u : 0u) << u;
+                }
             }
             // block-wide exclusive scan of the per-thread match counts
             const uint32_t cnt = (uint32_t)__popc(hit);
@@ -532,7 +582,8 @@ __global__ __launch_bounds__(BT_THREADS) void k_batch_pairs(SetArgs S, int64_t n
                                                             const unsigned int *cbase, const uint32_t *plist,
                                                             const uint32_t *pq, int rshift, int pbits,
                                                             unsigned long long *rcount, uint32_t r0, uint32_t r1,
-                                                            unsigned long long *cursor, unsigned long long *keys)
+                                                            unsigned long long *cursor, unsigned long long *keys,
+                                                            const double4 *chunk_bb)
 {
     __shared__ unsigned long long s_cnt[PAIR_RANGES];
     __shared__ uint32_t wsum[BT_THREADS / 64];
@@ -557,6 +608,7 @@ __global__ __launch_bounds__(BT_THREADS) void k_batch_pairs(SetArgs S, int64_t n
             const CanvasDesc d = S.cds[pq[p]];
             const CanvasView v = set_view(d, S.cells, S.coarse, S.cands, S.ledges, S.pspan);
             uint32_t mine = 0;
+            const uint32_t cw = chunk_word(v, chunk_bb[c]);   // one word for the whole chunk, or NO_WORD
             // the matches of this thread's points, in two sweeps: count, write
             auto sweep = [&](auto &&emit) {
 #pragma unroll
@@ -564,6 +616,10 @@ __global__ __launch_bounds__(BT_THREADS) void k_batch_pairs(SetArgs S, int64_t n
                     if (!COUNT) {
                         const uint32_t r = pid[u] >> rshift;
                         if (r < r0 || r >= r1) continue;
+                    }
+                    if (cw != NO_WORD) {
+                        if (cw != 0u && b + (int64_t)u * BT_THREADS + threadIdx.x < nfin) emit(u, cw - 1u);
+                        continue;
                     }
                     const uint32_t w = lookup(v, v.coarse, xs[u], ys[u]);
                     if (w == 0u) continue;
@@ -692,7 +748,7 @@ __global__ __launch_bounds__(BT_THREADS) void k_batch_count_direct(SetArgs S, in
             for (uint32_t t = 0; t < nl; ++t) {
                 const CanvasDesc d = S.cds[qlist[t]];
                 const CanvasView v = set_view(d, S.cells, S.coarse, S.cands, S.ledges, S.pspan);
-                auto add = [&](uint32_t label) {
+                auto add_n = [&](uint32_t label, uint32_t k) {
                     const unsigned long long key = (unsigned long long)caller_id(S, d.poly_base + label) + 1ull;
                     uint32_t h = (uint32_t)(key * 0x9E3779B97F4A7C15ull >> 55) & (HSLOTS - 1);
                     for (int probe = 0; probe < 8; ++probe, h = (h + 1) & (HSLOTS - 1)) {
@@ -701,10 +757,17 @@ __global__ __launch_bounds__(BT_THREADS) void k_batch_count_direct(SetArgs S, in
                             cur = atomicCAS(&hkey[h], 0ull, key);
                             if (cur == 0ull) cur = key;
                         }
-                        if (cur == key) { atomicAdd(&hval[h], 1u); return; }
+                        if (cur == key) { atomicAdd(&hval[h], k); return; }
                     }
-                    atomicAdd(&counts[key - 1ull], 1ull);
+                    atomicAdd(&counts[key - 1ull], (unsigned long long)k);
                 };
+                auto add = [&](uint32_t label) { add_n(label, 1u); };
+                const uint32_t cw = chunk_word(v, cb);
+                if (cw != NO_WORD) {
+                    // one word for the whole chunk: its points all count for one polygon, or none
+                    if (cw != 0u && threadIdx.x == 0) add_n(cw - 1u, (uint32_t)min<int64_t>(CHUNK, nfin - b));
+                    continue;
+                }
 #pragma unroll
                 for (int u = 0; u < BT_PER; ++u) {
                     const uint32_t w = lookup(v, v.coarse, xs[u], ys[u]);
@@ -876,7 +939,10 @@ int spade_table_create(spade_ctx *ctx, const spade_points *pts, spade_table **ou
     t->X0 = x0; t->Y0 = y0;
     t->sx = (x1 > x0) ? G / (x1 - x0) : 0.0;
     t->sy = (y1 > y0) ? G / (y1 - y0) : 0.0;
-    const int64_t ncell = (int64_t)G * G;
+    // cells in Z order: codes below P * P, P the power of two >= G
+    int64_t P = 1;
+    while (P < G) P <<= 1;
+    const int64_t ncell = P * P;
     // sort by cell
     DevBuf &dk = ctx->scratch[S_KEYS], &dk2 = ctx->scratch[S_KEYS2], &dv = ctx->scratch[S_VALS];
     if (ensure(ctx, dk, 4 * ns) || ensure(ctx, dk2, 4 * ns) || ensure(ctx, dv, 4 * ns) ||
@@ -884,7 +950,7 @@ int spade_table_create(spade_ctx *ctx, const spade_points *pts, spade_table **ou
         return fail(SPADE_E_NOMEM);
     if (n > 0) {
         hipLaunchKernelGGL(k_pt_key, dim3(grid_of(n)), dim3(256), 0, st, n, pts->x, pts->y, t->X0, t->Y0, t->sx, t->sy,
-                           G, (uint32_t *)dk.p, (uint32_t *)dv.p);
+                           G, (uint32_t)ncell, (uint32_t *)dk.p, (uint32_t *)dv.p);
         SPADE_HIP(ctx, hipGetLastError());
         DevBuf &cub = ctx->scratch[S_CUBTMP];
         size_t tb = 0;
@@ -1037,7 +1103,8 @@ int spade_batch_select(spade_ctx *ctx, const spade_canvas *set, const spade_tabl
     if (np > 0) {
         hipLaunchKernelGGL(k_batch_select<false>, dim3(grid), dim3(BT_THREADS), 0, st, S, t->nfin, t->nchunk,
                            (const double *)t->x.p, (const double *)t->y.p, (const uint32_t *)t->ids.p, P.cbase,
-                           P.plist, P.pq, pcount, nullptr, nullptr, 0u, (uint32_t)nq, 0ull, nullptr, 0, hits);
+                           P.plist, P.pq, pcount, nullptr, nullptr, 0u, (uint32_t)nq, 0ull, nullptr, 0, hits,
+                           (const double4 *)t->chunk_bb.p);
         SPADE_HIP(ctx, hipGetLastError());
     }
     // the timed probe of a batch selection is its count pass
@@ -1178,7 +1245,8 @@ int spade_batch_select(spade_ctx *ctx, const spade_canvas *set, const spade_tabl
             hipLaunchKernelGGL(k_batch_select<true>, dim3(grid), dim3(BT_THREADS), 0, st, S, t->nfin, t->nchunk,
                                (const double *)t->x.p, (const double *)t->y.p, (const uint32_t *)t->ids.p, P.cbase,
                                P.plist, P.pq, nullptr, (const unsigned long long *)pbase, out, (uint32_t)q0,
-                               (uint32_t)q1, (unsigned long long)kbase, qrun0, idbits, nullptr);
+                               (uint32_t)q1, (unsigned long long)kbase, qrun0, idbits, nullptr,
+                               (const double4 *)t->chunk_bb.p);
         }
         SPADE_HIP(ctx, hipGetLastError());
         return SPADE_OK;
@@ -1335,7 +1403,8 @@ int spade_batch_join_pairs(spade_ctx *ctx, const spade_canvas *set, const spade_
     if (P.np > 0) {
         hipLaunchKernelGGL(k_batch_pairs<true>, dim3(grid), dim3(BT_THREADS), 0, st, S, t->nfin, t->nchunk,
                            (const double *)t->x.p, (const double *)t->y.p, (const uint32_t *)t->ids.p, P.cbase,
-                           P.plist, P.pq, rshift, pbits, rcount, 0u, 0u, nullptr, nullptr);
+                           P.plist, P.pq, rshift, pbits, rcount, 0u, 0u, nullptr, nullptr,
+                           (const double4 *)t->chunk_bb.p);
         SPADE_HIP(ctx, hipGetLastError());
     }
     unsigned long long *h = (unsigned long long *)ensure_pinned(ctx, sizeof(unsigned long long) * PAIR_RANGES);
@@ -1383,7 +1452,7 @@ int spade_batch_join_pairs(spade_ctx *ctx, const spade_canvas *set, const spade_
             hipLaunchKernelGGL(k_batch_pairs<false>, dim3(grid), dim3(BT_THREADS), 0, st, S, t->nfin, t->nchunk,
                                (const double *)t->x.p, (const double *)t->y.p, (const uint32_t *)t->ids.p, P.cbase,
                                P.plist, P.pq, rshift, pbits, nullptr, r.r0, r.r1, cursor,
-                               (unsigned long long *)bo.p);
+                               (unsigned long long *)bo.p, (const double4 *)t->chunk_bb.p);
             SPADE_HIP(ctx, hipGetLastError());
             SPADE_HIP(ctx, hipcub::DeviceRadixSort::SortKeys(cub.p, tb, (const unsigned long long *)bo.p,
                                                              (unsigned long long *)bo2.p, (int)(r.k1 - r.k0), 0,
