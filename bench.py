@@ -241,8 +241,9 @@ def leg_c3(ctx, with_host, extra, restore_ppv):
             "points": N, "ids": n_ids, "autotune": {"pixels_per_vertex": ppv,
                                                     "trial_ms": {str(k): round(v, 3) for k, v in trials.items()}}, "ms_per_call": round(float(np.mean(ms)), 3), "probe_ms": round(pm, 3),
             "points_per_s": round(N / (float(np.mean(ms)) / 1e3), 1),
-            "roofline": roofline("k_emit_count + k_emit", 16.0 * N + 4.0 * n_ids, pm,
-                                 bytes_rule="16 B/point + 4 B/id"),
+            "roofline": roofline("k_emit_count_bits + k_emit_bits", 16.0 * N + 4.0 * n_ids, pm,
+                                 bytes_rule="16 B/point + 4 B/id (the write pass reads 1 result bit "
+                                            "per point, not the points)"),
             "gpu_matches_oracle_digest": parity}
 
 

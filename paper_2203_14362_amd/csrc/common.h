@@ -138,7 +138,7 @@ struct spade_ctx {
     std::string err;
     int32_t canvas_w = 0, canvas_h = 0;     // 0 = automatic
     double ppv = 256.0;                     // automatic sizing: pixels per vertex
-    spade::DevBuf scratch[17];              // reusable scratch slots (spade::S_NSLOTS)
+    spade::DevBuf scratch[18];              // reusable scratch slots (spade::S_NSLOTS)
     void *pinned = nullptr;                 // small pinned host staging area
     void *pend = nullptr;                   // pinned counters and flags of a deferred build
     spade_canvas *plain = nullptr;          // canvas reused by the plain query calls
@@ -169,10 +169,12 @@ namespace spade {
 // Scratch slot ids inside a context.
 enum Slot {
     S_BLOCKRED = 0, S_RINGPOLY, S_NROWS, S_ROWOFF, S_KEYS, S_KEYS2, S_VALS, S_VALS2,
-    S_ENTC, S_ENTF, S_CUBTMP, S_ROWCNT, S_NEXTP, S_PROBE, S_LOOKBACK, S_MISC, S_ROWSCAN, S_NSLOTS
+    S_ENTC, S_ENTF, S_CUBTMP, S_ROWCNT, S_NEXTP, S_PROBE, S_LOOKBACK, S_MISC, S_ROWSCAN,
+    S_BITS,     // the ordered emit's per-point result bits (used by nothing else)
+    S_NSLOTS
 };
 
-static_assert(S_NSLOTS == 17, "scratch slot count of spade_ctx");
+static_assert(S_NSLOTS == 18, "scratch slot count of spade_ctx");
 
 int set_error(spade_ctx *ctx, int code, const std::string &msg);
 int hip_fail(spade_ctx *ctx, hipError_t e, const char *what);

@@ -602,6 +602,144 @@ __global__ __launch_bounds__(EMIT_THREADS) void k_emit_count(CanvasView cv, int6
     }
 }
 
+// Count pass for a canvas of one polygon (a point matches at most once)
+// that also keeps every point's result, so that the write pass reads bits
+// instead of the points: bits[sg * (EMIT_SEG / 64) + j] holds the matches of
+// points sg * EMIT_SEG + 64 j + lane (bit = lane).  Boundary points are
+// queued and tested a wavefront at a time as in k_emit; each lane takes its
+// own points' results back with a shuffle.
+__global__ __launch_bounds__(EMIT_THREADS) void k_emit_count_bits(CanvasView cv, int64_t n, const double *X,
+                                                                  const double *Y, int64_t nseg,
+                                                                  unsigned long long *counts,
+                                                                  unsigned long long *bits)
+{
+    static_assert(EMIT_THREADS == CNT_THREADS, "the queue area is sized for CNT_THREADS");
+    static_assert(EMIT_SEG / 64 <= 64, "a segment's words are held one per lane");
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint16_t *coarse = (uint16_t *)smem;
+    const size_t coarse_bytes = ((size_t)cv.Wc * cv.Hc * (cv.cbyte ? 1 : 2) + 15) & ~(size_t)15;
+    unsigned char *qbase = smem + coarse_bytes;
+    const int wv = threadIdx.x >> 6;
+    double *qx = (double *)(qbase) + wv * QCAP;
+    double *qy = (double *)(qbase) + (EMIT_THREADS / 64) * QCAP + wv * QCAP;
+    uint32_t *qr = (uint32_t *)((double *)(qbase) + 2 * (EMIT_THREADS / 64) * QCAP) + wv * QCAP;
+    load_coarse(cv, coarse, EMIT_THREADS);
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const int64_t nwave = ((int64_t)gridDim.x * EMIT_THREADS) >> 6;
+    for (int64_t sg = ((int64_t)blockIdx.x * EMIT_THREADS + threadIdx.x) >> 6; sg < nseg; sg += nwave) {
+        const int64_t i0 = sg * EMIT_SEG + lane;
+        unsigned long long total = 0;   // wave-uniform
+        unsigned long long segw = 0;    // lane j < EMIT_SEG / 64: the word of points 64 j ..
+        for (int g = 0; g < EMIT_SEG / 64; g += EMIT_WGROUP) {
+            double xs[EMIT_WGROUP], ys[EMIT_WGROUP];
+#pragma unroll
+            for (int k = 0; k < EMIT_WGROUP; ++k) {
+                const int64_t i = i0 + 64 * (g + k);
+                xs[k] = i < n ? __builtin_nontemporal_load(X + i) : NAN;   // NaN: outside
+                ys[k] = i < n ? __builtin_nontemporal_load(Y + i) : NAN;
+            }
+            uint32_t ws[EMIT_WGROUP];
+#pragma unroll
+            for (int k = 0; k < EMIT_WGROUP; ++k) {
+                const Look lk = look_coarse(cv, coarse, xs[k], ys[k]);
+                ws[k] = lk.full ? ((gu32p)cv.cells)[lk.fidx] : lk.word;
+            }
+            uint32_t hit = 0, slot[EMIT_WGROUP];   // hit: bit k for this lane's point k
+            uint32_t qn = 0, pend = 0, mine = 0;
+            auto drain = [&]() {
+                __builtin_amdgcn_wave_barrier();
+                uint32_t m = 0;
+                if (lane < (int)qn) {
+                    const double x = qx[lane], y = qy[lane];
+                    uint32_t rec = qr[lane];
+                    while (true) {
+                        const Cand c0 = cv.cands[rec];
+                        if (cand_inside(cv, c0, x, y)) m = 1u;
+                        if (c0.meta & CAND_LAST) break;
+                        ++rec;
+                    }
+                }
+                __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                for (int k = 0; k < EMIT_WGROUP; ++k) {
+                    if (!(pend & (1u << k))) continue;
+                    const uint32_t c = (uint32_t)__shfl((int)m, (int)slot[k], 64);
+                    if ((mine & (1u << k)) && c) hit |= 1u << k;
+                }
+                pend = 0;
+                mine = 0;
+                qn = 0;
+            };
+#pragma unroll
+            for (int k = 0; k < EMIT_WGROUP; ++k) {
+                const uint32_t w = ws[k];
+                const bool bnd = (w & BFLAG) != 0;
+                if (w != 0u && !bnd) hit |= 1u << k;
+                slot[k] = 0;
+                const unsigned long long mask = __ballot(bnd);
+                const uint32_t nnew = (uint32_t)__popcll(mask);
+                if (nnew == 0) continue;
+                if (qn + nnew > QCAP) drain();
+                if (bnd) {
+                    const uint32_t sl = qn + (uint32_t)__popcll(mask & below);
+                    qx[sl] = xs[k];
+                    qy[sl] = ys[k];
+                    qr[sl] = w & ~BFLAG;
+                    slot[k] = sl;
+                    mine |= 1u << k;
+                }
+                qn += nnew;
+                pend |= 1u << k;
+            }
+            if (qn) drain();
+#pragma unroll
+            for (int k = 0; k < EMIT_WGROUP; ++k) {
+                const unsigned long long word = __ballot((hit >> k) & 1u);
+                total += (unsigned long long)__popcll(word);
+                if (lane == g + k) segw = word;
+            }
+        }
+        if (lane < EMIT_SEG / 64) bits[sg * (EMIT_SEG / 64) + lane] = segw;
+        if (lane == 0) counts[sg] = total;
+    }
+}
+
+// Write pass from the count pass's bits: each wavefront takes segments,
+// every lane 16 of a segment's points, and writes the ids of the set bits
+// ascending from offs[segment] on (below cap; polygon 0 into out_poly).
+__global__ __launch_bounds__(256) void k_emit_bits(int64_t nseg, const unsigned long long *offs,
+                                                   const unsigned long long *bits, uint32_t *out_pt,
+                                                   uint32_t *out_poly, int64_t cap)
+{
+    static_assert(EMIT_SEG == 64 * 16, "one lane takes 16 points of a segment");
+    const int lane = threadIdx.x & 63;
+    const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t sg = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; sg < nseg; sg += nwave) {
+        const unsigned long long word = bits[sg * (EMIT_SEG / 64) + (lane >> 2)];
+        uint32_t part = (uint32_t)(word >> (16 * (lane & 3))) & 0xffffu;
+        const uint32_t cnt = (uint32_t)__popc(part);
+        uint32_t inc = cnt;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t t = __shfl_up(inc, d, 64);
+            if (lane >= d) inc += t;
+        }
+        int64_t pos = (int64_t)offs[sg] + (inc - cnt);
+        const uint32_t base = (uint32_t)(sg * EMIT_SEG + 16 * lane);
+        while (part) {
+            const int b = __ffs(part) - 1;
+            part &= part - 1u;
+            if (pos < cap) {
+                out_pt[pos] = base + (uint32_t)b;
+                if (out_poly) out_poly[pos] = 0u;
+            }
+            ++pos;
+        }
+    }
+}
+
 __global__ void k_emit_zero(unsigned long long *p) { *p = 0ull; }
 
 int probe_emit(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts, uint32_t *out_pt,
@@ -627,9 +765,26 @@ int probe_emit(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts, 
                                        (int)(lds + QUEUE_BYTES)));
     SPADE_HIP(ctx, hipFuncSetAttribute((const void *)k_emit, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)(lds + QUEUE_BYTES)));
+    // a canvas of one polygon keeps every point's result in the count pass
+    // (one bit per point), so that the write pass need not read the points
+    unsigned long long *bits = nullptr;
+    if (cv->view.M == 1 && cap > 0) {
+        DevBuf &bb = ctx->scratch[S_BITS];
+        if (ensure(ctx, bb, sizeof(unsigned long long) * (EMIT_SEG / 64) * (size_t)nseg) == SPADE_OK)
+            bits = (unsigned long long *)bb.p;
+        else
+            ctx->err.clear();   // read the points twice instead
+    }
+    if (bits)
+        SPADE_HIP(ctx, hipFuncSetAttribute((const void *)k_emit_count_bits, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)(lds + QUEUE_BYTES)));
     if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[2], st));
-    hipLaunchKernelGGL(k_emit_count, dim3(grid), dim3(EMIT_THREADS), lds + QUEUE_BYTES, st, cv->view, n, pts->x,
-                       pts->y, nseg, counts);
+    if (bits)
+        hipLaunchKernelGGL(k_emit_count_bits, dim3(grid), dim3(EMIT_THREADS), lds + QUEUE_BYTES, st, cv->view, n,
+                           pts->x, pts->y, nseg, counts, bits);
+    else
+        hipLaunchKernelGGL(k_emit_count, dim3(grid), dim3(EMIT_THREADS), lds + QUEUE_BYTES, st, cv->view, n, pts->x,
+                           pts->y, nseg, counts);
     hipLaunchKernelGGL(k_emit_zero, dim3(1), dim3(1), 0, st, counts + nseg);
     SPADE_HIP(ctx, hipGetLastError());
     DevBuf &cub = ctx->scratch[S_CUBTMP];
@@ -637,7 +792,11 @@ int probe_emit(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts, 
     SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(nullptr, tb, counts, offs, (int)(nseg + 1), st));
     if (ensure(ctx, cub, std::max<size_t>(tb, 1))) return SPADE_E_NOMEM;
     SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(cub.p, tb, counts, offs, (int)(nseg + 1), st));
-    if (cap > 0) {
+    if (cap > 0 && bits) {
+        const int bg = (int)std::max<int64_t>(1, std::min<int64_t>((nseg + 3) / 4, (int64_t)cus * 16));
+        hipLaunchKernelGGL(k_emit_bits, dim3(bg), dim3(256), 0, st, nseg, offs, bits, out_pt, out_poly, cap);
+        SPADE_HIP(ctx, hipGetLastError());
+    } else if (cap > 0) {
         hipLaunchKernelGGL(k_emit, dim3(grid), dim3(EMIT_THREADS), lds + QUEUE_BYTES, st, cv->view, n, pts->x,
                            pts->y, nseg, offs, out_pt, out_poly, cap);
         SPADE_HIP(ctx, hipGetLastError());
