@@ -706,36 +706,31 @@ __global__ __launch_bounds__(EMIT_THREADS) void k_emit_count_bits(CanvasView cv,
     }
 }
 
-// Write pass from the count pass's bits: each wavefront takes segments,
-// every lane 16 of a segment's points, and writes the ids of the set bits
-// ascending from offs[segment] on (below cap; polygon 0 into out_poly).
+// Write pass from the count pass's bits: each wavefront takes segments and
+// walks a segment's words in point order; lane l writes point 64 j + l of
+// word j, so the ids of a word are stored to consecutive positions (below
+// cap; polygon 0 into out_poly), from offs[segment] on.
 __global__ __launch_bounds__(256) void k_emit_bits(int64_t nseg, const unsigned long long *offs,
                                                    const unsigned long long *bits, uint32_t *out_pt,
                                                    uint32_t *out_poly, int64_t cap)
 {
-    static_assert(EMIT_SEG == 64 * 16, "one lane takes 16 points of a segment");
     const int lane = threadIdx.x & 63;
+    const unsigned long long below = (1ull << lane) - 1ull;
     const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) >> 6;
     for (int64_t sg = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; sg < nseg; sg += nwave) {
-        const unsigned long long word = bits[sg * (EMIT_SEG / 64) + (lane >> 2)];
-        uint32_t part = (uint32_t)(word >> (16 * (lane & 3))) & 0xffffu;
-        const uint32_t cnt = (uint32_t)__popc(part);
-        uint32_t inc = cnt;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const uint32_t t = __shfl_up(inc, d, 64);
-            if (lane >= d) inc += t;
-        }
-        int64_t pos = (int64_t)offs[sg] + (inc - cnt);
-        const uint32_t base = (uint32_t)(sg * EMIT_SEG + 16 * lane);
-        while (part) {
-            const int b = __ffs(part) - 1;
-            part &= part - 1u;
-            if (pos < cap) {
-                out_pt[pos] = base + (uint32_t)b;
-                if (out_poly) out_poly[pos] = 0u;
+        int64_t pos = (int64_t)offs[sg];
+        const unsigned long long mine = lane < EMIT_SEG / 64 ? bits[sg * (EMIT_SEG / 64) + lane] : 0ull;
+        for (int j = 0; j < EMIT_SEG / 64; ++j) {
+            const unsigned long long word = (unsigned long long)__shfl((long long)mine, j, 64);
+            if (!word) continue;   // uniform over the wavefront
+            if ((word >> lane) & 1ull) {
+                const int64_t p = pos + __popcll(word & below);
+                if (p < cap) {
+                    out_pt[p] = (uint32_t)(sg * EMIT_SEG + 64 * j + lane);
+                    if (out_poly) out_poly[p] = 0u;
+                }
             }
-            ++pos;
+            pos += __popcll(word);
         }
     }
 }
