@@ -442,8 +442,14 @@ __global__ __launch_bounds__(BKT_THREADS) void k_bucket_hist(int64_t n, const ui
     for (int b = threadIdx.x; b < BUCKETS_MAX; b += BKT_THREADS) h[b] = 0u;
     __syncthreads();
     const int64_t nth = (int64_t)gridDim.x * BKT_THREADS;
-    for (int64_t i = (int64_t)blockIdx.x * BKT_THREADS + threadIdx.x; i < n; i += nth)
-        atomicAdd(&h[keys[i] >> L], 1u);
+    for (int64_t i0 = (int64_t)blockIdx.x * BKT_THREADS + threadIdx.x; i0 < n; i0 += 8 * nth) {
+        uint32_t kk[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) kk[u] = i0 + u * nth < n ? keys[i0 + u * nth] : 0u;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (i0 + u * nth < n) atomicAdd(&h[kk[u] >> L], 1u);
+    }
     __syncthreads();
     for (int b = threadIdx.x; b < BUCKETS_MAX; b += BKT_THREADS)
         if (h[b]) atomicAdd(&hist[b], h[b]);
@@ -519,48 +525,97 @@ __global__ __launch_bounds__(BKT_THREADS) void k_bucket_scatter(int64_t n, const
 // Bucket b's keys keys[boff[b], boff[b+1]) in ascending id order: the ids
 // (window << L | bit) of the set bits of its LDS bitmap, written to
 // out[boff[b] ...] below limit.  Reads every key of the bucket before
-// writing, so out may be keys (the buckets are disjoint ranges).
+// writing, so out may be keys (the buckets are disjoint ranges).  The bitmap
+// is read in blocks of 64 words; the ids of a block are written 64 at a
+// time, lane l taking the block's (r * 64 + l)-th set bit, so that a
+// wavefront's stores go to consecutive positions.
+constexpr int BM_WORDS_MAX = (1 << SORT_LBITS) >> 5;
+constexpr int BM_BLOCKS_MAX = BM_WORDS_MAX / 64;
+
 __global__ __launch_bounds__(BKT_THREADS) void k_bucket_bitmap(int nb, const uint32_t *boff, const uint32_t *keys,
                                                                int L, int H, uint32_t *out, int64_t limit)
 {
-    extern __shared__ uint32_t bm[];            // 2^L bits
+    extern __shared__ uint32_t bm[];            // 2^L bits, whole blocks of 64 words
+    __shared__ uint32_t btot[BM_BLOCKS_MAX];    // set bits per block, then the blocks' offsets
     __shared__ uint32_t wsum[BKT_THREADS / 64];
-    const int nw = (1 << L) >> 5 > 0 ? (1 << L) >> 5 : 1;
-    const int per = (nw + BKT_THREADS - 1) / BKT_THREADS;
-    const uint32_t lmask = (L >= 32) ? 0xffffffffu : ((1u << L) - 1u);
+    const int nw = ((1 << L) >> 5) > 0 ? (1 << L) >> 5 : 1;
+    const int nbk = (nw + 63) / 64;
+    const uint32_t lmask = (1u << L) - 1u;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    constexpr int NWAVE = BKT_THREADS / 64;
     for (int b = blockIdx.x; b < nb; b += gridDim.x) {
         const uint32_t s = boff[b], e = boff[b + 1];
         if (s == e || (int64_t)s >= limit) continue;   // uniform over the workgroup
-        for (int w = threadIdx.x; w < nw; w += BKT_THREADS) bm[w] = 0u;
+        for (int w = threadIdx.x; w < nbk * 64; w += BKT_THREADS) bm[w] = 0u;
         __syncthreads();
-        for (uint32_t i = s + threadIdx.x; i < e; i += BKT_THREADS) {
-            const uint32_t lo = keys[i] & lmask;
-            atomicOr(&bm[lo >> 5], 1u << (lo & 31));
+        // eight keys of each thread in flight at a time
+        for (uint32_t i0 = s; i0 < e; i0 += 8 * BKT_THREADS) {
+            uint32_t kk[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const uint32_t i = i0 + (uint32_t)(u * BKT_THREADS) + threadIdx.x;
+                kk[u] = i < e ? keys[i] : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (i0 + (uint32_t)(u * BKT_THREADS) + threadIdx.x >= e) continue;
+                const uint32_t lo = kk[u] & lmask;
+                atomicOr(&bm[lo >> 5], 1u << (lo & 31));
+            }
         }
         __syncthreads();
-        // thread t owns words [t * per, (t + 1) * per)
-        const int w0 = threadIdx.x * per;
-        uint32_t cnt = 0;
-        for (int w = w0; w < w0 + per && w < nw; ++w) cnt += (uint32_t)__popc(bm[w]);
-        uint32_t inc = cnt;
-        for (int d = 1; d < 64; d <<= 1) {
-            const uint32_t t = __shfl_up(inc, d, 64);
-            if (lane >= d) inc += t;
+        // set bits per block of 64 words
+        for (int k = wv; k < nbk; k += NWAVE) {
+            uint32_t c = (uint32_t)__popc(bm[k * 64 + lane]);
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) c += __shfl_xor(c, d, 64);
+            if (lane == 0) btot[k] = c;
         }
-        if (lane == 63) wsum[wv] = inc;
         __syncthreads();
-        uint32_t pre = 0;
-        for (int w = 0; w < wv; ++w) pre += wsum[w];
-        int64_t pos = (int64_t)s + pre + inc - cnt;
+        // exclusive scan of the block totals (nbk <= BKT_THREADS)
+        {
+            const uint32_t v = threadIdx.x < nbk ? btot[threadIdx.x] : 0u;
+            uint32_t inc = v;
+            for (int d = 1; d < 64; d <<= 1) {
+                const uint32_t t = __shfl_up(inc, d, 64);
+                if (lane >= d) inc += t;
+            }
+            if (lane == 63) wsum[wv] = inc;
+            __syncthreads();
+            uint32_t pre = 0;
+            for (int w = 0; w < wv; ++w) pre += wsum[w];
+            if (threadIdx.x < nbk) btot[threadIdx.x] = pre + inc - v;
+        }
+        __syncthreads();
         const uint32_t hi = (H > 0) ? ((uint32_t)b & ((1u << H) - 1u)) << L : 0u;
-        for (int w = w0; w < w0 + per && w < nw; ++w) {
-            uint32_t m = bm[w];
-            while (m) {
-                const int bit = __ffs(m) - 1;
-                m &= m - 1u;
-                if (pos < limit) out[pos] = hi | ((uint32_t)w << 5) | (uint32_t)bit;
-                ++pos;
+        for (int k = wv; k < nbk; k += NWAVE) {
+            const uint32_t word = bm[k * 64 + lane];
+            const uint32_t c = (uint32_t)__popc(word);
+            uint32_t incl = c;
+            for (int d = 1; d < 64; d <<= 1) {
+                const uint32_t t = __shfl_up(incl, d, 64);
+                if (lane >= d) incl += t;
+            }
+            const uint32_t excl = incl - c;
+            const uint32_t T = (uint32_t)__shfl((int)incl, 63, 64);
+            const int64_t base = (int64_t)s + btot[k];
+            for (uint32_t r0 = 0; r0 < T; r0 += 64) {
+                const uint32_t o = r0 + (uint32_t)lane;
+                // the word holding set bit o of the block: the last lane whose
+                // exclusive count is <= o
+                int at = 0;
+                for (int step = 32; step >= 1; step >>= 1) {
+                    const uint32_t ex = (uint32_t)__shfl((int)excl, at + step < 64 ? at + step : 63, 64);
+                    if (at + step < 64 && ex <= o) at += step;
+                }
+                uint32_t w = (uint32_t)__shfl((int)word, at, 64);
+                const uint32_t ex_at = (uint32_t)__shfl((int)excl, at, 64);
+                if (o < T) {
+                    for (uint32_t skip = o - ex_at; skip; --skip) w &= w - 1u;
+                    const int bit = __ffs(w) - 1;
+                    const int64_t pos = base + o;
+                    if (pos < limit) out[pos] = hi | ((uint32_t)(k * 64 + at) << 5) | (uint32_t)bit;
+                }
             }
         }
         __syncthreads();
@@ -1185,7 +1240,8 @@ int spade_batch_select(spade_ctx *ctx, const spade_canvas *set, const spade_tabl
     uint32_t *qrun0 = (uint32_t *)br.p;
     uint32_t *bhist = qrun0 + nq, *boff = bhist + nbmax, *bcur = boff + nbmax + 1;
     SPADE_HIP(ctx, hipMemcpyAsync(qrun0, hrun0.data(), sizeof(uint32_t) * (size_t)nq, hipMemcpyHostToDevice, st));
-    const size_t bm_lds = sizeof(uint32_t) * (size_t)std::max(1, (1 << LB) >> 5);
+    // the bitmap in whole blocks of 64 words
+    const size_t bm_lds = sizeof(uint32_t) * 64 * (size_t)((std::max(1, (1 << LB) >> 5) + 63) / 64);
     SPADE_HIP(ctx, hipFuncSetAttribute((const void *)k_bucket_bitmap, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)bm_lds));
     // with one window per query, a run's buckets are its queries: their

@@ -236,3 +236,20 @@ def test_batch_select_without_hit_masks(ctx, table_pts, stars, monkeypatch):
         assert np.array_equal(_u32(ids2)[off[q]:off[q + 1]], oracle.select(x, y, polys, q)), q
     b.close()
     t.close()
+
+
+@pytest.mark.parametrize("n", [1, 7, 33, 70])
+def test_batch_select_tiny_tables(ctx, n):
+    """Id spaces of a few bits: the ordering bitmap is a single word."""
+    rng = np.random.default_rng(50 + n)
+    x = rng.uniform(0.2, 0.8, n)
+    y = rng.uniform(0.2, 0.8, n)
+    polys, qb = gen.query_stars(5, 8, 40, seed=51, L=1.0, area=(0.05, 0.4), data_seed=3)
+    t = ctx.table(_dev(x), _dev(y))
+    b = ctx.batch(polys, qb)
+    ids, off = ctx.batch_select(b, t)
+    ids = _u32(ids)
+    for q in range(5):
+        assert np.array_equal(ids[off[q]:off[q + 1]], oracle.select(x, y, polys, q)), q
+    b.close()
+    t.close()
