@@ -256,7 +256,14 @@ def leg_c4(ctx, dx, dy, table):
     nq = len(qb) - 1
     res = {"workload": "1,024 star selections (8-20,000 vertices, areas 1e-4..0.15) and a 40,000-cell "
                        "census-like join-count over a resident 200M-point table", "table_points": N}
-    # batched: rasterise all queries as one canvas set, one pass over the table
+    # batched: rasterise all queries as one canvas set, one pass over the table,
+    # at the canvas resolution the autotuner picks for this batch
+    from paper_2203_14362_amd.autotune import Autotuner, BATCH_SELECT_CANDIDATES, tune_batch_select
+    restore_ppv = ctx.pixels_per_vertex()
+    bppv, btrials = tune_batch_select(ctx, stars, qb, table,
+                                      Autotuner(candidates=BATCH_SELECT_CANDIDATES, repeats=1), force=True)
+    log("c4 autotune: %.0f pixels per vertex (trials %s)" % (bppv, {k: round(v, 1) for k, v in btrials.items()}))
+    torch.cuda.empty_cache()
     ctx.set_timing(True)
     b = ctx.batch(stars, qb)
     ids, off = ctx.batch_select(b, table)
@@ -286,6 +293,7 @@ def leg_c4(ctx, dx, dy, table):
     del ids
     b.close()
     torch.cuda.empty_cache()
+    ctx.set_pixels_per_vertex(restore_ppv)
     # one query at a time through the plain call, on a sample of queries
     rvo = stars["ring_vtx_off"]
     sample = list(range(0, nq, 32))
@@ -305,6 +313,8 @@ def leg_c4(ctx, dx, dy, table):
     res["select_batched"] = {"queries": nq, "ids": total, "seconds": round(tb, 4),
                              "queries_per_s": round(nq / tb, 1), "points_queries_per_s": round(N * nq / tb, 1),
                              "gpu_matches_oracle_subsample": parity,
+                             "autotune": {"pixels_per_vertex": bppv,
+                                          "trial_ms": {str(k): round(v, 1) for k, v in btrials.items()}},
                              "chunk_query_overlaps": overlaps,
                              "roofline": roofline("k_batch_select (count pass)", BYTES_PER_POINT * CHUNK_POINTS * overlaps,
                                                   count_ms,

@@ -139,3 +139,41 @@ def tune_select(ctx, x, y, poly, tuner: Autotuner = None, force: bool = False):
         ctx.set_timing(was)
     ctx.set_pixels_per_vertex(ppv)
     return ppv, times
+
+
+BATCH_SELECT_CANDIDATES = (12.0, 24.0, 48.0, 96.0)
+
+
+def tune_batch_select(ctx, polys, qbound, table, tuner: Autotuner = None, force: bool = False):
+    """Tune and set ctx's pixels-per-vertex for batch selections of the
+    queries [qbound[q], qbound[q+1]) of `polys` over `table`: each trial
+    rebuilds the batch's canvas set and selects, timed on the host around a
+    device synchronisation (rasterisation, count pass, write pass and
+    ordering).  Returns (ppv, times)."""
+    import time
+    import numpy as np
+    import torch
+    tuner = tuner or Autotuner(candidates=BATCH_SELECT_CANDIDATES, repeats=2)
+    qb = np.asarray(qbound, dtype=np.int64)
+    nv = int(np.asarray(polys["ring_vtx_off"])[-1]) if len(polys["ring_vtx_off"]) else 0
+    key = signature("batch_select/q%d" % (qb.size - 1), int(polys["n_polys"]), nv, int(table.info()["n_points"]))
+    state = {"b": None}
+
+    def trial(ppv):
+        ctx.set_pixels_per_vertex(ppv)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        state["b"] = ctx.batch(polys, qb, into=state["b"])
+        ids, off = ctx.batch_select(state["b"], table)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) * 1e3
+        del ids
+        return dt
+
+    try:
+        ppv, times = tuner.tune(key, trial, force=force)
+    finally:
+        if state["b"] is not None:
+            state["b"].close()
+    ctx.set_pixels_per_vertex(ppv)
+    return ppv, times

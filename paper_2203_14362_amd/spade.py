@@ -465,6 +465,11 @@ class Context:
 
     def set_pixels_per_vertex(self, ppv: float):
         self._check(self.lib.spade_ctx_set_pixels_per_vertex(self.handle, float(ppv)))
+        self._ppv = float(ppv)
+
+    def pixels_per_vertex(self) -> float:
+        """The automatic canvas sizing's pixels per polygon vertex."""
+        return getattr(self, "_ppv", 256.0)
 
     def polys(self, polys):
         return polys if isinstance(polys, DevicePolys) else DevicePolys(polys, self.device)
