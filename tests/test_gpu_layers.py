@@ -134,3 +134,28 @@ def test_layered_degenerate(ctx, table_pts):
     counts = ctx.batch_join_count(b, t).cpu().numpy().astype(np.uint64)
     assert np.array_equal(counts, oracle.join_count(x, y, tiny))
     b.close()
+
+
+def test_batch_join_pairs_capacity_writes_first_cap(ctx, table_pts):
+    """A capacity below the total: the first cap pairs of the (point,
+    polygon) order are written and the total reported; with room for all of
+    them every pair is written."""
+    import ctypes
+    from paper_2203_14362_amd import spade
+    x, y, t = table_pts
+    polys = _overlap_set(66, nstars=30)
+    b = ctx.layered(polys)
+    opt, opg = oracle.join_pairs(x, y, polys)
+    for cap in (opt.size, opt.size + 7, opt.size // 3):
+        bpt = torch.full((max(cap, 1),), -1, dtype=torch.int32, device="cuda")
+        bpg = torch.full((max(cap, 1),), -1, dtype=torch.int32, device="cuda")
+        n = ctypes.c_int64()
+        ctx._sync_stream()
+        rc = ctx.lib.spade_batch_join_pairs(ctx.handle, b.handle, t.handle, ctypes.c_void_p(bpt.data_ptr()),
+                                            ctypes.c_void_p(bpg.data_ptr()), cap, ctypes.byref(n))
+        assert n.value == opt.size
+        assert rc == (spade.SPADE_OK if cap >= opt.size else spade.SPADE_E_CAPACITY)
+        m = min(cap, opt.size)
+        assert np.array_equal(bpt[:m].cpu().numpy().astype(np.uint32), opt[:m]), cap
+        assert np.array_equal(bpg[:m].cpu().numpy().astype(np.uint32), opg[:m]), cap
+    b.close()
