@@ -501,6 +501,16 @@ def leg_serve(dx, dy, seconds, warm_seconds, qps, oneshot):
     measured = [r for r in reqs if r.arrival >= t_warm]
     st = latency_stats(measured)
     waits = np.array([r.admitted - r.arrival for r in measured])
+    # latency by request kind, and the time from admission to completion
+    by_kind = {}
+    for kind in ("select", "count"):
+        lat = np.array([r.done - r.arrival for r in measured if r.kind == kind]) * 1e3
+        svc = np.array([r.done - r.admitted for r in measured if r.kind == kind]) * 1e3
+        if lat.size:
+            by_kind[kind] = {"requests": int(lat.size), "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                             "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                             "service_p50_ms": round(float(np.percentile(svc, 50)), 3),
+                             "service_p99_ms": round(float(np.percentile(svc, 99)), 3)}
     bsz = [len(bch) for bch in srv.batches]
     log("served %d requests (%d measured) in %.2fs: p50 %.2f ms, p99 %.2f ms, mean batch %.2f"
         % (n, len(measured), wall, st["p50_ms"], st["p99_ms"], float(np.mean(bsz))))
@@ -542,6 +552,7 @@ def leg_serve(dx, dy, seconds, warm_seconds, qps, oneshot):
             "served_requests_per_s": round(n / wall, 1),
             "admission_wait_p50_ms": round(float(np.percentile(waits, 50)) * 1e3, 3),
             "admission_wait_p99_ms": round(float(np.percentile(waits, 99)) * 1e3, 3),
+            "by_kind": by_kind,
             "batches": len(bsz), "mean_batch": round(float(np.mean(bsz)), 2), "max_batch": int(max(bsz)),
             "peak_accounted_gib": round(srv.peak_accounted / 2 ** 30, 2), "budget_gib": round(budget / 2 ** 30, 1),
             "free_hbm_gib_min_max": [round(min(trace) / 2 ** 30, 2), round(max(trace) / 2 ** 30, 2)],

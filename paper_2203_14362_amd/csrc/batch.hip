@@ -760,13 +760,16 @@ constexpr int HSLOTS = 512;   // LDS hash slots per workgroup
 // launches are captured into a graph and replayed batch after batch, each
 // replay reading the canvas set's descriptors as rebuilt for that batch.
 constexpr int QL_MAX = 1024;
+constexpr int64_t HIST_MAX_BATCH = 8192;   // polygons the count probe histograms in LDS
 
-__global__ void k_qbox(int nq, const CanvasDesc *cds, double4 *qbox)
+// Per-canvas boxes for the direct probe; a canvas with skip[q] set (counted
+// by another launch) gets an empty box.
+__global__ void k_qbox(int nq, const CanvasDesc *cds, const uint8_t *skip, double4 *qbox)
 {
     for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += gridDim.x * blockDim.x) {
         const CanvasDesc d = cds[q];
-        qbox[q] = d.empty ? make_double4(INFINITY, INFINITY, -INFINITY, -INFINITY)
-                          : make_double4(d.bx0, d.by0, d.bx1, d.by1);
+        qbox[q] = (d.empty || (skip && skip[q])) ? make_double4(INFINITY, INFINITY, -INFINITY, -INFINITY)
+                                                 : make_double4(d.bx0, d.by0, d.bx1, d.by1);
     }
 }
 
@@ -1338,11 +1341,11 @@ void drop_batch_graph(spade_canvas *cv)
 // The batch join-count's launches (clear the counts, the canvas boxes, the
 // one-pass probe) for the current buffers; all parameters are in `key`.
 static hipError_t batch_count_launches(spade_ctx *ctx, const spade_canvas *set, const spade_table *t, int64_t M,
-                                       uint64_t *out_counts, hipStream_t s)
+                                       uint64_t *out_counts, hipStream_t s, const uint8_t *skip = nullptr)
 {
     const int nq = set->nc;
     if (M > 0) hipLaunchKernelGGL(k_zero64, dim3(grid_of(M, 4096)), dim3(256), 0, s, M, (unsigned long long *)out_counts);
-    hipLaunchKernelGGL(k_qbox, dim3((nq + 255) / 256), dim3(256), 0, s, nq, (const CanvasDesc *)set->dcds.p,
+    hipLaunchKernelGGL(k_qbox, dim3((nq + 255) / 256), dim3(256), 0, s, nq, (const CanvasDesc *)set->dcds.p, skip,
                        (double4 *)set->qbox.p);
     const SetArgs S = set_args(set);
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(t->nchunk, (int64_t)num_cus_of(ctx->device) * 8));
@@ -1381,9 +1384,62 @@ int spade_batch_join_count(spade_ctx *ctx, const spade_canvas *set, const spade_
         (uint64_t)(uintptr_t)set->qbox.p, (uint64_t)(uintptr_t)(set->layered ? set->pid.p : nullptr),
         (uint64_t)set->nc, (uint64_t)M, (uint64_t)(uintptr_t)t->x.p, (uint64_t)(uintptr_t)t->y.p,
         (uint64_t)(uintptr_t)t->chunk_bb.p, (uint64_t)t->nfin, (uint64_t)t->nchunk, (uint64_t)(uintptr_t)out_counts};
+    // A canvas over at least a quarter of the table's box whose polygons fit
+    // the count probe's LDS histogram is counted by that probe over all the
+    // table's points (a canvas of a tessellation over the extent, say): it
+    // streams them several times faster than the per-chunk probe looks them
+    // up, which outweighs the per-chunk probe's one read of a chunk for all
+    // the canvases that meet it.  Not for a layered set, whose counts go
+    // through its polygon-id map.
+    std::vector<int> routed;
+    std::vector<uint8_t> hskip;   // read by an asynchronous copy: lives to the final synchronisation
+    if (!set->layered) {
+        const double tw = t->sx > 0 ? t->G / t->sx : 0.0, th = t->sy > 0 ? t->G / t->sy : 0.0;
+        const double tx1 = t->X0 + tw, ty1 = t->Y0 + th;
+        for (int q = 0; q < set->nc && t->nfin > 0; ++q) {
+            const CanvasDesc &d = set->descs[(size_t)q];
+            if (d.empty || d.M <= 0 || d.M > HIST_MAX_BATCH) continue;
+            const double ox = std::min(d.bx1, tx1) - std::max(d.bx0, t->X0);
+            const double oy = std::min(d.by1, ty1) - std::max(d.by0, t->Y0);
+            if (ox > 0 && oy > 0 && ox * oy >= 0.25 * tw * th) routed.push_back(q);
+        }
+    }
     if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[2], st));
     hipError_t e;
-    if (!ctx->graphs) {
+    if (!routed.empty()) {
+        e = hipSuccess;
+        const uint8_t *skip = nullptr;
+        int64_t Mrest = 0;
+        if ((int)routed.size() < set->nc) {
+            hskip.assign((size_t)set->nc, 0);
+            for (int q : routed) hskip[(size_t)q] = 1;
+            for (int q = 0; q < set->nc; ++q)
+                if (!hskip[(size_t)q]) Mrest += set->descs[(size_t)q].M;
+            DevBuf &bs = ctx->scratch[S_MISC];
+            if (ensure(ctx, bs, (size_t)set->nc)) return SPADE_E_NOMEM;
+            SPADE_HIP(ctx, hipMemcpyAsync(bs.p, hskip.data(), (size_t)set->nc, hipMemcpyHostToDevice, st));
+            skip = (const uint8_t *)bs.p;
+        }
+        if (Mrest > 0) e = batch_count_launches(ctx, set, t, M, out_counts, st, skip);
+        const bool timing = ctx->timing;
+        ctx->timing = false;   // the batch call's events frame every launch
+        spade_points tp{};
+        tp.n = t->nfin;
+        tp.x = (const double *)t->x.p;
+        tp.y = (const double *)t->y.p;
+        for (int q : routed) {
+            if (e != hipSuccess) break;
+            const CanvasDesc &d = set->descs[(size_t)q];
+            spade_canvas one;
+            one.view = view_of(set, q);
+            const int rc2 = probe_count(ctx, &one, &tp, out_counts + d.poly_base);
+            if (rc2) {
+                ctx->timing = timing;
+                return rc2;
+            }
+        }
+        ctx->timing = timing;
+    } else if (!ctx->graphs) {
         e = batch_count_launches(ctx, set, t, M, out_counts, st);
     } else if (cv->bexec && cv->bkey == key) {
         ++ctx->graph_replays;

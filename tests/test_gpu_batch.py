@@ -118,6 +118,36 @@ def test_batch_join_count(ctx):
     t.close()
 
 
+@pytest.mark.parametrize("case", ["one_tess", "three_tess_and_star", "large_tess_and_small"])
+def test_batch_join_count_full_extent_canvases(ctx, case):
+    """Canvases over most of the table's box (counted over the whole table)
+    beside canvases probed chunk by chunk: every count equals the oracle's."""
+    x, y = gen.uniform_points(60_000, seed=15)
+    star = gen.star_polygon(300, 0.15, (0.4, 0.6), L=1.0, seed=5)
+    if case == "one_tess":
+        parts = [gen.voronoi_jitter(500, 4, 30, seed=6, L=1.0)]
+    elif case == "three_tess_and_star":
+        parts = [gen.voronoi_jitter(m, 4, 20, seed=7 + m, L=1.0) for m in (40, 200, 900)] + [star]
+    else:
+        # more polygons than the count probe's LDS histogram holds, beside a small tessellation
+        parts = [gen.voronoi_jitter(9000, 4, 8, seed=9, L=1.0), gen.voronoi_jitter(30, 4, 20, seed=10, L=1.0), star]
+    allp = parts[0]
+    for p_ in parts[1:]:
+        allp = gen.concat_polys(allp, p_)
+    qb = np.cumsum([0] + [p_["n_polys"] for p_ in parts]).astype(np.int64)
+    t = ctx.table(_dev(x), _dev(y))
+    b = ctx.batch(allp, qb)
+    for rep in range(2):
+        got = ctx.batch_join_count(b, t).cpu().numpy().astype(np.uint64)
+        want = oracle.join_count(x, y, allp)
+        assert np.array_equal(got, want), rep
+    for q, p_ in enumerate(parts):
+        if p_ is not star:
+            assert int(got[qb[q]:qb[q + 1]].sum()) == x.size
+    b.close()
+    t.close()
+
+
 def test_batch_select_capacity_and_retry(ctx, table_pts, stars):
     from paper_2203_14362_amd import SPADE_E_CAPACITY
     x, y = table_pts
