@@ -182,6 +182,35 @@ int spade_select(spade_ctx *ctx, const spade_points *pts, const spade_polys *pol
 int spade_select_disk(spade_ctx *ctx, const spade_points *pts, double cx, double cy, double r,
                       uint32_t *out_ids, int64_t cap, int64_t *n_out);
 
+/* Distance selection from lines (Sec. 4.2, the rounded rectangle drawn
+ * around each segment of a line; Sec. 5.2, "Distance-Based Queries"): ids of
+ * the points whose Euclidean distance to some segment of `lines` is at most r
+ * (closed), ascending.  Every ring of `lines` is an open polyline: segments
+ * join consecutive vertices, with no closing segment, and a one-vertex ring is
+ * a point (n_polys and poly_ring_off are ignored; ring_vtx_off, vx, vy as for
+ * a polygon set, device pointers).  Decided exactly on the FP64 inputs (see
+ * the segment predicate: exact whenever no product of coordinate differences
+ * overflows or underflows into subnormals).  r must be finite and >= 0;
+ * invalid ring offsets or a non-finite vertex are SPADE_E_INVALID; points
+ * with a non-finite coordinate are never selected.  out_ids [cap] device
+ * buffer; *n_out (host, may be NULL) receives the number of selected points;
+ * beyond cap the first cap ids are written and SPADE_E_CAPACITY is returned
+ * (two-step Map, Sec. 5.1).  The segments are binned into a grid over their
+ * box widened by r, which the context keeps in scratch memory;
+ * SPADE_E_TOO_LARGE when its cell lists would exceed 2^31 entries (r far
+ * larger than the spacing of the segments). */
+int spade_select_near_lines(spade_ctx *ctx, const spade_points *pts, const spade_polys *lines, double r,
+                            uint32_t *out_ids, int64_t cap, int64_t *n_out);
+
+/* Distance selection from one polygon (Sec. 4.2: the polygon drawn together
+ * with the rounded rectangles of its edges): ids of the points inside the
+ * polygon (decided as spade_select decides) or within closed distance r of
+ * one of its edges (rings closed), ascending, exactly.  `poly` must hold
+ * exactly one polygon (SPADE_E_INVALID otherwise); arguments, errors and the
+ * capacity protocol as spade_select_near_lines. */
+int spade_select_within_polygon(spade_ctx *ctx, const spade_points *pts, const spade_polys *poly, double r,
+                                uint32_t *out_ids, int64_t cap, int64_t *n_out);
+
 /* Disks (device pointers): centres (cx[j], cy[j]) and radii r[j] (type-2
  * distance join), or one radius r_all for every disk when r is NULL (type
  * 1).  Disk ids are 0-based positions (n < 2^31 - 1). */

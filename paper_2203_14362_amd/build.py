@@ -8,7 +8,8 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libspade.so")
-SOURCES = ["capi.hip", "raster.hip", "probe.hip", "batch.hip", "disk.hip", "layers.hip", "dist.hip", "host.hip", "jobs.hip"]
+SOURCES = ["capi.hip", "raster.hip", "probe.hip", "batch.hip", "disk.hip", "layers.hip", "dist.hip", "host.hip", "jobs.hip",
+           "buffer.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

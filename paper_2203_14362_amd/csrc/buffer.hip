@@ -1,0 +1,359 @@
+// Distance selection from lines and from a polygon: the rounded rectangles
+// of Sec. 4.2 (every position within distance r of a segment) drawn around
+// every segment of a set of polylines, or around every edge of a polygon
+// together with the polygon itself, and the distance selection of Sec. 5.2
+// over that shape.
+//
+// Instead of rasterising the rounded rectangles, the segments are binned
+// into a uniform grid over their box widened by r: a cell lists every
+// segment whose widened box meets it (count, scan, fill).  One pass over the
+// points then keeps, per 1024-point segment of the stream, one result bit
+// per point: for a polygon, the canvas of the polygon answers first (coarse
+// level in LDS, full canvas, exact records, as the selection probe does);
+// a point not yet kept that lies in the grid's box is tested exactly against
+// the segments its cell lists, until one is within r.  The ordered ids are
+// then written from the bits (the two-step Map of the selection).
+#include "common.h"
+#include "lookup.h"
+#include "segdist.h"
+
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+namespace spade {
+
+constexpr int BUF_GRID_MAX = 4096;            // cells per side
+constexpr int BUF_THREADS = 1024;
+constexpr int BUF_WORDS = EMIT_SEG / 64;      // bit words per point segment
+
+// Order-preserving 64-bit key of a double (minima by atomicMin).
+__device__ __forceinline__ unsigned long long buf_key(double v)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    return (b & 0x8000000000000000ull) ? ~b : (b | 0x8000000000000000ull);
+}
+
+static double buf_from_key(unsigned long long k)
+{
+    const unsigned long long b = (k & 0x8000000000000000ull) ? (k & 0x7fffffffffffffffull) : ~k;
+    double d;
+    std::memcpy(&d, &b, sizeof d);
+    return d;
+}
+
+// The grid: cells of side 1 / inv from (X0, Y0); (X1, Y1) closes the box.
+struct BufGrid {
+    double X0, Y0, X1, Y1, inv;
+    int gx, gy;
+};
+
+__device__ __forceinline__ int buf_cell(double v, double v0, double inv, int g)
+{
+    const double u = __dmul_rn(__dsub_rn(v, v0), inv);
+    return (int)fmin(fmax(floor(u), 0.0), (double)(g - 1));
+}
+
+// One segment slot per vertex: vertex v of its ring to the next one (the
+// ring's first vertex after the last when `closed`; a one-vertex ring is a
+// point).  Validates the offsets and the vertices on the way (err bit 1:
+// offsets, bit 2: a non-finite vertex) and reduces the segments' box into
+// bb (min x, -max x, min y, -max y as ordered keys).
+__global__ void k_buf_segs(int64_t R, const int64_t *rvo, int64_t V, const double *vx, const double *vy,
+                           int closed, Seg *segs, uint8_t *valid, unsigned long long *bb, unsigned *err)
+{
+    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t k = gid; k <= R; k += nth) {
+        const int64_t o = rvo[k];
+        if ((k == 0 && o != 0) || (k == R && o != V) || (k < R && rvo[k + 1] < o)) atomicOr(err, 1u);
+    }
+    unsigned long long k0 = ~0ull, k1 = ~0ull, k2 = ~0ull, k3 = ~0ull;
+    for (int64_t v = gid; v < V; v += nth) {
+        valid[v] = 0;
+        // ring of v: the last ring whose first vertex is <= v
+        int64_t lo = 0, hi = R - 1;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (rvo[mid] <= v) lo = mid; else hi = mid - 1;
+        }
+        const int64_t o = rvo[lo], e = rvo[lo + 1];
+        if (!(o >= 0 && o <= v && v < e && e <= V)) {
+            atomicOr(err, 1u);
+            continue;
+        }
+        int64_t w;
+        if (e - o == 1) w = v;
+        else if (v + 1 < e) w = v + 1;
+        else if (closed) w = o;
+        else continue;
+        const double ax = vx[v], ay = vy[v], bx = vx[w], by = vy[w];
+        if (!(isfinite(ax) && isfinite(ay) && isfinite(bx) && isfinite(by))) {
+            atomicOr(err, 2u);
+            continue;
+        }
+        segs[v] = Seg{ax, ay, bx, by};
+        valid[v] = 1;
+        k0 = min(k0, min(buf_key(ax), buf_key(bx))); k1 = min(k1, min(buf_key(-ax), buf_key(-bx)));
+        k2 = min(k2, min(buf_key(ay), buf_key(by))); k3 = min(k3, min(buf_key(-ay), buf_key(-by)));
+    }
+    for (int d = 32; d > 0; d >>= 1) {
+        k0 = min(k0, (unsigned long long)__shfl_xor((long long)k0, d, 64));
+        k1 = min(k1, (unsigned long long)__shfl_xor((long long)k1, d, 64));
+        k2 = min(k2, (unsigned long long)__shfl_xor((long long)k2, d, 64));
+        k3 = min(k3, (unsigned long long)__shfl_xor((long long)k3, d, 64));
+    }
+    if ((threadIdx.x & 63) == 0 && k0 != ~0ull) {
+        atomicMin(&bb[0], k0); atomicMin(&bb[1], k1); atomicMin(&bb[2], k2); atomicMin(&bb[3], k3);
+    }
+}
+
+// Cells met by each valid segment's box widened by pad: counted (FILL false,
+// with the number of list entries summed into *tot) or listed (FILL true, in
+// per-cell slots from off[] claimed with cursor[]).
+template <bool FILL>
+__global__ void k_buf_bin(int64_t V, const Seg *segs, const uint8_t *valid, BufGrid g, double pad, uint32_t *cnt,
+                          const uint32_t *off, uint32_t *list, unsigned long long *tot)
+{
+    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < V; v += nth) {
+        if (!valid[v]) continue;
+        const Seg s = segs[v];
+        const int x0 = buf_cell(fmin(s.ax, s.bx) - pad, g.X0, g.inv, g.gx);
+        const int x1 = buf_cell(fmax(s.ax, s.bx) + pad, g.X0, g.inv, g.gx);
+        const int y0 = buf_cell(fmin(s.ay, s.by) - pad, g.Y0, g.inv, g.gy);
+        const int y1 = buf_cell(fmax(s.ay, s.by) + pad, g.Y0, g.inv, g.gy);
+        if (!FILL) atomicAdd(tot, (unsigned long long)(x1 - x0 + 1) * (unsigned long long)(y1 - y0 + 1));
+        for (int cy = y0; cy <= y1; ++cy)
+            for (int cx = x0; cx <= x1; ++cx) {
+                const int64_t c = (int64_t)cy * g.gx + cx;
+                if (FILL) list[off[c] + atomicAdd(&cnt[c], 1u)] = (uint32_t)v;
+                else atomicAdd(&cnt[c], 1u);
+            }
+    }
+}
+
+// One result bit per point (layout of the ordered emit: word j of segment sg
+// holds points sg * EMIT_SEG + 64 j + lane) and the count per segment.
+template <bool POLY>
+__global__ __launch_bounds__(BUF_THREADS) void k_buf_bits(CanvasView cv, int64_t n, const double *X, const double *Y,
+                                                          BufGrid g, const Seg *segs, const uint32_t *off,
+                                                          const uint32_t *list, double r, double r2, int64_t nseg,
+                                                          unsigned long long *counts, unsigned long long *bits)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint16_t *coarse = (uint16_t *)smem;
+    if (POLY) {
+        load_coarse(cv, coarse, BUF_THREADS);
+        __syncthreads();
+    }
+    const int lane = threadIdx.x & 63;
+    const int64_t nwave = ((int64_t)gridDim.x * BUF_THREADS) >> 6;
+    for (int64_t sg = ((int64_t)blockIdx.x * BUF_THREADS + threadIdx.x) >> 6; sg < nseg; sg += nwave) {
+        unsigned long long total = 0, segw = 0;
+        for (int j = 0; j < BUF_WORDS; ++j) {
+            const int64_t i = sg * EMIT_SEG + 64 * j + lane;
+            const double x = i < n ? __builtin_nontemporal_load(X + i) : NAN;
+            const double y = i < n ? __builtin_nontemporal_load(Y + i) : NAN;
+            bool hit = false;
+            if (POLY) {
+                const uint32_t w = lookup(cv, coarse, x, y);
+                if (w != 0u && !(w & BFLAG)) {
+                    hit = true;
+                } else if (w & BFLAG) {
+                    uint32_t rec = w & ~BFLAG;
+                    while (true) {
+                        const Cand c = cv.cands[rec];
+                        if (cand_inside(cv, c, x, y)) { hit = true; break; }
+                        if (c.meta & CAND_LAST) break;
+                        ++rec;
+                    }
+                }
+            }
+            // NaN fails the box test
+            if (!hit && x >= g.X0 && x <= g.X1 && y >= g.Y0 && y <= g.Y1) {
+                const int64_t c = (int64_t)buf_cell(y, g.Y0, g.inv, g.gy) * g.gx + buf_cell(x, g.X0, g.inv, g.gx);
+                for (uint32_t k = off[c], e = off[c + 1]; k < e; ++k)
+                    if (seg_near(x, y, segs[list[k]], r, r2)) { hit = true; break; }
+            }
+            const unsigned long long word = __ballot(hit);
+            total += (unsigned long long)__popcll(word);
+            if (lane == j) segw = word;
+        }
+        if (lane < BUF_WORDS) bits[sg * BUF_WORDS + lane] = segw;
+        if (lane == 0) counts[sg] = total;
+    }
+}
+
+__global__ void k_buf_zero(unsigned long long *p) { *p = 0ull; }
+
+int buffer_select(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts, const spade_polys *geom, double r,
+                  bool closed, uint32_t *out_ids, int64_t cap, int64_t *n_out)
+{
+    hipStream_t st = ctx->stream;
+    if (n_out) *n_out = 0;
+    if (!(std::isfinite(r) && r >= 0.0)) return set_error(ctx, SPADE_E_INVALID, "the distance must be finite and >= 0");
+    if (cap < 0) return set_error(ctx, SPADE_E_INVALID, "negative capacity");
+    if (cap > 0 && !out_ids) return set_error(ctx, SPADE_E_INVALID, "out_ids is NULL");
+    if (!geom) return set_error(ctx, SPADE_E_INVALID, "geometry is NULL");
+    const int64_t R = geom->n_rings;
+    if (R < 0) return set_error(ctx, SPADE_E_INVALID, "negative ring count");
+    if (R > 0 && (!geom->ring_vtx_off || !geom->vx || !geom->vy))
+        return set_error(ctx, SPADE_E_INVALID, "geometry array is NULL");
+    // vertex count: given, else read back
+    int64_t V = 0;
+    if (R > 0) {
+        if (geom->n_vertices > 0) {
+            V = geom->n_vertices;
+        } else {
+            int64_t *h = (int64_t *)ensure_pinned(ctx, 64);
+            if (!h) return set_error(ctx, SPADE_E_NOMEM, "pinned staging allocation failed");
+            SPADE_HIP(ctx, hipMemcpyAsync(h, geom->ring_vtx_off + R, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+            SPADE_HIP(ctx, hipStreamSynchronize(st));
+            V = h[0];
+        }
+        if (V < 0 || V >= (int64_t)0xffffffffLL) return set_error(ctx, SPADE_E_INVALID, "bad vertex count");
+    }
+    const int64_t n = pts->n;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || cus <= 0)
+        cus = 256;
+
+    // segments, their box, validation
+    DevBuf &bs = ctx->scratch[S_BUF_SEGS], &bg = ctx->scratch[S_BUF_GRID];
+    if (ensure(ctx, bs, sizeof(Seg) * (size_t)std::max<int64_t>(V, 1) + (size_t)V + 16) || ensure(ctx, bg, 256))
+        return SPADE_E_NOMEM;
+    Seg *segs = (Seg *)bs.p;
+    uint8_t *valid = (uint8_t *)(segs + std::max<int64_t>(V, 1));
+    unsigned long long *bb = (unsigned long long *)bg.p;
+    unsigned *err = (unsigned *)(bb + 4);
+    SPADE_HIP(ctx, hipMemsetAsync(bb, 0xff, 4 * sizeof(unsigned long long), st));
+    SPADE_HIP(ctx, hipMemsetAsync(err, 0, sizeof(unsigned), st));
+    if (R > 0) {
+        const int sgrid = (int)std::max<int64_t>(1, std::min<int64_t>((std::max(V, R + 1) + 255) / 256, (int64_t)cus * 8));
+        hipLaunchKernelGGL(k_buf_segs, dim3(sgrid), dim3(256), 0, st, R, geom->ring_vtx_off, V, geom->vx, geom->vy,
+                           closed ? 1 : 0, segs, valid, bb, err);
+        SPADE_HIP(ctx, hipGetLastError());
+    }
+    unsigned long long *h = (unsigned long long *)ensure_pinned(ctx, 64);
+    if (!h) return set_error(ctx, SPADE_E_NOMEM, "pinned staging allocation failed");
+    SPADE_HIP(ctx, hipMemcpyAsync(h, bb, 5 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    SPADE_HIP(ctx, hipStreamSynchronize(st));
+    const unsigned ef = (unsigned)(h[4] & 0xffffffffu);
+    if (ef & 1u) return set_error(ctx, SPADE_E_INVALID, "ring offsets are not a valid CSR array");
+    if (ef & 2u) return set_error(ctx, SPADE_E_INVALID, "a vertex coordinate is not finite");
+    const bool any = h[0] != ~0ull;
+    if (n == 0) return SPADE_OK;
+
+    // the grid over the segments' box widened by r (and a relative margin,
+    // so that rounding never drops a position within r)
+    BufGrid grid{0.0, 0.0, -1.0, -1.0, 1.0, 1, 1};   // empty box: no point is tested
+    double pad = 0.0;
+    uint32_t *off = nullptr, *list = nullptr;
+    if (any) {
+        const double x0 = buf_from_key(h[0]), x1 = -buf_from_key(h[1]);
+        const double y0 = buf_from_key(h[2]), y1 = -buf_from_key(h[3]);
+        const double mag = std::fabs(x0) + std::fabs(x1) + std::fabs(y0) + std::fabs(y1);
+        pad = r * (1.0 + 0x1p-40) + mag * 0x1p-40 + 1e-300;
+        const double X0 = x0 - pad, X1 = x1 + pad, Y0 = y0 - pad, Y1 = y1 + pad;
+        const double w = X1 - X0, hgt = Y1 - Y0;
+        // cells about as wide as r, at least one per two segments' share of
+        // the box, at most BUF_GRID_MAX per side
+        double cell = std::max(r, std::sqrt(w * hgt / (2.0 * (double)std::max<int64_t>(V, 1))));
+        cell = std::max(cell, std::max(w, hgt) / BUF_GRID_MAX);
+        if (!(cell > 1e-290)) cell = 1.0;
+        grid.X0 = X0; grid.Y0 = Y0; grid.X1 = X1; grid.Y1 = Y1;
+        grid.inv = 1.0 / cell;
+        grid.gx = (int)std::min<double>(BUF_GRID_MAX, std::max(1.0, std::ceil(w * grid.inv)));
+        grid.gy = (int)std::min<double>(BUF_GRID_MAX, std::max(1.0, std::ceil(hgt * grid.inv)));
+        const int64_t G = (int64_t)grid.gx * grid.gy;
+        DevBuf &bt = ctx->scratch[S_BUF_TMP];
+        if (ensure(ctx, bg, 256 + sizeof(uint32_t) * 3 * (size_t)(G + 1))) return SPADE_E_NOMEM;
+        bb = (unsigned long long *)bg.p;
+        uint32_t *cnt = (uint32_t *)((unsigned char *)bg.p + 256);
+        off = cnt + (G + 1);
+        uint32_t *cursor = off + (G + 1);
+        unsigned long long *tot = bb + 5;
+        SPADE_HIP(ctx, hipMemsetAsync(cnt, 0, sizeof(uint32_t) * (size_t)(G + 1), st));
+        SPADE_HIP(ctx, hipMemsetAsync(tot, 0, sizeof(unsigned long long), st));
+        const int bgrid = (int)std::max<int64_t>(1, std::min<int64_t>((V + 255) / 256, (int64_t)cus * 8));
+        hipLaunchKernelGGL(k_buf_bin<false>, dim3(bgrid), dim3(256), 0, st, V, (const Seg *)segs,
+                           (const uint8_t *)valid, grid, pad, cnt, (const uint32_t *)nullptr, (uint32_t *)nullptr,
+                           tot);
+        SPADE_HIP(ctx, hipGetLastError());
+        // the cell lists are indexed with 32 bits
+        SPADE_HIP(ctx, hipMemcpyAsync(h, tot, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+        SPADE_HIP(ctx, hipStreamSynchronize(st));
+        if (h[0] >= ((unsigned long long)1 << 31))
+            return set_error(ctx, SPADE_E_TOO_LARGE, "too many (segment, cell) entries: the distance is too large "
+                                                     "for the segments' spread");
+        size_t tb = 0;
+        SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(nullptr, tb, cnt, off, (int)(G + 1), st));
+        if (ensure(ctx, bt, std::max<size_t>(tb, 1))) return SPADE_E_NOMEM;
+        SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(bt.p, tb, cnt, off, (int)(G + 1), st));
+        uint32_t *hl = (uint32_t *)ensure_pinned(ctx, 64);
+        if (!hl) return set_error(ctx, SPADE_E_NOMEM, "pinned staging allocation failed");
+        SPADE_HIP(ctx, hipMemcpyAsync(hl, off + G, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        SPADE_HIP(ctx, hipStreamSynchronize(st));
+        const uint64_t total = hl[0];
+        DevBuf &bl = ctx->scratch[S_BUF_LIST];
+        if (ensure(ctx, bl, sizeof(uint32_t) * (size_t)std::max<uint64_t>(total, 1))) return SPADE_E_NOMEM;
+        list = (uint32_t *)bl.p;
+        SPADE_HIP(ctx, hipMemsetAsync(cursor, 0, sizeof(uint32_t) * (size_t)(G + 1), st));
+        hipLaunchKernelGGL(k_buf_bin<true>, dim3(bgrid), dim3(256), 0, st, V, (const Seg *)segs,
+                           (const uint8_t *)valid, grid, pad, cursor, (const uint32_t *)off, list,
+                           (unsigned long long *)nullptr);
+        SPADE_HIP(ctx, hipGetLastError());
+    }
+
+    // result bits and per-segment counts, then the ordered write pass
+    const int64_t nseg = (n + EMIT_SEG - 1) / EMIT_SEG;
+    DevBuf &lb = ctx->scratch[S_LOOKBACK], &bbits = ctx->scratch[S_BITS];
+    if (ensure(ctx, lb, sizeof(unsigned long long) * 2 * (size_t)(nseg + 1)) ||
+        ensure(ctx, bbits, sizeof(unsigned long long) * BUF_WORDS * (size_t)nseg))
+        return SPADE_E_NOMEM;
+    unsigned long long *counts = (unsigned long long *)lb.p;
+    unsigned long long *offs = counts + (nseg + 1);
+    unsigned long long *bits = (unsigned long long *)bbits.p;
+    const double r2 = r * r;
+    const int64_t wpb = BUF_THREADS / 64;
+    if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[2], st));
+    if (cv) {
+        const CanvasView &v = cv->view;
+        const size_t lds = ((size_t)v.Wc * v.Hc * (v.cbyte ? 1 : 2) + 15) & ~(size_t)15;
+        if (lds + 2048 > 160 * 1024) return set_error(ctx, SPADE_E_HIP, "internal: coarse level exceeds the LDS");
+        const int per_cu = std::max<int>(1, (int)((160 * 1024) / (lds + 2048)));
+        const int grid_b = (int)std::max<int64_t>(1, std::min<int64_t>((nseg + wpb - 1) / wpb, (int64_t)cus * std::min(per_cu, 2)));
+        SPADE_HIP(ctx, hipFuncSetAttribute((const void *)k_buf_bits<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        hipLaunchKernelGGL(k_buf_bits<true>, dim3(grid_b), dim3(BUF_THREADS), lds, st, v, n, pts->x, pts->y, grid,
+                           (const Seg *)segs, (const uint32_t *)off, (const uint32_t *)list, r, r2, nseg, counts, bits);
+    } else {
+        const int grid_b = (int)std::max<int64_t>(1, std::min<int64_t>((nseg + wpb - 1) / wpb, (int64_t)cus * 2));
+        hipLaunchKernelGGL(k_buf_bits<false>, dim3(grid_b), dim3(BUF_THREADS), 0, st, CanvasView{}, n, pts->x, pts->y,
+                           grid, (const Seg *)segs, (const uint32_t *)off, (const uint32_t *)list, r, r2, nseg,
+                           counts, bits);
+    }
+    hipLaunchKernelGGL(k_buf_zero, dim3(1), dim3(1), 0, st, counts + nseg);
+    SPADE_HIP(ctx, hipGetLastError());
+    DevBuf &bt = ctx->scratch[S_BUF_TMP];
+    size_t tb = 0;
+    SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(nullptr, tb, counts, offs, (int)(nseg + 1), st));
+    if (ensure(ctx, bt, std::max<size_t>(tb, 1))) return SPADE_E_NOMEM;
+    SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(bt.p, tb, counts, offs, (int)(nseg + 1), st));
+    if (cap > 0) {
+        const int eg = (int)std::max<int64_t>(1, std::min<int64_t>((nseg + 3) / 4, (int64_t)cus * 16));
+        hipLaunchKernelGGL(k_emit_bits, dim3(eg), dim3(256), 0, st, nseg, (const unsigned long long *)offs,
+                           (const unsigned long long *)bits, out_ids, (uint32_t *)nullptr, cap);
+        SPADE_HIP(ctx, hipGetLastError());
+    }
+    if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[3], st));
+    SPADE_HIP(ctx, hipMemcpyAsync(h, offs + nseg, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    SPADE_HIP(ctx, hipStreamSynchronize(st));
+    if (n_out) *n_out = (int64_t)h[0];
+    if ((int64_t)h[0] > cap) return set_error(ctx, SPADE_E_CAPACITY, "output capacity too small");
+    return SPADE_OK;
+}
+
+}  // namespace spade

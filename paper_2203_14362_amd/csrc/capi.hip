@@ -606,6 +606,34 @@ int spade_join_pairs(spade_ctx *ctx, const spade_points *pts, const spade_polys 
     });
 }
 
+int spade_select_near_lines(spade_ctx *ctx, const spade_points *pts, const spade_polys *lines, double r,
+                            uint32_t *out_ids, int64_t cap, int64_t *n_out)
+{
+    if (!ctx) return SPADE_E_INVALID;
+    SPADE_CTX_LOCK(ctx);
+    if (n_out) *n_out = 0;
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if ((rc = check_points(ctx, pts))) return rc;
+    ctx->timed_raster = false;
+    return spade::buffer_select(ctx, nullptr, pts, lines, r, false, out_ids, cap, n_out);
+}
+
+int spade_select_within_polygon(spade_ctx *ctx, const spade_points *pts, const spade_polys *poly, double r,
+                                uint32_t *out_ids, int64_t cap, int64_t *n_out)
+{
+    if (!ctx) return SPADE_E_INVALID;
+    SPADE_CTX_LOCK(ctx);
+    if (n_out) *n_out = 0;
+    if (poly && poly->n_polys != 1) return set_error(ctx, SPADE_E_INVALID, "the distance selection takes exactly one polygon");
+    if (!(std::isfinite(r) && r >= 0.0)) return set_error(ctx, SPADE_E_INVALID, "the distance must be finite and >= 0");
+    int rc = check_points(ctx, pts);
+    if (rc) return rc;
+    return plain_query(ctx, poly, [&](spade_canvas *cv) {
+        return spade::buffer_select(ctx, cv, pts, poly, r, true, out_ids, cap, n_out);
+    });
+}
+
 int spade_stream_read(spade_ctx *ctx, const spade_points *pts, int shape, double *out_sum)
 {
     if (!ctx) return SPADE_E_INVALID;

@@ -138,7 +138,7 @@ struct spade_ctx {
     std::string err;
     int32_t canvas_w = 0, canvas_h = 0;     // 0 = automatic
     double ppv = 256.0;                     // automatic sizing: pixels per vertex
-    spade::DevBuf scratch[18];              // reusable scratch slots (spade::S_NSLOTS)
+    spade::DevBuf scratch[22];              // reusable scratch slots (spade::S_NSLOTS)
     void *pinned = nullptr;                 // small pinned host staging area
     void *pend = nullptr;                   // pinned counters and flags of a deferred build
     spade_canvas *plain = nullptr;          // canvas reused by the plain query calls
@@ -171,10 +171,18 @@ enum Slot {
     S_BLOCKRED = 0, S_RINGPOLY, S_NROWS, S_ROWOFF, S_KEYS, S_KEYS2, S_VALS, S_VALS2,
     S_ENTC, S_ENTF, S_CUBTMP, S_ROWCNT, S_NEXTP, S_PROBE, S_LOOKBACK, S_MISC, S_ROWSCAN,
     S_BITS,     // the ordered emit's per-point result bits (used by nothing else)
+    S_BUF_SEGS, S_BUF_GRID, S_BUF_LIST, S_BUF_TMP,   // distance selection from lines / a polygon
     S_NSLOTS
 };
 
-static_assert(S_NSLOTS == 18, "scratch slot count of spade_ctx");
+static_assert(S_NSLOTS == 22, "scratch slot count of spade_ctx");
+
+// Points per segment of the ordered emit (bits: EMIT_SEG / 64 words each).
+constexpr int EMIT_SEG = 1024;
+// Write pass of an ordered selection from per-point result bits: segment sg
+// of EMIT_SEG points writes its ids from offs[sg] on (below cap).
+__global__ void k_emit_bits(int64_t nseg, const unsigned long long *offs, const unsigned long long *bits,
+                            uint32_t *out_pt, uint32_t *out_poly, int64_t cap);
 
 int set_error(spade_ctx *ctx, int code, const std::string &msg);
 int hip_fail(spade_ctx *ctx, hipError_t e, const char *what);
@@ -209,6 +217,12 @@ struct HostSet;
 int layer_index(spade_ctx *ctx, const spade_polys *polys, int res, int32_t *d_layer, int32_t *n_layers,
                 std::vector<int32_t> *host_layer, HostSet *hs_out);
 int layered_build(spade_ctx *ctx, const spade_polys *polys, int res, spade_canvas *cv, int32_t *n_layers);
+
+// Distance selection: the points within closed distance r of a segment of
+// `geom`'s rings (open polylines, or closed rings when `closed`), or kept by
+// the one-polygon canvas `cv` when it is not NULL; ascending ids.
+int buffer_select(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts, const spade_polys *geom, double r,
+                  bool closed, uint32_t *out_ids, int64_t cap, int64_t *n_out);
 
 // LDS bytes the count probe leaves for the coarse canvas, given the polygon
 // count (its histogram shares the LDS).

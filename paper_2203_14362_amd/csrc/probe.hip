@@ -36,7 +36,6 @@ constexpr int CNT_UNROLL = 5;             // points per thread per iteration (6 
 constexpr int QCAP = 64;                  // boundary queue entries per wavefront
 constexpr int HIST_MAX = 8192;            // polygons counted in LDS
 constexpr int EMIT_THREADS = 1024;
-constexpr int EMIT_SEG = 1024;            // points per wavefront segment
 constexpr int EMIT_GROUP = 8;             // points per lane in flight (count pass)
 constexpr int EMIT_WGROUP = 4;            // points per lane in flight (write pass)
 constexpr size_t LDS_TOTAL = 160 * 1024;

@@ -42,6 +42,7 @@ EXPORTS = [
     "spade_layered_build", "spade_distance_join_pairs", "spade_distance_join_count", "spade_knn_select",
     "spade_host_table_create", "spade_host_table_destroy", "spade_host_table_info", "spade_host_join_count",
     "spade_host_select", "spade_batch_submit", "spade_batch_wait", "spade_job_query", "spade_job_free",
+    "spade_select_near_lines", "spade_select_within_polygon",
 ]
 
 JOB_SELECT, JOB_COUNT, JOB_PAIRS = 1, 2, 3
@@ -105,6 +106,8 @@ def load_library():
     lib.spade_select.argtypes = [vp, P(_Points), P(_Polys), vp, i64, P(i64)]
     lib.spade_select_disk.argtypes = [vp, P(_Points), ctypes.c_double, ctypes.c_double, ctypes.c_double, vp, i64,
                                       P(i64)]
+    lib.spade_select_near_lines.argtypes = [vp, P(_Points), P(_Polys), ctypes.c_double, vp, i64, P(i64)]
+    lib.spade_select_within_polygon.argtypes = [vp, P(_Points), P(_Polys), ctypes.c_double, vp, i64, P(i64)]
     lib.spade_join_count.argtypes = [vp, P(_Points), P(_Polys), vp]
     lib.spade_join_pairs.argtypes = [vp, P(_Points), P(_Polys), vp, vp, i64, P(i64)]
     lib.spade_canvas_build.argtypes = [vp, P(_Polys), P(vp)]
@@ -720,6 +723,34 @@ class Context:
                 continue
             self._check(rc)
             return _ids(_compact(pt, int(nout.value)), P.n)
+
+    def _select_dist(self, fn, x, y, polys, r, cap):
+        P = _points(x, y)
+        dp = self.polys(polys)
+        if cap is None:
+            cap = max(P.n, 1)
+        while True:
+            pt = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device)
+            nout = ctypes.c_int64()
+            self._sync_stream()
+            rc = fn(self.handle, ctypes.byref(P), ctypes.byref(dp.cstruct()), float(r),
+                    ctypes.c_void_p(pt.data_ptr()), cap, ctypes.byref(nout))
+            if rc == SPADE_E_CAPACITY:
+                cap = int(nout.value)
+                continue
+            self._check(rc)
+            return _ids(_compact(pt, int(nout.value)), P.n)
+
+    def select_near_lines(self, x, y, lines, r, cap=None):
+        """Ascending ids of the points within closed distance r of a segment
+        of `lines` (every ring of the CSR set an open polyline), decided
+        exactly."""
+        return self._select_dist(self.lib.spade_select_near_lines, x, y, lines, r, cap)
+
+    def select_within(self, x, y, poly, r, cap=None):
+        """Ascending ids of the points inside the one polygon or within
+        closed distance r of one of its edges, decided exactly."""
+        return self._select_dist(self.lib.spade_select_within_polygon, x, y, poly, r, cap)
 
     def _disks(self, cx, cy, r):
         cx = _dev_f64(cx, self.device)

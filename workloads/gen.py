@@ -224,6 +224,26 @@ def star_polygon(V: int, area_frac: float, centre, L: float = EXTENT_M, seed: in
     return polys_from_rings([[ring]])
 
 
+def road_lines(n_lines: int, n_vertices: int, step: float, seed: int = 7, L: float = EXTENT_M,
+               turn: float = 0.35, data_seed: int = 2):
+    """Road-like polylines for distance selections: each starts at a point of
+    the taxi-like mixture of ``data_seed`` and walks ``n_vertices - 1`` steps
+    of length ~ U(0.5, 1.5) ``step`` with a heading that turns by
+    N(0, ``turn``) radians per step, clipped to the extent.  Returned as a
+    CSR set with one ring (an open polyline) per line."""
+    rng = rng_for(seed, 7)
+    sx, sy = _mixture_chunk(mixture_params(data_seed, L), n_lines, rng)
+    rings = []
+    for k in range(n_lines):
+        h = rng.uniform(0, 2 * math.pi)
+        hs = h + np.cumsum(rng.normal(0.0, turn, size=n_vertices - 1))
+        st = step * rng.uniform(0.5, 1.5, size=n_vertices - 1)
+        xs = np.concatenate([[sx[k]], sx[k] + np.cumsum(st * np.cos(hs))])
+        ys = np.concatenate([[sy[k]], sy[k] + np.cumsum(st * np.sin(hs))])
+        rings.append([np.stack([np.clip(xs, 0.0, L), np.clip(ys, 0.0, L)], axis=1)])
+    return polys_from_rings(rings)
+
+
 def query_stars(nq: int, vmin: int, vmax: int, seed: int = 6, L: float = EXTENT_M,
                 area=(1e-4, 1e-2), data_seed: int = 2, noise: float = 0.3):
     """A batch of nq star-shaped selection polygons (one per query).
