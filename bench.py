@@ -414,6 +414,41 @@ def leg_next(ctx, dx, dy, N):
         got = ctx.knn(dx, dy, px, py, 1000).cpu().numpy().astype(np.int64)
         ok &= bool(np.array_equal(got, disk.knn(dx.cpu().numpy(), dy.cpu().numpy(), px, py, 1000)))
     out["knn"] = {"k": 1000, "ms_per_query": round(float(np.mean(kn)), 3), "gpu_matches_oracle": ok}
+    # distance selections from lines (rounded rectangles around 23,800 road
+    # segments, 50 m) and from a polygon (a 10,000-vertex star and its 100 m
+    # edge buffers)
+    from oracle import buffer as obuf
+    roads = gen.road_lines(200, 120, 150.0, seed=79, L=L)
+    star = gen.star_polygon(10_000, 0.05, (L * 0.4, L * 0.6), L=L, seed=80)
+    ctx.set_timing(True)
+    for name, fn, geom, r, ofn in (("near_lines", ctx.select_near_lines, roads, 50.0, obuf.select_near_lines),
+                                   ("within_polygon", ctx.select_within, star, 100.0, obuf.select_within_polygon)):
+        res = {}
+        tb, pb = [], []
+        for i in range(4):
+            t0 = time.perf_counter()
+            res["ids"] = fn(dx, dy, geom, r)
+            torch.cuda.synchronize()
+            if i:
+                tb.append((time.perf_counter() - t0) * 1e3)
+                pb.append(ctx.last_timing()[1])
+        ids = res["ids"].cpu().numpy().astype(np.int64)
+        want = ofn(xs, ys, geom, r)
+        ok = bool(np.array_equal(ids[ids < 200_000], want))
+        probe_ms = float(np.median(pb))
+        nid = int(ids.size)
+        alg = 16.0 * N + 4.0 * nid + 2 * N / 8.0
+        out[name] = {"segments": int(geom["ring_vtx_off"][-1] - (geom["n_polys"] if name == "near_lines" else 0)),
+                     "distance_m": r, "ids": nid, "ms_per_call": round(float(np.median(tb)), 3),
+                     "probe_ms": round(probe_ms, 3), "points_per_s": round(N / (float(np.median(tb)) / 1e3), 1),
+                     "oracle_sample_200k_points": ok,
+                     "roofline": {"bound": "hbm", "achieved": round(alg / (probe_ms / 1e3) / 1e9, 1), "peak": 8000.0,
+                                  "unit": "GB/s", "frac": round(alg / (probe_ms / 1e3) / 8e12, 4), "traffic": None,
+                                  "kernel": "k_buf_bits + k_emit_bits",
+                                  "algorithmic_bytes_per_launch": int(alg),
+                                  "bytes_rule": "16 B per point + 4 B per id + 1 result bit per point written and read"}}
+        log("leg next: %s %.3f ms per call (probe %.3f ms), %d ids, oracle sample %s" %
+            (name, float(np.median(tb)), probe_ms, nid, ok))
     return out
 
 

@@ -44,9 +44,10 @@ static double buf_from_key(unsigned long long k)
     return d;
 }
 
-// The grid: cells of side 1 / inv from (X0, Y0); (X1, Y1) closes the box.
+// The grid: cells of side `cell` (1 / inv) from (X0, Y0); (X1, Y1) closes
+// the box.
 struct BufGrid {
-    double X0, Y0, X1, Y1, inv;
+    double X0, Y0, X1, Y1, inv, cell;
     int gx, gy;
 };
 
@@ -60,9 +61,11 @@ __device__ __forceinline__ int buf_cell(double v, double v0, double inv, int g)
 // ring's first vertex after the last when `closed`; a one-vertex ring is a
 // point).  Validates the offsets and the vertices on the way (err bit 1:
 // offsets, bit 2: a non-finite vertex) and reduces the segments' box into
-// bb (min x, -max x, min y, -max y as ordered keys).
+// bb (min x, -max x, min y, -max y as ordered keys); sums the segments'
+// lengths (an FP64 estimate, only for the grid's cell size) into *len.
 __global__ void k_buf_segs(int64_t R, const int64_t *rvo, int64_t V, const double *vx, const double *vy,
-                           int closed, Seg *segs, uint8_t *valid, unsigned long long *bb, unsigned *err)
+                           int closed, Seg *segs, uint8_t *valid, unsigned long long *bb, unsigned *err,
+                           double *len)
 {
     const int64_t nth = (int64_t)gridDim.x * blockDim.x;
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -71,6 +74,7 @@ __global__ void k_buf_segs(int64_t R, const int64_t *rvo, int64_t V, const doubl
         if ((k == 0 && o != 0) || (k == R && o != V) || (k < R && rvo[k + 1] < o)) atomicOr(err, 1u);
     }
     unsigned long long k0 = ~0ull, k1 = ~0ull, k2 = ~0ull, k3 = ~0ull;
+    double lsum = 0.0;
     for (int64_t v = gid; v < V; v += nth) {
         valid[v] = 0;
         // ring of v: the last ring whose first vertex is <= v
@@ -96,6 +100,7 @@ __global__ void k_buf_segs(int64_t R, const int64_t *rvo, int64_t V, const doubl
         }
         segs[v] = Seg{ax, ay, bx, by};
         valid[v] = 1;
+        lsum += hypot(bx - ax, by - ay);
         k0 = min(k0, min(buf_key(ax), buf_key(bx))); k1 = min(k1, min(buf_key(-ax), buf_key(-bx)));
         k2 = min(k2, min(buf_key(ay), buf_key(by))); k3 = min(k3, min(buf_key(-ay), buf_key(-by)));
     }
@@ -105,14 +110,20 @@ __global__ void k_buf_segs(int64_t R, const int64_t *rvo, int64_t V, const doubl
         k2 = min(k2, (unsigned long long)__shfl_xor((long long)k2, d, 64));
         k3 = min(k3, (unsigned long long)__shfl_xor((long long)k3, d, 64));
     }
+    for (int d = 32; d > 0; d >>= 1) lsum += __shfl_xor(lsum, d, 64);
     if ((threadIdx.x & 63) == 0 && k0 != ~0ull) {
         atomicMin(&bb[0], k0); atomicMin(&bb[1], k1); atomicMin(&bb[2], k2); atomicMin(&bb[3], k3);
+        atomicAdd(len, lsum);
     }
 }
 
-// Cells met by each valid segment's box widened by pad: counted (FILL false,
-// with the number of list entries summed into *tot) or listed (FILL true, in
-// per-cell slots from off[] claimed with cursor[]).
+// Cells that may hold a point within r of each valid segment: the cells of
+// its box widened by pad whose centre lies within r + half the cell diagonal
+// of the segment (FP64 distance, with a relative margin of 1e-9 and the
+// absolute part of pad, far above its rounding and that of the point-to-cell
+// mapping), counted (FILL false, with the number of list entries summed into
+// *tot) or listed (FILL true, in per-cell slots from off[] claimed with
+// cursor[]).
 template <bool FILL>
 __global__ void k_buf_bin(int64_t V, const Seg *segs, const uint8_t *valid, BufGrid g, double pad, uint32_t *cnt,
                           const uint32_t *off, uint32_t *list, unsigned long long *tot)
@@ -125,13 +136,23 @@ __global__ void k_buf_bin(int64_t V, const Seg *segs, const uint8_t *valid, BufG
         const int x1 = buf_cell(fmax(s.ax, s.bx) + pad, g.X0, g.inv, g.gx);
         const int y0 = buf_cell(fmin(s.ay, s.by) - pad, g.Y0, g.inv, g.gy);
         const int y1 = buf_cell(fmax(s.ay, s.by) + pad, g.Y0, g.inv, g.gy);
-        if (!FILL) atomicAdd(tot, (unsigned long long)(x1 - x0 + 1) * (unsigned long long)(y1 - y0 + 1));
+        const double ex = s.bx - s.ax, ey = s.by - s.ay, l2 = ex * ex + ey * ey;
+        const double reach = (pad + 0.7071067811865476 * g.cell) * (1.0 + 1e-9);
+        const double reach2 = reach * reach;
+        unsigned long long nlisted = 0;
         for (int cy = y0; cy <= y1; ++cy)
             for (int cx = x0; cx <= x1; ++cx) {
+                const double px = g.X0 + (cx + 0.5) * g.cell, py = g.Y0 + (cy + 0.5) * g.cell;
+                double t = l2 > 0.0 ? ((px - s.ax) * ex + (py - s.ay) * ey) / l2 : 0.0;
+                t = fmin(fmax(t, 0.0), 1.0);
+                const double dx = px - (s.ax + t * ex), dy = py - (s.ay + t * ey);
+                if (dx * dx + dy * dy > reach2) continue;
                 const int64_t c = (int64_t)cy * g.gx + cx;
                 if (FILL) list[off[c] + atomicAdd(&cnt[c], 1u)] = (uint32_t)v;
                 else atomicAdd(&cnt[c], 1u);
+                ++nlisted;
             }
+        if (!FILL) atomicAdd(tot, nlisted);
     }
 }
 
@@ -140,8 +161,9 @@ __global__ void k_buf_bin(int64_t V, const Seg *segs, const uint8_t *valid, BufG
 template <bool POLY>
 __global__ __launch_bounds__(BUF_THREADS) void k_buf_bits(CanvasView cv, int64_t n, const double *X, const double *Y,
                                                           BufGrid g, const Seg *segs, const uint32_t *off,
-                                                          const uint32_t *list, double r, double r2, int64_t nseg,
-                                                          unsigned long long *counts, unsigned long long *bits)
+                                                          const uint32_t *list, double r, double r2, double pad,
+                                                          int64_t nseg, unsigned long long *counts,
+                                                          unsigned long long *bits)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     uint16_t *coarse = (uint16_t *)smem;
@@ -175,8 +197,14 @@ __global__ __launch_bounds__(BUF_THREADS) void k_buf_bits(CanvasView cv, int64_t
             // NaN fails the box test
             if (!hit && x >= g.X0 && x <= g.X1 && y >= g.Y0 && y <= g.Y1) {
                 const int64_t c = (int64_t)buf_cell(y, g.Y0, g.inv, g.gy) * g.gx + buf_cell(x, g.X0, g.inv, g.gx);
-                for (uint32_t k = off[c], e = off[c + 1]; k < e; ++k)
-                    if (seg_near(x, y, segs[list[k]], r, r2)) { hit = true; break; }
+                for (uint32_t k = off[c], e = off[c + 1]; k < e; ++k) {
+                    const Seg s = segs[list[k]];
+                    // outside the segment's box widened by pad: farther than r
+                    if (x < fmin(s.ax, s.bx) - pad || x > fmax(s.ax, s.bx) + pad ||
+                        y < fmin(s.ay, s.by) - pad || y > fmax(s.ay, s.by) + pad)
+                        continue;
+                    if (seg_near(x, y, s, r, r2)) { hit = true; break; }
+                }
             }
             const unsigned long long word = __ballot(hit);
             total += (unsigned long long)__popcll(word);
@@ -229,27 +257,31 @@ int buffer_select(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pt
     uint8_t *valid = (uint8_t *)(segs + std::max<int64_t>(V, 1));
     unsigned long long *bb = (unsigned long long *)bg.p;
     unsigned *err = (unsigned *)(bb + 4);
+    double *dlen = (double *)(bb + 6);
     SPADE_HIP(ctx, hipMemsetAsync(bb, 0xff, 4 * sizeof(unsigned long long), st));
     SPADE_HIP(ctx, hipMemsetAsync(err, 0, sizeof(unsigned), st));
+    SPADE_HIP(ctx, hipMemsetAsync(dlen, 0, sizeof(double), st));
     if (R > 0) {
         const int sgrid = (int)std::max<int64_t>(1, std::min<int64_t>((std::max(V, R + 1) + 255) / 256, (int64_t)cus * 8));
         hipLaunchKernelGGL(k_buf_segs, dim3(sgrid), dim3(256), 0, st, R, geom->ring_vtx_off, V, geom->vx, geom->vy,
-                           closed ? 1 : 0, segs, valid, bb, err);
+                           closed ? 1 : 0, segs, valid, bb, err, dlen);
         SPADE_HIP(ctx, hipGetLastError());
     }
     unsigned long long *h = (unsigned long long *)ensure_pinned(ctx, 64);
     if (!h) return set_error(ctx, SPADE_E_NOMEM, "pinned staging allocation failed");
-    SPADE_HIP(ctx, hipMemcpyAsync(h, bb, 5 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    SPADE_HIP(ctx, hipMemcpyAsync(h, bb, 7 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
     SPADE_HIP(ctx, hipStreamSynchronize(st));
     const unsigned ef = (unsigned)(h[4] & 0xffffffffu);
     if (ef & 1u) return set_error(ctx, SPADE_E_INVALID, "ring offsets are not a valid CSR array");
     if (ef & 2u) return set_error(ctx, SPADE_E_INVALID, "a vertex coordinate is not finite");
     const bool any = h[0] != ~0ull;
+    double len_sum;
+    std::memcpy(&len_sum, &h[6], sizeof len_sum);
     if (n == 0) return SPADE_OK;
 
     // the grid over the segments' box widened by r (and a relative margin,
     // so that rounding never drops a position within r)
-    BufGrid grid{0.0, 0.0, -1.0, -1.0, 1.0, 1, 1};   // empty box: no point is tested
+    BufGrid grid{0.0, 0.0, -1.0, -1.0, 1.0, 1.0, 1, 1};   // empty box: no point is tested
     double pad = 0.0;
     uint32_t *off = nullptr, *list = nullptr;
     if (any) {
@@ -259,13 +291,16 @@ int buffer_select(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pt
         pad = r * (1.0 + 0x1p-40) + mag * 0x1p-40 + 1e-300;
         const double X0 = x0 - pad, X1 = x1 + pad, Y0 = y0 - pad, Y1 = y1 + pad;
         const double w = X1 - X0, hgt = Y1 - Y0;
-        // cells about as wide as r, at least one per two segments' share of
-        // the box, at most BUF_GRID_MAX per side
-        double cell = std::max(r, std::sqrt(w * hgt / (2.0 * (double)std::max<int64_t>(V, 1))));
+        // cells as wide as r or the mean segment length, whichever is
+        // larger (a segment then meets a few cells, a cell a few segments),
+        // at most BUF_GRID_MAX per side
+        const double lmean = std::isfinite(len_sum) ? len_sum / (double)std::max<int64_t>(V, 1) : 0.0;
+        double cell = std::max(r, std::min(lmean, std::sqrt(w * hgt / (2.0 * (double)std::max<int64_t>(V, 1)))));
         cell = std::max(cell, std::max(w, hgt) / BUF_GRID_MAX);
         if (!(cell > 1e-290)) cell = 1.0;
         grid.X0 = X0; grid.Y0 = Y0; grid.X1 = X1; grid.Y1 = Y1;
         grid.inv = 1.0 / cell;
+        grid.cell = cell;
         grid.gx = (int)std::min<double>(BUF_GRID_MAX, std::max(1.0, std::ceil(w * grid.inv)));
         grid.gy = (int)std::min<double>(BUF_GRID_MAX, std::max(1.0, std::ceil(hgt * grid.inv)));
         const int64_t G = (int64_t)grid.gx * grid.gy;
@@ -328,11 +363,12 @@ int buffer_select(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pt
         const int grid_b = (int)std::max<int64_t>(1, std::min<int64_t>((nseg + wpb - 1) / wpb, (int64_t)cus * std::min(per_cu, 2)));
         SPADE_HIP(ctx, hipFuncSetAttribute((const void *)k_buf_bits<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         hipLaunchKernelGGL(k_buf_bits<true>, dim3(grid_b), dim3(BUF_THREADS), lds, st, v, n, pts->x, pts->y, grid,
-                           (const Seg *)segs, (const uint32_t *)off, (const uint32_t *)list, r, r2, nseg, counts, bits);
+                           (const Seg *)segs, (const uint32_t *)off, (const uint32_t *)list, r, r2, pad, nseg, counts,
+                           bits);
     } else {
         const int grid_b = (int)std::max<int64_t>(1, std::min<int64_t>((nseg + wpb - 1) / wpb, (int64_t)cus * 2));
         hipLaunchKernelGGL(k_buf_bits<false>, dim3(grid_b), dim3(BUF_THREADS), 0, st, CanvasView{}, n, pts->x, pts->y,
-                           grid, (const Seg *)segs, (const uint32_t *)off, (const uint32_t *)list, r, r2, nseg,
+                           grid, (const Seg *)segs, (const uint32_t *)off, (const uint32_t *)list, r, r2, pad, nseg,
                            counts, bits);
     }
     hipLaunchKernelGGL(k_buf_zero, dim3(1), dim3(1), 0, st, counts + nseg);
