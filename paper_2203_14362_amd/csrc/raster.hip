@@ -766,6 +766,7 @@ struct RowArgs {
     const CanvasDesc *cds;   // canvases of the set
     int nc;
     int maxW;                // widest canvas (LDS column arrays)
+    int narrow;              // pixel classes in 16 bits (every canvas has < 2^15 polygons)
     int64_t Htot;            // rows of all canvases
     int cap;                 // entries of one row staged in LDS
     const uint32_t *row_off;
@@ -818,13 +819,31 @@ struct RowData {
 struct RowShared {
     int32_t *sa;        // footprint counts -> per-column record counts / bases
     int32_t *sb;        // claim counts -> per-column fill counters
-    uint32_t *sx;       // claimant xor -> pixel class
+    void *sx;           // claimant xor -> pixel class (16 or 32 bits per column)
     uint32_t *locfill;  // row-local fill counter of the local-edge array
     uint32_t *nint;     // number of footprint-union intervals of the row
     uint32_t *nlong;    // long runs deferred to whole waves, and their starts
     uint32_t *longq;
     const unsigned long long *nrec;   // records of the row (set by the count phase)
     int W;              // width of the row's canvas
+    bool narrow;        // sx in 16 bits: labels + 1 below 2^15, boundary flag in bit 15
+
+    __device__ __forceinline__ uint32_t sx_flag() const { return narrow ? 0x8000u : BFLAG; }
+    __device__ __forceinline__ uint32_t sx_get(int e) const
+    {
+        return narrow ? (uint32_t)((const uint16_t *)sx)[e] : ((const uint32_t *)sx)[e];
+    }
+    __device__ __forceinline__ void sx_set(int e, uint32_t v) const
+    {
+        if (narrow) ((uint16_t *)sx)[e] = (uint16_t)v;
+        else ((uint32_t *)sx)[e] = v;
+    }
+    // xor into element e (two 16-bit elements share an LDS word)
+    __device__ __forceinline__ void sx_xor(int e, uint32_t v) const
+    {
+        if (narrow) atomicXor((uint32_t *)sx + (e >> 1), v << ((e & 1) * 16));
+        else atomicXor((uint32_t *)sx + e, v);
+    }
 };
 
 // Runs longer than this are processed by a whole wave (lane-parallel scans)
@@ -980,7 +999,7 @@ __device__ void claimant_walk(const RowArgs &A, const RowData &D, const RowShare
     const int c0first = (int)(D.c[i] & 0xffff);
     if (par)
         for (int col = 0; col < c0first; ++col)
-            if (L.sx[cix(col)] & BFLAG) emit(col);
+            if (L.sx_get(cix(col)) & L.sx_flag()) emit(col);
     for (int q = i; q < je; ++q) {
         const uint32_t c = D.c[q];
         mx = max(mx, (int)(c >> 16));
@@ -989,7 +1008,7 @@ __device__ void claimant_walk(const RowArgs &A, const RowData &D, const RowShare
         const int lo = max((int)(c & 0xffff), mx + 1), hi = nc0 - 1;
         if (par)
             for (int col = lo; col <= hi; ++col)
-                if (L.sx[cix(col)] & BFLAG) emit(col);
+                if (L.sx_get(cix(col)) & L.sx_flag()) emit(col);
     }
 }
 
@@ -1014,9 +1033,9 @@ __device__ __forceinline__ void for_each_run(const RowData &D, Fn fn)
 // only, so they overlap), wave scans of the five totals, one barrier, then
 // the chunks rewritten from their running prefixes.  wt holds 5 words per
 // wave.
-__device__ void row_scans(int32_t *sa, int32_t *sb, uint32_t *sx, int W, uint32_t *pre, int n,
-                          uint32_t *ilen, int ni, uint32_t *wt)
+__device__ void row_scans(const RowShared &L, int W, uint32_t *pre, int n, uint32_t *ilen, int ni, uint32_t *wt)
 {
+    int32_t *sa = L.sa, *sb = L.sb;
     const int NW = row_threads() >> 6;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int pc = (W + row_threads() - 1) / row_threads(), pp = (n + row_threads() - 1) / row_threads();
@@ -1028,7 +1047,7 @@ __device__ void row_scans(int32_t *sa, int32_t *sb, uint32_t *sx, int W, uint32_
     for (int c = cb; c < ce; ++c) {
         ta += (uint32_t)sa[cix(c)];
         tb += (uint32_t)sb[cix(c)];
-        tx ^= sx[cix(c)];
+        tx ^= L.sx_get(cix(c));
     }
     for (int q = qb; q < qe; ++q) tp = pre_op(tp, pre[q]);
     for (int q = ib; q < ie; ++q) ti += ilen[q];
@@ -1054,9 +1073,9 @@ __device__ void row_scans(int32_t *sa, int32_t *sb, uint32_t *sx, int W, uint32_
         rp = pre_op(wt[3 * NW + w], rp); ri += wt[4 * NW + w];
     }
     for (int c = cb; c < ce; ++c) {
-        const uint32_t a = (uint32_t)sa[cix(c)], b = (uint32_t)sb[cix(c)], x = sx[cix(c)];
+        const uint32_t a = (uint32_t)sa[cix(c)], b = (uint32_t)sb[cix(c)], x = L.sx_get(cix(c));
         ra += a; rb += b; rx ^= x;
-        sa[cix(c)] = (int32_t)ra; sb[cix(c)] = (int32_t)rb; sx[cix(c)] = rx;
+        sa[cix(c)] = (int32_t)ra; sb[cix(c)] = (int32_t)rb; L.sx_set(cix(c), rx);
     }
     for (int q = qb; q < qe; ++q) { rp = pre_op(rp, pre[q]); pre[q] = rp; }
     for (int q = ib; q < ie; ++q) { ri += ilen[q]; ilen[q] = ri; }
@@ -1085,11 +1104,16 @@ __device__ void all_column_records(const RowArgs &A, const RowData &D, const Row
     }
 }
 
-// Dynamic LDS: three padded column arrays, then `cap` staged entries with
-// their auxiliary words and up to `cap` footprint intervals.
-__host__ __device__ inline size_t row_lds_bytes(int W, int cap)
+// 32-bit words of the pixel-class column array (16-bit elements when narrow).
+__host__ __device__ inline int sx_words(int cw, bool narrow) { return narrow ? (cw + 1) / 2 : cw; }
+
+// Dynamic LDS: three padded column arrays (the pixel classes in 16 bits when
+// narrow), then `cap` staged entries with their auxiliary words and up to
+// `cap` footprint intervals.
+__host__ __device__ inline size_t row_lds_bytes(int W, int cap, bool narrow)
 {
-    return (size_t)3 * col_words(W) * 4 + (size_t)cap * 37 + 32;
+    const int cw = col_words(W);
+    return (size_t)(2 * cw + sx_words(cw, narrow)) * 4 + (size_t)cap * 37 + 32;
 }
 
 // Phase 1 for one run by one thread: footprint counts, interior spans with
@@ -1105,7 +1129,7 @@ __device__ void run_serial(const RowData &D, const RowShared &L, int i, int je, 
     const int c0first = (int)(D.c[i] & 0xffff);
     if (par && c0first > 0) {
         atomicAdd(&L.sb[cix(0)], 1); atomicSub(&L.sb[cix(c0first)], 1);
-        atomicXor(&L.sx[cix(0)], lab); atomicXor(&L.sx[cix(c0first)], lab);
+        L.sx_xor(cix(0), lab); L.sx_xor(cix(c0first), lab);
     }
     for (int q = i; q < je; ++q) {
         const uint32_t c = D.c[q];
@@ -1122,7 +1146,7 @@ __device__ void run_serial(const RowData &D, const RowShared &L, int i, int je, 
         const int lo = max(c0, mx + 1), hi = nc0 - 1;
         if (par && lo <= hi) {
             atomicAdd(&L.sb[cix(lo)], 1); atomicSub(&L.sb[cix(hi + 1)], 1);
-            atomicXor(&L.sx[cix(lo)], lab); atomicXor(&L.sx[cix(hi + 1)], lab);
+            L.sx_xor(cix(lo), lab); L.sx_xor(cix(hi + 1), lab);
         }
     }
     // footprint-union intervals of the run
@@ -1186,7 +1210,7 @@ __device__ void run_wave(const RowData &D, const RowShared &L, int i, int W)
     const int c0first = (int)(D.c[i] & 0xffff);
     if (lane == 0 && wtot && c0first > 0) {
         atomicAdd(&L.sb[cix(0)], 1); atomicSub(&L.sb[cix(c0first)], 1);
-        atomicXor(&L.sx[cix(0)], lab); atomicXor(&L.sx[cix(c0first)], lab);
+        L.sx_xor(cix(0), lab); L.sx_xor(cix(c0first), lab);
     }
     uint32_t par_c = wtot;
     int mx_c = -1, mall_c = 0, mnh_c = 0, ulo_c = c0first;
@@ -1207,7 +1231,7 @@ __device__ void run_wave(const RowData &D, const RowShared &L, int i, int W)
         const int lo = max(c0, mx + 1), hi = nc0 - 1;
         if (valid && par && lo <= hi) {
             atomicAdd(&L.sb[cix(lo)], 1); atomicSub(&L.sb[cix(hi + 1)], 1);
-            atomicXor(&L.sx[cix(lo)], lab); atomicXor(&L.sx[cix(hi + 1)], lab);
+            L.sx_xor(cix(lo), lab); L.sx_xor(cix(hi + 1), lab);
         }
         // footprint-union intervals: an entry starts one when it begins more
         // than a column right of every earlier footprint of the run
@@ -1260,7 +1284,7 @@ __device__ void process_row(const RowArgs &A, const RowData &D, const RowShared 
 
     // phase 2: prefix scans -> per-pixel boundary count, claim count,
     //          claimant; per-entry partial/spanning prefixes; run spans
-    row_scans(L.sa, L.sb, L.sx, W, D.pre, D.n, D.ilen, (int)*L.nint, wtotu);
+    row_scans(L, W, D.pre, D.n, D.ilen, (int)*L.nint, wtotu);
 
     // phase 3: classify pixels.  sx := 0 (no polygon), label + 1, or for a
     // boundary pixel BFLAG | (label + 1 of its single interior claimant, or 0);
@@ -1268,9 +1292,9 @@ __device__ void process_row(const RowArgs &A, const RowData &D, const RowShared 
     uint32_t nb = 0, multi = 0;
     for (int c = tid; c < W; c += row_threads()) {
         const int32_t bc = L.sa[cix(c)], cc = L.sb[cix(c)];
-        const uint32_t xc = L.sx[cix(c)];
+        const uint32_t xc = L.sx_get(cix(c));
         const bool bnd = bc > 0 || cc >= 2;
-        L.sx[cix(c)] = bnd ? (BFLAG | (cc == 1 ? xc : 0u)) : (cc == 1 ? xc : 0u);
+        L.sx_set(cix(c), bnd ? (L.sx_flag() | (cc == 1 ? xc : 0u)) : (cc == 1 ? xc : 0u));
         L.sa[cix(c)] = (bnd && cc == 1) ? 1 : 0;
         L.sb[cix(c)] = 0;
         nb += bnd ? 1u : 0u;
@@ -1350,12 +1374,12 @@ __device__ void process_row(const RowArgs &A, const RowData &D, const RowShared 
         if (rmulti) for_each_run(D, [&](int i, int je) { claimant_walk<true>(A, D, L, i, je, rec_base_r, W); });
         else
             for (int c = tid; c < W; c += row_threads()) {
-                const uint32_t w = L.sx[cix(c)];
-                if ((w & BFLAG) && (w & ~BFLAG)) {
+                const uint32_t w = L.sx_get(cix(c));
+                if ((w & L.sx_flag()) && (w & ~L.sx_flag())) {
                     uint32_t last;
                     const uint64_t slot = rec_slot(L, c, rec_base_r, last);
                     Cand cd{};
-                    cd.poly = (w & ~BFLAG) - 1u;
+                    cd.poly = (w & ~L.sx_flag()) - 1u;
                     cd.meta = CAND_S | last;
                     cd.eoff = 0;
                     cd.poff = 0;
@@ -1373,8 +1397,8 @@ __device__ void process_row(const RowArgs &A, const RowData &D, const RowShared 
     // phase 6: write the canvas row (tile-major); a boundary pixel points
     //          at its first record (the last one carries CAND_LAST)
     for (int c = tid; c < W; c += row_threads()) {
-        uint32_t word = L.sx[cix(c)];
-        if (word & BFLAG) {
+        uint32_t word = L.sx_get(cix(c));
+        if (word & L.sx_flag()) {
             const int32_t b = c ? L.sa[cix(c - 1)] : 0;
             const int32_t e = L.sa[cix(c)];
             if (e - b <= 0 || L.sb[cix(c)] != e - b) { atomicOr(A.errflags, 8u); word = 0; }
@@ -1398,13 +1422,14 @@ __global__ __launch_bounds__(ROW_THREADS_MAX) void k_rows(RowArgs A)
     RowShared L;
     L.sa = (int32_t *)smem;
     L.sb = L.sa + cwmax;
-    L.sx = (uint32_t *)(L.sb + cwmax);
+    L.sx = (void *)(L.sb + cwmax);
+    L.narrow = A.narrow != 0;
     L.locfill = &s_locfill;
     L.nint = &s_nint;
     L.nlong = &s_nlong;
     L.longq = s_longq;
     L.nrec = &s_nrec;
-    uint32_t *lpoly = L.sx + cwmax;
+    uint32_t *lpoly = (uint32_t *)(L.sb + cwmax) + sx_words(cwmax, L.narrow);
     uint32_t *lc = lpoly + cap;
     uint32_t *ledge = lc + cap;
     uint32_t *lpm = ledge + cap;
@@ -1437,7 +1462,7 @@ __global__ __launch_bounds__(ROW_THREADS_MAX) void k_rows(RowArgs A)
                 lf[q] = A.sf[s + q];
             }
         }
-        for (int c = tid; c < cw; c += row_threads()) { L.sa[c] = 0; L.sb[c] = 0; L.sx[c] = 0; }
+        for (int c = tid; c < cw; c += row_threads()) { L.sa[c] = 0; L.sb[c] = 0; L.sx_set(c, 0u); }
         if (tid == 0) { s_locfill = 0; s_nint = 0; s_nbp = 0; s_multi = 0; s_nloc = 0; s_nrec = 0; s_nlong = 0; }
         __syncthreads();
         if (n <= cap) {
@@ -1945,7 +1970,11 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
     // LDS stage of the row kernel: up to `cap` entries of a row; narrow
     // canvases aim for three or four workgroups per CU, wider ones for two
     // (measured best).
-    const size_t col_bytes = row_lds_bytes(W, 0);
+    // pixel classes in 16 bits when every label + 1 fits in 15
+    int64_t maxM_all = 1;
+    for (int q = 0; q < nc; ++q) maxM_all = std::max<int64_t>(maxM_all, cds[q].M);
+    const bool narrow = maxM_all < 0x8000;
+    const size_t col_bytes = row_lds_bytes(W, 0, narrow);
     const size_t target = (col_bytes <= 40 * 1024) ? 38 * 1024 : (col_bytes <= 60 * 1024) ? 78 * 1024 : 150 * 1024;
     const int cap = (int)std::max<size_t>(256, (target - std::min(target - 256 * 37, col_bytes)) / 37);
     // rows up to capB entries run in the launch over all rows, taken first,
@@ -2090,9 +2119,10 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
     ra.rec_base = rec_base; ra.loc_base = loc_base; ra.part_base = part_base;
     ra.errflags = d_err;
     ra.cap = cap;
-    const size_t rlds = row_lds_bytes(W, ra.cap);
+    ra.narrow = narrow ? 1 : 0;
+    const size_t rlds = row_lds_bytes(W, ra.cap, narrow);
     // the longest rows: a stage for the longest of them, up to 150 KB
-    const size_t rlds_big = row_lds_bytes(W, cap_big);
+    const size_t rlds_big = row_lds_bytes(W, cap_big, narrow);
     if (maxrow > (uint64_t)cap_big || nlistB > 0) {
         // rows without a stage: global auxiliary words for them
         if (ensure(ctx, ctx->scratch[S_NEXTP], sizeof(uint32_t) * 6 * Ts)) return SPADE_E_NOMEM;
@@ -2205,7 +2235,7 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
         put((uint64_t)cbits); put((uint64_t)pbits); put((uint64_t)kbits); put(tbytes); put(tscan);
         put(bucketed ? 1 : 0); put(entries_done ? 1 : 0); put((uint64_t)ebits); put(sort_lds); put(nlistB); put(nlistC);
         put((uint64_t)capB); put((uint64_t)rstride);
-        put((uint64_t)ra.cap); put((uint64_t)cap_big); put(rlds); put(rlds_big);
+        put((uint64_t)ra.cap); put((uint64_t)cap_big); put(rlds); put(rlds_big); put((uint64_t)ra.narrow);
         put(ra.cap_rec); put(ra.cap_loc); put(ra.cap_part);
         putp(cv->edges.p); putp(epoly); putp(erow0); putp(nrows); putp(eoff); putp(d_cds);
         putp(dk.p); putp(dk2.p); putp(dv.p); putp(dv2.p); putp(dc.p); putp(df.p); putp(drow.p); putp(cub.p);

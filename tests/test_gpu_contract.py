@@ -104,6 +104,21 @@ def test_capacity_writes_first_cap_results(ctx):
     assert np.array_equal(bpt.cpu().numpy().astype(np.uint32), opt[:capp])
     assert np.array_equal(bpg.cpu().numpy().astype(np.uint32), opg[:capp])
 
+    # distance selections from lines and from a polygon
+    from oracle import buffer as obuf
+    lines = gen.polys_from_rings([[np.array([[0.1, 0.1], [0.5, 0.7], [0.9, 0.2]])],
+                                  [np.array([[0.2, 0.9], [0.8, 0.85]])]])
+    for fn, geom, r, want_fn in ((lib.spade_select_near_lines, lines, 0.05, obuf.select_near_lines),
+                                 (lib.spade_select_within_polygon, star, 0.03, obuf.select_within_polygon)):
+        wl = want_fn(x, y, geom, r)
+        capl = wl.size // 2
+        dg = ctx.polys(geom)
+        buf = torch.full((capl,), -1, dtype=torch.int32, device="cuda")
+        rc = fn(ctx.handle, ctypes.byref(P), ctypes.byref(dg.cstruct()), r, ctypes.c_void_p(buf.data_ptr()), capl,
+                ctypes.byref(n))
+        assert rc == spade.SPADE_E_CAPACITY and n.value == wl.size
+        assert np.array_equal(buf.cpu().numpy().astype(np.uint32), wl[:capl])
+
 
 def test_batch_select_capacity_writes_first_cap(ctx):
     L = gen.EXTENT_M
