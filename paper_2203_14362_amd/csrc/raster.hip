@@ -1508,6 +1508,7 @@ __global__ __launch_bounds__(256) void k_compact(const CanvasDesc *cds, int nc, 
         const uint32_t *cells = cells_all + cd.cell_off;
         uint16_t *coarse = coarse_all + cd.coarse_off;
         const int B = 1 << blog, J = (B * B) / 64;
+        if (cd.blog <= 4) continue;   // k_compact_tiles covers these canvases
         const int64_t cell = gcell - cd.coarse_off;
         const uint32_t fullw = cd.cbyte ? COARSE_BYTE_FULL : (uint32_t)COARSE_FULL;
         uint32_t v = 0u;
@@ -1526,6 +1527,58 @@ __global__ __launch_bounds__(256) void k_compact(const CanvasDesc *cds, int nc, 
         if (lane == 0) {
             if (cd.cbyte) ((uint8_t *)coarse)[cell] = (uint8_t)v;
             else coarse[cell] = (uint16_t)v;
+        }
+    }
+}
+
+// Canvas holding global tile g (canvas words are 256-word tiles).
+__device__ __forceinline__ int canvas_of_tile(const CanvasDesc *cds, int nc, int64_t g)
+{
+    int lo = 0, hi = nc - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if ((cds[mid].cell_off >> 8) <= g) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Coarse level of the canvases with 8 x 8 or 16 x 16 blocks, one wavefront
+// per 16 x 16 tile, read with one 16-byte load per lane (lane l holds tile
+// row l / 4, columns 4 (l % 4) .. 4 (l % 4) + 3): a block is uniform when
+// every in-canvas pixel equals its top-left one, found with one ballot.
+__global__ __launch_bounds__(256) void k_compact_tiles(const CanvasDesc *cds, int nc, int64_t ntiles,
+                                                       const uint32_t *cells_all, uint16_t *coarse_all)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t gt = wave; gt < ntiles; gt += nw) {
+        const CanvasDesc &cd = cds[canvas_of_tile(cds, nc, gt)];
+        if (cd.blog > 4) continue;
+        const int64_t t = gt - (cd.cell_off >> 8);
+        const int ty = (int)(t / cd.Wt), tx = (int)(t % cd.Wt);
+        const uint4 w = ((const uint4 *)(cells_all + cd.cell_off + t * 256))[lane];
+        const int r = ty * 16 + (lane >> 2), c0 = tx * 16 + (lane & 3) * 4;
+        const bool b8 = cd.blog == 3;
+        const int by = b8 ? (lane >> 5) : 0, bx = b8 ? ((lane & 3) >> 1) : 0;
+        const int ref_lane = by * 32 + bx * 2;
+        const uint32_t ref = (uint32_t)__shfl((int)w.x, ref_lane, 64);
+        const uint32_t wk[4] = {w.x, w.y, w.z, w.w};
+        bool same = true;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) same &= !(c0 + k < cd.W && r < cd.H) || wk[k] == ref;
+        const unsigned long long bad = __ballot(!same);
+        const unsigned long long mask = b8 ? ((bx ? 0xCCCCCCCCull : 0x33333333ull) << (by * 32)) : ~0ull;
+        if (lane == ref_lane) {
+            const int cx = b8 ? tx * 2 + bx : tx, cy = b8 ? ty * 2 + by : ty;
+            if (cx < cd.Wc && cy < cd.Hc) {
+                const uint32_t fullw = cd.cbyte ? COARSE_BYTE_FULL : (uint32_t)COARSE_FULL;
+                const uint32_t v = cd.empty ? 0u : ((bad & mask) == 0 && !(ref & BFLAG) && ref < fullw) ? ref : fullw;
+                const int64_t cell = (int64_t)cy * cd.Wc + cx;
+                uint16_t *coarse = coarse_all + cd.coarse_off;
+                if (cd.cbyte) ((uint8_t *)coarse)[cell] = (uint8_t)v;
+                else coarse[cell] = (uint16_t)v;
+            }
         }
     }
 }
@@ -2186,11 +2239,23 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
     };
     ra.cells = (uint32_t *)cv->cells.p;
 
-    // Coarse level from the canvas words.
+    // Coarse level from the canvas words: tile by tile for 8 x 8 and 16 x 16
+    // blocks, block by block for larger ones.
+    bool small_blocks = false, large_blocks = false;
+    for (int q = 0; q < nc; ++q) (cds[q].blog <= 4 ? small_blocks : large_blocks) = true;
+    const int compact_mode = (small_blocks ? 1 : 0) | (large_blocks ? 2 : 0);
     auto launch_compact = [&]() -> hipError_t {
-        const int cgrid = (int)std::max<int64_t>(1, std::min<int64_t>((coarse_tot + 3) / 4, 65536));
-        hipLaunchKernelGGL(k_compact, dim3(cgrid), dim3(256), 0, qs, d_cds, nc, coarse_tot,
-                           (const uint32_t *)cv->cells.p, (uint16_t *)cv->coarse.p);
+        if (small_blocks) {
+            const int64_t ntiles = cells_tot / 256;
+            const int tgrid = (int)std::max<int64_t>(1, std::min<int64_t>((ntiles + 3) / 4, 65536));
+            hipLaunchKernelGGL(k_compact_tiles, dim3(tgrid), dim3(256), 0, qs, d_cds, nc, ntiles,
+                               (const uint32_t *)cv->cells.p, (uint16_t *)cv->coarse.p);
+        }
+        if (large_blocks) {
+            const int cgrid = (int)std::max<int64_t>(1, std::min<int64_t>((coarse_tot + 3) / 4, 65536));
+            hipLaunchKernelGGL(k_compact, dim3(cgrid), dim3(256), 0, qs, d_cds, nc, coarse_tot,
+                               (const uint32_t *)cv->cells.p, (uint16_t *)cv->coarse.p);
+        }
         return hipGetLastError();
     };
 
@@ -2236,6 +2301,7 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
         put(bucketed ? 1 : 0); put(entries_done ? 1 : 0); put((uint64_t)ebits); put(sort_lds); put(nlistB); put(nlistC);
         put((uint64_t)capB); put((uint64_t)rstride);
         put((uint64_t)ra.cap); put((uint64_t)cap_big); put(rlds); put(rlds_big); put((uint64_t)ra.narrow);
+        put((uint64_t)compact_mode);
         put(ra.cap_rec); put(ra.cap_loc); put(ra.cap_part);
         putp(cv->edges.p); putp(epoly); putp(erow0); putp(nrows); putp(eoff); putp(d_cds);
         putp(dk.p); putp(dk2.p); putp(dv.p); putp(dv2.p); putp(dc.p); putp(df.p); putp(drow.p); putp(cub.p);

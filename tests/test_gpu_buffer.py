@@ -146,3 +146,18 @@ def test_capacity_and_degenerate(ctx, pts, roads):
     two = gen.concat_polys(gen.star_polygon(10, 0.01, (L / 3, L / 3), L=L), gen.star_polygon(10, 0.01, (L / 2, L / 2), L=L))
     with pytest.raises(SpadeError):
         ctx.select_within(_dev(x), _dev(y), two, 10.0)
+
+
+@pytest.mark.parametrize("r", [30.0, 400.0])
+def test_offset_frame(ctx, pts, roads, r):
+    """Web-Mercator-sized coordinates (+(-8.27e6, 4.94e6) m): the differences
+    of large coordinates are where the FP64 filters give way to the exact
+    expansions."""
+    x, y = pts
+    ox, oy, lines = gen.offset_frame(x, y, roads, L=L)
+    got = _ids(ctx.select_near_lines(_dev(ox), _dev(oy), lines, r))
+    assert np.array_equal(got, B.select_near_lines(ox, oy, lines, r))
+    star = gen.star_polygon(500, 0.01, (L * 0.55, L * 0.45), L=L, seed=47)
+    sx, sy, sp = gen.offset_frame(x, y, star, L=L)
+    got = _ids(ctx.select_within(_dev(sx), _dev(sy), sp, r))
+    assert np.array_equal(got, B.select_within_polygon(sx, sy, sp, r))
