@@ -505,7 +505,8 @@ def leg_serve(dx, dy, seconds, warm_seconds, qps, oneshot):
                  "vx": stars["vx"][srvo[i]:srvo[i + 1]], "vy": stars["vy"][srvo[i]:srvo[i + 1]]}
             reqs.append(Request(i, "select", p))
         else:
-            reqs.append(Request(i, "count", tess[int(rng.integers(0, len(tess)))]))
+            k = int(rng.integers(0, len(tess)))
+            reqs.append(Request(i, "count", tess[k], key=("tess", k)))
     ex = SpadeExecutor(dx, dy, n_workers=2)
     ppv, times = ex.autotune(reqs[:32])
     log("serving autotune: %.0f pixels per vertex" % ppv)
@@ -552,7 +553,7 @@ def leg_serve(dx, dy, seconds, warm_seconds, qps, oneshot):
     # alone vs served: the sampled requests again, served in one burst with
     # their results kept, and each alone through the plain calls
     ctx = Context(0)
-    sample = [Request(r.rid, r.kind, r.polys) for r in reqs if r.rid in keep]
+    sample = [Request(r.rid, r.kind, r.polys, key=r.key) for r in reqs if r.rid in keep]
     srv2 = Server(ex, budget_bytes=budget).start()
     for r in sample:
         srv2.submit(r)
@@ -572,13 +573,14 @@ def leg_serve(dx, dy, seconds, warm_seconds, qps, oneshot):
         (ctx.select if r.kind == "select" else ctx.join_count)(dx, dy, r.polys)
     torch.cuda.synchronize()
     one = (time.perf_counter() - t0) / k
-    burst = [Request(r.rid, r.kind, r.polys) for r in reqs[:600]]
+    burst = [Request(r.rid, r.kind, r.polys, key=r.key) for r in reqs[:600]]
     srv3 = Server(ex, budget_bytes=budget, keep_results=False).start()
     t0 = time.perf_counter()
     for r in burst:
         srv3.submit(r)
     srv3.stop()
     tb = time.perf_counter() - t0
+    cache = {"hits": ex.cache_hits, "builds": ex.cache_builds, "sets_per_worker": ex.cached_sets}
     ex.close()
     ctx.close()
     return {"qps_offered": qps, "seconds": seconds, "warmup_seconds": warm_seconds, "requests": n,
@@ -595,8 +597,9 @@ def leg_serve(dx, dy, seconds, warm_seconds, qps, oneshot):
             "capacity_batched_requests_per_s": round(len(burst) / tb, 1),
             "capacity_one_at_a_time_requests_per_s": round(1.0 / one, 1), "one_at_a_time_sample": k,
             "pixels_per_vertex": ppv,
+            "canvas_set_cache": cache,
             "mix": "50% selection (star, 8-20000 vertices, areas 1e-4..0.15), 50% join-count "
-                   "(one of 8 census-like tessellations, 64..40000 cells)"}
+                   "(one of 8 census-like tessellations, 64..40000 cells, keyed: their canvas sets are cached)"}
 
 
 def main():

@@ -425,7 +425,10 @@ typedef struct {
 /* polys: device CSR arrays that must stay valid until the job is done;
  * qbound: host offsets as for spade_batch_build (copied); set: a canvas set
  * from spade_batch_build (rebuilt in place; not the context's own canvas);
- * kind: SPADE_JOB_*.  *out receives the job handle. */
+ * kind: SPADE_JOB_*.  *out receives the job handle.  With polys NULL the job
+ * queries the set as it was last built (nq and qbound are then ignored): a
+ * caller that keeps the set of a polygon set it sees again skips its
+ * rasterisation. */
 int spade_batch_submit(spade_ctx *ctx, spade_canvas *set, const spade_polys *polys, int32_t nq,
                        const int64_t *qbound, const spade_table *t, int kind, spade_job **out);
 

@@ -318,21 +318,18 @@ int buffer_select(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pt
                            (const uint8_t *)valid, grid, pad, cnt, (const uint32_t *)nullptr, (uint32_t *)nullptr,
                            tot);
         SPADE_HIP(ctx, hipGetLastError());
-        // the cell lists are indexed with 32 bits
+        size_t tb = 0;
+        SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(nullptr, tb, cnt, off, (int)(G + 1), st));
+        if (ensure(ctx, bt, std::max<size_t>(tb, 1))) return SPADE_E_NOMEM;
+        SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(bt.p, tb, cnt, off, (int)(G + 1), st));
+        // the 64-bit entry count first: the cell lists are indexed with 32
+        // bits (the offsets are only used below 2^31 entries)
         SPADE_HIP(ctx, hipMemcpyAsync(h, tot, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
         SPADE_HIP(ctx, hipStreamSynchronize(st));
         if (h[0] >= ((unsigned long long)1 << 31))
             return set_error(ctx, SPADE_E_TOO_LARGE, "too many (segment, cell) entries: the distance is too large "
                                                      "for the segments' spread");
-        size_t tb = 0;
-        SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(nullptr, tb, cnt, off, (int)(G + 1), st));
-        if (ensure(ctx, bt, std::max<size_t>(tb, 1))) return SPADE_E_NOMEM;
-        SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(bt.p, tb, cnt, off, (int)(G + 1), st));
-        uint32_t *hl = (uint32_t *)ensure_pinned(ctx, 64);
-        if (!hl) return set_error(ctx, SPADE_E_NOMEM, "pinned staging allocation failed");
-        SPADE_HIP(ctx, hipMemcpyAsync(hl, off + G, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-        SPADE_HIP(ctx, hipStreamSynchronize(st));
-        const uint64_t total = hl[0];
+        const uint64_t total = h[0];
         DevBuf &bl = ctx->scratch[S_BUF_LIST];
         if (ensure(ctx, bl, sizeof(uint32_t) * (size_t)std::max<uint64_t>(total, 1))) return SPADE_E_NOMEM;
         list = (uint32_t *)bl.p;

@@ -29,6 +29,7 @@ struct spade_job {
     spade_ctx *ctx = nullptr;
     spade_canvas *set = nullptr;
     spade_polys polys{};
+    bool rebuild = true;         // false: query the set as it stands
     std::vector<int64_t> qbound;
     const spade_table *table = nullptr;
     int kind = 0;
@@ -75,8 +76,9 @@ static void run_job(JobQueue *jq, spade_job *j)
 {
     spade_ctx *ctx = j->ctx;
     ResBuf *rb = j->rb = take_buf(jq, j->kind);
-    int rc = rb ? spade_batch_rebuild(ctx, &j->polys, (int32_t)(j->qbound.size() - 1), j->qbound.data(), j->set)
-                : set_error(ctx, SPADE_E_NOMEM, "host allocation failed");
+    int rc = !rb ? set_error(ctx, SPADE_E_NOMEM, "host allocation failed")
+             : j->rebuild ? spade_batch_rebuild(ctx, &j->polys, (int32_t)(j->qbound.size() - 1), j->qbound.data(), j->set)
+                          : SPADE_OK;
     if (rc == SPADE_OK) {
         const int nq = (int)j->qbound.size() - 1;
         if (j->kind == SPADE_JOB_COUNT) {
@@ -189,7 +191,8 @@ int spade_batch_submit(spade_ctx *ctx, spade_canvas *set, const spade_polys *pol
 {
     if (!ctx || !out) return SPADE_E_INVALID;
     *out = nullptr;
-    if (!set || !polys || !t || !qbound || nq < 1) return set_error(ctx, SPADE_E_INVALID, "NULL argument or nq < 1");
+    if (!set || !t || (polys && (!qbound || nq < 1)))
+        return set_error(ctx, SPADE_E_INVALID, "NULL argument or nq < 1");
     if (kind != SPADE_JOB_SELECT && kind != SPADE_JOB_COUNT && kind != SPADE_JOB_PAIRS)
         return set_error(ctx, SPADE_E_INVALID, "unknown job kind");
     if (set == ctx->plain) return set_error(ctx, SPADE_E_INVALID, "not a caller-owned canvas set");
@@ -197,9 +200,18 @@ int spade_batch_submit(spade_ctx *ctx, spade_canvas *set, const spade_polys *pol
     if (!j) return set_error(ctx, SPADE_E_NOMEM, "host allocation failed");
     j->ctx = ctx;
     j->set = set;
-    j->polys = *polys;
-    j->polys.bbox = nullptr;   // the host array need not outlive the call
-    j->qbound.assign(qbound, qbound + nq + 1);
+    if (polys) {
+        j->polys = *polys;
+        j->polys.bbox = nullptr;   // the host array need not outlive the call
+        j->qbound.assign(qbound, qbound + nq + 1);
+    } else {
+        // query only: the set's own query bounds
+        SPADE_CTX_LOCK(ctx);
+        j->rebuild = false;
+        j->qbound.resize((size_t)set->nc + 1);
+        for (int q = 0; q < set->nc; ++q) j->qbound[(size_t)q] = set->descs[(size_t)q].poly_base;
+        j->qbound[(size_t)set->nc] = set->nc ? set->descs.back().poly_base + set->descs.back().M : 0;
+    }
     j->table = t;
     j->kind = kind;
     JobQueue *jq = (JobQueue *)ctx->jobs;

@@ -18,7 +18,10 @@ submits it asynchronously (``submit(worker, reqs)`` returning a token,
 completion thread collects, and no host thread blocks in a device call.
 ``SpadeExecutor`` is the device executor: one canvas set per worker and
 kind, evaluated by the library's asynchronous batch jobs over the shared
-resident table.
+resident table.  Requests may carry a ``key`` naming their polygon set (equal
+keys, equal polygons): a batch holding one keyed request keeps its canvas set
+in a small per-worker cache, and a later such batch with the same key is
+evaluated on it without rasterising again.
 
 Admission counts device memory three ways against one budget: the estimates
 of the requests in flight, the bytes of finished results the caller still
@@ -52,6 +55,7 @@ class Request:
     result: Any = None             # select: int32 ids; count: int64 counts
     error: Optional[str] = None
     result_size: Optional[int] = None   # when the server does not keep results
+    key: Any = None                # names the polygon set (equal keys, equal polygons); None: not cached
 
     @property
     def latency(self) -> Optional[float]:
@@ -363,7 +367,8 @@ class SpadeExecutor:
     resident table.  A batch becomes at most two canvas sets (its selections,
     its join-counts) evaluated with the library's batch calls."""
 
-    def __init__(self, x, y, n_workers: int = 2, device: int = 0, pixels_per_vertex: float = None):
+    def __init__(self, x, y, n_workers: int = 2, device: int = 0, pixels_per_vertex: float = None,
+                 cached_sets: int = 8):
         import torch
         from .spade import Context
         self.torch = torch
@@ -379,6 +384,11 @@ class SpadeExecutor:
                 self.ctxs.append(c)
         self.ppv = pixels_per_vertex or 256.0
         self._sets = [[None, None] for _ in range(n_workers)]
+        # per worker: canvas sets of keyed batches, least recently used first
+        self.cached_sets = int(cached_sets)
+        self._cache = [collections.OrderedDict() for _ in range(n_workers)]
+        self.cache_hits = 0
+        self.cache_builds = 0
         self._resident_w = [0] * n_workers
         with torch.cuda.stream(self.streams[0]):
             self.table = self.ctxs[0].table(x, y)
@@ -447,15 +457,34 @@ class SpadeExecutor:
                 rs = [r for r in reqs if r.kind == kind]
                 if rs:
                     polys, qb = concat_sets([r.polys for r in rs])
-                    work.append((kind, code, slot, rs, polys, qb))
-            # sets this worker lacks are built before its first job is queued
-            # (a call on a context waits for the job it is running)
-            for kind, code, slot, rs, polys, qb in work:
-                if self._sets[w][slot] is None:
+                    # a batch of one keyed request keeps its set: combinations
+                    # of several requests rarely come back
+                    key = (kind, rs[0].key) if len(rs) == 1 and rs[0].key is not None else None
+                    work.append((kind, code, slot, rs, polys, qb, key))
+            # sets this worker lacks (its reusable ones, or a keyed batch's
+            # set not cached yet) are built before its first job is queued (a
+            # call on a context waits for the job it is running)
+            cache = self._cache[w]
+            for kind, code, slot, rs, polys, qb, key in work:
+                if key is not None and self.cached_sets > 0:
+                    if key in cache:
+                        cache.move_to_end(key)
+                        self.cache_hits += 1
+                    else:
+                        cache[key] = ctx.batch(polys, qb)
+                        self.cache_builds += 1
+                        # the worker is free (its last batch was collected), so
+                        # no job of its context still reads an evicted set
+                        while len(cache) > self.cached_sets:
+                            cache.popitem(last=False)[1].close()
+                elif self._sets[w][slot] is None:
                     self._sets[w][slot] = ctx.batch(polys, qb)
             s.synchronize()
-            for kind, code, slot, rs, polys, qb in work:
-                jobs.append((kind, rs, qb, ctx.submit(self._sets[w][slot], polys, qb, self.table, code)))
+            for kind, code, slot, rs, polys, qb, key in work:
+                if key is not None and self.cached_sets > 0:
+                    jobs.append((kind, rs, qb, ctx.submit(cache[key], None, None, self.table, code)))
+                else:
+                    jobs.append((kind, rs, qb, ctx.submit(self._sets[w][slot], polys, qb, self.table, code)))
         return (w, jobs)
 
     def poll(self, token) -> bool:
@@ -488,7 +517,7 @@ class SpadeExecutor:
         """Worker w's resident device bytes (its context is idle): scratch,
         job result buffers and canvas sets."""
         tot = self.ctxs[w].mem_info()["ctx"]
-        for b in self._sets[w]:
+        for b in self._sets[w] + list(self._cache[w].values()):
             if b is not None:
                 tot += b.info()["device_bytes"]
         self._resident_w[w] = int(tot)
@@ -549,6 +578,10 @@ class SpadeExecutor:
             for b in pair:
                 if b is not None:
                     b.close()
+        for cache in self._cache:
+            for b in cache.values():
+                b.close()
+            cache.clear()
         self.table.close()
         for c in self.ctxs:
             c.close()

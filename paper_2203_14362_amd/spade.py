@@ -529,12 +529,17 @@ class Context:
 
     def submit(self, batch: "Batch", polys, qbound, table: Table, kind: int) -> Job:
         """Asynchronous batch job on this context's worker thread: rebuild
-        ``batch`` from ``polys`` / ``qbound`` and evaluate it over ``table``.
-        The result tensors are copies made on the current stream at wait."""
+        ``batch`` from ``polys`` / ``qbound`` and evaluate it over ``table``
+        (``polys`` None: evaluate ``batch`` as last built).  The result
+        tensors are copies made on the current stream at wait."""
         self._sync_stream()
+        h = ctypes.c_void_p()
+        if polys is None:
+            self._check(self.lib.spade_batch_submit(self.handle, batch.handle, None, 0, None, table.handle,
+                                                    int(kind), ctypes.byref(h)))
+            return Job(self, h, kind, (None, batch, table))
         dp = self.polys(polys)
         qb = np.ascontiguousarray(qbound, dtype=np.int64)
-        h = ctypes.c_void_p()
         self._check(self.lib.spade_batch_submit(self.handle, batch.handle, ctypes.byref(dp.cstruct()),
                                                 int(qb.size - 1), qb.ctypes.data_as(ctypes.c_void_p),
                                                 table.handle, int(kind), ctypes.byref(h)))

@@ -79,3 +79,34 @@ def test_served_equals_alone(ctx):
             want = oracle.join_count(x, y, r.polys)
             assert np.array_equal(r.result.cpu().numpy().astype(np.uint64), want)
     ex.close()
+
+
+def test_keyed_requests_reuse_their_canvas_sets(ctx):
+    """Join-counts keyed by their polygon set: later batches with the same
+    keys are evaluated on the cached canvas sets (no rasterisation), with
+    eviction beyond the cache size, and every result equals the plain call
+    and the oracle."""
+    from paper_2203_14362_amd.serve import Request, Server, SpadeExecutor
+    x, y = gen.mixture_points(1_000_000, seed=5, L=L)
+    dx, dy = _dev(x), _dev(y)
+    sets = [gen.voronoi_jitter(m, 4, 30, seed=60 + m, L=L) for m in (40, 90, 200)]
+    ex = SpadeExecutor(dx, dy, n_workers=2, cached_sets=2)
+    free, _ = torch.cuda.mem_get_info()
+    reqs = []
+    order = [0, 1, 0, 2, 1, 0, 2, 2, 0, 1, 1, 0]
+    for i, k in enumerate(order):
+        # one at a time, so that every batch holds a single keyed request
+        srv = Server(ex, budget_bytes=free // 2).start()
+        r = Request(i, "count", sets[k], key=("tess", k))
+        srv.submit(r)
+        srv.stop()
+        assert r.error is None, r.error
+        reqs.append((k, r))
+    assert ex.cache_hits > 0 and ex.cache_builds > 3   # hits, and rebuilds after evictions
+    assert ex.cache_hits + ex.cache_builds == len(order)
+    for k, r in reqs:
+        assert torch.equal(r.result.cpu(), ctx.join_count(dx, dy, sets[k]).cpu()), r.rid
+    for k in range(3):
+        got = next(r for kk, r in reqs if kk == k).result.cpu().numpy().astype(np.uint64)
+        assert np.array_equal(got, oracle.join_count(x, y, sets[k]))
+    ex.close()
