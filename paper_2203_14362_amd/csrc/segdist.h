@@ -3,11 +3,12 @@
 // around lines and polygon edges (the rounded rectangles of Sec. 4.2).
 //
 // With t = (p - a).(b - a), L = |b - a|^2 and C = cross(b - a, p - a), the
-// point is within distance r iff |p - a| <= r, or |p - b| <= r, or
-// 0 < t < L and C^2 <= r^2 L (for a == b only the first test applies).  The
-// endpoint tests are the exact closed-disk predicate; the sign of t and of
-// (p - b).(a - b) = L - t are decided like an orientation determinant (same
-// a-priori bound, then an expansion from TwoDiff / TwoProduct); the sign of
+// point is within distance r iff |p - a| <= r when t <= 0, |p - b| <= r when
+// t >= L, and C^2 <= r^2 L when 0 < t < L (for a == b the first test
+// alone).  The endpoint tests are the exact closed-disk predicate; the signs
+// of t and of (p - b).(a - b) = L - t are decided like an orientation
+// determinant (same a-priori bound, then an expansion from TwoDiff /
+// TwoProduct); the sign of
 // r^2 L - C^2 is accepted from FP64 values when an interval enclosing C (the
 // orientation bound) and L clears it by a relative 1e-12 margin, and is
 // otherwise rebuilt as an expansion: C and L as expansions of their exact
@@ -173,15 +174,18 @@ __device__ __forceinline__ int perp_sign(double px, double py, const Seg &s, dou
 }
 
 // The closed-distance test of (px, py) against segment s; r2 = fl(r * r).
-// Points with a non-finite coordinate are never within.
+// The nearest point of the segment is a when t <= 0, b when t >= L, else
+// the foot of the perpendicular, whose distance is at most both endpoint
+// distances: so one endpoint disk or the perpendicular test decides (a
+// point segment is its disk).  Points with a non-finite coordinate are never
+// within.
 __device__ __forceinline__ bool seg_near(double px, double py, const Seg &s, double r, double r2)
 {
-    if (in_disk(px, py, s.ax, s.ay, r, r2)) return true;
     if (!(fabs(px) <= 1.7976931348623157e308 && fabs(py) <= 1.7976931348623157e308)) return false;
-    if (s.ax == s.bx && s.ay == s.by) return false;
-    if (in_disk(px, py, s.bx, s.by, r, r2)) return true;
-    if (dot_sign(px, py, s.ax, s.ay, s.bx, s.by) <= 0) return false;   // t <= 0
-    if (dot_sign(px, py, s.bx, s.by, s.ax, s.ay) <= 0) return false;   // t >= L
+    if ((s.ax == s.bx && s.ay == s.by) || dot_sign(px, py, s.ax, s.ay, s.bx, s.by) <= 0)   // t <= 0
+        return in_disk(px, py, s.ax, s.ay, r, r2);
+    if (dot_sign(px, py, s.bx, s.by, s.ax, s.ay) <= 0)                                      // t >= L
+        return in_disk(px, py, s.bx, s.by, r, r2);
     return perp_sign(px, py, s, r, r2) >= 0;
 }
 
