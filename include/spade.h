@@ -197,7 +197,7 @@ int spade_select_disk(spade_ctx *ctx, const spade_points *pts, double cx, double
  * beyond cap the first cap ids are written and SPADE_E_CAPACITY is returned
  * (two-step Map, Sec. 5.1).  The segments are binned into a grid over their
  * box widened by r, which the context keeps in scratch memory;
- * SPADE_E_TOO_LARGE when its cell lists would exceed 2^31 entries (r far
+ * SPADE_E_TOO_LARGE when its cell lists would exceed 2^28 entries (r far
  * larger than the spacing of the segments). */
 int spade_select_near_lines(spade_ctx *ctx, const spade_points *pts, const spade_polys *lines, double r,
                             uint32_t *out_ids, int64_t cap, int64_t *n_out);

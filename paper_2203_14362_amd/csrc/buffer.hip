@@ -122,11 +122,12 @@ __global__ void k_buf_segs(int64_t R, const int64_t *rvo, int64_t V, const doubl
 // of the segment (FP64 distance, with a relative margin of 1e-9 and the
 // absolute part of pad, far above its rounding and that of the point-to-cell
 // mapping), counted (FILL false, with the number of list entries summed into
-// *tot) or listed (FILL true, in per-cell slots from off[] claimed with
-// cursor[]).
+// *tot) or listed (FILL true: a copy of the segment in a per-cell slot from
+// off[] claimed with cursor[], so that a point reads its cell's candidates
+// contiguously, with no index to follow).
 template <bool FILL>
 __global__ void k_buf_bin(int64_t V, const Seg *segs, const uint8_t *valid, BufGrid g, double pad, uint32_t *cnt,
-                          const uint32_t *off, uint32_t *list, unsigned long long *tot)
+                          const uint32_t *off, Seg *list, unsigned long long *tot)
 {
     const int64_t nth = (int64_t)gridDim.x * blockDim.x;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < V; v += nth) {
@@ -148,7 +149,7 @@ __global__ void k_buf_bin(int64_t V, const Seg *segs, const uint8_t *valid, BufG
                 const double dx = px - (s.ax + t * ex), dy = py - (s.ay + t * ey);
                 if (dx * dx + dy * dy > reach2) continue;
                 const int64_t c = (int64_t)cy * g.gx + cx;
-                if (FILL) list[off[c] + atomicAdd(&cnt[c], 1u)] = (uint32_t)v;
+                if (FILL) list[off[c] + atomicAdd(&cnt[c], 1u)] = s;
                 else atomicAdd(&cnt[c], 1u);
                 ++nlisted;
             }
@@ -161,7 +162,7 @@ __global__ void k_buf_bin(int64_t V, const Seg *segs, const uint8_t *valid, BufG
 template <bool POLY>
 __global__ __launch_bounds__(BUF_THREADS) void k_buf_bits(CanvasView cv, int64_t n, const double *X, const double *Y,
                                                           BufGrid g, const Seg *segs, const uint32_t *off,
-                                                          const uint32_t *list, double r, double r2, double pad,
+                                                          const Seg *list, double r, double r2, double pad,
                                                           int64_t nseg, unsigned long long *counts,
                                                           unsigned long long *bits)
 {
@@ -198,7 +199,7 @@ __global__ __launch_bounds__(BUF_THREADS) void k_buf_bits(CanvasView cv, int64_t
             if (!hit && x >= g.X0 && x <= g.X1 && y >= g.Y0 && y <= g.Y1) {
                 const int64_t c = (int64_t)buf_cell(y, g.Y0, g.inv, g.gy) * g.gx + buf_cell(x, g.X0, g.inv, g.gx);
                 for (uint32_t k = off[c], e = off[c + 1]; k < e; ++k) {
-                    const Seg s = segs[list[k]];
+                    const Seg s = list[k];
                     // outside the segment's box widened by pad: farther than r
                     if (x < fmin(s.ax, s.bx) - pad || x > fmax(s.ax, s.bx) + pad ||
                         y < fmin(s.ay, s.by) - pad || y > fmax(s.ay, s.by) + pad)
@@ -283,7 +284,8 @@ int buffer_select(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pt
     // so that rounding never drops a position within r)
     BufGrid grid{0.0, 0.0, -1.0, -1.0, 1.0, 1.0, 1, 1};   // empty box: no point is tested
     double pad = 0.0;
-    uint32_t *off = nullptr, *list = nullptr;
+    uint32_t *off = nullptr;
+    Seg *list = nullptr;
     if (any) {
         const double x0 = buf_from_key(h[0]), x1 = -buf_from_key(h[1]);
         const double y0 = buf_from_key(h[2]), y1 = -buf_from_key(h[3]);
@@ -315,24 +317,24 @@ int buffer_select(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pt
         SPADE_HIP(ctx, hipMemsetAsync(tot, 0, sizeof(unsigned long long), st));
         const int bgrid = (int)std::max<int64_t>(1, std::min<int64_t>((V + 255) / 256, (int64_t)cus * 8));
         hipLaunchKernelGGL(k_buf_bin<false>, dim3(bgrid), dim3(256), 0, st, V, (const Seg *)segs,
-                           (const uint8_t *)valid, grid, pad, cnt, (const uint32_t *)nullptr, (uint32_t *)nullptr,
+                           (const uint8_t *)valid, grid, pad, cnt, (const uint32_t *)nullptr, (Seg *)nullptr,
                            tot);
         SPADE_HIP(ctx, hipGetLastError());
         size_t tb = 0;
         SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(nullptr, tb, cnt, off, (int)(G + 1), st));
         if (ensure(ctx, bt, std::max<size_t>(tb, 1))) return SPADE_E_NOMEM;
         SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(bt.p, tb, cnt, off, (int)(G + 1), st));
-        // the 64-bit entry count first: the cell lists are indexed with 32
-        // bits (the offsets are only used below 2^31 entries)
+        // the 64-bit entry count first: the cell lists (32 bytes an entry)
+        // stay below 2^28 entries, so their 32-bit offsets are exact
         SPADE_HIP(ctx, hipMemcpyAsync(h, tot, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
         SPADE_HIP(ctx, hipStreamSynchronize(st));
-        if (h[0] >= ((unsigned long long)1 << 31))
+        if (h[0] >= ((unsigned long long)1 << 28))
             return set_error(ctx, SPADE_E_TOO_LARGE, "too many (segment, cell) entries: the distance is too large "
                                                      "for the segments' spread");
         const uint64_t total = h[0];
         DevBuf &bl = ctx->scratch[S_BUF_LIST];
-        if (ensure(ctx, bl, sizeof(uint32_t) * (size_t)std::max<uint64_t>(total, 1))) return SPADE_E_NOMEM;
-        list = (uint32_t *)bl.p;
+        if (ensure(ctx, bl, sizeof(Seg) * (size_t)std::max<uint64_t>(total, 1))) return SPADE_E_NOMEM;
+        list = (Seg *)bl.p;
         SPADE_HIP(ctx, hipMemsetAsync(cursor, 0, sizeof(uint32_t) * (size_t)(G + 1), st));
         hipLaunchKernelGGL(k_buf_bin<true>, dim3(bgrid), dim3(256), 0, st, V, (const Seg *)segs,
                            (const uint8_t *)valid, grid, pad, cursor, (const uint32_t *)off, list,
@@ -360,12 +362,12 @@ int buffer_select(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pt
         const int grid_b = (int)std::max<int64_t>(1, std::min<int64_t>((nseg + wpb - 1) / wpb, (int64_t)cus * std::min(per_cu, 2)));
         SPADE_HIP(ctx, hipFuncSetAttribute((const void *)k_buf_bits<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         hipLaunchKernelGGL(k_buf_bits<true>, dim3(grid_b), dim3(BUF_THREADS), lds, st, v, n, pts->x, pts->y, grid,
-                           (const Seg *)segs, (const uint32_t *)off, (const uint32_t *)list, r, r2, pad, nseg, counts,
+                           (const Seg *)segs, (const uint32_t *)off, (const Seg *)list, r, r2, pad, nseg, counts,
                            bits);
     } else {
         const int grid_b = (int)std::max<int64_t>(1, std::min<int64_t>((nseg + wpb - 1) / wpb, (int64_t)cus * 2));
         hipLaunchKernelGGL(k_buf_bits<false>, dim3(grid_b), dim3(BUF_THREADS), 0, st, CanvasView{}, n, pts->x, pts->y,
-                           grid, (const Seg *)segs, (const uint32_t *)off, (const uint32_t *)list, r, r2, pad, nseg,
+                           grid, (const Seg *)segs, (const uint32_t *)off, (const Seg *)list, r, r2, pad, nseg,
                            counts, bits);
     }
     hipLaunchKernelGGL(k_buf_zero, dim3(1), dim3(1), 0, st, counts + nseg);
