@@ -766,7 +766,7 @@ struct RowArgs {
     const CanvasDesc *cds;   // canvases of the set
     int nc;
     int maxW;                // widest canvas (LDS column arrays)
-    int narrow;              // pixel classes in 16 bits (every canvas has < 2^15 polygons)
+    int cls16;              // pixel classes in 16 bits (every canvas has < 2^15 polygons)
     int64_t Htot;            // rows of all canvases
     int cap;                 // entries of one row staged in LDS
     const uint32_t *row_off;
@@ -826,22 +826,22 @@ struct RowShared {
     uint32_t *longq;
     const unsigned long long *nrec;   // records of the row (set by the count phase)
     int W;              // width of the row's canvas
-    bool narrow;        // sx in 16 bits: labels + 1 below 2^15, boundary flag in bit 15
+    bool cls16;        // sx in 16 bits: labels + 1 below 2^15, boundary flag in bit 15
 
-    __device__ __forceinline__ uint32_t sx_flag() const { return narrow ? 0x8000u : BFLAG; }
+    __device__ __forceinline__ uint32_t sx_flag() const { return cls16 ? 0x8000u : BFLAG; }
     __device__ __forceinline__ uint32_t sx_get(int e) const
     {
-        return narrow ? (uint32_t)((const uint16_t *)sx)[e] : ((const uint32_t *)sx)[e];
+        return cls16 ? (uint32_t)((const uint16_t *)sx)[e] : ((const uint32_t *)sx)[e];
     }
     __device__ __forceinline__ void sx_set(int e, uint32_t v) const
     {
-        if (narrow) ((uint16_t *)sx)[e] = (uint16_t)v;
+        if (cls16) ((uint16_t *)sx)[e] = (uint16_t)v;
         else ((uint32_t *)sx)[e] = v;
     }
     // xor into element e (two 16-bit elements share an LDS word)
     __device__ __forceinline__ void sx_xor(int e, uint32_t v) const
     {
-        if (narrow) atomicXor((uint32_t *)sx + (e >> 1), v << ((e & 1) * 16));
+        if (cls16) atomicXor((uint32_t *)sx + (e >> 1), v << ((e & 1) * 16));
         else atomicXor((uint32_t *)sx + e, v);
     }
 };
@@ -1104,16 +1104,16 @@ __device__ void all_column_records(const RowArgs &A, const RowData &D, const Row
     }
 }
 
-// 32-bit words of the pixel-class column array (16-bit elements when narrow).
-__host__ __device__ inline int sx_words(int cw, bool narrow) { return narrow ? (cw + 1) / 2 : cw; }
+// 32-bit words of the pixel-class column array (16-bit elements when cls16).
+__host__ __device__ inline int sx_words(int cw, bool cls16) { return cls16 ? (cw + 1) / 2 : cw; }
 
 // Dynamic LDS: three padded column arrays (the pixel classes in 16 bits when
-// narrow), then `cap` staged entries with their auxiliary words and up to
+// 16-bit), then `cap` staged entries with their auxiliary words and up to
 // `cap` footprint intervals.
-__host__ __device__ inline size_t row_lds_bytes(int W, int cap, bool narrow)
+__host__ __device__ inline size_t row_lds_bytes(int W, int cap, bool cls16)
 {
     const int cw = col_words(W);
-    return (size_t)(2 * cw + sx_words(cw, narrow)) * 4 + (size_t)cap * 37 + 32;
+    return (size_t)(2 * cw + sx_words(cw, cls16)) * 4 + (size_t)cap * 37 + 32;
 }
 
 // Phase 1 for one run by one thread: footprint counts, interior spans with
@@ -1423,13 +1423,13 @@ __global__ __launch_bounds__(ROW_THREADS_MAX) void k_rows(RowArgs A)
     L.sa = (int32_t *)smem;
     L.sb = L.sa + cwmax;
     L.sx = (void *)(L.sb + cwmax);
-    L.narrow = A.narrow != 0;
+    L.cls16 = A.cls16 != 0;
     L.locfill = &s_locfill;
     L.nint = &s_nint;
     L.nlong = &s_nlong;
     L.longq = s_longq;
     L.nrec = &s_nrec;
-    uint32_t *lpoly = (uint32_t *)(L.sb + cwmax) + sx_words(cwmax, L.narrow);
+    uint32_t *lpoly = (uint32_t *)(L.sb + cwmax) + sx_words(cwmax, L.cls16);
     uint32_t *lc = lpoly + cap;
     uint32_t *ledge = lc + cap;
     uint32_t *lpm = ledge + cap;
@@ -2022,12 +2022,12 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
 
     // LDS stage of the row kernel: up to `cap` entries of a row; narrow
     // canvases aim for three or four workgroups per CU, wider ones for two
-    // (measured best).
-    // pixel classes in 16 bits when every label + 1 fits in 15
+    // (measured best).  Pixel classes take 16 bits when every label + 1 fits
+    // in 15.
     int64_t maxM_all = 1;
     for (int q = 0; q < nc; ++q) maxM_all = std::max<int64_t>(maxM_all, cds[q].M);
-    const bool narrow = maxM_all < 0x8000;
-    const size_t col_bytes = row_lds_bytes(W, 0, narrow);
+    const bool cls16 = maxM_all < 0x8000;
+    const size_t col_bytes = row_lds_bytes(W, 0, cls16);
     const size_t target = (col_bytes <= 40 * 1024) ? 38 * 1024 : (col_bytes <= 60 * 1024) ? 78 * 1024 : 150 * 1024;
     const int cap = (int)std::max<size_t>(256, (target - std::min(target - 256 * 37, col_bytes)) / 37);
     // rows up to capB entries run in the launch over all rows, taken first,
@@ -2172,10 +2172,10 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
     ra.rec_base = rec_base; ra.loc_base = loc_base; ra.part_base = part_base;
     ra.errflags = d_err;
     ra.cap = cap;
-    ra.narrow = narrow ? 1 : 0;
-    const size_t rlds = row_lds_bytes(W, ra.cap, narrow);
+    ra.cls16 = cls16 ? 1 : 0;
+    const size_t rlds = row_lds_bytes(W, ra.cap, cls16);
     // the longest rows: a stage for the longest of them, up to 150 KB
-    const size_t rlds_big = row_lds_bytes(W, cap_big, narrow);
+    const size_t rlds_big = row_lds_bytes(W, cap_big, cls16);
     if (maxrow > (uint64_t)cap_big || nlistB > 0) {
         // rows without a stage: global auxiliary words for them
         if (ensure(ctx, ctx->scratch[S_NEXTP], sizeof(uint32_t) * 6 * Ts)) return SPADE_E_NOMEM;
@@ -2300,7 +2300,7 @@ int build_set(spade_ctx *ctx, const spade_polys *polys, int nc, const int64_t *p
         put((uint64_t)cbits); put((uint64_t)pbits); put((uint64_t)kbits); put(tbytes); put(tscan);
         put(bucketed ? 1 : 0); put(entries_done ? 1 : 0); put((uint64_t)ebits); put(sort_lds); put(nlistB); put(nlistC);
         put((uint64_t)capB); put((uint64_t)rstride);
-        put((uint64_t)ra.cap); put((uint64_t)cap_big); put(rlds); put(rlds_big); put((uint64_t)ra.narrow);
+        put((uint64_t)ra.cap); put((uint64_t)cap_big); put(rlds); put(rlds_big); put((uint64_t)ra.cls16);
         put((uint64_t)compact_mode);
         put(ra.cap_rec); put(ra.cap_loc); put(ra.cap_part);
         putp(cv->edges.p); putp(epoly); putp(erow0); putp(nrows); putp(eoff); putp(d_cds);
