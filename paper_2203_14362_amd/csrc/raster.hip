@@ -1107,8 +1107,8 @@ __device__ void all_column_records(const RowArgs &A, const RowData &D, const Row
 // 32-bit words of the pixel-class column array (16-bit elements when cls16).
 __host__ __device__ inline int sx_words(int cw, bool cls16) { return cls16 ? (cw + 1) / 2 : cw; }
 
-// Dynamic LDS: three padded column arrays (the pixel classes in 16 bits when
-// 16-bit), then `cap` staged entries with their auxiliary words and up to
+// Dynamic LDS: three padded column arrays (the pixel classes in 16 bits with
+// cls16), then `cap` staged entries with their auxiliary words and up to
 // `cap` footprint intervals.
 __host__ __device__ inline size_t row_lds_bytes(int W, int cap, bool cls16)
 {
