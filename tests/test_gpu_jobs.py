@@ -128,3 +128,24 @@ def test_job_loop_allocates_nothing_after_first_round(data):
     t.close()
     b.close()
     c.close()
+
+
+def test_query_only_jobs_reuse_the_built_set(ctx, data):
+    """A job submitted without polygons evaluates the set as last built: the
+    same results as the job that rebuilt it, for selections and counts."""
+    x, y, stars, qb, tess = data
+    dx, dy = _dev(x), _dev(y)
+    t = ctx.table(dx, dy)
+    tp, tqb = _one_set(tess)
+    bs, bc = ctx.batch(stars, qb), ctx.batch(tp, tqb)
+    ids, off = ctx.submit(bs, stars, qb, t, JOB_SELECT).wait()
+    counts = ctx.submit(bc, tp, tqb, t, JOB_COUNT).wait()
+    for rep in range(2):
+        ids2, off2 = ctx.submit(bs, None, None, t, JOB_SELECT).wait()
+        counts2 = ctx.submit(bc, None, None, t, JOB_COUNT).wait()
+        assert np.array_equal(off, off2) and torch.equal(ids, ids2)
+        assert torch.equal(counts, counts2)
+    assert np.array_equal(counts.cpu().numpy().astype(np.uint64), oracle.join_count(x, y, tess))
+    bs.close()
+    bc.close()
+    t.close()
