@@ -29,6 +29,10 @@ by), or whose magnitudes leave the safe range, is decided again with
 Geometry uses the polygon-set CSR layout (``ring_vtx_off``, ``vx``, ``vy``).
 As lines, every ring is an open polyline (segments between consecutive
 vertices; a one-vertex ring is a point); as a polygon, rings are closed.
+
+The distance join with lines (Sec. 5.2, types (1) and (2)) takes every ring
+as one line object: the pairs (point, line) of every point within r (one
+distance, or one per line) of that line, ascending by (point, line).
 """
 from __future__ import annotations
 
@@ -195,3 +199,31 @@ def seg_within_clamped(px, py, ax, ay, bx, by, r) -> bool:
     s = Fraction(0) if L == 0 else min(Fraction(1), max(Fraction(0), ((P[0] - A[0]) * ex + (P[1] - A[1]) * ey) / L))
     qx, qy = A[0] + s * ex, A[1] + s * ey
     return (P[0] - qx) ** 2 + (P[1] - qy) ** 2 <= Fraction(r) * Fraction(r)
+
+
+def distance_join_lines(x, y, lines, r):
+    """Distance join of the points with a set of lines (Sec. 5.2, types (1)
+    and (2)): (point ids, line ids) int64, ascending by (point, line), of
+    every point within distance r[j] (or the scalar r) of line j, ring j of
+    the CSR set as an open polyline.  One exact selection per line."""
+    rvo = np.asarray(lines["ring_vtx_off"], dtype=np.int64)
+    nl = rvo.size - 1
+    rr = np.broadcast_to(np.asarray(r, dtype=np.float64), (nl,))
+    pts, lns = [], []
+    for j in range(nl):
+        one = {"ring_vtx_off": np.array([0, rvo[j + 1] - rvo[j]]),
+               "vx": np.asarray(lines["vx"])[rvo[j]:rvo[j + 1]], "vy": np.asarray(lines["vy"])[rvo[j]:rvo[j + 1]]}
+        ids = select_near_lines(x, y, one, float(rr[j]))
+        pts.append(ids)
+        lns.append(np.full(ids.size, j, dtype=np.int64))
+    if not pts:
+        return np.zeros(0, np.int64), np.zeros(0, np.int64)
+    p = np.concatenate(pts)
+    q = np.concatenate(lns)
+    order = np.lexsort((q, p))
+    return p[order], q[order]
+
+
+def distance_join_lines_count(x, y, lines, r):
+    _, q = distance_join_lines(x, y, lines, r)
+    return np.bincount(q, minlength=np.asarray(lines["ring_vtx_off"]).size - 1).astype(np.uint64)

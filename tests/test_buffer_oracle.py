@@ -140,3 +140,40 @@ def test_lines_and_polygon_composition():
     zero = np.zeros(x.size, bool)
     zero[B.select_within_polygon(x, y, sq, 0.0)] = True
     assert zero[0] and zero[2] and not zero[1]
+
+
+def test_line_join_pins():
+    """The line join against the disk join (point lines), the line selection
+    (one line), and type (2) with equal radii against type (1)."""
+    rng = np.random.default_rng(12)
+    x = rng.uniform(0, 50, 20000)
+    y = rng.uniform(0, 50, 20000)
+    cx, cy = rng.uniform(0, 50, 30), rng.uniform(0, 50, 30)
+    pts_lines = {"ring_vtx_off": np.arange(31), "vx": cx, "vy": cy}
+    a = B.distance_join_lines(x, y, pts_lines, 2.5)
+    b = D.distance_join(x, y, cx, cy, 2.5)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    rad = rng.uniform(0.5, 4.0, 30)
+    a = B.distance_join_lines(x, y, pts_lines, rad)
+    b = D.distance_join(x, y, cx, cy, rad)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    line = {"ring_vtx_off": np.array([0, 4]), "vx": np.array([1.0, 20.0, 30.0, 45.0]),
+            "vy": np.array([1.0, 30.0, 5.0, 40.0])}
+    p, q = B.distance_join_lines(x, y, line, 1.5)
+    assert np.array_equal(p, B.select_near_lines(x, y, line, 1.5)) and (q == 0).all()
+    lines = gen_lines(rng)
+    a = B.distance_join_lines(x, y, lines, 1.0)
+    b = B.distance_join_lines(x, y, lines, np.full(lines["ring_vtx_off"].size - 1, 1.0))
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    c = B.distance_join_lines_count(x, y, lines, 1.0)
+    assert c.sum() == a[0].size and (np.diff(a[0]) >= 0).all()
+
+
+def gen_lines(rng):
+    rings, off = [], [0]
+    for k in range(12):
+        n = int(rng.integers(1, 6))
+        rings.append(rng.uniform(0, 50, (n, 2)))
+        off.append(off[-1] + n)
+    v = np.concatenate(rings)
+    return {"ring_vtx_off": np.array(off), "vx": v[:, 0], "vy": v[:, 1]}
