@@ -211,6 +211,29 @@ int spade_select_near_lines(spade_ctx *ctx, const spade_points *pts, const spade
 int spade_select_within_polygon(spade_ctx *ctx, const spade_points *pts, const spade_polys *poly, double r,
                                 uint32_t *out_ids, int64_t cap, int64_t *n_out);
 
+/* Distance join of the points with a set of lines (Sec. 5.2, "Distance-Based
+ * Queries", join types (1) and (2) with lines as the constraint dataset):
+ * every ring j of `lines` is line j, an open polyline as for
+ * spade_select_near_lines; r (device, may be NULL) holds one distance per
+ * line (type 2), else r_all applies to every line (type 1).  The pairs
+ * (point, line) of every point within closed distance r_j of line j, decided
+ * exactly, ascending by point id then line id, into out_pt / out_line
+ * (device, capacity cap); *n_out (host, may be NULL) receives the number of
+ * pairs, and beyond cap the first cap pairs are written and SPADE_E_CAPACITY
+ * is returned.  Distances must be finite and >= 0, vertices finite and the
+ * offsets valid (SPADE_E_INVALID); fewer than 2^31 - 1 lines
+ * (SPADE_E_TOO_LARGE); SPADE_E_TOO_LARGE also when the grid's cell lists
+ * would exceed 2^26 entries (distances far larger than the spacing of the
+ * segments). */
+int spade_distance_join_lines_pairs(spade_ctx *ctx, const spade_points *pts, const spade_polys *lines,
+                                    const double *r, double r_all, uint32_t *out_pt, uint32_t *out_line, int64_t cap,
+                                    int64_t *n_out);
+
+/* Aggregation over the same join: out_counts [n_rings] (device, overwritten)
+ * receives the number of points within each line's distance. */
+int spade_distance_join_lines_count(spade_ctx *ctx, const spade_points *pts, const spade_polys *lines,
+                                    const double *r, double r_all, uint64_t *out_counts);
+
 /* Disks (device pointers): centres (cx[j], cy[j]) and radii r[j] (type-2
  * distance join), or one radius r_all for every disk when r is NULL (type
  * 1).  Disk ids are 0-based positions (n < 2^31 - 1). */

@@ -391,4 +391,432 @@ int buffer_select(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pt
     return SPADE_OK;
 }
 
+
+// ------------------------------------------------------------ distance join with lines
+//
+// Sec. 5.2's distance joins of types (1) and (2) with lines as the
+// constraint dataset: every ring of the line set is one line object j (an
+// open polyline) with its distance r_j (type 2) or one distance for all
+// (type 1), and the join returns the pairs (point, line) of the points within
+// r_j of line j.  The segments, each with its line and distance, are binned
+// as for the selection; each cell's list is then sorted by segment id, so
+// that a line's segments are consecutive in it and a point meets each of its
+// lines once, in ascending line order: the first segment of a line within
+// that line's distance emits the pair, the rest of the line is skipped.
+
+struct JSeg {
+    double ax, ay, bx, by, r;
+    uint32_t line, pad_;
+};
+
+// Segment slot v of a set of open polylines: its line (ring) and far end,
+// or false (last vertex of a ring, or malformed offsets: err bit 1).
+__device__ __forceinline__ bool line_seg_of(int64_t R, const int64_t *rvo, int64_t V, int64_t v, int64_t &ring,
+                                            int64_t &w, unsigned *err)
+{
+    int64_t lo = 0, hi = R - 1;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (rvo[mid] <= v) lo = mid; else hi = mid - 1;
+    }
+    const int64_t o = rvo[lo], e = rvo[lo + 1];
+    if (!(o >= 0 && o <= v && v < e && e <= V)) {
+        atomicOr(err, 1u);
+        return false;
+    }
+    ring = lo;
+    if (e - o == 1) w = v;
+    else if (v + 1 < e) w = v + 1;
+    else return false;
+    return true;
+}
+
+// Segments with their line and distance; validates offsets (err bit 1),
+// vertices (bit 2) and distances (bit 4); reduces the segments' box into bb
+// and the largest distance into bb[7] (as the ordered key of -r).
+__global__ void k_bufj_segs(int64_t R, const int64_t *rvo, int64_t V, const double *vx, const double *vy,
+                            const double *rline, double r_all, JSeg *segs, uint8_t *valid,
+                            unsigned long long *bb, unsigned *err, double *len)
+{
+    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t k = gid; k <= R; k += nth) {
+        const int64_t o = rvo[k];
+        if ((k == 0 && o != 0) || (k == R && o != V) || (k < R && rvo[k + 1] < o)) atomicOr(err, 1u);
+        if (k < R && rline && !(isfinite(rline[k]) && rline[k] >= 0.0)) atomicOr(err, 4u);
+    }
+    unsigned long long k0 = ~0ull, k1 = ~0ull, k2 = ~0ull, k3 = ~0ull, kr = ~0ull;
+    double lsum = 0.0;
+    for (int64_t v = gid; v < V; v += nth) {
+        valid[v] = 0;
+        int64_t ring, w;
+        if (!line_seg_of(R, rvo, V, v, ring, w, err)) continue;
+        const double ax = vx[v], ay = vy[v], bx = vx[w], by = vy[w];
+        const double r = rline ? rline[ring] : r_all;
+        if (!(isfinite(ax) && isfinite(ay) && isfinite(bx) && isfinite(by))) {
+            atomicOr(err, 2u);
+            continue;
+        }
+        if (!(isfinite(r) && r >= 0.0)) continue;   // reported through bit 4
+        segs[v] = JSeg{ax, ay, bx, by, r, (uint32_t)ring, 0u};
+        valid[v] = 1;
+        lsum += hypot(bx - ax, by - ay);
+        k0 = min(k0, min(buf_key(ax), buf_key(bx))); k1 = min(k1, min(buf_key(-ax), buf_key(-bx)));
+        k2 = min(k2, min(buf_key(ay), buf_key(by))); k3 = min(k3, min(buf_key(-ay), buf_key(-by)));
+        kr = min(kr, buf_key(-r));
+    }
+    for (int d = 32; d > 0; d >>= 1) {
+        k0 = min(k0, (unsigned long long)__shfl_xor((long long)k0, d, 64));
+        k1 = min(k1, (unsigned long long)__shfl_xor((long long)k1, d, 64));
+        k2 = min(k2, (unsigned long long)__shfl_xor((long long)k2, d, 64));
+        k3 = min(k3, (unsigned long long)__shfl_xor((long long)k3, d, 64));
+        kr = min(kr, (unsigned long long)__shfl_xor((long long)kr, d, 64));
+        lsum += __shfl_xor(lsum, d, 64);
+    }
+    if ((threadIdx.x & 63) == 0 && k0 != ~0ull) {
+        atomicMin(&bb[0], k0); atomicMin(&bb[1], k1); atomicMin(&bb[2], k2); atomicMin(&bb[3], k3);
+        atomicMin(&bb[7], kr);
+        atomicAdd(len, lsum);
+    }
+}
+
+// Cells that may hold a point within a segment's own distance of it (as
+// k_buf_bin, with the segment's pad r (1 + 2^-40) + magpad): counted
+// (FILL false, entries summed into *tot) or listed as sort keys
+// (cell << 32 | segment) with the segment as value.
+template <bool FILL>
+__global__ void k_bufj_bin(int64_t V, const JSeg *segs, const uint8_t *valid, BufGrid g, double magpad,
+                           uint32_t *cnt, const uint32_t *off, unsigned long long *keys, uint32_t *vals,
+                           unsigned long long *tot)
+{
+    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < V; v += nth) {
+        if (!valid[v]) continue;
+        const JSeg s = segs[v];
+        const double pad = s.r * (1.0 + 0x1p-40) + magpad;
+        const int x0 = buf_cell(fmin(s.ax, s.bx) - pad, g.X0, g.inv, g.gx);
+        const int x1 = buf_cell(fmax(s.ax, s.bx) + pad, g.X0, g.inv, g.gx);
+        const int y0 = buf_cell(fmin(s.ay, s.by) - pad, g.Y0, g.inv, g.gy);
+        const int y1 = buf_cell(fmax(s.ay, s.by) + pad, g.Y0, g.inv, g.gy);
+        const double ex = s.bx - s.ax, ey = s.by - s.ay, l2 = ex * ex + ey * ey;
+        const double reach = (pad + 0.7071067811865476 * g.cell) * (1.0 + 1e-9);
+        const double reach2 = reach * reach;
+        unsigned long long nlisted = 0;
+        for (int cy = y0; cy <= y1; ++cy)
+            for (int cx = x0; cx <= x1; ++cx) {
+                const double px = g.X0 + (cx + 0.5) * g.cell, py = g.Y0 + (cy + 0.5) * g.cell;
+                double t = l2 > 0.0 ? ((px - s.ax) * ex + (py - s.ay) * ey) / l2 : 0.0;
+                t = fmin(fmax(t, 0.0), 1.0);
+                const double dx = px - (s.ax + t * ex), dy = py - (s.ay + t * ey);
+                if (dx * dx + dy * dy > reach2) continue;
+                const int64_t c = (int64_t)cy * g.gx + cx;
+                if (FILL) {
+                    const uint32_t at = off[c] + atomicAdd(&cnt[c], 1u);
+                    keys[at] = ((unsigned long long)c << 32) | (unsigned long long)v;
+                    vals[at] = (uint32_t)v;
+                } else {
+                    atomicAdd(&cnt[c], 1u);
+                }
+                ++nlisted;
+            }
+        if (!FILL) atomicAdd(tot, nlisted);
+    }
+}
+
+// Cell lists in sorted order: copies of the segments.
+__global__ void k_bufj_gather(int64_t ntot, const uint32_t *vals, const JSeg *segs, JSeg *list)
+{
+    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ntot; i += nth) list[i] = segs[vals[i]];
+}
+
+// Calls hit(line) for each line within its distance of (x, y), in
+// ascending line order, each line once.
+template <typename Hit>
+__device__ __forceinline__ void bufj_walk(double x, double y, const BufGrid &g, const uint32_t *off,
+                                          const JSeg *list, double magpad, Hit &&hit)
+{
+    if (!(x >= g.X0 && x <= g.X1 && y >= g.Y0 && y <= g.Y1)) return;   // NaN fails too
+    const int64_t c = (int64_t)buf_cell(y, g.Y0, g.inv, g.gy) * g.gx + buf_cell(x, g.X0, g.inv, g.gx);
+    uint32_t last = 0xffffffffu;
+    for (uint32_t k = off[c], e = off[c + 1]; k < e; ++k) {
+        const JSeg s = list[k];
+        if (s.line == last) continue;   // this line is already paired with the point
+        const double pad = s.r * (1.0 + 0x1p-40) + magpad;
+        if (x < fmin(s.ax, s.bx) - pad || x > fmax(s.ax, s.bx) + pad || y < fmin(s.ay, s.by) - pad ||
+            y > fmax(s.ay, s.by) + pad)
+            continue;
+        if (seg_near(x, y, Seg{s.ax, s.ay, s.bx, s.by}, s.r, s.r * s.r)) {
+            hit(s.line);
+            last = s.line;
+        }
+    }
+}
+
+// MODE 0: pairs per 1024-point segment (counts[sg]); MODE 1: the pairs, from
+// offs[sg] on (below cap; the first cap in (point, line) order); MODE 2:
+// pairs per line added into lcount (an LDS histogram when nlines <= hist).
+template <int MODE>
+__global__ __launch_bounds__(BUF_THREADS) void k_bufj_pairs(int64_t n, const double *X, const double *Y, BufGrid g,
+                                                            const uint32_t *off, const JSeg *list, double magpad,
+                                                            int64_t nseg, unsigned long long *counts,
+                                                            const unsigned long long *offs, uint32_t *out_pt,
+                                                            uint32_t *out_line, int64_t cap,
+                                                            unsigned long long *lcount, int nlines, int hist)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint32_t *h = (uint32_t *)smem;
+    const bool lds = MODE == 2 && nlines <= hist;
+    if (lds) {
+        for (int k = threadIdx.x; k < nlines; k += BUF_THREADS) h[k] = 0u;
+        __syncthreads();
+    }
+    const int lane = threadIdx.x & 63;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const int64_t nwave = ((int64_t)gridDim.x * BUF_THREADS) >> 6;
+    for (int64_t sg = ((int64_t)blockIdx.x * BUF_THREADS + threadIdx.x) >> 6; sg < nseg; sg += nwave) {
+        unsigned long long total = 0;
+        int64_t pos = MODE == 1 ? (int64_t)offs[sg] : 0;
+        for (int j = 0; j < BUF_WORDS; ++j) {
+            const int64_t i = sg * EMIT_SEG + 64 * j + lane;
+            const double x = i < n ? __builtin_nontemporal_load(X + i) : NAN;
+            const double y = i < n ? __builtin_nontemporal_load(Y + i) : NAN;
+            uint32_t cnt = 0;
+            if (MODE == 2) {
+                bufj_walk(x, y, g, off, list, magpad, [&](uint32_t line) {
+                    if (lds) atomicAdd(&h[line], 1u);
+                    else atomicAdd(&lcount[line], 1ull);
+                });
+                continue;
+            }
+            bufj_walk(x, y, g, off, list, magpad, [&](uint32_t) { ++cnt; });
+            // the wavefront's pairs of this word, in lane order
+            uint32_t pre = cnt;
+            for (int d = 1; d < 64; d <<= 1) {
+                const uint32_t t = (uint32_t)__shfl_up((int)pre, d, 64);
+                if (lane >= d) pre += t;
+            }
+            const uint32_t wsum = (uint32_t)__shfl((int)pre, 63, 64);
+            if (MODE == 1 && cnt) {
+                int64_t p = pos + (int64_t)(pre - cnt);
+                bufj_walk(x, y, g, off, list, magpad, [&](uint32_t line) {
+                    if (p < cap) {
+                        out_pt[p] = (uint32_t)i;
+                        out_line[p] = line;
+                    }
+                    ++p;
+                });
+            }
+            pos += wsum;
+            total += wsum;
+        }
+        if (MODE == 0 && lane == 0) counts[sg] = total;
+    }
+    if (lds) {
+        __syncthreads();
+        for (int k = threadIdx.x; k < nlines; k += BUF_THREADS)
+            if (h[k]) atomicAdd(&lcount[k], (unsigned long long)h[k]);
+    }
+}
+
+__global__ void k_bufj_zero(int64_t n, unsigned long long *p)
+{
+    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += nth) p[i] = 0ull;
+}
+
+int buffer_join_lines(spade_ctx *ctx, const spade_points *pts, const spade_polys *lines, const double *r,
+                      double r_all, uint32_t *out_pt, uint32_t *out_line, int64_t cap, int64_t *n_out,
+                      uint64_t *out_counts)
+{
+    hipStream_t st = ctx->stream;
+    if (n_out) *n_out = 0;
+    const bool counting = out_counts != nullptr;
+    if (!r && !(std::isfinite(r_all) && r_all >= 0.0))
+        return set_error(ctx, SPADE_E_INVALID, "the distance must be finite and >= 0");
+    if (!counting) {
+        if (cap < 0) return set_error(ctx, SPADE_E_INVALID, "negative capacity");
+        if (cap > 0 && (!out_pt || !out_line)) return set_error(ctx, SPADE_E_INVALID, "output array is NULL");
+    }
+    if (!lines) return set_error(ctx, SPADE_E_INVALID, "line set is NULL");
+    const int64_t R = lines->n_rings;
+    if (R < 0) return set_error(ctx, SPADE_E_INVALID, "negative ring count");
+    if (R >= 0x7fffffffLL) return set_error(ctx, SPADE_E_TOO_LARGE, "line ids must be < 2^31 - 1");
+    if (R > 0 && (!lines->ring_vtx_off || !lines->vx || !lines->vy))
+        return set_error(ctx, SPADE_E_INVALID, "line array is NULL");
+    int64_t V = 0;
+    if (R > 0) {
+        if (lines->n_vertices > 0) {
+            V = lines->n_vertices;
+        } else {
+            int64_t *hv = (int64_t *)ensure_pinned(ctx, 64);
+            if (!hv) return set_error(ctx, SPADE_E_NOMEM, "pinned staging allocation failed");
+            SPADE_HIP(ctx, hipMemcpyAsync(hv, lines->ring_vtx_off + R, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+            SPADE_HIP(ctx, hipStreamSynchronize(st));
+            V = hv[0];
+        }
+        if (V < 0 || V >= (int64_t)0xffffffffLL) return set_error(ctx, SPADE_E_INVALID, "bad vertex count");
+    }
+    const int64_t n = pts->n;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || cus <= 0)
+        cus = 256;
+    if (counting && R > 0)
+        hipLaunchKernelGGL(k_bufj_zero, dim3((unsigned)std::min<int64_t>((R + 255) / 256, 4096)), dim3(256), 0, st, R,
+                           (unsigned long long *)out_counts);
+
+    DevBuf &bs = ctx->scratch[S_BUF_SEGS], &bg = ctx->scratch[S_BUF_GRID];
+    if (ensure(ctx, bs, sizeof(JSeg) * (size_t)std::max<int64_t>(V, 1) + (size_t)V + 16) || ensure(ctx, bg, 256))
+        return SPADE_E_NOMEM;
+    JSeg *segs = (JSeg *)bs.p;
+    uint8_t *valid = (uint8_t *)(segs + std::max<int64_t>(V, 1));
+    unsigned long long *bb = (unsigned long long *)bg.p;
+    unsigned *err = (unsigned *)(bb + 4);
+    double *dlen = (double *)(bb + 6);
+    SPADE_HIP(ctx, hipMemsetAsync(bb, 0xff, 8 * sizeof(unsigned long long), st));
+    SPADE_HIP(ctx, hipMemsetAsync(bb + 4, 0, 3 * sizeof(unsigned long long), st));
+    if (R > 0) {
+        const int sgrid = (int)std::max<int64_t>(1, std::min<int64_t>((std::max(V, R + 1) + 255) / 256, (int64_t)cus * 8));
+        hipLaunchKernelGGL(k_bufj_segs, dim3(sgrid), dim3(256), 0, st, R, lines->ring_vtx_off, V, lines->vx, lines->vy,
+                           r, r_all, segs, valid, bb, err, dlen);
+        SPADE_HIP(ctx, hipGetLastError());
+    }
+    unsigned long long *h = (unsigned long long *)ensure_pinned(ctx, 64);
+    if (!h) return set_error(ctx, SPADE_E_NOMEM, "pinned staging allocation failed");
+    SPADE_HIP(ctx, hipMemcpyAsync(h, bb, 8 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    SPADE_HIP(ctx, hipStreamSynchronize(st));
+    const unsigned ef = (unsigned)(h[4] & 0xffffffffu);
+    if (ef & 1u) return set_error(ctx, SPADE_E_INVALID, "ring offsets are not a valid CSR array");
+    if (ef & 2u) return set_error(ctx, SPADE_E_INVALID, "a vertex coordinate is not finite");
+    if (ef & 4u) return set_error(ctx, SPADE_E_INVALID, "a line's distance is not finite and >= 0");
+    const bool any = h[0] != ~0ull;
+    double len_sum;
+    std::memcpy(&len_sum, &h[6], sizeof len_sum);
+    const double rmax = any ? -buf_from_key(h[7]) : 0.0;
+    if (n == 0) return SPADE_OK;
+
+    BufGrid grid{0.0, 0.0, -1.0, -1.0, 1.0, 1.0, 1, 1};   // empty box: no point is tested
+    double magpad = 0.0;
+    uint32_t *off = nullptr;
+    JSeg *list = nullptr;
+    if (any) {
+        const double x0 = buf_from_key(h[0]), x1 = -buf_from_key(h[1]);
+        const double y0 = buf_from_key(h[2]), y1 = -buf_from_key(h[3]);
+        const double mag = std::fabs(x0) + std::fabs(x1) + std::fabs(y0) + std::fabs(y1);
+        magpad = mag * 0x1p-40 + 1e-300;
+        const double pad = rmax * (1.0 + 0x1p-40) + magpad;
+        const double X0 = x0 - pad, X1 = x1 + pad, Y0 = y0 - pad, Y1 = y1 + pad;
+        const double w = X1 - X0, hgt = Y1 - Y0;
+        const double lmean = std::isfinite(len_sum) ? len_sum / (double)std::max<int64_t>(V, 1) : 0.0;
+        double cell = std::max(rmax, std::min(lmean, std::sqrt(w * hgt / (2.0 * (double)std::max<int64_t>(V, 1)))));
+        cell = std::max(cell, std::max(w, hgt) / BUF_GRID_MAX);
+        if (!(cell > 1e-290)) cell = 1.0;
+        grid.X0 = X0; grid.Y0 = Y0; grid.X1 = X1; grid.Y1 = Y1;
+        grid.inv = 1.0 / cell;
+        grid.cell = cell;
+        grid.gx = (int)std::min<double>(BUF_GRID_MAX, std::max(1.0, std::ceil(w * grid.inv)));
+        grid.gy = (int)std::min<double>(BUF_GRID_MAX, std::max(1.0, std::ceil(hgt * grid.inv)));
+        const int64_t G = (int64_t)grid.gx * grid.gy;
+        if (ensure(ctx, bg, 256 + sizeof(uint32_t) * 3 * (size_t)(G + 1))) return SPADE_E_NOMEM;
+        bb = (unsigned long long *)bg.p;
+        uint32_t *cnt = (uint32_t *)((unsigned char *)bg.p + 256);
+        off = cnt + (G + 1);
+        uint32_t *cursor = off + (G + 1);
+        unsigned long long *tot = bb + 5;
+        SPADE_HIP(ctx, hipMemsetAsync(cnt, 0, sizeof(uint32_t) * (size_t)(G + 1), st));
+        SPADE_HIP(ctx, hipMemsetAsync(tot, 0, sizeof(unsigned long long), st));
+        const int bgrid = (int)std::max<int64_t>(1, std::min<int64_t>((V + 255) / 256, (int64_t)cus * 8));
+        hipLaunchKernelGGL(k_bufj_bin<false>, dim3(bgrid), dim3(256), 0, st, V, (const JSeg *)segs,
+                           (const uint8_t *)valid, grid, magpad, cnt, (const uint32_t *)nullptr,
+                           (unsigned long long *)nullptr, (uint32_t *)nullptr, tot);
+        SPADE_HIP(ctx, hipGetLastError());
+        DevBuf &bt = ctx->scratch[S_BUF_TMP];
+        size_t tb = 0;
+        SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(nullptr, tb, cnt, off, (int)(G + 1), st));
+        if (ensure(ctx, bt, std::max<size_t>(tb, 1))) return SPADE_E_NOMEM;
+        SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(bt.p, tb, cnt, off, (int)(G + 1), st));
+        SPADE_HIP(ctx, hipMemcpyAsync(h, tot, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+        SPADE_HIP(ctx, hipStreamSynchronize(st));
+        if (h[0] >= ((unsigned long long)1 << 26))
+            return set_error(ctx, SPADE_E_TOO_LARGE, "too many (segment, cell) entries: the distances are too "
+                                                     "large for the segments' spread");
+        const int64_t total = (int64_t)h[0];
+        // cell lists: sort keys and values, sorted copies of the segments
+        DevBuf &bl = ctx->scratch[S_BUF_LIST];
+        const size_t keyb = sizeof(unsigned long long) * (size_t)std::max<int64_t>(total, 1);
+        const size_t valb = sizeof(uint32_t) * (size_t)std::max<int64_t>(total, 1);
+        const size_t listb = sizeof(JSeg) * (size_t)std::max<int64_t>(total, 1);
+        if (ensure(ctx, bl, 2 * keyb + 2 * valb + listb + 64)) return SPADE_E_NOMEM;
+        unsigned long long *k1 = (unsigned long long *)bl.p, *k2 = k1 + std::max<int64_t>(total, 1);
+        uint32_t *v1 = (uint32_t *)(k2 + std::max<int64_t>(total, 1)), *v2 = v1 + std::max<int64_t>(total, 1);
+        list = (JSeg *)(((uintptr_t)(v2 + std::max<int64_t>(total, 1)) + 15) & ~(uintptr_t)15);
+        SPADE_HIP(ctx, hipMemsetAsync(cursor, 0, sizeof(uint32_t) * (size_t)(G + 1), st));
+        hipLaunchKernelGGL(k_bufj_bin<true>, dim3(bgrid), dim3(256), 0, st, V, (const JSeg *)segs,
+                           (const uint8_t *)valid, grid, magpad, cursor, (const uint32_t *)off, k1, v1,
+                           (unsigned long long *)nullptr);
+        SPADE_HIP(ctx, hipGetLastError());
+        if (total > 0) {
+            int cb = 1;
+            while (cb < 40 && ((uint64_t)(G - 1) >> cb) != 0) ++cb;
+            size_t sb = 0;
+            SPADE_HIP(ctx, hipcub::DeviceRadixSort::SortPairs(nullptr, sb, (const unsigned long long *)k1, k2,
+                                                              (const uint32_t *)v1, v2, (int)total, 0, 32 + cb, st));
+            if (ensure(ctx, bt, std::max<size_t>(sb, 1))) return SPADE_E_NOMEM;
+            SPADE_HIP(ctx, hipcub::DeviceRadixSort::SortPairs(bt.p, sb, (const unsigned long long *)k1, k2,
+                                                              (const uint32_t *)v1, v2, (int)total, 0, 32 + cb, st));
+            const int ggrid = (int)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, (int64_t)cus * 8));
+            hipLaunchKernelGGL(k_bufj_gather, dim3(ggrid), dim3(256), 0, st, (int64_t)total, (const uint32_t *)v2,
+                               (const JSeg *)segs, list);
+            SPADE_HIP(ctx, hipGetLastError());
+        }
+    }
+
+    const int64_t nseg = (n + EMIT_SEG - 1) / EMIT_SEG;
+    const int64_t wpb = BUF_THREADS / 64;
+    const int gridp = (int)std::max<int64_t>(1, std::min<int64_t>((nseg + wpb - 1) / wpb, (int64_t)cus * 2));
+    if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[2], st));
+    if (counting) {
+        constexpr int HIST = 16384;
+        const size_t lds = R <= HIST ? sizeof(uint32_t) * (size_t)std::max<int64_t>(R, 1) : 0;
+        SPADE_HIP(ctx, hipFuncSetAttribute((const void *)k_bufj_pairs<2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)std::max<size_t>(lds, 4)));
+        hipLaunchKernelGGL(k_bufj_pairs<2>, dim3(gridp), dim3(BUF_THREADS), lds, st, n, pts->x, pts->y, grid,
+                           (const uint32_t *)off, (const JSeg *)list, magpad, nseg, (unsigned long long *)nullptr,
+                           (const unsigned long long *)nullptr, (uint32_t *)nullptr, (uint32_t *)nullptr, (int64_t)0,
+                           (unsigned long long *)out_counts, (int)R, HIST);
+        SPADE_HIP(ctx, hipGetLastError());
+        if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[3], st));
+        SPADE_HIP(ctx, hipStreamSynchronize(st));
+        return SPADE_OK;
+    }
+    DevBuf &lb = ctx->scratch[S_LOOKBACK];
+    if (ensure(ctx, lb, sizeof(unsigned long long) * 2 * (size_t)(nseg + 1))) return SPADE_E_NOMEM;
+    unsigned long long *counts = (unsigned long long *)lb.p;
+    unsigned long long *offs = counts + (nseg + 1);
+    hipLaunchKernelGGL(k_bufj_pairs<0>, dim3(gridp), dim3(BUF_THREADS), 0, st, n, pts->x, pts->y, grid,
+                       (const uint32_t *)off, (const JSeg *)list, magpad, nseg, counts,
+                       (const unsigned long long *)nullptr, (uint32_t *)nullptr, (uint32_t *)nullptr, (int64_t)0,
+                       (unsigned long long *)nullptr, (int)R, 0);
+    hipLaunchKernelGGL(k_buf_zero, dim3(1), dim3(1), 0, st, counts + nseg);
+    SPADE_HIP(ctx, hipGetLastError());
+    DevBuf &bt = ctx->scratch[S_BUF_TMP];
+    size_t tb = 0;
+    SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(nullptr, tb, counts, offs, (int)(nseg + 1), st));
+    if (ensure(ctx, bt, std::max<size_t>(tb, 1))) return SPADE_E_NOMEM;
+    SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(bt.p, tb, counts, offs, (int)(nseg + 1), st));
+    if (cap > 0) {
+        hipLaunchKernelGGL(k_bufj_pairs<1>, dim3(gridp), dim3(BUF_THREADS), 0, st, n, pts->x, pts->y, grid,
+                           (const uint32_t *)off, (const JSeg *)list, magpad, nseg, (unsigned long long *)nullptr,
+                           (const unsigned long long *)offs, out_pt, out_line, cap, (unsigned long long *)nullptr,
+                           (int)R, 0);
+        SPADE_HIP(ctx, hipGetLastError());
+    }
+    if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[3], st));
+    SPADE_HIP(ctx, hipMemcpyAsync(h, offs + nseg, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    SPADE_HIP(ctx, hipStreamSynchronize(st));
+    if (n_out) *n_out = (int64_t)h[0];
+    if ((int64_t)h[0] > cap) return set_error(ctx, SPADE_E_CAPACITY, "output capacity too small");
+    return SPADE_OK;
+}
+
 }  // namespace spade

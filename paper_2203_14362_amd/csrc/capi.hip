@@ -634,6 +634,35 @@ int spade_select_within_polygon(spade_ctx *ctx, const spade_points *pts, const s
     });
 }
 
+int spade_distance_join_lines_pairs(spade_ctx *ctx, const spade_points *pts, const spade_polys *lines,
+                                    const double *r, double r_all, uint32_t *out_pt, uint32_t *out_line, int64_t cap,
+                                    int64_t *n_out)
+{
+    if (!ctx) return SPADE_E_INVALID;
+    SPADE_CTX_LOCK(ctx);
+    if (n_out) *n_out = 0;
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if ((rc = check_points(ctx, pts))) return rc;
+    ctx->timed_raster = false;
+    return spade::buffer_join_lines(ctx, pts, lines, r, r_all, out_pt, out_line, cap, n_out, nullptr);
+}
+
+int spade_distance_join_lines_count(spade_ctx *ctx, const spade_points *pts, const spade_polys *lines,
+                                    const double *r, double r_all, uint64_t *out_counts)
+{
+    if (!ctx) return SPADE_E_INVALID;
+    SPADE_CTX_LOCK(ctx);
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if ((rc = check_points(ctx, pts))) return rc;
+    if (lines && lines->n_rings > 0 && !out_counts) return set_error(ctx, SPADE_E_INVALID, "out_counts is NULL");
+    ctx->timed_raster = false;
+    uint64_t dummy = 0;
+    return spade::buffer_join_lines(ctx, pts, lines, r, r_all, nullptr, nullptr, 0, nullptr,
+                                    out_counts ? out_counts : &dummy);
+}
+
 int spade_stream_read(spade_ctx *ctx, const spade_points *pts, int shape, double *out_sum)
 {
     if (!ctx) return SPADE_E_INVALID;

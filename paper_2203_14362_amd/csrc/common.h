@@ -224,6 +224,13 @@ int layered_build(spade_ctx *ctx, const spade_polys *polys, int res, spade_canva
 int buffer_select(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts, const spade_polys *geom, double r,
                   bool closed, uint32_t *out_ids, int64_t cap, int64_t *n_out);
 
+// Distance join with lines: pairs (point, line) of the points within r[line]
+// (or r_all when r is NULL) of each ring of `lines` as an open polyline, in
+// (point, line) order; or, with out_counts, the pairs per line.
+int buffer_join_lines(spade_ctx *ctx, const spade_points *pts, const spade_polys *lines, const double *r,
+                      double r_all, uint32_t *out_pt, uint32_t *out_line, int64_t cap, int64_t *n_out,
+                      uint64_t *out_counts);
+
 // LDS bytes the count probe leaves for the coarse canvas, given the polygon
 // count (its histogram shares the LDS).
 size_t coarse_lds_budget(int64_t M);

@@ -42,7 +42,8 @@ EXPORTS = [
     "spade_layered_build", "spade_distance_join_pairs", "spade_distance_join_count", "spade_knn_select",
     "spade_host_table_create", "spade_host_table_destroy", "spade_host_table_info", "spade_host_join_count",
     "spade_host_select", "spade_batch_submit", "spade_batch_wait", "spade_job_query", "spade_job_free",
-    "spade_select_near_lines", "spade_select_within_polygon",
+    "spade_select_near_lines", "spade_select_within_polygon", "spade_distance_join_lines_pairs",
+    "spade_distance_join_lines_count",
 ]
 
 JOB_SELECT, JOB_COUNT, JOB_PAIRS = 1, 2, 3
@@ -108,6 +109,9 @@ def load_library():
                                       P(i64)]
     lib.spade_select_near_lines.argtypes = [vp, P(_Points), P(_Polys), ctypes.c_double, vp, i64, P(i64)]
     lib.spade_select_within_polygon.argtypes = [vp, P(_Points), P(_Polys), ctypes.c_double, vp, i64, P(i64)]
+    lib.spade_distance_join_lines_pairs.argtypes = [vp, P(_Points), P(_Polys), vp, ctypes.c_double, vp, vp, i64,
+                                                    P(i64)]
+    lib.spade_distance_join_lines_count.argtypes = [vp, P(_Points), P(_Polys), vp, ctypes.c_double, vp]
     lib.spade_join_count.argtypes = [vp, P(_Points), P(_Polys), vp]
     lib.spade_join_pairs.argtypes = [vp, P(_Points), P(_Polys), vp, vp, i64, P(i64)]
     lib.spade_canvas_build.argtypes = [vp, P(_Polys), P(vp)]
@@ -751,6 +755,48 @@ class Context:
         of `lines` (every ring of the CSR set an open polyline), decided
         exactly."""
         return self._select_dist(self.lib.spade_select_near_lines, x, y, lines, r, cap)
+
+    def _line_radii(self, r):
+        if np.ndim(r) == 0 and not isinstance(r, torch.Tensor):
+            return None, float(r)
+        return _dev_f64(r, self.device), 0.0
+
+    def distance_join_lines(self, x, y, lines, r, cap=None):
+        """(point ids, line ids) int32 tensors, ascending by (point, line), of
+        every point within r (a scalar, or one distance per line) of each ring
+        of `lines` taken as an open polyline, decided exactly."""
+        P = _points(x, y)
+        dl = self.polys(lines)
+        rr, r_all = self._line_radii(r)
+        if cap is None:
+            cap = max(P.n, 1)
+        while True:
+            pt = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device)
+            pl = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device)
+            nout = ctypes.c_int64()
+            self._sync_stream()
+            rc = self.lib.spade_distance_join_lines_pairs(
+                self.handle, ctypes.byref(P), ctypes.byref(dl.cstruct()),
+                None if rr is None else ctypes.c_void_p(rr.data_ptr()), r_all, ctypes.c_void_p(pt.data_ptr()),
+                ctypes.c_void_p(pl.data_ptr()), cap, ctypes.byref(nout))
+            if rc == SPADE_E_CAPACITY:
+                cap = int(nout.value)
+                continue
+            self._check(rc)
+            m = int(nout.value)
+            return _ids(_compact(pt, m), P.n), _compact(pl, m)
+
+    def distance_join_lines_count(self, x, y, lines, r):
+        """Per-line counts (int64) of the points within each line's distance."""
+        P = _points(x, y)
+        dl = self.polys(lines)
+        rr, r_all = self._line_radii(r)
+        out = torch.empty(max(dl.n_rings, 1), dtype=torch.int64, device=self.device)
+        self._sync_stream()
+        self._check(self.lib.spade_distance_join_lines_count(
+            self.handle, ctypes.byref(P), ctypes.byref(dl.cstruct()),
+            None if rr is None else ctypes.c_void_p(rr.data_ptr()), r_all, ctypes.c_void_p(out.data_ptr())))
+        return out[:dl.n_rings]
 
     def select_within(self, x, y, poly, r, cap=None):
         """Ascending ids of the points inside the one polygon or within
