@@ -449,6 +449,29 @@ def leg_next(ctx, dx, dy, N):
                                   "bytes_rule": "16 B per point + 4 B per id + 1 result bit per point written and read"}}
         log("leg next: %s %.3f ms per call (probe %.3f ms), %d ids, oracle sample %s" %
             (name, float(np.median(tb)), probe_ms, nid, ok))
+    # distance join with the same roads as line objects, one distance per
+    # road (type 2: 25-100 m)
+    rad = np.random.default_rng(81).uniform(25.0, 100.0, roads["n_polys"])
+    res = {}
+    tj, pj = [], []
+    for i in range(4):
+        t0 = time.perf_counter()
+        res["p"] = ctx.distance_join_lines(dx, dy, roads, rad)
+        torch.cuda.synchronize()
+        if i:
+            tj.append((time.perf_counter() - t0) * 1e3)
+            pj.append(ctx.last_timing()[1])
+    lp, ll = (t.cpu().numpy().astype(np.int64) for t in res["p"])
+    m = int(np.searchsorted(lp, 200_000))
+    op, ol = obuf.distance_join_lines(xs, ys, roads, rad)
+    lj_ok = bool(np.array_equal(lp[:m], op) and np.array_equal(ll[:m], ol))
+    out["distance_join_lines"] = {"lines": int(roads["n_polys"]), "segments": 23800, "distance_m": "25-100 per line",
+                                  "pairs": int(lp.size), "ms_per_call": round(float(np.median(tj)), 3),
+                                  "probe_ms": round(float(np.median(pj)), 3),
+                                  "points_per_s": round(N / (float(np.median(tj)) / 1e3), 1),
+                                  "oracle_sample_200k_points": lj_ok}
+    log("leg next: line distance join %.3f ms per call, %d pairs, oracle sample %s"
+        % (float(np.median(tj)), lp.size, lj_ok))
     return out
 
 
