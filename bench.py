@@ -652,7 +652,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        log("bench.py measures one GPU: this build runs on a single MI355X and has no "
+        log("bench.py measures one GPU: the library runs on a single MI355X and has no "
             "multi-GPU path (--gpus %d requested)." % args.gpus)
         sys.exit(2)
     legs = [l for l in args.legs.split(",") if l]

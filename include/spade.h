@@ -59,7 +59,7 @@ enum {
     SPADE_E_CAPACITY = -2,     /* output buffer too small; *n_out = needed   */
     SPADE_E_NOMEM = -3,        /* device allocation failed                   */
     SPADE_E_HIP = -4,          /* HIP runtime error (message has the text)   */
-    SPADE_E_UNSUPPORTED = -5,  /* valid request outside this build's limits  */
+    SPADE_E_UNSUPPORTED = -5,  /* valid request outside the library's limits */
     SPADE_E_TOO_LARGE = -6     /* n >= 2^32 points or n_polys >= 2^31 - 1    */
 };
 
