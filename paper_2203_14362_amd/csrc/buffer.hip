@@ -11,11 +11,15 @@
 // per point: for a polygon, the canvas of the polygon answers first (coarse
 // level in LDS, full canvas, exact records, as the selection probe does);
 // a point not yet kept that lies in the grid's box is tested exactly against
-// the segments its cell lists, until one is within r.  The ordered ids are
+// the segments its cell lists, until one is within r.  The tests of a
+// wavefront's 64 points are spread over its lanes (buf_wave_walk), so that a
+// wavefront takes about as many rounds as its points have candidates in
+// total / 64 rather than as many as its longest list.  The ordered ids are
 // then written from the bits (the two-step Map of the selection).
 #include "common.h"
 #include "lookup.h"
 #include "segdist.h"
+#include "wavewalk.h"
 
 #include <hipcub/hipcub.hpp>
 
@@ -157,6 +161,40 @@ __global__ void k_buf_bin(int64_t V, const Seg *segs, const uint8_t *valid, BufG
     }
 }
 
+// The candidate tests of one wavefront's points, balanced over its lanes
+// (wave_round): lane i's point has the candidates list[k, k + rem) left, and
+// a point any of whose candidates in a round was within r drops the rest.
+// Returns whether this lane's point was hit.  Called by every lane of the
+// wavefront.
+__device__ __forceinline__ bool buf_wave_walk(double x, double y, uint32_t k, uint32_t rem, const Seg *list,
+                                              double r, double r2, double pad, int lane)
+{
+    bool hit = false;
+    while (__ballot(rem != 0u)) {
+        const WaveRound w = wave_round(rem, lane);
+        const uint32_t ok = __shfl(k, w.o, 64);
+        const double ox = __shfl(x, w.o, 64), oy = __shfl(y, w.o, 64);
+        bool h = false;
+        if ((uint32_t)lane < w.ntake) {
+            const Seg s = list[ok + ((uint32_t)lane - w.opre)];
+            // outside the segment's box widened by pad: farther than r
+            if (!(ox < fmin(s.ax, s.bx) - pad || ox > fmax(s.ax, s.bx) + pad || oy < fmin(s.ay, s.by) - pad ||
+                  oy > fmax(s.ay, s.by) + pad))
+                h = seg_near(ox, oy, s, r, r2);
+        }
+        const unsigned long long hm = __ballot(h);
+        const uint32_t len = wave_round_len(w);
+        if (hm & wave_round_mask(w)) {
+            hit = true;
+            rem = 0u;
+        } else {
+            k += len;
+            rem -= len;
+        }
+    }
+    return hit;
+}
+
 // One result bit per point (layout of the ordered emit: word j of segment sg
 // holds points sg * EMIT_SEG + 64 j + lane) and the count per segment.
 template <bool POLY>
@@ -196,17 +234,13 @@ __global__ __launch_bounds__(BUF_THREADS) void k_buf_bits(CanvasView cv, int64_t
                 }
             }
             // NaN fails the box test
+            uint32_t k = 0u, rem = 0u;
             if (!hit && x >= g.X0 && x <= g.X1 && y >= g.Y0 && y <= g.Y1) {
                 const int64_t c = (int64_t)buf_cell(y, g.Y0, g.inv, g.gy) * g.gx + buf_cell(x, g.X0, g.inv, g.gx);
-                for (uint32_t k = off[c], e = off[c + 1]; k < e; ++k) {
-                    const Seg s = list[k];
-                    // outside the segment's box widened by pad: farther than r
-                    if (x < fmin(s.ax, s.bx) - pad || x > fmax(s.ax, s.bx) + pad ||
-                        y < fmin(s.ay, s.by) - pad || y > fmax(s.ay, s.by) + pad)
-                        continue;
-                    if (seg_near(x, y, s, r, r2)) { hit = true; break; }
-                }
+                k = off[c];
+                rem = off[c + 1] - k;
             }
+            if (buf_wave_walk(x, y, k, rem, list, r, r2, pad, lane)) hit = true;
             const unsigned long long word = __ballot(hit);
             total += (unsigned long long)__popcll(word);
             if (lane == j) segw = word;
@@ -530,26 +564,73 @@ __global__ void k_bufj_gather(int64_t ntot, const uint32_t *vals, const JSeg *se
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ntot; i += nth) list[i] = segs[vals[i]];
 }
 
-// Calls hit(line) for each line within its distance of (x, y), in
-// ascending line order, each line once.
-template <typename Hit>
-__device__ __forceinline__ void bufj_walk(double x, double y, const BufGrid &g, const uint32_t *off,
-                                          const JSeg *list, double magpad, Hit &&hit)
+// The cell's candidates of a point: list[k, k + rem), or none outside the
+// grid's box (NaN fails the test too).
+__device__ __forceinline__ void bufj_range(double x, double y, const BufGrid &g, const uint32_t *off, uint32_t &k,
+                                           uint32_t &rem)
 {
-    if (!(x >= g.X0 && x <= g.X1 && y >= g.Y0 && y <= g.Y1)) return;   // NaN fails too
-    const int64_t c = (int64_t)buf_cell(y, g.Y0, g.inv, g.gy) * g.gx + buf_cell(x, g.X0, g.inv, g.gx);
+    k = 0u;
+    rem = 0u;
+    if (x >= g.X0 && x <= g.X1 && y >= g.Y0 && y <= g.Y1) {
+        const int64_t c = (int64_t)buf_cell(y, g.Y0, g.inv, g.gy) * g.gx + buf_cell(x, g.X0, g.inv, g.gx);
+        k = off[c];
+        rem = off[c + 1] - k;
+    }
+}
+
+// The (point, line) pairs of a wavefront's points, with the candidate tests
+// balanced over the lanes (wave_round).  A cell's list is sorted by segment,
+// so a line's segments are consecutive in it, and a hit repeats its point's
+// previous hit exactly when it has the same line: the previous hit is found
+// among the round's earlier positions of the same point, else it is the last
+// line the point met in earlier rounds.  A repeated line is not tested again
+// once its point has met it in an earlier round.  For each new pair the
+// testing lane calls pair(o, slot, line) with o the point's lane and slot =
+// base of lane o + the pair's rank among the point's pairs (ascending line
+// order); on return cnt holds the number of pairs of this lane's point.
+// Called by every lane of the wavefront.
+template <typename Pair>
+__device__ __forceinline__ void bufj_wave_walk(double x, double y, uint32_t k, uint32_t rem, const JSeg *list,
+                                               double magpad, uint32_t base, int lane, uint32_t &cnt, Pair &&pair)
+{
     uint32_t last = 0xffffffffu;
-    for (uint32_t k = off[c], e = off[c + 1]; k < e; ++k) {
-        const JSeg s = list[k];
-        if (s.line == last) continue;   // this line is already paired with the point
-        const double pad = s.r * (1.0 + 0x1p-40) + magpad;
-        if (x < fmin(s.ax, s.bx) - pad || x > fmax(s.ax, s.bx) + pad || y < fmin(s.ay, s.by) - pad ||
-            y > fmax(s.ay, s.by) + pad)
-            continue;
-        if (seg_near(x, y, Seg{s.ax, s.ay, s.bx, s.by}, s.r, s.r * s.r)) {
-            hit(s.line);
-            last = s.line;
+    cnt = 0u;
+    while (__ballot(rem != 0u)) {
+        const WaveRound w = wave_round(rem, lane);
+        const uint32_t ok = __shfl(k, w.o, 64);
+        const uint32_t olast = __shfl(last, w.o, 64);
+        const uint32_t ocnt = __shfl(cnt, w.o, 64);
+        const uint32_t obase = __shfl(base, w.o, 64);
+        const double ox = __shfl(x, w.o, 64), oy = __shfl(y, w.o, 64);
+        bool h = false;
+        uint32_t line = 0xffffffffu;
+        if ((uint32_t)lane < w.ntake) {
+            const JSeg sg = list[ok + ((uint32_t)lane - w.opre)];
+            line = sg.line;
+            if (line != olast) {
+                const double pad = sg.r * (1.0 + 0x1p-40) + magpad;
+                if (!(ox < fmin(sg.ax, sg.bx) - pad || ox > fmax(sg.ax, sg.bx) + pad ||
+                      oy < fmin(sg.ay, sg.by) - pad || oy > fmax(sg.ay, sg.by) + pad))
+                    h = seg_near(ox, oy, Seg{sg.ax, sg.ay, sg.bx, sg.by}, sg.r, sg.r * sg.r);
+            }
         }
+        const unsigned long long hm = __ballot(h);
+        // the previous hit of the same point in this round, if any
+        const unsigned long long own = wave_round_before(w, lane);
+        const unsigned long long ph = hm & own;
+        const uint32_t pline = __shfl(line, ph ? 63 - __clzll((long long)ph) : lane, 64);
+        const bool fresh = h && line != (ph ? pline : olast);
+        const unsigned long long nm = __ballot(fresh);
+        if (fresh) pair(w.o, obase + ocnt + (uint32_t)__popcll(nm & own), line);
+        // this point's pairs of the round, and its last hit line
+        const unsigned long long mine = wave_round_mask(w);
+        const unsigned long long myh = hm & mine;
+        const uint32_t hline = __shfl(line, myh ? 63 - __clzll((long long)myh) : lane, 64);
+        if (myh) last = hline;
+        cnt += (uint32_t)__popcll(nm & mine);
+        const uint32_t len = wave_round_len(w);
+        k += len;
+        rem -= len;
     }
 }
 
@@ -572,7 +653,6 @@ __global__ __launch_bounds__(BUF_THREADS) void k_bufj_pairs(int64_t n, const dou
         __syncthreads();
     }
     const int lane = threadIdx.x & 63;
-    const unsigned long long below = (1ull << lane) - 1ull;
     const int64_t nwave = ((int64_t)gridDim.x * BUF_THREADS) >> 6;
     for (int64_t sg = ((int64_t)blockIdx.x * BUF_THREADS + threadIdx.x) >> 6; sg < nseg; sg += nwave) {
         unsigned long long total = 0;
@@ -581,15 +661,16 @@ __global__ __launch_bounds__(BUF_THREADS) void k_bufj_pairs(int64_t n, const dou
             const int64_t i = sg * EMIT_SEG + 64 * j + lane;
             const double x = i < n ? __builtin_nontemporal_load(X + i) : NAN;
             const double y = i < n ? __builtin_nontemporal_load(Y + i) : NAN;
-            uint32_t cnt = 0;
+            uint32_t k, rem, cnt;
+            bufj_range(x, y, g, off, k, rem);
             if (MODE == 2) {
-                bufj_walk(x, y, g, off, list, magpad, [&](uint32_t line) {
+                bufj_wave_walk(x, y, k, rem, list, magpad, 0u, lane, cnt, [&](int, uint32_t, uint32_t line) {
                     if (lds) atomicAdd(&h[line], 1u);
                     else atomicAdd(&lcount[line], 1ull);
                 });
                 continue;
             }
-            bufj_walk(x, y, g, off, list, magpad, [&](uint32_t) { ++cnt; });
+            bufj_wave_walk(x, y, k, rem, list, magpad, 0u, lane, cnt, [](int, uint32_t, uint32_t) {});
             // the wavefront's pairs of this word, in lane order
             uint32_t pre = cnt;
             for (int d = 1; d < 64; d <<= 1) {
@@ -597,15 +678,18 @@ __global__ __launch_bounds__(BUF_THREADS) void k_bufj_pairs(int64_t n, const dou
                 if (lane >= d) pre += t;
             }
             const uint32_t wsum = (uint32_t)__shfl((int)pre, 63, 64);
-            if (MODE == 1 && cnt) {
-                int64_t p = pos + (int64_t)(pre - cnt);
-                bufj_walk(x, y, g, off, list, magpad, [&](uint32_t line) {
-                    if (p < cap) {
-                        out_pt[p] = (uint32_t)i;
-                        out_line[p] = line;
-                    }
-                    ++p;
-                });
+            if (MODE == 1 && wsum) {
+                // again, writing each pair at pos + (pairs of earlier lanes) + rank
+                const int64_t w0 = sg * EMIT_SEG + 64 * j;
+                uint32_t c2;
+                bufj_wave_walk(x, y, k, cnt ? rem : 0u, list, magpad, pre - cnt, lane, c2,
+                               [&](int o, uint32_t slot, uint32_t line) {
+                                   const int64_t p = pos + (int64_t)slot;
+                                   if (p < cap) {
+                                       out_pt[p] = (uint32_t)(w0 + o);
+                                       out_line[p] = line;
+                                   }
+                               });
             }
             pos += wsum;
             total += wsum;

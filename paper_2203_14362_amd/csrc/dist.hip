@@ -10,9 +10,13 @@
 // cell's list and every listed disk gets the exact closed-disk predicate, so
 // results are exact and independent of the grid.  Pairs come out ascending
 // by (point id, disk id) from the paper's two-step Map (count pass per
-// wavefront segment, scan, write pass), with no sort.
+// wavefront segment, scan, write pass), with no sort.  The disk tests of a
+// wavefront's points are spread over its lanes (wave_round), so that a
+// wavefront's rounds follow its candidates in total rather than its longest
+// list.
 #include "common.h"
 #include "disk.h"
+#include "wavewalk.h"
 
 #include <hipcub/hipcub.hpp>
 
@@ -143,18 +147,50 @@ struct DiskCanvas {
     DiskArgs D;
 };
 
-// Matches of point (x, y): every listed disk of its cell, in ascending id.
-template <typename F>
-__device__ __forceinline__ void disk_matches(const DiskCanvas &K, double x, double y, F &&f)
+// The candidates of point (x, y): its cell's disks cell_disk[k, k + rem)
+// (none outside the disks' box; NaN fails the test too).
+__device__ __forceinline__ void disk_range(const DiskCanvas &K, double x, double y, uint32_t &k, uint32_t &rem)
 {
-    if (!(K.g.bx0 <= x && x <= K.g.bx1 && K.g.by0 <= y && y <= K.g.by1)) return;   // NaN fails
+    k = 0u;
+    rem = 0u;
+    if (!(K.g.bx0 <= x && x <= K.g.bx1 && K.g.by0 <= y && y <= K.g.by1)) return;
     const int c = min((int)((x - K.g.X0) * K.g.sx), K.g.W - 1);
     const int r = min((int)((y - K.g.Y0) * K.g.sy), K.g.H - 1);
     const int64_t cell = (int64_t)max(r, 0) * K.g.W + max(c, 0);
-    for (uint32_t t = K.cell_off[cell]; t < K.cell_off[cell + 1]; ++t) {
-        const uint32_t j = K.cell_disk[t];
-        const double rj = radius_of(K.D, j);
-        if (in_disk(x, y, K.D.cx[j], K.D.cy[j], rj, rj * rj)) f(j);
+    k = K.cell_off[cell];
+    rem = K.cell_off[cell + 1] - k;
+}
+
+// The (point, disk) pairs of a wavefront's points with the disk tests
+// balanced over the lanes: for each pair the testing lane calls pair(o,
+// slot, j) with o the point's lane and slot = base of lane o + the pair's
+// rank among the point's pairs (ascending disk id, the order of the cell
+// lists); on return cnt holds the number of pairs of this lane's point.
+// Called by every lane of the wavefront.
+template <typename Pair>
+__device__ __forceinline__ void disk_wave_walk(const DiskCanvas &K, double x, double y, uint32_t k, uint32_t rem,
+                                               uint32_t base, int lane, uint32_t &cnt, Pair &&pair)
+{
+    cnt = 0u;
+    while (__ballot(rem != 0u)) {
+        const WaveRound w = wave_round(rem, lane);
+        const uint32_t ok = __shfl(k, w.o, 64);
+        const uint32_t ocnt = __shfl(cnt, w.o, 64);
+        const uint32_t obase = __shfl(base, w.o, 64);
+        const double ox = __shfl(x, w.o, 64), oy = __shfl(y, w.o, 64);
+        bool h = false;
+        uint32_t j = 0u;
+        if ((uint32_t)lane < w.ntake) {
+            j = K.cell_disk[ok + ((uint32_t)lane - w.opre)];
+            const double rj = radius_of(K.D, j);
+            h = in_disk(ox, oy, K.D.cx[j], K.D.cy[j], rj, rj * rj);
+        }
+        const unsigned long long hm = __ballot(h);
+        if (h) pair(w.o, obase + ocnt + (uint32_t)__popcll(hm & wave_round_before(w, lane)), j);
+        cnt += (uint32_t)__popcll(hm & wave_round_mask(w));
+        const uint32_t len = wave_round_len(w);
+        k += len;
+        rem -= len;
     }
 }
 
@@ -188,16 +224,16 @@ __global__ __launch_bounds__(DJ_THREADS) void k_djoin(DiskCanvas K, int64_t n, c
         }
         unsigned long long pos = MODE == 1 ? offs[sg] : 0ull;
         for (int k = 0; k < DJ_ROUNDS; ++k) {
-            const int64_t i = i0 + 64 * k;
+            uint32_t c0, rem, m;
+            disk_range(K, xs[k], ys[k], c0, rem);
             if (MODE == 2) {
-                disk_matches(K, xs[k], ys[k], [&](uint32_t j) {
+                disk_wave_walk(K, xs[k], ys[k], c0, rem, 0u, lane, m, [&](int, uint32_t, uint32_t j) {
                     if (ldsh) atomicAdd(&hist[j], 1u);
                     else atomicAdd(&dcount[j], 1ull);
                 });
                 continue;
             }
-            uint32_t m = 0;
-            disk_matches(K, xs[k], ys[k], [&](uint32_t) { ++m; });
+            disk_wave_walk(K, xs[k], ys[k], c0, rem, 0u, lane, m, [](int, uint32_t, uint32_t) {});
             uint32_t inc = m;
 #pragma unroll
             for (int d = 1; d < 64; d <<= 1) {
@@ -205,15 +241,18 @@ __global__ __launch_bounds__(DJ_THREADS) void k_djoin(DiskCanvas K, int64_t n, c
                 if (lane >= d) inc += t;
             }
             const uint32_t tot = __shfl(inc, 63, 64);
-            if (MODE == 1 && m) {
-                unsigned long long p = pos + (inc - m);
-                disk_matches(K, xs[k], ys[k], [&](uint32_t j) {
-                    if ((int64_t)p < cap) {
-                        out_pt[p] = (uint32_t)i;
-                        out_disk[p] = j;
-                    }
-                    ++p;
-                });
+            if (MODE == 1 && tot) {
+                // again, writing each pair at pos + (pairs of earlier lanes) + rank
+                const int64_t w0 = sg * DJ_SEG + 64 * k;
+                uint32_t m2;
+                disk_wave_walk(K, xs[k], ys[k], c0, m ? rem : 0u, inc - m, lane, m2,
+                               [&](int o, uint32_t slot, uint32_t j) {
+                                   const unsigned long long p = pos + slot;
+                                   if ((int64_t)p < cap) {
+                                       out_pt[p] = (uint32_t)(w0 + o);
+                                       out_disk[p] = j;
+                                   }
+                               });
             }
             pos += tot;
         }
