@@ -267,9 +267,13 @@ int spade_distance_join_count(spade_ctx *ctx, const spade_points *pts, const spa
  * by exact Euclidean distance, nearest first, equal distances by ascending
  * id.  out_ids [k] (device); *n_out (host) = min(k, number of points with
  * finite coordinates).  Follows the paper's plan: an aggregation over nested
- * circles r_i = r_max / 2^i around the point (r_max: the farthest corner of
- * the points' bounding box), a distance selection with the smallest circle
- * holding k points, and a sort of those candidates by distance (exact). */
+ * circles around the point whose radii halve from one to the next (here the
+ * powers of two 2^j, -511 <= j <= 511, so no pass over the points is needed
+ * to find the paper's outer radius r_max; only when the k points reach
+ * beyond 2^511 the circles r_max / 2^i, r_max the farthest corner of the
+ * points' bounding box), a distance selection with the smallest circle
+ * holding k points, and a sort of those candidates by distance (exact).
+ * Exact while no squared distance overflows or falls into subnormals. */
 int spade_knn_select(spade_ctx *ctx, const spade_points *pts, double px, double py, int64_t k,
                      uint32_t *out_ids, int64_t *n_out);
 

@@ -170,7 +170,7 @@ namespace spade {
 enum Slot {
     S_BLOCKRED = 0, S_RINGPOLY, S_NROWS, S_ROWOFF, S_KEYS, S_KEYS2, S_VALS, S_VALS2,
     S_ENTC, S_ENTF, S_CUBTMP, S_ROWCNT, S_NEXTP, S_PROBE, S_LOOKBACK, S_MISC, S_ROWSCAN,
-    S_BITS,     // the ordered emit's per-point result bits (used by nothing else)
+    S_BITS,     // per-point result bits of the ordered emits (count pass to write pass)
     S_BUF_SEGS, S_BUF_GRID, S_BUF_LIST, S_BUF_TMP,   // distance selection from lines / a polygon
     S_NSLOTS
 };

@@ -8,10 +8,10 @@
 //
 // Output follows the paper's two-step Map (Sec. 5.1): a count pass writes
 // the number of selected points of every wavefront segment of DISK_SEG
-// points, an exclusive scan gives each segment its start, and a write pass
-// recomputes the predicate and writes the ids in order (ballot ranks within
-// the wavefront).  Both passes evaluate the same function on the same
-// inputs, so the write pass fills exactly the counted slots.
+// points and keeps one result bit per point, an exclusive scan gives each
+// segment its start, and the write pass (k_emit_bits, shared with the
+// selection probe) writes the ids in order from the bits, so the points are
+// read once.
 #include "common.h"
 #include "disk.h"
 
@@ -27,18 +27,16 @@ constexpr int DISK_ROUNDS = 16;   // 64-point rounds per wavefront segment
 constexpr int64_t DISK_SEG = 64 * DISK_ROUNDS;
 
 // Every wavefront owns segments of DISK_SEG consecutive points (grid-stride
-// over segments).  WRITE == false: counts[s] = selected points of segment s.
-// WRITE == true: the ids of segment s's selected points, ascending, from
-// out[offs[s]] on; positions at or beyond cap are not written.  No barriers:
-// a wavefront ranks its points by ballot.
-template <bool WRITE>
+// over segments): counts[s] = selected points of segment s, and word k of
+// segment s in bits holds the results of points s * DISK_SEG + 64 k + lane
+// (the layout k_emit_bits reads).  No barriers: a wavefront counts its
+// points by ballot.
+static_assert(DISK_SEG == EMIT_SEG, "the write pass reads the count pass's bits per EMIT_SEG points");
 __global__ __launch_bounds__(DISK_THREADS) void k_disk(int64_t n, const double *X, const double *Y, double cx,
                                                        double cy, double r, double r2, int64_t nseg,
-                                                       uint32_t *counts, const uint32_t *offs, uint32_t *out,
-                                                       int64_t cap)
+                                                       unsigned long long *counts, unsigned long long *bits)
 {
     const int lane = threadIdx.x & 63;
-    const unsigned long long below = (1ull << lane) - 1ull;
     const int64_t nwave = ((int64_t)gridDim.x * DISK_THREADS) >> 6;
     for (int64_t sg = ((int64_t)blockIdx.x * DISK_THREADS + threadIdx.x) >> 6; sg < nseg; sg += nwave) {
         const int64_t i0 = sg * DISK_SEG + lane;
@@ -50,22 +48,21 @@ __global__ __launch_bounds__(DISK_THREADS) void k_disk(int64_t n, const double *
             xs[k] = i < n ? __builtin_nontemporal_load(X + i) : NAN;
             ys[k] = i < n ? __builtin_nontemporal_load(Y + i) : NAN;
         }
-        uint32_t pos = WRITE ? offs[sg] : 0u;
+        unsigned long long pos = 0ull, segw = 0ull;
 #pragma unroll
         for (int k = 0; k < DISK_ROUNDS; ++k) {
             const bool in = in_disk(xs[k], ys[k], cx, cy, r, r2);   // NaN padding is outside
             const unsigned long long m = __ballot(in);
-            if (WRITE && in) {
-                const uint32_t at = pos + (uint32_t)__popcll(m & below);
-                if ((int64_t)at < cap) out[at] = (uint32_t)(i0 + 64 * k);
-            }
-            pos += (uint32_t)__popcll(m);
+            if (lane == k) segw = m;
+            pos += (unsigned long long)__popcll(m);
         }
-        if (!WRITE && lane == 0) counts[sg] = pos;
+        if (lane < DISK_ROUNDS) bits[sg * DISK_ROUNDS + lane] = segw;
+        if (lane == 0) counts[sg] = pos;
     }
 }
 
-__global__ void k_disk_zero(uint32_t *p) { *p = 0u; }
+__global__ void k_disk_zero(unsigned long long *p) { *p = 0ull; }
+
 
 int select_disk(spade_ctx *ctx, const spade_points *pts, double cx, double cy, double r, uint32_t *out_ids,
                 int64_t cap, int64_t *n_out)
@@ -81,17 +78,20 @@ int select_disk(spade_ctx *ctx, const spade_points *pts, double cx, double cy, d
         return SPADE_OK;
     }
     const int64_t nseg = (n + DISK_SEG - 1) / DISK_SEG;
-    DevBuf &cb = ctx->scratch[S_LOOKBACK];
-    if (ensure(ctx, cb, sizeof(uint32_t) * 2 * (size_t)(nseg + 1))) return SPADE_E_NOMEM;
-    uint32_t *counts = (uint32_t *)cb.p;
-    uint32_t *offs = counts + (nseg + 1);
+    DevBuf &cb = ctx->scratch[S_LOOKBACK], &bb = ctx->scratch[S_BITS];
+    if (ensure(ctx, cb, sizeof(unsigned long long) * 2 * (size_t)(nseg + 1)) ||
+        ensure(ctx, bb, sizeof(unsigned long long) * DISK_ROUNDS * (size_t)nseg))
+        return SPADE_E_NOMEM;
+    unsigned long long *counts = (unsigned long long *)cb.p;
+    unsigned long long *offs = counts + (nseg + 1);
+    unsigned long long *bits = (unsigned long long *)bb.p;
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || cus <= 0)
         cus = 256;
     const int grid = (int)std::min<int64_t>((nseg + DISK_THREADS / 64 - 1) / (DISK_THREADS / 64), (int64_t)cus * 8);
     const double r2 = r * r;
-    hipLaunchKernelGGL(k_disk<false>, dim3(grid), dim3(DISK_THREADS), 0, st, n, pts->x, pts->y, cx, cy, r, r2,
-                       nseg, counts, nullptr, nullptr, (int64_t)0);
+    hipLaunchKernelGGL(k_disk, dim3(grid), dim3(DISK_THREADS), 0, st, n, pts->x, pts->y, cx, cy, r, r2, nseg, counts,
+                       bits);
     hipLaunchKernelGGL(k_disk_zero, dim3(1), dim3(1), 0, st, counts + nseg);
     SPADE_HIP(ctx, hipGetLastError());
     DevBuf &cub = ctx->scratch[S_CUBTMP];
@@ -99,20 +99,20 @@ int select_disk(spade_ctx *ctx, const spade_points *pts, double cx, double cy, d
     SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(nullptr, tb, counts, offs, (int)(nseg + 1), st));
     if (ensure(ctx, cub, std::max<size_t>(tb, 1))) return SPADE_E_NOMEM;
     SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(cub.p, tb, counts, offs, (int)(nseg + 1), st));
-    uint32_t *h = (uint32_t *)ensure_pinned(ctx, 64);
+    // the write pass also runs when the buffer is too small: the first cap
+    // ids are written (two-step Map), the call then reports the shortfall
+    if (cap > 0) {
+        const int eg = (int)std::max<int64_t>(1, std::min<int64_t>((nseg + 3) / 4, (int64_t)cus * 16));
+        hipLaunchKernelGGL(k_emit_bits, dim3(eg), dim3(256), 0, st, nseg, (const unsigned long long *)offs,
+                           (const unsigned long long *)bits, out_ids, (uint32_t *)nullptr, cap);
+        SPADE_HIP(ctx, hipGetLastError());
+    }
+    unsigned long long *h = (unsigned long long *)ensure_pinned(ctx, 64);
     if (!h) return set_error(ctx, SPADE_E_NOMEM, "pinned staging allocation failed");
-    SPADE_HIP(ctx, hipMemcpyAsync(h, offs + nseg, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    SPADE_HIP(ctx, hipMemcpyAsync(h, offs + nseg, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
     SPADE_HIP(ctx, hipStreamSynchronize(st));
     const int64_t total = (int64_t)h[0];
     if (n_out) *n_out = total;
-    // the write pass also runs when the buffer is too small: the first cap
-    // ids are written (two-step Map), the call then reports the shortfall
-    if (total > 0 && cap > 0) {
-        hipLaunchKernelGGL(k_disk<true>, dim3(grid), dim3(DISK_THREADS), 0, st, n, pts->x, pts->y, cx, cy, r, r2,
-                           nseg, nullptr, offs, out_ids, cap);
-        SPADE_HIP(ctx, hipGetLastError());
-        SPADE_HIP(ctx, hipStreamSynchronize(st));
-    }
     if (total > cap) return set_error(ctx, SPADE_E_CAPACITY, "output capacity too small for the selection");
     return SPADE_OK;
 }

@@ -456,16 +456,22 @@ int distance_join(spade_ctx *ctx, const spade_points *pts, const spade_disks *dk
 
 // ------------------------------------------------------------ kNN selection
 //
-// The paper's plan (Sec. 5.2, "kNN Queries"): circles around the query point
-// with radii r_i = r_max / alpha^i (r_max: the largest distance from the
-// point to a corner of the points' bounding box), one aggregation pass that
-// counts the points in every circle, a distance selection with the smallest
-// circle that holds at least k points, and a sort of those candidates by
-// distance.  Here alpha = 2 and the circles run down to r_max 2^-KNN_LEVELS.
-// Every comparison is exact: the circle counts use the exact closed-disk
-// test, and the candidates are ordered by their FP64 squared distance, then
-// every run of keys too close to tell apart is re-ordered exactly (ties in
-// distance: smaller id first).
+// The paper's plan (Sec. 5.2, "kNN Queries"): nested circles around the
+// query point with radii in a geometric progression, one aggregation pass
+// that counts the points in every circle, a distance selection with the
+// smallest circle that holds at least k points, and a sort of those
+// candidates by distance.  The paper anchors the circles at r_max (the
+// largest distance from the point to a corner of the points' bounding box)
+// with r_i = r_max / alpha^i.  Here alpha = 2 and the circles are first the
+// powers of two r_j = 2^j, -511 <= j <= 511 (r_j^2 is a normal double, so
+// the exact closed-disk test applies): they need no bounding box, so the
+// aggregation is the only pass before the selection.  Only when more than
+// the points inside r_511 are needed (distances beyond 6.7e153) does the
+// query fall back to circles r_max 2^-i (i <= KNN_LEVELS) from the bounding
+// box.  Every comparison is exact: the circle counts use the exact
+// closed-disk test, and the candidates are ordered by their FP64 squared
+// distance, then every run of keys too close to tell apart is re-ordered
+// exactly (ties in distance: smaller id first).
 
 constexpr int KNN_LEVELS = 48;
 constexpr int KNN_THREADS = 256;
@@ -526,6 +532,49 @@ __global__ __launch_bounds__(KNN_THREADS) void k_knn_levels(int64_t n, const dou
         if (h[k]) atomicAdd(&level[k], (unsigned long long)h[k]);
 }
 
+constexpr int KNN_JMIN = -511, KNN_JMAX = 511;
+constexpr int KNN_BINS = KNN_JMAX - KNN_JMIN + 2;   // + the points outside every circle
+
+__device__ __forceinline__ bool in_circle_pow2(double x, double y, double px, double py, int j)
+{
+    return in_disk(x, y, px, py, ldexp(1.0, j), ldexp(1.0, 2 * j));
+}
+
+// Aggregation over the circles r_j = 2^j: bins[j - KNN_JMIN] counts the
+// finite points whose innermost containing circle is j, bins[KNN_BINS - 1]
+// those outside circle KNN_JMAX.  The FP64 squared distance only gives the
+// first guess at j (4^j <= d2 up to rounding); the exact test settles it,
+// usually with two tests: j is outside, j + 1 inside.
+// Only bins that were hit are added to the global counts.
+__global__ __launch_bounds__(KNN_THREADS) void k_knn_pow2(int64_t n, const double *X, const double *Y, double px,
+                                                          double py, unsigned long long *bins)
+{
+    __shared__ unsigned int h[KNN_BINS];
+    for (int k = threadIdx.x; k < KNN_BINS; k += KNN_THREADS) h[k] = 0;
+    __syncthreads();
+    for (int64_t i = (int64_t)blockIdx.x * KNN_THREADS + threadIdx.x; i < n; i += (int64_t)gridDim.x * KNN_THREADS) {
+        const double x = __builtin_nontemporal_load(X + i), y = __builtin_nontemporal_load(Y + i);
+        if (!(fabs(x) <= 1.7976931348623157e308 && fabs(y) <= 1.7976931348623157e308)) continue;
+        const double dx = x - px, dy = y - py;
+        const double d2 = dx * dx + dy * dy;
+        int j;
+        if (!(d2 > 0.0)) j = KNN_JMIN;
+        else if (!(d2 <= 1.7976931348623157e308)) j = KNN_JMAX + 1;
+        else j = min(max(ilogb(d2) >> 1, KNN_JMIN), KNN_JMAX + 1);   // 4^j <= d2 up to rounding
+        if (j <= KNN_JMAX && !in_circle_pow2(x, y, px, py, j)) {
+            do ++j;
+            while (j <= KNN_JMAX && !in_circle_pow2(x, y, px, py, j));
+        } else {
+            // in circle j (or j past the last one): move inwards while inside
+            while (j > KNN_JMIN && in_circle_pow2(x, y, px, py, j - 1)) --j;
+        }
+        atomicAdd(&h[j - KNN_JMIN], 1u);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < KNN_BINS; k += KNN_THREADS)
+        if (h[k]) atomicAdd(&bins[k], (unsigned long long)h[k]);
+}
+
 // Candidate keys: FP64 squared distance (non-negative, so its bits order it)
 // and the id.
 __global__ void k_knn_keys(int64_t m, const uint32_t *ids, const double *X, const double *Y, double px, double py,
@@ -580,68 +629,93 @@ int knn_select(spade_ctx *ctx, const spade_points *pts, double px, double py, in
     if (k > 0 && !out_ids) return set_error(ctx, SPADE_E_INVALID, "out_ids is NULL");
     const int64_t n = pts->n;
     if (k == 0 || n == 0) return SPADE_OK;
-    // bounding box of the points -> r_max
-    DevBuf &bb = ctx->scratch[S_BLOCKRED];
-    if (ensure(ctx, bb, 64 + 8 * (KNN_LEVELS + 1) + 16 * (KNN_LEVELS + 1))) return SPADE_E_NOMEM;
-    unsigned long long *dbb = (unsigned long long *)bb.p;
-    unsigned long long *level = dbb + 4;
-    SPADE_HIP(ctx, hipMemsetAsync(dbb, 0xff, 32, st));
-    hipLaunchKernelGGL(k_dj_zero, dim3(1), dim3(64), 0, st, (int64_t)(KNN_LEVELS + 1), level);
-    hipLaunchKernelGGL(k_knn_box, dim3(dj_grid(n, 1024)), dim3(256), 0, st, n, pts->x, pts->y, dbb);
-    SPADE_HIP(ctx, hipGetLastError());
-    unsigned long long *h = (unsigned long long *)ensure_pinned(ctx, 8 * (KNN_LEVELS + 8));
-    if (!h) return set_error(ctx, SPADE_E_NOMEM, "pinned staging allocation failed");
-    SPADE_HIP(ctx, hipMemcpyAsync(h, dbb, 32, hipMemcpyDeviceToHost, st));
-    SPADE_HIP(ctx, hipStreamSynchronize(st));
-    if (h[0] == ~0ull) return SPADE_OK;   // no finite point
-    auto from_key = [](unsigned long long kk) {
-        const unsigned long long b = (kk & 0x8000000000000000ull) ? (kk & 0x7fffffffffffffffull) : ~kk;
-        double d;
-        std::memcpy(&d, &b, sizeof d);
-        return d;
-    };
-    const double x0 = from_key(h[0]), x1 = -from_key(h[1]), y0 = from_key(h[2]), y1 = -from_key(h[3]);
-    double rmax = 0.0;
-    for (double cx : {x0, x1})
-        for (double cy : {y0, y1}) rmax = std::max(rmax, std::hypot(cx - px, cy - py));
-    // round up by a relative 2^-40: every finite point is then in circle 0
-    // (the exact test decides), whatever the rounding of hypot
-    rmax = rmax * (1.0 + std::ldexp(1.0, -40)) + std::ldexp(1.0, -1000);
-    KnnCircles C;
-    C.px = px;
-    C.py = py;
-    for (int i = 0; i <= KNN_LEVELS; ++i) {
-        C.r[i] = std::ldexp(rmax, -i);
-        C.r2[i] = C.r[i] * C.r[i];
-    }
     const int cus = num_cus_dj(ctx->device);
-    double *cr = (double *)(level + (KNN_LEVELS + 1));
-    double *hr = (double *)ensure_pinned(ctx, 8 * (KNN_LEVELS + 8) + 16 * (KNN_LEVELS + 1));
-    if (!hr) return set_error(ctx, SPADE_E_NOMEM, "pinned staging allocation failed");
-    h = (unsigned long long *)hr;
-    hr += KNN_LEVELS + 8;
-    std::memcpy(hr, C.r, 8 * (KNN_LEVELS + 1));
-    std::memcpy(hr + KNN_LEVELS + 1, C.r2, 8 * (KNN_LEVELS + 1));
-    SPADE_HIP(ctx, hipMemcpyAsync(cr, hr, 16 * (KNN_LEVELS + 1), hipMemcpyHostToDevice, st));
+    // circles r_j = 2^j: bins of the innermost containing circle
+    DevBuf &bb = ctx->scratch[S_BLOCKRED];
+    const size_t bin_bytes = 8 * (size_t)KNN_BINS;
+    if (ensure(ctx, bb, std::max<size_t>(bin_bytes, 64 + 8 * (KNN_LEVELS + 1) + 16 * (KNN_LEVELS + 1))))
+        return SPADE_E_NOMEM;
+    unsigned long long *dbins = (unsigned long long *)bb.p;
+    hipLaunchKernelGGL(k_dj_zero, dim3(4), dim3(256), 0, st, (int64_t)KNN_BINS, dbins);
     if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[2], st));
-    hipLaunchKernelGGL(k_knn_levels, dim3((unsigned)std::min<int64_t>((n + KNN_THREADS - 1) / KNN_THREADS, cus * 8)),
-                       dim3(KNN_THREADS), 0, st, n, pts->x, pts->y, px, py, (const double *)cr, level);
+    hipLaunchKernelGGL(k_knn_pow2, dim3((unsigned)std::min<int64_t>((n + KNN_THREADS - 1) / KNN_THREADS, cus * 8)),
+                       dim3(KNN_THREADS), 0, st, n, pts->x, pts->y, px, py, dbins);
     SPADE_HIP(ctx, hipGetLastError());
-    SPADE_HIP(ctx, hipMemcpyAsync(h, level, 8 * (KNN_LEVELS + 1), hipMemcpyDeviceToHost, st));
+    unsigned long long *hb = (unsigned long long *)ensure_pinned(ctx, bin_bytes + 16 * (KNN_LEVELS + 8));
+    if (!hb) return set_error(ctx, SPADE_E_NOMEM, "pinned staging allocation failed");
+    SPADE_HIP(ctx, hipMemcpyAsync(hb, dbins, bin_bytes, hipMemcpyDeviceToHost, st));
     SPADE_HIP(ctx, hipStreamSynchronize(st));
-    // count(r_i) = points whose innermost circle is i or deeper
-    int64_t cum = 0, total = 0;
-    for (int i = 0; i <= KNN_LEVELS; ++i) total += (int64_t)h[i];
-    int sel = 0;
-    for (int i = KNN_LEVELS; i >= 0; --i) {
-        cum += (int64_t)h[i];
-        if (cum >= std::min<int64_t>(k, total)) { sel = i; break; }
+    int64_t total = 0;
+    for (int b = 0; b < KNN_BINS; ++b) total += (int64_t)hb[b];
+    if (total == 0) return SPADE_OK;   // no finite point
+    const int64_t want = std::min<int64_t>(k, total);
+    int64_t cum = 0;
+    double rsel = -1.0;
+    for (int b = 0; b + 1 < KNN_BINS; ++b) {
+        cum += (int64_t)hb[b];
+        if (cum >= want) {
+            rsel = std::ldexp(1.0, KNN_JMIN + b);
+            break;
+        }
+    }
+    if (rsel < 0.0) {
+        // more points are needed than lie within 2^511: the circles
+        // r_max 2^-i from the points' bounding box
+        unsigned long long *dbb = dbins;
+        unsigned long long *level = dbb + 4;
+        SPADE_HIP(ctx, hipMemsetAsync(dbb, 0xff, 32, st));
+        hipLaunchKernelGGL(k_dj_zero, dim3(1), dim3(64), 0, st, (int64_t)(KNN_LEVELS + 1), level);
+        hipLaunchKernelGGL(k_knn_box, dim3(dj_grid(n, 1024)), dim3(256), 0, st, n, pts->x, pts->y, dbb);
+        SPADE_HIP(ctx, hipGetLastError());
+        unsigned long long *h = hb;
+        SPADE_HIP(ctx, hipMemcpyAsync(h, dbb, 32, hipMemcpyDeviceToHost, st));
+        SPADE_HIP(ctx, hipStreamSynchronize(st));
+        auto from_key = [](unsigned long long kk) {
+            const unsigned long long b = (kk & 0x8000000000000000ull) ? (kk & 0x7fffffffffffffffull) : ~kk;
+            double d;
+            std::memcpy(&d, &b, sizeof d);
+            return d;
+        };
+        const double x0 = from_key(h[0]), x1 = -from_key(h[1]), y0 = from_key(h[2]), y1 = -from_key(h[3]);
+        double rmax = 0.0;
+        for (double cx : {x0, x1})
+            for (double cy : {y0, y1}) rmax = std::max(rmax, std::hypot(cx - px, cy - py));
+        // round up by a relative 2^-40: every finite point is then in circle 0
+        // (the exact test decides), whatever the rounding of hypot
+        rmax = rmax * (1.0 + std::ldexp(1.0, -40)) + std::ldexp(1.0, -1000);
+        KnnCircles C;
+        C.px = px;
+        C.py = py;
+        for (int i = 0; i <= KNN_LEVELS; ++i) {
+            C.r[i] = std::ldexp(rmax, -i);
+            C.r2[i] = C.r[i] * C.r[i];
+        }
+        double *cr = (double *)(level + (KNN_LEVELS + 1));
+        double *hr = (double *)(hb + KNN_LEVELS + 8);
+        std::memcpy(hr, C.r, 8 * (KNN_LEVELS + 1));
+        std::memcpy(hr + KNN_LEVELS + 1, C.r2, 8 * (KNN_LEVELS + 1));
+        SPADE_HIP(ctx, hipMemcpyAsync(cr, hr, 16 * (KNN_LEVELS + 1), hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(k_knn_levels, dim3((unsigned)std::min<int64_t>((n + KNN_THREADS - 1) / KNN_THREADS, cus * 8)),
+                           dim3(KNN_THREADS), 0, st, n, pts->x, pts->y, px, py, (const double *)cr, level);
+        SPADE_HIP(ctx, hipGetLastError());
+        SPADE_HIP(ctx, hipMemcpyAsync(h, level, 8 * (KNN_LEVELS + 1), hipMemcpyDeviceToHost, st));
+        SPADE_HIP(ctx, hipStreamSynchronize(st));
+        // count(r_i) = points whose innermost circle is i or deeper
+        int64_t ltot = 0;
+        for (int i = 0; i <= KNN_LEVELS; ++i) ltot += (int64_t)h[i];
+        cum = 0;
+        int sel = 0;
+        for (int i = KNN_LEVELS; i >= 0; --i) {
+            cum += (int64_t)h[i];
+            if (cum >= std::min<int64_t>(k, ltot)) { sel = i; break; }
+        }
+        rsel = C.r[sel];
     }
     // distance selection with circle sel: the candidates, ascending ids
     int64_t m = 0;
     DevBuf &bc = ctx->scratch[S_VALS2];
     if (ensure(ctx, bc, 4 * (size_t)std::max<int64_t>(cum, 1))) return SPADE_E_NOMEM;
-    int rc = select_disk(ctx, pts, px, py, C.r[sel], (uint32_t *)bc.p, cum, &m);
+    int rc = select_disk(ctx, pts, px, py, rsel, (uint32_t *)bc.p, cum, &m);
     if (rc) return rc;
     if (m != cum) return set_error(ctx, SPADE_E_HIP, "internal: circle count and selection disagree");
     // order by distance, exactly; the first k are the result

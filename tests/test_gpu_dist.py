@@ -102,3 +102,20 @@ def test_knn_ties_and_edges(ctx):
         assert np.array_equal(got, disk.knn(x, y, px, py, k)), (px, py, k)
     assert ctx.knn(dx, dy, 0.0, 0.0, 0).numel() == 0
     assert ctx.knn(dx[:0], dy[:0], 0.0, 0.0, 5).numel() == 0
+
+
+def test_knn_beyond_power_of_two_circles(ctx):
+    """Points farther than 2^511 (6.7e153) from the query lie outside every
+    power-of-two circle: a k that needs them takes the circles r_max / 2^i
+    from the points' bounding box.  Squared distances stay below the FP64
+    maximum, inside the exact predicate's range."""
+    g = np.arange(-5, 6, dtype=np.float64)
+    X, Y = np.meshgrid(g, g)
+    far_x = np.array([9e153, 0.0, -6e153, 5e153, 3.0])
+    far_y = np.array([0.0, 8e153, -6e153, 0.0, 7e153])
+    x = np.concatenate([X.ravel(), far_x])
+    y = np.concatenate([Y.ravel(), far_y])
+    dx, dy = _dev(x), _dev(y)
+    for k in (5, 121, 122, 123, 124, 200):
+        got = ctx.knn(dx, dy, 0.5, 0.25, k).cpu().numpy().astype(np.int64)
+        assert np.array_equal(got, disk.knn(x, y, 0.5, 0.25, k)), k
