@@ -38,6 +38,7 @@ constexpr int HIST_MAX = 8192;            // polygons counted in LDS
 constexpr int EMIT_THREADS = 1024;
 constexpr int EMIT_GROUP = 8;             // points per lane in flight (count pass)
 constexpr int EMIT_WGROUP = 4;            // points per lane in flight (write pass)
+constexpr int EMIT_WDRAIN = 8;            // words of the write pass sharing one boundary queue
 constexpr size_t LDS_TOTAL = 160 * 1024;
 constexpr size_t LDS_RESERVE = 2048;      // static LDS of the kernels
 constexpr size_t QUEUE_BYTES = (size_t)(CNT_THREADS / 64) * QCAP * 20;
@@ -396,26 +397,14 @@ __global__ __launch_bounds__(EMIT_THREADS) void k_emit(CanvasView cv, int64_t n,
     for (int64_t sg = ((int64_t)blockIdx.x * EMIT_THREADS + threadIdx.x) >> 6; sg < nseg; sg += nwave) {
         const int64_t i0 = sg * EMIT_SEG + lane;
         unsigned long long pos = offs[sg];
-        for (int g = 0; g < EMIT_SEG / 64; g += EMIT_WGROUP) {
-            // the group's points, then their canvas words, level by level
-            double xs[EMIT_WGROUP], ys[EMIT_WGROUP];
-#pragma unroll
-            for (int k = 0; k < EMIT_WGROUP; ++k) {
-                const int64_t i = i0 + 64 * (g + k);
-                xs[k] = i < n ? __builtin_nontemporal_load(X + i) : NAN;   // NaN: outside
-                ys[k] = i < n ? __builtin_nontemporal_load(Y + i) : NAN;
-            }
-            uint32_t ws[EMIT_WGROUP];
-#pragma unroll
-            for (int k = 0; k < EMIT_WGROUP; ++k) {
-                const Look lk = look_coarse(cv, coarse, xs[k], ys[k]);
-                ws[k] = lk.full ? ((gu32p)cv.cells)[lk.fidx] : lk.word;
-            }
-            // matches of every point: interior words at once, boundary
-            // points through the queue
-            uint32_t cnt[EMIT_WGROUP], lab[EMIT_WGROUP], slot[EMIT_WGROUP];
-            uint32_t qn = 0, pend = 0;   // wave-uniform: queue length, rounds queued
-            uint32_t mine = 0;           // rounds whose point of this lane is queued
+        // EMIT_WDRAIN words share one boundary queue (drained when full and
+        // at their end); their points are loaded EMIT_WGROUP words at a time
+        for (int g0 = 0; g0 < EMIT_SEG / 64; g0 += EMIT_WDRAIN) {
+            // per word: the entry count (the queue slot while its boundary
+            // point waits in the queue) and the label or first record
+            uint32_t cs[EMIT_WDRAIN], lab[EMIT_WDRAIN];
+            uint32_t qn = 0, pend = 0;   // wave-uniform: queue length, words queued
+            uint32_t mine = 0;           // words whose point of this lane is queued
             auto drain = [&]() {
                 __builtin_amdgcn_wave_barrier();
                 uint32_t m = 0, first = 0, rec0 = 0;
@@ -436,53 +425,75 @@ __global__ __launch_bounds__(EMIT_THREADS) void k_emit(CanvasView cv, int64_t n,
                 __builtin_amdgcn_wave_barrier();
                 const uint32_t rl = m == 1 ? first : (m > 1 ? rec0 : 0u);
 #pragma unroll
-                for (int k = 0; k < EMIT_WGROUP; ++k) {
+                for (int k = 0; k < EMIT_WDRAIN; ++k) {
                     if (!(pend & (1u << k))) continue;
-                    const uint32_t c = (uint32_t)__shfl((int)m, (int)slot[k], 64);
-                    const uint32_t l = (uint32_t)__shfl((int)rl, (int)slot[k], 64);
-                    if (mine & (1u << k)) { cnt[k] = c; lab[k] = l; }
+                    const int from = (mine & (1u << k)) ? (int)cs[k] : 0;
+                    const uint32_t c = (uint32_t)__shfl((int)m, from, 64);
+                    const uint32_t l = (uint32_t)__shfl((int)rl, from, 64);
+                    if (mine & (1u << k)) { cs[k] = c; lab[k] = l; }
                 }
                 pend = 0;
                 mine = 0;
                 qn = 0;
             };
 #pragma unroll
-            for (int k = 0; k < EMIT_WGROUP; ++k) {
-                const uint32_t w = ws[k];
-                const bool bnd = (w & BFLAG) != 0;
-                cnt[k] = (w != 0u && !bnd) ? 1u : 0u;
-                lab[k] = (w != 0u && !bnd) ? w - 1u : 0u;
-                slot[k] = 0;
-                const unsigned long long mask = __ballot(bnd);
-                const uint32_t nnew = (uint32_t)__popcll(mask);
-                if (nnew == 0) continue;
-                if (qn + nnew > QCAP) drain();
-                if (bnd) {
-                    const uint32_t sl = qn + (uint32_t)__popcll(mask & below);
-                    qx[sl] = xs[k];
-                    qy[sl] = ys[k];
-                    qr[sl] = w & ~BFLAG;
-                    slot[k] = sl;
-                    mine |= 1u << k;
+            for (int g = 0; g < EMIT_WDRAIN; g += EMIT_WGROUP) {
+                // the group's points, then their canvas words, level by level
+                double xs[EMIT_WGROUP], ys[EMIT_WGROUP];
+#pragma unroll
+                for (int k = 0; k < EMIT_WGROUP; ++k) {
+                    const int64_t i = i0 + 64 * (g0 + g + k);
+                    xs[k] = i < n ? __builtin_nontemporal_load(X + i) : NAN;   // NaN: outside
+                    ys[k] = i < n ? __builtin_nontemporal_load(Y + i) : NAN;
                 }
-                qn += nnew;
-                pend |= 1u << k;
+                uint32_t ws[EMIT_WGROUP];
+#pragma unroll
+                for (int k = 0; k < EMIT_WGROUP; ++k) {
+                    const Look lk = look_coarse(cv, coarse, xs[k], ys[k]);
+                    ws[k] = lk.full ? ((gu32p)cv.cells)[lk.fidx] : lk.word;
+                }
+                // matches of every point: interior words at once, boundary
+                // points through the queue
+#pragma unroll
+                for (int k = 0; k < EMIT_WGROUP; ++k) {
+                    const int kk = g + k;
+                    const uint32_t w = ws[k];
+                    const bool bnd = (w & BFLAG) != 0;
+                    cs[kk] = (w != 0u && !bnd) ? 1u : 0u;
+                    lab[kk] = (w != 0u && !bnd) ? w - 1u : 0u;
+                    const unsigned long long mask = __ballot(bnd);
+                    const uint32_t nnew = (uint32_t)__popcll(mask);
+                    if (nnew == 0) continue;
+                    if (qn + nnew > QCAP) drain();
+                    if (bnd) {
+                        const uint32_t sl = qn + (uint32_t)__popcll(mask & below);
+                        qx[sl] = xs[k];
+                        qy[sl] = ys[k];
+                        qr[sl] = w & ~BFLAG;
+                        cs[kk] = sl;
+                        mine |= 1u << kk;
+                    }
+                    qn += nnew;
+                    pend |= 1u << kk;
+                }
             }
             if (qn) drain();
 #pragma unroll
-            for (int k = 0; k < EMIT_WGROUP; ++k) {
+            for (int k = 0; k < EMIT_WDRAIN; ++k) {
                 // inclusive scan of the entry counts across the wavefront
-                uint32_t inc = cnt[k];
+                const uint32_t cnt = cs[k];
+                uint32_t inc = cnt;
 #pragma unroll
                 for (int d = 1; d < 64; d <<= 1) {
                     const uint32_t t = __shfl_up(inc, d, 64);
                     if (lane >= d) inc += t;
                 }
                 const uint32_t tot = __shfl(inc, 63, 64);
-                if (cnt[k]) {
-                    const uint32_t pt = (uint32_t)(i0 + 64 * (g + k));
-                    unsigned long long p = pos + (inc - cnt[k]);
-                    if (cnt[k] == 1) {
+                if (cnt) {
+                    const int64_t i = i0 + 64 * (g0 + k);
+                    const uint32_t pt = (uint32_t)i;
+                    unsigned long long p = pos + (inc - cnt);
+                    if (cnt == 1) {
                         if ((int64_t)p < cap) {
                             out_pt[p] = pt;
                             if (out_poly) out_poly[p] = lab[k];
@@ -490,13 +501,14 @@ __global__ __launch_bounds__(EMIT_THREADS) void k_emit(CanvasView cv, int64_t n,
                     } else {
                         // several polygons: each pass takes the smallest
                         // matching polygon above the last one
+                        const double x = X[i], y = Y[i];
                         uint32_t prev = 0;
-                        for (uint32_t t = 0; t < cnt[k]; ++t) {
+                        for (uint32_t t = 0; t < cnt; ++t) {
                             uint32_t best = 0xffffffffu;
                             uint32_t rec = lab[k];
                             while (true) {
                                 const Cand cd = cv.cands[rec];
-                                if ((t == 0 || cd.poly > prev) && cd.poly < best && cand_inside(cv, cd, xs[k], ys[k]))
+                                if ((t == 0 || cd.poly > prev) && cd.poly < best && cand_inside(cv, cd, x, y))
                                     best = cd.poly;
                                 if (cd.meta & CAND_LAST) break;
                                 ++rec;
@@ -631,7 +643,38 @@ __global__ __launch_bounds__(EMIT_THREADS) void k_emit_count_bits(CanvasView cv,
         const int64_t i0 = sg * EMIT_SEG + lane;
         unsigned long long total = 0;   // wave-uniform
         unsigned long long segw = 0;    // lane j < EMIT_SEG / 64: the word of points 64 j ..
-        for (int g = 0; g < EMIT_SEG / 64; g += EMIT_WGROUP) {
+        // the segment's words share one boundary queue (drained when full
+        // and at the segment's end); points are loaded EMIT_WGROUP words at
+        // a time
+        constexpr int NW = EMIT_SEG / 64;
+        uint32_t hit = 0, slot[NW];   // hit: bit k for this lane's point of word k
+        uint32_t qn = 0, pend = 0, mine = 0;
+        auto drain = [&]() {
+            __builtin_amdgcn_wave_barrier();
+            uint32_t m = 0;
+            if (lane < (int)qn) {
+                const double x = qx[lane], y = qy[lane];
+                uint32_t rec = qr[lane];
+                while (true) {
+                    const Cand c0 = cv.cands[rec];
+                    if (cand_inside(cv, c0, x, y)) m = 1u;
+                    if (c0.meta & CAND_LAST) break;
+                    ++rec;
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int k = 0; k < NW; ++k) {
+                if (!(pend & (1u << k))) continue;
+                const uint32_t c = (uint32_t)__shfl((int)m, (int)slot[k], 64);
+                if ((mine & (1u << k)) && c) hit |= 1u << k;
+            }
+            pend = 0;
+            mine = 0;
+            qn = 0;
+        };
+#pragma unroll
+        for (int g = 0; g < NW; g += EMIT_WGROUP) {
             double xs[EMIT_WGROUP], ys[EMIT_WGROUP];
 #pragma unroll
             for (int k = 0; k < EMIT_WGROUP; ++k) {
@@ -645,38 +688,13 @@ __global__ __launch_bounds__(EMIT_THREADS) void k_emit_count_bits(CanvasView cv,
                 const Look lk = look_coarse(cv, coarse, xs[k], ys[k]);
                 ws[k] = lk.full ? ((gu32p)cv.cells)[lk.fidx] : lk.word;
             }
-            uint32_t hit = 0, slot[EMIT_WGROUP];   // hit: bit k for this lane's point k
-            uint32_t qn = 0, pend = 0, mine = 0;
-            auto drain = [&]() {
-                __builtin_amdgcn_wave_barrier();
-                uint32_t m = 0;
-                if (lane < (int)qn) {
-                    const double x = qx[lane], y = qy[lane];
-                    uint32_t rec = qr[lane];
-                    while (true) {
-                        const Cand c0 = cv.cands[rec];
-                        if (cand_inside(cv, c0, x, y)) m = 1u;
-                        if (c0.meta & CAND_LAST) break;
-                        ++rec;
-                    }
-                }
-                __builtin_amdgcn_wave_barrier();
-#pragma unroll
-                for (int k = 0; k < EMIT_WGROUP; ++k) {
-                    if (!(pend & (1u << k))) continue;
-                    const uint32_t c = (uint32_t)__shfl((int)m, (int)slot[k], 64);
-                    if ((mine & (1u << k)) && c) hit |= 1u << k;
-                }
-                pend = 0;
-                mine = 0;
-                qn = 0;
-            };
 #pragma unroll
             for (int k = 0; k < EMIT_WGROUP; ++k) {
+                const int kk = g + k;
                 const uint32_t w = ws[k];
                 const bool bnd = (w & BFLAG) != 0;
-                if (w != 0u && !bnd) hit |= 1u << k;
-                slot[k] = 0;
+                if (w != 0u && !bnd) hit |= 1u << kk;
+                slot[kk] = 0;
                 const unsigned long long mask = __ballot(bnd);
                 const uint32_t nnew = (uint32_t)__popcll(mask);
                 if (nnew == 0) continue;
@@ -686,19 +704,19 @@ __global__ __launch_bounds__(EMIT_THREADS) void k_emit_count_bits(CanvasView cv,
                     qx[sl] = xs[k];
                     qy[sl] = ys[k];
                     qr[sl] = w & ~BFLAG;
-                    slot[k] = sl;
-                    mine |= 1u << k;
+                    slot[kk] = sl;
+                    mine |= 1u << kk;
                 }
                 qn += nnew;
-                pend |= 1u << k;
+                pend |= 1u << kk;
             }
-            if (qn) drain();
+        }
+        if (qn) drain();
 #pragma unroll
-            for (int k = 0; k < EMIT_WGROUP; ++k) {
-                const unsigned long long word = __ballot((hit >> k) & 1u);
-                total += (unsigned long long)__popcll(word);
-                if (lane == g + k) segw = word;
-            }
+        for (int k = 0; k < NW; ++k) {
+            const unsigned long long word = __ballot((hit >> k) & 1u);
+            total += (unsigned long long)__popcll(word);
+            if (lane == k) segw = word;
         }
         if (lane < EMIT_SEG / 64) bits[sg * (EMIT_SEG / 64) + lane] = segw;
         if (lane == 0) counts[sg] = total;
