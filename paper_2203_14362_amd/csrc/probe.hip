@@ -375,12 +375,16 @@ int probe_count_noalloc(spade_ctx *ctx, const spade_canvas *cv, const spade_poin
 // written in point order (ascending polygon order for a point in several
 // polygons) from position offs[s] on; positions at or beyond cap are not
 // written.  No barriers after the coarse canvas is loaded.
+template <bool MULTI>
 __global__ __launch_bounds__(EMIT_THREADS) void k_emit(CanvasView cv, int64_t n, const double *X,
                                                        const double *Y, int64_t nseg,
                                                        const unsigned long long *offs, uint32_t *out_pt,
-                                                       uint32_t *out_poly, int64_t cap)
+                                                       uint32_t *out_poly, int64_t cap, const unsigned *multi)
 {
     static_assert(EMIT_THREADS == CNT_THREADS, "the queue area is sized for CNT_THREADS");
+    // both variants are launched; the one that does not fit the count
+    // pass's finding returns at once
+    if ((*multi != 0u) != MULTI) return;
     extern __shared__ __align__(16) unsigned char smem[];
     uint16_t *coarse = (uint16_t *)smem;
     const size_t coarse_bytes = ((size_t)cv.Wc * cv.Hc * (cv.cbyte ? 1 : 2) + 15) & ~(size_t)15;
@@ -498,28 +502,38 @@ __global__ __launch_bounds__(EMIT_THREADS) void k_emit(CanvasView cv, int64_t n,
                             out_pt[p] = pt;
                             if (out_poly) out_poly[p] = lab[k];
                         }
-                    } else {
-                        // several polygons: each pass takes the smallest
-                        // matching polygon above the last one
-                        const double x = X[i], y = Y[i];
-                        uint32_t prev = 0;
-                        for (uint32_t t = 0; t < cnt; ++t) {
-                            uint32_t best = 0xffffffffu;
-                            uint32_t rec = lab[k];
+                    } else if (MULTI && (int64_t)p < cap) {
+                        // several polygons: the smallest L of them (all when
+                        // below cap), ascending, kept in out_poly[p, p + L)
+                        // by insertion during one pass over the pixel's
+                        // records (this lane's own range, read back by this
+                        // lane only)
+                        const uint32_t L = (int64_t)(p + cnt) <= cap ? cnt : (uint32_t)(cap - (int64_t)p);
+                        if (out_poly) {
+                            const double x = X[i], y = Y[i];
+                            uint32_t rec = lab[k], j = 0;
                             while (true) {
                                 const Cand cd = cv.cands[rec];
-                                if ((t == 0 || cd.poly > prev) && cd.poly < best && cand_inside(cv, cd, x, y))
-                                    best = cd.poly;
+                                if (cand_inside(cv, cd, x, y)) {
+                                    const uint32_t v = cd.poly;
+                                    uint32_t at = j;
+                                    if (j < L) ++j;
+                                    else at = out_poly[p + L - 1] > v ? L - 1 : L;   // L: v is not kept
+                                    if (at < L) {
+                                        while (at > 0) {
+                                            const uint32_t u = out_poly[p + at - 1];
+                                            if (u < v) break;
+                                            out_poly[p + at] = u;
+                                            --at;
+                                        }
+                                        out_poly[p + at] = v;
+                                    }
+                                }
                                 if (cd.meta & CAND_LAST) break;
                                 ++rec;
                             }
-                            if ((int64_t)p < cap) {
-                                out_pt[p] = pt;
-                                if (out_poly) out_poly[p] = best;
-                            }
-                            ++p;
-                            prev = best;
                         }
+                        for (uint32_t t = 0; t < L; ++t) out_pt[p + t] = pt;
                     }
                 }
                 pos += tot;
@@ -534,7 +548,7 @@ __global__ __launch_bounds__(EMIT_THREADS) void k_emit(CanvasView cv, int64_t n,
 // so the counts match what the write pass writes.
 __global__ __launch_bounds__(EMIT_THREADS) void k_emit_count(CanvasView cv, int64_t n, const double *X,
                                                              const double *Y, int64_t nseg,
-                                                             unsigned long long *counts)
+                                                             unsigned long long *counts, unsigned *multi)
 {
     static_assert(EMIT_THREADS == CNT_THREADS, "the queue area is sized for CNT_THREADS");
     extern __shared__ __align__(16) unsigned char smem[];
@@ -571,6 +585,9 @@ __global__ __launch_bounds__(EMIT_THREADS) void k_emit_count(CanvasView cv, int6
                 }
             }
             __builtin_amdgcn_wave_barrier();
+            // a point in several polygons: the write pass takes its
+            // several-polygon variant
+            if (__ballot(m > 1u) && lane == 0) *multi = 1u;
 #pragma unroll
             for (int d = 32; d >= 1; d >>= 1) m += __shfl_xor(m, d, 64);
             total += m;
@@ -753,6 +770,7 @@ __global__ __launch_bounds__(256) void k_emit_bits(int64_t nseg, const unsigned 
 }
 
 __global__ void k_emit_zero(unsigned long long *p) { *p = 0ull; }
+__global__ void k_emit_flag0(unsigned *p) { *p = 0u; }
 
 int probe_emit(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts, uint32_t *out_pt,
                uint32_t *out_poly, int64_t cap, int64_t *n_out)
@@ -763,9 +781,10 @@ int probe_emit(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts, 
     if (n == 0 || cv->view.M == 0) return SPADE_OK;
     const int64_t nseg = (n + EMIT_SEG - 1) / EMIT_SEG;
     DevBuf &lb = ctx->scratch[S_LOOKBACK];
-    if (ensure(ctx, lb, sizeof(unsigned long long) * 2 * (size_t)(nseg + 1))) return SPADE_E_NOMEM;
+    if (ensure(ctx, lb, sizeof(unsigned long long) * (2 * (size_t)(nseg + 1) + 1))) return SPADE_E_NOMEM;
     unsigned long long *counts = (unsigned long long *)lb.p;
     unsigned long long *offs = counts + (nseg + 1);
+    unsigned *multi = (unsigned *)(offs + (nseg + 1));   // set by the count pass: a point in several polygons
     const size_t lds = coarse_bytes_of(cv->view);
     if (lds + QUEUE_BYTES + LDS_RESERVE > LDS_TOTAL)
         return set_error(ctx, SPADE_E_HIP, "internal: emit probe LDS budget exceeded");
@@ -775,7 +794,9 @@ int probe_emit(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts, 
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((nseg + wpb - 1) / wpb, (int64_t)cus * std::min(per_cu, 2)));
     SPADE_HIP(ctx, hipFuncSetAttribute((const void *)k_emit_count, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)(lds + QUEUE_BYTES)));
-    SPADE_HIP(ctx, hipFuncSetAttribute((const void *)k_emit, hipFuncAttributeMaxDynamicSharedMemorySize,
+    SPADE_HIP(ctx, hipFuncSetAttribute((const void *)k_emit<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)(lds + QUEUE_BYTES)));
+    SPADE_HIP(ctx, hipFuncSetAttribute((const void *)k_emit<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)(lds + QUEUE_BYTES)));
     // a canvas of one polygon keeps every point's result in the count pass
     // (one bit per point), so that the write pass need not read the points
@@ -794,9 +815,11 @@ int probe_emit(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts, 
     if (bits)
         hipLaunchKernelGGL(k_emit_count_bits, dim3(grid), dim3(EMIT_THREADS), lds + QUEUE_BYTES, st, cv->view, n,
                            pts->x, pts->y, nseg, counts, bits);
-    else
+    else {
+        hipLaunchKernelGGL(k_emit_flag0, dim3(1), dim3(1), 0, st, multi);
         hipLaunchKernelGGL(k_emit_count, dim3(grid), dim3(EMIT_THREADS), lds + QUEUE_BYTES, st, cv->view, n, pts->x,
-                           pts->y, nseg, counts);
+                           pts->y, nseg, counts, multi);
+    }
     hipLaunchKernelGGL(k_emit_zero, dim3(1), dim3(1), 0, st, counts + nseg);
     SPADE_HIP(ctx, hipGetLastError());
     DevBuf &cub = ctx->scratch[S_CUBTMP];
@@ -809,8 +832,10 @@ int probe_emit(spade_ctx *ctx, const spade_canvas *cv, const spade_points *pts, 
         hipLaunchKernelGGL(k_emit_bits, dim3(bg), dim3(256), 0, st, nseg, offs, bits, out_pt, out_poly, cap);
         SPADE_HIP(ctx, hipGetLastError());
     } else if (cap > 0) {
-        hipLaunchKernelGGL(k_emit, dim3(grid), dim3(EMIT_THREADS), lds + QUEUE_BYTES, st, cv->view, n, pts->x,
-                           pts->y, nseg, offs, out_pt, out_poly, cap);
+        hipLaunchKernelGGL(k_emit<false>, dim3(grid), dim3(EMIT_THREADS), lds + QUEUE_BYTES, st, cv->view, n, pts->x,
+                           pts->y, nseg, offs, out_pt, out_poly, cap, (const unsigned *)multi);
+        hipLaunchKernelGGL(k_emit<true>, dim3(grid), dim3(EMIT_THREADS), lds + QUEUE_BYTES, st, cv->view, n, pts->x,
+                           pts->y, nseg, offs, out_pt, out_poly, cap, (const unsigned *)multi);
         SPADE_HIP(ctx, hipGetLastError());
     }
     if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[3], st));

@@ -104,6 +104,25 @@ def test_capacity_writes_first_cap_results(ctx):
     assert np.array_equal(bpt.cpu().numpy().astype(np.uint32), opt[:capp])
     assert np.array_equal(bpg.cpu().numpy().astype(np.uint32), opg[:capp])
 
+    # join pairs with overlapping polygons: caps that cut through the
+    # entries of a point in several polygons keep its smallest polygons
+    stars, _ = gen.query_stars(40, 8, 64, seed=35, L=1.0, area=(0.02, 0.2), data_seed=2)
+    opt, opg = oracle.join_pairs(x, y, stars)
+    runs = np.nonzero((opt[1:-1] == opt[:-2]) & (opt[1:-1] == opt[2:]))[0] + 1
+    assert runs.size > 100
+    dps = ctx.polys(stars)
+    for capp in (int(runs[0]), int(runs[runs.size // 2]), int(runs[-1]) + 1, opt.size - 1):
+        bpt = torch.full((capp,), -1, dtype=torch.int32, device="cuda")
+        bpg = torch.full((capp,), -1, dtype=torch.int32, device="cuda")
+        rc = lib.spade_join_pairs(ctx.handle, ctypes.byref(P), ctypes.byref(dps.cstruct()),
+                                  ctypes.c_void_p(bpt.data_ptr()), ctypes.c_void_p(bpg.data_ptr()), capp,
+                                  ctypes.byref(n))
+        assert rc == spade.SPADE_E_CAPACITY and n.value == opt.size
+        assert np.array_equal(bpt.cpu().numpy().astype(np.uint32), opt[:capp]), capp
+        assert np.array_equal(bpg.cpu().numpy().astype(np.uint32), opg[:capp]), capp
+    full_pt, full_pg = ctx.join_pairs(_dev(x), _dev(y), stars)
+    assert np.array_equal(full_pt.cpu().numpy(), opt) and np.array_equal(full_pg.cpu().numpy(), opg)
+
     # distance selections from lines and from a polygon
     from oracle import buffer as obuf
     lines = gen.polys_from_rings([[np.array([[0.1, 0.1], [0.5, 0.7], [0.9, 0.2]])],
