@@ -247,7 +247,8 @@ static int stream_chunks(spade_ctx *ctx, spade_host_table *t, const std::vector<
     int64_t total = 0;
     // the copy stream may reuse a buffer once the compute stream has passed it
     for (int b = 0; b < 2; ++b) SPADE_HIP(ctx, hipEventRecord(t->freed[b], st));
-    for (size_t k = 0; k < chunks.size(); ++k) {
+    std::vector<int64_t> filled(chunks.size(), 0);
+    auto enqueue_copy = [&](size_t k) -> int {
         const int b = (int)(k & 1);
         SPADE_HIP(ctx, hipStreamWaitEvent(t->copy, t->freed[b], 0));
         int64_t off = 0;
@@ -261,15 +262,30 @@ static int stream_chunks(spade_ctx *ctx, spade_host_table *t, const std::vector<
             off += p.m;
         }
         SPADE_HIP(ctx, hipEventRecord(t->ready[b], t->copy));
+        filled[k] = off;
+        return SPADE_OK;
+    };
+    if (!chunks.empty()) {
+        int rc = enqueue_copy(0);
+        if (rc) return rc;
+    }
+    for (size_t k = 0; k < chunks.size(); ++k) {
+        const int b = (int)(k & 1);
+        // the next chunk's copies are queued before this chunk's probe, which
+        // may wait on the host, so that they overlap it
+        if (k + 1 < chunks.size()) {
+            int rc = enqueue_copy(k + 1);
+            if (rc) return rc;
+        }
         SPADE_HIP(ctx, hipStreamWaitEvent(st, t->ready[b], 0));
-        int rc = probe((const double *)t->dx[b].p, (const double *)t->dy[b].p, (const uint32_t *)t->did[b].p, off,
-                       (int64_t)k);
+        int rc = probe((const double *)t->dx[b].p, (const double *)t->dy[b].p, (const uint32_t *)t->did[b].p,
+                       filled[k], (int64_t)k);
         if (rc) {
             (void)hipStreamSynchronize(t->copy);
             return rc;
         }
         SPADE_HIP(ctx, hipEventRecord(t->freed[b], st));
-        total += off;
+        total += filled[k];
     }
     if (streamed) *streamed = total;
     return SPADE_OK;

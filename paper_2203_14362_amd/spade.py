@@ -408,6 +408,7 @@ class Context:
         self.handle = h
         self.timing_enabled = False
         self._select_cap = 1 << 20
+        self._pairs_hint = {}        # id of a polygon set -> pairs of its last join (first capacity tried)
 
     # -- helpers
     def _check(self, rc):
@@ -573,10 +574,13 @@ class Context:
         return out[:dp.n_polys]
 
     def host_select(self, table: HostTable, poly, cap=None):
+        """Ids of the table's points inside one polygon, ascending.  The
+        default capacity is the table's point count, so that the points are
+        streamed once (a capacity shortfall would stream them again)."""
         dp = self.polys(poly)
         n = table.info()["n_points"]
         if cap is None:
-            cap = max(1, min(n, 1 << 24))
+            cap = max(1, n)
         while True:
             out = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device)
             nout, st = ctypes.c_int64(), ctypes.c_int64()
@@ -679,7 +683,14 @@ class Context:
         P = _points(x, y)
         n = P.n
         if cap is None:
+            # a selection has at most n results; join pairs can have more
+            # (overlapping polygons): the last join with the same polygons
+            # gives the first capacity tried, so that repeated joins run once
             cap = max(n, 1)
+            if pairs:
+                hint = getattr(target, "last_pairs", 0) if isinstance(target, Canvas) else \
+                    self._pairs_hint.get(id(target), 0)
+                cap = max(cap, hint)
         while True:
             pt = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device)
             pg = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device) if pairs else None
@@ -708,6 +719,13 @@ class Context:
                 continue
             self._check(rc)
             m = int(nout.value)
+            if pairs:
+                if isinstance(target, Canvas):
+                    target.last_pairs = m
+                else:
+                    if len(self._pairs_hint) >= 64:
+                        self._pairs_hint.pop(next(iter(self._pairs_hint)))
+                    self._pairs_hint[id(target)] = m
             return (_ids(_compact(pt, m), n), _compact(pg, m)) if pairs else _ids(_compact(pt, m), n)
 
     def select(self, x, y, poly_or_canvas, cap=None):
