@@ -408,7 +408,7 @@ class Context:
         self.handle = h
         self.timing_enabled = False
         self._select_cap = 1 << 20
-        self._pairs_hint = {}        # id of a polygon set -> pairs of its last join (first capacity tried)
+        self._pairs_hint = {}        # id of a join's constraint set -> pairs of its last join (first capacity tried)
 
     # -- helpers
     def _check(self, rc):
@@ -679,6 +679,16 @@ class Context:
                                                   ctypes.byref(dp.cstruct()), ctypes.c_void_p(optr)))
         return out
 
+    def _hint_cap(self, n, key):
+        """First capacity of a join: the point count or the last join's
+        total with the same constraint set, whichever is larger."""
+        return max(n, 1, self._pairs_hint.get(key, 0))
+
+    def _remember_pairs(self, key, m):
+        if len(self._pairs_hint) >= 64 and key not in self._pairs_hint:
+            self._pairs_hint.pop(next(iter(self._pairs_hint)))
+        self._pairs_hint[key] = m
+
     def _emit(self, x, y, target, pairs, cap):
         P = _points(x, y)
         n = P.n
@@ -688,9 +698,8 @@ class Context:
             # gives the first capacity tried, so that repeated joins run once
             cap = max(n, 1)
             if pairs:
-                hint = getattr(target, "last_pairs", 0) if isinstance(target, Canvas) else \
-                    self._pairs_hint.get(id(target), 0)
-                cap = max(cap, hint)
+                cap = max(cap, getattr(target, "last_pairs", 0)) if isinstance(target, Canvas) else \
+                    self._hint_cap(n, id(target))
         while True:
             pt = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device)
             pg = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device) if pairs else None
@@ -723,9 +732,7 @@ class Context:
                 if isinstance(target, Canvas):
                     target.last_pairs = m
                 else:
-                    if len(self._pairs_hint) >= 64:
-                        self._pairs_hint.pop(next(iter(self._pairs_hint)))
-                    self._pairs_hint[id(target)] = m
+                    self._remember_pairs(id(target), m)
             return (_ids(_compact(pt, m), n), _compact(pg, m)) if pairs else _ids(_compact(pt, m), n)
 
     def select(self, x, y, poly_or_canvas, cap=None):
@@ -786,8 +793,9 @@ class Context:
         P = _points(x, y)
         dl = self.polys(lines)
         rr, r_all = self._line_radii(r)
+        key = (id(lines), id(r))
         if cap is None:
-            cap = max(P.n, 1)
+            cap = self._hint_cap(P.n, key)
         while True:
             pt = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device)
             pl = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device)
@@ -802,6 +810,7 @@ class Context:
                 continue
             self._check(rc)
             m = int(nout.value)
+            self._remember_pairs(key, m)
             return _ids(_compact(pt, m), P.n), _compact(pl, m)
 
     def distance_join_lines_count(self, x, y, lines, r):
@@ -840,8 +849,9 @@ class Context:
         by (point, disk); closed disks, decided exactly."""
         P = _points(x, y)
         D, keep = self._disks(cx, cy, r)
+        key = (id(cx), id(cy), id(r))
         if cap is None:
-            cap = max(P.n, 1)
+            cap = self._hint_cap(P.n, key)
         while True:
             pt = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device)
             pd = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device)
@@ -855,6 +865,7 @@ class Context:
                 continue
             self._check(rc)
             m = int(nout.value)
+            self._remember_pairs(key, m)
             return _ids(_compact(pt, m), P.n), _compact(pd, m)
 
     def distance_join_count(self, x, y, cx, cy, r):

@@ -81,6 +81,8 @@ def test_crowded_line_join(ctx, pts, crowd):
     p, q = ctx.distance_join_lines(_dev(x), _dev(y), crowd, rad)
     wp, wq = B.distance_join_lines(x, y, crowd, rad)
     assert np.array_equal(_i64(p), wp) and np.array_equal(_i64(q), wq)
+    p2, q2 = ctx.distance_join_lines(_dev(x), _dev(y), crowd, rad)   # from the remembered total
+    assert np.array_equal(_i64(p2), wp) and np.array_equal(_i64(q2), wq)
     # most crowded points meet several lines
     assert wp.size > 2 * np.unique(wp).size
     cnt = ctx.distance_join_lines_count(_dev(x), _dev(y), crowd, rad).cpu().numpy().astype(np.uint64)
@@ -98,5 +100,10 @@ def test_crowded_disk_join(ctx, pts):
         wp, wd = D.distance_join(x, y, cx, cy, r)
         assert np.array_equal(_i64(p), wp) and np.array_equal(_i64(d), wd)
         assert wp.size > 64 * 1000
+        # more pairs than points: the first call retried with the total, a
+        # repeated one starts from it
+        assert wp.size > x.size
+        p2, d2 = ctx.distance_join(_dev(x), _dev(y), cx, cy, r)
+        assert np.array_equal(_i64(p2), wp) and np.array_equal(_i64(d2), wd)
         cnt = ctx.distance_join_count(_dev(x), _dev(y), cx, cy, r).cpu().numpy().astype(np.uint64)
         assert np.array_equal(cnt, D.distance_join_count(x, y, cx, cy, r))
