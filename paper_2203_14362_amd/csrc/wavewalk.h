@@ -10,13 +10,15 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <rocprim/warp/warp_scan.hpp>
 #include <stdint.h>
 
 namespace spade {
 
 // One round: this lane's point has rem candidates left, of which c (at most
 // 64, so that the prefix sums stay small) take the positions [pre, incl)
-// of the round's sequence; positions below ntake (at most 64) are tested.
+// of the round's sequence (a wavefront scan, rocPRIM's cross-lane warp scan);
+// positions below ntake (at most 64) are tested.
 // Lane t tests position t, which belongs to lane o (the first lane whose
 // inclusive prefix exceeds t, found by a binary search over the lanes) and
 // is the (t - opre)-th of o's candidates this round.
@@ -30,14 +32,12 @@ __device__ __forceinline__ WaveRound wave_round(uint32_t rem, int lane)
 {
     WaveRound w;
     w.c = min(rem, 64u);
-    uint32_t incl = w.c;
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t v = __shfl_up(incl, d, 64);
-        if (lane >= d) incl += v;
-    }
+    uint32_t incl, total;
+    typename rocprim::warp_scan<uint32_t, 64>::storage_type scan_storage;
+    rocprim::warp_scan<uint32_t, 64>().inclusive_scan(w.c, incl, total, scan_storage, rocprim::plus<uint32_t>());
     w.incl = incl;
     w.pre = incl - w.c;
-    w.ntake = min(__shfl(incl, 63, 64), 64u);
+    w.ntake = min(total, 64u);
     int o = 0;
     for (int st = 32; st > 0; st >>= 1)
         if (__shfl(incl, o + st - 1, 64) <= (uint32_t)lane) o += st;
