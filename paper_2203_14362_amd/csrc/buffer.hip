@@ -634,7 +634,8 @@ __device__ __forceinline__ void bufj_wave_walk(double x, double y, uint32_t k, u
     }
 }
 
-// MODE 0: pairs per 1024-point segment (counts[sg]); MODE 1: the pairs, from
+// MODE 0: pairs per 1024-point segment (counts[sg]; with pcount, also the
+// pairs of every point, so that the write pass walks once); MODE 1: the pairs, from
 // offs[sg] on (below cap; the first cap in (point, line) order); MODE 2:
 // pairs per line added into lcount (an LDS histogram when nlines <= hist).
 template <int MODE>
@@ -643,7 +644,8 @@ __global__ __launch_bounds__(BUF_THREADS) void k_bufj_pairs(int64_t n, const dou
                                                             int64_t nseg, unsigned long long *counts,
                                                             const unsigned long long *offs, uint32_t *out_pt,
                                                             uint32_t *out_line, int64_t cap,
-                                                            unsigned long long *lcount, int nlines, int hist)
+                                                            unsigned long long *lcount, int nlines, int hist,
+                                                            uint32_t *pcount)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     uint32_t *h = (uint32_t *)smem;
@@ -670,7 +672,12 @@ __global__ __launch_bounds__(BUF_THREADS) void k_bufj_pairs(int64_t n, const dou
                 });
                 continue;
             }
-            bufj_wave_walk(x, y, k, rem, list, magpad, 0u, lane, cnt, [](int, uint32_t, uint32_t) {});
+            if (MODE == 1 && pcount) {
+                cnt = i < n ? pcount[i] : 0u;   // the count pass's pairs of this point
+            } else {
+                bufj_wave_walk(x, y, k, rem, list, magpad, 0u, lane, cnt, [](int, uint32_t, uint32_t) {});
+                if (MODE == 0 && pcount && i < n) pcount[i] = cnt;
+            }
             // the wavefront's pairs of this word, in lane order
             uint32_t pre = cnt;
             for (int d = 1; d < 64; d <<= 1) {
@@ -867,7 +874,7 @@ int buffer_join_lines(spade_ctx *ctx, const spade_points *pts, const spade_polys
         hipLaunchKernelGGL(k_bufj_pairs<2>, dim3(gridp), dim3(BUF_THREADS), lds, st, n, pts->x, pts->y, grid,
                            (const uint32_t *)off, (const JSeg *)list, magpad, nseg, (unsigned long long *)nullptr,
                            (const unsigned long long *)nullptr, (uint32_t *)nullptr, (uint32_t *)nullptr, (int64_t)0,
-                           (unsigned long long *)out_counts, (int)R, HIST);
+                           (unsigned long long *)out_counts, (int)R, HIST, (uint32_t *)nullptr);
         SPADE_HIP(ctx, hipGetLastError());
         if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[3], st));
         SPADE_HIP(ctx, hipStreamSynchronize(st));
@@ -877,10 +884,18 @@ int buffer_join_lines(spade_ctx *ctx, const spade_points *pts, const spade_polys
     if (ensure(ctx, lb, sizeof(unsigned long long) * 2 * (size_t)(nseg + 1))) return SPADE_E_NOMEM;
     unsigned long long *counts = (unsigned long long *)lb.p;
     unsigned long long *offs = counts + (nseg + 1);
+    // pairs per point, kept by the count pass for the write pass (without the
+    // room, the write pass counts again)
+    DevBuf &pb = ctx->scratch[S_BITS];
+    uint32_t *pcount = nullptr;
+    if (cap > 0) {
+        if (ensure(ctx, pb, sizeof(uint32_t) * (size_t)n) == SPADE_OK) pcount = (uint32_t *)pb.p;
+        else ctx->err.clear();
+    }
     hipLaunchKernelGGL(k_bufj_pairs<0>, dim3(gridp), dim3(BUF_THREADS), 0, st, n, pts->x, pts->y, grid,
                        (const uint32_t *)off, (const JSeg *)list, magpad, nseg, counts,
                        (const unsigned long long *)nullptr, (uint32_t *)nullptr, (uint32_t *)nullptr, (int64_t)0,
-                       (unsigned long long *)nullptr, (int)R, 0);
+                       (unsigned long long *)nullptr, (int)R, 0, pcount);
     hipLaunchKernelGGL(k_buf_zero, dim3(1), dim3(1), 0, st, counts + nseg);
     SPADE_HIP(ctx, hipGetLastError());
     DevBuf &bt = ctx->scratch[S_BUF_TMP];
@@ -892,7 +907,7 @@ int buffer_join_lines(spade_ctx *ctx, const spade_points *pts, const spade_polys
         hipLaunchKernelGGL(k_bufj_pairs<1>, dim3(gridp), dim3(BUF_THREADS), 0, st, n, pts->x, pts->y, grid,
                            (const uint32_t *)off, (const JSeg *)list, magpad, nseg, (unsigned long long *)nullptr,
                            (const unsigned long long *)offs, out_pt, out_line, cap, (unsigned long long *)nullptr,
-                           (int)R, 0);
+                           (int)R, 0, pcount);
         SPADE_HIP(ctx, hipGetLastError());
     }
     if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[3], st));

@@ -194,14 +194,16 @@ __device__ __forceinline__ void disk_wave_walk(const DiskCanvas &K, double x, do
     }
 }
 
-// MODE 0: counts per wavefront segment; 1: pairs written from offs[s] on
-// (positions at or beyond cap are not written); 2: per-disk counts.
+// MODE 0: counts per wavefront segment (and, with pcount, the pairs of every
+// point, so that the write pass walks each point's candidates once); 1: pairs
+// written from offs[s] on (positions at or beyond cap are not written); 2:
+// per-disk counts.
 template <int MODE>
 __global__ __launch_bounds__(DJ_THREADS) void k_djoin(DiskCanvas K, int64_t n, const double *X, const double *Y,
                                                       int64_t nseg, unsigned long long *counts,
                                                       const unsigned long long *offs, uint32_t *out_pt,
                                                       uint32_t *out_disk, int64_t cap, int64_t ndisk,
-                                                      unsigned long long *dcount)
+                                                      unsigned long long *dcount, uint32_t *pcount)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     uint32_t *hist = (uint32_t *)smem;
@@ -233,7 +235,13 @@ __global__ __launch_bounds__(DJ_THREADS) void k_djoin(DiskCanvas K, int64_t n, c
                 });
                 continue;
             }
-            disk_wave_walk(K, xs[k], ys[k], c0, rem, 0u, lane, m, [](int, uint32_t, uint32_t) {});
+            const int64_t ip = i0 + 64 * k;
+            if (MODE == 1 && pcount) {
+                m = ip < n ? pcount[ip] : 0u;   // the count pass's pairs of this point
+            } else {
+                disk_wave_walk(K, xs[k], ys[k], c0, rem, 0u, lane, m, [](int, uint32_t, uint32_t) {});
+                if (MODE == 0 && pcount && ip < n) pcount[ip] = m;
+            }
             uint32_t inc = m;
 #pragma unroll
             for (int d = 1; d < 64; d <<= 1) {
@@ -421,7 +429,8 @@ int distance_join(spade_ctx *ctx, const spade_points *pts, const spade_disks *dk
     if (counting) {
         const size_t lds = m <= DJ_HIST_MAX ? 4 * (size_t)m : 16;
         hipLaunchKernelGGL(k_djoin<2>, dim3(grid), dim3(DJ_THREADS), lds, st, K, n, pts->x, pts->y, nseg, nullptr,
-                           nullptr, nullptr, nullptr, (int64_t)0, m, (unsigned long long *)out_counts);
+                           nullptr, nullptr, nullptr, (int64_t)0, m, (unsigned long long *)out_counts,
+                           (uint32_t *)nullptr);
         SPADE_HIP(ctx, hipGetLastError());
         if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[3], st));
         SPADE_HIP(ctx, hipStreamSynchronize(st));
@@ -430,8 +439,16 @@ int distance_join(spade_ctx *ctx, const spade_points *pts, const spade_disks *dk
     DevBuf &lb = ctx->scratch[S_LOOKBACK];
     if (ensure(ctx, lb, sizeof(unsigned long long) * 2 * (size_t)(nseg + 1))) return SPADE_E_NOMEM;
     unsigned long long *counts = (unsigned long long *)lb.p, *offs = counts + (nseg + 1);
+    // pairs per point, kept by the count pass for the write pass (without the
+    // room, the write pass counts again)
+    DevBuf &pb = ctx->scratch[S_BITS];
+    uint32_t *pcount = nullptr;
+    if (cap > 0) {
+        if (ensure(ctx, pb, sizeof(uint32_t) * (size_t)n) == SPADE_OK) pcount = (uint32_t *)pb.p;
+        else ctx->err.clear();
+    }
     hipLaunchKernelGGL(k_djoin<0>, dim3(grid), dim3(DJ_THREADS), 0, st, K, n, pts->x, pts->y, nseg, counts, nullptr,
-                       nullptr, nullptr, (int64_t)0, m, nullptr);
+                       nullptr, nullptr, (int64_t)0, m, nullptr, pcount);
     hipLaunchKernelGGL(k_dj_zero, dim3(1), dim3(64), 0, st, (int64_t)1, counts + nseg);
     SPADE_HIP(ctx, hipGetLastError());
     DevBuf &cub = ctx->scratch[S_CUBTMP];
@@ -441,7 +458,7 @@ int distance_join(spade_ctx *ctx, const spade_points *pts, const spade_disks *dk
     SPADE_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(cub.p, tb, counts, offs, (int)(nseg + 1), st));
     if (cap > 0) {
         hipLaunchKernelGGL(k_djoin<1>, dim3(grid), dim3(DJ_THREADS), 0, st, K, n, pts->x, pts->y, nseg, nullptr, offs,
-                           out_pt, out_disk, cap, m, nullptr);
+                           out_pt, out_disk, cap, m, nullptr, pcount);
         SPADE_HIP(ctx, hipGetLastError());
     }
     if (ctx->timing) SPADE_HIP(ctx, hipEventRecord(ctx->ev[3], st));
